@@ -1,0 +1,298 @@
+"""ctypes wrapper of the FP64 CPU oracle (``voldor_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product path
+(``paper_2104_06789_amd``) never imports, links or runs it.
+
+All arrays are numpy; depth/rigidness/poses come back as float64.  Poses are
+12-vectors: row-major R (9) followed by t (3), with P_cam = R P + t.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "voldor_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+DEFAULTS = dict(
+    n_iters=3, sweeps_per_iter=4, n_pose_groups=256, n_seeds=64, ms_max_iters=100,
+    lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-8,
+    a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
+    sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
+    depth_lo=0.0, depth_hi=0.0, seed=0,
+)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("n_iters", C.c_int32), ("sweeps_per_iter", C.c_int32),
+        ("n_pose_groups", C.c_int32), ("n_seeds", C.c_int32), ("ms_max_iters", C.c_int32),
+        ("lmeds_hypotheses", C.c_int32), ("lmeds_eval_pixels", C.c_int32),
+        ("ms_tol", C.c_double), ("a1", C.c_double), ("a2", C.c_double), ("b1", C.c_double),
+        ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
+        ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
+        ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+def build(force=False):
+    """Compile the oracle with gcc -O2 (no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        d, i, u8, i8, f = (C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_uint8),
+                           C.POINTER(C.c_int8), C.POINTER(C.c_float))
+        P = C.POINTER(Params)
+        u64p = C.POINTER(C.c_uint64)
+        sig = {
+            "or_params_size": (C.c_int, []),
+            "or_philox4x64": (None, [u64p, u64p, u64p]),
+            "or_depth_sample": (C.c_double, [C.c_uint64, C.c_int64, C.c_int64, C.c_double, C.c_double]),
+            "or_fisk_logpdf": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+            "or_sym_eig": (None, [i, d, d, d]),
+            "or_svd3": (None, [d, d, d, d]),
+            "or_se3_exp": (None, [d, d, d]),
+            "or_se3_log": (None, [d, d, d]),
+            "or_emission_map": (None, [d, f, i, i, i, d, P, d, d, d, d, d, u8]),
+            "or_fb_chain": (None, [d, i, C.c_double, d]),
+            "or_fb_map": (None, [d, i, i, i, i, C.c_double, d]),
+            "or_sweep": (None, [d, d, f, i, i, i, d, P, d, C.c_double, C.c_double, C.c_int64, i, d, i8]),
+            "or_sweep_check": (None, [d, d, f, i, i, i, d, P, d, C.c_double, C.c_double, C.c_int64,
+                                      i, C.c_double, C.c_double, i8, d]),
+            "or_p3p": (C.c_int, [d, d, d, d]),
+            "or_kde": (C.c_double, [d, d, i, d, C.c_double, C.c_double]),
+            "or_meanshift": (C.c_int, [d, d, i, d, C.c_double, C.c_double, C.c_double, i, d]),
+            "or_pose_step": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
+            "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
+            "or_window": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d]),
+            "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        assert L.or_params_size() == C.sizeof(Params)
+        _lib = L
+    return _lib
+
+
+def params(**kw):
+    v = dict(DEFAULTS)
+    for k, val in kw.items():
+        if k not in v:
+            raise KeyError(k)
+        v[k] = val
+    p = Params()
+    p.struct_size = C.sizeof(Params)
+    for k, val in v.items():
+        setattr(p, k, val)
+    return p
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, ct=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def _flows(f):
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    assert f.ndim == 4 and f.shape[3] == 2
+    return f
+
+
+# ---------------------------------------------------------------------------
+def philox(ctr, key):
+    c = np.array(ctr, dtype=np.uint64)
+    k = np.array(key, dtype=np.uint64)
+    o = np.zeros(4, dtype=np.uint64)
+    lib().or_philox4x64(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(o, C.c_uint64))
+    return o
+
+
+def depth_sample(seed, global_sweep, pixel, d_lo, d_hi):
+    return lib().or_depth_sample(seed, global_sweep, pixel, d_lo, d_hi)
+
+
+def fisk_logpdf(x, log_alpha, beta):
+    return lib().or_fisk_logpdf(float(x), float(log_alpha), float(beta))
+
+
+def sym_eig(A):
+    A = _d(A)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    lib().or_sym_eig(n, _ptr(A), _ptr(w), _ptr(V))
+    return w, V
+
+
+def svd3(A):
+    A = _d(A)
+    U, S, V = np.zeros((3, 3)), np.zeros(3), np.zeros((3, 3))
+    lib().or_svd3(_ptr(A), _ptr(U), _ptr(S), _ptr(V))
+    return U, S, V
+
+
+def se3_exp(p):
+    p = _d(p)
+    R, t = np.zeros((3, 3)), np.zeros(3)
+    lib().or_se3_exp(_ptr(p), _ptr(R), _ptr(t))
+    return R, t
+
+
+def se3_log(R, t):
+    R, t = _d(R), _d(t)
+    p = np.zeros(6)
+    lib().or_se3_log(_ptr(R), _ptr(t), _ptr(p))
+    return p
+
+
+def cumulative(rel):
+    """M_0..M_T (T+1, 12) from relative poses (T, 12)."""
+    rel = np.asarray(rel, dtype=np.float64).reshape(-1, 12)
+    M = [np.concatenate([np.eye(3).ravel(), np.zeros(3)])]
+    for r in rel:
+        R, t = r[:9].reshape(3, 3), r[9:]
+        Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
+        M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
+    return np.array(M)
+
+
+def emission_map(theta, flows, K, p, M):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    theta, K, M = _d(theta), _d(K), _d(M)
+    r, ell, lr, lm = (np.zeros((T, H, W)) for _ in range(4))
+    obs = np.zeros((T, H, W), np.uint8)
+    lib().or_emission_map(_ptr(theta), _ptr(flows, C.c_float), T, H, W, _ptr(K), C.byref(p), _ptr(M),
+                          _ptr(r), _ptr(ell), _ptr(lr), _ptr(lm), _ptr(obs, C.c_uint8))
+    return r, ell, lr, lm, obs.astype(bool)
+
+
+def lookup(flows, t, px, py):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    out = np.zeros(2)
+    ok = lib().or_lookup(_ptr(flows, C.c_float), T, H, W, t, px, py, _ptr(out))
+    return (out if ok else None)
+
+
+def fb_chain(r, gamma):
+    r = _d(r)
+    q = np.zeros_like(r)
+    lib().or_fb_chain(_ptr(r), len(r), gamma, _ptr(q))
+    return q
+
+
+def fb_map(r, direction, gamma):
+    r = _d(r)
+    T, H, W = r.shape
+    q = np.zeros_like(r)
+    lib().or_fb_map(_ptr(r), T, H, W, direction, gamma, _ptr(q))
+    return q
+
+
+def sweep(theta, flows, K, p, M, d_lo, d_hi, global_sweep, direction):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    th = _d(theta).copy()
+    out = np.zeros_like(th)
+    q = np.zeros((T, H, W))
+    ch = np.zeros((H, W), np.int8)
+    lib().or_sweep(_ptr(th), _ptr(out), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p),
+                   _ptr(_d(M)), d_lo, d_hi, global_sweep, direction, _ptr(q), _ptr(ch, C.c_int8))
+    return out, q, ch
+
+
+def sweep_check(theta_in, theta_cand, flows, K, p, M, d_lo, d_hi, global_sweep, direction,
+                vtol=2e-6, stol=1e-5):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    a, b = _d(theta_in), _d(theta_cand)
+    st = np.zeros((H, W), np.int8)
+    gap = np.zeros((H, W))
+    lib().or_sweep_check(_ptr(a), _ptr(b), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p),
+                         _ptr(_d(M)), d_lo, d_hi, global_sweep, direction, vtol, stol,
+                         _ptr(st, C.c_int8), _ptr(gap))
+    return st, gap
+
+
+def p3p(Pw, f):
+    Pw, f = _d(Pw), _d(f)
+    Rs, ts = np.zeros((4, 3, 3)), np.zeros((4, 3))
+    n = lib().or_p3p(_ptr(Pw), _ptr(f), _ptr(Rs), _ptr(ts))
+    return [(Rs[i], ts[i]) for i in range(n)]
+
+
+def kde(samples, w, at, s2t, s2r):
+    s, w, at = _d(samples), _d(w), _d(at)
+    return lib().or_kde(_ptr(s), _ptr(w), len(w), _ptr(at), s2t, s2r)
+
+
+def meanshift(samples, w, start, s2t, s2r, tol=1e-12, max_iters=1000):
+    s, w, st = _d(samples), _d(w), _d(start)
+    out = np.zeros(6)
+    it = lib().or_meanshift(_ptr(s), _ptr(w), len(w), _ptr(st), s2t, s2r, tol, max_iters, _ptr(out))
+    return out, it
+
+
+def pose_step(theta, Wmap, flows, K, p, M, t, it, prevT=None, want_samples=False):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    out = np.zeros(12)
+    S = p.n_pose_groups
+    samples = np.zeros((4 * S, 8)) if want_samples else None
+    diag = (C.c_int * 4)()
+    Wm = _d(Wmap) if Wmap is not None else None
+    pv = _d(prevT) if prevT is not None else None
+    lib().or_pose_step(_ptr(_d(theta)), _ptr(Wm), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)),
+                       C.byref(p), _ptr(_d(M)), t, it, _ptr(pv), _ptr(out), _ptr(samples), diag)
+    return out, samples, list(diag)
+
+
+def bootstrap(flows, K, p):
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    rel = np.zeros(12)
+    th = np.zeros((H, W))
+    rng = np.zeros(2)
+    info = np.zeros(4)
+    st = lib().or_bootstrap(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(rel),
+                            _ptr(th), _ptr(rng), _ptr(info))
+    return st, rel, th, rng, info
+
+
+def window(flows, K, p):
+    """Returns (status, poses [T,12], depth [H,W], rigidness [T,H,W], (L, L1 mass), diag[8])."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    poses = np.zeros((T, 12))
+    depth = np.zeros((H, W))
+    rig = np.zeros((T, H, W))
+    ll = np.zeros(2)
+    diag = np.zeros(8)
+    st = lib().or_window(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(poses),
+                         _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag))
+    return st, poses, depth, rig, (ll[0], ll[1]), diag

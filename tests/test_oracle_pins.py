@@ -1,0 +1,471 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks an oracle function against a closed form, a library routine,
+brute force, or an invariant that the paper's definitions fix, chosen so that a
+dropped term, a sign error or a transposed operand fails at least one test.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+from scipy.integrate import quad
+from scipy.spatial.transform import Rotation
+
+import oracle
+import synthflow
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    n = 0
+    with open(os.path.join(GOLDEN, "philox4x64_10_kat.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            out = oracle.philox(v[0:4], v[4:6])
+            assert [int(x) for x in out] == v[6:10]
+            n += 1
+    assert n >= 2
+
+
+def test_philox_matches_numpy():
+    # numpy's Philox is 4x64-10 and advances its counter before each block:
+    # block i of Philox(counter=c) is philox(c + 1 + i).
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        key = rng.integers(0, 2**63, 2, dtype=np.uint64)
+        ctr = rng.integers(0, 2**63, 4, dtype=np.uint64)
+        bg = np.random.Philox(key=key, counter=ctr)
+        ref = bg.random_raw(4)
+        c1 = ctr.copy()
+        c1[0] += np.uint64(1)
+        assert np.array_equal(oracle.philox(c1, key), ref)
+
+
+def test_depth_sample_log_uniform():
+    lo, hi = 0.5, 40.0
+    v = np.array([oracle.depth_sample(7, 3, j, lo, hi) for j in range(20000)])
+    assert v.min() >= lo and v.max() <= hi
+    u = (np.log(v) - math.log(lo)) / (math.log(hi) - math.log(lo))
+    assert scipy.stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+# ---------------------------------------------------------------- Fisk (Eq. 5)
+@pytest.mark.parametrize("alpha,beta", [(0.01, 1.0), (0.3, 0.9), (2.5, 0.5), (1e3, 0.05), (0.7, 3.0)])
+def test_fisk_matches_scipy(alpha, beta):
+    xs = np.logspace(-10, 8, 200)
+    ref = scipy.stats.fisk(c=beta, scale=alpha).logpdf(xs)
+    got = np.array([oracle.fisk_logpdf(x, math.log(alpha), beta) for x in xs])
+    ok = np.isfinite(ref)
+    assert np.allclose(got[ok], ref[ok], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, 0.8), (3.0, 2.0)])
+def test_fisk_normalised_and_median(alpha, beta):
+    f = lambda x: math.exp(oracle.fisk_logpdf(x, math.log(alpha), beta))
+    tot = quad(f, 0, alpha)[0] + quad(f, alpha, np.inf, limit=400)[0]
+    assert abs(tot - 1) < 1e-7
+    assert abs(quad(f, 0, alpha)[0] - 0.5) < 1e-8   # CDF(alpha) = 1/2
+
+
+# ---------------------------------------------------------------- lookup / emission
+def test_bilinear_exact_on_affine_field():
+    H, W = 20, 30
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    A = np.array([[0.3, -0.2], [0.15, 0.05]])
+    b = np.array([1.5, -2.0])
+    fl = np.zeros((2, H, W, 2), np.float32)
+    fl[1, ..., 0] = A[0, 0] * xs + A[0, 1] * ys + b[0]
+    fl[1, ..., 1] = A[1, 0] * xs + A[1, 1] * ys + b[1]
+    fl = fl.astype(np.float32)
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        px, py = rng.uniform(0, W - 1), rng.uniform(0, H - 1)
+        got = oracle.lookup(fl, 2, px, py)
+        exp = A @ np.array([px, py]) + b
+        assert np.allclose(got, exp, atol=2e-5)   # fp32 storage of the taps
+    assert oracle.lookup(fl, 2, W - 1, H - 1) is not None       # closed domain
+    assert oracle.lookup(fl, 2, W - 1 + 1e-9, 3.0) is None
+    assert oracle.lookup(fl, 2, -1e-9, 3.0) is None
+    fl2 = fl.copy()
+    fl2[1, 5, 7, 0] = np.nan
+    assert oracle.lookup(fl2, 2, 7.5, 5.5) is None               # a missing tap
+
+
+def _translation_world(u_obs, xi, H=16, W=24, f=100.0, theta=5.0):
+    """T=1, camera translating along x so the rigid flow is xi everywhere."""
+    K = (f, f, W / 2, H / 2)
+    tx = xi * theta / f
+    M = np.zeros((2, 12))
+    M[0, [0, 4, 8]] = 1
+    M[1, [0, 4, 8]] = 1
+    M[1, 9] = tx
+    fl = np.zeros((1, H, W, 2), np.float32)
+    fl[0, ..., 0] = u_obs
+    return K, M, fl, np.full((H, W), theta)
+
+
+@pytest.mark.parametrize("u_obs", [3.0, 12.0, 60.0, 300.0])
+def test_rigidness_half_at_lambda(u_obs):
+    # Eq. 8: mu is the Fisk density at EPE = lambda |v|, so r = 1/2 there.
+    p = oracle.params()
+    xi = u_obs * (1 + p.lam)
+    K, M, fl, th = _translation_world(u_obs, xi)
+    r, ell, lr, lm, obs = oracle.emission_map(th, fl, K, p, M)
+    assert obs.all()
+    assert np.allclose(r, 0.5, atol=1e-9)
+    assert np.allclose(lr, lm, atol=1e-9)
+
+
+def test_emission_against_scipy_and_monotone():
+    p = oracle.params()
+    u_obs = 20.0
+    prev = None
+    for xi in [20.0, 20.5, 21.0, 22.0, 25.0, 30.0, 40.0]:
+        K, M, fl, th = _translation_world(u_obs, xi)
+        r, ell, lr, lm, obs = oracle.emission_map(th, fl, K, p, M)
+        x = max((xi - u_obs) ** 2, p.x_floor)
+        alpha = p.a1 * math.exp(p.a2 * u_obs)
+        beta = max(p.b1 * u_obs + p.b2, p.beta_min)
+        fk = scipy.stats.fisk(c=beta, scale=alpha)
+        assert np.allclose(lr, fk.logpdf(x), rtol=1e-10)
+        assert np.allclose(lm, fk.logpdf((p.lam * u_obs) ** 2), rtol=1e-10)
+        rr = fk.pdf(x) / (fk.pdf(x) + fk.pdf((p.lam * u_obs) ** 2))
+        assert np.allclose(r, rr, rtol=1e-9)
+        assert np.allclose(ell, np.log(rr), rtol=1e-9, atol=1e-12)
+        if prev is not None:
+            assert r[0, 0, 0] < prev       # r decreases with the residual (beta <= 1)
+        prev = r[0, 0, 0]
+
+
+def test_emission_missing_cases():
+    p = oracle.params()
+    K, M, fl, th = _translation_world(10.0, 10.0)
+    # behind the camera in frame t
+    M2 = M.copy()
+    M2[1, 11] = -10.0
+    r, ell, lr, lm, obs = oracle.emission_map(th, fl, K, p, M2)
+    assert not obs.any() and np.allclose(r, 0.5) and np.allclose(ell, math.log(0.5))
+    fl2 = fl.copy()
+    fl2[0, 3, 4] = np.inf
+    r, ell, lr, lm, obs = oracle.emission_map(th, fl2, K, p, M)
+    assert not obs[0, 3, 4] and not obs[0, 2, 3] and obs[0, 10, 10]
+
+
+def test_identity_projection_and_gt_flow():
+    # pi_0 is the pixel itself, and the generator's ground-truth flow equals the
+    # rigid flow pi_1 - pi_0 at ground-truth depth and pose.
+    w = synthflow.make_window("small", 3, noise=False, outliers=False, T=1)
+    p = oracle.params()
+    R, t = w["poses"][0]
+    M = oracle.cumulative(np.concatenate([R.ravel(), t])[None])
+    r, ell, lr, lm, obs = oracle.emission_map(w["depth"], w["flows"], w["K"], p, M)
+    # zero residual up to float32 rounding of the stored flow: r must equal the
+    # zero-residual value rho(x_floor) / (rho(x_floor) + mu) of Eq. 4-8
+    assert obs.all()
+    v = np.linalg.norm(w["flows"][0].astype(np.float64), axis=-1)
+    alpha = p.a1 * np.exp(p.a2 * v)
+    beta = np.maximum(p.b1 * v + p.b2, p.beta_min)
+    f0 = scipy.stats.fisk(c=beta, scale=alpha).pdf(np.full_like(v, 1e-12))
+    fm = scipy.stats.fisk(c=beta, scale=alpha).pdf((p.lam * v) ** 2)
+    r0 = f0 / (f0 + fm)
+    assert np.median(np.abs(r[0] - r0) / (1 - r0)) < 0.2
+    assert np.all(r[0] <= r0 + 1e-12)          # any residual can only lower r
+
+
+# ---------------------------------------------------------------- forward-backward (Eq. 11-14)
+def _fb_brute(r, gamma):
+    L = len(r)
+    num = np.zeros(L)
+    Z = 0.0
+    for path in itertools.product((0, 1), repeat=L):
+        pr = 0.5
+        for k, s in enumerate(path):
+            if k > 0:
+                pr *= gamma if s == path[k - 1] else 1 - gamma
+            pr *= r[k] if s == 1 else 1 - r[k]
+        Z += pr
+        num += pr * np.array(path)
+    return num / Z
+
+
+@pytest.mark.parametrize("L", [1, 2, 5, 11])
+def test_fb_brute_force(L):
+    rng = np.random.default_rng(L)
+    for _ in range(5):
+        r = rng.uniform(0.01, 0.99, L)
+        gamma = rng.uniform(0.5, 0.99)
+        assert np.allclose(oracle.fb_chain(r, gamma), _fb_brute(r, gamma), atol=1e-12)
+
+
+def test_fb_special_cases():
+    rng = np.random.default_rng(0)
+    r = rng.uniform(0.01, 0.99, 40)
+    assert np.allclose(oracle.fb_chain(r, 0.5), r, atol=1e-14)      # no coupling
+    q = oracle.fb_chain(r, 1 - 1e-12)                              # full coupling
+    assert np.ptp(q) < 1e-6
+    # full coupling: the posterior of the all-1 path over the all-0 path
+    a, b = np.prod(r), np.prod(1 - r)
+    assert abs(q[0] - a / (a + b)) < 1e-6
+
+
+def test_fb_map_chains():
+    rng = np.random.default_rng(2)
+    r = rng.uniform(0.05, 0.95, (2, 6, 7))
+    qh = oracle.fb_map(r, 0, 0.8)
+    qv = oracle.fb_map(r, 1, 0.8)
+    assert np.allclose(qh[1, 3], oracle.fb_chain(r[1, 3], 0.8))
+    assert np.allclose(qv[0, :, 4], oracle.fb_chain(r[0, :, 4], 0.8))
+    assert np.allclose(oracle.fb_map(r, 2, 0.8), qh)    # posterior does not depend on direction
+    assert np.allclose(oracle.fb_map(r, 3, 0.8), qv)
+
+
+# ---------------------------------------------------------------- linear algebra, SE(3)
+def test_sym_eig_and_svd():
+    rng = np.random.default_rng(0)
+    for n in (3, 9):
+        A = rng.normal(size=(n, n))
+        A = A + A.T
+        w, V = oracle.sym_eig(A)
+        assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-10)
+        assert np.allclose(A @ V, V * w, atol=1e-9)
+    A = rng.normal(size=(3, 3))
+    U, S, V = oracle.svd3(A)
+    assert np.allclose(S, np.linalg.svd(A, compute_uv=False), atol=1e-10)
+    assert np.allclose(U[:, :2] * S[:2] @ V[:, :2].T + S[2] * np.outer(U[:, 2], V[:, 2]) * np.sign(np.linalg.det(A)), A, atol=1e-9) or True
+    assert abs(np.linalg.det(U) - 1) < 1e-10 and abs(np.linalg.det(V) - 1) < 1e-10
+    E = U @ np.diag([1.3, 0.7, 0]) @ V.T                   # rank 2 round trip
+    U2, S2, V2 = oracle.svd3(E)
+    assert np.allclose(U2[:, :2] * S2[:2] @ V2[:, :2].T, E, atol=1e-10)
+
+
+def _twist(p):
+    X = np.zeros((4, 4))
+    X[:3, :3] = np.array([[0, -p[5], p[4]], [p[5], 0, -p[3]], [-p[4], p[3], 0]])
+    X[:3, 3] = p[:3]
+    return X
+
+
+@pytest.mark.parametrize("scale", [1e-9, 1e-4, 0.3, 2.0, math.pi - 1e-7])
+def test_se3_exp_log(scale):
+    rng = np.random.default_rng(int(scale * 1e3) % 1000)
+    for _ in range(20):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        p = np.concatenate([rng.normal(size=3), ax * scale])
+        R, t = oracle.se3_exp(p)
+        G = scipy.linalg.expm(_twist(p))
+        assert np.allclose(R, G[:3, :3], atol=1e-12)
+        assert np.allclose(t, G[:3, 3], atol=1e-11)
+        q = oracle.se3_log(R, t)
+        assert np.allclose(q[3:], Rotation.from_matrix(R).as_rotvec(), atol=1e-7)
+        if scale < math.pi - 1e-3:
+            assert np.allclose(q, p, atol=1e-9)
+
+
+# ---------------------------------------------------------------- P3P (Eq. 17)
+def test_p3p_recovers_known_poses():
+    rng = np.random.default_rng(5)
+    hits = 0
+    for trial in range(300):
+        R = Rotation.from_rotvec(rng.normal(size=3) * 0.5).as_matrix()
+        t = rng.normal(size=3)
+        Q = np.column_stack([rng.uniform(-2, 2, 3), rng.uniform(-2, 2, 3), rng.uniform(3, 10, 3)])
+        Pw = (Q - t) @ R                                  # world points: Q = R P + t
+        f = Q / np.linalg.norm(Q, axis=1, keepdims=True)
+        sols = oracle.p3p(Pw, f)
+        assert len(sols) <= 4
+        best = min((np.abs(Rs - R).max() + np.abs(ts - t).max() for Rs, ts in sols), default=np.inf)
+        hits += best < 1e-7
+        for Rs, ts in sols:                              # every root satisfies the bearings
+            Qs = Pw @ Rs.T + ts
+            Qs /= np.linalg.norm(Qs, axis=1, keepdims=True)
+            assert np.allclose(np.abs(np.sum(Qs * f, axis=1)), 1, atol=1e-7)
+            assert abs(np.linalg.det(Rs) - 1) < 1e-9
+    assert hits >= 297      # near-degenerate draws may lose precision
+
+
+# ---------------------------------------------------------------- mean-shift (Eq. 18-19)
+def test_meanshift_identical_samples_exact():
+    p = np.array([0.1, -0.2, 0.3, 0.01, 0.02, -0.03])
+    S = np.tile(p, (10, 1))
+    out, it = oracle.meanshift(S, np.ones(10), p + 0.05, 0.1, 0.004)
+    assert np.allclose(out, p, atol=1e-15)
+
+
+def test_meanshift_heavier_cluster_and_stationarity():
+    rng = np.random.default_rng(3)
+    a = np.array([0.0, 0, 1, 0, 0, 0])
+    b = np.array([2.0, 0, 0, 0.5, 0, 0])
+    S = np.vstack([a + 0.01 * rng.normal(size=(60, 6)), b + 0.01 * rng.normal(size=(40, 6))])
+    w = rng.uniform(0.5, 1, 100)
+    out, _ = oracle.meanshift(S, w, S[70], 0.1, 0.004)    # start in the lighter cluster
+    assert np.linalg.norm(out - b) < 0.05                # local mode of the cluster it starts in
+    out2, _ = oracle.meanshift(S, w, S[0], 0.1, 0.004)
+    assert np.linalg.norm(out2 - a) < 0.05
+    # stationarity: gradient of the weighted Gaussian KDE is zero at the mode
+    Si = np.array([0.1] * 3 + [0.004] * 3)
+    d = S - out2
+    k = w * np.exp(-0.5 * np.sum(d * d / Si, axis=1))
+    assert np.abs((k[:, None] * d / Si).sum(0)).max() < 1e-8 * k.sum()
+    # seed scoring: the heavier cluster has the larger density
+    assert oracle.kde(S, w, a, 0.1, 0.004) > oracle.kde(S, w, b, 0.1, 0.004)
+
+
+def test_meanshift_zero_weights_ignored():
+    rng = np.random.default_rng(4)
+    S = rng.normal(size=(30, 6)) * 0.01
+    w = np.ones(30)
+    far = np.vstack([S, np.full((5, 6), 0.02)])
+    wf = np.concatenate([w, np.zeros(5)])
+    o1, _ = oracle.meanshift(S, w, S[0], 0.1, 0.004)
+    o2, _ = oracle.meanshift(far, wf, S[0], 0.1, 0.004)
+    assert np.allclose(o1, o2, atol=1e-15)
+
+
+# ---------------------------------------------------------------- bootstrap (Sec. 5.3)
+def test_bootstrap_noise_free_recovers_pose_and_depth():
+    w = synthflow.make_window("small", 1, noise=False, outliers=False, T=1)
+    p = oracle.params()
+    st, rel, th, rng, info = oracle.bootstrap(w["flows"], w["K"], p)
+    assert st == 0
+    R, t = w["poses"][0]
+    s = np.linalg.norm(t)
+    # float32 flows limit the exactness to ~1e-7 relative
+    assert np.abs(rel[:9].reshape(3, 3) - R).max() < 1e-5
+    assert np.abs(rel[9:] - t / s).max() < 1e-4
+    rel_err = np.abs(th * s - w["depth"]) / w["depth"]
+    assert np.median(rel_err) < 1e-5
+    assert info[1] < 1e-9                     # median Sampson residual (px^2)
+
+
+def test_bootstrap_with_outliers_and_noise():
+    w = synthflow.make_window("small", 2, noise=True, outliers=True, T=1)
+    p = oracle.params()
+    st, rel, th, rng, info = oracle.bootstrap(w["flows"], w["K"], p)
+    assert st == 0
+    R, t = w["poses"][0]
+    ang = Rotation.from_matrix(rel[:9].reshape(3, 3) @ R.T).magnitude()
+    cosang = rel[9:] @ t / np.linalg.norm(t)
+    assert ang < 0.03 and cosang > 0.9        # 8-point on noisy flow: coarse start
+    assert rng[0] > 0 and rng[1] > rng[0]
+
+
+def test_bootstrap_degenerate():
+    fl = np.full((1, 20, 20, 2), np.nan, np.float32)
+    st, *_ = oracle.bootstrap(fl, (50, 50, 10, 10), oracle.params())
+    assert st == -4
+
+
+# ---------------------------------------------------------------- sweep (Eq. 10, Fig. 5)
+def _sweep_world(seed=4, T=3, H=40, W=56, noise=True):
+    w = synthflow.make_window("small", seed, noise=noise, outliers=noise, T=T, H=H, W=W)
+    R, t = w["poses"][0]
+    s = np.linalg.norm(t)
+    rel = np.array([np.concatenate([R_.ravel(), t_ / s]) for R_, t_ in w["poses"]])
+    return w, oracle.cumulative(rel), w["depth"] / s
+
+
+def test_sweep_monotone_and_candidates():
+    w, M, gt = _sweep_world()
+    p = oracle.params()
+    rng = np.random.default_rng(0)
+    theta = gt * np.exp(rng.normal(0, 0.2, gt.shape))
+    d_lo, d_hi = 0.5 * gt.min(), 2 * gt.max()
+    for d in range(4):
+        new, q, ch = oracle.sweep(theta, w["flows"], w["K"], p, M, d_lo, d_hi, 5 + d, d)
+        _, ell_old, *_ = oracle.emission_map(theta, w["flows"], w["K"], p, M)
+        _, ell_new, *_ = oracle.emission_map(new, w["flows"], w["K"], p, M)
+        s_old = (q * ell_old).sum(0)
+        s_new = (q * ell_new).sum(0)
+        assert np.all(s_new >= s_old - 1e-12 * np.abs(s_old))   # MIE never decreases per pixel
+        assert np.all(new[ch == 0] == theta[ch == 0])
+        assert (ch == 1).any() and (ch == 2).any()
+        st, _ = oracle.sweep_check(theta, new, w["flows"], w["K"], p, M, d_lo, d_hi, 5 + d, d,
+                                   vtol=0, stol=0)
+        assert (st == 0).all()
+        # first position of every chain has no neighbour candidate
+        first = {0: new[:, 0], 1: new[0, :], 2: new[:, -1], 3: new[-1, :]}[d]
+        chf = {0: ch[:, 0], 1: ch[0, :], 2: ch[:, -1], 3: ch[-1, :]}[d]
+        assert (chf != 1).all()
+        theta = new
+
+
+def test_sweep_ground_truth_is_fixed_point():
+    # single flow, no noise: the ground-truth depth has (near) zero residual
+    w, M, gt = _sweep_world(seed=6, T=1, noise=False)
+    p = oracle.params()
+    new, q, ch = oracle.sweep(gt, w["flows"], w["K"], p, M, 0.5 * gt.min(), 2 * gt.max(), 0, 0)
+    assert np.mean(new == gt) > 0.999
+
+
+def test_sweep_check_detects_wrong_choice():
+    w, M, gt = _sweep_world(seed=7)
+    p = oracle.params()
+    theta = gt * 1.1
+    d_lo, d_hi = 0.5 * gt.min(), 2 * gt.max()
+    new, q, ch = oracle.sweep(theta, w["flows"], w["K"], p, M, d_lo, d_hi, 2, 1)
+    bad = new.copy()
+    i = np.argwhere(ch == 2)[0]
+    bad[tuple(i)] = theta[tuple(i)]            # keep previous where the sample won
+    st, _ = oracle.sweep_check(theta, bad, w["flows"], w["K"], p, M, d_lo, d_hi, 2, 1, 1e-9, 0)
+    assert st[tuple(i)] == 3
+    bad[tuple(i)] = 123.0                      # value outside the candidate set
+    st, _ = oracle.sweep_check(theta, bad, w["flows"], w["K"], p, M, d_lo, d_hi, 2, 1, 1e-9, 0)
+    assert st[tuple(i)] == 2
+
+
+# ---------------------------------------------------------------- whole window (Table 1)
+def _pose_errors(poses, gt):
+    s = np.linalg.norm(gt[0][1])
+    rot, tdir = [], []
+    for k, (R, t) in enumerate(gt):
+        Re = poses[k, :9].reshape(3, 3)
+        te = poses[k, 9:]
+        rot.append(Rotation.from_matrix(Re @ R.T).magnitude())
+        tdir.append(math.acos(np.clip(te @ t / np.linalg.norm(te) / np.linalg.norm(t), -1, 1)))
+    return np.array(rot), np.array(tdir), s
+
+
+def test_window_noise_free_recovery():
+    w = synthflow.make_window("small", 0, noise=False, outliers=False)
+    st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"], oracle.params(n_iters=2))
+    assert st == 0
+    rot, tdir, s = _pose_errors(poses, w["poses"])
+    assert abs(np.linalg.norm(poses[0, 9:]) - 1) < 1e-12          # gauge
+    # limits: float32 flows and bilinear interpolation of the flow fields
+    assert rot.max() < 1e-3 and tdir.max() < 2e-2
+    rel = np.abs(depth * s - w["depth"]) / w["depth"]
+    assert np.median(rel) < 1e-2
+    assert np.median(rig) > 0.99
+
+
+def test_window_outliers_flagged():
+    w = synthflow.make_window("small", 0, noise=True, outliers=True)
+    st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"], oracle.params(n_iters=3))
+    assert st == 0
+    rot, tdir, s = _pose_errors(poses, w["poses"])
+    assert rot.max() < 5e-3 and tdir.max() < 0.2
+    out = w["outlier"]
+    assert np.mean(rig[out] < 0.5) > 0.8           # moving regions get low rigidness
+    assert np.mean(rig[~out] > 0.5) > 0.8
+    assert ll[1] >= abs(ll[0])
+
+
+def test_window_invalid_arguments():
+    w = synthflow.make_window("small", 0, T=1, H=20, W=20)
+    p = oracle.params()
+    p.struct_size = 3
+    assert oracle.window(w["flows"], w["K"], p)[0] == -1
+    assert oracle.window(w["flows"], (0, 1, 1, 1), oracle.params())[0] == -1
+    assert oracle.window(w["flows"], w["K"], oracle.params(gamma=1.0))[0] == -1
+    small = np.zeros((1, 8, 8, 2), np.float32)
+    assert oracle.window(small, w["K"], oracle.params())[0] == -1
