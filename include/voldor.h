@@ -1,0 +1,160 @@
+/*
+ * voldor.h -- C ABI of the MI355X (gfx950) window solver of VOLDOR
+ * (Min, Yang, Dunn, "VOLDOR: Visual Odometry from Log-logistic Dense Optical
+ * flow Residuals", CVPR 2020).
+ *
+ * The library infers, from T externally computed dense optical-flow fields
+ * X_1..X_T (X_t maps image I_{t-1} to I_t; problem statement, Sec. 3), the
+ * relative camera poses T_1..T_T, the depth map theta of the first frame and
+ * the per-frame rigidness maps W_1..W_T, by the generalized-EM loop of
+ * Table 1: bootstrap; then per iteration the pose of every frame (Eq. 15-19),
+ * the rigidness E-step by forward-backward on image rows/columns (Eq. 11-14),
+ * the depth M-step by the maximum-inlier criterion with sampling and
+ * propagation (Eq. 10, Fig. 5), and the unsmoothed rigidness.
+ *
+ * Conventions shared by every entry point
+ *   - pixel j = (x, y), integer pixel centres, index j = y*W + x;
+ *   - flows: float32 [T][H][W][2], (u, v) = displacement in pixels of pixel
+ *     (x, y) of image t-1; non-finite components mark a missing observation;
+ *   - poses: 12 doubles, row-major R (9) then t (3); a point moves as
+ *     P_t = R P_{t-1} + t (relative pose of frame t to frame t-1);
+ *   - depth: z-depth along K^-1 [x y 1]^T, in units of |t_1| (= 1);
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns all buffers; nothing
+ *     is retained after a call returns.
+ *   - every call returns a voldor_status; nothing throws across the ABI.
+ *     VOLDOR_EINVAL leaves all outputs untouched.
+ */
+#ifndef VOLDOR_H
+#define VOLDOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VOLDOR_OK = 0,
+    VOLDOR_EINVAL = -1,      /* bad argument: null pointer, size, parameter range   */
+    VOLDOR_ENOMEM = -2,      /* device allocation failed (voldor_create only)       */
+    VOLDOR_EDEVICE = -3,     /* a HIP runtime call failed                            */
+    VOLDOR_EDEGENERATE = -4  /* bootstrap impossible: < 8 usable flows in X_1, or no */
+                             /* finite epipolar hypothesis, or no valid depth       */
+} voldor_status;
+
+/* Solver parameters.  struct_size must equal sizeof(voldor_params).
+ * Defaults (voldor_params_default) follow the paper's experiments: lambda =
+ * 0.15, gamma = 0.9, kernel covariance diag(0.1 I3, 0.004 I3), a1 = 0.01,
+ * a2 = 0.09, b1 = -0.0022, b2 = 1.0 (Sec. 6.1). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t n_iters;           /* EM iterations (Table 1 loop)                       */
+    int32_t sweeps_per_iter;   /* directional sweeps per iteration: L>R,T>B,R>L,B>T */
+    int32_t n_pose_groups;     /* S: P3P groups per frame (Eq. 16), <= 8192          */
+    int32_t n_seeds;           /* mean-shift start candidates from the samples, <=255*/
+    int32_t ms_max_iters;      /* mean-shift iteration cap                           */
+    int32_t lmeds_hypotheses;  /* bootstrap 8-point hypotheses, <= 4096              */
+    int32_t lmeds_eval_pixels; /* bootstrap residual subset, 8..16384                */
+    double ms_tol;             /* mean-shift stop: Mahalanobis length of the step    */
+    double a1, a2, b1, b2;     /* Fisk scale A(v) = a1 exp(a2|v|), shape B(v) = b1|v|+b2 (Eq. 6-7) */
+    double lambda;             /* outlier density: Fisk at EPE = lambda |v| (Eq. 8)  */
+    double gamma;              /* rigidness transition probability (Eq. 11), [0.5,1)*/
+    double sigma2_trans;       /* kernel covariance, translation variance (Eq. 18)   */
+    double sigma2_rot;         /* kernel covariance, rotation variance (Eq. 18)      */
+    double beta_min;           /* floor applied to B(v)                               */
+    double x_floor;            /* floor applied to squared residuals (px^2)           */
+    double depth_lo, depth_hi; /* > 0: fixed depth sampling range; 0: from bootstrap */
+    uint64_t seed;             /* Philox4x64-10 key word 0 of every random draw      */
+} voldor_params;
+
+/* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
+ * 100 mean-shift iterations, tol 1e-8, 512 hypotheses, 16384 eval pixels,
+ * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0). */
+void voldor_params_default(voldor_params *p);
+
+/* Static description of a status code. */
+const char *voldor_status_str(int status);
+
+/* Opaque solver context: owns the device workspace for windows up to
+ * T_max x H_max x W_max with at most S_max pose groups per frame, on the device
+ * current at creation.  T_max <= 16, 16 <= H_max, W_max <= 4096.
+ * Returns VOLDOR_ENOMEM / VOLDOR_EDEVICE on allocation failure. */
+typedef struct voldor_ctx voldor_ctx;
+int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max);
+void voldor_destroy(voldor_ctx *ctx);
+
+/* Solve one window (Table 1).
+ *   flows     device float32 [T][H][W][2], 8-byte aligned
+ *   K         host double[4] = fx, fy, cx, cy (pixels)
+ *   p         host parameters
+ *   poses     device double [T][12], relative poses T_1..T_T (output)
+ *   depth     device float  [H][W], depth of frame 0 (output)
+ *   rigidness device float  [T][H][W], final unsmoothed W_t (output)
+ *   loglik    device double [2] or NULL: log-likelihood of Eq. 3 under the final
+ *             rigidness, and the L1 mass of its terms (output)
+ *   stream    hipStream_t (NULL = default stream)
+ * Work is enqueued on `stream`; the call waits for it to finish and returns
+ * the device-side status (VOLDOR_EDEGENERATE leaves the outputs unspecified).
+ * Calls that share a context must not overlap. */
+int voldor_window(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                  const voldor_params *p, double *poses, float *depth, float *rigidness,
+                  double *loglik, void *stream);
+
+/* ---- step entry points: one step of the loop on explicit state ----------- */
+
+/* Philox4x64-10 (Salmon et al., SC'11) on n counters: ctr, out device
+ * uint64 [n][4]; key = (key0, key1). */
+int voldor_philox(const uint64_t *ctr, uint64_t key0, uint64_t key1, uint64_t *out, int n,
+                  void *stream);
+
+/* Emission of Eq. 2-8 for the depth map theta (device float [H][W]) under the
+ * cumulative poses M (host double [T+1][12], M_0 = I): r = rho/(rho+mu),
+ * ell = log r, log rho, log mu, each device float [T][H][W] (any may be NULL).
+ * Missing observations give r = 1/2, ell = log 1/2, logrho = logmu = 0. */
+int voldor_emission(voldor_ctx *ctx, const float *theta, const float *flows, int T, int H, int W,
+                    const double *K, const voldor_params *p, const double *M, float *r, float *ell,
+                    float *logrho, float *logmu, void *stream);
+
+/* One directional sweep (E-step forward-backward on the chains of direction
+ * dir, then the MIE depth walk with q held fixed; Eq. 10-14, Fig. 5).
+ *   theta_in / theta_out  device float [H][W] (may alias)
+ *   M        host double [T+1][12] cumulative poses
+ *   d_lo, d_hi  depth sampling range; global_sweep = it*sweeps_per_iter + s
+ *   dir      0 left->right (rows), 1 top->bottom (columns), 2 right->left, 3 bottom->top
+ *   q_out    device float [T][H][W] or NULL: smoothed rigidness of the E-step */
+int voldor_sweep(voldor_ctx *ctx, const float *theta_in, float *theta_out, const float *flows,
+                 int T, int H, int W, const double *K, const voldor_params *p, const double *M,
+                 double d_lo, double d_hi, int64_t global_sweep, int dir, float *q_out,
+                 void *stream);
+
+/* Pose of frame t (1..T) for EM iteration `it` (Eq. 15-19): P3P samples of
+ * S random pixel triples, weighted by the product of their rigidness, mapped
+ * to se(3), mode by Gaussian mean-shift.
+ *   theta     device float [H][W]; rig device float [T][H][W] or NULL (all 1)
+ *   M         host double [T+1][12] (M_{t-1} is used)
+ *   prevT     host double[12] or NULL: previous estimate of T_t (also returned
+ *             when no sample carries weight)
+ *   T_out     host double[12] (output)
+ *   samples   device double [4S][8] or NULL: (p[6], weight, valid) per group slot
+ *   diag      host int[4] or NULL: samples, valid groups, mean-shift iterations,
+ *             fallback flag */
+int voldor_pose_step(voldor_ctx *ctx, const float *theta, const float *rig, const float *flows,
+                     int T, int H, int W, const double *K, const voldor_params *p, const double *M,
+                     int t, int it, const double *prevT, double *T_out, double *samples, int *diag,
+                     void *stream);
+
+/* Bootstrap (Sec. 5.3): T_1 by least median of squares over 8-point
+ * essential-matrix hypotheses of X_1, depth by two-view triangulation, the
+ * depth sampling range [0.5 P1, 2 P99] of the triangulated depths.
+ *   relT   host double[12] (output); theta device float [H][W] (output);
+ *   range  host double[2] (output); info host double[4] or NULL: best
+ *          hypothesis, its median Sampson residual, valid depths, cheirality count */
+int voldor_bootstrap(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                     const voldor_params *p, double *relT, float *theta, double *range,
+                     double *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOLDOR_H */

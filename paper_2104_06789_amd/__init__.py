@@ -1,0 +1,253 @@
+"""MI355X (gfx950) window solver of VOLDOR (Min, Yang, Dunn, CVPR 2020).
+
+Thin ctypes binding of ``libvoldor.so`` (C ABI in ``include/voldor.h``).  The
+binding only marshals arguments: every step of the solver runs in the HIP
+kernels of the library.  PyTorch provides device memory and streams.  If the
+library has not been built, importing the native layer raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["Params", "default_params", "Solver", "philox", "lib", "status_str", "VoldorError"]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libvoldor.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EDEGENERATE = 0, -1, -2, -3, -4
+
+
+class VoldorError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    """Mirror of voldor_params (include/voldor.h)."""
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("n_iters", C.c_int32), ("sweeps_per_iter", C.c_int32),
+        ("n_pose_groups", C.c_int32), ("n_seeds", C.c_int32), ("ms_max_iters", C.c_int32),
+        ("lmeds_hypotheses", C.c_int32), ("lmeds_eval_pixels", C.c_int32),
+        ("ms_tol", C.c_double), ("a1", C.c_double), ("a2", C.c_double), ("b1", C.c_double),
+        ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
+        ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
+        ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvoldor.so; raises if it was not built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {_LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(_LIB_PATH)
+    vp, i, d, f = C.c_void_p, C.c_int, C.c_double, C.c_float
+    P = C.POINTER(Params)
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int)
+    sig = {
+        "voldor_params_default": (None, [P]),
+        "voldor_status_str": (C.c_char_p, [i]),
+        "voldor_create": (i, [C.POINTER(vp), i, i, i, i]),
+        "voldor_destroy": (None, [vp]),
+        "voldor_window": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp]),
+        "voldor_philox": (i, [vp, C.c_uint64, C.c_uint64, vp, i, vp]),
+        "voldor_emission": (i, [vp, vp, vp, i, i, i, dp, P, dp, vp, vp, vp, vp, vp]),
+        "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
+        "voldor_pose_step": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, i, i, dp, dp, vp, ip, vp]),
+        "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def status_str(code):
+    try:
+        return lib().voldor_status_str(int(code)).decode()
+    except RuntimeError:
+        return str(code)
+
+
+def default_params(**kw):
+    p = Params()
+    lib().voldor_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _dbl(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(code, what):
+    if code != OK:
+        raise VoldorError(code, what)
+
+
+def _flows(flows):
+    import torch
+    if not (isinstance(flows, torch.Tensor) and flows.is_cuda and flows.dtype == torch.float32):
+        raise TypeError("flows must be a float32 CUDA tensor [T,H,W,2]")
+    if flows.dim() != 4 or flows.shape[3] != 2 or not flows.is_contiguous():
+        raise ValueError("flows must be contiguous [T,H,W,2]")
+    return flows
+
+
+class Solver:
+    """A context of the HIP library sized for windows up to T_max x H_max x W_max."""
+
+    def __init__(self, T_max, H_max, W_max, S_max=4096):
+        import torch
+        torch.cuda.init()
+        self._ctx = C.c_void_p()
+        _check(lib().voldor_create(C.byref(self._ctx), T_max, H_max, W_max, S_max), "voldor_create")
+        self.T_max, self.H_max, self.W_max, self.S_max = T_max, H_max, W_max, S_max
+
+    def close(self):
+        if self._ctx:
+            lib().voldor_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- whole window --------------------------------------------------------
+    def window(self, flows, K, params, out=None, stream=None, want_loglik=True):
+        """Solve one window.  Returns (poses [T,12] f64, depth [H,W] f32,
+        rigidness [T,H,W] f32, loglik [2] f64 or None), all CUDA tensors."""
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        dev = flows.device
+        if out is None:
+            out = (torch.empty((T, 12), dtype=torch.float64, device=dev),
+                   torch.empty((H, W), dtype=torch.float32, device=dev),
+                   torch.empty((T, H, W), dtype=torch.float32, device=dev),
+                   torch.empty(2, dtype=torch.float64, device=dev) if want_loglik else None)
+        poses, depth, rig, ll = out
+        Kd, Kp = _dbl(K)
+        rc = lib().voldor_window(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(poses),
+                                 _ptr(depth), _ptr(rig), _ptr(ll), _stream(stream))
+        _check(rc, "voldor_window")
+        return poses, depth, rig, ll
+
+    def window_status(self, flows, K, params, stream=None):
+        """Like window() but returns the status code instead of raising."""
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        dev = flows.device
+        poses = torch.zeros((T, 12), dtype=torch.float64, device=dev)
+        depth = torch.zeros((H, W), dtype=torch.float32, device=dev)
+        rig = torch.zeros((T, H, W), dtype=torch.float32, device=dev)
+        Kd, Kp = _dbl(K)
+        return lib().voldor_window(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(poses),
+                                   _ptr(depth), _ptr(rig), None, _stream(stream))
+
+    # -- single steps ---------------------------------------------------------
+    def emission(self, theta, flows, K, params, M, stream=None):
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        outs = [torch.empty((T, H, W), dtype=torch.float32, device=flows.device) for _ in range(4)]
+        Kd, Kp = _dbl(K)
+        Md, Mp = _dbl(M)
+        th = theta.to(torch.float32).contiguous()
+        rc = lib().voldor_emission(self._ctx, _ptr(th), _ptr(flows), T, H, W, Kp, C.byref(params), Mp,
+                                   *[_ptr(o) for o in outs], _stream(stream))
+        _check(rc, "voldor_emission")
+        return outs
+
+    def sweep(self, theta, flows, K, params, M, d_lo, d_hi, global_sweep, direction, want_q=False,
+              stream=None):
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        th = theta.to(torch.float32).contiguous()
+        out = torch.empty_like(th)
+        q = torch.empty((T, H, W), dtype=torch.float32, device=flows.device) if want_q else None
+        Kd, Kp = _dbl(K)
+        Md, Mp = _dbl(M)
+        rc = lib().voldor_sweep(self._ctx, _ptr(th), _ptr(out), _ptr(flows), T, H, W, Kp, C.byref(params),
+                                Mp, float(d_lo), float(d_hi), int(global_sweep), int(direction), _ptr(q),
+                                _stream(stream))
+        _check(rc, "voldor_sweep")
+        return out, q
+
+    def pose_step(self, theta, rig, flows, K, params, M, t, it, prevT=None, want_samples=False,
+                  stream=None):
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        th = theta.to(torch.float32).contiguous()
+        rg = rig.to(torch.float32).contiguous() if rig is not None else None
+        samples = (torch.zeros((4 * params.n_pose_groups, 8), dtype=torch.float64, device=flows.device)
+                   if want_samples else None)
+        Kd, Kp = _dbl(K)
+        Md, Mp = _dbl(M)
+        Tout = np.zeros(12)
+        diag = (C.c_int * 4)()
+        if prevT is not None:
+            pv, pp = _dbl(prevT)
+        else:
+            pv, pp = None, None
+        rc = lib().voldor_pose_step(self._ctx, _ptr(th), _ptr(rg), _ptr(flows), T, H, W, Kp, C.byref(params),
+                                    Mp, int(t), int(it), pp, Tout.ctypes.data_as(C.POINTER(C.c_double)),
+                                    _ptr(samples), diag, _stream(stream))
+        _check(rc, "voldor_pose_step")
+        return Tout, samples, list(diag)
+
+    def bootstrap(self, flows, K, params, stream=None):
+        """Returns (status, relT [12], theta [H,W] CUDA f32, range [2], info [4])."""
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        theta = torch.empty((H, W), dtype=torch.float32, device=flows.device)
+        rel, rng, info = np.zeros(12), np.zeros(2), np.zeros(4)
+        Kd, Kp = _dbl(K)
+        rc = lib().voldor_bootstrap(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params),
+                                    rel.ctypes.data_as(C.POINTER(C.c_double)), _ptr(theta),
+                                    rng.ctypes.data_as(C.POINTER(C.c_double)),
+                                    info.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream))
+        return rc, rel, theta, rng, info
+
+
+def philox(ctr, key0, key1, stream=None):
+    """Philox4x64-10 of a CUDA int64 tensor of counters [n,4] (bit patterns)."""
+    import torch
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    _check(lib().voldor_philox(_ptr(ctr), int(key0), int(key1), _ptr(out), ctr.shape[0], _stream(stream)),
+           "voldor_philox")
+    return out

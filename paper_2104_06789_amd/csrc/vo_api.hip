@@ -1,0 +1,367 @@
+// vo_api.hip -- the C ABI (include/voldor.h): argument checking, context
+// workspace, and the launch sequence of one window (Table 1):
+//   bootstrap; for each iteration: pose of frames 1..T in order, the
+//   directional sweeps, the unsmoothed rigidness, the scale gauge;
+//   finally the log-likelihood.
+// All launches go to the caller's stream; only voldor_window's final status
+// read and the host outputs of the step entry points synchronise.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "vo_internal.hpp"
+
+using namespace vo;
+
+namespace {
+
+__global__ void k_reset_status(int *status)
+{
+    if (threadIdx.x == 0) *status = kStatusOk;
+}
+
+bool params_ok(const voldor_params *p)
+{
+    if (!p || p->struct_size != sizeof(voldor_params)) return false;
+    if (p->n_iters < 1 || p->sweeps_per_iter < 1) return false;
+    if (p->n_pose_groups < 1 || p->n_pose_groups > kMaxGroups) return false;
+    if (p->n_seeds < 1 || p->n_seeds > kMaxSeeds || p->ms_max_iters < 0) return false;
+    if (p->lmeds_hypotheses < 1 || p->lmeds_hypotheses > kMaxHyp) return false;
+    if (p->lmeds_eval_pixels < 8 || p->lmeds_eval_pixels > kEvalThreads * kEvalPerThread) return false;
+    if (!(p->gamma >= 0.5 && p->gamma < 1.0) || !(p->lambda > 0) || !(p->a1 > 0)) return false;
+    if (!isfinite(p->a2) || !isfinite(p->b1) || !isfinite(p->b2)) return false;
+    if (!(p->sigma2_trans > 0) || !(p->sigma2_rot > 0)) return false;
+    if (!(p->beta_min > 0) || !(p->x_floor > 0) || !(p->ms_tol >= 0)) return false;
+    if (!(p->depth_lo >= 0) || !(p->depth_hi >= 0)) return false;
+    if (p->depth_lo > 0 && p->depth_hi > 0 && !(p->depth_hi > p->depth_lo)) return false;
+    return true;
+}
+
+bool dims_ok(const voldor_ctx *c, int T, int H, int W)
+{
+    if (!c) return false;
+    if (T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max) return false;
+    const int Lmax = H > W ? H : W;
+    if (Lmax > kBlock * kMaxPerThread) return false;
+    const int Tb = T;
+    if (kBlock / Tb < 1) return false;
+    if ((int)sweep_lds_bytes(T, W) > c->max_lds || (int)sweep_lds_bytes(T, H) > c->max_lds) return false;
+    return true;
+}
+
+bool K_ok(const double *K)
+{
+    return K && K[0] > 0 && K[1] > 0 && isfinite(K[0]) && isfinite(K[1]) && isfinite(K[2]) &&
+           isfinite(K[3]);
+}
+
+WinDims dims(int T, int H, int W, const double *K)
+{
+    WinDims d;
+    d.T = T;
+    d.H = H;
+    d.W = W;
+    d.use_w = 0;
+    d.fx = K[0];
+    d.fy = K[1];
+    d.cx = K[2];
+    d.cy = K[3];
+    return d;
+}
+
+EmisParams emis(const double *K, const voldor_params *p)
+{
+    EmisParams e;
+    e.fx = (float)K[0];
+    e.fy = (float)K[1];
+    e.cx = (float)K[2];
+    e.cy = (float)K[3];
+    e.log_a1 = (float)log(p->a1);
+    e.a2 = (float)p->a2;
+    e.b1 = (float)p->b1;
+    e.b2 = (float)p->b2;
+    e.lam2 = (float)(p->lambda * p->lambda);
+    e.beta_min = (float)p->beta_min;
+    e.x_floor = (float)p->x_floor;
+    e.pad = 0.0f;
+    return e;
+}
+
+PoseParams pose_params(const voldor_params *p)
+{
+    PoseParams pp;
+    pp.S = p->n_pose_groups;
+    pp.n_seeds = p->n_seeds;
+    pp.ms_max_iters = p->ms_max_iters;
+    pp.pad = 0;
+    pp.ms_tol = p->ms_tol;
+    pp.s2t = p->sigma2_trans;
+    pp.s2r = p->sigma2_rot;
+    pp.seed = p->seed;
+    return pp;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, n * sizeof(T) + 16);
+}
+
+int upload_M(voldor_ctx *c, const double *M, int T, hipStream_t s)
+{
+    if (hipMemcpyAsync(c->Mcum, M, sizeof(double) * 12 * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    return launch_frames(c, T, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void voldor_params_default(voldor_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(voldor_params);
+    p->n_iters = 3;
+    p->sweeps_per_iter = 4;
+    p->n_pose_groups = 256;
+    p->n_seeds = 64;
+    p->ms_max_iters = 100;
+    p->lmeds_hypotheses = 512;
+    p->lmeds_eval_pixels = 16384;
+    p->ms_tol = 1e-8;
+    p->a1 = 0.01;
+    p->a2 = 0.09;
+    p->b1 = -0.0022;
+    p->b2 = 1.0;
+    p->lambda = 0.15;
+    p->gamma = 0.9;
+    p->sigma2_trans = 0.1;
+    p->sigma2_rot = 0.004;
+    p->beta_min = 0.01;
+    p->x_floor = 1e-12;
+    p->depth_lo = 0.0;
+    p->depth_hi = 0.0;
+    p->seed = 0;
+}
+
+const char *voldor_status_str(int status)
+{
+    switch (status) {
+    case VOLDOR_OK: return "ok";
+    case VOLDOR_EINVAL: return "invalid argument";
+    case VOLDOR_ENOMEM: return "device allocation failed";
+    case VOLDOR_EDEVICE: return "HIP runtime error";
+    case VOLDOR_EDEGENERATE: return "degenerate bootstrap";
+    default: return "unknown status";
+    }
+}
+
+int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
+{
+    if (!out) return VOLDOR_EINVAL;
+    *out = nullptr;
+    if (T_max < 1 || T_max > kTMax || H_max < 16 || W_max < 16 || H_max > 4096 || W_max > 4096 ||
+        S_max < 1 || S_max > kMaxGroups)
+        return VOLDOR_EINVAL;
+    voldor_ctx *c = (voldor_ctx *)calloc(1, sizeof(voldor_ctx));
+    if (!c) return VOLDOR_ENOMEM;
+    if (hipGetDevice(&c->device) != hipSuccess) { free(c); return VOLDOR_EDEVICE; }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
+        free(c);
+        return VOLDOR_EDEVICE;
+    }
+    // static LDS of the sweep kernel (frames + segment scan) comes off the top
+    c->max_lds = lds - (int)(sizeof(FrameF) * (kTMax + 1) + 12 * kBlock * sizeof(float)) - 256;
+    c->T_max = T_max;
+    c->H_max = H_max;
+    c->W_max = W_max;
+    c->S_max = S_max;
+    const size_t HW = (size_t)H_max * W_max;
+    bool ok = true;
+    ok = ok && dalloc(&c->Mcum, 12 * (T_max + 1)) == hipSuccess;
+    ok = ok && dalloc(&c->frames, T_max + 1) == hipSuccess;
+    ok = ok && dalloc(&c->range, 4) == hipSuccess;
+    ok = ok && dalloc(&c->status, 8) == hipSuccess;
+    ok = ok && dalloc(&c->samples, (size_t)8 * 4 * S_max) == hipSuccess;
+    ok = ok && dalloc(&c->seed_score, (size_t)8 * (kMaxSeeds + 1)) == hipSuccess;
+    ok = ok && dalloc(&c->pose_diag, 4 * T_max) == hipSuccess;
+    ok = ok && dalloc(&c->hyp, (size_t)18 * kMaxHyp) == hipSuccess;
+    ok = ok && dalloc(&c->hyp_score, kMaxHyp) == hipSuccess;
+    ok = ok && dalloc(&c->boot_info, 4) == hipSuccess;
+    ok = ok && dalloc(&c->dkeys, HW) == hipSuccess;
+    ok = ok && dalloc(&c->hist, 3 * 256) == hipSuccess;
+    ok = ok && dalloc(&c->sel, 16) == hipSuccess;
+    ok = ok && dalloc(&c->ll_part, 2 * kLLBlocks) == hipSuccess;
+    ok = ok && dalloc(&c->prev_pose, 12) == hipSuccess;
+    ok = ok && dalloc(&c->pose_tmp, 16) == hipSuccess;
+    ok = ok && dalloc(&c->rel_tmp, 12 * T_max) == hipSuccess;
+    ok = ok && dalloc(&c->theta_tmp, HW) == hipSuccess;
+    if (!ok) {
+        voldor_destroy(c);
+        return VOLDOR_ENOMEM;
+    }
+    if (hipMemset(c->status, 0, 8 * sizeof(int)) != hipSuccess ||
+        hipMemset(c->pose_diag, 0, 4 * T_max * sizeof(int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        voldor_destroy(c);
+        return VOLDOR_EDEVICE;
+    }
+    *out = c;
+    return VOLDOR_OK;
+}
+
+void voldor_destroy(voldor_ctx *c)
+{
+    if (!c) return;
+    void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
+                    c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->dkeys, c->hist,
+                    c->sel, c->ll_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    free(c);
+}
+
+int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                  const voldor_params *p, double *poses, float *depth, float *rigidness,
+                  double *loglik, void *stream)
+{
+    if (!c || !flows || !poses || !depth || !rigidness) return VOLDOR_EINVAL;
+    if (((uintptr_t)flows & 7) != 0) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (p->n_pose_groups > c->S_max) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const float2 *X = (const float2 *)flows;
+    WinDims d = dims(T, H, W, K);
+    const EmisParams e = emis(K, p);
+    const PoseParams pp = pose_params(p);
+    int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
+                              p->depth_lo, p->depth_hi, poses, depth, s);
+    for (int it = 0; it < p->n_iters && rc == 0; ++it) {
+        d.use_w = it > 0;
+        for (int t = 1; t <= T && rc == 0; ++t)
+            rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0,
+                                  poses, s);
+        if (rc == 0) rc = launch_frames(c, T, s);
+        for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw) {
+            const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
+            rc = launch_sweep(c, depth, depth, X, d, e, (float)p->gamma, p->seed, gs, (int)(gs % 4),
+                              c->range, nullptr, s);
+        }
+        if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, rigidness, nullptr, nullptr, nullptr, nullptr, s);
+        if (rc == 0) rc = launch_gauge(c, poses, depth, d, s);
+    }
+    if (rc == 0 && loglik) {
+        rc = launch_frames(c, T, s);
+        if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, loglik, s);
+    }
+    if (rc != 0) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
+    int st = 0;
+    if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
+    return st;
+}
+
+int voldor_philox(const uint64_t *ctr, uint64_t key0, uint64_t key1, uint64_t *out, int n, void *stream)
+{
+    if (!ctr || !out || n < 0) return VOLDOR_EINVAL;
+    const int rc = launch_philox(ctr, key0, key1, out, n, (hipStream_t)stream);
+    if (rc) return rc;
+    return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+int voldor_emission(voldor_ctx *c, const float *theta, const float *flows, int T, int H, int W,
+                    const double *K, const voldor_params *p, const double *M, float *r, float *ell,
+                    float *logrho, float *logmu, void *stream)
+{
+    if (!c || !theta || !flows || !M) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
+    int rc = upload_M(c, M, T, s);
+    if (rc == 0)
+        rc = launch_rigidness(c, theta, (const float2 *)flows, dims(T, H, W, K), emis(K, p), r, ell,
+                              logrho, logmu, nullptr, s);
+    if (rc) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float *flows, int T,
+                 int H, int W, const double *K, const voldor_params *p, const double *M, double d_lo,
+                 double d_hi, int64_t global_sweep, int dir, float *q_out, void *stream)
+{
+    if (!c || !theta_in || !theta_out || !flows || !M) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (dir < 0 || dir > 3 || !(d_lo > 0) || !(d_hi > d_lo) || global_sweep < 0) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double rng[4] = {d_lo, d_hi, 1.0, 0.0};
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
+    if (hipMemcpyAsync(c->range, rng, sizeof rng, hipMemcpyHostToDevice, s) != hipSuccess) return VOLDOR_EDEVICE;
+    int rc = upload_M(c, M, T, s);
+    if (rc == 0)
+        rc = launch_sweep(c, theta_in, theta_out, (const float2 *)flows, dims(T, H, W, K), emis(K, p),
+                          (float)p->gamma, p->seed, global_sweep, dir, c->range, q_out, s);
+    if (rc) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+int voldor_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float *flows, int T,
+                     int H, int W, const double *K, const voldor_params *p, const double *M, int t,
+                     int it, const double *prevT, double *T_out, double *samples, int *diag,
+                     void *stream)
+{
+    if (!c || !theta || !flows || !M || !T_out) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (t < 1 || t > T || it < 0 || p->n_pose_groups > c->S_max) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
+    if (hipMemcpyAsync(c->Mcum, M, sizeof(double) * 12 * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    // previous estimate of T_t (or identity as the fallback of the frame before)
+    double ident[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+    const double *pv = prevT ? prevT : ident;
+    if (hipMemcpyAsync(c->rel_tmp + 12 * (t - 1), pv, sizeof ident, hipMemcpyHostToDevice, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    if (t >= 2 && hipMemcpyAsync(c->rel_tmp + 12 * (t - 2), ident, sizeof ident, hipMemcpyHostToDevice, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    WinDims d = dims(T, H, W, K);
+    d.use_w = rig ? 1 : 0;
+    int rc = launch_pose_step(c, theta, rig, (const float2 *)flows, d, pose_params(p), t, it,
+                              prevT ? 1 : 0, c->rel_tmp, s);
+    if (rc) return rc;
+    if (samples &&
+        hipMemcpyAsync(samples, c->samples, sizeof(double) * 32 * p->n_pose_groups, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
+    if (hipMemcpy(T_out, c->rel_tmp + 12 * (t - 1), sizeof(double) * 12, hipMemcpyDeviceToHost) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    if (diag && hipMemcpy(diag, c->pose_diag + 4 * (t - 1), sizeof(int) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    return VOLDOR_OK;
+}
+
+int voldor_bootstrap(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                     const voldor_params *p, double *relT, float *theta, double *range, double *info,
+                     void *stream)
+{
+    if (!c || !flows || !relT || !theta || !range) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = launch_bootstrap(c, (const float2 *)flows, dims(T, H, W, K), p->lmeds_hypotheses,
+                              p->lmeds_eval_pixels, p->seed, p->depth_lo, p->depth_hi, c->rel_tmp, theta, s);
+    if (rc) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
+    int st = 0;
+    if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
+    if (st != VOLDOR_OK) return st;
+    if (hipMemcpy(relT, c->rel_tmp, sizeof(double) * 12, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(range, c->range, sizeof(double) * 2, hipMemcpyDeviceToHost) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    if (info && hipMemcpy(info, c->boot_info, sizeof(double) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    return VOLDOR_OK;
+}
+
+}  // extern "C"

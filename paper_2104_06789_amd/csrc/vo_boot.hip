@@ -1,0 +1,561 @@
+// vo_boot.hip -- FP64 bootstrap of a window (Sec. 5.3, Table 1):
+//   k_boot_hyp     8-point essential-matrix hypotheses from random
+//                  correspondences x <-> x + X_1(x) (null vector of the 8x9
+//                  epipolar system by fully pivoted elimination), projected
+//                  onto the essential manifold U diag(1,1,0) V^T;
+//   k_boot_score   least median of squares: exact lower median of the
+//                  pixel-space Sampson distances over a fixed pixel subset,
+//                  by radix selection on the residuals held in registers;
+//   k_boot_pick    best hypothesis, its four (R, +-t) decompositions and the
+//                  cheirality vote -> T_1 with |t_1| = 1;
+//   k_boot_tri     two-view triangulation of every pixel along its frame-0 ray;
+//   k_hist/_pick   radix selection of the 1st, 50th and 99th percentile depth;
+//   k_boot_final   invalid depths -> median, clamp to [0.5 P1, 2 P99].
+#include "vo_internal.hpp"
+
+namespace vo {
+
+__device__ __forceinline__ bool flow_present(const float2 *X1, int64_t j)
+{
+    const float2 f = X1[j];
+    return isfinite(f.x) && isfinite(f.y);
+}
+
+// symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations; columns of V
+__device__ void eig3_sym(const double *S_in, double *w, double *V)
+{
+    double S[9];
+    for (int i = 0; i < 9; ++i) { S[i] = S_in[i]; V[i] = (i == 0 || i == 4 || i == 8) ? 1.0 : 0.0; }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        const double off = S[1] * S[1] + S[2] * S[2] + S[5] * S[5];
+        const double dia = S[0] * S[0] + S[4] * S[4] + S[8] * S[8];
+        if (off <= 1e-32 * dia || off == 0.0) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const double spq = S[3 * p + q];
+            if (spq == 0.0) continue;
+            const double tau = (S[3 * q + q] - S[3 * p + p]) / (2.0 * spq);
+            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
+            for (int k = 0; k < 3; ++k) {  // columns p, q of S
+                const double a = S[3 * k + p], b = S[3 * k + q];
+                S[3 * k + p] = cs * a - sn * b;
+                S[3 * k + q] = sn * a + cs * b;
+            }
+            for (int k = 0; k < 3; ++k) {  // rows p, q of S
+                const double a = S[3 * p + k], b = S[3 * q + k];
+                S[3 * p + k] = cs * a - sn * b;
+                S[3 * q + k] = sn * a + cs * b;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double a = V[3 * k + p], b = V[3 * k + q];
+                V[3 * k + p] = cs * a - sn * b;
+                V[3 * k + q] = sn * a + cs * b;
+            }
+        }
+    }
+    w[0] = S[0];
+    w[1] = S[4];
+    w[2] = S[8];
+}
+
+// Rank-2 factors of E: E ~ u1 v1^T s1 + u2 v2^T s2 with proper rotations
+// U = [u1 u2 u1xu2], V = [v1 v2 v1xv2] (columns, row-major storage).
+__device__ void essential_factors(const double *E, double *U, double *V)
+{
+    double EtE[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            EtE[3 * i + j] = E[i] * E[j] + E[3 + i] * E[3 + j] + E[6 + i] * E[6 + j];
+    double w[3], Q[9];
+    eig3_sym(EtE, w, Q);
+    // order eigen-pairs by decreasing eigenvalue
+    int o[3] = {0, 1, 2};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (w[o[b]] > w[o[a]]) { const int t = o[a]; o[a] = o[b]; o[b] = t; }
+    double v[3][3], u[3][3];
+    for (int c = 0; c < 2; ++c)
+        for (int k = 0; k < 3; ++k) v[c][k] = Q[3 * k + o[c]];
+    cross3d(v[0], v[1], v[2]);
+    for (int c = 0; c < 2; ++c) {
+        mv3(E, v[c], u[c]);
+        const double n = sqrt(dot3d(u[c], u[c]));
+        for (int k = 0; k < 3; ++k) u[c][k] /= (n > 0 ? n : 1.0);
+    }
+    const double dd = dot3d(u[0], u[1]);
+    for (int k = 0; k < 3; ++k) u[1][k] -= dd * u[0][k];
+    const double n1 = sqrt(dot3d(u[1], u[1]));
+    for (int k = 0; k < 3; ++k) u[1][k] /= (n1 > 0 ? n1 : 1.0);
+    cross3d(u[0], u[1], u[2]);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            U[3 * r + c] = u[c][r];
+            V[3 * r + c] = v[c][r];
+        }
+}
+
+struct HypArgs {
+    const float2 *X1;
+    double *hyp;
+    double *score;
+    int H, W, M;
+    double fx, fy, cx, cy;
+    uint64_t seed;
+};
+
+__global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= a.M) return;
+    const int64_t HW = (int64_t)a.H * a.W;
+    int64_t idx[8];
+    bool ok = false;
+    for (int att = 0; att < 16 && !ok; ++att) {
+        uint64_t c[4] = {(uint64_t)h, (uint64_t)att, 0ull, 0ull};
+        philox4x64_10(c, a.seed, kBootStream);
+        ok = true;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t u = (k & 1) ? (uint32_t)(c[k >> 1] >> 32) : (uint32_t)c[k >> 1];
+            idx[k] = u32_to_index(u, HW);
+            ok = ok && flow_present(a.X1, idx[k]);
+            for (int m = 0; m < k; ++m) ok = ok && idx[m] != idx[k];
+        }
+    }
+    a.score[h] = __longlong_as_double(0x7ff0000000000000ll);  // +inf until scored
+    double *out = a.hyp + 18 * h;
+    if (!ok) {
+        out[0] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    // epipolar rows: b^T E a = 0 with a = K^-1 x, b = K^-1 (x + X_1(x))
+    double A[8][9];
+    for (int k = 0; k < 8; ++k) {
+        const int x = (int)(idx[k] % a.W), y = (int)(idx[k] / a.W);
+        const float2 f = a.X1[idx[k]];
+        const double av[3] = {(x - a.cx) / a.fx, (y - a.cy) / a.fy, 1.0};
+        const double bv[3] = {(x + (double)f.x - a.cx) / a.fx, (y + (double)f.y - a.cy) / a.fy, 1.0};
+        for (int i = 0; i < 3; ++i)
+            for (int l = 0; l < 3; ++l) A[k][3 * i + l] = bv[i] * av[l];
+    }
+    // null vector by Gaussian elimination with full pivoting
+    int perm[9];
+    for (int i = 0; i < 9; ++i) perm[i] = i;
+    bool degenerate = false;
+    for (int r = 0; r < 8; ++r) {
+        int pr = r, pc = r;
+        double best = 0.0;
+        for (int i = r; i < 8; ++i)
+            for (int j = r; j < 9; ++j) {
+                const double v = fabs(A[i][j]);
+                if (v > best) { best = v; pr = i; pc = j; }
+            }
+        if (best == 0.0) { degenerate = true; break; }
+        if (pr != r)
+            for (int j = 0; j < 9; ++j) { const double t = A[r][j]; A[r][j] = A[pr][j]; A[pr][j] = t; }
+        if (pc != r) {
+            for (int i = 0; i < 8; ++i) { const double t = A[i][r]; A[i][r] = A[i][pc]; A[i][pc] = t; }
+            const int t = perm[r]; perm[r] = perm[pc]; perm[pc] = t;
+        }
+        for (int i = r + 1; i < 8; ++i) {
+            const double f = A[i][r] / A[r][r];
+            for (int j = r; j < 9; ++j) A[i][j] -= f * A[r][j];
+        }
+    }
+    if (degenerate) {
+        out[0] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    double xp[9];
+    xp[8] = 1.0;
+    for (int r = 7; r >= 0; --r) {
+        double s = 0.0;
+        for (int j = r + 1; j < 9; ++j) s += A[r][j] * xp[j];
+        xp[r] = -s / A[r][r];
+    }
+    double e[9], nrm = 0.0;
+    for (int j = 0; j < 9; ++j) e[perm[j]] = xp[j];
+    for (int j = 0; j < 9; ++j) nrm += e[j] * e[j];
+    nrm = sqrt(nrm);
+    for (int j = 0; j < 9; ++j) e[j] /= nrm;
+    double U[9], V[9], E[9];
+    essential_factors(e, U, V);
+    for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) E[3 * i + l] = U[3 * i] * V[3 * l] + U[3 * i + 1] * V[3 * l + 1];
+    // F = K^-T E K^-1
+    const double Ki[9] = {1.0 / a.fx, 0, -a.cx / a.fx, 0, 1.0 / a.fy, -a.cy / a.fy, 0, 0, 1};
+    double KiT[9], T1[9], F[9];
+    for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) KiT[3 * i + l] = Ki[3 * l + i];
+    mm3(KiT, E, T1);
+    mm3(T1, Ki, F);
+    bool fin = true;
+    for (int i = 0; i < 9; ++i) fin = fin && isfinite(E[i]) && isfinite(F[i]);
+    if (!fin) {
+        out[0] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    for (int i = 0; i < 9; ++i) { out[i] = E[i]; out[9 + i] = F[i]; }
+}
+
+struct ScoreArgs {
+    const float2 *X1;
+    const double *hyp;
+    double *score;
+    int H, W, Ne;
+};
+
+__global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ int cnt_red[kEvalThreads / 64];
+    __shared__ uint64_t s_prefix;
+    __shared__ int s_rank;
+    const int h = blockIdx.x, tid = threadIdx.x;
+    const double *hp = a.hyp + 18 * h;
+    if (isnan(hp[0])) return;  // invalid hypothesis keeps +inf
+    double F[9];
+    for (int i = 0; i < 9; ++i) F[i] = hp[9 + i];
+    const int64_t HW = (int64_t)a.H * a.W;
+    uint64_t key[kEvalPerThread];
+    int n = 0;
+#pragma unroll
+    for (int m = 0; m < kEvalPerThread; ++m) {
+        const int i = tid + m * kEvalThreads;
+        uint64_t kk = ~0ull;
+        if (i < a.Ne) {
+            const int64_t j = ((int64_t)i * HW) / a.Ne;
+            const float2 f = a.X1[j];
+            if (isfinite(f.x) && isfinite(f.y)) {
+                const double x = (double)(j % a.W), y = (double)(j / a.W);
+                const double x2 = x + f.x, y2 = y + f.y;
+                const double Fx0 = F[0] * x + F[1] * y + F[2];
+                const double Fx1 = F[3] * x + F[4] * y + F[5];
+                const double Fx2 = F[6] * x + F[7] * y + F[8];
+                const double Ft0 = F[0] * x2 + F[3] * y2 + F[6];
+                const double Ft1 = F[1] * x2 + F[4] * y2 + F[7];
+                const double e = x2 * Fx0 + y2 * Fx1 + Fx2;
+                const double r = e * e / (Fx0 * Fx0 + Fx1 * Fx1 + Ft0 * Ft0 + Ft1 * Ft1);
+                kk = (uint64_t)__double_as_longlong(r);
+                ++n;
+            }
+        }
+        key[m] = kk;
+    }
+    // count of present pixels in the subset
+    int c = n;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((tid & 63) == 0) cnt_red[tid >> 6] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int tot = 0;
+        for (int i = 0; i < kEvalThreads / 64; ++i) tot += cnt_red[i];
+        s_rank = tot > 0 ? (tot - 1) / 2 : -1;
+        s_prefix = 0;
+    }
+    __syncthreads();
+    if (s_rank < 0) return;  // no usable pixel: the hypothesis keeps +inf
+    uint64_t mask = 0;
+    for (int pass = 7; pass >= 0; --pass) {
+        const int shift = 8 * pass;
+        for (int b = tid; b < 256; b += kEvalThreads) hist[b] = 0;
+        __syncthreads();
+        const uint64_t pre = s_prefix;
+#pragma unroll
+        for (int m = 0; m < kEvalPerThread; ++m)
+            if ((key[m] & mask) == pre) atomicAdd(&hist[(key[m] >> shift) & 255], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            int rank = s_rank;
+            uint32_t cum = 0;
+            int sel = 255;
+            for (int b = 0; b < 256; ++b) {
+                if ((uint32_t)rank < cum + hist[b]) { sel = b; break; }
+                cum += hist[b];
+            }
+            s_rank = rank - (int)cum;
+            s_prefix = pre | ((uint64_t)sel << shift);
+        }
+        mask |= 255ull << shift;
+        __syncthreads();
+    }
+    if (tid == 0) a.score[h] = __longlong_as_double((long long)s_prefix);
+}
+
+struct PickArgs {
+    const float2 *X1;
+    const double *hyp;
+    const double *score;
+    double *rel;        // [T][12]
+    double *Mcum;       // [T+1][12]
+    double *info;       // [4]
+    int *status;
+    int H, W, M, Ne, T;
+    double fx, fy, cx, cy;
+};
+
+__device__ __forceinline__ double tri_depth(const double *R, const double *t, double xn, double yn,
+                                            double bx, double by, bool &ok)
+{
+    const double r[3] = {xn, yn, 1.0};
+    double av[3];
+    mv3(R, r, av);
+    const double c0 = av[0] - bx * av[2], c1 = av[1] - by * av[2];
+    const double e0 = t[0] - bx * t[2], e1 = t[1] - by * t[2];
+    const double cc = c0 * c0 + c1 * c1;
+    const double th = -(c0 * e0 + c1 * e1) / cc;
+    ok = cc >= 1e-12 && th > 0 && isfinite(th);
+    return th;
+}
+
+__global__ void __launch_bounds__(1024) k_boot_pick(PickArgs a)
+{
+    __shared__ int s_best;
+    __shared__ double Rc[2][9], tc[3];
+    __shared__ int red[4][16];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int best = -1;
+        double bs = 0.0;
+        for (int h = 0; h < a.M; ++h) {
+            const double s = a.score[h];
+            if (!isfinite(s)) continue;
+            if (best < 0 || s < bs) { best = h; bs = s; }
+        }
+        s_best = best;
+        if (best < 0) {
+            *a.status = kStatusDegenerate;
+        } else {
+            double U[9], V[9];
+            essential_factors(a.hyp + 18 * best, U, V);
+            const double Wm[9] = {0, -1, 0, 1, 0, 0, 0, 0, 1};
+            const double WmT[9] = {0, 1, 0, -1, 0, 0, 0, 0, 1};
+            double VT[9], T1[9];
+            for (int i = 0; i < 3; ++i)
+                for (int l = 0; l < 3; ++l) VT[3 * i + l] = V[3 * l + i];
+            mm3(U, Wm, T1);
+            mm3(T1, VT, Rc[0]);
+            mm3(U, WmT, T1);
+            mm3(T1, VT, Rc[1]);
+            tc[0] = U[2];
+            tc[1] = U[5];
+            tc[2] = U[8];
+            a.info[0] = best;
+            a.info[1] = bs;
+        }
+    }
+    __syncthreads();
+    if (s_best < 0) return;
+    const int64_t HW = (int64_t)a.H * a.W;
+    int cnt[4] = {0, 0, 0, 0};
+    for (int i = tid; i < a.Ne; i += 1024) {
+        const int64_t j = ((int64_t)i * HW) / a.Ne;
+        const float2 f = a.X1[j];
+        if (!(isfinite(f.x) && isfinite(f.y))) continue;
+        const int x = (int)(j % a.W), y = (int)(j / a.W);
+        const double xn = (x - a.cx) / a.fx, yn = (y - a.cy) / a.fy;
+        const double bx = (x + (double)f.x - a.cx) / a.fx, by = (y + (double)f.y - a.cy) / a.fy;
+        for (int c = 0; c < 4; ++c) {
+            const double *R = Rc[c >> 1];
+            const double sg = (c & 1) ? -1.0 : 1.0;
+            const double t[3] = {sg * tc[0], sg * tc[1], sg * tc[2]};
+            bool ok;
+            const double th = tri_depth(R, t, xn, yn, bx, by, ok);
+            if (!ok) continue;
+            const double z1 = th * (R[6] * xn + R[7] * yn + R[8]) + t[2];
+            if (z1 > 0) ++cnt[c];
+        }
+    }
+    for (int c = 0; c < 4; ++c) {
+        int v = cnt[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if ((tid & 63) == 0) red[c][tid >> 6] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int bc = 0, bn = -1;
+        for (int c = 0; c < 4; ++c) {
+            int tot = 0;
+            for (int i = 0; i < 16; ++i) tot += red[c][i];
+            if (tot > bn) { bn = tot; bc = c; }
+        }
+        const double sg = (bc & 1) ? -1.0 : 1.0;
+        double t[3] = {sg * tc[0], sg * tc[1], sg * tc[2]};
+        const double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        for (int k = 0; k < 9; ++k) a.rel[k] = Rc[bc >> 1][k];
+        for (int k = 0; k < 3; ++k) a.rel[9 + k] = t[k] / tn;
+        for (int tt = 1; tt < a.T; ++tt)
+            for (int k = 0; k < 12; ++k) a.rel[12 * tt + k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+        for (int k = 0; k < 12; ++k) a.Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+        pose_mul(a.rel, a.Mcum, a.Mcum + 12);
+        a.info[3] = bn;
+    }
+}
+
+struct TriArgs {
+    const float2 *X1;
+    const double *rel;
+    float *theta;
+    uint32_t *keys;
+    uint32_t *sel;       // sel[12] accumulates the valid count
+    const int *status;
+    int H, W;
+    double fx, fy, cx, cy;
+};
+
+__global__ void __launch_bounds__(256) k_boot_tri(TriArgs a)
+{
+    if (*a.status != kStatusOk) return;
+    __shared__ int red[4];
+    const int64_t HW = (int64_t)a.H * a.W;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int valid = 0;
+    if (j < HW) {
+        const float2 f = a.X1[j];
+        uint32_t key = 0xffffffffu;
+        float th32 = 0.0f;
+        if (isfinite(f.x) && isfinite(f.y)) {
+            const int x = (int)(j % a.W), y = (int)(j / a.W);
+            bool ok;
+            const double th = tri_depth(a.rel, a.rel + 9, (x - a.cx) / a.fx, (y - a.cy) / a.fy,
+                                        (x + (double)f.x - a.cx) / a.fx, (y + (double)f.y - a.cy) / a.fy, ok);
+            if (ok) {
+                th32 = (float)th;
+                key = __float_as_uint(th32);
+                valid = 1;
+            }
+        }
+        a.theta[j] = th32;
+        a.keys[j] = key;
+    }
+    for (int off = 32; off > 0; off >>= 1) valid += __shfl_down(valid, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = valid;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = red[0] + red[1] + red[2] + red[3];
+        if (tot) atomicAdd(&a.sel[12], (uint32_t)tot);
+    }
+}
+
+// sel layout: [0..2] prefix, [3..5] rank, [6..8] result, [12] valid count
+__global__ void k_sel_init(uint32_t *sel, uint32_t *hist, int *status)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 3 * 256; i += blockDim.x) hist[i] = 0;
+    if (tid == 0) {
+        if (*status != kStatusOk) return;
+        const uint32_t n = sel[12];
+        if (n == 0) { *status = kStatusDegenerate; return; }
+        const double q[3] = {0.01, 0.50, 0.99};
+        for (int i = 0; i < 3; ++i) {
+            sel[i] = 0;
+            sel[3 + i] = (uint32_t)floor(q[i] * (double)(n - 1));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_hist(const uint32_t *keys, int64_t n, const uint32_t *sel,
+                                              uint32_t *hist, int pass, const int *status)
+{
+    if (*status != kStatusOk) return;
+    __shared__ uint32_t lh[3][256];
+    for (int i = threadIdx.x; i < 768; i += 256) (&lh[0][0])[i] = 0;
+    __syncthreads();
+    const int shift = 8 * pass;
+    const uint32_t mask = pass == 3 ? 0u : (0xffffffffu << (shift + 8));
+    const uint32_t p0 = sel[0], p1 = sel[1], p2 = sel[2];
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        const uint32_t k = keys[j];
+        if (k == 0xffffffffu) continue;
+        const uint32_t dgt = (k >> shift) & 255u;
+        const uint32_t km = k & mask;
+        if (km == p0) atomicAdd(&lh[0][dgt], 1u);
+        if (km == p1) atomicAdd(&lh[1][dgt], 1u);
+        if (km == p2) atomicAdd(&lh[2][dgt], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 768; i += 256) {
+        const uint32_t v = (&lh[0][0])[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+__global__ void k_hist_pick(uint32_t *sel, uint32_t *hist, int pass, const int *status)
+{
+    if (*status != kStatusOk) return;
+    const int shift = 8 * pass;
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        uint32_t rank = sel[3 + q], cum = 0;
+        uint32_t b = 255;
+        for (uint32_t i = 0; i < 256; ++i) {
+            const uint32_t h = hist[256 * q + i];
+            if (rank < cum + h) { b = i; break; }
+            cum += h;
+        }
+        sel[3 + q] = rank - cum;
+        sel[q] |= b << shift;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 768; i += blockDim.x) hist[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_boot_final(float *theta, const uint32_t *keys, int64_t n,
+                                                    const uint32_t *sel, double *range, double *info,
+                                                    double depth_lo, double depth_hi, const int *status)
+{
+    if (*status != kStatusOk) return;
+    const float P1 = __uint_as_float(sel[0]), P50 = __uint_as_float(sel[1]), P99 = __uint_as_float(sel[2]);
+    const double dlo = depth_lo > 0 ? depth_lo : 0.5 * (double)P1;
+    const double dhi = depth_hi > 0 ? depth_hi : 2.0 * (double)P99;
+    const float flo = (float)dlo, fhi = (float)dhi;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j == 0) {
+        range[0] = dlo;
+        range[1] = dhi;
+        range[2] = 1.0;
+        info[2] = (double)sel[12];
+    }
+    if (j < n) {
+        float th = keys[j] == 0xffffffffu ? P50 : theta[j];
+        th = fminf(fmaxf(th, flo), fhi);
+        theta[j] = th;
+    }
+}
+
+__global__ void k_boot_init(int *status, uint32_t *sel)
+{
+    if (threadIdx.x == 0) *status = kStatusOk;
+    if (threadIdx.x < 16) sel[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
+                     uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
+                     float *theta, hipStream_t s)
+{
+    const int64_t HW = (int64_t)d.H * d.W;
+    const int Ne = (int)(n_eval < HW ? n_eval : HW);
+    hipLaunchKernelGGL(k_boot_init, dim3(1), dim3(64), 0, s, c->status, c->sel);
+    HypArgs h{flows, c->hyp, c->hyp_score, d.H, d.W, n_hyp, d.fx, d.fy, d.cx, d.cy, seed};
+    hipLaunchKernelGGL(k_boot_hyp, dim3((n_hyp + 63) / 64), dim3(64), 0, s, h);
+    ScoreArgs sc{flows, c->hyp, c->hyp_score, d.H, d.W, Ne};
+    hipLaunchKernelGGL(k_boot_score, dim3(n_hyp), dim3(kEvalThreads), 0, s, sc);
+    PickArgs pk{flows, c->hyp, c->hyp_score, rel_poses, c->Mcum, c->boot_info, c->status,
+                d.H, d.W, n_hyp, Ne, d.T, d.fx, d.fy, d.cx, d.cy};
+    hipLaunchKernelGGL(k_boot_pick, dim3(1), dim3(1024), 0, s, pk);
+    TriArgs tr{flows, rel_poses, theta, c->dkeys, c->sel, c->status, d.H, d.W, d.fx, d.fy, d.cx, d.cy};
+    hipLaunchKernelGGL(k_boot_tri, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, tr);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->hist, c->status);
+    int blocks = (int)((HW + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    for (int pass = 3; pass >= 0; --pass) {
+        hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(256), 0, s, c->dkeys, HW, c->sel, c->hist, pass, c->status);
+        hipLaunchKernelGGL(k_hist_pick, dim3(1), dim3(256), 0, s, c->sel, c->hist, pass, c->status);
+    }
+    hipLaunchKernelGGL(k_boot_final, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, theta, c->dkeys,
+                       HW, c->sel, c->range, c->boot_info, depth_lo, depth_hi, c->status);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+}  // namespace vo

@@ -1,0 +1,476 @@
+// vo_device.hpp -- device-side building blocks of the gfx950 window solver.
+//
+// Philox4x64-10 counters, the FP32 emission of Eq. 1-8 (projection, bilinear
+// flow lookup, Fisk log-densities in log form), FP64 3x3 algebra, SE(3)
+// exp/log and the P3P solver used by the pose step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vo {
+
+constexpr int kTMax = 16;          // frames per window
+constexpr int kBlock = 256;        // threads of the chain kernels
+constexpr int kMaxPerThread = 16;  // chain positions per thread (L <= 4096)
+
+enum : uint64_t { kDepthStream = 1, kPoseStream = 2, kBootStream = 3 };
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 64x64->128 multiplies with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t h0 = __umul64hi(m0, c[0]), l0 = m0 * c[0];
+        const uint64_t h1 = __umul64hi(m1, c[2]), l1 = m1 * c[2];
+        const uint64_t n0 = h1 ^ c[1] ^ k0;
+        const uint64_t n2 = h0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = l1;
+        c[2] = n2;
+        c[3] = l0;
+        k0 += w0;
+        k1 += w1;
+    }
+}
+
+// index in [0, n) from a 32-bit uniform word
+__device__ __forceinline__ int64_t u32_to_index(uint32_t u, int64_t n)
+{
+    return (int64_t)(((uint64_t)u * (uint64_t)n) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 frame data: cumulative pose M_t = (R, t) stored as D = R - I and t so
+// that pixel displacements avoid the cancellation of pi_t - pixel.
+// ---------------------------------------------------------------------------
+struct FrameF {
+    float D[9];
+    float t[3];
+};
+
+struct EmisParams {
+    float fx, fy, cx, cy;
+    float log_a1, a2, b1, b2;
+    float lam2, beta_min, x_floor, pad;
+};
+
+// Displacement pi_t(theta) - (x, y) of the frame-0 pixel with normalised
+// coordinates (xh, yh) at depth th.  False if the point is not in front.
+__device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh, float th,
+                                             float fx, float fy, float &dx, float &dy)
+{
+    const float e0 = fmaf(f.D[0], xh, fmaf(f.D[1], yh, f.D[2]));
+    const float e1 = fmaf(f.D[3], xh, fmaf(f.D[4], yh, f.D[5]));
+    const float e2 = fmaf(f.D[6], xh, fmaf(f.D[7], yh, f.D[8]));
+    const float ax = fmaf(-xh, e2, e0), ay = fmaf(-yh, e2, e1), az = 1.0f + e2;
+    const float bx = fmaf(-xh, f.t[2], f.t[0]), by = fmaf(-yh, f.t[2], f.t[1]);
+    const float pz = fmaf(th, az, f.t[2]);
+    if (!(pz > 0.0f)) return false;
+    const float inv = 1.0f / pz;
+    dx = fx * fmaf(th, ax, bx) * inv;
+    dy = fy * fmaf(th, ay, by) * inv;
+    return true;
+}
+
+// log(1 + e) for e in [0, 1]: series where 1 + e would round away e.
+__device__ __forceinline__ float log1p_unit(float e)
+{
+    return e < 1e-3f ? e * (1.0f - e * (0.5f - e * (1.0f / 3.0f))) : __logf(1.0f + e);
+}
+
+__device__ __forceinline__ float softplus(float z)
+{
+    return fmaxf(z, 0.0f) + log1p_unit(__expf(-fabsf(z)));
+}
+
+// Bilinear sample of flow X (one frame, float2 [H][W]) at (px, py).
+// Domain [0, W-1] x [0, H-1]; all four taps must be finite.
+__device__ __forceinline__ bool sample_flow(const float2 *__restrict__ X, int H, int W, float px,
+                                            float py, float &u, float &v)
+{
+    if (!(px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1))) return false;
+    int x0 = (int)floorf(px), y0 = (int)floorf(py);
+    x0 = min(x0, W - 2);
+    y0 = min(y0, H - 2);
+    const float ax = px - (float)x0, ay = py - (float)y0;
+    const float2 *row0 = X + (size_t)y0 * W + x0;
+    const float2 *row1 = row0 + W;
+    const float2 a = row0[0], b = row0[1], c = row1[0], d = row1[1];
+    u = (1.0f - ay) * fmaf(ax, b.x - a.x, a.x) + ay * fmaf(ax, d.x - c.x, c.x);
+    v = (1.0f - ay) * fmaf(ax, b.y - a.y, a.y) + ay * fmaf(ax, d.y - c.y, c.y);
+    return isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y);
+}
+
+struct Emis {
+    float ell;  // log r
+    float r;    // rho / (rho + mu)
+};
+
+// Emission given the residual (rx, ry) = xi - v and the observed flow v:
+// d = log(mu / rho) with the Fisk densities of Eq. 4 and Eq. 8 sharing
+// log(alpha) = log a1 + a2 |v| and beta = max(b1 |v| + b2, beta_min);
+// the common log(beta) - log(alpha) term cancels in the ratio.
+__device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, float vy,
+                                                  const EmisParams &e)
+{
+    const float x2 = fmaxf(fmaf(rx, rx, ry * ry), e.x_floor);
+    const float vn2 = fmaf(vx, vx, vy * vy);
+    const float vn = sqrtf(vn2);
+    const float la = fmaf(e.a2, vn, e.log_a1);
+    const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+    const float lx = __logf(x2);
+    const float lm = __logf(fmaxf(e.lam2 * vn2, e.x_floor));
+    const float z1 = beta * (lx - la), z2 = beta * (lm - la);
+    return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+}
+
+__device__ __forceinline__ Emis emis_from_d(float d)
+{
+    const float e = __expf(-fabsf(d));
+    const float inv = 1.0f / (1.0f + e);
+    Emis o;
+    o.ell = -(fmaxf(d, 0.0f) + log1p_unit(e));
+    o.r = d < 0.0f ? inv : e * inv;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 helpers
+// ---------------------------------------------------------------------------
+struct M3 {
+    double a[9];
+};
+
+__device__ __forceinline__ void mv3(const double *A, const double *x, double *y)
+{
+    y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+    y[1] = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+    y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+}
+
+__device__ __forceinline__ void mm3(const double *A, const double *B, double *C)
+{
+    double T[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) C[i] = T[i];
+}
+
+__device__ __forceinline__ double dot3d(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ __forceinline__ void cross3d(const double *a, const double *b, double *c)
+{
+    const double c0 = a[1] * b[2] - a[2] * b[1];
+    const double c1 = a[2] * b[0] - a[0] * b[2];
+    const double c2 = a[0] * b[1] - a[1] * b[0];
+    c[0] = c0;
+    c[1] = c1;
+    c[2] = c2;
+}
+
+// compose C = A o B for 12-double poses (R row-major, t)
+__device__ __forceinline__ void pose_mul(const double *A, const double *B, double *C)
+{
+    double R[9], t[3];
+    mm3(A, B, R);
+    mv3(A, B + 9, t);
+    for (int k = 0; k < 3; ++k) t[k] += A[9 + k];
+    for (int k = 0; k < 9; ++k) C[k] = R[k];
+    for (int k = 0; k < 3; ++k) C[9 + k] = t[k];
+}
+
+// rotation angle in [0, pi]
+__device__ __forceinline__ double rot_angle(const double *R)
+{
+    const double wx = R[7] - R[5], wy = R[2] - R[6], wz = R[3] - R[1];
+    return atan2(0.5 * sqrt(wx * wx + wy * wy + wz * wz), 0.5 * (R[0] + R[4] + R[8] - 1.0));
+}
+
+// se(3) exp: p = (rho, phi) -> R, t = V rho
+__device__ inline void se3_exp(const double *p, double *R, double *t)
+{
+    const double *w = p + 3;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-5) {
+        A = 1.0 - th2 * (1.0 / 6.0) + th2 * th2 * (1.0 / 120.0);
+        B = 0.5 - th2 * (1.0 / 24.0) + th2 * th2 * (1.0 / 720.0);
+        C = 1.0 / 6.0 - th2 * (1.0 / 120.0) + th2 * th2 * (1.0 / 5040.0);
+    } else {
+        const double s = sin(th), c = cos(th);
+        A = s / th;
+        B = (1.0 - c) / th2;
+        C = (th - s) / (th2 * th);
+    }
+    // W = [w]x, W^2 = w w^T - th2 I
+    const double W[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+    double W2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) W2[3 * i + j] = w[i] * w[j] - (i == j ? th2 : 0.0);
+    double V[9];
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i == 0 || i == 4 || i == 8) ? 1.0 : 0.0;
+        R[i] = I + A * W[i] + B * W2[i];
+        V[i] = I + B * W[i] + C * W2[i];
+    }
+    mv3(V, p, t);
+}
+
+// se(3) log: R, t -> p = (V^-1 t, phi), |phi| in [0, pi]
+__device__ inline void se3_log(const double *R, const double *t, double *p)
+{
+    const double wx = R[7] - R[5], wy = R[2] - R[6], wz = R[3] - R[1];
+    const double s = 0.5 * sqrt(wx * wx + wy * wy + wz * wz);
+    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    const double th = atan2(s, c);
+    double phi[3];
+    if (th < 1e-5) {
+        const double f = 0.5 + th * th * (1.0 / 12.0);
+        phi[0] = f * wx;
+        phi[1] = f * wy;
+        phi[2] = f * wz;
+    } else if (th < 3.1405926535897931) {
+        const double f = th / (2.0 * sin(th));
+        phi[0] = f * wx;
+        phi[1] = f * wy;
+        phi[2] = f * wz;
+    } else {
+        // near pi: the symmetric part (R + R^T)/2 = c I + (1 - c) n n^T
+        const double oc = 1.0 - c;
+        const double d[3] = {R[0], R[4], R[8]};
+        int m = 0;
+        if (d[1] > d[m]) m = 1;
+        if (d[2] > d[m]) m = 2;
+        double n[3];
+        n[m] = sqrt(fmax(0.0, (d[m] - c) / oc));
+        for (int k = 0; k < 3; ++k)
+            if (k != m) n[k] = (R[3 * m + k] + R[3 * k + m]) / (2.0 * oc * n[m]);
+        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        double sg = (n[0] * wx + n[1] * wy + n[2] * wz) < 0 ? -1.0 : 1.0;
+        for (int k = 0; k < 3; ++k) phi[k] = sg * th * n[k] / nn;
+    }
+    // V^-1 = I - 1/2 [phi]x + D [phi]x^2
+    double Dc;
+    if (th < 1e-5) {
+        Dc = 1.0 / 12.0 + th * th * (1.0 / 720.0);
+    } else {
+        Dc = (1.0 - th * sin(th) / (2.0 * (1.0 - cos(th)))) / (th * th);
+    }
+    const double W[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double Vi[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double W2 = phi[i] * phi[j] - (i == j ? th2 : 0.0);
+            Vi[3 * i + j] = (i == j ? 1.0 : 0.0) - 0.5 * W[3 * i + j] + Dc * W2;
+        }
+    mv3(Vi, t, p);
+    p[3] = phi[0];
+    p[4] = phi[1];
+    p[5] = phi[2];
+}
+
+// ---------------------------------------------------------------------------
+// P3P.  With unknown distances s_i along unit bearings f_i and the side
+// lengths of the 3-D triangle, the law of cosines gives three quadrics.  With
+// u = s2/s1 and v = s3/s1, subtracting two of them yields u as a rational
+// function N(v)/D(v); substituting into the third gives a quartic in v
+// (Grunert's route).  Its real roots are found in closed form (Ferrari, via
+// the resolvent cubic) and polished by Newton steps.  The camera-frame
+// triangle s_i f_i is then aligned rigidly onto the 3-D triangle.
+// ---------------------------------------------------------------------------
+__device__ inline int cubic_real_roots(double a2, double a1, double a0, double *x)
+{
+    // x^3 + a2 x^2 + a1 x + a0
+    const double q = (3.0 * a1 - a2 * a2) / 9.0;
+    const double r = (9.0 * a2 * a1 - 27.0 * a0 - 2.0 * a2 * a2 * a2) / 54.0;
+    const double disc = q * q * q + r * r;
+    const double sh = a2 / 3.0;
+    if (disc > 0) {
+        const double sd = sqrt(disc);
+        const double s = cbrt(r + sd), t = cbrt(r - sd);
+        x[0] = s + t - sh;
+        return 1;
+    }
+    if (q == 0) {
+        x[0] = -sh;
+        return 1;
+    }
+    const double mq = sqrt(-q);
+    const double th = acos(fmin(1.0, fmax(-1.0, r / (mq * mq * mq))));
+    x[0] = 2.0 * mq * cos(th / 3.0) - sh;
+    x[1] = 2.0 * mq * cos((th + 2.0 * 3.14159265358979323846) / 3.0) - sh;
+    x[2] = 2.0 * mq * cos((th + 4.0 * 3.14159265358979323846) / 3.0) - sh;
+    return 3;
+}
+
+__device__ inline double quartic_eval(const double *c, double v)
+{
+    return (((c[4] * v + c[3]) * v + c[2]) * v + c[1]) * v + c[0];
+}
+
+// real roots of c4 v^4 + ... + c0 (c4 != 0); up to 4
+__device__ inline int quartic_real_roots(const double *c, double *out)
+{
+    const double b = c[3] / c[4], cc = c[2] / c[4], d = c[1] / c[4], e = c[0] / c[4];
+    const double b2 = b * b;
+    const double p = cc - 0.375 * b2;
+    const double q = d - 0.5 * b * cc + 0.125 * b2 * b;
+    const double r = e - 0.25 * b * d + 0.0625 * b2 * cc - 3.0 / 256.0 * b2 * b2;
+    double ys[4];
+    int n = 0;
+    const double scale = fmax(1.0, fmax(fabs(p), sqrt(fabs(r))));
+    if (fabs(q) < 1e-14 * scale * sqrt(scale)) {
+        // biquadratic y^4 + p y^2 + r
+        const double dd = p * p - 4.0 * r;
+        if (dd >= 0) {
+            const double sd = sqrt(dd);
+            const double z1 = 0.5 * (-p + sd), z2 = 0.5 * (-p - sd);
+            if (z1 >= 0) { ys[n++] = sqrt(z1); ys[n++] = -sqrt(z1); }
+            if (z2 >= 0) { ys[n++] = sqrt(z2); ys[n++] = -sqrt(z2); }
+        }
+    } else {
+        // resolvent: m^3 + p m^2 + (p^2/4 - r) m - q^2/8 = 0, take the largest root (> 0)
+        double ms[3];
+        const int nm = cubic_real_roots(p, 0.25 * p * p - r, -0.125 * q * q, ms);
+        double m = ms[0];
+        for (int i = 1; i < nm; ++i) m = fmax(m, ms[i]);
+        // Newton polish of the resolvent root
+        for (int it = 0; it < 2; ++it) {
+            const double f = ((m + p) * m + (0.25 * p * p - r)) * m - 0.125 * q * q;
+            const double df = (3.0 * m + 2.0 * p) * m + (0.25 * p * p - r);
+            if (df != 0) m -= f / df;
+        }
+        if (m > 0) {
+            const double s = sqrt(2.0 * m);
+            const double k = q / (2.0 * s);
+            // y^2 - s y + (p/2 + m + k) = 0 and y^2 + s y + (p/2 + m - k) = 0
+            const double c1 = 0.5 * p + m + k, c2 = 0.5 * p + m - k;
+            const double d1 = s * s - 4.0 * c1, d2 = s * s - 4.0 * c2;
+            const double tol = -1e-12 * (s * s + 4.0 * fabs(c1) + 4.0 * fabs(c2));
+            if (d1 >= tol) {
+                const double sq = sqrt(fmax(d1, 0.0));
+                ys[n++] = 0.5 * (s + sq);
+                ys[n++] = 0.5 * (s - sq);
+            }
+            if (d2 >= tol) {
+                const double sq = sqrt(fmax(d2, 0.0));
+                ys[n++] = 0.5 * (-s + sq);
+                ys[n++] = 0.5 * (-s - sq);
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double v = ys[i] - 0.25 * b;
+        for (int it = 0; it < 3; ++it) {  // Newton polish on the original quartic
+            const double f = quartic_eval(c, v);
+            const double df = ((4.0 * c[4] * v + 3.0 * c[3]) * v + 2.0 * c[2]) * v + c[1];
+            if (df == 0) break;
+            const double dv = f / df;
+            v -= dv;
+            if (fabs(dv) <= 1e-16 * fabs(v)) break;
+        }
+        out[i] = v;
+    }
+    return n;
+}
+
+// Orthonormal frame of a triangle: columns e1 along X1->X2, e3 normal, e2 = e3 x e1.
+__device__ inline void triangle_frame(const double *X1, const double *X2, const double *X3, double *F)
+{
+    double e1[3] = {X2[0] - X1[0], X2[1] - X1[1], X2[2] - X1[2]};
+    const double d[3] = {X3[0] - X1[0], X3[1] - X1[1], X3[2] - X1[2]};
+    const double n1 = sqrt(dot3d(e1, e1));
+    for (int k = 0; k < 3; ++k) e1[k] /= n1;
+    double e3[3];
+    cross3d(e1, d, e3);
+    const double n3 = sqrt(dot3d(e3, e3));
+    for (int k = 0; k < 3; ++k) e3[k] /= n3;
+    double e2[3];
+    cross3d(e3, e1, e2);
+    for (int k = 0; k < 3; ++k) {
+        F[3 * k] = e1[k];
+        F[3 * k + 1] = e2[k];
+        F[3 * k + 2] = e3[k];
+    }
+}
+
+// P: 3 points (rows) in the source frame; f: 3 unit bearings (rows) in the
+// target camera.  Writes up to 4 poses (R 9, t 3) with f_i ~ R P_i + t.
+__device__ inline int p3p_solve(const double *P, const double *f, double *Rs, double *ts)
+{
+    double s23[3], s13[3], s12[3];
+    for (int k = 0; k < 3; ++k) {
+        s23[k] = P[3 + k] - P[6 + k];
+        s13[k] = P[k] - P[6 + k];
+        s12[k] = P[k] - P[3 + k];
+    }
+    const double A2 = dot3d(s23, s23), B2 = dot3d(s13, s13), C2 = dot3d(s12, s12);
+    if (!(A2 > 0) || !(B2 > 0) || !(C2 > 0)) return 0;
+    const double ca = dot3d(f + 3, f + 6), cb = dot3d(f, f + 6), cg = dot3d(f, f + 3);
+    // N(v) = n2 v^2 + n1 v + n0 ; D(v) = e1 v + e0 ; Q(v) = v^2 - 2 cb v + 1
+    const double K = C2 - A2;
+    const double n2 = B2 + K, n1 = -2.0 * K * cb, n0 = K - B2;
+    const double e1 = 2.0 * B2 * ca, e0 = -2.0 * B2 * cg;
+    // quartic: B2 N^2 - 2 B2 cg N D + (B2 - C2 Q) D^2
+    const double g2 = -C2, g1 = 2.0 * C2 * cb, g0 = B2 - C2;  // B2 - C2 Q
+    double c[5];
+    // N D is cubic; N^2 and (B2 - C2 Q) D^2 are quartic
+    c[4] = B2 * n2 * n2 + g2 * e1 * e1;
+    c[3] = B2 * 2.0 * n2 * n1 - 2.0 * B2 * cg * (n2 * e1) + (g1 * e1 * e1 + 2.0 * g2 * e1 * e0);
+    c[2] = B2 * (n1 * n1 + 2.0 * n2 * n0) - 2.0 * B2 * cg * (n2 * e0 + n1 * e1) +
+           (g0 * e1 * e1 + 2.0 * g1 * e1 * e0 + g2 * e0 * e0);
+    c[1] = B2 * 2.0 * n1 * n0 - 2.0 * B2 * cg * (n1 * e0 + n0 * e1) + (2.0 * g0 * e1 * e0 + g1 * e0 * e0);
+    c[0] = B2 * n0 * n0 - 2.0 * B2 * cg * (n0 * e0) + g0 * e0 * e0;
+    if (c[4] == 0) return 0;
+    double vs[4];
+    const int nv = quartic_real_roots(c, vs);
+    double FP[9];
+    triangle_frame(P, P + 3, P + 6, FP);
+    int n = 0;
+    for (int i = 0; i < nv; ++i) {
+        const double v = vs[i];
+        const double D = e1 * v + e0, Q = (v - 2.0 * cb) * v + 1.0;
+        if (!(v > 0) || fabs(D) < 1e-14 * B2 || !(Q > 0)) continue;
+        const double u = ((n2 * v + n1) * v + n0) / D;
+        if (!(u > 0)) continue;
+        const double s1 = sqrt(B2 / Q), s2 = u * s1, s3 = v * s1;
+        double X[9];
+        for (int k = 0; k < 3; ++k) {
+            X[k] = s1 * f[k];
+            X[3 + k] = s2 * f[3 + k];
+            X[6 + k] = s3 * f[6 + k];
+        }
+        double FX[9];
+        triangle_frame(X, X + 3, X + 6, FX);
+        double *R = Rs + 9 * n, *t = ts + 3 * n;
+        for (int a = 0; a < 3; ++a)  // R = FX FP^T
+            for (int bb = 0; bb < 3; ++bb)
+                R[3 * a + bb] = FX[3 * a] * FP[3 * bb] + FX[3 * a + 1] * FP[3 * bb + 1] +
+                                FX[3 * a + 2] * FP[3 * bb + 2];
+        double RP[3];
+        mv3(R, P, RP);
+        for (int k = 0; k < 3; ++k) t[k] = X[k] - RP[k];
+        bool ok = true;
+        for (int k = 0; k < 9; ++k) ok = ok && isfinite(R[k]);
+        for (int k = 0; k < 3; ++k) ok = ok && isfinite(t[k]);
+        if (ok) ++n;
+    }
+    return n;
+}
+
+}  // namespace vo

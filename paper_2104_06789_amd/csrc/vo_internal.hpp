@@ -1,0 +1,89 @@
+// vo_internal.hpp -- context layout and kernel launchers shared by the
+// translation units of the gfx950 library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "voldor.h"
+#include "vo_device.hpp"
+
+namespace vo {
+
+constexpr int kMaxSeeds = 255;      // mean-shift start candidates drawn from samples
+constexpr int kMaxHyp = 4096;       // bootstrap hypotheses
+constexpr int kEvalThreads = 512;   // threads of the bootstrap scoring kernel
+constexpr int kEvalPerThread = 32;  // residuals held per thread (16384 max)
+constexpr int kMaxGroups = 8192;    // P3P groups per frame
+constexpr int kLLBlocks = 1024;     // partial sums of the log-likelihood
+
+// Device status word values (mirror voldor_status).
+enum : int { kStatusOk = 0, kStatusDegenerate = -4 };
+
+// Window-level device parameters shared by all kernels of one call.
+struct WinDims {
+    int T, H, W;
+    int use_w;          // pose weights from the rigidness buffer (else all 1)
+    double fx, fy, cx, cy;
+};
+
+struct PoseParams {
+    int S, n_seeds, ms_max_iters, pad;
+    double ms_tol, s2t, s2r;
+    uint64_t seed;
+};
+
+}  // namespace vo
+
+struct voldor_ctx {
+    int device;
+    int T_max, H_max, W_max, S_max;
+    int max_lds;           // bytes of LDS one workgroup may allocate
+    // persistent device state
+    double *Mcum;          // [(T_max+1)][12] cumulative poses M_0..M_T
+    vo::FrameF *frames;    // [T_max+1] FP32 copy of Mcum for the sweeps
+    double *range;         // [4]: d_lo, d_hi, gauge scale, spare
+    int *status;           // [8]: status word, pose diagnostics scratch
+    double *samples;       // [4 S_max][8] pose samples (p, weight, valid)
+    double *seed_score;    // [kMaxSeeds + 1][8] (p, density, valid)
+    int *pose_diag;        // [T_max][4]
+    double *hyp;           // [kMaxHyp][18]: essential E (9), fundamental F (9)
+    double *hyp_score;     // [kMaxHyp] median Sampson residual
+    double *boot_info;     // [4]
+    uint32_t *dkeys;       // [H_max W_max] order-preserving keys of triangulated depths
+    uint32_t *hist;        // [3][256] radix histograms
+    uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
+    double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
+    double *prev_pose;     // [12] staging of a host-provided previous pose
+    double *pose_tmp;      // [16]
+    double *rel_tmp;       // [T_max][12] poses for step entry points
+    float *theta_tmp;      // [H_max W_max]
+};
+
+namespace vo {
+
+// ---- sweep / emission (vo_sweep.hip)
+int launch_frames(voldor_ctx *c, int T, hipStream_t s);
+int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
+                 const WinDims &d, const EmisParams &e, float gamma, uint64_t seed,
+                 int64_t gsweep, int dir, const double *range_dev, float *q_out, hipStream_t s);
+int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, const WinDims &d,
+                     const EmisParams &e, float *r, float *ell, float *logrho, float *logmu,
+                     double *ll_out, hipStream_t s);
+int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
+                  hipStream_t s);
+size_t sweep_lds_bytes(int T, int L);
+
+// ---- pose (vo_pose.hip)
+int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
+                     const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
+                     double *rel_poses, hipStream_t s);
+int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s);
+int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
+
+// ---- bootstrap (vo_boot.hip)
+int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
+                     uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
+                     float *theta, hipStream_t s);
+
+}  // namespace vo

@@ -1,0 +1,445 @@
+// vo_pose.hip -- FP64 pose step of one frame (Sec. 5.2, Eq. 15-19):
+//   k_pose_groups  S random pixel triples -> 3-D points in camera t-1 and
+//                  bearings in camera t through the flow X_t -> P3P roots in
+//                  front of both cameras -> se(3) samples weighted by the
+//                  product of the three rigidness values;
+//   k_pose_seed    kernel density of each start candidate (previous pose and
+//                  the first samples in group order) over all samples;
+//   k_pose_ms      densest candidate, Gaussian mean-shift to the mode,
+//                  T_t = exp(p*), M_t = T_t o M_{t-1};
+// plus the scale gauge |t_1| = 1.
+#include "vo_internal.hpp"
+
+namespace vo {
+
+struct GroupArgs {
+    const float *theta;
+    const float *rig;
+    const float2 *flows;
+    const double *Mprev;   // M_{t-1}
+    double *samples;       // [4S][8]
+    const int *status;
+    WinDims d;
+    int S, t, it;
+    uint64_t seed;
+};
+
+__device__ __forceinline__ bool flow_bilinear_d(const float2 *X, int H, int W, double px, double py,
+                                                double &u, double &v)
+{
+    if (!(px >= 0.0 && px <= (double)(W - 1) && py >= 0.0 && py <= (double)(H - 1))) return false;
+    int x0 = (int)floor(px), y0 = (int)floor(py);
+    x0 = min(x0, W - 2);
+    y0 = min(y0, H - 2);
+    const double ax = px - x0, ay = py - y0;
+    const float2 a = X[(size_t)y0 * W + x0], b = X[(size_t)y0 * W + x0 + 1];
+    const float2 c = X[(size_t)(y0 + 1) * W + x0], dd = X[(size_t)(y0 + 1) * W + x0 + 1];
+    if (!isfinite(a.x + a.y + b.x + b.y + c.x + c.y + dd.x + dd.y)) return false;
+    const double w00 = (1 - ax) * (1 - ay), w01 = ax * (1 - ay), w10 = (1 - ax) * ay, w11 = ax * ay;
+    u = w00 * a.x + w01 * b.x + w10 * c.x + w11 * dd.x;
+    v = w00 * a.y + w01 * b.y + w10 * c.y + w11 * dd.y;
+    return true;
+}
+
+__global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.S) return;
+    double *out = a.samples + (size_t)8 * 4 * g;
+    for (int i = 0; i < 32; ++i) out[i] = 0.0;
+    const int H = a.d.H, W = a.d.W;
+    const int64_t HW = (int64_t)H * W;
+    int64_t j[3];
+    bool drawn = false;
+    for (int att = 0; att < 8 && !drawn; ++att) {
+        uint64_t c[4] = {(uint64_t)a.it, (uint64_t)a.t, (uint64_t)g, (uint64_t)att};
+        philox4x64_10(c, a.seed, kPoseStream);
+        for (int k = 0; k < 3; ++k) j[k] = u32_to_index((uint32_t)(c[k] >> 32), HW);
+        drawn = j[0] != j[1] && j[0] != j[2] && j[1] != j[2];
+    }
+    if (!drawn) return;
+    double P[9], f[9], w = 1.0;
+    const double *M = a.Mprev;
+    const float2 *X = a.flows + (size_t)(a.t - 1) * HW;
+    for (int k = 0; k < 3; ++k) {
+        const int x = (int)(j[k] % W), y = (int)(j[k] / W);
+        const double th = (double)a.theta[j[k]];
+        const double r[3] = {(x - a.d.cx) / a.d.fx, (y - a.d.cy) / a.d.fy, 1.0};
+        double Q[3];
+        mv3(M, r, Q);
+        for (int c = 0; c < 3; ++c) Q[c] = th * Q[c] + M[9 + c];
+        if (!(Q[2] > 0)) return;
+        double u0 = a.d.fx * Q[0] / Q[2] + a.d.cx, v0 = a.d.fy * Q[1] / Q[2] + a.d.cy;
+        if (a.t == 1) { u0 = x; v0 = y; }   // pi_0 is the pixel itself
+        double fu, fv;
+        if (!flow_bilinear_d(X, H, W, u0, v0, fu, fv)) return;
+        const double bx = (u0 + fu - a.d.cx) / a.d.fx, by = (v0 + fv - a.d.cy) / a.d.fy;
+        const double nb = sqrt(bx * bx + by * by + 1.0);
+        P[3 * k] = Q[0];
+        P[3 * k + 1] = Q[1];
+        P[3 * k + 2] = Q[2];
+        f[3 * k] = bx / nb;
+        f[3 * k + 1] = by / nb;
+        f[3 * k + 2] = 1.0 / nb;
+        if (a.rig) w *= (double)a.rig[(size_t)(a.t - 1) * HW + j[k]];
+    }
+    double Rs[36], ts[12];
+    const int nr = p3p_solve(P, f, Rs, ts);
+    int keep[4], nk = 0;
+    double key[4][4];
+    for (int i = 0; i < nr; ++i) {
+        bool front = true;
+        for (int k = 0; k < 3; ++k) {
+            const double z = Rs[9 * i + 6] * P[3 * k] + Rs[9 * i + 7] * P[3 * k + 1] +
+                             Rs[9 * i + 8] * P[3 * k + 2] + ts[3 * i + 2];
+            front = front && z > 0;
+        }
+        if (!front) continue;
+        key[nk][0] = rot_angle(Rs + 9 * i);
+        key[nk][1] = ts[3 * i];
+        key[nk][2] = ts[3 * i + 1];
+        key[nk][3] = ts[3 * i + 2];
+        keep[nk++] = i;
+    }
+    // canonical order: rotation angle, then t_x, t_y, t_z (insertion sort)
+    for (int a1 = 1; a1 < nk; ++a1) {
+        for (int b1 = a1; b1 > 0; --b1) {
+            bool less = false;
+            for (int c = 0; c < 4; ++c) {
+                if (key[b1][c] < key[b1 - 1][c]) { less = true; break; }
+                if (key[b1][c] > key[b1 - 1][c]) break;
+            }
+            if (!less) break;
+            for (int c = 0; c < 4; ++c) { const double tmp = key[b1][c]; key[b1][c] = key[b1 - 1][c]; key[b1 - 1][c] = tmp; }
+            const int tk = keep[b1]; keep[b1] = keep[b1 - 1]; keep[b1 - 1] = tk;
+        }
+    }
+    for (int s = 0; s < nk; ++s) {
+        const int i = keep[s];
+        double p[6];
+        se3_log(Rs + 9 * i, ts + 3 * i, p);
+        bool fin = true;
+        for (int c = 0; c < 6; ++c) fin = fin && isfinite(p[c]);
+        if (!fin) continue;
+        double *o = out + 8 * s;
+        for (int c = 0; c < 6; ++c) o[c] = p[c];
+        o[6] = w;
+        o[7] = 1.0;
+    }
+}
+
+__device__ __forceinline__ double mahal2(const double *a, const double *b, double is2t, double is2r)
+{
+    const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+    const double d3 = a[3] - b[3], d4 = a[4] - b[4], d5 = a[5] - b[5];
+    return (d0 * d0 + d1 * d1 + d2 * d2) * is2t + (d3 * d3 + d4 * d4 + d5 * d5) * is2r;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < NT / 64; ++i) s += red[i];
+        red[NT / 64] = s;
+    }
+    __syncthreads();
+    return red[NT / 64];
+}
+
+struct SeedArgs {
+    const double *samples;
+    double *seed_score;    // [n_seeds + 1][8]
+    const double *prev;    // previous relative pose T_t or null
+    const int *status;
+    int n_slots, n_seeds, have_prev;
+    double is2t, is2r;
+};
+
+__global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    __shared__ double red[8];
+    __shared__ double seed[6];
+    __shared__ int found;
+    __shared__ int cnt[256];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    double *o = a.seed_score + 8 * b;
+    if (tid == 0) found = 0;
+    __syncthreads();
+    if (b == 0) {
+        if (!a.have_prev) {
+            if (tid == 0) o[7] = 0.0;
+            return;
+        }
+        if (tid == 0) {
+            double p[6];
+            se3_log(a.prev, a.prev + 9, p);
+            for (int c = 0; c < 6; ++c) seed[c] = p[c];
+            found = 1;
+        }
+    } else {
+        // the (b-1)-th valid sample in slot order
+        const int want = b - 1;
+        const int chunk = (a.n_slots + 255) / 256;
+        const int lo = min(tid * chunk, a.n_slots), hi = min(lo + chunk, a.n_slots);
+        int c = 0;
+        for (int i = lo; i < hi; ++i) c += a.samples[8 * i + 7] != 0.0;
+        cnt[tid] = c;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int i = 0; i < 256; ++i) { const int v = cnt[i]; cnt[i] = acc; acc += v; }
+        }
+        __syncthreads();
+        int rank = cnt[tid];
+        if (want >= rank && want < rank + c) {
+            for (int i = lo; i < hi; ++i) {
+                if (a.samples[8 * i + 7] != 0.0) {
+                    if (rank == want) {
+                        for (int k = 0; k < 6; ++k) seed[k] = a.samples[8 * i + k];
+                        found = 1;
+                        break;
+                    }
+                    ++rank;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!found) {
+        if (tid == 0) o[7] = 0.0;
+        return;
+    }
+    double s = 0.0;
+    for (int i = tid; i < a.n_slots; i += 256) {
+        const double *q = a.samples + 8 * i;
+        if (q[7] != 0.0) s += q[6] * exp(-0.5 * mahal2(seed, q, a.is2t, a.is2r));
+    }
+    const double D = block_sum<256>(s, red);
+    if (tid == 0) {
+        for (int c = 0; c < 6; ++c) o[c] = seed[c];
+        o[6] = D;
+        o[7] = 1.0;
+    }
+}
+
+struct MsArgs {
+    const double *samples;
+    const double *seed_score;
+    double *rel;            // relative poses [T][12]; T_t written at t-1
+    double *Mcum;           // cumulative poses [T+1][12]; M_t written
+    int *diag;              // [4]
+    const int *status;
+    int n_slots, n_seeds, t, max_iters, fallback_prev_frame;
+    double is2t, is2r, tol;
+};
+
+constexpr int kMsThreads = 1024;
+
+__global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    __shared__ double red[kMsThreads / 64 + 1];
+    __shared__ double p[6];
+    __shared__ int stop;
+    const int tid = threadIdx.x;
+    // number of samples and total weight
+    double n = 0.0, ws = 0.0;
+    for (int i = tid; i < a.n_slots; i += kMsThreads) {
+        const double *q = a.samples + 8 * i;
+        if (q[7] != 0.0) { n += 1.0; ws += q[6]; }
+    }
+    const double N = block_sum<kMsThreads>(n, red);
+    const double WS = block_sum<kMsThreads>(ws, red);
+    double *Tt = a.rel + 12 * (a.t - 1);
+    if (N == 0.0 || !(WS > 0.0)) {
+        if (tid == 0) {
+            if (a.fallback_prev_frame)
+                for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
+            pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
+            a.diag[0] = (int)N; a.diag[2] = 0; a.diag[3] = 1;
+        }
+        return;
+    }
+    if (tid == 0) {
+        int best = -1;
+        double bd = 0.0;
+        for (int i = 0; i <= a.n_seeds; ++i) {
+            const double *s = a.seed_score + 8 * i;
+            if (s[7] == 0.0) continue;
+            if (best < 0 || s[6] > bd) { best = i; bd = s[6]; }
+        }
+        if (best < 0) {
+            // no start candidate: the first valid sample in slot order
+            for (int i = 0; i < a.n_slots; ++i)
+                if (a.samples[8 * i + 7] != 0.0) { for (int c = 0; c < 6; ++c) p[c] = a.samples[8 * i + c]; break; }
+        } else {
+            for (int c = 0; c < 6; ++c) p[c] = a.seed_score[8 * best + c];
+        }
+        stop = 0;
+    }
+    __syncthreads();
+    int it = 0;
+    for (; it < a.max_iters; ++it) {
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        double pc[6];
+        for (int c = 0; c < 6; ++c) pc[c] = p[c];
+        for (int i = tid; i < a.n_slots; i += kMsThreads) {
+            const double *q = a.samples + 8 * i;
+            if (q[7] == 0.0) continue;
+            const double k = q[6] * exp(-0.5 * mahal2(pc, q, a.is2t, a.is2r));
+            acc[6] += k;
+            for (int c = 0; c < 6; ++c) acc[c] += k * q[c];
+        }
+        double tot[7];
+        for (int c = 0; c < 7; ++c) tot[c] = block_sum<kMsThreads>(acc[c], red);
+        if (tid == 0) {
+            if (!(tot[6] > 0.0)) {
+                stop = 2;
+            } else {
+                double np[6];
+                for (int c = 0; c < 6; ++c) np[c] = tot[c] / tot[6];
+                const double step = sqrt(mahal2(np, pc, a.is2t, a.is2r));
+                for (int c = 0; c < 6; ++c) p[c] = np[c];
+                stop = step < a.tol ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        const int st = stop;
+        __syncthreads();
+        if (st == 2) break;
+        if (st == 1) { ++it; break; }
+    }
+    if (tid == 0) {
+        double pp[6], R[9], tv[3];
+        for (int c = 0; c < 6; ++c) pp[c] = p[c];
+        se3_exp(pp, R, tv);
+        for (int k = 0; k < 9; ++k) Tt[k] = R[k];
+        for (int k = 0; k < 3; ++k) Tt[9 + k] = tv[k];
+        pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
+        a.diag[0] = (int)N;
+        a.diag[2] = it;
+        a.diag[3] = 0;
+    }
+}
+
+__global__ void k_group_count(const double *samples, int S, const int *status, int *diag)
+{
+    if (status && *status != kStatusOk) return;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int c = 0;
+    for (int g = threadIdx.x; g < S; g += blockDim.x) {
+        bool any = false;
+        for (int s = 0; s < 4; ++s) any = any || samples[8 * (4 * g + s) + 7] != 0.0;
+        c += any;
+    }
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) diag[1] = cnt;
+}
+
+// scale gauge |t_1| = 1: translations, depth range, cumulative poses
+__global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    if (threadIdx.x != 0) return;
+    const double *t1 = rel + 9;
+    const double s = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    const double inv = s > 0 ? 1.0 / s : 1.0;
+    range[2] = s > 0 ? s : 1.0;
+    for (int t = 0; t < T; ++t)
+        for (int k = 0; k < 3; ++k) rel[12 * t + 9 + k] *= inv;
+    range[0] *= inv;
+    range[1] *= inv;
+    for (int k = 0; k < 12; ++k) Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+    for (int t = 1; t <= T; ++t) pose_mul(rel + 12 * (t - 1), Mcum + 12 * (t - 1), Mcum + 12 * t);
+}
+
+__global__ void k_gauge_theta(float *theta, int HW, const double *range, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < HW) theta[j] = (float)((double)theta[j] / range[2]);
+}
+
+__global__ void k_cumulative(const double *rel, double *Mcum, int T)
+{
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 12; ++k) Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+    for (int t = 1; t <= T; ++t) pose_mul(rel + 12 * (t - 1), Mcum + 12 * (t - 1), Mcum + 12 * t);
+}
+
+// ---------------------------------------------------------------------------
+int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
+                     const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
+                     double *rel_poses, hipStream_t s)
+{
+    GroupArgs g;
+    g.theta = theta;
+    g.rig = d.use_w ? rig : nullptr;
+    g.flows = flows;
+    g.Mprev = c->Mcum + 12 * (t - 1);
+    g.samples = c->samples;
+    g.status = c->status;
+    g.d = d;
+    g.S = pp.S;
+    g.t = t;
+    g.it = it;
+    g.seed = pp.seed;
+    hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
+    int *diag = c->pose_diag + 4 * (t - 1);
+    hipLaunchKernelGGL(k_group_count, dim3(1), dim3(256), 0, s, c->samples, pp.S, c->status, diag);
+    SeedArgs sa;
+    sa.samples = c->samples;
+    sa.seed_score = c->seed_score;
+    sa.prev = rel_poses + 12 * (t - 1);
+    sa.status = c->status;
+    sa.n_slots = 4 * pp.S;
+    sa.n_seeds = pp.n_seeds;
+    sa.have_prev = have_prev;
+    sa.is2t = 1.0 / pp.s2t;
+    sa.is2r = 1.0 / pp.s2r;
+    hipLaunchKernelGGL(k_pose_seed, dim3(pp.n_seeds + 1), dim3(256), 0, s, sa);
+    MsArgs m;
+    m.samples = c->samples;
+    m.seed_score = c->seed_score;
+    m.rel = rel_poses;
+    m.Mcum = c->Mcum;
+    m.diag = diag;
+    m.status = c->status;
+    m.n_slots = 4 * pp.S;
+    m.n_seeds = pp.n_seeds;
+    m.t = t;
+    m.max_iters = pp.ms_max_iters;
+    m.fallback_prev_frame = (!have_prev && t >= 2) ? 1 : 0;
+    m.is2t = 1.0 / pp.s2t;
+    m.is2r = 1.0 / pp.s2r;
+    m.tol = pp.ms_tol;
+    hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauge_poses, dim3(1), dim3(64), 0, s, rel_poses, c->Mcum, c->range, d.T, c->status);
+    const int HW = d.H * d.W;
+    hipLaunchKernelGGL(k_gauge_theta, dim3((HW + 255) / 256), dim3(256), 0, s, theta, HW, c->range, c->status);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cumulative, dim3(1), dim3(64), 0, s, rel_poses, c->Mcum, T);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+}  // namespace vo

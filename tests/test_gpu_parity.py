@@ -1,0 +1,209 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Step-level tests feed identical explicit state to one step of both sides;
+window tests run the whole loop.  Tolerances:
+  * emission: FP32 log-domain arithmetic vs FP64 -> |dr| <= 2e-4, |d ell| <= 2e-4 (1 + |ell|)
+  * sweeps: every GPU decision is the oracle's argmax except near ties whose
+    score gap is within 1e-4 of the score mass (FP32 resolution of T sums)
+  * window: rotation <= 1e-4 rad, translation direction <= 1e-4 rad, median
+    relative depth <= 1e-3, rigidness <= 1e-4 at the 99th percentile,
+    log-likelihood <= 1e-5 relative to its L1 mass.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthflow
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def vo():
+    import paper_2104_06789_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _rot_angle(Ra, Rb):
+    return math.acos(max(-1.0, min(1.0, (np.trace(Ra @ Rb.T) - 1) / 2)))
+
+
+def _tdir_angle(a, b):
+    return math.acos(max(-1.0, min(1.0, a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))))
+
+
+def _world(seed, T, H, W, noise=True):
+    w = synthflow.make_window("small", seed, noise=noise, outliers=noise, T=T, H=H, W=W)
+    R, t = w["poses"][0]
+    s = np.linalg.norm(t)
+    rel = np.array([np.concatenate([R_.ravel(), t_ / s]) for R_, t_ in w["poses"]])
+    return w, rel, oracle.cumulative(rel), w["depth"] / s
+
+
+def test_philox_bit_exact(vo, torch):
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**63, (4096, 4), dtype=np.int64)
+    out = vo.philox(torch.from_numpy(ctr).cuda(), 12345, 3).cpu().numpy().view(np.uint64)
+    for i in range(0, 4096, 97):
+        ref = oracle.philox(ctr[i].view(np.uint64), [12345, 3])
+        assert np.array_equal(out[i], ref)
+
+
+def test_emission_parity(vo, torch):
+    w, rel, M, gt = _world(11, 3, 50, 70)
+    theta = (gt * np.exp(np.random.default_rng(1).normal(0, 0.1, gt.shape))).astype(np.float32)
+    p = vo.default_params()
+    s = vo.Solver(3, 50, 70, 256)
+    r, ell, lr, lm = [x.cpu().numpy() for x in s.emission(torch.from_numpy(theta).cuda(),
+                                                          torch.from_numpy(w["flows"]).cuda(), w["K"], p, M)]
+    orr, oell, olr, olm, obs = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"],
+                                                   oracle.params(), M)
+    agree = (r == np.float32(0.5)) == ~obs
+    assert agree.mean() > 0.999
+    m = obs & agree
+    assert np.abs(r[m] - orr[m]).max() < 2e-4
+    assert np.all(np.abs(ell[m] - oell[m]) <= 2e-4 * (1 + np.abs(oell[m])))
+    assert np.all(np.abs(lr[m] - olr[m]) <= 2e-4 * (1 + np.abs(olr[m])))
+
+
+@pytest.mark.parametrize("direction", [0, 1, 2, 3])
+def test_sweep_parity(vo, torch, direction):
+    # ragged sizes: rows of 83, columns of 45, several FB segments per chain
+    T, H, W = 4, 45, 83
+    w, rel, M, gt = _world(20 + direction, T, H, W)
+    rng = np.random.default_rng(direction)
+    theta = (gt * np.exp(rng.normal(0, 0.15, gt.shape))).astype(np.float32)
+    d_lo, d_hi = 0.5 * float(gt.min()), 2.0 * float(gt.max())
+    p = vo.default_params()
+    s = vo.Solver(T, H, W, 256)
+    gs = 7 + direction
+    out, q = s.sweep(torch.from_numpy(theta).cuda(), torch.from_numpy(w["flows"]).cuda(), w["K"], p, M,
+                     d_lo, d_hi, gs, direction, want_q=True)
+    out, q = out.cpu().numpy(), q.cpu().numpy()
+    op = oracle.params()
+    # E-step: smoothed rigidness of the previous depth
+    orr, *_ = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"], op, M)
+    oq = oracle.fb_map(orr, direction, op.gamma)
+    assert np.abs(q - oq).max() < 2e-3
+    assert np.median(np.abs(q - oq)) < 1e-5
+    # M-step: every decision valid under FP64 scoring, up to FP32 near ties
+    st, gap = oracle.sweep_check(theta.astype(np.float64), out.astype(np.float64), w["flows"], w["K"], op,
+                                 M, d_lo, d_hi, gs, direction, vtol=2e-6, stol=1e-4)
+    assert (st <= 1).all(), np.unique(st, return_counts=True)
+    assert (st == 0).mean() > 0.995
+    # the oracle's own walk from the same state agrees almost everywhere
+    ref, _, _ = oracle.sweep(theta.astype(np.float64), w["flows"], w["K"], op, M, d_lo, d_hi, gs, direction)
+    same = np.abs(out - ref) <= 2e-6 * ref
+    assert same.mean() > 0.99
+
+
+def test_pose_step_parity(vo, torch):
+    T, H, W = 3, 60, 80
+    w, rel, M, gt = _world(31, T, H, W)
+    theta = gt.astype(np.float32)
+    rng = np.random.default_rng(3)
+    rig = rng.uniform(0.2, 1.0, (T, H, W)).astype(np.float32)
+    s = vo.Solver(T, H, W, 512)
+    for t, it, prev, use_rig in [(1, 0, rel[0], False), (2, 0, None, False), (3, 1, rel[2], True)]:
+        p = vo.default_params(n_pose_groups=300, seed=5)
+        Tg, smp, diag = s.pose_step(torch.from_numpy(theta).cuda(),
+                                    torch.from_numpy(rig).cuda() if use_rig else None,
+                                    torch.from_numpy(w["flows"]).cuda(), w["K"], p, M, t, it, prevT=prev,
+                                    want_samples=True)
+        To, osmp, odiag = oracle.pose_step(theta.astype(np.float64), rig.astype(np.float64) if use_rig else None,
+                                           w["flows"], w["K"], oracle.params(n_pose_groups=300, seed=5), M, t, it,
+                                           prevT=prev, want_samples=True)
+        smp = smp.cpu().numpy()
+        # same groups are valid, same number of roots per group
+        assert np.array_equal(smp[:, 7] > 0, osmp[:, 7] > 0) or \
+            np.mean((smp[:, 7] > 0) == (osmp[:, 7] > 0)) > 0.99
+        both = (smp[:, 7] > 0) & (osmp[:, 7] > 0)
+        dif = np.abs(smp[both, :6] - osmp[both, :6]).max(axis=1)
+        assert np.median(dif) < 1e-9 and np.mean(dif < 1e-6) > 0.98
+        assert diag[0] == odiag[0] or abs(diag[0] - odiag[0]) <= 2
+        assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-6
+        assert np.abs(Tg[9:] - To[9:]).max() < 1e-5
+
+
+def test_bootstrap_parity(vo, torch):
+    w = synthflow.make_window("small", 41, T=2, H=72, W=100)
+    s = vo.Solver(2, 72, 100, 256)
+    st, rel, th, rng, info = s.bootstrap(torch.from_numpy(w["flows"]).cuda(), w["K"], vo.default_params())
+    ost, orel, oth, orng, oinfo = oracle.bootstrap(w["flows"], w["K"], oracle.params())
+    assert st == 0 and ost == 0
+    assert info[0] == oinfo[0]                       # same winning hypothesis
+    assert abs(info[1] - oinfo[1]) <= 1e-9 * oinfo[1]
+    assert _rot_angle(rel[:9].reshape(3, 3), orel[:9].reshape(3, 3)) < 1e-9
+    assert np.abs(rel[9:] - orel[9:]).max() < 1e-9
+    assert np.allclose(rng, orng, rtol=1e-6)
+    th = th.cpu().numpy()
+    assert np.max(np.abs(th - oth) / oth) < 1e-6
+
+
+def test_bootstrap_degenerate(vo, torch):
+    fl = np.full((1, 32, 32, 2), np.nan, np.float32)
+    s = vo.Solver(1, 32, 32, 64)
+    st, *_ = s.bootstrap(torch.from_numpy(fl).cuda(), (40.0, 40.0, 16.0, 16.0), vo.default_params())
+    assert st == -4
+    assert s.window_status(torch.from_numpy(fl).cuda(), (40.0, 40.0, 16.0, 16.0), vo.default_params()) == -4
+
+
+def test_invalid_arguments(vo, torch):
+    s = vo.Solver(2, 32, 32, 64)
+    fl = torch.zeros((2, 32, 32, 2), device="cuda")
+    p = vo.default_params()
+    p.struct_size = 7
+    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), p) == -1
+    assert s.window_status(fl, (0.0, 40.0, 16.0, 16.0), vo.default_params()) == -1
+    big = torch.zeros((3, 32, 32, 2), device="cuda")
+    assert s.window_status(big, (40.0, 40.0, 16.0, 16.0), vo.default_params()) == -1
+    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(gamma=0.3)) == -1
+
+
+def _window_compare(vo, torch, w, kw, T, H, W, S):
+    p = vo.default_params(**kw)
+    s = vo.Solver(T, H, W, S)
+    poses, depth, rig, ll = s.window(torch.from_numpy(w["flows"]).cuda(), w["K"], p)
+    gp, gd, gr, gl = (x.cpu().numpy() for x in (poses, depth, rig, ll))
+    st, op, od, orig, oll, diag = oracle.window(w["flows"], w["K"], oracle.params(**kw))
+    assert st == 0
+    rot = [_rot_angle(gp[t, :9].reshape(3, 3), op[t, :9].reshape(3, 3)) for t in range(T)]
+    tdir = [_tdir_angle(gp[t, 9:], op[t, 9:]) for t in range(T)]
+    rel = np.abs(gd - od) / od
+    dr = np.abs(gr - orig)
+    return dict(rot=max(rot), tdir=max(tdir), depth_med=float(np.median(rel)),
+                rig_p99=float(np.percentile(dr, 99)), rig_p999=float(np.percentile(dr, 99.9)),
+                ll=abs(gl[0] - oll[0]) / oll[1])
+
+
+def test_window_parity_small(vo, torch):
+    T, H, W = 3, 48, 72
+    w = synthflow.make_window("small", 51, T=T, H=H, W=W)
+    r = _window_compare(vo, torch, w, dict(n_iters=2, n_pose_groups=200), T, H, W, 256)
+    print(r)
+    assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
+    assert r["depth_med"] <= 1e-3
+    assert r["rig_p99"] <= 1e-4
+    assert r["ll"] <= 1e-5
+
+
+def test_window_parity_cpu_sized_workload(vo, torch):
+    # T=5, 160x120, 3 iterations, 256 groups per frame, seed 0
+    w = synthflow.make_window("small", 0)
+    spec = w["spec"]
+    r = _window_compare(vo, torch, w, dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups),
+                        spec.T, spec.H, spec.W, 256)
+    print(r)
+    assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
+    assert r["depth_med"] <= 1e-3
+    assert r["rig_p99"] <= 1e-4
+    assert r["ll"] <= 1e-5
