@@ -101,6 +101,14 @@ int voldor_window(voldor_ctx *ctx, const float *flows, int T, int H, int W, cons
                   const voldor_params *p, double *poses, float *depth, float *rigidness,
                   double *loglik, void *stream);
 
+/* Phase timing of voldor_window with HIP events recorded on its stream.
+ * voldor_set_timing(ctx, 1) creates the events (0 destroys them); after a
+ * window, voldor_last_timing fills out[8] with milliseconds: [0] bootstrap,
+ * [1] pose steps, [2] directional sweeps, [3] number of sweep launches,
+ * [4] rigidness and gauge, [5] log-likelihood, [6] whole window, [7] unused. */
+int voldor_set_timing(voldor_ctx *ctx, int enable);
+int voldor_last_timing(voldor_ctx *ctx, double *out);
+
 /* ---- step entry points: one step of the loop on explicit state ----------- */
 
 /* Philox4x64-10 (Salmon et al., SC'11) on n counters: ctr, out device

@@ -85,6 +85,7 @@ def lib():
             "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
             "or_window": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d]),
             "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
+            "or_null_vector_8x9": (None, [d, d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -146,6 +147,13 @@ def sym_eig(A):
     V = np.zeros((n, n))
     lib().or_sym_eig(n, _ptr(A), _ptr(w), _ptr(V))
     return w, V
+
+
+def null_vector_8x9(A):
+    A = _d(A)
+    e = np.zeros(9)
+    lib().or_null_vector_8x9(_ptr(A), _ptr(e))
+    return e
 
 
 def svd3(A):

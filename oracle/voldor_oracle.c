@@ -1030,6 +1030,43 @@ static int cmp_double(const void *a, const void *b)
     return x < y ? -1 : x > y;
 }
 
+/* Unit null vector of the 8x9 epipolar system (rows of A): with exactly eight
+ * correspondences the least-squares solution of the 8-point method is the
+ * null vector of A.  It is the last column of Q in the Householder QR
+ * factorisation A^T = Q R (9x9 Q). */
+void or_null_vector_8x9(const double *A, double *e)
+{
+    double M[9][8], V[8][9], beta[8];
+    for (int i = 0; i < 9; ++i)
+        for (int k = 0; k < 8; ++k) M[i][k] = A[9 * k + i];
+    for (int k = 0; k < 8; ++k) {
+        double nrm = 0;
+        for (int i = k; i < 9; ++i) nrm += M[i][k] * M[i][k];
+        nrm = sqrt(nrm);
+        double alpha = M[k][k] > 0 ? -nrm : nrm;
+        double vn = 0;
+        for (int i = 0; i < 9; ++i) V[k][i] = i < k ? 0 : M[i][k];
+        V[k][k] -= alpha;
+        for (int i = k; i < 9; ++i) vn += V[k][i] * V[k][i];
+        beta[k] = vn > 0 ? 2.0 / vn : 0.0;
+        for (int j = k; j < 8; ++j) {
+            double s = 0;
+            for (int i = k; i < 9; ++i) s += V[k][i] * M[i][j];
+            for (int i = k; i < 9; ++i) M[i][j] -= beta[k] * s * V[k][i];
+        }
+    }
+    for (int i = 0; i < 9; ++i) e[i] = (i == 8);
+    for (int k = 7; k >= 0; --k) {   /* Q e_9 = H_0 H_1 ... H_7 e_9 */
+        double s = 0;
+        for (int i = k; i < 9; ++i) s += V[k][i] * e[i];
+        for (int i = k; i < 9; ++i) e[i] -= beta[k] * s * V[k][i];
+    }
+    double n = 0;
+    for (int i = 0; i < 9; ++i) n += e[i] * e[i];
+    n = sqrt(n);
+    for (int i = 0; i < 9; ++i) e[i] /= n;
+}
+
 /* triangulated z-depth along the frame-0 ray from relative pose (R, t) */
 static double triangulate(const double *R, const double *t, double xn, double yn, double bx,
                           double by, int *ok)
@@ -1085,7 +1122,7 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
         }
         if (!got) continue;
         /* 8-point system b^T E a = 0 in normalised coordinates */
-        double A[72], AtA[81], w[9], V[81];
+        double A[72];
         for (int k = 0; k < 8; ++k) {
             int x = (int)(idx[k] % W), y = (int)(idx[k] / W);
             double a[3] = {(x - cx) / fx, (y - cy) / fy, 1};
@@ -1093,15 +1130,8 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
             for (int i = 0; i < 3; ++i)
                 for (int l = 0; l < 3; ++l) A[9 * k + 3 * i + l] = b[i] * a[l];
         }
-        for (int i = 0; i < 9; ++i)
-            for (int l = 0; l < 9; ++l) {
-                double s = 0;
-                for (int k = 0; k < 8; ++k) s += A[9 * k + i] * A[9 * k + l];
-                AtA[9 * i + l] = s;
-            }
-        or_sym_eig(9, AtA, w, V);
         double E0[9], U[9], Sg[3], Vv[9], E[9];
-        for (int i = 0; i < 9; ++i) E0[i] = V[9 * i + 0];
+        or_null_vector_8x9(A, E0);
         /* projection onto the essential manifold: U diag(1,1,0) V^T */
         or_svd3(E0, U, Sg, Vv);
         for (int i = 0; i < 3; ++i)

@@ -66,6 +66,8 @@ def lib():
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
         "voldor_pose_step": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, i, i, dp, dp, vp, ip, vp]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
+        "voldor_set_timing": (i, [vp, i]),
+        "voldor_last_timing": (i, [vp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -174,6 +176,18 @@ class Solver:
         Kd, Kp = _dbl(K)
         return lib().voldor_window(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(poses),
                                    _ptr(depth), _ptr(rig), None, _stream(stream))
+
+    def set_timing(self, enable=True):
+        _check(lib().voldor_set_timing(self._ctx, 1 if enable else 0), "voldor_set_timing")
+
+    def last_timing(self):
+        """Milliseconds of the last window: bootstrap, pose, sweeps, sweep launches,
+        rigidness+gauge, log-likelihood, whole window."""
+        out = np.zeros(8)
+        _check(lib().voldor_last_timing(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "voldor_last_timing")
+        keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window"]
+        return dict(zip(keys, out[:7].tolist()))
 
     # -- single steps ---------------------------------------------------------
     def emission(self, theta, flows, K, params, M, stream=None):

@@ -107,6 +107,35 @@ hipError_t dalloc(T **p, size_t n)
     return hipMalloc((void **)p, n * sizeof(T) + 16);
 }
 
+// phase timing: an event after each phase; the interval ending at event i
+// belongs to ev_phase[i]
+enum { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseRig = 4, kPhaseLL = 5 };
+
+void mark(voldor_ctx *c, hipStream_t s, int phase)
+{
+    if (!c->timing || c->n_ev >= 256) return;
+    if (hipEventRecord(c->ev[c->n_ev], s) != hipSuccess) return;
+    c->ev_phase[c->n_ev] = phase;
+    ++c->n_ev;
+}
+
+// last_ms: [0] bootstrap, [1] pose steps, [2] sweeps, [3] sweep launches,
+// [4] rigidness + gauge, [5] log-likelihood, [6] whole window
+void collect_timing(voldor_ctx *c)
+{
+    if (!c->timing) return;
+    for (int i = 0; i < 8; ++i) c->last_ms[i] = 0.0;
+    for (int i = 1; i < c->n_ev; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[i - 1], c->ev[i]) != hipSuccess) continue;
+        const int ph = c->ev_phase[i];
+        if (ph >= 0 && ph < 6) c->last_ms[ph] += ms;
+        if (ph == kPhaseSweep) c->last_ms[3] += 1.0;
+    }
+    float tot = 0.0f;
+    if (c->n_ev > 1 && hipEventElapsedTime(&tot, c->ev[0], c->ev[c->n_ev - 1]) == hipSuccess) c->last_ms[6] = tot;
+}
+
 int upload_M(voldor_ctx *c, const double *M, int T, hipStream_t s)
 {
     if (hipMemcpyAsync(c->Mcum, M, sizeof(double) * 12 * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -216,6 +245,7 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
 void voldor_destroy(voldor_ctx *c)
 {
     if (!c) return;
+    voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->dkeys, c->hist,
                     c->sel, c->ll_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
@@ -237,31 +267,60 @@ int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const 
     WinDims d = dims(T, H, W, K);
     const EmisParams e = emis(K, p);
     const PoseParams pp = pose_params(p);
+    c->n_ev = 0;
+    mark(c, s, kPhaseNone);
     int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
                               p->depth_lo, p->depth_hi, poses, depth, s);
+    mark(c, s, kPhaseBoot);
     for (int it = 0; it < p->n_iters && rc == 0; ++it) {
         d.use_w = it > 0;
         for (int t = 1; t <= T && rc == 0; ++t)
             rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0,
                                   poses, s);
         if (rc == 0) rc = launch_frames(c, T, s);
+        mark(c, s, kPhasePose);
         for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw) {
             const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
             rc = launch_sweep(c, depth, depth, X, d, e, (float)p->gamma, p->seed, gs, (int)(gs % 4),
                               c->range, nullptr, s);
+            mark(c, s, kPhaseSweep);
         }
         if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, rigidness, nullptr, nullptr, nullptr, nullptr, s);
         if (rc == 0) rc = launch_gauge(c, poses, depth, d, s);
+        mark(c, s, kPhaseRig);
     }
     if (rc == 0 && loglik) {
         rc = launch_frames(c, T, s);
         if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, loglik, s);
+        mark(c, s, kPhaseLL);
     }
     if (rc != 0) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
+    collect_timing(c);
     int st = 0;
     if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
     return st;
+}
+
+int voldor_set_timing(voldor_ctx *c, int enable)
+{
+    if (!c) return VOLDOR_EINVAL;
+    if (enable && !c->timing) {
+        for (int i = 0; i < 256; ++i)
+            if (hipEventCreate(&c->ev[i]) != hipSuccess) return VOLDOR_EDEVICE;
+        c->timing = 1;
+    } else if (!enable && c->timing) {
+        for (int i = 0; i < 256; ++i) (void)hipEventDestroy(c->ev[i]);
+        c->timing = 0;
+    }
+    return VOLDOR_OK;
+}
+
+int voldor_last_timing(voldor_ctx *c, double *out)
+{
+    if (!c || !out) return VOLDOR_EINVAL;
+    for (int i = 0; i < 8; ++i) out[i] = c->last_ms[i];
+    return VOLDOR_OK;
 }
 
 int voldor_philox(const uint64_t *ctr, uint64_t key0, uint64_t key1, uint64_t *out, int n, void *stream)

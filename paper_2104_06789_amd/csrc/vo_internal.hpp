@@ -58,6 +58,12 @@ struct voldor_ctx {
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
     float *theta_tmp;      // [H_max W_max]
+    // optional phase timing of voldor_window (HIP events on the caller's stream)
+    int timing;
+    int n_ev;
+    hipEvent_t ev[256];
+    int ev_phase[256];     // phase of the interval that ends at ev[i]
+    double last_ms[8];
 };
 
 namespace vo {

@@ -230,7 +230,7 @@ def _fisk_noise(rng, flow, c1, c0, beta):
     return np.stack([e * np.cos(ang), e * np.sin(ang)], axis=-1)
 
 
-def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None):
+def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None, keep_focal=False):
     """Generate one window.
 
     Returns a dict with
@@ -251,10 +251,15 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None)
         sy = (H if H is not None else spec.H) / spec.H
         spec.W = W if W is not None else spec.W
         spec.H = H if H is not None else spec.H
-        spec.fx *= sx
-        spec.cx *= sx
-        spec.fy *= sy
-        spec.cy *= sy
+        if keep_focal:
+            # centre crop: same focal length, so flow magnitudes stay realistic
+            spec.cx *= sx
+            spec.cy *= sy
+        else:
+            spec.fx *= sx
+            spec.cx *= sx
+            spec.fy *= sy
+            spec.cy *= sy
     rng = np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0x5EED0000)))
     Tn, Hn, Wn = spec.T, spec.H, spec.W
 

@@ -247,6 +247,16 @@ def test_sym_eig_and_svd():
     assert np.allclose(U2[:, :2] * S2[:2] @ V2[:, :2].T, E, atol=1e-10)
 
 
+def test_null_vector_matches_svd():
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        A = rng.normal(size=(8, 9))
+        e = oracle.null_vector_8x9(A)
+        ref = np.linalg.svd(A)[2][-1]
+        assert abs(abs(e @ ref) - 1) < 1e-12
+        assert np.abs(A @ e).max() < 1e-12
+
+
 def _twist(p):
     X = np.zeros((4, 4))
     X[:3, :3] = np.array([[0, -p[5], p[4]], [p[5], 0, -p[3]], [-p[4], p[3], 0]])
