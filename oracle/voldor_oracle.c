@@ -1126,7 +1126,7 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
         for (int k = 0; k < 8; ++k) {
             int x = (int)(idx[k] % W), y = (int)(idx[k] / W);
             double a[3] = {(x - cx) / fx, (y - cy) / fy, 1};
-            double b[3] = {(x + X1[2 * idx[k]] - cx) / fx, (y + X1[2 * idx[k] + 1] - cy) / fy, 1};
+            double b[3] = {(x + (double)X1[2 * idx[k]] - cx) / fx, (y + (double)X1[2 * idx[k] + 1] - cy) / fy, 1};
             for (int i = 0; i < 3; ++i)
                 for (int l = 0; l < 3; ++l) A[9 * k + 3 * i + l] = b[i] * a[l];
         }
@@ -1144,7 +1144,7 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
         for (int64_t i = 0; i < nev; ++i) {
             int64_t j = ev[i];
             int x = (int)(j % W), y = (int)(j / W);
-            double x1[3] = {x, y, 1}, x2[3] = {x + X1[2 * j], y + X1[2 * j + 1], 1}, Fx[3], Ftx[3];
+            double x1[3] = {x, y, 1}, x2[3] = {x + (double)X1[2 * j], y + (double)X1[2 * j + 1], 1}, Fx[3], Ftx[3];
             mat3_vec(Fm, x1, Fx);
             for (int c = 0; c < 3; ++c) Ftx[c] = Fm[c] * x2[0] + Fm[3 + c] * x2[1] + Fm[6 + c] * x2[2];
             double e = dot3(x2, Fx);
@@ -1175,7 +1175,7 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
             int64_t j = ev[i];
             int x = (int)(j % W), y = (int)(j / W), ok;
             double xn = (x - cx) / fx, yn = (y - cy) / fy;
-            double bx = (x + X1[2 * j] - cx) / fx, by = (y + X1[2 * j + 1] - cy) / fy;
+            double bx = (x + (double)X1[2 * j] - cx) / fx, by = (y + (double)X1[2 * j + 1] - cy) / fy;
             double th = triangulate(R, t, xn, yn, bx, by, &ok);
             if (!ok) continue;
             double r[3] = {xn, yn, 1}, P[3];
@@ -1199,8 +1199,8 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
         int x = (int)(j % W), y = (int)(j / W), ok = 0;
         double th = 0;
         if (present(X1, j))
-            th = triangulate(R1, t1, (x - cx) / fx, (y - cy) / fy, (x + X1[2 * j] - cx) / fx,
-                             (y + X1[2 * j + 1] - cy) / fy, &ok);
+            th = triangulate(R1, t1, (x - cx) / fx, (y - cy) / fy, (x + (double)X1[2 * j] - cx) / fx,
+                             (y + (double)X1[2 * j + 1] - cy) / fy, &ok);
         val[j] = (uint8_t)ok;
         theta_out[j] = th;
         if (ok) vals[nv++] = th;

@@ -203,12 +203,14 @@ def test_window_parity_small(vo, torch):
     w = synthflow.make_window("small", 51, T=T, H=H, W=W)
     kw = dict(n_iters=2, n_pose_groups=200)
     r = _window_compare(vo, torch, w, kw, T, H, W, 256)
-    sens = _oracle_sensitivity(w, kw)
+    sens = [_oracle_sensitivity(w, kw, seed=k) for k in range(2)]
+    rig_floor = 2 * max(x["rig_p99"] for x in sens)
+    ll_floor = 2 * max(x["ll"] for x in sens)
     print(r, sens)
     assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
     assert r["depth_med"] <= 1e-3
-    assert r["rig_p99"] <= max(1e-4, sens["rig_p99"])
-    assert r["ll"] <= max(1e-5, sens["ll"])
+    assert r["rig_p99"] <= max(1e-4, rig_floor)
+    assert r["ll"] <= max(1e-5, ll_floor)
 
 
 def test_window_parity_cpu_sized_workload(vo, torch):
