@@ -41,10 +41,6 @@ bool dims_ok(const voldor_ctx *c, int T, int H, int W)
 {
     if (!c) return false;
     if (T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max) return false;
-    const int Lmax = H > W ? H : W;
-    if (Lmax > kBlock * kMaxPerThread) return false;
-    const int Tb = T;
-    if (kBlock / Tb < 1) return false;
     if ((int)sweep_lds_bytes(T, W) > c->max_lds || (int)sweep_lds_bytes(T, H) > c->max_lds) return false;
     return true;
 }
@@ -202,8 +198,8 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
         free(c);
         return VOLDOR_EDEVICE;
     }
-    // static LDS of the sweep kernel (frames + segment scan) comes off the top
-    c->max_lds = lds - (int)(sizeof(FrameF) * (kTMax + 1) + 12 * kBlock * sizeof(float)) - 256;
+    // static LDS of the sweep kernel (frames, list counters) comes off the top
+    c->max_lds = lds - (int)(sizeof(FrameF) * (kTMax + 1)) - 256;
     c->T_max = T_max;
     c->H_max = H_max;
     c->W_max = W_max;
@@ -224,6 +220,7 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->hist, 3 * 256) == hipSuccess;
     ok = ok && dalloc(&c->sel, 16) == hipSuccess;
     ok = ok && dalloc(&c->ll_part, 2 * kLLBlocks) == hipSuccess;
+    ok = ok && dalloc(&c->ms_part, (size_t)2 * 8 * (kMaxGroups / 256 + 1)) == hipSuccess;
     ok = ok && dalloc(&c->prev_pose, 12) == hipSuccess;
     ok = ok && dalloc(&c->pose_tmp, 16) == hipSuccess;
     ok = ok && dalloc(&c->rel_tmp, 12 * T_max) == hipSuccess;
@@ -248,7 +245,7 @@ void voldor_destroy(voldor_ctx *c)
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->dkeys, c->hist,
-                    c->sel, c->ll_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
+                    c->sel, c->ll_part, c->ms_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(c);

@@ -11,8 +11,6 @@
 namespace vo {
 
 constexpr int kTMax = 16;          // frames per window
-constexpr int kBlock = 256;        // threads of the chain kernels
-constexpr int kMaxPerThread = 16;  // chain positions per thread (L <= 4096)
 
 enum : uint64_t { kDepthStream = 1, kPoseStream = 2, kBootStream = 3 };
 

@@ -54,6 +54,7 @@ struct voldor_ctx {
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
+    double *ms_part;       // [2][kMaxGroups / 256][8] mean-shift partial sums
     double *prev_pose;     // [12] staging of a host-provided previous pose
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points

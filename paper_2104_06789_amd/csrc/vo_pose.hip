@@ -8,7 +8,11 @@
 //   k_pose_ms      densest candidate, Gaussian mean-shift to the mode,
 //                  T_t = exp(p*), M_t = T_t o M_{t-1};
 // plus the scale gauge |t_1| = 1.
+#include <hip/hip_cooperative_groups.h>
+
 #include "vo_internal.hpp"
+
+namespace cg = cooperative_groups;
 
 namespace vo {
 
@@ -231,44 +235,91 @@ __global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
 }
 
 struct MsArgs {
-    const double *samples;
+    const double *samples;  // [4S][8]
     const double *seed_score;
     double *rel;            // relative poses [T][12]; T_t written at t-1
     double *Mcum;           // cumulative poses [T+1][12]; M_t written
     int *diag;              // [4]
+    double *part;           // [2][gridDim][8] per-workgroup partial sums
     const int *status;
-    int n_slots, n_seeds, t, max_iters, fallback_prev_frame;
+    int S, n_seeds, t, max_iters, fallback_prev_frame;
     double is2t, is2r, tol;
 };
 
-constexpr int kMsThreads = 1024;
+constexpr int kMsThreads = 256;
 
+// Sum eight doubles over the workgroup; thread 0 writes them to out[0..7].
+__device__ __forceinline__ void block_sum8(double v[8], double (*red)[8], double *out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_down(v[c], off, 64);
+    if (lane == 0)
+        for (int c = 0; c < 8; ++c) red[wv][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double s = 0.0;
+        for (int w = 0; w < kMsThreads / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Mean-shift of frame t over all samples, cooperative: one P3P group (four
+// sample slots) per thread, samples held in registers for all iterations;
+// per-workgroup partial sums are combined in a fixed order after a grid
+// barrier, so every workgroup derives the same next estimate.
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 {
+    cg::grid_group grid = cg::this_grid();
     if (a.status && *a.status != kStatusOk) return;
-    __shared__ double red[kMsThreads / 64 + 1];
-    __shared__ double p[6];
-    __shared__ int stop;
-    const int tid = threadIdx.x;
-    // number of samples and total weight
-    double n = 0.0, ws = 0.0;
-    for (int i = tid; i < a.n_slots; i += kMsThreads) {
-        const double *q = a.samples + 8 * i;
-        if (q[7] != 0.0) { n += 1.0; ws += q[6]; }
+    __shared__ double red[kMsThreads / 64][8];
+    __shared__ double p[8];
+    __shared__ double tot[8];
+    __shared__ int s_stop;
+    const int tid = threadIdx.x, G = gridDim.x;
+    const int g = blockIdx.x * kMsThreads + tid;
+    double q[4][7];
+    bool v[4];
+    double nv = 0.0, ws = 0.0, anyg = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double *src = a.samples + (size_t)8 * (4 * g + s);
+        v[s] = g < a.S && src[7] != 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) q[s][c] = v[s] ? src[c] : 0.0;
+        if (v[s]) { nv += 1.0; ws += q[s][6]; anyg = 1.0; }
     }
-    const double N = block_sum<kMsThreads>(n, red);
-    const double WS = block_sum<kMsThreads>(ws, red);
+    int round = 0;
+    {
+        double vals[8] = {nv, ws, anyg, 0, 0, 0, 0, 0};
+        block_sum8(vals, red, a.part + (size_t)8 * ((round & 1) * G + blockIdx.x));
+    }
+    __threadfence();
+    grid.sync();
+    if (tid < 8) {
+        double s = 0.0;
+        for (int b = 0; b < G; ++b) s += a.part[(size_t)8 * ((round & 1) * G + b) + tid];
+        tot[tid] = s;
+    }
+    ++round;
+    __syncthreads();
+    const double N = tot[0], WS = tot[1], NG = tot[2];
     double *Tt = a.rel + 12 * (a.t - 1);
     if (N == 0.0 || !(WS > 0.0)) {
-        if (tid == 0) {
+        if (blockIdx.x == 0 && tid == 0) {
             if (a.fallback_prev_frame)
                 for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
             pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
-            a.diag[0] = (int)N; a.diag[2] = 0; a.diag[3] = 1;
+            a.diag[0] = (int)N;
+            a.diag[1] = (int)NG;
+            a.diag[2] = 0;
+            a.diag[3] = 1;
         }
         return;
     }
     if (tid == 0) {
+        // densest start candidate (earliest on ties)
         int best = -1;
         double bd = 0.0;
         for (int i = 0; i <= a.n_seeds; ++i) {
@@ -277,47 +328,53 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
             if (best < 0 || s[6] > bd) { best = i; bd = s[6]; }
         }
         if (best < 0) {
-            // no start candidate: the first valid sample in slot order
-            for (int i = 0; i < a.n_slots; ++i)
+            for (int i = 0; i < 4 * a.S; ++i)
                 if (a.samples[8 * i + 7] != 0.0) { for (int c = 0; c < 6; ++c) p[c] = a.samples[8 * i + c]; break; }
         } else {
             for (int c = 0; c < 6; ++c) p[c] = a.seed_score[8 * best + c];
         }
-        stop = 0;
+        s_stop = 0;
     }
     __syncthreads();
     int it = 0;
     for (; it < a.max_iters; ++it) {
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
         double pc[6];
         for (int c = 0; c < 6; ++c) pc[c] = p[c];
-        for (int i = tid; i < a.n_slots; i += kMsThreads) {
-            const double *q = a.samples + 8 * i;
-            if (q[7] == 0.0) continue;
-            const double k = q[6] * exp(-0.5 * mahal2(pc, q, a.is2t, a.is2r));
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (!v[s]) continue;
+            const double k = q[s][6] * exp(-0.5 * mahal2(pc, q[s], a.is2t, a.is2r));
             acc[6] += k;
-            for (int c = 0; c < 6; ++c) acc[c] += k * q[c];
+            for (int c = 0; c < 6; ++c) acc[c] += k * q[s][c];
         }
-        double tot[7];
-        for (int c = 0; c < 7; ++c) tot[c] = block_sum<kMsThreads>(acc[c], red);
+        block_sum8(acc, red, a.part + (size_t)8 * ((round & 1) * G + blockIdx.x));
+        __threadfence();
+        grid.sync();
+        if (tid < 7) {
+            double s = 0.0;
+            for (int b = 0; b < G; ++b) s += a.part[(size_t)8 * ((round & 1) * G + b) + tid];
+            tot[tid] = s;
+        }
+        ++round;
+        __syncthreads();
         if (tid == 0) {
             if (!(tot[6] > 0.0)) {
-                stop = 2;
+                s_stop = 2;
             } else {
                 double np[6];
                 for (int c = 0; c < 6; ++c) np[c] = tot[c] / tot[6];
                 const double step = sqrt(mahal2(np, pc, a.is2t, a.is2r));
                 for (int c = 0; c < 6; ++c) p[c] = np[c];
-                stop = step < a.tol ? 1 : 0;
+                s_stop = step < a.tol ? 1 : 0;
             }
         }
         __syncthreads();
-        const int st = stop;
-        __syncthreads();
+        const int st = s_stop;
         if (st == 2) break;
         if (st == 1) { ++it; break; }
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         double pp[6], R[9], tv[3];
         for (int c = 0; c < 6; ++c) pp[c] = p[c];
         se3_exp(pp, R, tv);
@@ -325,26 +382,10 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         for (int k = 0; k < 3; ++k) Tt[9 + k] = tv[k];
         pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
         a.diag[0] = (int)N;
+        a.diag[1] = (int)NG;
         a.diag[2] = it;
         a.diag[3] = 0;
     }
-}
-
-__global__ void k_group_count(const double *samples, int S, const int *status, int *diag)
-{
-    if (status && *status != kStatusOk) return;
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    int c = 0;
-    for (int g = threadIdx.x; g < S; g += blockDim.x) {
-        bool any = false;
-        for (int s = 0; s < 4; ++s) any = any || samples[8 * (4 * g + s) + 7] != 0.0;
-        c += any;
-    }
-    atomicAdd(&cnt, c);
-    __syncthreads();
-    if (threadIdx.x == 0) diag[1] = cnt;
 }
 
 // scale gauge |t_1| = 1: translations, depth range, cumulative poses
@@ -397,7 +438,6 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.seed = pp.seed;
     hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
     int *diag = c->pose_diag + 4 * (t - 1);
-    hipLaunchKernelGGL(k_group_count, dim3(1), dim3(256), 0, s, c->samples, pp.S, c->status, diag);
     SeedArgs sa;
     sa.samples = c->samples;
     sa.seed_score = c->seed_score;
@@ -415,8 +455,9 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.rel = rel_poses;
     m.Mcum = c->Mcum;
     m.diag = diag;
+    m.part = c->ms_part;
     m.status = c->status;
-    m.n_slots = 4 * pp.S;
+    m.S = pp.S;
     m.n_seeds = pp.n_seeds;
     m.t = t;
     m.max_iters = pp.ms_max_iters;
@@ -424,7 +465,10 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.is2t = 1.0 / pp.s2t;
     m.is2r = 1.0 / pp.s2r;
     m.tol = pp.ms_tol;
-    hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
+    void *kargs[] = {&m};
+    const int G = (pp.S + kMsThreads - 1) / kMsThreads;
+    if (hipLaunchCooperativeKernel((const void *)k_pose_ms, dim3(G), dim3(kMsThreads), kargs, 0, s) != hipSuccess)
+        return VOLDOR_EDEVICE;
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 

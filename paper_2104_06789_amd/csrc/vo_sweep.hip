@@ -3,23 +3,30 @@
 // propagation, Eq. 10 and Fig. 5), the unsmoothed rigidness with the
 // log-likelihood of Eq. 3, and the Philox test kernel.
 //
-// One workgroup owns one chain (an image row for directions 0/2, a column for
-// 1/3) for all T frames, so every phase of a sweep runs out of LDS:
-//   A  ell_t(prev) and r_t(prev) for every chain position and frame;
-//   B  forward-backward per frame as a segmented scan of 2x2 transfer
-//      matrices (one segment per thread, serial over the segments);
-//   S  scores of the previous depth and of the random sample under q, the
-//      local best a_j = best(prev, sample);
-//   C  for every position k, how far its local best would survive as the
-//      propagated neighbour: next(k) = first j > k where it loses;
-//   D  the propagation path 0 -> next(0) -> next(next(0)) ... found by pointer
-//      doubling; every position takes the local best of the last path node
-//      at or before it.
-// C/D reproduce the serial left-to-right walk exactly (each score is the same
-// FP32 function of position and value), without a serial dependency chain.
+// One workgroup of kSweepThreads owns one chain (an image row for directions
+// 0/2, a column for 1/3) for all T frames; every phase runs out of LDS:
+//   A  ell_t and r_t of the previous depth, one thread per (position, frame);
+//   B  forward-backward per frame: one wave per frame, one chain segment per
+//      lane, 2x2 transfer matrices combined by wave shuffles (prefix and
+//      suffix scans), then each lane replays its segment;
+//   S  MIE scores sum_t q_t ell_t of the previous depth and of the random
+//      sample, the local best a_k = best(prev, sample) with its score;
+//   C  for every origin k, next(k) = first j > k where a_k loses as the
+//      propagated neighbour (prev > neighbour > sample on ties), found in
+//      rounds over a shrinking list of live origins with a look-ahead that
+//      grows as the list shrinks;
+//   D  the propagation path 0 -> next(0) -> next(next(0)) ... by pointer
+//      doubling; each position takes the local best of the last path node at
+//      or before it.
+// C/D give exactly the result of the serial walk along the chain: each score
+// is the same FP32 function of (position, value) in every phase.
 #include "vo_internal.hpp"
 
 namespace vo {
+
+constexpr int kSweepThreads = 512;
+constexpr int kSweepWaves = kSweepThreads / 64;
+constexpr float kLogHalf = -0.69314718055994531f;
 
 __device__ __forceinline__ int chain_pixel(int dir, int H, int W, int c, int k)
 {
@@ -31,43 +38,85 @@ __device__ __forceinline__ int chain_pixel(int dir, int H, int W, int c, int k)
     }
 }
 
-// Emission terms of depth th at pixel (x, y) for frame t (1..T): returns the
-// log-odds d = log(mu/rho), or +nan when the observation is missing.
-__device__ __forceinline__ float frame_log_odds(const FrameF *fr, const float2 *__restrict__ flows,
-                                                int H, int W, const EmisParams &e, int x, int y,
-                                                float xh, float yh, float th, int t, float &px0,
-                                                float &py0, bool &ok0)
+// log(mu/rho) of depth th at pixel (x, y) for frame t; false if missing
+__device__ __forceinline__ bool item_log_odds(const FrameF *fr, const float2 *__restrict__ flows,
+                                              int H, int W, const EmisParams &e, int x, int y,
+                                              float xh, float yh, float th, int t, float &d)
 {
-    // px0/py0/ok0 carry pi_{t-1} - pixel between consecutive frames
-    float dx1, dy1;
-    const bool ok1 = displacement(fr[t], xh, yh, th, e.fx, e.fy, dx1, dy1);
-    float d = __int_as_float(0x7fc00000);
-    if (ok0 && ok1) {
-        float vu, vv;
-        const float2 *X = flows + (size_t)(t - 1) * H * W;
-        if (sample_flow(X, H, W, (float)x + px0, (float)y + py0, vu, vv)) {
-            const float rx = (dx1 - px0) - vu, ry = (dy1 - py0) - vv;
-            d = log_mu_over_rho(rx, ry, vu, vv, e);
-        }
-    }
-    px0 = dx1;
-    py0 = dy1;
-    ok0 = ok1;
-    return d;
+    if (!(th > 0.0f)) return false;
+    float dx0 = 0.0f, dy0 = 0.0f, dx1, dy1;
+    if (t > 1 && !displacement(fr[t - 1], xh, yh, th, e.fx, e.fy, dx0, dy0)) return false;
+    if (!displacement(fr[t], xh, yh, th, e.fx, e.fy, dx1, dy1)) return false;
+    float vu, vv;
+    if (!sample_flow(flows + (size_t)(t - 1) * H * W, H, W, (float)x + dx0, (float)y + dy0, vu, vv))
+        return false;
+    d = log_mu_over_rho((dx1 - dx0) - vu, (dy1 - dy0) - vv, vu, vv, e);
+    return true;
 }
 
-// MIE score sum_t q_t ell_t(th) at chain position k (q in LDS, [T][L]).
-__device__ __forceinline__ float mie_score(const FrameF *fr, const float2 *__restrict__ flows,
-                                           int T, int H, int W, const EmisParams &e, int x, int y,
-                                           float xh, float yh, float th, const float *q, int L,
-                                           int k)
+// MIE score sum_t q_t ell_t(th) at chain position k, frames in chunks of four
+// so that the flow gathers of a chunk are in flight together
+__device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
+                                             int T, int H, int W, const EmisParams &e, int x, int y,
+                                             float xh, float yh, float th, const float *q, int L,
+                                             int k)
 {
-    float px0 = 0.0f, py0 = 0.0f, s = 0.0f;
-    bool ok0 = th > 0.0f;
-    for (int t = 1; t <= T; ++t) {
-        const float d = frame_log_odds(fr, flows, H, W, e, x, y, xh, yh, th, t, px0, py0, ok0);
-        const float ell = isnan(d) ? -0.69314718055994531f : emis_from_d(d).ell;
-        s = fmaf(q[(t - 1) * L + k], ell, s);
+    float s = 0.0f;
+    float pdx = 0.0f, pdy = 0.0f;
+    bool pok = th > 0.0f;
+    const size_t HW = (size_t)H * W;
+    for (int t0 = 1; t0 <= T; t0 += 4) {
+        float dx[4], dy[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            dx[u] = 0.0f;
+            dy[u] = 0.0f;
+            ok[u] = t <= T && th > 0.0f && displacement(fr[t <= T ? t : T], xh, yh, th, e.fx, e.fy, dx[u], dy[u]);
+        }
+        float2 ta[4], tb[4], tc[4], td[4];
+        float ax[4], ay[4], lx[4], ly[4];
+        bool val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float bdx = u == 0 ? pdx : dx[u - 1], bdy = u == 0 ? pdy : dy[u - 1];
+            const bool bok = u == 0 ? pok : ok[u - 1];
+            const float px = (float)x + bdx, py = (float)y + bdy;
+            val[u] = bok && ok[u] && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f &&
+                     py <= (float)(H - 1);
+            lx[u] = bdx;
+            ly[u] = bdy;
+            const float spx = val[u] ? px : 0.0f, spy = val[u] ? py : 0.0f;
+            const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
+            ax[u] = spx - (float)x0;
+            ay[u] = spy - (float)y0;
+            const int tf = val[u] ? t0 + u - 1 : 0;
+            const float2 *r0 = flows + (size_t)tf * HW + (size_t)y0 * W + x0;
+            ta[u] = r0[0];
+            tb[u] = r0[1];
+            tc[u] = r0[W];
+            td[u] = r0[W + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            if (t > T) break;
+            float ell = kLogHalf;
+            if (val[u]) {
+                const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
+                if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
+                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    const float dd = log_mu_over_rho((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                    ell = emis_from_d(dd).ell;
+                }
+            }
+            s = fmaf(q[(t - 1) * L + k], ell, s);
+        }
+        pdx = dx[3];
+        pdy = dy[3];
+        pok = ok[3];
     }
     return s;
 }
@@ -87,41 +136,86 @@ struct SweepArgs {
     int64_t gsweep;
 };
 
-__global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
+struct Mat2 {
+    float a, b, c, d;  // [[a b] [c d]]
+};
+
+__device__ __forceinline__ Mat2 mul_norm(const Mat2 &x, const Mat2 &y)
+{
+    Mat2 r;
+    r.a = x.a * y.a + x.b * y.c;
+    r.b = x.a * y.b + x.b * y.d;
+    r.c = x.c * y.a + x.d * y.c;
+    r.d = x.c * y.b + x.d * y.d;
+    const float inv = 1.0f / (r.a + r.b + r.c + r.d);
+    r.a *= inv;
+    r.b *= inv;
+    r.c *= inv;
+    r.d *= inv;
+    return r;
+}
+
+__device__ __forceinline__ Mat2 shfl_up_m(const Mat2 &m, int d)
+{
+    Mat2 r;
+    r.a = __shfl_up(m.a, d, 64);
+    r.b = __shfl_up(m.b, d, 64);
+    r.c = __shfl_up(m.c, d, 64);
+    r.d = __shfl_up(m.d, d, 64);
+    return r;
+}
+
+__device__ __forceinline__ Mat2 shfl_down_m(const Mat2 &m, int d)
+{
+    Mat2 r;
+    r.a = __shfl_down(m.a, d, 64);
+    r.b = __shfl_down(m.b, d, 64);
+    r.c = __shfl_down(m.c, d, 64);
+    r.d = __shfl_down(m.d, d, 64);
+    return r;
+}
+
+// LDS words of the dynamic area for a chain of length L and T frames
+__host__ __device__ inline int sweep_region2_words(int T, int L)
+{
+    int w = T * L;
+    if (w < 8 * L) w = 8 * L;
+    if (w < 4 * L + kSweepThreads) w = 4 * L + kSweepThreads;
+    return w;
+}
+
+__global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
     extern __shared__ float lds[];
     __shared__ FrameF fr[kTMax + 1];
-    __shared__ float seg_f[kBlock][4], seg_b[kBlock][4];  // per-thread segment matrices
-    __shared__ float fin[kBlock][2], bout[kBlock][2];      // segment boundary messages
+    __shared__ int s_cnt[2];
 
     const int T = a.T, H = a.H, W = a.W, dir = a.dir;
     const int L = (dir & 1) ? H : W;
     const int tid = threadIdx.x;
-    // XCD-aware chain order: consecutive chains on one XCD share its L2
+    // XCD-aware chain order: workgroups are dealt round-robin to the 8 XCDs,
+    // so give each XCD a contiguous range of chains (neighbouring chains
+    // share flow cache lines in that XCD's L2)
     const int nchain = gridDim.x;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int per = (nchain + 7) >> 3;
-    int chain = xcd * per + slot;
-    {
-        // map the 8 interleaved ranges back onto [0, nchain) without holes
-        const int full = nchain - (per - 1) * 8;  // XCDs that get `per` chains
-        if (xcd < full) chain = xcd * per + slot;
-        else chain = full * per + (xcd - full) * (per - 1) + slot;
-    }
+    const int full = nchain - (per - 1) * 8;
+    const int chain = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
 
-    float *th = lds;                       // [L] previous depth
-    float *sm = th + L;                    // [L] random sample
-    float *lq = sm + L;                    // [T][L] ell(prev); later overlay
-    const int over = (T > 8 ? T : 8);
-    float *fq = lq + over * L;             // [T][L] r -> forward message -> q
+    float *th = lds;                                   // [L]   previous depth
+    float *sm = th + L;                                // [L]   random sample
+    float *aval = sm + L;                              // [L]   local best value
+    float *sa = aval + L;                              // [L]   score: previous, then local best
+    int *flg = (int *)(sa + L);                        // [L]   1 if the sample is the local best
+    int *nxt = flg + L;                                // [L]   next(k)
+    float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
+    float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
 
-    for (int i = tid; i < (T + 1) * 12; i += kBlock) ((float *)fr)[i] = ((const float *)a.frames)[i];
-
-    const float d_lo = (float)a.range[0];
+    for (int i = tid; i < (T + 1) * 12; i += kSweepThreads) ((float *)fr)[i] = ((const float *)a.frames)[i];
+    const float llo = (float)log(a.range[0]);
     const float lrange = (float)(log(a.range[1]) - log(a.range[0]));
-    const float llo = logf(d_lo);
-    for (int k = tid; k < L; k += kBlock) {
+    for (int k = tid; k < L; k += kSweepThreads) {
         const int j = chain_pixel(dir, H, W, chain, k);
         th[k] = a.theta_in[j];
         uint64_t c[4] = {(uint64_t)a.gsweep, (uint64_t)j, 0ull, 0ull};
@@ -131,193 +225,211 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
     }
     __syncthreads();
 
-    // ---- A: emissions of the previous depth
-    for (int k = tid; k < L; k += kBlock) {
+    // ---- A: ell and r of the previous depth, one item per (position, frame)
+    for (int i = tid; i < T * L; i += kSweepThreads) {
+        const int t = i / L + 1, k = i - (t - 1) * L;
         const int j = chain_pixel(dir, H, W, chain, k);
         const int x = j % W, y = j / W;
         const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
-        const float t0 = th[k];
-        float px0 = 0.0f, py0 = 0.0f;
-        bool ok0 = t0 > 0.0f;
-        for (int t = 1; t <= T; ++t) {
-            const float d = frame_log_odds(fr, a.flows, H, W, a.e, x, y, xh, yh, t0, t, px0, py0, ok0);
-            Emis m;
-            if (isnan(d)) { m.ell = -0.69314718055994531f; m.r = 0.5f; }
-            else m = emis_from_d(d);
-            lq[(t - 1) * L + k] = m.ell;
-            fq[(t - 1) * L + k] = m.r;
+        float d;
+        float ell = kLogHalf, r = 0.5f;
+        if (item_log_odds(fr, a.flows, H, W, a.e, x, y, xh, yh, th[k], t, d)) {
+            const Emis m = emis_from_d(d);
+            ell = m.ell;
+            r = m.r;
         }
+        lq[i] = ell;
+        fq[i] = r;
     }
     __syncthreads();
 
-    // ---- B: forward-backward per frame, one segment per thread
-    const int nseg = kBlock / T;
-    const int seglen = (L + nseg - 1) / nseg;
-    const float g = a.gamma, gc = 1.0f - a.gamma;
-    const int ft = tid / nseg, fs = tid - ft * nseg;
-    const bool fb_thread = ft < T;
-    const int s0 = min(fs * seglen, L), s1 = min(s0 + seglen, L);
-    if (fb_thread) {
-        const float *rr = fq + ft * L;
-        // forward: A_k = diag(r, 1-r) Gamma ; product A_{s1-1} ... A_{s0}
-        float F00 = 1, F01 = 0, F10 = 0, F11 = 1;
-        for (int k = s0; k < s1; ++k) {
-            const float r1 = rr[k], r0 = 1.0f - r1;
-            const float a00 = r1 * g, a01 = r1 * gc, a10 = r0 * gc, a11 = r0 * g;
-            const float n00 = a00 * F00 + a01 * F10, n01 = a00 * F01 + a01 * F11;
-            const float n10 = a10 * F00 + a11 * F10, n11 = a10 * F01 + a11 * F11;
-            const float inv = 1.0f / (n00 + n01 + n10 + n11);
-            F00 = n00 * inv; F01 = n01 * inv; F10 = n10 * inv; F11 = n11 * inv;
-        }
-        // backward: G_k = Gamma diag(r, 1-r) ; product G_{s0} ... G_{s1-1}
-        float B00 = 1, B01 = 0, B10 = 0, B11 = 1;
-        for (int k = s1 - 1; k >= s0; --k) {
-            const float r1 = rr[k], r0 = 1.0f - r1;
-            const float g00 = g * r1, g01 = gc * r0, g10 = gc * r1, g11 = g * r0;
-            const float n00 = g00 * B00 + g01 * B10, n01 = g00 * B01 + g01 * B11;
-            const float n10 = g10 * B00 + g11 * B10, n11 = g10 * B01 + g11 * B11;
-            const float inv = 1.0f / (n00 + n01 + n10 + n11);
-            B00 = n00 * inv; B01 = n01 * inv; B10 = n10 * inv; B11 = n11 * inv;
-        }
-        seg_f[tid][0] = F00; seg_f[tid][1] = F01; seg_f[tid][2] = F10; seg_f[tid][3] = F11;
-        seg_b[tid][0] = B00; seg_b[tid][1] = B01; seg_b[tid][2] = B10; seg_b[tid][3] = B11;
-    }
-    __syncthreads();
-    if (tid < T) {
-        const int base = tid * nseg;
-        float m1 = 0.5f, m0 = 0.5f;  // m_f(-1)
-        for (int s = 0; s < nseg; ++s) {
-            fin[base + s][0] = m1;
-            fin[base + s][1] = m0;
-            const float *F = seg_f[base + s];
-            const float n1 = F[0] * m1 + F[1] * m0, n0 = F[2] * m1 + F[3] * m0;
-            const float inv = 1.0f / (n1 + n0);
-            m1 = n1 * inv;
-            m0 = n0 * inv;
-        }
-        float b1 = 0.5f, b0 = 0.5f;  // m_b(L-1)
-        for (int s = nseg - 1; s >= 0; --s) {
-            bout[base + s][0] = b1;
-            bout[base + s][1] = b0;
-            const float *B = seg_b[base + s];
-            const float n1 = B[0] * b1 + B[1] * b0, n0 = B[2] * b1 + B[3] * b0;
-            const float inv = 1.0f / (n1 + n0);
-            b1 = n1 * inv;
-            b0 = n0 * inv;
-        }
-    }
-    __syncthreads();
-    if (fb_thread && s0 < s1) {
-        float *qq = fq + ft * L;
-        const float *ll = lq + ft * L;
-        float f1 = fin[tid][0], f0 = fin[tid][1];
-        for (int k = s0; k < s1; ++k) {
-            const float r1 = qq[k], r0 = 1.0f - r1;
-            const float p1 = g * f1 + gc * f0, p0 = gc * f1 + g * f0;
-            const float n1 = r1 * p1, n0 = r0 * p0;
-            const float inv = 1.0f / (n1 + n0);
-            f1 = n1 * inv;
-            f0 = n0 * inv;
-            qq[k] = f1;
-        }
-        float b1 = bout[tid][0], b0 = bout[tid][1];
-        for (int k = s1 - 1; k >= s0; --k) {
-            const float ff1 = qq[k], ff0 = 1.0f - ff1;
-            const float n1 = ff1 * b1, n0 = ff0 * b0;
-            qq[k] = n1 / (n1 + n0);
-            if (k > s0) {
-                const float r1 = __expf(ll[k]), r0 = 1.0f - r1;
-                const float e1 = r1 * b1, e0 = r0 * b0;
-                const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
-                const float inv = 1.0f / (m1 + m0);
-                b1 = m1 * inv;
-                b0 = m0 * inv;
+    // ---- B: forward-backward, one wave per frame, one segment per lane
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        const int seglen = (L + 63) / 64;
+        const float g = a.gamma, gc = 1.0f - a.gamma;
+        const int s0 = min(lane * seglen, L), s1 = min(s0 + seglen, L);
+        for (int t = wv; t < T; t += kSweepWaves) {
+            float *rq = fq + t * L;
+            const float *ll = lq + t * L;
+            // segment transfer matrices: forward A_k = diag(r,1-r) Gamma,
+            // product A_{s1-1}..A_{s0}; backward G_k = Gamma diag(r,1-r),
+            // product G_{s0}..G_{s1-1}
+            Mat2 F = {1, 0, 0, 1}, B = {1, 0, 0, 1};
+            for (int k = s0; k < s1; ++k) {
+                const float r1 = rq[k], r0 = 1.0f - r1;
+                const Mat2 A = {r1 * g, r1 * gc, r0 * gc, r0 * g};
+                F = mul_norm(A, F);
+            }
+            for (int k = s1 - 1; k >= s0; --k) {
+                const float r1 = rq[k], r0 = 1.0f - r1;
+                const Mat2 G = {g * r1, gc * r0, gc * r1, g * r0};
+                B = mul_norm(G, B);
+            }
+            // inclusive prefix of forward products (later segments on the left)
+            Mat2 P = F;
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const Mat2 Q = shfl_up_m(P, dd);
+                if (lane >= dd) P = mul_norm(P, Q);
+            }
+            // inclusive suffix of backward products (earlier segments on the left)
+            Mat2 Sx = B;
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const Mat2 Q = shfl_down_m(Sx, dd);
+                if (lane + dd < 64) Sx = mul_norm(Sx, Q);
+            }
+            const Mat2 Pp = shfl_up_m(P, 1), Sn = shfl_down_m(Sx, 1);
+            float f1 = 0.5f, f0 = 0.5f;   // m_f before the segment
+            if (lane > 0) {
+                const float n1 = 0.5f * (Pp.a + Pp.b), n0 = 0.5f * (Pp.c + Pp.d);
+                f1 = n1 / (n1 + n0);
+                f0 = n0 / (n1 + n0);
+            }
+            float b1 = 0.5f, b0 = 0.5f;   // m_b at the segment's last position
+            if (lane < 63) {
+                const float n1 = 0.5f * (Sn.a + Sn.b), n0 = 0.5f * (Sn.c + Sn.d);
+                b1 = n1 / (n1 + n0);
+                b0 = n0 / (n1 + n0);
+            }
+            for (int k = s0; k < s1; ++k) {
+                const float r1 = rq[k], r0 = 1.0f - r1;
+                const float p1 = g * f1 + gc * f0, p0 = gc * f1 + g * f0;
+                const float n1 = r1 * p1, n0 = r0 * p0;
+                const float inv = 1.0f / (n1 + n0);
+                f1 = n1 * inv;
+                f0 = n0 * inv;
+                rq[k] = f1;
+            }
+            for (int k = s1 - 1; k >= s0; --k) {
+                const float ff1 = rq[k], ff0 = 1.0f - ff1;
+                const float n1 = ff1 * b1, n0 = ff0 * b0;
+                rq[k] = n1 / (n1 + n0);
+                if (k > s0) {
+                    const float r1 = __expf(ll[k]), r0 = 1.0f - r1;
+                    const float e1 = r1 * b1, e0 = r0 * b0;
+                    const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
+                    const float inv = 1.0f / (m1 + m0);
+                    b1 = m1 * inv;
+                    b0 = m0 * inv;
+                }
             }
         }
     }
     __syncthreads();
     if (a.q_out) {
-        for (int i = tid; i < T * L; i += kBlock) {
+        for (int i = tid; i < T * L; i += kSweepThreads) {
             const int t = i / L, k = i - t * L;
             a.q_out[(size_t)t * H * W + chain_pixel(dir, H, W, chain, k)] = fq[i];
         }
     }
 
-    // ---- S: score of the previous depth (ell from A), kept in registers
-    float sprev[kMaxPerThread];
-#pragma unroll
-    for (int i = 0; i < kMaxPerThread; ++i) {
-        const int k = tid + i * kBlock;
+    // ---- S: score of the previous depth
+    for (int k = tid; k < L; k += kSweepThreads) {
         float s = 0.0f;
-        if (k < L)
-            for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
-        sprev[i] = s;
+        for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        sa[k] = s;
     }
-    __syncthreads();  // lq becomes the overlay below
-    float *aval = lq;                      // [L] local best value
-    float *sa = aval + L;                  // [L] its score
-    int *flg = (int *)(sa + L);            // [L] 1 if the sample is the local best
-    int *nxt = flg + L;                    // [L] next(k)
-    int *J0 = nxt + L, *J1 = J0 + L;       // [L] doubling pointers
-    int *mark = J1 + L;                    // [L] on the propagation path
-    float *thn = (float *)(mark + L);      // [L] new depth
-#pragma unroll
-    for (int i = 0; i < kMaxPerThread; ++i) {
-        const int k = tid + i * kBlock;
-        if (k < L) {
-            const int j = chain_pixel(dir, H, W, chain, k);
-            const int x = j % W, y = j / W;
-            const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
-            const float ss = mie_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, sm[k], fq, L, k);
-            const bool smp = ss > sprev[i];
-            aval[k] = smp ? sm[k] : th[k];
-            sa[k] = smp ? ss : sprev[i];
-            flg[k] = smp ? 1 : 0;
-            mark[k] = (k == 0);
-        }
+    __syncthreads();
+    // ell of the random sample, one item per (position, frame)
+    for (int i = tid; i < T * L; i += kSweepThreads) {
+        const int t = i / L + 1, k = i - (t - 1) * L;
+        const int j = chain_pixel(dir, H, W, chain, k);
+        const int x = j % W, y = j / W;
+        const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
+        float d, ell = kLogHalf;
+        if (item_log_odds(fr, a.flows, H, W, a.e, x, y, xh, yh, sm[k], t, d)) ell = emis_from_d(d).ell;
+        lq[i] = ell;
+    }
+    __syncthreads();
+    for (int k = tid; k < L; k += kSweepThreads) {
+        float s = 0.0f;
+        for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        const bool smp = s > sa[k];
+        aval[k] = smp ? sm[k] : th[k];
+        if (smp) sa[k] = s;
+        flg[k] = smp ? 1 : 0;
+    }
+    if (tid == 0) {
+        s_cnt[0] = L - 1;
+        s_cnt[1] = 0;
+    }
+    // live origins (origin, next position to test): every k < L-1 starts at k+1
+    int2 *list0 = (int2 *)lq, *list1 = list0 + L;
+    int *win = (int *)(list1 + L);
+    for (int k = tid; k < L; k += kSweepThreads) {
+        if (k < L - 1) list0[k] = make_int2(k, k + 1);
+        else nxt[k] = L;
     }
     __syncthreads();
 
     // ---- C: survival of every local best as the propagated neighbour
-    for (int k = tid; k < L; k += kBlock) {
-        const float v = aval[k];
-        int jpos = k + 1;
-        for (; jpos < L; ++jpos) {
-            const int j = chain_pixel(dir, H, W, chain, jpos);
-            const int x = j % W, y = j / W;
-            const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
-            const float s = mie_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, v, fq, L, jpos);
-            // the neighbour beats the previous depth only strictly, and the
-            // sample on ties (previous > neighbour > sample)
-            const bool win = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
-            if (!win) break;
+    int cur = 0;
+    for (;;) {
+        const int n = s_cnt[cur];
+        if (n == 0) break;
+        int2 *lc = cur ? list1 : list0, *ln = cur ? list0 : list1;
+        int la = kSweepThreads / n;                  // look-ahead per live origin
+        if (la < 1) la = 1;
+        if (la > 64) la = 64;
+        const int items = n * la;
+        for (int i = tid; i < items; i += kSweepThreads) {
+            const int sl = i / la, p = i - sl * la;
+            const int2 e = lc[sl];
+            const int jpos = e.y + p;
+            int w = 0;
+            if (jpos < L) {
+                const int j = chain_pixel(dir, H, W, chain, jpos);
+                const int x = j % W, y = j / W;
+                const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
+                const float s = chain_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
+                w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
+            }
+            win[i] = w;
         }
-        nxt[k] = jpos;
-        J0[k] = jpos;
+        if (tid == 0) s_cnt[cur ^ 1] = 0;
+        __syncthreads();
+        for (int sl = tid; sl < n; sl += kSweepThreads) {
+            const int2 e = lc[sl];
+            int p = 0;
+            while (p < la && win[sl * la + p]) ++p;
+            if (p < la) {
+                nxt[e.x] = min(e.y + p, L);
+            } else if (e.y + la >= L) {
+                nxt[e.x] = L;
+            } else {
+                const int at = atomicAdd(&s_cnt[cur ^ 1], 1);
+                ln[at] = make_int2(e.x, e.y + la);
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
     }
-    __syncthreads();
 
     // ---- D: nodes reachable from 0 through next(), by pointer doubling
+    int *J0 = (int *)lq, *J1 = J0 + L, *mark = J1 + L;
+    float *thn = (float *)(mark + L);
+    for (int k = tid; k < L; k += kSweepThreads) {
+        J0[k] = nxt[k];
+        mark[k] = k == 0;
+    }
+    __syncthreads();
     int *Jc = J0, *Jn = J1;
     for (int span = 1; span < L; span <<= 1) {
-        for (int k = tid; k < L; k += kBlock) {
+        for (int k = tid; k < L; k += kSweepThreads) {
             const int to = Jc[k];
             if (mark[k] && to < L) mark[to] = 1;
         }
         __syncthreads();
-        for (int k = tid; k < L; k += kBlock) {
+        for (int k = tid; k < L; k += kSweepThreads) {
             const int to = Jc[k];
             Jn[k] = to < L ? Jc[to] : L;
         }
         __syncthreads();
-        int *tmp = Jc; Jc = Jn; Jn = tmp;
+        int *tmp = Jc;
+        Jc = Jn;
+        Jn = tmp;
     }
-    for (int k = tid; k < L; k += kBlock) {
-        const int to = Jc[k];
-        if (mark[k] && to < L) mark[to] = 1;
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += kBlock) {
+    for (int k = tid; k < L; k += kSweepThreads) {
         if (mark[k]) {
             const int e = nxt[k];
             const float v = aval[k];
@@ -325,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
         }
     }
     __syncthreads();
-    for (int k = tid; k < L; k += kBlock) a.theta_out[chain_pixel(dir, H, W, chain, k)] = thn[k];
+    for (int k = tid; k < L; k += kSweepThreads) a.theta_out[chain_pixel(dir, H, W, chain, k)] = thn[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -465,8 +577,7 @@ __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t
 // ---------------------------------------------------------------------------
 size_t sweep_lds_bytes(int T, int L)
 {
-    const int over = T > 8 ? T : 8;
-    return (size_t)(2 + over + T) * L * sizeof(float);
+    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L)) * sizeof(float);
 }
 
 int launch_frames(voldor_ctx *c, int T, hipStream_t s)
@@ -482,7 +593,7 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     const int L = (dir & 1) ? d.H : d.W;
     const int nchain = (dir & 1) ? d.W : d.H;
     const size_t lds = sweep_lds_bytes(d.T, L);
-    if (L > kBlock * kMaxPerThread) return VOLDOR_EINVAL;
+    if (L < 16) return VOLDOR_EINVAL;
     SweepArgs a;
     a.theta_in = theta_in;
     a.theta_out = theta_out;
@@ -502,7 +613,7 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     if (lds > 65536 &&
         hipFuncSetAttribute((const void *)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return VOLDOR_EDEVICE;
-    hipLaunchKernelGGL(k_sweep, dim3(nchain), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(k_sweep, dim3(nchain), dim3(kSweepThreads), lds, s, a);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
