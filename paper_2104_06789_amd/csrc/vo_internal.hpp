@@ -54,7 +54,8 @@ struct voldor_ctx {
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
-    double *ms_part;       // [2][kMaxGroups / 256][8] mean-shift partial sums
+    double *dense;         // [7][4 S_max] valid pose samples in group order (SoA)
+    double *pose_info;     // [4]: samples, weight sum, groups with a sample
     double *prev_pose;     // [12] staging of a host-provided previous pose
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points

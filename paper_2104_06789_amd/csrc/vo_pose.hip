@@ -8,11 +8,8 @@
 //   k_pose_ms      densest candidate, Gaussian mean-shift to the mode,
 //                  T_t = exp(p*), M_t = T_t o M_{t-1};
 // plus the scale gauge |t_1| = 1.
-#include <hip/hip_cooperative_groups.h>
-
 #include "vo_internal.hpp"
 
-namespace cg = cooperative_groups;
 
 namespace vo {
 
@@ -157,169 +154,166 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return red[NT / 64];
 }
 
-struct SeedArgs {
-    const double *samples;
-    double *seed_score;    // [n_seeds + 1][8]
-    const double *prev;    // previous relative pose T_t or null
+// Dense copy of the valid samples in (group, root) order: SoA dense[c][i],
+// c = 0..5 the se(3) coordinates, c = 6 the weight; info = (N, sum w, groups).
+struct CompactArgs {
+    const double *samples;  // [4S][8]
+    double *dense;          // [7][stride]
+    double *info;           // [4]
     const int *status;
-    int n_slots, n_seeds, have_prev;
+    int S, stride;
+};
+
+constexpr int kCompactThreads = 1024;
+
+__global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    __shared__ int wsum[kCompactThreads / 64];
+    __shared__ double red[3][kCompactThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int chunk = (a.S + kCompactThreads - 1) / kCompactThreads;
+    const int g0 = min(tid * chunk, a.S), g1 = min(g0 + chunk, a.S);
+    int cnt = 0, groups = 0;
+    double wt = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        int c = 0;
+        for (int s = 0; s < 4; ++s) {
+            const double *q = a.samples + (size_t)8 * (4 * g + s);
+            if (q[7] != 0.0) { ++c; wt += q[6]; }
+        }
+        cnt += c;
+        groups += c > 0;
+    }
+    // exclusive scan of cnt over the workgroup
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wv; ++w) base += wsum[w];
+    int off = base + incl - cnt;
+    for (int g = g0; g < g1; ++g)
+        for (int s = 0; s < 4; ++s) {
+            const double *q = a.samples + (size_t)8 * (4 * g + s);
+            if (q[7] == 0.0) continue;
+            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + off] = q[c];
+            ++off;
+        }
+    double v3[3] = {(double)cnt, wt, (double)groups};
+    for (int c = 0; c < 3; ++c) {
+        double v = v3[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) red[c][wv] = v;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double s = 0.0;
+        for (int w = 0; w < kCompactThreads / 64; ++w) s += red[tid][w];
+        a.info[tid] = s;
+    }
+}
+
+struct SeedArgs {
+    const double *dense;
+    const double *info;
+    double *seed_score;    // [n_seeds + 1][8]: p, density, valid
+    const double *prev;    // previous relative pose T_t
+    const int *status;
+    int stride, have_prev;
     double is2t, is2r;
 };
 
+// density of one start candidate (block 0: the previous pose; block b: the
+// (b-1)-th sample in group order) over all samples
 __global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
     __shared__ double red[8];
     __shared__ double seed[6];
-    __shared__ int found;
-    __shared__ int cnt[256];
     const int b = blockIdx.x, tid = threadIdx.x;
+    const int N = (int)a.info[0];
     double *o = a.seed_score + 8 * b;
-    if (tid == 0) found = 0;
-    __syncthreads();
-    if (b == 0) {
-        if (!a.have_prev) {
-            if (tid == 0) o[7] = 0.0;
-            return;
-        }
-        if (tid == 0) {
-            double p[6];
-            se3_log(a.prev, a.prev + 9, p);
-            for (int c = 0; c < 6; ++c) seed[c] = p[c];
-            found = 1;
-        }
-    } else {
-        // the (b-1)-th valid sample in slot order
-        const int want = b - 1;
-        const int chunk = (a.n_slots + 255) / 256;
-        const int lo = min(tid * chunk, a.n_slots), hi = min(lo + chunk, a.n_slots);
-        int c = 0;
-        for (int i = lo; i < hi; ++i) c += a.samples[8 * i + 7] != 0.0;
-        cnt[tid] = c;
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int i = 0; i < 256; ++i) { const int v = cnt[i]; cnt[i] = acc; acc += v; }
-        }
-        __syncthreads();
-        int rank = cnt[tid];
-        if (want >= rank && want < rank + c) {
-            for (int i = lo; i < hi; ++i) {
-                if (a.samples[8 * i + 7] != 0.0) {
-                    if (rank == want) {
-                        for (int k = 0; k < 6; ++k) seed[k] = a.samples[8 * i + k];
-                        found = 1;
-                        break;
-                    }
-                    ++rank;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (!found) {
+    if ((b == 0 && !a.have_prev) || (b > 0 && b - 1 >= N)) {
         if (tid == 0) o[7] = 0.0;
         return;
     }
+    if (tid == 0) {
+        if (b == 0) {
+            double p[6];
+            se3_log(a.prev, a.prev + 9, p);
+            for (int c = 0; c < 6; ++c) seed[c] = p[c];
+        } else {
+            for (int c = 0; c < 6; ++c) seed[c] = a.dense[(size_t)c * a.stride + (b - 1)];
+        }
+    }
+    __syncthreads();
+    double sd[6];
+    for (int c = 0; c < 6; ++c) sd[c] = seed[c];
     double s = 0.0;
-    for (int i = tid; i < a.n_slots; i += 256) {
-        const double *q = a.samples + 8 * i;
-        if (q[7] != 0.0) s += q[6] * exp(-0.5 * mahal2(seed, q, a.is2t, a.is2r));
+    for (int i = tid; i < N; i += 256) {
+        double q[6];
+        for (int c = 0; c < 6; ++c) q[c] = a.dense[(size_t)c * a.stride + i];
+        s += a.dense[(size_t)6 * a.stride + i] * exp(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
     }
     const double D = block_sum<256>(s, red);
     if (tid == 0) {
-        for (int c = 0; c < 6; ++c) o[c] = seed[c];
+        for (int c = 0; c < 6; ++c) o[c] = sd[c];
         o[6] = D;
         o[7] = 1.0;
     }
 }
 
 struct MsArgs {
-    const double *samples;  // [4S][8]
+    const double *dense;
+    const double *info;
     const double *seed_score;
     double *rel;            // relative poses [T][12]; T_t written at t-1
     double *Mcum;           // cumulative poses [T+1][12]; M_t written
     int *diag;              // [4]
-    double *part;           // [2][gridDim][8] per-workgroup partial sums
     const int *status;
-    int S, n_seeds, t, max_iters, fallback_prev_frame;
+    int stride, n_seeds, t, max_iters, fallback_prev_frame;
     double is2t, is2r, tol;
 };
 
-constexpr int kMsThreads = 256;
+constexpr int kMsThreads = 512;
+constexpr int kMsRegs = 8;   // samples held in registers per thread
 
-// Sum eight doubles over the workgroup; thread 0 writes them to out[0..7].
-__device__ __forceinline__ void block_sum8(double v[8], double (*red)[8], double *out)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_down(v[c], off, 64);
-    if (lane == 0)
-        for (int c = 0; c < 8; ++c) red[wv][c] = v[c];
-    __syncthreads();
-    if (threadIdx.x < 8) {
-        double s = 0.0;
-        for (int w = 0; w < kMsThreads / 64; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
-// Mean-shift of frame t over all samples, cooperative: one P3P group (four
-// sample slots) per thread, samples held in registers for all iterations;
-// per-workgroup partial sums are combined in a fixed order after a grid
-// barrier, so every workgroup derives the same next estimate.
+// Gaussian mean-shift from the densest start candidate, one workgroup;
+// samples beyond kMsThreads * kMsRegs are streamed from memory each iteration.
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 {
-    cg::grid_group grid = cg::this_grid();
     if (a.status && *a.status != kStatusOk) return;
     __shared__ double red[kMsThreads / 64][8];
     __shared__ double p[8];
-    __shared__ double tot[8];
     __shared__ int s_stop;
-    const int tid = threadIdx.x, G = gridDim.x;
-    const int g = blockIdx.x * kMsThreads + tid;
-    double q[4][7];
-    bool v[4];
-    double nv = 0.0, ws = 0.0, anyg = 0.0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const double *src = a.samples + (size_t)8 * (4 * g + s);
-        v[s] = g < a.S && src[7] != 0.0;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) q[s][c] = v[s] ? src[c] : 0.0;
-        if (v[s]) { nv += 1.0; ws += q[s][6]; anyg = 1.0; }
-    }
-    int round = 0;
-    {
-        double vals[8] = {nv, ws, anyg, 0, 0, 0, 0, 0};
-        block_sum8(vals, red, a.part + (size_t)8 * ((round & 1) * G + blockIdx.x));
-    }
-    __threadfence();
-    grid.sync();
-    if (tid < 8) {
-        double s = 0.0;
-        for (int b = 0; b < G; ++b) s += a.part[(size_t)8 * ((round & 1) * G + b) + tid];
-        tot[tid] = s;
-    }
-    ++round;
-    __syncthreads();
-    const double N = tot[0], WS = tot[1], NG = tot[2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int N = (int)a.info[0];
+    const double WS = a.info[1];
     double *Tt = a.rel + 12 * (a.t - 1);
-    if (N == 0.0 || !(WS > 0.0)) {
-        if (blockIdx.x == 0 && tid == 0) {
+    if (N == 0 || !(WS > 0.0)) {
+        if (tid == 0) {
             if (a.fallback_prev_frame)
                 for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
             pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
-            a.diag[0] = (int)N;
-            a.diag[1] = (int)NG;
+            a.diag[0] = N;
+            a.diag[1] = (int)a.info[2];
             a.diag[2] = 0;
             a.diag[3] = 1;
         }
         return;
     }
+    double q[kMsRegs][7];
+#pragma unroll
+    for (int m = 0; m < kMsRegs; ++m) {
+        const int i = tid + m * kMsThreads;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) q[m][c] = i < N ? a.dense[(size_t)c * a.stride + i] : 0.0;
+    }
     if (tid == 0) {
-        // densest start candidate (earliest on ties)
         int best = -1;
         double bd = 0.0;
         for (int i = 0; i <= a.n_seeds; ++i) {
@@ -327,12 +321,7 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
             if (s[7] == 0.0) continue;
             if (best < 0 || s[6] > bd) { best = i; bd = s[6]; }
         }
-        if (best < 0) {
-            for (int i = 0; i < 4 * a.S; ++i)
-                if (a.samples[8 * i + 7] != 0.0) { for (int c = 0; c < 6; ++c) p[c] = a.samples[8 * i + c]; break; }
-        } else {
-            for (int c = 0; c < 6; ++c) p[c] = a.seed_score[8 * best + c];
-        }
+        for (int c = 0; c < 6; ++c) p[c] = best >= 0 ? a.seed_score[8 * best + c] : a.dense[(size_t)c * a.stride];
         s_stop = 0;
     }
     __syncthreads();
@@ -340,30 +329,42 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
     for (; it < a.max_iters; ++it) {
         double pc[6];
         for (int c = 0; c < 6; ++c) pc[c] = p[c];
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (!v[s]) continue;
-            const double k = q[s][6] * exp(-0.5 * mahal2(pc, q[s], a.is2t, a.is2r));
-            acc[6] += k;
-            for (int c = 0; c < 6; ++c) acc[c] += k * q[s][c];
+        for (int m = 0; m < kMsRegs; ++m) {
+            if (tid + m * kMsThreads < N) {
+                const double k = q[m][6] * exp(-0.5 * mahal2(pc, q[m], a.is2t, a.is2r));
+                acc[6] += k;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] += k * q[m][c];
+            }
         }
-        block_sum8(acc, red, a.part + (size_t)8 * ((round & 1) * G + blockIdx.x));
-        __threadfence();
-        grid.sync();
+        for (int i = tid + kMsRegs * kMsThreads; i < N; i += kMsThreads) {
+            double qq[7];
+            for (int c = 0; c < 7; ++c) qq[c] = a.dense[(size_t)c * a.stride + i];
+            const double k = qq[6] * exp(-0.5 * mahal2(pc, qq, a.is2t, a.is2r));
+            acc[6] += k;
+            for (int c = 0; c < 6; ++c) acc[c] += k * qq[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+            for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_down(acc[c], off, 64);
+        if (lane == 0)
+            for (int c = 0; c < 7; ++c) red[wv][c] = acc[c];
+        __syncthreads();
         if (tid < 7) {
             double s = 0.0;
-            for (int b = 0; b < G; ++b) s += a.part[(size_t)8 * ((round & 1) * G + b) + tid];
-            tot[tid] = s;
+            for (int w = 0; w < kMsThreads / 64; ++w) s += red[w][tid];
+            red[0][tid] = s;   // row 0 is read back only after the next barrier
         }
-        ++round;
         __syncthreads();
         if (tid == 0) {
-            if (!(tot[6] > 0.0)) {
+            const double den = red[0][6];
+            if (!(den > 0.0)) {
                 s_stop = 2;
             } else {
                 double np[6];
-                for (int c = 0; c < 6; ++c) np[c] = tot[c] / tot[6];
+                for (int c = 0; c < 6; ++c) np[c] = red[0][c] / den;
                 const double step = sqrt(mahal2(np, pc, a.is2t, a.is2r));
                 for (int c = 0; c < 6; ++c) p[c] = np[c];
                 s_stop = step < a.tol ? 1 : 0;
@@ -374,15 +375,15 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         if (st == 2) break;
         if (st == 1) { ++it; break; }
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (tid == 0) {
         double pp[6], R[9], tv[3];
         for (int c = 0; c < 6; ++c) pp[c] = p[c];
         se3_exp(pp, R, tv);
         for (int k = 0; k < 9; ++k) Tt[k] = R[k];
         for (int k = 0; k < 3; ++k) Tt[9 + k] = tv[k];
         pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
-        a.diag[0] = (int)N;
-        a.diag[1] = (int)NG;
+        a.diag[0] = N;
+        a.diag[1] = (int)a.info[2];
         a.diag[2] = it;
         a.diag[3] = 0;
     }
@@ -438,26 +439,29 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.seed = pp.seed;
     hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
     int *diag = c->pose_diag + 4 * (t - 1);
+    const int stride = 4 * c->S_max;
+    CompactArgs ca{c->samples, c->dense, c->pose_info, c->status, pp.S, stride};
+    hipLaunchKernelGGL(k_pose_compact, dim3(1), dim3(kCompactThreads), 0, s, ca);
     SeedArgs sa;
-    sa.samples = c->samples;
+    sa.dense = c->dense;
+    sa.info = c->pose_info;
     sa.seed_score = c->seed_score;
     sa.prev = rel_poses + 12 * (t - 1);
     sa.status = c->status;
-    sa.n_slots = 4 * pp.S;
-    sa.n_seeds = pp.n_seeds;
+    sa.stride = stride;
     sa.have_prev = have_prev;
     sa.is2t = 1.0 / pp.s2t;
     sa.is2r = 1.0 / pp.s2r;
     hipLaunchKernelGGL(k_pose_seed, dim3(pp.n_seeds + 1), dim3(256), 0, s, sa);
     MsArgs m;
-    m.samples = c->samples;
+    m.dense = c->dense;
+    m.info = c->pose_info;
     m.seed_score = c->seed_score;
     m.rel = rel_poses;
     m.Mcum = c->Mcum;
     m.diag = diag;
-    m.part = c->ms_part;
     m.status = c->status;
-    m.S = pp.S;
+    m.stride = stride;
     m.n_seeds = pp.n_seeds;
     m.t = t;
     m.max_iters = pp.ms_max_iters;
@@ -465,10 +469,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.is2t = 1.0 / pp.s2t;
     m.is2r = 1.0 / pp.s2r;
     m.tol = pp.ms_tol;
-    void *kargs[] = {&m};
-    const int G = (pp.S + kMsThreads - 1) / kMsThreads;
-    if (hipLaunchCooperativeKernel((const void *)k_pose_ms, dim3(G), dim3(kMsThreads), kargs, 0, s) != hipSuccess)
-        return VOLDOR_EDEVICE;
+    hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
