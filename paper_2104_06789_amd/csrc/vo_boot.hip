@@ -198,6 +198,31 @@ __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
     for (int i = 0; i < 9; ++i) { out[i] = E[i]; out[9 + i] = F[i]; }
 }
 
+// Bin of a 256-bin histogram (counts h, read by threads 0..255) that holds
+// the element of rank `rank`: the unique thread with excl <= rank < incl
+// writes the bin and the rank within it.  Called by the whole workgroup.
+__device__ __forceinline__ void select_bin(uint32_t h, uint32_t rank, uint32_t *wtot, uint32_t *bin,
+                                           uint32_t *rank_in_bin)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t incl = h;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (tid < 256 && lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    if (tid < 256) {
+        for (int w = 0; w < wv; ++w) incl += wtot[w];
+        const uint32_t excl = incl - h;
+        if (rank >= excl && rank < incl) {
+            *bin = (uint32_t)tid;
+            *rank_in_bin = rank - excl;
+        }
+    }
+    __syncthreads();
+}
+
 struct ScoreArgs {
     const float2 *X1;
     const double *hyp;
@@ -211,6 +236,7 @@ __global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
     __shared__ int cnt_red[kEvalThreads / 64];
     __shared__ uint64_t s_prefix;
     __shared__ int s_rank;
+    __shared__ uint32_t s_wtot[4], s_bin, s_rib;
     const int h = blockIdx.x, tid = threadIdx.x;
     const double *hp = a.hyp + 18 * h;
     if (isnan(hp[0])) return;  // invalid hypothesis keeps +inf
@@ -265,16 +291,14 @@ __global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
         for (int m = 0; m < kEvalPerThread; ++m)
             if ((key[m] & mask) == pre) atomicAdd(&hist[(key[m] >> shift) & 255], 1u);
         __syncthreads();
+        if (tid == 0) s_bin = 255;
+        const uint32_t hb = tid < 256 ? hist[tid] : 0u;
+        const uint32_t rank = (uint32_t)s_rank;
+        __syncthreads();
+        select_bin(hb, rank, s_wtot, &s_bin, &s_rib);
         if (tid == 0) {
-            int rank = s_rank;
-            uint32_t cum = 0;
-            int sel = 255;
-            for (int b = 0; b < 256; ++b) {
-                if ((uint32_t)rank < cum + hist[b]) { sel = b; break; }
-                cum += hist[b];
-            }
-            s_rank = rank - (int)cum;
-            s_prefix = pre | ((uint64_t)sel << shift);
+            s_rank = (int)s_rib;
+            s_prefix = pre | ((uint64_t)s_bin << shift);
         }
         mask |= 255ull << shift;
         __syncthreads();
@@ -480,23 +504,25 @@ __global__ void __launch_bounds__(256) k_hist(const uint32_t *keys, int64_t n, c
     }
 }
 
-__global__ void k_hist_pick(uint32_t *sel, uint32_t *hist, int pass, const int *status)
+__global__ void __launch_bounds__(256) k_hist_pick(uint32_t *sel, uint32_t *hist, int pass, const int *status)
 {
     if (*status != kStatusOk) return;
+    __shared__ uint32_t s_wtot[4], s_bin, s_rib;
     const int shift = 8 * pass;
-    if (threadIdx.x < 3) {
-        const int q = threadIdx.x;
-        uint32_t rank = sel[3 + q], cum = 0;
-        uint32_t b = 255;
-        for (uint32_t i = 0; i < 256; ++i) {
-            const uint32_t h = hist[256 * q + i];
-            if (rank < cum + h) { b = i; break; }
-            cum += h;
+    for (int q = 0; q < 3; ++q) {
+        if (threadIdx.x == 0) {
+            s_bin = 255;
+            s_rib = 0;
         }
-        sel[3 + q] = rank - cum;
-        sel[q] |= b << shift;
+        const uint32_t rank = sel[3 + q];
+        __syncthreads();
+        select_bin(hist[256 * q + threadIdx.x], rank, s_wtot, &s_bin, &s_rib);
+        if (threadIdx.x == 0) {
+            sel[3 + q] = s_rib;
+            sel[q] |= s_bin << shift;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int i = threadIdx.x; i < 768; i += blockDim.x) hist[i] = 0;
 }
 

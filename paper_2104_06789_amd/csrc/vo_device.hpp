@@ -141,6 +141,30 @@ __device__ __forceinline__ Emis emis_from_d(float d)
 // ---------------------------------------------------------------------------
 // FP64 helpers
 // ---------------------------------------------------------------------------
+
+// e^x for x <= 0 (Gaussian kernel weights).  Range reduction x = n ln2 + r
+// with ln2 split into a 31-bit head (n * head exact for |n| <= 1022) and a
+// tail, |r| <= ln2/2; e^r by its Taylor series to degree 11 (truncation
+// error below 7e-15 relative); 2^n assembled from the exponent bits.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    if (!(x > -708.0)) return 0.0;
+    const double n = rint(x * 1.4426950408889634);
+    const double r = fma(-n, 1.9082149292705877e-10, fma(-n, 0.6931471803691238, x));
+    double p = 1.0 / 39916800.0;
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return p * __longlong_as_double((long long)((int)n + 1023) << 52);
+}
 struct M3 {
     double a[9];
 };

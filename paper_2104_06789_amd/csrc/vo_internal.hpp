@@ -56,6 +56,7 @@ struct voldor_ctx {
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
     double *dense;         // [7][4 S_max] valid pose samples in group order (SoA)
     double *pose_info;     // [4]: samples, weight sum, groups with a sample
+    int *gcnt;             // [S_max] valid samples per group
     double *prev_pose;     // [12] staging of a host-provided previous pose
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points

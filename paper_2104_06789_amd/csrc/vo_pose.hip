@@ -19,6 +19,7 @@ struct GroupArgs {
     const float2 *flows;
     const double *Mprev;   // M_{t-1}
     double *samples;       // [4S][8]
+    int *gcnt;             // [S] valid samples of each group
     const int *status;
     WinDims d;
     int S, t, it;
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
     if (g >= a.S) return;
     double *out = a.samples + (size_t)8 * 4 * g;
     for (int i = 0; i < 32; ++i) out[i] = 0.0;
+    a.gcnt[g] = 0;
     const int H = a.d.H, W = a.d.W;
     const int64_t HW = (int64_t)H * W;
     int64_t j[3];
@@ -116,6 +118,7 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
             const int tk = keep[b1]; keep[b1] = keep[b1 - 1]; keep[b1 - 1] = tk;
         }
     }
+    int nv = 0;
     for (int s = 0; s < nk; ++s) {
         const int i = keep[s];
         double p[6];
@@ -127,7 +130,9 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
         for (int c = 0; c < 6; ++c) o[c] = p[c];
         o[6] = w;
         o[7] = 1.0;
+        ++nv;
     }
+    a.gcnt[g] = nv;
 }
 
 __device__ __forceinline__ double mahal2(const double *a, const double *b, double is2t, double is2r)
@@ -158,6 +163,7 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 // c = 0..5 the se(3) coordinates, c = 6 the weight; info = (N, sum w, groups).
 struct CompactArgs {
     const double *samples;  // [4S][8]
+    const int *gcnt;        // [S]
     double *dense;          // [7][stride]
     double *info;           // [4]
     const int *status;
@@ -165,6 +171,7 @@ struct CompactArgs {
 };
 
 constexpr int kCompactThreads = 1024;
+constexpr int kCompactGroups = kMaxGroups / kCompactThreads;  // groups per thread (max)
 
 __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
 {
@@ -174,18 +181,15 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int chunk = (a.S + kCompactThreads - 1) / kCompactThreads;
     const int g0 = min(tid * chunk, a.S), g1 = min(g0 + chunk, a.S);
+    int cn[kCompactGroups];
     int cnt = 0, groups = 0;
-    double wt = 0.0;
-    for (int g = g0; g < g1; ++g) {
-        int c = 0;
-        for (int s = 0; s < 4; ++s) {
-            const double *q = a.samples + (size_t)8 * (4 * g + s);
-            if (q[7] != 0.0) { ++c; wt += q[6]; }
-        }
-        cnt += c;
-        groups += c > 0;
+#pragma unroll
+    for (int u = 0; u < kCompactGroups; ++u) {
+        cn[u] = (g0 + u < g1) ? a.gcnt[g0 + u] : 0;
+        cnt += cn[u];
+        groups += cn[u] > 0;
     }
-    // exclusive scan of cnt over the workgroup
+    // exclusive scan of the counts over the workgroup
     int incl = cnt;
     for (int off = 1; off < 64; off <<= 1) {
         const int v = __shfl_up(incl, off, 64);
@@ -196,13 +200,26 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     int base = 0;
     for (int w = 0; w < wv; ++w) base += wsum[w];
     int off = base + incl - cnt;
-    for (int g = g0; g < g1; ++g)
+    double wt = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCompactGroups; ++u) {
+        if (g0 + u >= g1) break;
+        const double *q = a.samples + (size_t)32 * (g0 + u);
+        // valid samples occupy the first slots of a group except after a
+        // non-finite logarithm; copy every valid slot in slot order
+        double v[4][8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v[s][c] = q[8 * s + c];
+#pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const double *q = a.samples + (size_t)8 * (4 * g + s);
-            if (q[7] == 0.0) continue;
-            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + off] = q[c];
+            if (v[s][7] == 0.0) continue;
+            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + off] = v[s][c];
+            wt += v[s][6];
             ++off;
         }
+    }
     double v3[3] = {(double)cnt, wt, (double)groups};
     for (int c = 0; c < 3; ++c) {
         double v = v3[c];
@@ -211,9 +228,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     }
     __syncthreads();
     if (tid < 3) {
-        double s = 0.0;
-        for (int w = 0; w < kCompactThreads / 64; ++w) s += red[tid][w];
-        a.info[tid] = s;
+        double sum = 0.0;
+        for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[tid][w];
+        a.info[tid] = sum;
     }
 }
 
@@ -257,7 +274,7 @@ __global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
     for (int i = tid; i < N; i += 256) {
         double q[6];
         for (int c = 0; c < 6; ++c) q[c] = a.dense[(size_t)c * a.stride + i];
-        s += a.dense[(size_t)6 * a.stride + i] * exp(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
+        s += a.dense[(size_t)6 * a.stride + i] * exp_nonpos(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
     }
     const double D = block_sum<256>(s, red);
     if (tid == 0) {
@@ -333,7 +350,7 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 #pragma unroll
         for (int m = 0; m < kMsRegs; ++m) {
             if (tid + m * kMsThreads < N) {
-                const double k = q[m][6] * exp(-0.5 * mahal2(pc, q[m], a.is2t, a.is2r));
+                const double k = q[m][6] * exp_nonpos(-0.5 * mahal2(pc, q[m], a.is2t, a.is2r));
                 acc[6] += k;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) acc[c] += k * q[m][c];
@@ -342,7 +359,7 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         for (int i = tid + kMsRegs * kMsThreads; i < N; i += kMsThreads) {
             double qq[7];
             for (int c = 0; c < 7; ++c) qq[c] = a.dense[(size_t)c * a.stride + i];
-            const double k = qq[6] * exp(-0.5 * mahal2(pc, qq, a.is2t, a.is2r));
+            const double k = qq[6] * exp_nonpos(-0.5 * mahal2(pc, qq, a.is2t, a.is2r));
             acc[6] += k;
             for (int c = 0; c < 6; ++c) acc[c] += k * qq[c];
         }
@@ -431,6 +448,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.flows = flows;
     g.Mprev = c->Mcum + 12 * (t - 1);
     g.samples = c->samples;
+    g.gcnt = c->gcnt;
     g.status = c->status;
     g.d = d;
     g.S = pp.S;
@@ -440,7 +458,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
     int *diag = c->pose_diag + 4 * (t - 1);
     const int stride = 4 * c->S_max;
-    CompactArgs ca{c->samples, c->dense, c->pose_info, c->status, pp.S, stride};
+    CompactArgs ca{c->samples, c->gcnt, c->dense, c->pose_info, c->status, pp.S, stride};
     hipLaunchKernelGGL(k_pose_compact, dim3(1), dim3(kCompactThreads), 0, s, ca);
     SeedArgs sa;
     sa.dense = c->dense;
