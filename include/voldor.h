@@ -69,7 +69,7 @@ typedef struct {
 } voldor_params;
 
 /* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
- * 100 mean-shift iterations, tol 1e-8, 512 hypotheses, 16384 eval pixels,
+ * 100 mean-shift iterations, tol 1e-6, 512 hypotheses, 16384 eval pixels,
  * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0). */
 void voldor_params_default(voldor_params *p);
 

@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 DEFAULTS = dict(
     n_iters=3, sweeps_per_iter=4, n_pose_groups=256, n_seeds=64, ms_max_iters=100,
-    lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-8,
+    lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-6,
     a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
     sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
     depth_lo=0.0, depth_hi=0.0, seed=0,

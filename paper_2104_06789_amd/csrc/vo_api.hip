@@ -155,7 +155,7 @@ void voldor_params_default(voldor_params *p)
     p->ms_max_iters = 100;
     p->lmeds_hypotheses = 512;
     p->lmeds_eval_pixels = 16384;
-    p->ms_tol = 1e-8;
+    p->ms_tol = 1e-6;
     p->a1 = 0.01;
     p->a2 = 0.09;
     p->b1 = -0.0022;
@@ -389,9 +389,7 @@ int voldor_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     int rc = launch_pose_step(c, theta, rig, (const float2 *)flows, d, pose_params(p), t, it,
                               prevT ? 1 : 0, c->rel_tmp, s);
     if (rc) return rc;
-    if (samples &&
-        hipMemcpyAsync(samples, c->samples, sizeof(double) * 32 * p->n_pose_groups, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return VOLDOR_EDEVICE;
+    if (samples && launch_samples_aos(c, p->n_pose_groups, samples, s) != 0) return VOLDOR_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
     if (hipMemcpy(T_out, c->rel_tmp + 12 * (t - 1), sizeof(double) * 12, hipMemcpyDeviceToHost) != hipSuccess)
         return VOLDOR_EDEVICE;

@@ -44,7 +44,7 @@ struct voldor_ctx {
     vo::FrameF *frames;    // [T_max+1] FP32 copy of Mcum for the sweeps
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
     int *status;           // [8]: status word, pose diagnostics scratch
-    double *samples;       // [4 S_max][8] pose samples (p, weight, valid)
+    double *samples;       // SoA [8][4 S] pose sample slots (p, weight, valid)
     double *seed_score;    // [kMaxSeeds + 1][8] (p, density, valid)
     int *pose_diag;        // [T_max][4]
     double *hyp;           // [kMaxHyp][18]: essential E (9), fundamental F (9)
@@ -87,6 +87,7 @@ size_t sweep_lds_bytes(int T, int L);
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
                      const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
                      double *rel_poses, hipStream_t s);
+int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s);
 int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s);
 int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
 

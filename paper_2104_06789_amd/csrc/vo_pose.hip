@@ -18,11 +18,11 @@ struct GroupArgs {
     const float *rig;
     const float2 *flows;
     const double *Mprev;   // M_{t-1}
-    double *samples;       // [4S][8]
+    double *samples;       // SoA [8][ns]: p (6), weight, valid; slot 4g+r of group g
     int *gcnt;             // [S] valid samples of each group
     const int *status;
     WinDims d;
-    int S, t, it;
+    int S, t, it, ns;
     uint64_t seed;
 };
 
@@ -48,8 +48,9 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
     if (a.status && *a.status != kStatusOk) return;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.S) return;
-    double *out = a.samples + (size_t)8 * 4 * g;
-    for (int i = 0; i < 32; ++i) out[i] = 0.0;
+    double *out = a.samples + (size_t)4 * g;
+    for (int c = 0; c < 8; ++c)
+        for (int r = 0; r < 4; ++r) out[(size_t)c * a.ns + r] = 0.0;
     a.gcnt[g] = 0;
     const int H = a.d.H, W = a.d.W;
     const int64_t HW = (int64_t)H * W;
@@ -126,10 +127,10 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
         bool fin = true;
         for (int c = 0; c < 6; ++c) fin = fin && isfinite(p[c]);
         if (!fin) continue;
-        double *o = out + 8 * s;
-        for (int c = 0; c < 6; ++c) o[c] = p[c];
-        o[6] = w;
-        o[7] = 1.0;
+        double *o = out + s;
+        for (int c = 0; c < 6; ++c) o[(size_t)c * a.ns] = p[c];
+        o[(size_t)6 * a.ns] = w;
+        o[(size_t)7 * a.ns] = 1.0;
         ++nv;
     }
     a.gcnt[g] = nv;
@@ -162,12 +163,12 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 // Dense copy of the valid samples in (group, root) order: SoA dense[c][i],
 // c = 0..5 the se(3) coordinates, c = 6 the weight; info = (N, sum w, groups).
 struct CompactArgs {
-    const double *samples;  // [4S][8]
+    const double *samples;  // SoA [8][ns]
     const int *gcnt;        // [S]
     double *dense;          // [7][stride]
     double *info;           // [4]
     const int *status;
-    int S, stride;
+    int S, ns, stride;
 };
 
 constexpr int kCompactThreads = 1024;
@@ -177,6 +178,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
     __shared__ int wsum[kCompactThreads / 64];
+    __shared__ int goff[kMaxGroups];
     __shared__ double red[3][kCompactThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int chunk = (a.S + kCompactThreads - 1) / kCompactThreads;
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
         cnt += cn[u];
         groups += cn[u] > 0;
     }
-    // exclusive scan of the counts over the workgroup
+    // exclusive scan of the counts: first dense index of every group
     int incl = cnt;
     for (int off = 1; off < 64; off <<= 1) {
         const int v = __shfl_up(incl, off, 64);
@@ -200,25 +202,25 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     int base = 0;
     for (int w = 0; w < wv; ++w) base += wsum[w];
     int off = base + incl - cnt;
-    double wt = 0.0;
 #pragma unroll
-    for (int u = 0; u < kCompactGroups; ++u) {
-        if (g0 + u >= g1) break;
-        const double *q = a.samples + (size_t)32 * (g0 + u);
-        // valid samples occupy the first slots of a group except after a
-        // non-finite logarithm; copy every valid slot in slot order
-        double v[4][8];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) v[s][c] = q[8 * s + c];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (v[s][7] == 0.0) continue;
-            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + off] = v[s][c];
-            wt += v[s][6];
-            ++off;
+    for (int u = 0; u < kCompactGroups; ++u)
+        if (g0 + u < g1) {
+            goff[g0 + u] = off;
+            off += cn[u];
         }
+    __syncthreads();
+    // coalesced copy, slot by slot; a valid slot's rank inside its group is
+    // the number of valid slots before it
+    double wt = 0.0;
+    const int nslot = 4 * a.S;
+    for (int sl = tid; sl < nslot; sl += kCompactThreads) {
+        if (a.samples[(size_t)7 * a.ns + sl] == 0.0) continue;
+        const int g = sl >> 2;
+        int r = 0;
+        for (int q = 4 * g; q < sl; ++q) r += a.samples[(size_t)7 * a.ns + q] != 0.0;
+        const int dst = goff[g] + r;
+        for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + dst] = a.samples[(size_t)c * a.ns + sl];
+        wt += a.samples[(size_t)6 * a.ns + sl];
     }
     double v3[3] = {(double)cnt, wt, (double)groups};
     for (int c = 0; c < 3; ++c) {
@@ -232,6 +234,14 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
         for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[tid][w];
         a.info[tid] = sum;
     }
+}
+
+// AoS copy [4S][8] of the sample slots (test hook of the pose step)
+__global__ void k_samples_aos(const double *soa, int ns, double *aos)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    for (int c = 0; c < 8; ++c) aos[(size_t)8 * i + c] = soa[(size_t)c * ns + i];
 }
 
 struct SeedArgs {
@@ -330,16 +340,31 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 #pragma unroll
         for (int c = 0; c < 7; ++c) q[m][c] = i < N ? a.dense[(size_t)c * a.stride + i] : 0.0;
     }
-    if (tid == 0) {
-        int best = -1;
-        double bd = 0.0;
-        for (int i = 0; i <= a.n_seeds; ++i) {
-            const double *s = a.seed_score + 8 * i;
-            if (s[7] == 0.0) continue;
-            if (best < 0 || s[6] > bd) { best = i; bd = s[6]; }
+    // densest start candidate, earliest on ties (a workgroup arg-max)
+    {
+        double sc = -1.0;
+        int id = kMsThreads;
+        if (tid <= a.n_seeds && a.seed_score[8 * tid + 7] != 0.0) {
+            sc = a.seed_score[8 * tid + 6];
+            id = tid;
         }
-        for (int c = 0; c < 6; ++c) p[c] = best >= 0 ? a.seed_score[8 * best + c] : a.dense[(size_t)c * a.stride];
-        s_stop = 0;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double so = __shfl_down(sc, o, 64);
+            const int io = __shfl_down(id, o, 64);
+            if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
+        }
+        if (lane == 0) { red[wv][0] = sc; red[wv][1] = (double)id; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kMsThreads / 64; ++w) {
+                const double so = red[w][0];
+                const int io = (int)red[w][1];
+                if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
+            }
+            for (int c = 0; c < 6; ++c)
+                p[c] = id < kMsThreads ? a.seed_score[8 * id + c] : a.dense[(size_t)c * a.stride];
+            s_stop = 0;
+        }
     }
     __syncthreads();
     int it = 0;
@@ -452,13 +477,14 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.status = c->status;
     g.d = d;
     g.S = pp.S;
+    g.ns = 4 * pp.S;
     g.t = t;
     g.it = it;
     g.seed = pp.seed;
     hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
     int *diag = c->pose_diag + 4 * (t - 1);
     const int stride = 4 * c->S_max;
-    CompactArgs ca{c->samples, c->gcnt, c->dense, c->pose_info, c->status, pp.S, stride};
+    CompactArgs ca{c->samples, c->gcnt, c->dense, c->pose_info, c->status, pp.S, 4 * pp.S, stride};
     hipLaunchKernelGGL(k_pose_compact, dim3(1), dim3(kCompactThreads), 0, s, ca);
     SeedArgs sa;
     sa.dense = c->dense;
@@ -488,6 +514,13 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.is2r = 1.0 / pp.s2r;
     m.tol = pp.ms_tol;
     hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s)
+{
+    const int ns = 4 * S;
+    hipLaunchKernelGGL(k_samples_aos, dim3((ns + 255) / 256), dim3(256), 0, s, c->samples, ns, out);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 

@@ -121,6 +121,50 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     return s;
 }
 
+// log(mu/rho) for a batch of B independent (pixel, frame, depth) items; the
+// flow gathers of the whole batch are issued before any of them is used.
+// ok[b] false: missing observation (or inactive item).
+template <int B>
+__device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *__restrict__ flows, int H,
+                                               int W, const EmisParams &e, const int *x, const int *y,
+                                               const float *th, const int *t, const bool *act, float *d,
+                                               bool *ok)
+{
+    const size_t HW = (size_t)H * W;
+    float dx0[B], dy0[B], dx1[B], dy1[B], ax[B], ay[B];
+    float2 ta[B], tb[B], tc[B], td[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float xh = ((float)x[b] - e.cx) / e.fx, yh = ((float)y[b] - e.cy) / e.fy;
+        bool v = act[b] && th[b] > 0.0f;
+        const int tt = act[b] ? t[b] : 1;
+        dx0[b] = 0.0f;
+        dy0[b] = 0.0f;
+        if (tt > 1) v = v && displacement(fr[tt - 1], xh, yh, th[b], e.fx, e.fy, dx0[b], dy0[b]);
+        v = v && displacement(fr[tt], xh, yh, th[b], e.fx, e.fy, dx1[b], dy1[b]);
+        const float px = (float)x[b] + dx0[b], py = (float)y[b] + dy0[b];
+        v = v && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1);
+        ok[b] = v;
+        const float spx = v ? px : 0.0f, spy = v ? py : 0.0f;
+        const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
+        ax[b] = spx - (float)x0;
+        ay[b] = spy - (float)y0;
+        const float2 *r0 = flows + (size_t)(v ? tt - 1 : 0) * HW + (size_t)y0 * W + x0;
+        ta[b] = r0[0];
+        tb[b] = r0[1];
+        tc[b] = r0[W];
+        td[b] = r0[W + 1];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float2 A = ta[b], Bv = tb[b], Cv = tc[b], Dv = td[b];
+        ok[b] = ok[b] && isfinite(A.x + A.y + Bv.x + Bv.y + Cv.x + Cv.y + Dv.x + Dv.y);
+        const float vu = (1.0f - ay[b]) * fmaf(ax[b], Bv.x - A.x, A.x) + ay[b] * fmaf(ax[b], Dv.x - Cv.x, Cv.x);
+        const float vv = (1.0f - ay[b]) * fmaf(ax[b], Bv.y - A.y, A.y) + ay[b] * fmaf(ax[b], Dv.y - Cv.y, Cv.y);
+        d[b] = ok[b] ? log_mu_over_rho((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+    }
+}
+
 struct SweepArgs {
     const float *theta_in;
     float *theta_out;
@@ -225,28 +269,45 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
     }
     __syncthreads();
 
-    // ---- A: ell and r of the previous depth, one item per (position, frame)
-    for (int i = tid; i < T * L; i += kSweepThreads) {
-        const int t = i / L + 1, k = i - (t - 1) * L;
-        const int j = chain_pixel(dir, H, W, chain, k);
-        const int x = j % W, y = j / W;
-        const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
-        float d;
-        float ell = kLogHalf, r = 0.5f;
-        if (item_log_odds(fr, a.flows, H, W, a.e, x, y, xh, yh, th[k], t, d)) {
-            const Emis m = emis_from_d(d);
-            ell = m.ell;
-            r = m.r;
+    // ---- A: ell and r of the previous depth, one item per (position, frame),
+    // four items per thread in flight
+    for (int i0 = tid; i0 < T * L; i0 += 4 * kSweepThreads) {
+        int xs[4], ys[4], ts[4];
+        float ths[4], dd[4];
+        bool act[4], ok[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + b * kSweepThreads;
+            act[b] = i < T * L;
+            const int t = act[b] ? i / L + 1 : 1, k = act[b] ? i - (t - 1) * L : 0;
+            const int j = chain_pixel(dir, H, W, chain, k);
+            xs[b] = j % W;
+            ys[b] = j / W;
+            ts[b] = t;
+            ths[b] = th[k];
         }
-        lq[i] = ell;
-        fq[i] = r;
+        batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + b * kSweepThreads;
+            if (!act[b]) continue;
+            float ell = kLogHalf, r = 0.5f;
+            if (ok[b]) {
+                const Emis m = emis_from_d(dd[b]);
+                ell = m.ell;
+                r = m.r;
+            }
+            lq[i] = ell;
+            fq[i] = r;
+        }
     }
     __syncthreads();
 
     // ---- B: forward-backward, one wave per frame, one segment per lane
     {
         const int lane = tid & 63, wv = tid >> 6;
-        const int seglen = (L + 63) / 64;
+        // odd segment length: lanes then read LDS with an odd stride (no bank conflicts)
+        const int seglen = ((L + 63) / 64) | 1;
         const float g = a.gamma, gc = 1.0f - a.gamma;
         const int s0 = min(lane * seglen, L), s1 = min(s0 + seglen, L);
         for (int t = wv; t < T; t += kSweepWaves) {
@@ -331,14 +392,27 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
     }
     __syncthreads();
     // ell of the random sample, one item per (position, frame)
-    for (int i = tid; i < T * L; i += kSweepThreads) {
-        const int t = i / L + 1, k = i - (t - 1) * L;
-        const int j = chain_pixel(dir, H, W, chain, k);
-        const int x = j % W, y = j / W;
-        const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
-        float d, ell = kLogHalf;
-        if (item_log_odds(fr, a.flows, H, W, a.e, x, y, xh, yh, sm[k], t, d)) ell = emis_from_d(d).ell;
-        lq[i] = ell;
+    for (int i0 = tid; i0 < T * L; i0 += 4 * kSweepThreads) {
+        int xs[4], ys[4], ts[4];
+        float ths[4], dd[4];
+        bool act[4], ok[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + b * kSweepThreads;
+            act[b] = i < T * L;
+            const int t = act[b] ? i / L + 1 : 1, k = act[b] ? i - (t - 1) * L : 0;
+            const int j = chain_pixel(dir, H, W, chain, k);
+            xs[b] = j % W;
+            ys[b] = j / W;
+            ts[b] = t;
+            ths[b] = sm[k];
+        }
+        batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + b * kSweepThreads;
+            if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+        }
     }
     __syncthreads();
     for (int k = tid; k < L; k += kSweepThreads) {
