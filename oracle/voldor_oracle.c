@@ -961,6 +961,7 @@ int or_pose_step(const double *theta, const double *Wmap, const float *flows, in
                 }
                 if (less) { keep[a] = ib; keep[b] = ia; }
             }
+        int slot = 0; /* valid samples fill the group's slots without gaps */
         for (int a = 0; a < nk; ++a) {
             int i = keep[a];
             double pv[6];
@@ -971,11 +972,12 @@ int or_pose_step(const double *theta, const double *Wmap, const float *flows, in
             memcpy(smp + 6 * n, pv, sizeof pv);
             wts[n] = wgt;
             if (samples_out) {
-                double *so = samples_out + 8 * (4 * g + a);
+                double *so = samples_out + 8 * (4 * g + slot);
                 memcpy(so, pv, sizeof pv);
                 so[6] = wgt;
                 so[7] = 1;
             }
+            ++slot;
             ++n;
         }
     }

@@ -80,6 +80,9 @@ EmisParams emis(const double *K, const voldor_params *p)
     e.beta_min = (float)p->beta_min;
     e.x_floor = (float)p->x_floor;
     e.pad = 0.0f;
+    e.ifx = (float)(1.0 / K[0]);
+    e.ify = (float)(1.0 / K[1]);
+    e.pad2 = e.pad3 = 0.0f;
     return e;
 }
 

@@ -335,17 +335,29 @@ __device__ __forceinline__ double tri_depth(const double *R, const double *t, do
 __global__ void __launch_bounds__(1024) k_boot_pick(PickArgs a)
 {
     __shared__ int s_best;
+    __shared__ double s_rs[16];
+    __shared__ int s_rh[16];
     __shared__ double Rc[2][9], tc[3];
     __shared__ int red[4][16];
     const int tid = threadIdx.x;
+    // least median of squares: lowest finite score, lowest index on ties
+    double bs = __longlong_as_double(0x7ff0000000000000ll);
+    int best = 0x7fffffff;
+    for (int h = tid; h < a.M; h += 1024) {
+        const double s = a.score[h];
+        if (isfinite(s) && (s < bs || (s == bs && h < best))) { bs = s; best = h; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double so = __shfl_down(bs, o, 64);
+        const int ho = __shfl_down(best, o, 64);
+        if (so < bs || (so == bs && ho < best)) { bs = so; best = ho; }
+    }
+    if ((tid & 63) == 0) { s_rs[tid >> 6] = bs; s_rh[tid >> 6] = best; }
+    __syncthreads();
     if (tid == 0) {
-        int best = -1;
-        double bs = 0.0;
-        for (int h = 0; h < a.M; ++h) {
-            const double s = a.score[h];
-            if (!isfinite(s)) continue;
-            if (best < 0 || s < bs) { best = h; bs = s; }
-        }
+        for (int w = 1; w < 16; ++w)
+            if (s_rs[w] < bs || (s_rs[w] == bs && s_rh[w] < best)) { bs = s_rs[w]; best = s_rh[w]; }
+        if (!isfinite(bs)) best = -1;
         s_best = best;
         if (best < 0) {
             *a.status = kStatusDegenerate;

@@ -56,7 +56,11 @@ struct EmisParams {
     float fx, fy, cx, cy;
     float log_a1, a2, b1, b2;
     float lam2, beta_min, x_floor, pad;
+    float ifx, ify, pad2, pad3;   // 1/fx, 1/fy
 };
+
+// hardware reciprocal (v_rcp_f32, about 1 ulp) instead of an IEEE division
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Displacement pi_t(theta) - (x, y) of the frame-0 pixel with normalised
 // coordinates (xh, yh) at depth th.  False if the point is not in front.
@@ -70,7 +74,7 @@ __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh
     const float bx = fmaf(-xh, f.t[2], f.t[0]), by = fmaf(-yh, f.t[2], f.t[1]);
     const float pz = fmaf(th, az, f.t[2]);
     if (!(pz > 0.0f)) return false;
-    const float inv = 1.0f / pz;
+    const float inv = frcp(pz);
     dx = fx * fmaf(th, ax, bx) * inv;
     dy = fy * fmaf(th, ay, by) * inv;
     return true;
@@ -117,9 +121,10 @@ struct Emis {
 __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, float vy,
                                                   const EmisParams &e)
 {
-    const float x2 = fmaxf(fmaf(rx, rx, ry * ry), e.x_floor);
+    // squared residual clamped to [x_floor, 1e30] so every exponent below stays finite
+    const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
     const float vn2 = fmaf(vx, vx, vy * vy);
-    const float vn = sqrtf(vn2);
+    const float vn = __builtin_amdgcn_sqrtf(vn2);
     const float la = fmaf(e.a2, vn, e.log_a1);
     const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
     const float lx = __logf(x2);
@@ -131,7 +136,7 @@ __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, f
 __device__ __forceinline__ Emis emis_from_d(float d)
 {
     const float e = __expf(-fabsf(d));
-    const float inv = 1.0f / (1.0f + e);
+    const float inv = frcp(1.0f + e);
     Emis o;
     o.ell = -(fmaxf(d, 0.0f) + log1p_unit(e));
     o.r = d < 0.0f ? inv : e * inv;

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
         bool fin = true;
         for (int c = 0; c < 6; ++c) fin = fin && isfinite(p[c]);
         if (!fin) continue;
-        double *o = out + s;
+        double *o = out + nv;   // valid samples fill the group's slots without gaps
         for (int c = 0; c < 6; ++c) o[(size_t)c * a.ns] = p[c];
         o[(size_t)6 * a.ns] = w;
         o[(size_t)7 * a.ns] = 1.0;
@@ -179,6 +179,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     if (a.status && *a.status != kStatusOk) return;
     __shared__ int wsum[kCompactThreads / 64];
     __shared__ int goff[kMaxGroups];
+    __shared__ unsigned char gcl[kMaxGroups];
     __shared__ double red[3][kCompactThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int chunk = (a.S + kCompactThreads - 1) / kCompactThreads;
@@ -206,21 +207,32 @@ __global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
     for (int u = 0; u < kCompactGroups; ++u)
         if (g0 + u < g1) {
             goff[g0 + u] = off;
+            gcl[g0 + u] = (unsigned char)cn[u];
             off += cn[u];
         }
     __syncthreads();
-    // coalesced copy, slot by slot; a valid slot's rank inside its group is
-    // the number of valid slots before it
+    // coalesced copy, slot by slot: the valid samples of group g fill its
+    // slots 4g .. 4g + gcnt[g] - 1
     double wt = 0.0;
     const int nslot = 4 * a.S;
-    for (int sl = tid; sl < nslot; sl += kCompactThreads) {
-        if (a.samples[(size_t)7 * a.ns + sl] == 0.0) continue;
-        const int g = sl >> 2;
-        int r = 0;
-        for (int q = 4 * g; q < sl; ++q) r += a.samples[(size_t)7 * a.ns + q] != 0.0;
-        const int dst = goff[g] + r;
-        for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + dst] = a.samples[(size_t)c * a.ns + sl];
-        wt += a.samples[(size_t)6 * a.ns + sl];
+    for (int s0 = tid; s0 < nslot; s0 += 4 * kCompactThreads) {
+        double v[4][7];
+        int dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = s0 + u * kCompactThreads;
+            const int g = sl >> 2, r = sl & 3;
+            dst[u] = (sl < nslot && r < gcl[g]) ? goff[g] + r : -1;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) v[u][c] = dst[u] >= 0 ? a.samples[(size_t)c * a.ns + sl] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (dst[u] < 0) continue;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + dst[u]] = v[u][c];
+            wt += v[u][6];
+        }
     }
     double v3[3] = {(double)cnt, wt, (double)groups};
     for (int c = 0; c < 3; ++c) {

@@ -135,7 +135,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
     float2 ta[B], tb[B], tc[B], td[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const float xh = ((float)x[b] - e.cx) / e.fx, yh = ((float)y[b] - e.cy) / e.fy;
+        const float xh = ((float)x[b] - e.cx) * e.ifx, yh = ((float)y[b] - e.cy) * e.ify;
         bool v = act[b] && th[b] > 0.0f;
         const int tt = act[b] ? t[b] : 1;
         dx0[b] = 0.0f;
@@ -191,7 +191,7 @@ __device__ __forceinline__ Mat2 mul_norm(const Mat2 &x, const Mat2 &y)
     r.b = x.a * y.b + x.b * y.d;
     r.c = x.c * y.a + x.d * y.c;
     r.d = x.c * y.b + x.d * y.d;
-    const float inv = 1.0f / (r.a + r.b + r.c + r.d);
+    const float inv = frcp(r.a + r.b + r.c + r.d);
     r.a *= inv;
     r.b *= inv;
     r.c *= inv;
@@ -343,20 +343,22 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
             float f1 = 0.5f, f0 = 0.5f;   // m_f before the segment
             if (lane > 0) {
                 const float n1 = 0.5f * (Pp.a + Pp.b), n0 = 0.5f * (Pp.c + Pp.d);
-                f1 = n1 / (n1 + n0);
-                f0 = n0 / (n1 + n0);
+                const float inv = frcp(n1 + n0);
+                f1 = n1 * inv;
+                f0 = n0 * inv;
             }
             float b1 = 0.5f, b0 = 0.5f;   // m_b at the segment's last position
             if (lane < 63) {
                 const float n1 = 0.5f * (Sn.a + Sn.b), n0 = 0.5f * (Sn.c + Sn.d);
-                b1 = n1 / (n1 + n0);
-                b0 = n0 / (n1 + n0);
+                const float inv = frcp(n1 + n0);
+                b1 = n1 * inv;
+                b0 = n0 * inv;
             }
             for (int k = s0; k < s1; ++k) {
                 const float r1 = rq[k], r0 = 1.0f - r1;
                 const float p1 = g * f1 + gc * f0, p0 = gc * f1 + g * f0;
                 const float n1 = r1 * p1, n0 = r0 * p0;
-                const float inv = 1.0f / (n1 + n0);
+                const float inv = frcp(n1 + n0);
                 f1 = n1 * inv;
                 f0 = n0 * inv;
                 rq[k] = f1;
@@ -364,12 +366,12 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
             for (int k = s1 - 1; k >= s0; --k) {
                 const float ff1 = rq[k], ff0 = 1.0f - ff1;
                 const float n1 = ff1 * b1, n0 = ff0 * b0;
-                rq[k] = n1 / (n1 + n0);
+                rq[k] = n1 * frcp(n1 + n0);
                 if (k > s0) {
                     const float r1 = __expf(ll[k]), r0 = 1.0f - r1;
                     const float e1 = r1 * b1, e0 = r0 * b0;
                     const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
-                    const float inv = 1.0f / (m1 + m0);
+                    const float inv = frcp(m1 + m0);
                     b1 = m1 * inv;
                     b0 = m0 * inv;
                 }
@@ -454,7 +456,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
             if (jpos < L) {
                 const int j = chain_pixel(dir, H, W, chain, jpos);
                 const int x = j % W, y = j / W;
-                const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
+                const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
                 const float s = chain_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
             }
@@ -541,7 +543,7 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
     double acc = 0.0, mass = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < HW; j += gridDim.x * blockDim.x) {
         const int x = j % a.W, y = j / a.W;
-        const float xh = ((float)x - a.e.cx) / a.e.fx, yh = ((float)y - a.e.cy) / a.e.fy;
+        const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
         const float th = a.theta[j];
         float px0 = 0.0f, py0 = 0.0f;
         bool ok0 = th > 0.0f;
@@ -560,10 +562,10 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                     r = m.r;
                     ell = m.ell;
                     if (a.logrho || a.logmu || a.ll_part) {
-                        const float vn = sqrtf(fmaf(vu, vu, vv * vv));
+                        const float vn = __builtin_amdgcn_sqrtf(fmaf(vu, vu, vv * vv));
                         const float la = fmaf(a.e.a2, vn, a.e.log_a1);
                         const float beta = fmaxf(fmaf(a.e.b1, vn, a.e.b2), a.e.beta_min);
-                        const float x2 = fmaxf(fmaf(rx, rx, ry * ry), a.e.x_floor);
+                        const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), a.e.x_floor), 1e30f);
                         const float s1 = __logf(x2) - la;
                         const float lb = __logf(beta) - la;
                         lr = lb + (beta - 1.0f) * s1 - 2.0f * softplus(beta * s1);
