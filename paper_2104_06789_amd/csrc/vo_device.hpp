@@ -80,15 +80,21 @@ __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh
     return true;
 }
 
+// Natural log / exp on the hardware base-2 units (v_log_f32, v_exp_f32):
+// arguments here are normal positive numbers (logs) or bounded (exps), so no
+// denormal fix-ups are needed; results within a few ulp.
+__device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
 // log(1 + e) for e in [0, 1]: series where 1 + e would round away e.
 __device__ __forceinline__ float log1p_unit(float e)
 {
-    return e < 1e-3f ? e * (1.0f - e * (0.5f - e * (1.0f / 3.0f))) : __logf(1.0f + e);
+    return e < 1e-3f ? e * (1.0f - e * (0.5f - e * (1.0f / 3.0f))) : fast_log(1.0f + e);
 }
 
 __device__ __forceinline__ float softplus(float z)
 {
-    return fmaxf(z, 0.0f) + log1p_unit(__expf(-fabsf(z)));
+    return fmaxf(z, 0.0f) + log1p_unit(fast_exp(-fabsf(z)));
 }
 
 // Bilinear sample of flow X (one frame, float2 [H][W]) at (px, py).
@@ -127,15 +133,15 @@ __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, f
     const float vn = __builtin_amdgcn_sqrtf(vn2);
     const float la = fmaf(e.a2, vn, e.log_a1);
     const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-    const float lx = __logf(x2);
-    const float lm = __logf(fmaxf(e.lam2 * vn2, e.x_floor));
+    const float lx = fast_log(x2);
+    const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
     const float z1 = beta * (lx - la), z2 = beta * (lm - la);
     return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
 }
 
 __device__ __forceinline__ Emis emis_from_d(float d)
 {
-    const float e = __expf(-fabsf(d));
+    const float e = fast_exp(-fabsf(d));
     const float inv = frcp(1.0f + e);
     Emis o;
     o.ell = -(fmaxf(d, 0.0f) + log1p_unit(e));

@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
                 const float n1 = ff1 * b1, n0 = ff0 * b0;
                 rq[k] = n1 * frcp(n1 + n0);
                 if (k > s0) {
-                    const float r1 = __expf(ll[k]), r0 = 1.0f - r1;
+                    const float r1 = fast_exp(ll[k]), r0 = 1.0f - r1;
                     const float e1 = r1 * b1, e0 = r0 * b0;
                     const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
                     const float inv = frcp(m1 + m0);
@@ -566,8 +566,8 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                         const float la = fmaf(a.e.a2, vn, a.e.log_a1);
                         const float beta = fmaxf(fmaf(a.e.b1, vn, a.e.b2), a.e.beta_min);
                         const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), a.e.x_floor), 1e30f);
-                        const float s1 = __logf(x2) - la;
-                        const float lb = __logf(beta) - la;
+                        const float s1 = fast_log(x2) - la;
+                        const float lb = fast_log(beta) - la;
                         lr = lb + (beta - 1.0f) * s1 - 2.0f * softplus(beta * s1);
                         lm = lr + d;
                         const double w = r;
