@@ -10,11 +10,15 @@ Metric: pixel-frame EM updates/s = T*H*W*n_iters / (seconds per window).
 Default workload: the indoor shape (T=6, 640x480, 4 iterations, 2048 P3P
 groups per frame); --workload driving runs T=8, 1242x375.
 
-The roofline object reports the dominant kernel (the fused sweep) against HBM
-bandwidth: algorithmic bytes per launch = flow stack read (8 B per pixel-frame)
-plus depth read and write (8 B per pixel), divided by the mean sweep duration
-measured with HIP events on the solver's stream.  The cpu_baseline object times
-the FP64 CPU oracle on one window of the same workload.
+The roofline object reports the dominant GPU kernel, the fused directional
+sweep, against the VALU issue rate it is bound by.  Algorithmic work per
+launch = 3 emission evaluations per pixel-frame (previous depth, random sample,
+propagated neighbour: what the serial walk needs) x EMISSION_VALU_OPS FP32
+VALU lane-instructions each, divided by the mean sweep duration measured with
+HIP events on the solver's stream; the peak is 256 CUs x 64 lanes x 2.4 GHz.
+The HBM view of the same launch (flow stack read + depth read/write) is kept
+alongside for reference.  The cpu_baseline object times the FP64 CPU oracle on
+one window of the same workload.
 """
 import argparse
 import json
@@ -28,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # FP32 lane-instructions/s (non-packed), 39.3 T
+EMISSION_VALU_OPS = 182                      # VALU instructions of one emission evaluation (gfx950 ISA)
 
 
 def _pose_error(poses, gt):
@@ -96,7 +102,9 @@ def main():
     launches = float(np.mean([x["sweep_launches"] for x in phases]))
     sweep_ms = ph["sweeps"] / max(launches, 1.0)
     alg_bytes = 8.0 * T * H * W + 8.0 * H * W
-    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    achieved_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    alg_ops = 3.0 * T * H * W * EMISSION_VALU_OPS
+    achieved = alg_ops / (sweep_ms * 1e-3) / 1e12
 
     rot_err, tdir_err = _pose_error(out[0].cpu().numpy(), w["poses"])
 
@@ -120,9 +128,11 @@ def main():
         "windows_per_s": 1e3 / ms,
         "phase_ms": ph,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "launch_ms": sweep_ms},
+        "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms,
+                     "hbm_view": {"alg_bytes_per_launch": alg_bytes, "achieved_GBs": achieved_gbs,
+                                  "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
     }
 
     if not args.no_cpu_baseline:
