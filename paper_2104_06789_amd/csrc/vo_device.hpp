@@ -282,16 +282,24 @@ __device__ inline void se3_log(const double *R, const double *t, double *p)
         phi[1] = f * wy;
         phi[2] = f * wz;
     } else {
-        // near pi: the symmetric part (R + R^T)/2 = c I + (1 - c) n n^T
+        // near pi: the symmetric part (R + R^T)/2 = c I + (1 - c) n n^T; the
+        // largest diagonal entry gives the best-conditioned component of n
         const double oc = 1.0 - c;
-        const double d[3] = {R[0], R[4], R[8]};
-        int m = 0;
-        if (d[1] > d[m]) m = 1;
-        if (d[2] > d[m]) m = 2;
+        const int m = R[8] > (R[4] > R[0] ? R[4] : R[0]) ? 2 : (R[4] > R[0] ? 1 : 0);
         double n[3];
-        n[m] = sqrt(fmax(0.0, (d[m] - c) / oc));
-        for (int k = 0; k < 3; ++k)
-            if (k != m) n[k] = (R[3 * m + k] + R[3 * k + m]) / (2.0 * oc * n[m]);
+        if (m == 0) {
+            n[0] = sqrt(fmax(0.0, (R[0] - c) / oc));
+            n[1] = (R[1] + R[3]) / (2.0 * oc * n[0]);
+            n[2] = (R[2] + R[6]) / (2.0 * oc * n[0]);
+        } else if (m == 1) {
+            n[1] = sqrt(fmax(0.0, (R[4] - c) / oc));
+            n[0] = (R[3] + R[1]) / (2.0 * oc * n[1]);
+            n[2] = (R[5] + R[7]) / (2.0 * oc * n[1]);
+        } else {
+            n[2] = sqrt(fmax(0.0, (R[8] - c) / oc));
+            n[0] = (R[6] + R[2]) / (2.0 * oc * n[2]);
+            n[1] = (R[7] + R[5]) / (2.0 * oc * n[2]);
+        }
         const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         double sg = (n[0] * wx + n[1] * wy + n[2] * wz) < 0 ? -1.0 : 1.0;
         for (int k = 0; k < 3; ++k) phi[k] = sg * th * n[k] / nn;
@@ -322,33 +330,30 @@ __device__ inline void se3_log(const double *R, const double *t, double *p)
 // lengths of the 3-D triangle, the law of cosines gives three quadrics.  With
 // u = s2/s1 and v = s3/s1, subtracting two of them yields u as a rational
 // function N(v)/D(v); substituting into the third gives a quartic in v
-// (Grunert's route).  Its real roots are found in closed form (Ferrari, via
-// the resolvent cubic) and polished by Newton steps.  The camera-frame
-// triangle s_i f_i is then aligned rigidly onto the 3-D triangle.
+// (Grunert's route).  The quartic factors into two quadratics (Ferrari, via
+// the largest root of the resolvent cubic); root slots 0, 1 belong to the
+// first factor and 2, 3 to the second, so that one lane can solve one slot.
+// Each real root is polished by Newton steps, and the camera-frame triangle
+// s_i f_i is aligned rigidly onto the 3-D triangle.  Everything is indexed
+// statically: no private-memory arrays.
 // ---------------------------------------------------------------------------
-__device__ inline int cubic_real_roots(double a2, double a1, double a0, double *x)
+// largest real root of x^3 + a2 x^2 + a1 x + a0
+__device__ inline double cubic_largest_root(double a2, double a1, double a0)
 {
-    // x^3 + a2 x^2 + a1 x + a0
     const double q = (3.0 * a1 - a2 * a2) / 9.0;
     const double r = (9.0 * a2 * a1 - 27.0 * a0 - 2.0 * a2 * a2 * a2) / 54.0;
     const double disc = q * q * q + r * r;
     const double sh = a2 / 3.0;
     if (disc > 0) {
         const double sd = sqrt(disc);
-        const double s = cbrt(r + sd), t = cbrt(r - sd);
-        x[0] = s + t - sh;
-        return 1;
+        return cbrt(r + sd) + cbrt(r - sd) - sh;
     }
-    if (q == 0) {
-        x[0] = -sh;
-        return 1;
-    }
+    if (q == 0) return -sh;
     const double mq = sqrt(-q);
     const double th = acos(fmin(1.0, fmax(-1.0, r / (mq * mq * mq))));
-    x[0] = 2.0 * mq * cos(th / 3.0) - sh;
-    x[1] = 2.0 * mq * cos((th + 2.0 * 3.14159265358979323846) / 3.0) - sh;
-    x[2] = 2.0 * mq * cos((th + 4.0 * 3.14159265358979323846) / 3.0) - sh;
-    return 3;
+    // of the three trigonometric roots 2 mq cos((th + 2 pi k) / 3) - sh,
+    // k = 0 is the largest for th in [0, pi]
+    return 2.0 * mq * cos(th / 3.0) - sh;
 }
 
 __device__ inline double quartic_eval(const double *c, double v)
@@ -356,33 +361,33 @@ __device__ inline double quartic_eval(const double *c, double v)
     return (((c[4] * v + c[3]) * v + c[2]) * v + c[1]) * v + c[0];
 }
 
-// real roots of c4 v^4 + ... + c0 (c4 != 0); up to 4
-__device__ inline int quartic_real_roots(const double *c, double *out)
+// Real root in `slot` (0..3) of c4 v^4 + ... + c0 (c4 != 0); false if that
+// root of the factorisation is complex.
+__device__ inline bool quartic_root_slot(const double *c, int slot, double &out)
 {
     const double b = c[3] / c[4], cc = c[2] / c[4], d = c[1] / c[4], e = c[0] / c[4];
     const double b2 = b * b;
     const double p = cc - 0.375 * b2;
     const double q = d - 0.5 * b * cc + 0.125 * b2 * b;
     const double r = e - 0.25 * b * d + 0.0625 * b2 * cc - 3.0 / 256.0 * b2 * b2;
-    double ys[4];
-    int n = 0;
+    const double sgn = (slot & 1) ? -1.0 : 1.0;
+    double y = 0.0;
+    bool ok = false;
     const double scale = fmax(1.0, fmax(fabs(p), sqrt(fabs(r))));
     if (fabs(q) < 1e-14 * scale * sqrt(scale)) {
-        // biquadratic y^4 + p y^2 + r
+        // biquadratic y^4 + p y^2 + r: y^2 = z1 (slots 0, 1) or z2 (slots 2, 3)
         const double dd = p * p - 4.0 * r;
         if (dd >= 0) {
             const double sd = sqrt(dd);
-            const double z1 = 0.5 * (-p + sd), z2 = 0.5 * (-p - sd);
-            if (z1 >= 0) { ys[n++] = sqrt(z1); ys[n++] = -sqrt(z1); }
-            if (z2 >= 0) { ys[n++] = sqrt(z2); ys[n++] = -sqrt(z2); }
+            const double z = slot < 2 ? 0.5 * (-p + sd) : 0.5 * (-p - sd);
+            if (z >= 0) {
+                y = sgn * sqrt(z);
+                ok = true;
+            }
         }
     } else {
-        // resolvent: m^3 + p m^2 + (p^2/4 - r) m - q^2/8 = 0, take the largest root (> 0)
-        double ms[3];
-        const int nm = cubic_real_roots(p, 0.25 * p * p - r, -0.125 * q * q, ms);
-        double m = ms[0];
-        for (int i = 1; i < nm; ++i) m = fmax(m, ms[i]);
-        // Newton polish of the resolvent root
+        // resolvent m^3 + p m^2 + (p^2/4 - r) m - q^2/8 = 0, largest root (> 0)
+        double m = cubic_largest_root(p, 0.25 * p * p - r, -0.125 * q * q);
         for (int it = 0; it < 2; ++it) {
             const double f = ((m + p) * m + (0.25 * p * p - r)) * m - 0.125 * q * q;
             const double df = (3.0 * m + 2.0 * p) * m + (0.25 * p * p - r);
@@ -395,31 +400,26 @@ __device__ inline int quartic_real_roots(const double *c, double *out)
             const double c1 = 0.5 * p + m + k, c2 = 0.5 * p + m - k;
             const double d1 = s * s - 4.0 * c1, d2 = s * s - 4.0 * c2;
             const double tol = -1e-12 * (s * s + 4.0 * fabs(c1) + 4.0 * fabs(c2));
-            if (d1 >= tol) {
-                const double sq = sqrt(fmax(d1, 0.0));
-                ys[n++] = 0.5 * (s + sq);
-                ys[n++] = 0.5 * (s - sq);
-            }
-            if (d2 >= tol) {
-                const double sq = sqrt(fmax(d2, 0.0));
-                ys[n++] = 0.5 * (-s + sq);
-                ys[n++] = 0.5 * (-s - sq);
+            const double dq = slot < 2 ? d1 : d2;
+            if (dq >= tol) {
+                const double sq = sqrt(fmax(dq, 0.0));
+                y = 0.5 * ((slot < 2 ? s : -s) + sgn * sq);
+                ok = true;
             }
         }
     }
-    for (int i = 0; i < n; ++i) {
-        double v = ys[i] - 0.25 * b;
-        for (int it = 0; it < 3; ++it) {  // Newton polish on the original quartic
-            const double f = quartic_eval(c, v);
-            const double df = ((4.0 * c[4] * v + 3.0 * c[3]) * v + 2.0 * c[2]) * v + c[1];
-            if (df == 0) break;
-            const double dv = f / df;
-            v -= dv;
-            if (fabs(dv) <= 1e-16 * fabs(v)) break;
-        }
-        out[i] = v;
+    if (!ok) return false;
+    double v = y - 0.25 * b;
+    for (int it = 0; it < 3; ++it) {  // Newton polish on the original quartic
+        const double f = quartic_eval(c, v);
+        const double df = ((4.0 * c[4] * v + 3.0 * c[3]) * v + 2.0 * c[2]) * v + c[1];
+        if (df == 0) break;
+        const double dv = f / df;
+        v -= dv;
+        if (fabs(dv) <= 1e-16 * fabs(v)) break;
     }
-    return n;
+    out = v;
+    return true;
 }
 
 // Orthonormal frame of a triangle: columns e1 along X1->X2, e3 normal, e2 = e3 x e1.
@@ -443,8 +443,9 @@ __device__ inline void triangle_frame(const double *X1, const double *X2, const 
 }
 
 // P: 3 points (rows) in the source frame; f: 3 unit bearings (rows) in the
-// target camera.  Writes up to 4 poses (R 9, t 3) with f_i ~ R P_i + t.
-__device__ inline int p3p_solve(const double *P, const double *f, double *Rs, double *ts)
+// target camera.  The pose (R, t) with f_i ~ R P_i + t of quartic root slot
+// `slot`; false if that root is complex, not admissible or not finite.
+__device__ inline bool p3p_root(const double *P, const double *f, int slot, double *R, double *t)
 {
     double s23[3], s13[3], s12[3];
     for (int k = 0; k < 3; ++k) {
@@ -453,7 +454,7 @@ __device__ inline int p3p_solve(const double *P, const double *f, double *Rs, do
         s12[k] = P[k] - P[3 + k];
     }
     const double A2 = dot3d(s23, s23), B2 = dot3d(s13, s13), C2 = dot3d(s12, s12);
-    if (!(A2 > 0) || !(B2 > 0) || !(C2 > 0)) return 0;
+    if (!(A2 > 0) || !(B2 > 0) || !(C2 > 0)) return false;
     const double ca = dot3d(f + 3, f + 6), cb = dot3d(f, f + 6), cg = dot3d(f, f + 3);
     // N(v) = n2 v^2 + n1 v + n0 ; D(v) = e1 v + e0 ; Q(v) = v^2 - 2 cb v + 1
     const double K = C2 - A2;
@@ -469,41 +470,34 @@ __device__ inline int p3p_solve(const double *P, const double *f, double *Rs, do
            (g0 * e1 * e1 + 2.0 * g1 * e1 * e0 + g2 * e0 * e0);
     c[1] = B2 * 2.0 * n1 * n0 - 2.0 * B2 * cg * (n1 * e0 + n0 * e1) + (2.0 * g0 * e1 * e0 + g1 * e0 * e0);
     c[0] = B2 * n0 * n0 - 2.0 * B2 * cg * (n0 * e0) + g0 * e0 * e0;
-    if (c[4] == 0) return 0;
-    double vs[4];
-    const int nv = quartic_real_roots(c, vs);
-    double FP[9];
-    triangle_frame(P, P + 3, P + 6, FP);
-    int n = 0;
-    for (int i = 0; i < nv; ++i) {
-        const double v = vs[i];
-        const double D = e1 * v + e0, Q = (v - 2.0 * cb) * v + 1.0;
-        if (!(v > 0) || fabs(D) < 1e-14 * B2 || !(Q > 0)) continue;
-        const double u = ((n2 * v + n1) * v + n0) / D;
-        if (!(u > 0)) continue;
-        const double s1 = sqrt(B2 / Q), s2 = u * s1, s3 = v * s1;
-        double X[9];
-        for (int k = 0; k < 3; ++k) {
-            X[k] = s1 * f[k];
-            X[3 + k] = s2 * f[3 + k];
-            X[6 + k] = s3 * f[6 + k];
-        }
-        double FX[9];
-        triangle_frame(X, X + 3, X + 6, FX);
-        double *R = Rs + 9 * n, *t = ts + 3 * n;
-        for (int a = 0; a < 3; ++a)  // R = FX FP^T
-            for (int bb = 0; bb < 3; ++bb)
-                R[3 * a + bb] = FX[3 * a] * FP[3 * bb] + FX[3 * a + 1] * FP[3 * bb + 1] +
-                                FX[3 * a + 2] * FP[3 * bb + 2];
-        double RP[3];
-        mv3(R, P, RP);
-        for (int k = 0; k < 3; ++k) t[k] = X[k] - RP[k];
-        bool ok = true;
-        for (int k = 0; k < 9; ++k) ok = ok && isfinite(R[k]);
-        for (int k = 0; k < 3; ++k) ok = ok && isfinite(t[k]);
-        if (ok) ++n;
+    if (c[4] == 0) return false;
+    double v;
+    if (!quartic_root_slot(c, slot, v)) return false;
+    const double D = e1 * v + e0, Q = (v - 2.0 * cb) * v + 1.0;
+    if (!(v > 0) || fabs(D) < 1e-14 * B2 || !(Q > 0)) return false;
+    const double u = ((n2 * v + n1) * v + n0) / D;
+    if (!(u > 0)) return false;
+    const double s1 = sqrt(B2 / Q), s2 = u * s1, s3 = v * s1;
+    double X[9];
+    for (int k = 0; k < 3; ++k) {
+        X[k] = s1 * f[k];
+        X[3 + k] = s2 * f[3 + k];
+        X[6 + k] = s3 * f[6 + k];
     }
-    return n;
+    double FP[9], FX[9];
+    triangle_frame(P, P + 3, P + 6, FP);
+    triangle_frame(X, X + 3, X + 6, FX);
+    for (int a = 0; a < 3; ++a)  // R = FX FP^T
+        for (int bb = 0; bb < 3; ++bb)
+            R[3 * a + bb] = FX[3 * a] * FP[3 * bb] + FX[3 * a + 1] * FP[3 * bb + 1] +
+                            FX[3 * a + 2] * FP[3 * bb + 2];
+    double RP[3];
+    mv3(R, P, RP);
+    for (int k = 0; k < 3; ++k) t[k] = X[k] - RP[k];
+    bool ok = true;
+    for (int k = 0; k < 9; ++k) ok = ok && isfinite(R[k]);
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite(t[k]);
+    return ok;
 }
 
 }  // namespace vo

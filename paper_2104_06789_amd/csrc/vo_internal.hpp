@@ -44,7 +44,7 @@ struct voldor_ctx {
     vo::FrameF *frames;    // [T_max+1] FP32 copy of Mcum for the sweeps
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
     int *status;           // [8]: status word, pose diagnostics scratch
-    double *samples;       // SoA [8][4 S] pose sample slots (p, weight, valid)
+    double *samples;       // SoA [7][slots] pose samples (p, weight), compacted per block of groups
     double *seed_score;    // [kMaxSeeds + 1][8] (p, density, valid)
     int *pose_diag;        // [T_max][4]
     double *hyp;           // [kMaxHyp][18]: essential E (9), fundamental F (9)
@@ -54,9 +54,10 @@ struct voldor_ctx {
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
-    double *dense;         // [7][4 S_max] valid pose samples in group order (SoA)
-    double *pose_info;     // [4]: samples, weight sum, groups with a sample
+    double *dense;         // [7][4 S_max] mean-shift samples beyond the register capacity
     int *gcnt;             // [S_max] valid samples per group
+    int *gpre;             // [S_max] first sample of each group inside its block
+    int *bcnt;             // [S_max / 16 + 1][2] samples and valid groups per block
     double *prev_pose;     // [12] staging of a host-provided previous pose
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
@@ -88,6 +89,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
                      const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
                      double *rel_poses, hipStream_t s);
 int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s);
+size_t pose_sample_slots(int S_max);
 int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s);
 int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
 

@@ -1,10 +1,10 @@
-// vo_pose.hip -- FP64 pose step of one frame (Sec. 5.2, Eq. 15-19):
+// vo_pose.hip -- pose step of one frame (Sec. 5.2, Eq. 15-19):
 //   k_pose_groups  S random pixel triples -> 3-D points in camera t-1 and
 //                  bearings in camera t through the flow X_t -> P3P roots in
 //                  front of both cameras -> se(3) samples weighted by the
-//                  product of the three rigidness values;
+//                  product of the three rigidness values (FP64);
 //   k_pose_seed    kernel density of each start candidate (previous pose and
-//                  the first samples in group order) over all samples;
+//                  the first samples in group order) over all samples (FP64);
 //   k_pose_ms      densest candidate, Gaussian mean-shift to the mode,
 //                  T_t = exp(p*), M_t = T_t o M_{t-1};
 // plus the scale gauge |t_1| = 1.
@@ -13,13 +13,25 @@
 
 namespace vo {
 
+// P3P groups are solved by 4 lanes each (one lane per quartic root slot), 16
+// groups to a 64-lane workgroup.  The valid samples of one workgroup are
+// stored contiguously in (group, root) order at slots [64 b, 64 b + bcnt[b]),
+// so that the dense sample order of the paper's description is the block
+// order followed by the order inside each block.
+constexpr int kGrpLanes = 4;
+constexpr int kGrpPerBlk = 64 / kGrpLanes;
+constexpr int kSlotsPerBlk = 64;
+constexpr int kMaxPoseBlks = kMaxGroups / kGrpPerBlk;
+
 struct GroupArgs {
     const float *theta;
     const float *rig;
     const float2 *flows;
     const double *Mprev;   // M_{t-1}
-    double *samples;       // SoA [8][ns]: p (6), weight, valid; slot 4g+r of group g
-    int *gcnt;             // [S] valid samples of each group
+    double *samples;       // SoA [7][ns]: p (6), weight
+    int *gcnt;             // [S] samples of each group
+    int *gpre;             // [S] first sample of each group inside its block
+    int *bcnt;             // [nb][2] samples of each block, groups with a valid setup
     const int *status;
     WinDims d;
     int S, t, it, ns;
@@ -46,94 +58,137 @@ __device__ __forceinline__ bool flow_bilinear_d(const float2 *X, int H, int W, d
 __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.S) return;
-    double *out = a.samples + (size_t)4 * g;
-    for (int c = 0; c < 8; ++c)
-        for (int r = 0; r < 4; ++r) out[(size_t)c * a.ns + r] = 0.0;
-    a.gcnt[g] = 0;
+    const int lane = threadIdx.x, r = lane & (kGrpLanes - 1), base = lane & ~(kGrpLanes - 1);
+    const int g = blockIdx.x * kGrpPerBlk + (lane >> 2);
     const int H = a.d.H, W = a.d.W;
     const int64_t HW = (int64_t)H * W;
-    int64_t j[3];
-    bool drawn = false;
-    for (int att = 0; att < 8 && !drawn; ++att) {
-        uint64_t c[4] = {(uint64_t)a.it, (uint64_t)a.t, (uint64_t)g, (uint64_t)att};
-        philox4x64_10(c, a.seed, kPoseStream);
-        for (int k = 0; k < 3; ++k) j[k] = u32_to_index((uint32_t)(c[k] >> 32), HW);
-        drawn = j[0] != j[1] && j[0] != j[2] && j[1] != j[2];
-    }
-    if (!drawn) return;
-    double P[9], f[9], w = 1.0;
-    const double *M = a.Mprev;
-    const float2 *X = a.flows + (size_t)(a.t - 1) * HW;
-    for (int k = 0; k < 3; ++k) {
-        const int x = (int)(j[k] % W), y = (int)(j[k] / W);
-        const double th = (double)a.theta[j[k]];
-        const double r[3] = {(x - a.d.cx) / a.d.fx, (y - a.d.cy) / a.d.fy, 1.0};
-        double Q[3];
-        mv3(M, r, Q);
-        for (int c = 0; c < 3; ++c) Q[c] = th * Q[c] + M[9 + c];
-        if (!(Q[2] > 0)) return;
-        double u0 = a.d.fx * Q[0] / Q[2] + a.d.cx, v0 = a.d.fy * Q[1] / Q[2] + a.d.cy;
-        if (a.t == 1) { u0 = x; v0 = y; }   // pi_0 is the pixel itself
-        double fu, fv;
-        if (!flow_bilinear_d(X, H, W, u0, v0, fu, fv)) return;
-        const double bx = (u0 + fu - a.d.cx) / a.d.fx, by = (v0 + fv - a.d.cy) / a.d.fy;
-        const double nb = sqrt(bx * bx + by * by + 1.0);
-        P[3 * k] = Q[0];
-        P[3 * k + 1] = Q[1];
-        P[3 * k + 2] = Q[2];
-        f[3 * k] = bx / nb;
-        f[3 * k + 1] = by / nb;
-        f[3 * k + 2] = 1.0 / nb;
-        if (a.rig) w *= (double)a.rig[(size_t)(a.t - 1) * HW + j[k]];
-    }
-    double Rs[36], ts[12];
-    const int nr = p3p_solve(P, f, Rs, ts);
-    int keep[4], nk = 0;
-    double key[4][4];
-    for (int i = 0; i < nr; ++i) {
-        bool front = true;
-        for (int k = 0; k < 3; ++k) {
-            const double z = Rs[9 * i + 6] * P[3 * k] + Rs[9 * i + 7] * P[3 * k + 1] +
-                             Rs[9 * i + 8] * P[3 * k + 2] + ts[3 * i + 2];
-            front = front && z > 0;
+    // the three pixels of the group (every lane of the group draws the same)
+    bool ok = g < a.S;
+    int64_t j0 = 0, j1 = 0, j2 = 0;
+    if (ok) {
+        bool drawn = false;
+        for (int att = 0; att < 8 && !drawn; ++att) {
+            uint64_t c[4] = {(uint64_t)a.it, (uint64_t)a.t, (uint64_t)g, (uint64_t)att};
+            philox4x64_10(c, a.seed, kPoseStream);
+            j0 = u32_to_index((uint32_t)(c[0] >> 32), HW);
+            j1 = u32_to_index((uint32_t)(c[1] >> 32), HW);
+            j2 = u32_to_index((uint32_t)(c[2] >> 32), HW);
+            drawn = j0 != j1 && j0 != j2 && j1 != j2;
         }
-        if (!front) continue;
-        key[nk][0] = rot_angle(Rs + 9 * i);
-        key[nk][1] = ts[3 * i];
-        key[nk][2] = ts[3 * i + 1];
-        key[nk][3] = ts[3 * i + 2];
-        keep[nk++] = i;
+        ok = drawn;
     }
-    // canonical order: rotation angle, then t_x, t_y, t_z (insertion sort)
-    for (int a1 = 1; a1 < nk; ++a1) {
-        for (int b1 = a1; b1 > 0; --b1) {
-            bool less = false;
-            for (int c = 0; c < 4; ++c) {
-                if (key[b1][c] < key[b1 - 1][c]) { less = true; break; }
-                if (key[b1][c] > key[b1 - 1][c]) break;
+    // lane r < 3 of the group: point r in camera t-1 and its bearing in camera t
+    double Pk[3] = {0.0, 0.0, 0.0}, fk[3] = {0.0, 0.0, 1.0}, wk = 1.0;
+    int okk = 1;
+    if (ok && r < 3) {
+        const int64_t jj = r == 0 ? j0 : (r == 1 ? j1 : j2);
+        const int x = (int)(jj % W), y = (int)(jj / W);
+        const double th = (double)a.theta[jj];
+        const double ray[3] = {(x - a.d.cx) / a.d.fx, (y - a.d.cy) / a.d.fy, 1.0};
+        const double *M = a.Mprev;
+        mv3(M, ray, Pk);
+        for (int c = 0; c < 3; ++c) Pk[c] = th * Pk[c] + M[9 + c];
+        okk = Pk[2] > 0;
+        double fu = 0.0, fv = 0.0;
+        if (okk) {
+            double u0 = a.d.fx * Pk[0] / Pk[2] + a.d.cx, v0 = a.d.fy * Pk[1] / Pk[2] + a.d.cy;
+            if (a.t == 1) { u0 = x; v0 = y; }   // pi_0 is the pixel itself
+            okk = flow_bilinear_d(a.flows + (size_t)(a.t - 1) * HW, H, W, u0, v0, fu, fv);
+            if (okk) {
+                const double bx = (u0 + fu - a.d.cx) / a.d.fx, by = (v0 + fv - a.d.cy) / a.d.fy;
+                const double nb = sqrt(bx * bx + by * by + 1.0);
+                fk[0] = bx / nb;
+                fk[1] = by / nb;
+                fk[2] = 1.0 / nb;
             }
-            if (!less) break;
-            for (int c = 0; c < 4; ++c) { const double tmp = key[b1][c]; key[b1][c] = key[b1 - 1][c]; key[b1 - 1][c] = tmp; }
-            const int tk = keep[b1]; keep[b1] = keep[b1 - 1]; keep[b1 - 1] = tk;
         }
+        if (a.rig) wk = (double)a.rig[(size_t)(a.t - 1) * HW + jj];
     }
-    int nv = 0;
-    for (int s = 0; s < nk; ++s) {
-        const int i = keep[s];
-        double p[6];
-        se3_log(Rs + 9 * i, ts + 3 * i, p);
-        bool fin = true;
-        for (int c = 0; c < 6; ++c) fin = fin && isfinite(p[c]);
-        if (!fin) continue;
-        double *o = out + nv;   // valid samples fill the group's slots without gaps
+    // every lane of the group gathers the three points
+    double P[9], f[9], w = 1.0;
+    bool gok = ok;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            P[3 * k + c] = __shfl(Pk[c], base + k, 64);
+            f[3 * k + c] = __shfl(fk[c], base + k, 64);
+        }
+        w *= __shfl(wk, base + k, 64);
+        gok = gok && __shfl(okk, base + k, 64) != 0;
+    }
+    // root slot r: pose, then all three points in front of camera t
+    double R[9], tv[3];
+    bool val = gok && p3p_root(P, f, r, R, tv);
+    if (val)
+        for (int k = 0; k < 3; ++k)
+            val = val && R[6] * P[3 * k] + R[7] * P[3 * k + 1] + R[8] * P[3 * k + 2] + tv[2] > 0;
+    // canonical order among the group's roots: rotation angle, then t_x, t_y, t_z
+    double key[4] = {0.0, 0.0, 0.0, 0.0};
+    if (val) {
+        key[0] = rot_angle(R);
+        key[1] = tv[0];
+        key[2] = tv[1];
+        key[3] = tv[2];
+    }
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < kGrpLanes; ++q) {
+        double kq[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kq[c] = __shfl(key[c], base + q, 64);
+        const int vq = __shfl((int)val, base + q, 64);
+        int cmp = 0;   // -1: root q precedes this lane's root, +1: follows
+#pragma unroll
+        for (int c = 3; c >= 0; --c) cmp = kq[c] < key[c] ? -1 : (kq[c] > key[c] ? 1 : cmp);
+        if (q != r && vq && (cmp < 0 || (cmp == 0 && q < r))) ++rank;
+    }
+    double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (val) {
+        se3_log(R, tv, p);
+        for (int c = 0; c < 6; ++c) val = val && isfinite(p[c]);
+    }
+    // valid samples fill the group's positions without gaps, in canonical order
+    const unsigned long long vm = __ballot(val);
+    int pos = 0;
+#pragma unroll
+    for (int q = 0; q < kGrpLanes; ++q) {
+        const int rq = __shfl(rank, base + q, 64);
+        if (((vm >> (base + q)) & 1ull) && rq < rank) ++pos;
+    }
+    const int excl = __popcll(vm & ((1ull << base) - 1ull));
+    const unsigned long long gm = __ballot(gok && r == 0);
+    if (r == 0 && g < a.S) {
+        a.gcnt[g] = __popcll((vm >> base) & 0xFull);
+        a.gpre[g] = excl;
+    }
+    if (lane == 0) {
+        a.bcnt[2 * blockIdx.x] = __popcll(vm);
+        a.bcnt[2 * blockIdx.x + 1] = __popcll(gm);
+    }
+    if (val) {
+        double *o = a.samples + (size_t)kSlotsPerBlk * blockIdx.x + excl + pos;
         for (int c = 0; c < 6; ++c) o[(size_t)c * a.ns] = p[c];
         o[(size_t)6 * a.ns] = w;
-        o[(size_t)7 * a.ns] = 1.0;
-        ++nv;
     }
-    a.gcnt[g] = nv;
+}
+
+// AoS copy [4S][8] of the samples in per-group slots 4g + r (p, weight, valid;
+// zero where a group has fewer samples): test hook of the pose step
+__global__ void k_samples_aos(const double *soa, const int *gcnt, const int *gpre, int S, int ns,
+                              double *aos)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * S) return;
+    const int g = i >> 2, r = i & 3;
+    double *o = aos + (size_t)8 * i;
+    if (r < gcnt[g]) {
+        const size_t src = (size_t)kSlotsPerBlk * (g / kGrpPerBlk) + gpre[g] + r;
+        for (int c = 0; c < 7; ++c) o[c] = soa[(size_t)c * ns + src];
+        o[7] = 1.0;
+    } else {
+        for (int c = 0; c < 8; ++c) o[c] = 0.0;
+    }
 }
 
 __device__ __forceinline__ double mahal2(const double *a, const double *b, double is2t, double is2r)
@@ -141,6 +196,30 @@ __device__ __forceinline__ double mahal2(const double *a, const double *b, doubl
     const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
     const double d3 = a[3] - b[3], d4 = a[4] - b[4], d5 = a[5] - b[5];
     return (d0 * d0 + d1 * d1 + d2 * d2) * is2t + (d3 * d3 + d4 * d4 + d5 * d5) * is2r;
+}
+
+// Exclusive prefix of v over a workgroup of NT threads; *tot receives the sum.
+// wsum: NT / 64 ints of LDS.  Contains two barriers.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &tot)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int b = 0;
+    tot = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        const int s = wsum[w];
+        b += w < wv ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    return b + incl - v;
 }
 
 template <int NT>
@@ -152,130 +231,57 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     if (lane == 0) red[wv] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < NT / 64; ++i) s += red[i];
-        red[NT / 64] = s;
-    }
-    __syncthreads();
-    return red[NT / 64];
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
 }
 
-// Dense copy of the valid samples in (group, root) order: SoA dense[c][i],
-// c = 0..5 the se(3) coordinates, c = 6 the weight; info = (N, sum w, groups).
-struct CompactArgs {
-    const double *samples;  // SoA [8][ns]
-    const int *gcnt;        // [S]
-    double *dense;          // [7][stride]
-    double *info;           // [4]
-    const int *status;
-    int S, ns, stride;
-};
-
-constexpr int kCompactThreads = 1024;
-constexpr int kCompactGroups = kMaxGroups / kCompactThreads;  // groups per thread (max)
-
-__global__ void __launch_bounds__(kCompactThreads) k_pose_compact(CompactArgs a)
+// Map of the dense sample order onto the block-compacted slots: idx[i] = slot
+// of the i-th valid sample in (group, root) order.  Reads bcnt [nb][2]; returns
+// N and the number of groups with a valid setup.  Contains barriers.
+template <int NT>
+__device__ __forceinline__ void dense_index(const int *bcnt, int nb, int *lcnt, int *lpre, int *wsum,
+                                           unsigned short *idx, int &N, int &groups)
 {
-    if (a.status && *a.status != kStatusOk) return;
-    __shared__ int wsum[kCompactThreads / 64];
-    __shared__ int goff[kMaxGroups];
-    __shared__ unsigned char gcl[kMaxGroups];
-    __shared__ double red[3][kCompactThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int chunk = (a.S + kCompactThreads - 1) / kCompactThreads;
-    const int g0 = min(tid * chunk, a.S), g1 = min(g0 + chunk, a.S);
-    int cn[kCompactGroups];
-    int cnt = 0, groups = 0;
-#pragma unroll
-    for (int u = 0; u < kCompactGroups; ++u) {
-        cn[u] = (g0 + u < g1) ? a.gcnt[g0 + u] : 0;
-        cnt += cn[u];
-        groups += cn[u] > 0;
-    }
-    // exclusive scan of the counts: first dense index of every group
-    int incl = cnt;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wv; ++w) base += wsum[w];
-    int off = base + incl - cnt;
-#pragma unroll
-    for (int u = 0; u < kCompactGroups; ++u)
-        if (g0 + u < g1) {
-            goff[g0 + u] = off;
-            gcl[g0 + u] = (unsigned char)cn[u];
-            off += cn[u];
-        }
-    __syncthreads();
-    // coalesced copy, slot by slot: the valid samples of group g fill its
-    // slots 4g .. 4g + gcnt[g] - 1
-    double wt = 0.0;
-    const int nslot = 4 * a.S;
-    for (int s0 = tid; s0 < nslot; s0 += 4 * kCompactThreads) {
-        double v[4][7];
-        int dst[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int sl = s0 + u * kCompactThreads;
-            const int g = sl >> 2, r = sl & 3;
-            dst[u] = (sl < nslot && r < gcl[g]) ? goff[g] + r : -1;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) v[u][c] = dst[u] >= 0 ? a.samples[(size_t)c * a.ns + sl] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (dst[u] < 0) continue;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) a.dense[(size_t)c * a.stride + dst[u]] = v[u][c];
-            wt += v[u][6];
-        }
-    }
-    double v3[3] = {(double)cnt, wt, (double)groups};
-    for (int c = 0; c < 3; ++c) {
-        double v = v3[c];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (lane == 0) red[c][wv] = v;
+    const int tid = threadIdx.x;
+    const int v = tid < nb ? bcnt[2 * tid] : 0;
+    const int gv = tid < nb ? bcnt[2 * tid + 1] : 0;
+    if (tid < nb) lcnt[tid] = v;
+    const int ex = block_excl_scan<NT>(v, wsum, N);
+    if (tid < nb) lpre[tid] = ex;
+    block_excl_scan<NT>(gv, wsum, groups);   // its barriers also publish lcnt / lpre
+    for (int s = tid; s < kSlotsPerBlk * nb; s += NT) {
+        const int b = s / kSlotsPerBlk, k = s % kSlotsPerBlk;
+        if (k < lcnt[b]) idx[lpre[b] + k] = (unsigned short)s;
     }
     __syncthreads();
-    if (tid < 3) {
-        double sum = 0.0;
-        for (int w = 0; w < kCompactThreads / 64; ++w) sum += red[tid][w];
-        a.info[tid] = sum;
-    }
-}
-
-// AoS copy [4S][8] of the sample slots (test hook of the pose step)
-__global__ void k_samples_aos(const double *soa, int ns, double *aos)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns) return;
-    for (int c = 0; c < 8; ++c) aos[(size_t)8 * i + c] = soa[(size_t)c * ns + i];
 }
 
 struct SeedArgs {
-    const double *dense;
-    const double *info;
+    const double *samples; // SoA [7][ns], block-compacted
+    const int *bcnt;       // [nb][2]
     double *seed_score;    // [n_seeds + 1][8]: p, density, valid
     const double *prev;    // previous relative pose T_t
     const int *status;
-    int stride, have_prev;
+    int ns, nb, have_prev;
     double is2t, is2r;
 };
 
-// density of one start candidate (block 0: the previous pose; block b: the
-// (b-1)-th sample in group order) over all samples
-__global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
+constexpr int kSeedThreads = 512;
+
+// Density of one start candidate (block 0: the previous pose; block b: the
+// (b-1)-th sample in group order) over all samples, FP64 throughout.
+__global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
-    __shared__ double red[8];
+    __shared__ unsigned short idx[4 * kMaxGroups];
+    __shared__ int lcnt[kMaxPoseBlks], lpre[kMaxPoseBlks];
+    __shared__ int wsum[kSeedThreads / 64];
+    __shared__ double red[kSeedThreads / 64];
     __shared__ double seed[6];
     const int b = blockIdx.x, tid = threadIdx.x;
-    const int N = (int)a.info[0];
     double *o = a.seed_score + 8 * b;
+    int N, groups;
+    dense_index<kSeedThreads>(a.bcnt, a.nb, lcnt, lpre, wsum, idx, N, groups);
     if ((b == 0 && !a.have_prev) || (b > 0 && b - 1 >= N)) {
         if (tid == 0) o[7] = 0.0;
         return;
@@ -286,19 +292,21 @@ __global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
             se3_log(a.prev, a.prev + 9, p);
             for (int c = 0; c < 6; ++c) seed[c] = p[c];
         } else {
-            for (int c = 0; c < 6; ++c) seed[c] = a.dense[(size_t)c * a.stride + (b - 1)];
+            const int sl = idx[b - 1];
+            for (int c = 0; c < 6; ++c) seed[c] = a.samples[(size_t)c * a.ns + sl];
         }
     }
     __syncthreads();
     double sd[6];
     for (int c = 0; c < 6; ++c) sd[c] = seed[c];
     double s = 0.0;
-    for (int i = tid; i < N; i += 256) {
+    for (int i = tid; i < N; i += kSeedThreads) {
+        const int sl = idx[i];
         double q[6];
-        for (int c = 0; c < 6; ++c) q[c] = a.dense[(size_t)c * a.stride + i];
-        s += a.dense[(size_t)6 * a.stride + i] * exp_nonpos(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
+        for (int c = 0; c < 6; ++c) q[c] = a.samples[(size_t)c * a.ns + sl];
+        s += a.samples[(size_t)6 * a.ns + sl] * exp_nonpos(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
     }
-    const double D = block_sum<256>(s, red);
+    const double D = block_sum<kSeedThreads>(s, red);
     if (tid == 0) {
         for (int c = 0; c < 6; ++c) o[c] = sd[c];
         o[6] = D;
@@ -307,51 +315,64 @@ __global__ void __launch_bounds__(256) k_pose_seed(SeedArgs a)
 }
 
 struct MsArgs {
-    const double *dense;
-    const double *info;
+    const double *samples;  // SoA [7][ns], block-compacted
+    const int *bcnt;        // [nb][2]
     const double *seed_score;
+    double *spill;          // [7][spill_stride] samples beyond the register capacity
     double *rel;            // relative poses [T][12]; T_t written at t-1
     double *Mcum;           // cumulative poses [T+1][12]; M_t written
     int *diag;              // [4]
     const int *status;
-    int stride, n_seeds, t, max_iters, fallback_prev_frame;
+    int ns, nb, n_seeds, t, max_iters, fallback_prev_frame, spill_stride;
     double is2t, is2r, tol;
 };
 
 constexpr int kMsThreads = 512;
-constexpr int kMsRegs = 8;   // samples held in registers per thread
+constexpr int kMsRegs = 16;                         // samples held in registers per thread
+constexpr int kMsRegCap = kMsThreads * kMsRegs;
 
-// Gaussian mean-shift from the densest start candidate, one workgroup;
-// samples beyond kMsThreads * kMsRegs are streamed from memory each iteration.
+// Sum of v[0..7] over the wave, transposed: on return every lane l holds the
+// wave total of component l >> 3.  Ten cross-lane exchanges instead of 48.
+__device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
+{
+    const bool h1 = lane & 32, h2 = lane & 16, h3 = lane & 8;
+    float a4[4], b2[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float send = h1 ? v[j] : v[j + 4], keep = h1 ? v[j + 4] : v[j];
+        a4[j] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float send = h2 ? a4[j] : a4[j + 2], keep = h2 ? a4[j + 2] : a4[j];
+        b2[j] = keep + __shfl_xor(send, 16, 64);
+    }
+    float x = (h3 ? b2[1] : b2[0]) + __shfl_xor(h3 ? b2[0] : b2[1], 8, 64);
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 1, 64);
+    return x;
+}
+
+// Gaussian mean-shift from the densest start candidate in one workgroup.
+// The samples are held as FP32 offsets from the current mean in whitened
+// coordinates (o_c = (p_c - m_c) s_c with s_c^2 = log2(e) / (2 sigma_c^2), so
+// that the kernel weight is 2^(-|o|^2)), re-centred after every step, and
+// their weights as log2 w; a running log2 density c2 keeps every weight in
+// FP32 range.  The mean itself is kept in FP64.  Every wave evaluates the
+// same totals, so the stop decision is uniform with one barrier per step.
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
-    __shared__ double red[kMsThreads / 64][8];
-    __shared__ double p[8];
-    __shared__ int s_stop;
+    __shared__ unsigned short idx[4 * kMaxGroups];
+    __shared__ int lcnt[kMaxPoseBlks], lpre[kMaxPoseBlks];
+    __shared__ int wsum[kMsThreads / 64];
+    __shared__ double dred[kMsThreads / 64];
+    __shared__ float red[2][64];
+    __shared__ double s_p0[8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int N = (int)a.info[0];
-    const double WS = a.info[1];
     double *Tt = a.rel + 12 * (a.t - 1);
-    if (N == 0 || !(WS > 0.0)) {
-        if (tid == 0) {
-            if (a.fallback_prev_frame)
-                for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
-            pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
-            a.diag[0] = N;
-            a.diag[1] = (int)a.info[2];
-            a.diag[2] = 0;
-            a.diag[3] = 1;
-        }
-        return;
-    }
-    double q[kMsRegs][7];
-#pragma unroll
-    for (int m = 0; m < kMsRegs; ++m) {
-        const int i = tid + m * kMsThreads;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) q[m][c] = i < N ? a.dense[(size_t)c * a.stride + i] : 0.0;
-    }
+
     // densest start candidate, earliest on ties (a workgroup arg-max)
     {
         double sc = -1.0;
@@ -365,79 +386,136 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
             const int io = __shfl_down(id, o, 64);
             if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
         }
-        if (lane == 0) { red[wv][0] = sc; red[wv][1] = (double)id; }
+        if (lane == 0) { dred[wv] = sc; wsum[wv] = id; }
         __syncthreads();
         if (tid == 0) {
             for (int w = 1; w < kMsThreads / 64; ++w) {
-                const double so = red[w][0];
-                const int io = (int)red[w][1];
+                const double so = dred[w];
+                const int io = wsum[w];
                 if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
             }
+            const bool have = id < kMsThreads;
+            for (int c = 0; c < 6; ++c) s_p0[c] = have ? a.seed_score[8 * id + c] : 0.0;
+            s_p0[6] = have ? sc : 0.0;
+        }
+        __syncthreads();
+    }
+    int N, groups;
+    dense_index<kMsThreads>(a.bcnt, a.nb, lcnt, lpre, wsum, idx, N, groups);
+    double p0[6], sc[6];
+    for (int c = 0; c < 6; ++c) {
+        p0[c] = s_p0[c];
+        sc[c] = sqrt(0.72134752044448170 * (c < 3 ? a.is2t : a.is2r));   // log2(e) / 2 / sigma^2
+    }
+    const double D0 = s_p0[6];
+    const int nreg = min(N, kMsRegCap);
+
+    float o[kMsRegs][6], lw[kMsRegs];
+    double wsl = 0.0;
+#pragma unroll
+    for (int m = 0; m < kMsRegs; ++m) {
+        const int i = tid + m * kMsThreads;
+        lw[m] = -INFINITY;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[m][c] = 0.0f;
+        if (i < nreg) {
+            const int sl = idx[i];
+#pragma unroll
             for (int c = 0; c < 6; ++c)
-                p[c] = id < kMsThreads ? a.seed_score[8 * id + c] : a.dense[(size_t)c * a.stride];
-            s_stop = 0;
+                o[m][c] = (float)((a.samples[(size_t)c * a.ns + sl] - p0[c]) * sc[c]);
+            const double w = a.samples[(size_t)6 * a.ns + sl];
+            wsl += w;
+            int e;
+            const double mt = frexp(w, &e);
+            lw[m] = (float)e + __builtin_amdgcn_logf((float)mt);
         }
     }
-    __syncthreads();
+    const int nsp = a.spill_stride;   // 4 S_max >= N
+    for (int i = kMsRegCap + tid; i < N; i += kMsThreads) {
+        const int sl = idx[i];
+        for (int c = 0; c < 6; ++c)
+            a.spill[(size_t)c * nsp + (i - kMsRegCap)] = (a.samples[(size_t)c * a.ns + sl] - p0[c]) * sc[c];
+        const double w = a.samples[(size_t)6 * a.ns + sl];
+        wsl += w;
+        a.spill[(size_t)6 * nsp + (i - kMsRegCap)] = log2(w);
+    }
+    const double WS = block_sum<kMsThreads>(wsl, dred);
+    if (N == 0 || !(WS > 0.0)) {
+        if (tid == 0) {
+            if (a.fallback_prev_frame)
+                for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
+            pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
+            a.diag[0] = N;
+            a.diag[1] = groups;
+            a.diag[2] = 0;
+            a.diag[3] = 1;
+        }
+        return;
+    }
+    // c2: log2 of the density at the current mean (starts at the candidate's)
+    float c2 = D0 > 0.0 ? (float)log2(D0) : 0.0f;
+    double cen[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // whitened mean - p0
+    const double tol2 = a.tol * a.tol * 0.72134752044448170;
     int it = 0;
-    for (; it < a.max_iters; ++it) {
-        double pc[6];
-        for (int c = 0; c < 6; ++c) pc[c] = p[c];
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (; it < a.max_iters && D0 > 0.0; ++it) {
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m = 0; m < kMsRegs; ++m) {
-            if (tid + m * kMsThreads < N) {
-                const double k = q[m][6] * exp_nonpos(-0.5 * mahal2(pc, q[m], a.is2t, a.is2r));
+            if (tid + m * kMsThreads < nreg) {
+                float q2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) q2 = fmaf(o[m][c], o[m][c], q2);
+                const float k = __builtin_amdgcn_exp2f(lw[m] - c2 - q2);
                 acc[6] += k;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) acc[c] += k * q[m][c];
+                for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, o[m][c], acc[c]);
             }
         }
-        for (int i = tid + kMsRegs * kMsThreads; i < N; i += kMsThreads) {
-            double qq[7];
-            for (int c = 0; c < 7; ++c) qq[c] = a.dense[(size_t)c * a.stride + i];
-            const double k = qq[6] * exp_nonpos(-0.5 * mahal2(pc, qq, a.is2t, a.is2r));
+        for (int i = kMsRegCap + tid; i < N; i += kMsThreads) {
+            float d[6], q2 = 0.0f;
+            for (int c = 0; c < 6; ++c) {
+                d[c] = (float)(a.spill[(size_t)c * nsp + (i - kMsRegCap)] - cen[c]);
+                q2 = fmaf(d[c], d[c], q2);
+            }
+            const float k = __builtin_amdgcn_exp2f((float)a.spill[(size_t)6 * nsp + (i - kMsRegCap)] - c2 - q2);
             acc[6] += k;
-            for (int c = 0; c < 6; ++c) acc[c] += k * qq[c];
+            for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, d[c], acc[c]);
         }
+        const float x = wave_sum8_t(acc, lane);
+        float *rb = red[it & 1];
+        if ((lane & 7) == 0) rb[8 * wv + (lane >> 3)] = x;
+        __syncthreads();
+        float y = rb[lane];   // wave lane >> 3, component lane & 7
+        y += __shfl_xor(y, 8, 64);
+        y += __shfl_xor(y, 16, 64);
+        y += __shfl_xor(y, 32, 64);
+        const double den = (double)__shfl(y, 6, 64);
+        if (!(den > 0.0)) break;
+        double step2 = 0.0;
+        float sf[6];
 #pragma unroll
-        for (int c = 0; c < 7; ++c)
-            for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_down(acc[c], off, 64);
-        if (lane == 0)
-            for (int c = 0; c < 7; ++c) red[wv][c] = acc[c];
-        __syncthreads();
-        if (tid < 7) {
-            double s = 0.0;
-            for (int w = 0; w < kMsThreads / 64; ++w) s += red[w][tid];
-            red[0][tid] = s;   // row 0 is read back only after the next barrier
+        for (int c = 0; c < 6; ++c) {
+            const double sh = (double)__shfl(y, c, 64) / den;
+            sf[c] = (float)sh;
+            cen[c] += (double)sf[c];
+            step2 += sh * sh;
         }
-        __syncthreads();
-        if (tid == 0) {
-            const double den = red[0][6];
-            if (!(den > 0.0)) {
-                s_stop = 2;
-            } else {
-                double np[6];
-                for (int c = 0; c < 6; ++c) np[c] = red[0][c] / den;
-                const double step = sqrt(mahal2(np, pc, a.is2t, a.is2r));
-                for (int c = 0; c < 6; ++c) p[c] = np[c];
-                s_stop = step < a.tol ? 1 : 0;
-            }
-        }
-        __syncthreads();
-        const int st = s_stop;
-        if (st == 2) break;
-        if (st == 1) { ++it; break; }
+        c2 += __builtin_amdgcn_logf((float)den);
+#pragma unroll
+        for (int m = 0; m < kMsRegs; ++m)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) o[m][c] -= sf[c];
+        if (step2 < tol2) { ++it; break; }
     }
     if (tid == 0) {
         double pp[6], R[9], tv[3];
-        for (int c = 0; c < 6; ++c) pp[c] = p[c];
+        for (int c = 0; c < 6; ++c) pp[c] = p0[c] + cen[c] / sc[c];
         se3_exp(pp, R, tv);
         for (int k = 0; k < 9; ++k) Tt[k] = R[k];
         for (int k = 0; k < 3; ++k) Tt[9 + k] = tv[k];
         pose_mul(Tt, a.Mcum + 12 * (a.t - 1), a.Mcum + 12 * a.t);
         a.diag[0] = N;
-        a.diag[1] = (int)a.info[2];
+        a.diag[1] = groups;
         a.diag[2] = it;
         a.diag[3] = 0;
     }
@@ -475,10 +553,13 @@ __global__ void k_cumulative(const double *rel, double *Mcum, int T)
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
                      const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
                      double *rel_poses, hipStream_t s)
 {
+    const int nb = (pp.S + kGrpPerBlk - 1) / kGrpPerBlk;
+    const int ns = kSlotsPerBlk * nb;
     GroupArgs g;
     g.theta = theta;
     g.rig = d.use_w ? rig : nullptr;
@@ -486,38 +567,40 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.Mprev = c->Mcum + 12 * (t - 1);
     g.samples = c->samples;
     g.gcnt = c->gcnt;
+    g.gpre = c->gpre;
+    g.bcnt = c->bcnt;
     g.status = c->status;
     g.d = d;
     g.S = pp.S;
-    g.ns = 4 * pp.S;
     g.t = t;
     g.it = it;
+    g.ns = ns;
     g.seed = pp.seed;
-    hipLaunchKernelGGL(k_pose_groups, dim3((pp.S + 63) / 64), dim3(64), 0, s, g);
-    int *diag = c->pose_diag + 4 * (t - 1);
-    const int stride = 4 * c->S_max;
-    CompactArgs ca{c->samples, c->gcnt, c->dense, c->pose_info, c->status, pp.S, 4 * pp.S, stride};
-    hipLaunchKernelGGL(k_pose_compact, dim3(1), dim3(kCompactThreads), 0, s, ca);
+    hipLaunchKernelGGL(k_pose_groups, dim3(nb), dim3(64), 0, s, g);
     SeedArgs sa;
-    sa.dense = c->dense;
-    sa.info = c->pose_info;
+    sa.samples = c->samples;
+    sa.bcnt = c->bcnt;
     sa.seed_score = c->seed_score;
     sa.prev = rel_poses + 12 * (t - 1);
     sa.status = c->status;
-    sa.stride = stride;
+    sa.ns = ns;
+    sa.nb = nb;
     sa.have_prev = have_prev;
     sa.is2t = 1.0 / pp.s2t;
     sa.is2r = 1.0 / pp.s2r;
-    hipLaunchKernelGGL(k_pose_seed, dim3(pp.n_seeds + 1), dim3(256), 0, s, sa);
+    hipLaunchKernelGGL(k_pose_seed, dim3(pp.n_seeds + 1), dim3(kSeedThreads), 0, s, sa);
     MsArgs m;
-    m.dense = c->dense;
-    m.info = c->pose_info;
+    m.samples = c->samples;
+    m.bcnt = c->bcnt;
     m.seed_score = c->seed_score;
+    m.spill = c->dense;
+    m.spill_stride = 4 * c->S_max;
     m.rel = rel_poses;
     m.Mcum = c->Mcum;
-    m.diag = diag;
+    m.diag = c->pose_diag + 4 * (t - 1);
     m.status = c->status;
-    m.stride = stride;
+    m.ns = ns;
+    m.nb = nb;
     m.n_seeds = pp.n_seeds;
     m.t = t;
     m.max_iters = pp.ms_max_iters;
@@ -531,9 +614,15 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
 
 int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s)
 {
-    const int ns = 4 * S;
-    hipLaunchKernelGGL(k_samples_aos, dim3((ns + 255) / 256), dim3(256), 0, s, c->samples, ns, out);
+    const int ns = kSlotsPerBlk * ((S + kGrpPerBlk - 1) / kGrpPerBlk);
+    hipLaunchKernelGGL(k_samples_aos, dim3((4 * S + 255) / 256), dim3(256), 0, s, c->samples, c->gcnt,
+                       c->gpre, S, ns, out);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+size_t pose_sample_slots(int S_max)
+{
+    return (size_t)kSlotsPerBlk * ((S_max + kGrpPerBlk - 1) / kGrpPerBlk);
 }
 
 int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s)

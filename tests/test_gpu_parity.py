@@ -130,6 +130,35 @@ def test_pose_step_parity(vo, torch):
         dif = np.abs(smp[both, :6] - osmp[both, :6]).max(axis=1)
         assert np.median(dif) < 1e-9 and np.mean(dif < 1e-6) > 0.98
         assert diag[0] == odiag[0] or abs(diag[0] - odiag[0]) <= 2
+        assert abs(diag[1] - odiag[1]) <= 2          # groups with a valid setup
+        assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-6
+        assert np.abs(Tg[9:] - To[9:]).max() < 1e-5
+
+
+def test_pose_step_many_groups(vo, torch):
+    # 8192 groups: more samples than the mean-shift holds in registers, so the
+    # streamed remainder is exercised; the ragged block of groups is the last one
+    T, H, W = 2, 64, 88
+    w, rel, M, gt = _world(37, T, H, W)
+    theta = gt.astype(np.float32)
+    rng = np.random.default_rng(4)
+    rig = rng.uniform(0.1, 1.0, (T, H, W)).astype(np.float32)
+    for S in (8192, 8181):
+        s = vo.Solver(T, H, W, 8192)
+        p = vo.default_params(n_pose_groups=S, seed=9)
+        Tg, smp, diag = s.pose_step(torch.from_numpy(theta).cuda(), torch.from_numpy(rig).cuda(),
+                                    torch.from_numpy(w["flows"]).cuda(), w["K"], p, M, 2, 1, prevT=rel[1],
+                                    want_samples=True)
+        To, osmp, odiag = oracle.pose_step(theta.astype(np.float64), rig.astype(np.float64), w["flows"], w["K"],
+                                           oracle.params(n_pose_groups=S, seed=9), M, 2, 1, prevT=rel[1],
+                                           want_samples=True)
+        assert odiag[0] > 8192 and odiag[3] == 0
+        assert abs(diag[0] - odiag[0]) <= 4 and abs(diag[1] - odiag[1]) <= 4
+        smp = smp.cpu().numpy()
+        both = (smp[:, 7] > 0) & (osmp[:, 7] > 0)
+        assert both.sum() >= odiag[0] - 4
+        dif = np.abs(smp[both, :6] - osmp[both, :6]).max(axis=1)
+        assert np.median(dif) < 1e-9
         assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-6
         assert np.abs(Tg[9:] - To[9:]).max() < 1e-5
 
