@@ -223,10 +223,12 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->hist, 3 * 256) == hipSuccess;
     ok = ok && dalloc(&c->sel, 16) == hipSuccess;
     ok = ok && dalloc(&c->ll_part, 2 * kLLBlocks) == hipSuccess;
-    ok = ok && dalloc(&c->dense, (size_t)7 * 4 * S_max) == hipSuccess;
+    ok = ok && dalloc(&c->sampf, (size_t)7 * pose_sample_slots(S_max)) == hipSuccess;
     ok = ok && dalloc(&c->gcnt, S_max) == hipSuccess;
     ok = ok && dalloc(&c->gpre, S_max) == hipSuccess;
     ok = ok && dalloc(&c->bcnt, 2 * (S_max / 16 + 1)) == hipSuccess;
+    ok = ok && dalloc(&c->bws, S_max / 16 + 1) == hipSuccess;
+    ok = ok && dalloc(&c->seed_part, (kMaxSeeds + 1) * pose_seed_parts()) == hipSuccess;
     ok = ok && dalloc(&c->prev_pose, 12) == hipSuccess;
     ok = ok && dalloc(&c->pose_tmp, 16) == hipSuccess;
     ok = ok && dalloc(&c->rel_tmp, 12 * T_max) == hipSuccess;
@@ -251,7 +253,7 @@ void voldor_destroy(voldor_ctx *c)
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->dkeys, c->hist,
-                    c->sel, c->ll_part, c->dense, c->gcnt, c->gpre, c->bcnt, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
+                    c->sel, c->ll_part, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(c);

@@ -45,7 +45,7 @@ struct voldor_ctx {
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
     int *status;           // [8]: status word, pose diagnostics scratch
     double *samples;       // SoA [7][slots] pose samples (p, weight), compacted per block of groups
-    double *seed_score;    // [kMaxSeeds + 1][8] (p, density, valid)
+    double *seed_score;    // [kMaxSeeds + 1][8] (p, unused, valid)
     int *pose_diag;        // [T_max][4]
     double *hyp;           // [kMaxHyp][18]: essential E (9), fundamental F (9)
     double *hyp_score;     // [kMaxHyp] median Sampson residual
@@ -54,10 +54,12 @@ struct voldor_ctx {
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
-    double *dense;         // [7][4 S_max] mean-shift samples beyond the register capacity
+    float *sampf;          // SoA [7][slots] whitened pose samples (FP32) for the mean-shift
     int *gcnt;             // [S_max] valid samples per group
     int *gpre;             // [S_max] first sample of each group inside its block
     int *bcnt;             // [S_max / 16 + 1][2] samples and valid groups per block
+    double *bws;           // [S_max / 16 + 1] weight sum per block
+    double *seed_part;     // [kMaxSeeds + 1][seed parts] partial densities of the start candidates
     double *prev_pose;     // [12] staging of a host-provided previous pose
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
@@ -90,6 +92,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
                      double *rel_poses, hipStream_t s);
 int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s);
 size_t pose_sample_slots(int S_max);
+size_t pose_seed_parts();
 int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s);
 int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
 

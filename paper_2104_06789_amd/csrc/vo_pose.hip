@@ -32,10 +32,13 @@ struct GroupArgs {
     int *gcnt;             // [S] samples of each group
     int *gpre;             // [S] first sample of each group inside its block
     int *bcnt;             // [nb][2] samples of each block, groups with a valid setup
+    double *bws;           // [nb] weight sum of each block's samples
+    float *sampf;          // SoA [7][ns]: whitened p (p_c s_c), log2 weight (FP32)
     const int *status;
     WinDims d;
     int S, t, it, ns;
     uint64_t seed;
+    double wt, wr;         // whitening scales s_c of translation and rotation
 };
 
 __device__ __forceinline__ bool flow_bilinear_d(const float2 *X, int H, int W, double px, double py,
@@ -162,14 +165,25 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
         a.gcnt[g] = __popcll((vm >> base) & 0xFull);
         a.gpre[g] = excl;
     }
+    double wv_sum = val ? w : 0.0;
+    for (int off = 32; off > 0; off >>= 1) wv_sum += __shfl_xor(wv_sum, off, 64);
     if (lane == 0) {
         a.bcnt[2 * blockIdx.x] = __popcll(vm);
         a.bcnt[2 * blockIdx.x + 1] = __popcll(gm);
+        a.bws[blockIdx.x] = wv_sum;
     }
     if (val) {
-        double *o = a.samples + (size_t)kSlotsPerBlk * blockIdx.x + excl + pos;
-        for (int c = 0; c < 6; ++c) o[(size_t)c * a.ns] = p[c];
+        const size_t sl = (size_t)kSlotsPerBlk * blockIdx.x + excl + pos;
+        double *o = a.samples + sl;
+        float *of = a.sampf + sl;
+        for (int c = 0; c < 6; ++c) {
+            o[(size_t)c * a.ns] = p[c];
+            of[(size_t)c * a.ns] = (float)(p[c] * (c < 3 ? a.wt : a.wr));
+        }
         o[(size_t)6 * a.ns] = w;
+        int e;
+        const double mt = frexp(w, &e);
+        of[(size_t)6 * a.ns] = (float)e + __builtin_amdgcn_logf((float)mt);   // log2 w
     }
 }
 
@@ -198,164 +212,195 @@ __device__ __forceinline__ double mahal2(const double *a, const double *b, doubl
     return (d0 * d0 + d1 * d1 + d2 * d2) * is2t + (d3 * d3 + d4 * d4 + d5 * d5) * is2r;
 }
 
-// Exclusive prefix of v over a workgroup of NT threads; *tot receives the sum.
-// wsum: NT / 64 ints of LDS.  Contains two barriers.
-template <int NT>
-__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &tot)
+__device__ __forceinline__ double wave_sum_d(double v)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = v;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
     for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += u;
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
     }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int b = 0;
-    tot = 0;
-    for (int w = 0; w < NT / 64; ++w) {
-        const int s = wsum[w];
-        b += w < wv ? s : 0;
-        tot += s;
-    }
-    __syncthreads();
-    return b + incl - v;
-}
-
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double *red)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int i = 0; i < NT / 64; ++i) s += red[i];
-    return s;
-}
-
-// Map of the dense sample order onto the block-compacted slots: idx[i] = slot
-// of the i-th valid sample in (group, root) order.  Reads bcnt [nb][2]; returns
-// N and the number of groups with a valid setup.  Contains barriers.
-template <int NT>
-__device__ __forceinline__ void dense_index(const int *bcnt, int nb, int *lcnt, int *lpre, int *wsum,
-                                           unsigned short *idx, int &N, int &groups)
-{
-    const int tid = threadIdx.x;
-    const int v = tid < nb ? bcnt[2 * tid] : 0;
-    const int gv = tid < nb ? bcnt[2 * tid + 1] : 0;
-    if (tid < nb) lcnt[tid] = v;
-    const int ex = block_excl_scan<NT>(v, wsum, N);
-    if (tid < nb) lpre[tid] = ex;
-    block_excl_scan<NT>(gv, wsum, groups);   // its barriers also publish lcnt / lpre
-    for (int s = tid; s < kSlotsPerBlk * nb; s += NT) {
-        const int b = s / kSlotsPerBlk, k = s % kSlotsPerBlk;
-        if (k < lcnt[b]) idx[lpre[b] + k] = (unsigned short)s;
-    }
-    __syncthreads();
+    return v;
 }
 
 struct SeedArgs {
     const double *samples; // SoA [7][ns], block-compacted
     const int *bcnt;       // [nb][2]
-    double *seed_score;    // [n_seeds + 1][8]: p, density, valid
+    double *seed_score;    // [n_seeds + 1][8]: p (6), unused, valid
+    double *seed_part;     // [n_seeds + 1][kSeedParts] partial densities
     const double *prev;    // previous relative pose T_t
     const int *status;
     int ns, nb, have_prev;
     double is2t, is2r;
 };
 
-constexpr int kSeedThreads = 512;
+constexpr int kSeedThreads = 256;
+constexpr int kSeedParts = 8;                                  // workgroups per candidate
+constexpr int kSeedWaves = kSeedParts * kSeedThreads / 64;     // waves sharing one candidate
+constexpr int kSeedBatch = 4;                                  // sample blocks in flight per wave
 
-// Density of one start candidate (block 0: the previous pose; block b: the
-// (b-1)-th sample in group order) over all samples, FP64 throughout.
+// Partial kernel density of one start candidate (candidate 0: the previous
+// pose; candidate k: the (k-1)-th sample in group order) over the sample
+// blocks b = w, w + 32, ... of wave w of the candidate's eight workgroups,
+// FP64 throughout.  The partials are added in a fixed order by the mean-shift.
 __global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
-    __shared__ unsigned short idx[4 * kMaxGroups];
-    __shared__ int lcnt[kMaxPoseBlks], lpre[kMaxPoseBlks];
-    __shared__ int wsum[kSeedThreads / 64];
+    __shared__ double seed[8];
     __shared__ double red[kSeedThreads / 64];
-    __shared__ double seed[6];
-    const int b = blockIdx.x, tid = threadIdx.x;
-    double *o = a.seed_score + 8 * b;
-    int N, groups;
-    dense_index<kSeedThreads>(a.bcnt, a.nb, lcnt, lpre, wsum, idx, N, groups);
-    if ((b == 0 && !a.have_prev) || (b > 0 && b - 1 >= N)) {
-        if (tid == 0) o[7] = 0.0;
-        return;
-    }
-    if (tid == 0) {
-        if (b == 0) {
-            double p[6];
-            se3_log(a.prev, a.prev + 9, p);
-            for (int c = 0; c < 6; ++c) seed[c] = p[c];
+    const int cand = blockIdx.x / kSeedParts, part = blockIdx.x % kSeedParts;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int gw = part * (kSeedThreads / 64) + wv;
+    const int nbw = a.nb > gw ? (a.nb - gw + kSeedWaves - 1) / kSeedWaves : 0;   // blocks of this wave
+    // first batch of this wave's samples, in flight while the candidate is found
+    double raw[kSeedBatch][7];
+    bool ok[kSeedBatch];
+    // the slots of a block are loaded whatever its count (they lie inside the
+    // buffer; unused ones are masked), so counts and samples travel together
+    auto load_batch = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < kSeedBatch; ++u) {
+            const int j = j0 + u;
+            const int b = gw + kSeedWaves * j;
+            const int cnt = j < nbw ? a.bcnt[2 * b] : 0;
+            ok[u] = lane < cnt;
+            const size_t sl = j < nbw ? (size_t)kSlotsPerBlk * b + lane : 0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) raw[u][c] = a.samples[(size_t)c * a.ns + sl];
+        }
+    };
+    load_batch(0);
+    if (tid < 64) {
+        if (cand == 0) {
+            if (tid == 0) {
+                seed[6] = a.have_prev ? 1.0 : 0.0;
+                if (a.have_prev) {
+                    double p[6];
+                    se3_log(a.prev, a.prev + 9, p);
+                    for (int c = 0; c < 6; ++c) seed[c] = p[c];
+                }
+            }
         } else {
-            const int sl = idx[b - 1];
-            for (int c = 0; c < 6; ++c) seed[c] = a.samples[(size_t)c * a.ns + sl];
+            // dense index cand - 1: scan the block counts 64 blocks at a time
+            const int target = cand - 1;
+            int base = 0;
+            bool found = false;
+            for (int q = 0; q * 64 < a.nb && !found; ++q) {
+                const int b = 64 * q + lane;
+                const int cnt = b < a.nb ? a.bcnt[2 * b] : 0;
+                const int incl = wave_incl_scan(cnt, lane);
+                const int tot = __shfl(incl, 63, 64);
+                if (target < base + tot) {
+                    found = true;
+                    const int ex = base + incl - cnt;
+                    if (ex <= target && target < ex + cnt) {
+                        const size_t sl = (size_t)kSlotsPerBlk * b + (target - ex);
+                        for (int c = 0; c < 6; ++c) seed[c] = a.samples[(size_t)c * a.ns + sl];
+                    }
+                }
+                base += tot;
+            }
+            if (lane == 0) seed[6] = found ? 1.0 : 0.0;
         }
     }
     __syncthreads();
+    if (seed[6] == 0.0) {
+        if (part == 0 && tid == 0) a.seed_score[8 * cand + 7] = 0.0;
+        return;
+    }
     double sd[6];
     for (int c = 0; c < 6; ++c) sd[c] = seed[c];
     double s = 0.0;
-    for (int i = tid; i < N; i += kSeedThreads) {
-        const int sl = idx[i];
-        double q[6];
-        for (int c = 0; c < 6; ++c) q[c] = a.samples[(size_t)c * a.ns + sl];
-        s += a.samples[(size_t)6 * a.ns + sl] * exp_nonpos(-0.5 * mahal2(sd, q, a.is2t, a.is2r));
+    for (int j0 = 0; j0 < nbw; j0 += kSeedBatch) {
+        if (j0 > 0) load_batch(j0);
+#pragma unroll
+        for (int u = 0; u < kSeedBatch; ++u)
+            if (ok[u]) s += raw[u][6] * exp_nonpos(-0.5 * mahal2(sd, raw[u], a.is2t, a.is2r));
     }
-    const double D = block_sum<kSeedThreads>(s, red);
+    s = wave_sum_d(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
     if (tid == 0) {
-        for (int c = 0; c < 6; ++c) o[c] = sd[c];
-        o[6] = D;
-        o[7] = 1.0;
+        double D = 0.0;
+        for (int w = 0; w < kSeedThreads / 64; ++w) D += red[w];
+        a.seed_part[kSeedParts * cand + part] = D;
+        if (part == 0) {
+            for (int c = 0; c < 6; ++c) a.seed_score[8 * cand + c] = sd[c];
+            a.seed_score[8 * cand + 7] = 1.0;
+        }
     }
 }
 
 struct MsArgs {
-    const double *samples;  // SoA [7][ns], block-compacted
+    const float *sampf;     // SoA [7][ns], block-compacted: whitened p, log2 weight
     const int *bcnt;        // [nb][2]
+    const double *bws;      // [nb] weight sum of each block's samples
     const double *seed_score;
-    double *spill;          // [7][spill_stride] samples beyond the register capacity
+    const double *seed_part;
     double *rel;            // relative poses [T][12]; T_t written at t-1
     double *Mcum;           // cumulative poses [T+1][12]; M_t written
     int *diag;              // [4]
     const int *status;
-    int ns, nb, n_seeds, t, max_iters, fallback_prev_frame, spill_stride;
-    double is2t, is2r, tol;
+    int ns, nb, n_seeds, t, max_iters, fallback_prev_frame;
+    double wt, wr, tol;     // whitening scales s_c, stop tolerance (Mahalanobis)
 };
 
 constexpr int kMsThreads = 512;
-constexpr int kMsRegs = 16;                         // samples held in registers per thread
-constexpr int kMsRegCap = kMsThreads * kMsRegs;
+constexpr int kMsWaves = kMsThreads / 64;
+constexpr int kMsRegs = 16;                         // samples held in registers per lane
+constexpr int kMsWaveCap = 64 * kMsRegs;            // register samples per wave
+constexpr int kMsListCap = kSlotsPerBlk * (kMaxPoseBlks / kMsWaves);   // samples per wave, at most
 
-// Sum of v[0..7] over the wave, transposed: on return every lane l holds the
-// wave total of component l >> 3.  Ten cross-lane exchanges instead of 48.
-__device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
+// Cross-lane sums without the LDS crossbar.  swap32_sum: lane l gets
+// a[l] + a[l + 32] in the lower half and b[l - 32] + b[l] in the upper half
+// (gfx950 lane-half swap); swap16_sum: the same between rows 2k and 2k + 1 of
+// 16 lanes; dpp: row-local permutations (ror:8 = xor 8, half-mirror, quad xor).
+__device__ __forceinline__ float swap32_sum(float a, float b)
 {
-    const bool h1 = lane & 32, h2 = lane & 16, h3 = lane & 8;
-    float a4[4], b2[2];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float send = h1 ? v[j] : v[j + 4], keep = h1 ? v[j + 4] : v[j];
-        a4[j] = keep + __shfl_xor(send, 32, 64);
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const float send = h2 ? a4[j] : a4[j + 2], keep = h2 ? a4[j + 2] : a4[j];
-        b2[j] = keep + __shfl_xor(send, 16, 64);
-    }
-    float x = (h3 ? b2[1] : b2[0]) + __shfl_xor(h3 ? b2[0] : b2[1], 8, 64);
-    x += __shfl_xor(x, 4, 64);
-    x += __shfl_xor(x, 2, 64);
-    x += __shfl_xor(x, 1, 64);
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+constexpr int kDppRowRor8 = 0x128, kDppHalfMirror = 0x141, kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+// sum over the 8 lanes of each aligned group of 8
+__device__ __forceinline__ float group8_sum(float x)
+{
+    x += dpp<kDppHalfMirror>(x);
+    x += dpp<kDppQuadXor1>(x);
+    x += dpp<kDppQuadXor2>(x);
     return x;
 }
 
+// Sum of v[0..7] over the wave, transposed: on return every lane l holds the
+// wave total of component l >> 3.  Seven exchanges instead of 48 shuffles.
+__device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
+{
+    float a4[4], b2[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a4[j] = swap32_sum(v[j], v[j + 4]);       // component 4 h1 + j
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b2[j] = swap16_sum(a4[j], a4[j + 2]);     // 4 h1 + 2 h2 + j
+    const bool h3 = lane & 8;
+    const float x = (h3 ? b2[1] : b2[0]) + dpp<kDppRowRor8>(h3 ? b2[0] : b2[1]);
+    return group8_sum(x);
+}
+
 // Gaussian mean-shift from the densest start candidate in one workgroup.
-// The samples are held as FP32 offsets from the current mean in whitened
+// Wave w owns the sample blocks b = w, w + 8, ...; it lists their samples in
+// LDS and holds them as FP32 offsets from the current mean in whitened
 // coordinates (o_c = (p_c - m_c) s_c with s_c^2 = log2(e) / (2 sigma_c^2), so
 // that the kernel weight is 2^(-|o|^2)), re-centred after every step, and
 // their weights as log2 w; a running log2 density c2 keeps every weight in
@@ -364,83 +409,74 @@ __device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
-    __shared__ unsigned short idx[4 * kMaxGroups];
-    __shared__ int lcnt[kMaxPoseBlks], lpre[kMaxPoseBlks];
-    __shared__ int wsum[kMsThreads / 64];
-    __shared__ double dred[kMsThreads / 64];
+    __shared__ unsigned short widx[kMsWaves][kMsListCap];
+    __shared__ double wbest[kMsWaves][8];   // p (6), density, id
+    __shared__ double wtot[kMsWaves][4];    // samples, valid groups, weight sum
     __shared__ float red[2][64];
-    __shared__ double s_p0[8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double *Tt = a.rel + 12 * (a.t - 1);
 
-    // densest start candidate, earliest on ties (a workgroup arg-max)
-    {
-        double sc = -1.0;
-        int id = kMsThreads;
-        if (tid <= a.n_seeds && a.seed_score[8 * tid + 7] != 0.0) {
-            sc = a.seed_score[8 * tid + 6];
+    // this wave's sample list (lane j: block wv + 8 j)
+    const int b = wv + kMsWaves * lane;
+    const bool hb = b < a.nb;
+    const int cnt = hb ? a.bcnt[2 * b] : 0;
+    const int gv = hb ? a.bcnt[2 * b + 1] : 0;
+    const double bw = hb ? a.bws[b] : 0.0;
+    // start candidates: lane-parallel densities (partials added in order)
+    double dens = -1.0;
+    double cp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int id = 1 << 30;
+    if (tid <= a.n_seeds) {   // all loads issued together, selected afterwards
+        double part[kSeedParts], cc[6];
+        for (int p = 0; p < kSeedParts; ++p) part[p] = a.seed_part[kSeedParts * tid + p];
+        for (int c = 0; c < 6; ++c) cc[c] = a.seed_score[8 * tid + c];
+        if (a.seed_score[8 * tid + 7] != 0.0) {
+            double D = 0.0;
+            for (int p = 0; p < kSeedParts; ++p) D += part[p];
+            dens = D;
             id = tid;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double so = __shfl_down(sc, o, 64);
-            const int io = __shfl_down(id, o, 64);
-            if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
-        }
-        if (lane == 0) { dred[wv] = sc; wsum[wv] = id; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < kMsThreads / 64; ++w) {
-                const double so = dred[w];
-                const int io = wsum[w];
-                if (so > sc || (so == sc && io < id)) { sc = so; id = io; }
-            }
-            const bool have = id < kMsThreads;
-            for (int c = 0; c < 6; ++c) s_p0[c] = have ? a.seed_score[8 * id + c] : 0.0;
-            s_p0[6] = have ? sc : 0.0;
-        }
-        __syncthreads();
-    }
-    int N, groups;
-    dense_index<kMsThreads>(a.bcnt, a.nb, lcnt, lpre, wsum, idx, N, groups);
-    double p0[6], sc[6];
-    for (int c = 0; c < 6; ++c) {
-        p0[c] = s_p0[c];
-        sc[c] = sqrt(0.72134752044448170 * (c < 3 ? a.is2t : a.is2r));   // log2(e) / 2 / sigma^2
-    }
-    const double D0 = s_p0[6];
-    const int nreg = min(N, kMsRegCap);
-
-    float o[kMsRegs][6], lw[kMsRegs];
-    double wsl = 0.0;
-#pragma unroll
-    for (int m = 0; m < kMsRegs; ++m) {
-        const int i = tid + m * kMsThreads;
-        lw[m] = -INFINITY;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) o[m][c] = 0.0f;
-        if (i < nreg) {
-            const int sl = idx[i];
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-                o[m][c] = (float)((a.samples[(size_t)c * a.ns + sl] - p0[c]) * sc[c]);
-            const double w = a.samples[(size_t)6 * a.ns + sl];
-            wsl += w;
-            int e;
-            const double mt = frexp(w, &e);
-            lw[m] = (float)e + __builtin_amdgcn_logf((float)mt);
+            for (int c = 0; c < 6; ++c) cp[c] = cc[c];
         }
     }
-    const int nsp = a.spill_stride;   // 4 S_max >= N
-    for (int i = kMsRegCap + tid; i < N; i += kMsThreads) {
-        const int sl = idx[i];
-        for (int c = 0; c < 6; ++c)
-            a.spill[(size_t)c * nsp + (i - kMsRegCap)] = (a.samples[(size_t)c * a.ns + sl] - p0[c]) * sc[c];
-        const double w = a.samples[(size_t)6 * a.ns + sl];
-        wsl += w;
-        a.spill[(size_t)6 * nsp + (i - kMsRegCap)] = log2(w);
+    const int incl = wave_incl_scan(cnt, lane);
+    const int Nw = __shfl(incl, 63, 64);
+    const int ex = incl - cnt;
+    const int nbw = a.nb > wv ? (a.nb - wv + kMsWaves - 1) / kMsWaves : 0;   // blocks of this wave
+    for (int j = 0; j < nbw; ++j) {
+        const int cj = __builtin_amdgcn_readlane(cnt, j), ej = __builtin_amdgcn_readlane(ex, j);
+        if (lane < cj) widx[wv][ej + lane] = (unsigned short)(kSlotsPerBlk * (wv + kMsWaves * j) + lane);
     }
-    const double WS = block_sum<kMsThreads>(wsl, dred);
-    if (N == 0 || !(WS > 0.0)) {
+    // wave arg-max of the candidates, earliest on ties
+    double bd = dens;
+    int bi = id;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double so = __shfl_xor(bd, o, 64);
+        const int io = __shfl_xor(bi, o, 64);
+        if (so > bd || (so == bd && io < bi)) { bd = so; bi = io; }
+    }
+    const int gsum = wave_incl_scan(gv, lane);
+    const double wsum = wave_sum_d(bw);
+    if (id == bi && bi < (1 << 30))
+        for (int c = 0; c < 6; ++c) wbest[wv][c] = cp[c];
+    if (lane == 0) {
+        wbest[wv][6] = bd;
+        wbest[wv][7] = (double)bi;
+        wtot[wv][0] = (double)Nw;
+        wtot[wv][2] = wsum;
+    }
+    if (lane == 63) wtot[wv][1] = (double)gsum;
+    __syncthreads();
+    // workgroup totals and the densest candidate (every thread, same order)
+    int N = 0, groups = 0, bw_ = 0;
+    double WS = 0.0, D0 = -1.0, bid = (double)(1 << 30);
+    for (int w = 0; w < kMsWaves; ++w) {
+        N += (int)wtot[w][0];
+        groups += (int)wtot[w][1];
+        WS += wtot[w][2];
+        const double so = wbest[w][6], io = wbest[w][7];
+        if (so > D0 || (so == D0 && io < bid)) { D0 = so; bid = io; bw_ = w; }
+    }
+    if (N == 0 || !(WS > 0.0) || !(bid < (double)(1 << 30))) {
         if (tid == 0) {
             if (a.fallback_prev_frame)
                 for (int k = 0; k < 12; ++k) Tt[k] = a.rel[12 * (a.t - 2) + k];
@@ -452,16 +488,40 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         }
         return;
     }
+    // start: the candidate in whitened coordinates, rounded to FP32 (the
+    // register frame is centred on that exactly representable point)
+    double sc[6], P0[6];
+    for (int c = 0; c < 6; ++c) {
+        sc[c] = c < 3 ? a.wt : a.wr;
+        P0[c] = (double)(float)(wbest[bw_][c] * sc[c]);
+    }
+    const int nreg = min(Nw, kMsWaveCap);
+
+    float o[kMsRegs][6], lw[kMsRegs];
+    // register samples: every load in flight at once, straight into place
+#pragma unroll
+    for (int m = 0; m < kMsRegs; ++m) {
+        const int i = lane + 64 * m;
+        const bool in = i < nreg;
+        const int sl = in ? widx[wv][i] : 0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[m][c] = in ? a.sampf[(size_t)c * a.ns + sl] : 0.0f;
+        lw[m] = in ? a.sampf[(size_t)6 * a.ns + sl] : -INFINITY;
+    }
+#pragma unroll
+    for (int m = 0; m < kMsRegs; ++m)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[m][c] -= (float)P0[c];
     // c2: log2 of the density at the current mean (starts at the candidate's)
     float c2 = D0 > 0.0 ? (float)log2(D0) : 0.0f;
-    double cen[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // whitened mean - p0
+    double cen[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // whitened mean - P0
     const double tol2 = a.tol * a.tol * 0.72134752044448170;
     int it = 0;
     for (; it < a.max_iters && D0 > 0.0; ++it) {
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m = 0; m < kMsRegs; ++m) {
-            if (tid + m * kMsThreads < nreg) {
+            if (lane + 64 * m < nreg) {
                 float q2 = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) q2 = fmaf(o[m][c], o[m][c], q2);
@@ -471,31 +531,39 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
                 for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, o[m][c], acc[c]);
             }
         }
-        for (int i = kMsRegCap + tid; i < N; i += kMsThreads) {
-            float d[6], q2 = 0.0f;
+        if (Nw > kMsWaveCap) {
+            // the rest from memory, centred by a two-float split of the mean
+            float chi[6], clo[6];
             for (int c = 0; c < 6; ++c) {
-                d[c] = (float)(a.spill[(size_t)c * nsp + (i - kMsRegCap)] - cen[c]);
-                q2 = fmaf(d[c], d[c], q2);
+                const double C = P0[c] + cen[c];
+                chi[c] = (float)C;
+                clo[c] = (float)(C - (double)chi[c]);
             }
-            const float k = __builtin_amdgcn_exp2f((float)a.spill[(size_t)6 * nsp + (i - kMsRegCap)] - c2 - q2);
-            acc[6] += k;
-            for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, d[c], acc[c]);
+            for (int i = kMsWaveCap + lane; i < Nw; i += 64) {
+                const int sl = widx[wv][i];
+                float d[6], q2 = 0.0f;
+                for (int c = 0; c < 6; ++c) {
+                    d[c] = (a.sampf[(size_t)c * a.ns + sl] - chi[c]) - clo[c];
+                    q2 = fmaf(d[c], d[c], q2);
+                }
+                const float k = __builtin_amdgcn_exp2f(a.sampf[(size_t)6 * a.ns + sl] - c2 - q2);
+                acc[6] += k;
+                for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, d[c], acc[c]);
+            }
         }
         const float x = wave_sum8_t(acc, lane);
         float *rb = red[it & 1];
-        if ((lane & 7) == 0) rb[8 * wv + (lane >> 3)] = x;
+        if ((lane & 7) == 0) rb[8 * (lane >> 3) + wv] = x;   // [component][wave]
         __syncthreads();
-        float y = rb[lane];   // wave lane >> 3, component lane & 7
-        y += __shfl_xor(y, 8, 64);
-        y += __shfl_xor(y, 16, 64);
-        y += __shfl_xor(y, 32, 64);
-        const double den = (double)__shfl(y, 6, 64);
+        const float y = group8_sum(rb[lane]);   // lanes 8c .. 8c + 7: total of component c
+        const double den = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 48));
         if (!(den > 0.0)) break;
+        const double iden = 1.0 / den;
         double step2 = 0.0;
         float sf[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const double sh = (double)__shfl(y, c, 64) / den;
+            const double sh = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 8 * c)) * iden;
             sf[c] = (float)sh;
             cen[c] += (double)sf[c];
             step2 += sh * sh;
@@ -503,13 +571,14 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         c2 += __builtin_amdgcn_logf((float)den);
 #pragma unroll
         for (int m = 0; m < kMsRegs; ++m)
+            if (lane + 64 * m < nreg)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) o[m][c] -= sf[c];
+                for (int c = 0; c < 6; ++c) o[m][c] -= sf[c];
         if (step2 < tol2) { ++it; break; }
     }
     if (tid == 0) {
         double pp[6], R[9], tv[3];
-        for (int c = 0; c < 6; ++c) pp[c] = p0[c] + cen[c] / sc[c];
+        for (int c = 0; c < 6; ++c) pp[c] = (P0[c] + cen[c]) / sc[c];
         se3_exp(pp, R, tv);
         for (int k = 0; k < 9; ++k) Tt[k] = R[k];
         for (int k = 0; k < 3; ++k) Tt[9 + k] = tv[k];
@@ -569,6 +638,10 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.gcnt = c->gcnt;
     g.gpre = c->gpre;
     g.bcnt = c->bcnt;
+    g.bws = c->bws;
+    g.sampf = c->sampf;
+    g.wt = sqrt(0.72134752044448170 / pp.s2t);   // s_c^2 = log2(e) / (2 sigma_c^2)
+    g.wr = sqrt(0.72134752044448170 / pp.s2r);
     g.status = c->status;
     g.d = d;
     g.S = pp.S;
@@ -581,6 +654,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     sa.samples = c->samples;
     sa.bcnt = c->bcnt;
     sa.seed_score = c->seed_score;
+    sa.seed_part = c->seed_part;
     sa.prev = rel_poses + 12 * (t - 1);
     sa.status = c->status;
     sa.ns = ns;
@@ -588,13 +662,13 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     sa.have_prev = have_prev;
     sa.is2t = 1.0 / pp.s2t;
     sa.is2r = 1.0 / pp.s2r;
-    hipLaunchKernelGGL(k_pose_seed, dim3(pp.n_seeds + 1), dim3(kSeedThreads), 0, s, sa);
+    hipLaunchKernelGGL(k_pose_seed, dim3((pp.n_seeds + 1) * kSeedParts), dim3(kSeedThreads), 0, s, sa);
     MsArgs m;
-    m.samples = c->samples;
+    m.sampf = c->sampf;
     m.bcnt = c->bcnt;
+    m.bws = c->bws;
     m.seed_score = c->seed_score;
-    m.spill = c->dense;
-    m.spill_stride = 4 * c->S_max;
+    m.seed_part = c->seed_part;
     m.rel = rel_poses;
     m.Mcum = c->Mcum;
     m.diag = c->pose_diag + 4 * (t - 1);
@@ -605,8 +679,8 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.t = t;
     m.max_iters = pp.ms_max_iters;
     m.fallback_prev_frame = (!have_prev && t >= 2) ? 1 : 0;
-    m.is2t = 1.0 / pp.s2t;
-    m.is2r = 1.0 / pp.s2r;
+    m.wt = g.wt;
+    m.wr = g.wr;
     m.tol = pp.ms_tol;
     hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
@@ -619,6 +693,8 @@ int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s)
                        c->gpre, S, ns, out);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
+
+size_t pose_seed_parts() { return kSeedParts; }
 
 size_t pose_sample_slots(int S_max)
 {
