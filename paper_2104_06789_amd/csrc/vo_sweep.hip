@@ -38,6 +38,13 @@ __device__ __forceinline__ int chain_pixel(int dir, int H, int W, int c, int k)
     }
 }
 
+// pixel coordinates of chain position k (no integer division)
+__device__ __forceinline__ void chain_xy(int dir, int H, int W, int c, int k, int &x, int &y)
+{
+    x = (dir & 1) ? c : (dir == 0 ? k : W - 1 - k);
+    y = (dir & 1) ? (dir == 1 ? k : H - 1 - k) : c;
+}
+
 // log(mu/rho) of depth th at pixel (x, y) for frame t; false if missing
 __device__ __forceinline__ bool item_log_odds(const FrameF *fr, const float2 *__restrict__ flows,
                                               int H, int W, const EmisParams &e, int x, int y,
@@ -64,7 +71,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     float s = 0.0f;
     float pdx = 0.0f, pdy = 0.0f;
     bool pok = th > 0.0f;
-    const size_t HW = (size_t)H * W;
+    const int HW = H * W;   // T H W < 2^31 (frames <= 16, sides <= 4096)
     for (int t0 = 1; t0 <= T; t0 += 4) {
         float dx[4], dy[4];
         bool ok[4];
@@ -92,7 +99,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             ax[u] = spx - (float)x0;
             ay[u] = spy - (float)y0;
             const int tf = val[u] ? t0 + u - 1 : 0;
-            const float2 *r0 = flows + (size_t)tf * HW + (size_t)y0 * W + x0;
+            const float2 *r0 = flows + (tf * HW + y0 * W + x0);
             ta[u] = r0[0];
             tb[u] = r0[1];
             tc[u] = r0[W];
@@ -130,7 +137,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
                                                const float *th, const int *t, const bool *act, float *d,
                                                bool *ok)
 {
-    const size_t HW = (size_t)H * W;
+    const int HW = H * W;
     float dx0[B], dy0[B], dx1[B], dy1[B], ax[B], ay[B];
     float2 ta[B], tb[B], tc[B], td[B];
 #pragma unroll
@@ -149,7 +156,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
         ax[b] = spx - (float)x0;
         ay[b] = spy - (float)y0;
-        const float2 *r0 = flows + (size_t)(v ? tt - 1 : 0) * HW + (size_t)y0 * W + x0;
+        const float2 *r0 = flows + ((v ? tt - 1 : 0) * HW + y0 * W + x0);
         ta[b] = r0[0];
         tb[b] = r0[1];
         tc[b] = r0[W];
@@ -275,16 +282,17 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         int xs[4], ys[4], ts[4];
         float ths[4], dd[4];
         bool act[4], ok[4];
+        // item i = (t - 1) L + k; the thread's items are kSweepThreads apart
+        int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = i0 + b * kSweepThreads;
-            act[b] = i < T * L;
-            const int t = act[b] ? i / L + 1 : 1, k = act[b] ? i - (t - 1) * L : 0;
-            const int j = chain_pixel(dir, H, W, chain, k);
-            xs[b] = j % W;
-            ys[b] = j / W;
-            ts[b] = t;
-            ths[b] = th[k];
+            act[b] = i0 + b * kSweepThreads < T * L;
+            const int kk = act[b] ? k : 0;
+            chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
+            ts[b] = act[b] ? t : 1;
+            ths[b] = th[kk];
+            k += kSweepThreads;
+            while (k >= L) { k -= L; ++t; }
         }
         batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
@@ -398,16 +406,17 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         int xs[4], ys[4], ts[4];
         float ths[4], dd[4];
         bool act[4], ok[4];
+        // item i = (t - 1) L + k; the thread's items are kSweepThreads apart
+        int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = i0 + b * kSweepThreads;
-            act[b] = i < T * L;
-            const int t = act[b] ? i / L + 1 : 1, k = act[b] ? i - (t - 1) * L : 0;
-            const int j = chain_pixel(dir, H, W, chain, k);
-            xs[b] = j % W;
-            ys[b] = j / W;
-            ts[b] = t;
-            ths[b] = sm[k];
+            act[b] = i0 + b * kSweepThreads < T * L;
+            const int kk = act[b] ? k : 0;
+            chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
+            ts[b] = act[b] ? t : 1;
+            ths[b] = sm[kk];
+            k += kSweepThreads;
+            while (k >= L) { k -= L; ++t; }
         }
         batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
@@ -449,13 +458,14 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         if (la > 64) la = 64;
         const int items = n * la;
         for (int i = tid; i < items; i += kSweepThreads) {
-            const int sl = i / la, p = i - sl * la;
+            // i / la through FP32: (i + 1/2) / la is at least 1/(2 la) from an integer
+            const int sl = (int)(((float)i + 0.5f) * frcp((float)la)), p = i - sl * la;
             const int2 e = lc[sl];
             const int jpos = e.y + p;
             int w = 0;
             if (jpos < L) {
-                const int j = chain_pixel(dir, H, W, chain, jpos);
-                const int x = j % W, y = j / W;
+                int x, y;
+                chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
                 const float s = chain_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
