@@ -264,6 +264,10 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
     float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
 
     for (int i = tid; i < (T + 1) * 12; i += kSweepThreads) ((float *)fr)[i] = ((const float *)a.frames)[i];
+    if (tid == 0) {
+        s_cnt[0] = 0;
+        s_cnt[1] = 0;
+    }
     const float llo = (float)log(a.range[0]);
     const float lrange = (float)(log(a.range[1]) - log(a.range[0]));
     for (int k = tid; k < L; k += kSweepThreads) {
@@ -434,16 +438,21 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         if (smp) sa[k] = s;
         flg[k] = smp ? 1 : 0;
     }
-    if (tid == 0) {
-        s_cnt[0] = L - 1;
-        s_cnt[1] = 0;
-    }
-    // live origins (origin, next position to test): every k < L-1 starts at k+1
+    __syncthreads();   // the live lists below reuse the sample's ell area
+    // live origins (origin, next position to test), starting at k+1; a local
+    // best equal to the previous depth at k+1 scores exactly that depth there
+    // and loses (the previous depth wins ties), so next(k) = k+1 at once
     int2 *list0 = (int2 *)lq, *list1 = list0 + L;
     int *win = (int *)(list1 + L);
     for (int k = tid; k < L; k += kSweepThreads) {
-        if (k < L - 1) list0[k] = make_int2(k, k + 1);
-        else nxt[k] = L;
+        if (k == L - 1) {
+            nxt[k] = L;
+        } else if (aval[k] == th[k + 1]) {
+            nxt[k] = k + 1;
+        } else {
+            const int at = atomicAdd(&s_cnt[0], 1);
+            list0[at] = make_int2(k, k + 1);
+        }
     }
     __syncthreads();
 
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
             const int2 e = lc[sl];
             const int jpos = e.y + p;
             int w = 0;
-            if (jpos < L) {
+            if (jpos < L && !(aval[e.x] == th[jpos])) {   // equal to the previous depth: loses
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
