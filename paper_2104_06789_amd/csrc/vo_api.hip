@@ -219,6 +219,8 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->hyp, (size_t)18 * kMaxHyp) == hipSuccess;
     ok = ok && dalloc(&c->hyp_score, kMaxHyp) == hipSuccess;
     ok = ok && dalloc(&c->boot_info, 4) == hipSuccess;
+    ok = ok && dalloc(&c->boot_cand, 24) == hipSuccess;
+    ok = ok && dalloc(&c->boot_sub, (size_t)kEvalThreads * kEvalPerThread) == hipSuccess;
     ok = ok && dalloc(&c->dkeys, HW) == hipSuccess;
     ok = ok && dalloc(&c->hist, 3 * 256) == hipSuccess;
     ok = ok && dalloc(&c->sel, 16) == hipSuccess;
@@ -252,7 +254,7 @@ void voldor_destroy(voldor_ctx *c)
     if (!c) return;
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
-                    c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->dkeys, c->hist,
+                    c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->boot_cand, c->boot_sub, c->dkeys, c->hist,
                     c->sel, c->ll_part, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

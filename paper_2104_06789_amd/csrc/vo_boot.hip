@@ -99,13 +99,27 @@ struct HypArgs {
     const float2 *X1;
     double *hyp;
     double *score;
-    int H, W, M;
+    float4 *sub;        // [Ne] scoring subset: x, y, X_1(x) (NaN flow if missing)
+    int H, W, M, Ne;
     double fx, fy, cx, cy;
     uint64_t seed;
 };
 
 __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
 {
+    const int nhb = (a.M + 63) / 64;
+    if ((int)blockIdx.x >= nhb) {
+        // trailing blocks: the pixel subset j_i = floor(i HW / Ne) of the median
+        const int i = (blockIdx.x - nhb) * 64 + threadIdx.x;
+        if (i < a.Ne) {
+            const int j = (int)(((int64_t)i * ((int64_t)a.H * a.W)) / a.Ne);
+            const int y = j / a.W, x = j - y * a.W;
+            float2 f = a.X1[j];
+            if (!(isfinite(f.x) && isfinite(f.y))) f.x = f.y = __int_as_float(0x7fc00000);
+            a.sub[i] = make_float4((float)x, (float)y, f.x, f.y);
+        }
+        return;
+    }
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= a.M) return;
     const int64_t HW = (int64_t)a.H * a.W;
@@ -115,10 +129,12 @@ __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
         uint64_t c[4] = {(uint64_t)h, (uint64_t)att, 0ull, 0ull};
         philox4x64_10(c, a.seed, kBootStream);
         ok = true;
+#pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t u = (k & 1) ? (uint32_t)(c[k >> 1] >> 32) : (uint32_t)c[k >> 1];
             idx[k] = u32_to_index(u, HW);
             ok = ok && flow_present(a.X1, idx[k]);
+#pragma unroll
             for (int m = 0; m < k; ++m) ok = ok && idx[m] != idx[k];
         }
     }
@@ -130,35 +146,64 @@ __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
     }
     // epipolar rows: b^T E a = 0 with a = K^-1 x, b = K^-1 (x + X_1(x))
     double A[8][9];
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int x = (int)(idx[k] % a.W), y = (int)(idx[k] / a.W);
+        const int jk = (int)idx[k], y = jk / a.W, x = jk - y * a.W;
         const float2 f = a.X1[idx[k]];
         const double av[3] = {(x - a.cx) / a.fx, (y - a.cy) / a.fy, 1.0};
         const double bv[3] = {(x + (double)f.x - a.cx) / a.fx, (y + (double)f.y - a.cy) / a.fy, 1.0};
         for (int i = 0; i < 3; ++i)
             for (int l = 0; l < 3; ++l) A[k][3 * i + l] = bv[i] * av[l];
     }
-    // null vector by Gaussian elimination with full pivoting
+    // null vector by Gaussian elimination with full pivoting; every index is
+    // static (row and column exchanges by selects) so the system stays in
+    // registers
     int perm[9];
+#pragma unroll
     for (int i = 0; i < 9; ++i) perm[i] = i;
     bool degenerate = false;
+#pragma unroll
     for (int r = 0; r < 8; ++r) {
         int pr = r, pc = r;
         double best = 0.0;
+#pragma unroll
         for (int i = r; i < 8; ++i)
+#pragma unroll
             for (int j = r; j < 9; ++j) {
                 const double v = fabs(A[i][j]);
-                if (v > best) { best = v; pr = i; pc = j; }
+                const bool gt = v > best;
+                best = gt ? v : best;
+                pr = gt ? i : pr;
+                pc = gt ? j : pc;
             }
-        if (best == 0.0) { degenerate = true; break; }
-        if (pr != r)
-            for (int j = 0; j < 9; ++j) { const double t = A[r][j]; A[r][j] = A[pr][j]; A[pr][j] = t; }
-        if (pc != r) {
-            for (int i = 0; i < 8; ++i) { const double t = A[i][r]; A[i][r] = A[i][pc]; A[i][pc] = t; }
-            const int t = perm[r]; perm[r] = perm[pc]; perm[pc] = t;
+        degenerate = degenerate || best == 0.0;
+#pragma unroll
+        for (int i = r + 1; i < 8; ++i) {
+            const bool sw = pr == i;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const double x = A[r][j], y = A[i][j];
+                A[r][j] = sw ? y : x;
+                A[i][j] = sw ? x : y;
+            }
         }
+#pragma unroll
+        for (int j = r + 1; j < 9; ++j) {
+            const bool sw = pc == j;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double x = A[i][r], y = A[i][j];
+                A[i][r] = sw ? y : x;
+                A[i][j] = sw ? x : y;
+            }
+            const int x = perm[r], y = perm[j];
+            perm[r] = sw ? y : x;
+            perm[j] = sw ? x : y;
+        }
+#pragma unroll
         for (int i = r + 1; i < 8; ++i) {
             const double f = A[i][r] / A[r][r];
+#pragma unroll
             for (int j = r; j < 9; ++j) A[i][j] -= f * A[r][j];
         }
     }
@@ -168,13 +213,21 @@ __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
     }
     double xp[9];
     xp[8] = 1.0;
+#pragma unroll
     for (int r = 7; r >= 0; --r) {
         double s = 0.0;
+#pragma unroll
         for (int j = r + 1; j < 9; ++j) s += A[r][j] * xp[j];
         xp[r] = -s / A[r][r];
     }
     double e[9], nrm = 0.0;
-    for (int j = 0; j < 9; ++j) e[perm[j]] = xp[j];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v = perm[j] == q ? xp[j] : v;
+        e[q] = v;
+    }
     for (int j = 0; j < 9; ++j) nrm += e[j] * e[j];
     nrm = sqrt(nrm);
     for (int j = 0; j < 9; ++j) e[j] /= nrm;
@@ -224,37 +277,52 @@ __device__ __forceinline__ void select_bin(uint32_t h, uint32_t rank, uint32_t *
 }
 
 struct ScoreArgs {
-    const float2 *X1;
+    const float4 *sub;
     const double *hyp;
     double *score;
-    int H, W, Ne;
+    int Ne;
 };
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, o, 64), hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lower median of the Sampson distances of one hypothesis over the fixed
+// pixel subset, exactly: the distances are held as order-preserving 64-bit
+// keys (non-negative FP64 bit patterns), 32 per thread.  The bits shared by
+// the smallest and the largest key are skipped; radix passes below them
+// narrow the median's bucket until it holds at most one key per thread, and
+// those candidates are ranked against each other directly.  Wide digits keep
+// the lanes of one atomic on distinct histogram bins.
+constexpr int kEvalCand = kEvalThreads;
+constexpr int kDigitBits = 12;   // 4096 bins = 8 per thread
 
 __global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
 {
-    __shared__ uint32_t hist[256];
+    __shared__ uint32_t hist[1 << kDigitBits];
     __shared__ int cnt_red[kEvalThreads / 64];
-    __shared__ uint64_t s_prefix;
-    __shared__ int s_rank;
-    __shared__ uint32_t s_wtot[4], s_bin, s_rib;
-    const int h = blockIdx.x, tid = threadIdx.x;
+    __shared__ uint64_t kmin_red[kEvalThreads / 64], kmax_red[kEvalThreads / 64];
+    __shared__ uint64_t cand[kEvalCand];
+    __shared__ uint32_t s_wtot[kEvalThreads / 64], s_bin, s_rib, s_inb, s_nc;
+    const int h = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double *hp = a.hyp + 18 * h;
     if (isnan(hp[0])) return;  // invalid hypothesis keeps +inf
     double F[9];
     for (int i = 0; i < 9; ++i) F[i] = hp[9 + i];
-    const int64_t HW = (int64_t)a.H * a.W;
     uint64_t key[kEvalPerThread];
-    int n = 0;
+    uint32_t valid = 0;
+    uint64_t kmin = ~0ull, kmax = 0;
 #pragma unroll
     for (int m = 0; m < kEvalPerThread; ++m) {
         const int i = tid + m * kEvalThreads;
-        uint64_t kk = ~0ull;
+        uint64_t kk = 0;
         if (i < a.Ne) {
-            const int64_t j = ((int64_t)i * HW) / a.Ne;
-            const float2 f = a.X1[j];
-            if (isfinite(f.x) && isfinite(f.y)) {
-                const double x = (double)(j % a.W), y = (double)(j / a.W);
-                const double x2 = x + f.x, y2 = y + f.y;
+            const float4 sp = a.sub[i];
+            if (isfinite(sp.z) && isfinite(sp.w)) {
+                const double x = (double)sp.x, y = (double)sp.y;
+                const double x2 = x + sp.z, y2 = y + sp.w;
                 const double Fx0 = F[0] * x + F[1] * y + F[2];
                 const double Fx1 = F[3] * x + F[4] * y + F[5];
                 const double Fx2 = F[6] * x + F[7] * y + F[8];
@@ -263,59 +331,129 @@ __global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
                 const double e = x2 * Fx0 + y2 * Fx1 + Fx2;
                 const double r = e * e / (Fx0 * Fx0 + Fx1 * Fx1 + Ft0 * Ft0 + Ft1 * Ft1);
                 kk = (uint64_t)__double_as_longlong(r);
-                ++n;
+                valid |= 1u << m;
+                kmin = kk < kmin ? kk : kmin;
+                kmax = kk > kmax ? kk : kmax;
             }
         }
         key[m] = kk;
     }
-    // count of present pixels in the subset
-    int c = n;
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((tid & 63) == 0) cnt_red[tid >> 6] = c;
-    __syncthreads();
-    if (tid == 0) {
-        int tot = 0;
-        for (int i = 0; i < kEvalThreads / 64; ++i) tot += cnt_red[i];
-        s_rank = tot > 0 ? (tot - 1) / 2 : -1;
-        s_prefix = 0;
+    // present pixels and the key range over the workgroup
+    int c = __popc(valid);
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        const uint64_t mn = shfl_xor_u64(kmin, o), mx = shfl_xor_u64(kmax, o);
+        kmin = mn < kmin ? mn : kmin;
+        kmax = mx > kmax ? mx : kmax;
     }
+    if (lane == 0) {
+        cnt_red[wv] = c;
+        kmin_red[wv] = kmin;
+        kmax_red[wv] = kmax;
+    }
+    if (tid == 0) s_nc = 0;
     __syncthreads();
-    if (s_rank < 0) return;  // no usable pixel: the hypothesis keeps +inf
-    uint64_t mask = 0;
-    for (int pass = 7; pass >= 0; --pass) {
-        const int shift = 8 * pass;
-        for (int b = tid; b < 256; b += kEvalThreads) hist[b] = 0;
-        __syncthreads();
-        const uint64_t pre = s_prefix;
+    int tot = 0;
+    for (int w = 0; w < kEvalThreads / 64; ++w) {
+        tot += cnt_red[w];
+        kmin = kmin_red[w] < kmin ? kmin_red[w] : kmin;
+        kmax = kmax_red[w] > kmax ? kmax_red[w] : kmax;
+    }
+    if (tot == 0) return;  // no usable pixel: the hypothesis keeps +inf
+    uint32_t rank = (uint32_t)((tot - 1) / 2);
+    uint64_t prefix = kmin;
+    if (kmin != kmax) {
+        // bits below the common prefix of all keys
+        int shift = 64 - __clzll((long long)(kmin ^ kmax));   // number of varying low bits
+        prefix = (kmin >> shift) << shift;
+        uint32_t inbin = (uint32_t)tot;
+        while (shift > 0 && inbin > (uint32_t)kEvalCand) {
+            const int ds = shift > kDigitBits ? shift - kDigitBits : 0;   // digit = bits [ds, shift)
+            const int nbin = 1 << (shift - ds);
+            for (int q = tid; q < nbin; q += kEvalThreads) hist[q] = 0;
+            __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kEvalPerThread; ++m)
-            if ((key[m] & mask) == pre) atomicAdd(&hist[(key[m] >> shift) & 255], 1u);
-        __syncthreads();
-        if (tid == 0) s_bin = 255;
-        const uint32_t hb = tid < 256 ? hist[tid] : 0u;
-        const uint32_t rank = (uint32_t)s_rank;
-        __syncthreads();
-        select_bin(hb, rank, s_wtot, &s_bin, &s_rib);
-        if (tid == 0) {
-            s_rank = (int)s_rib;
-            s_prefix = pre | ((uint64_t)s_bin << shift);
+            for (int m = 0; m < kEvalPerThread; ++m)
+                if (((valid >> m) & 1u) && (key[m] >> shift) == (prefix >> shift))
+                    atomicAdd(&hist[(uint32_t)(key[m] >> ds) & (uint32_t)(nbin - 1)], 1u);
+            __syncthreads();
+            // bins [8 tid, 8 tid + 8) per thread; the thread whose range holds the rank finds the bin
+            uint32_t c8[8], loc = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                c8[q] = 8 * tid + q < nbin ? hist[8 * tid + q] : 0u;
+                loc += c8[q];
+            }
+            uint32_t incl = loc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) s_wtot[wv] = incl;
+            __syncthreads();
+            for (int w = 0; w < wv; ++w) incl += s_wtot[w];
+            uint32_t ex = incl - loc;
+            if (ex <= rank && rank < incl) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (ex <= rank && rank < ex + c8[q]) {
+                        s_bin = 8 * tid + q;
+                        s_rib = rank - ex;
+                        s_inb = c8[q];
+                    }
+                    ex += c8[q];
+                }
+            }
+            __syncthreads();
+            rank = s_rib;
+            inbin = s_inb;
+            prefix |= (uint64_t)s_bin << ds;
+            shift = ds;
+            __syncthreads();   // hist, s_wtot and s_bin are reused by the next pass
         }
-        mask |= 255ull << shift;
-        __syncthreads();
+        if (shift > 0) {
+            // at most kEvalCand keys share the bucket: gather them (one atomic per
+            // wave and key slot) and rank them against each other
+#pragma unroll
+            for (int m = 0; m < kEvalPerThread; ++m) {
+                const bool take = ((valid >> m) & 1u) && (key[m] >> shift) == (prefix >> shift);
+                const uint64_t bal = __ballot(take);
+                if (bal) {
+                    const int leader = __ffsll((long long)bal) - 1;
+                    uint32_t base = 0;
+                    if (lane == leader) base = atomicAdd(&s_nc, (uint32_t)__popcll(bal));
+                    base = __shfl(base, leader, 64);
+                    if (take) cand[base + __popcll(bal & __lanemask_lt())] = key[m];
+                }
+            }
+            __syncthreads();
+            const uint32_t nc = s_nc;
+            if ((uint32_t)tid < nc) {
+                const uint64_t v = cand[tid];
+                uint32_t less = 0, eq = 0;
+                for (uint32_t q = 0; q < nc; ++q) {
+                    const uint64_t u = cand[q];
+                    less += u < v;
+                    eq += u == v;
+                }
+                if (less <= rank && rank < less + eq) a.score[h] = __longlong_as_double((long long)v);
+            }
+            return;
+        }
     }
-    if (tid == 0) a.score[h] = __longlong_as_double((long long)s_prefix);
+    if (tid == 0) a.score[h] = __longlong_as_double((long long)prefix);
 }
 
+// sel layout: [0..2] prefix, [3..5] rank, [8..11] cheirality votes, [12] valid count
+constexpr int kSelVotes = 8;
+
 struct PickArgs {
-    const float2 *X1;
     const double *hyp;
     const double *score;
-    double *rel;        // [T][12]
-    double *Mcum;       // [T+1][12]
+    double *cand;       // [21]: R of both decompositions (2 x 9), t up to sign (3)
     double *info;       // [4]
     int *status;
-    int H, W, M, Ne, T;
-    double fx, fy, cx, cy;
+    int M;
 };
 
 __device__ __forceinline__ double tri_depth(const double *R, const double *t, double xn, double yn,
@@ -332,20 +470,18 @@ __device__ __forceinline__ double tri_depth(const double *R, const double *t, do
     return th;
 }
 
-__global__ void __launch_bounds__(1024) k_boot_pick(PickArgs a)
+// least median of squares: lowest finite score, lowest index on ties; the
+// two rotations and the translation direction of its essential matrix
+__global__ void __launch_bounds__(256) k_boot_pick(PickArgs a)
 {
-    __shared__ int s_best;
-    __shared__ double s_rs[16];
-    __shared__ int s_rh[16];
-    __shared__ double Rc[2][9], tc[3];
-    __shared__ int red[4][16];
+    __shared__ double s_rs[4];
+    __shared__ int s_rh[4];
     const int tid = threadIdx.x;
-    // least median of squares: lowest finite score, lowest index on ties
     double bs = __longlong_as_double(0x7ff0000000000000ll);
     int best = 0x7fffffff;
-    for (int h = tid; h < a.M; h += 1024) {
-        const double s = a.score[h];
-        if (isfinite(s) && (s < bs || (s == bs && h < best))) { bs = s; best = h; }
+    for (int h = tid; h < a.M; h += 256) {
+        const double sc = a.score[h];
+        if (isfinite(sc) && (sc < bs || (sc == bs && h < best))) { bs = sc; best = h; }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const double so = __shfl_down(bs, o, 64);
@@ -354,43 +490,63 @@ __global__ void __launch_bounds__(1024) k_boot_pick(PickArgs a)
     }
     if ((tid & 63) == 0) { s_rs[tid >> 6] = bs; s_rh[tid >> 6] = best; }
     __syncthreads();
-    if (tid == 0) {
-        for (int w = 1; w < 16; ++w)
-            if (s_rs[w] < bs || (s_rs[w] == bs && s_rh[w] < best)) { bs = s_rs[w]; best = s_rh[w]; }
-        if (!isfinite(bs)) best = -1;
-        s_best = best;
-        if (best < 0) {
-            *a.status = kStatusDegenerate;
-        } else {
-            double U[9], V[9];
-            essential_factors(a.hyp + 18 * best, U, V);
-            const double Wm[9] = {0, -1, 0, 1, 0, 0, 0, 0, 1};
-            const double WmT[9] = {0, 1, 0, -1, 0, 0, 0, 0, 1};
-            double VT[9], T1[9];
-            for (int i = 0; i < 3; ++i)
-                for (int l = 0; l < 3; ++l) VT[3 * i + l] = V[3 * l + i];
-            mm3(U, Wm, T1);
-            mm3(T1, VT, Rc[0]);
-            mm3(U, WmT, T1);
-            mm3(T1, VT, Rc[1]);
-            tc[0] = U[2];
-            tc[1] = U[5];
-            tc[2] = U[8];
-            a.info[0] = best;
-            a.info[1] = bs;
-        }
+    if (tid != 0) return;
+    for (int w = 1; w < 4; ++w)
+        if (s_rs[w] < bs || (s_rs[w] == bs && s_rh[w] < best)) { bs = s_rs[w]; best = s_rh[w]; }
+    if (!isfinite(bs)) {
+        *a.status = kStatusDegenerate;
+        return;
     }
-    __syncthreads();
-    if (s_best < 0) return;
+    double U[9], V[9];
+    essential_factors(a.hyp + 18 * best, U, V);
+    const double Wm[9] = {0, -1, 0, 1, 0, 0, 0, 0, 1};
+    const double WmT[9] = {0, 1, 0, -1, 0, 0, 0, 0, 1};
+    double VT[9], T1[9];
+    for (int i = 0; i < 3; ++i)
+        for (int l = 0; l < 3; ++l) VT[3 * i + l] = V[3 * l + i];
+    mm3(U, Wm, T1);
+    mm3(T1, VT, a.cand);
+    mm3(U, WmT, T1);
+    mm3(T1, VT, a.cand + 9);
+    a.cand[18] = U[2];
+    a.cand[19] = U[5];
+    a.cand[20] = U[8];
+    a.info[0] = best;
+    a.info[1] = bs;
+}
+
+struct VoteArgs {
+    const float2 *X1;
+    const double *cand;
+    uint32_t *sel;
+    const int *status;
+    int H, W, Ne;
+    double fx, fy, cx, cy;
+};
+
+// cheirality vote of the four decompositions (R_a, +t), (R_a, -t), (R_b, +t),
+// (R_b, -t) over the pixel subset
+__global__ void __launch_bounds__(256) k_boot_vote(VoteArgs a)
+{
+    if (*a.status != kStatusOk) return;
+    __shared__ int red[4][4];
+    const int tid = threadIdx.x;
+    double Rc[2][9], tc[3];
+    for (int k = 0; k < 9; ++k) {
+        Rc[0][k] = a.cand[k];
+        Rc[1][k] = a.cand[9 + k];
+    }
+    for (int k = 0; k < 3; ++k) tc[k] = a.cand[18 + k];
     const int64_t HW = (int64_t)a.H * a.W;
     int cnt[4] = {0, 0, 0, 0};
-    for (int i = tid; i < a.Ne; i += 1024) {
-        const int64_t j = ((int64_t)i * HW) / a.Ne;
+    for (int i = blockIdx.x * 256 + tid; i < a.Ne; i += gridDim.x * 256) {
+        const int j = (int)(((int64_t)i * HW) / a.Ne);
         const float2 f = a.X1[j];
         if (!(isfinite(f.x) && isfinite(f.y))) continue;
-        const int x = (int)(j % a.W), y = (int)(j / a.W);
+        const int y = j / a.W, x = j - y * a.W;
         const double xn = (x - a.cx) / a.fx, yn = (y - a.cy) / a.fy;
         const double bx = (x + (double)f.x - a.cx) / a.fx, by = (y + (double)f.y - a.cy) / a.fy;
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
             const double *R = Rc[c >> 1];
             const double sg = (c & 1) ? -1.0 : 1.0;
@@ -408,52 +564,67 @@ __global__ void __launch_bounds__(1024) k_boot_pick(PickArgs a)
         if ((tid & 63) == 0) red[c][tid >> 6] = v;
     }
     __syncthreads();
-    if (tid == 0) {
-        int bc = 0, bn = -1;
-        for (int c = 0; c < 4; ++c) {
-            int tot = 0;
-            for (int i = 0; i < 16; ++i) tot += red[c][i];
-            if (tot > bn) { bn = tot; bc = c; }
-        }
-        const double sg = (bc & 1) ? -1.0 : 1.0;
-        double t[3] = {sg * tc[0], sg * tc[1], sg * tc[2]};
-        const double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-        for (int k = 0; k < 9; ++k) a.rel[k] = Rc[bc >> 1][k];
-        for (int k = 0; k < 3; ++k) a.rel[9 + k] = t[k] / tn;
-        for (int tt = 1; tt < a.T; ++tt)
-            for (int k = 0; k < 12; ++k) a.rel[12 * tt + k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
-        for (int k = 0; k < 12; ++k) a.Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
-        pose_mul(a.rel, a.Mcum, a.Mcum + 12);
-        a.info[3] = bn;
+    if (tid < 4) {
+        const int v = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+        if (v) atomicAdd(&a.sel[kSelVotes + tid], (uint32_t)v);
     }
 }
 
 struct TriArgs {
     const float2 *X1;
-    const double *rel;
+    const double *cand;
+    double *rel;         // [T][12]
+    double *Mcum;        // [T+1][12]
+    double *info;
     float *theta;
     uint32_t *keys;
-    uint32_t *sel;       // sel[12] accumulates the valid count
+    uint32_t *sel;       // votes in; sel[12] accumulates the valid count
     const int *status;
-    int H, W;
+    int H, W, T;
     double fx, fy, cx, cy;
 };
 
+// the decomposition with most points in front of both cameras (first on
+// ties) -> T_1 with |t_1| = 1; two-view depth of every pixel along its ray
 __global__ void __launch_bounds__(256) k_boot_tri(TriArgs a)
 {
     if (*a.status != kStatusOk) return;
     __shared__ int red[4];
-    const int64_t HW = (int64_t)a.H * a.W;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bc = 0;
+    uint32_t bn = 0;
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t v = a.sel[kSelVotes + c];
+        if (c == 0 || v > bn) { bn = v; bc = c; }
+    }
+    double R[9], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = a.cand[9 * (bc >> 1) + k];
+    {
+        const double sg = (bc & 1) ? -1.0 : 1.0;
+        for (int k = 0; k < 3; ++k) t[k] = sg * a.cand[18 + k];
+        const double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        for (int k = 0; k < 3; ++k) t[k] /= tn;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < 9; ++k) a.rel[k] = R[k];
+        for (int k = 0; k < 3; ++k) a.rel[9 + k] = t[k];
+        for (int tt = 1; tt < a.T; ++tt)
+            for (int k = 0; k < 12; ++k) a.rel[12 * tt + k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+        for (int k = 0; k < 12; ++k) a.Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+        for (int k = 0; k < 9; ++k) a.Mcum[12 + k] = R[k];
+        for (int k = 0; k < 3; ++k) a.Mcum[21 + k] = t[k];
+        a.info[3] = bn;
+    }
+    const int HW = a.H * a.W;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     int valid = 0;
     if (j < HW) {
         const float2 f = a.X1[j];
         uint32_t key = 0xffffffffu;
         float th32 = 0.0f;
         if (isfinite(f.x) && isfinite(f.y)) {
-            const int x = (int)(j % a.W), y = (int)(j / a.W);
+            const int y = j / a.W, x = j - y * a.W;
             bool ok;
-            const double th = tri_depth(a.rel, a.rel + 9, (x - a.cx) / a.fx, (y - a.cy) / a.fy,
+            const double th = tri_depth(R, t, (x - a.cx) / a.fx, (y - a.cy) / a.fy,
                                         (x + (double)f.x - a.cx) / a.fx, (y + (double)f.y - a.cy) / a.fy, ok);
             if (ok) {
                 th32 = (float)th;
@@ -473,7 +644,6 @@ __global__ void __launch_bounds__(256) k_boot_tri(TriArgs a)
     }
 }
 
-// sel layout: [0..2] prefix, [3..5] rank, [6..8] result, [12] valid count
 __global__ void k_sel_init(uint32_t *sel, uint32_t *hist, int *status)
 {
     const int tid = threadIdx.x;
@@ -575,14 +745,16 @@ int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n
     const int64_t HW = (int64_t)d.H * d.W;
     const int Ne = (int)(n_eval < HW ? n_eval : HW);
     hipLaunchKernelGGL(k_boot_init, dim3(1), dim3(64), 0, s, c->status, c->sel);
-    HypArgs h{flows, c->hyp, c->hyp_score, d.H, d.W, n_hyp, d.fx, d.fy, d.cx, d.cy, seed};
-    hipLaunchKernelGGL(k_boot_hyp, dim3((n_hyp + 63) / 64), dim3(64), 0, s, h);
-    ScoreArgs sc{flows, c->hyp, c->hyp_score, d.H, d.W, Ne};
+    HypArgs h{flows, c->hyp, c->hyp_score, c->boot_sub, d.H, d.W, n_hyp, Ne, d.fx, d.fy, d.cx, d.cy, seed};
+    hipLaunchKernelGGL(k_boot_hyp, dim3((n_hyp + 63) / 64 + (Ne + 63) / 64), dim3(64), 0, s, h);
+    ScoreArgs sc{c->boot_sub, c->hyp, c->hyp_score, Ne};
     hipLaunchKernelGGL(k_boot_score, dim3(n_hyp), dim3(kEvalThreads), 0, s, sc);
-    PickArgs pk{flows, c->hyp, c->hyp_score, rel_poses, c->Mcum, c->boot_info, c->status,
-                d.H, d.W, n_hyp, Ne, d.T, d.fx, d.fy, d.cx, d.cy};
-    hipLaunchKernelGGL(k_boot_pick, dim3(1), dim3(1024), 0, s, pk);
-    TriArgs tr{flows, rel_poses, theta, c->dkeys, c->sel, c->status, d.H, d.W, d.fx, d.fy, d.cx, d.cy};
+    PickArgs pk{c->hyp, c->hyp_score, c->boot_cand, c->boot_info, c->status, n_hyp};
+    hipLaunchKernelGGL(k_boot_pick, dim3(1), dim3(256), 0, s, pk);
+    VoteArgs va{flows, c->boot_cand, c->sel, c->status, d.H, d.W, Ne, d.fx, d.fy, d.cx, d.cy};
+    hipLaunchKernelGGL(k_boot_vote, dim3((Ne + 255) / 256), dim3(256), 0, s, va);
+    TriArgs tr{flows, c->boot_cand, rel_poses, c->Mcum, c->boot_info, theta, c->dkeys, c->sel, c->status,
+               d.H, d.W, d.T, d.fx, d.fy, d.cx, d.cy};
     hipLaunchKernelGGL(k_boot_tri, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, tr);
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c->sel, c->hist, c->status);
     int blocks = (int)((HW + 255) / 256);

@@ -50,6 +50,8 @@ struct voldor_ctx {
     double *hyp;           // [kMaxHyp][18]: essential E (9), fundamental F (9)
     double *hyp_score;     // [kMaxHyp] median Sampson residual
     double *boot_info;     // [4]
+    double *boot_cand;     // [24] rotations and translation of the best essential matrix
+    float4 *boot_sub;      // [kEvalThreads kEvalPerThread] pixel subset of the median (x, y, flow)
     uint32_t *dkeys;       // [H_max W_max] order-preserving keys of triangulated depths
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
