@@ -139,7 +139,7 @@ int upload_M(voldor_ctx *c, const double *M, int T, hipStream_t s)
 {
     if (hipMemcpyAsync(c->Mcum, M, sizeof(double) * 12 * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess)
         return VOLDOR_EDEVICE;
-    return launch_frames(c, T, s);
+    return 0;
 }
 
 }  // namespace
@@ -210,7 +210,6 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     const size_t HW = (size_t)H_max * W_max;
     bool ok = true;
     ok = ok && dalloc(&c->Mcum, 12 * (T_max + 1)) == hipSuccess;
-    ok = ok && dalloc(&c->frames, T_max + 1) == hipSuccess;
     ok = ok && dalloc(&c->range, 4) == hipSuccess;
     ok = ok && dalloc(&c->status, 8) == hipSuccess;
     ok = ok && dalloc(&c->samples, (size_t)7 * pose_sample_slots(S_max)) == hipSuccess;
@@ -253,7 +252,7 @@ void voldor_destroy(voldor_ctx *c)
 {
     if (!c) return;
     voldor_set_timing(c, 0);
-    void *bufs[] = {c->Mcum, c->frames, c->range, c->status, c->samples, c->seed_score,
+    void *bufs[] = {c->Mcum, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->boot_cand, c->boot_sub, c->dkeys, c->hist,
                     c->sel, c->ll_part, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
     for (void *b : bufs)
@@ -284,7 +283,6 @@ int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const 
         for (int t = 1; t <= T && rc == 0; ++t)
             rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0,
                                   poses, s);
-        if (rc == 0) rc = launch_frames(c, T, s);
         mark(c, s, kPhasePose);
         for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw) {
             const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
@@ -292,13 +290,14 @@ int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const 
                               c->range, nullptr, s);
             mark(c, s, kPhaseSweep);
         }
-        if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, rigidness, nullptr, nullptr, nullptr, nullptr, s);
-        if (rc == 0) rc = launch_gauge(c, poses, depth, d, s);
+        // unsmoothed W, then the scale gauge: depth rescaled in the same pass
+        if (rc == 0)
+            rc = launch_rigidness(c, depth, X, d, e, rigidness, nullptr, nullptr, nullptr, nullptr, s, depth, poses);
+        if (rc == 0) rc = launch_gauge_poses(c, poses, d, s);
         mark(c, s, kPhaseRig);
     }
     if (rc == 0 && loglik) {
-        rc = launch_frames(c, T, s);
-        if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, loglik, s);
+        rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, loglik, s);
         mark(c, s, kPhaseLL);
     }
     if (rc != 0) return rc;

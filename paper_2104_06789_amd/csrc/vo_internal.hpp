@@ -41,7 +41,6 @@ struct voldor_ctx {
     int max_lds;           // bytes of LDS one workgroup may allocate
     // persistent device state
     double *Mcum;          // [(T_max+1)][12] cumulative poses M_0..M_T
-    vo::FrameF *frames;    // [T_max+1] FP32 copy of Mcum for the sweeps
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
     int *status;           // [8]: status word, pose diagnostics scratch
     double *samples;       // SoA [7][slots] pose samples (p, weight), compacted per block of groups
@@ -77,13 +76,14 @@ struct voldor_ctx {
 namespace vo {
 
 // ---- sweep / emission (vo_sweep.hip)
-int launch_frames(voldor_ctx *c, int T, hipStream_t s);
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
                  const WinDims &d, const EmisParams &e, float gamma, uint64_t seed,
                  int64_t gsweep, int dir, const double *range_dev, float *q_out, hipStream_t s);
+// theta_gauge (with rel_poses): also writes theta / |t_1| there, after use
 int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, const WinDims &d,
                      const EmisParams &e, float *r, float *ell, float *logrho, float *logmu,
-                     double *ll_out, hipStream_t s);
+                     double *ll_out, hipStream_t s, float *theta_gauge = nullptr,
+                     const double *rel_poses = nullptr);
 int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
                   hipStream_t s);
 size_t sweep_lds_bytes(int T, int L);
@@ -95,7 +95,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
 int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s);
 size_t pose_sample_slots(int S_max);
 size_t pose_seed_parts();
-int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s);
+int launch_gauge_poses(voldor_ctx *c, double *rel_poses, const WinDims &d, hipStream_t s);
 int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
 
 // ---- bootstrap (vo_boot.hip)

@@ -590,7 +590,8 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
     }
 }
 
-// scale gauge |t_1| = 1: translations, depth range, cumulative poses
+// scale gauge |t_1| = 1: translations, depth range, cumulative poses (the
+// depth map is rescaled by the rigidness pass that precedes this kernel)
 __global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, const int *status)
 {
     if (status && *status != kStatusOk) return;
@@ -605,13 +606,6 @@ __global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, c
     range[1] *= inv;
     for (int k = 0; k < 12; ++k) Mcum[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
     for (int t = 1; t <= T; ++t) pose_mul(rel + 12 * (t - 1), Mcum + 12 * (t - 1), Mcum + 12 * t);
-}
-
-__global__ void k_gauge_theta(float *theta, int HW, const double *range, const int *status)
-{
-    if (status && *status != kStatusOk) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < HW) theta[j] = (float)((double)theta[j] / range[2]);
 }
 
 __global__ void k_cumulative(const double *rel, double *Mcum, int T)
@@ -701,11 +695,9 @@ size_t pose_sample_slots(int S_max)
     return (size_t)kSlotsPerBlk * ((S_max + kGrpPerBlk - 1) / kGrpPerBlk);
 }
 
-int launch_gauge(voldor_ctx *c, double *rel_poses, float *theta, const WinDims &d, hipStream_t s)
+int launch_gauge_poses(voldor_ctx *c, double *rel_poses, const WinDims &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gauge_poses, dim3(1), dim3(64), 0, s, rel_poses, c->Mcum, c->range, d.T, c->status);
-    const int HW = d.H * d.W;
-    hipLaunchKernelGGL(k_gauge_theta, dim3((HW + 255) / 256), dim3(256), 0, s, theta, HW, c->range, c->status);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 

@@ -38,6 +38,18 @@ __device__ __forceinline__ int chain_pixel(int dir, int H, int W, int c, int k)
     }
 }
 
+// FP32 frame t (R - I, t) of the FP64 cumulative pose M_t, built by threads
+// 0..T of a workgroup into LDS
+__device__ __forceinline__ void load_frames(const double *Mcum, int T, FrameF *fr)
+{
+    const int t = threadIdx.x;
+    if (t <= T) {
+        const double *m = Mcum + 12 * t;
+        for (int i = 0; i < 9; ++i) fr[t].D[i] = (float)(m[i] - ((i == 0 || i == 4 || i == 8) ? 1.0 : 0.0));
+        for (int i = 0; i < 3; ++i) fr[t].t[i] = (float)m[9 + i];
+    }
+}
+
 // pixel coordinates of chain position k (no integer division)
 __device__ __forceinline__ void chain_xy(int dir, int H, int W, int c, int k, int &x, int &y)
 {
@@ -176,7 +188,7 @@ struct SweepArgs {
     const float *theta_in;
     float *theta_out;
     const float2 *flows;
-    const FrameF *frames;
+    const double *Mcum;    // cumulative poses M_0..M_T (device)
     const double *range;   // d_lo, d_hi (device)
     float *q_out;
     const int *status;
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
     float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
     float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
 
-    for (int i = tid; i < (T + 1) * 12; i += kSweepThreads) ((float *)fr)[i] = ((const float *)a.frames)[i];
+    load_frames(a.Mcum, T, fr);
     if (tid == 0) {
         s_cnt[0] = 0;
         s_cnt[1] = 0;
@@ -541,8 +553,10 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
 // ---------------------------------------------------------------------------
 struct RigArgs {
     const float *theta;
+    float *theta_gauge;     // optional: theta / |t_1| written back in place (scale gauge)
+    const double *rel;      // relative poses (t_1 gives the gauge)
     const float2 *flows;
-    const FrameF *frames;
+    const double *Mcum;
     const int *status;
     float *r, *ell, *logrho, *logmu;
     double *ll_part;
@@ -555,10 +569,15 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
     if (a.status && *a.status != kStatusOk) return;
     __shared__ FrameF fr[kTMax + 1];
     __shared__ double red[2][256];
-    for (int i = threadIdx.x; i < (a.T + 1) * 12; i += blockDim.x)
-        ((float *)fr)[i] = ((const float *)a.frames)[i];
+    load_frames(a.Mcum, a.T, fr);
     __syncthreads();
     const int HW = a.H * a.W;
+    double gscale = 1.0;
+    if (a.theta_gauge) {
+        const double *t1 = a.rel + 9;
+        const double g = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+        gscale = g > 0 ? g : 1.0;
+    }
     double acc = 0.0, mass = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < HW; j += gridDim.x * blockDim.x) {
         const int x = j % a.W, y = j / a.W;
@@ -605,6 +624,7 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
             if (a.logrho) a.logrho[o] = lr;
             if (a.logmu) a.logmu[o] = lm;
         }
+        if (a.theta_gauge) a.theta_gauge[j] = (float)((double)th / gscale);
     }
     if (a.ll_part) {
         red[0][threadIdx.x] = acc;
@@ -650,16 +670,6 @@ __global__ void k_ll_reduce(const double *part, int n, const int *status, double
     }
 }
 
-// FP32 frames (R - I, t) from the FP64 cumulative poses
-__global__ void k_frames(const double *M, FrameF *fr, int T)
-{
-    const int t = threadIdx.x;
-    if (t > T) return;
-    const double *m = M + 12 * t;
-    for (int i = 0; i < 9; ++i) fr[t].D[i] = (float)(m[i] - ((i == 0 || i == 4 || i == 8) ? 1.0 : 0.0));
-    for (int i = 0; i < 3; ++i) fr[t].t[i] = (float)m[9 + i];
-}
-
 __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -675,12 +685,6 @@ size_t sweep_lds_bytes(int T, int L)
     return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L)) * sizeof(float);
 }
 
-int launch_frames(voldor_ctx *c, int T, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_frames, dim3(1), dim3(64), 0, s, c->Mcum, c->frames, T);
-    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
-}
-
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
                  const WinDims &d, const EmisParams &e, float gamma, uint64_t seed, int64_t gsweep,
                  int dir, const double *range_dev, float *q_out, hipStream_t s)
@@ -693,7 +697,7 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.theta_in = theta_in;
     a.theta_out = theta_out;
     a.flows = flows;
-    a.frames = c->frames;
+    a.Mcum = c->Mcum;
     a.range = range_dev;
     a.q_out = q_out;
     a.status = c->status;
@@ -714,12 +718,14 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
 
 int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, const WinDims &d,
                      const EmisParams &e, float *r, float *ell, float *logrho, float *logmu,
-                     double *ll_out, hipStream_t s)
+                     double *ll_out, hipStream_t s, float *theta_gauge, const double *rel_poses)
 {
     RigArgs a;
     a.theta = theta;
+    a.theta_gauge = theta_gauge;
+    a.rel = rel_poses;
     a.flows = flows;
-    a.frames = c->frames;
+    a.Mcum = c->Mcum;
     a.status = c->status;
     a.r = r;
     a.ell = ell;
