@@ -14,7 +14,7 @@
 //   C  for every origin k, next(k) = first j > k where a_k loses as the
 //      propagated neighbour (prev > neighbour > sample on ties), found in
 //      rounds over a shrinking list of live origins with a look-ahead that
-//      grows as the list shrinks;
+//      grows as the list shrinks (the whole workgroup evaluates each round);
 //   D  the propagation path 0 -> next(0) -> next(next(0)) ... by pointer
 //      doubling; each position takes the local best of the last path node at
 //      or before it.
@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
     // best equal to the previous depth at k+1 scores exactly that depth there
     // and loses (the previous depth wins ties), so next(k) = k+1 at once
     int2 *list0 = (int2 *)lq, *list1 = list0 + L;
-    int *win = (int *)(list1 + L);
+    // first losing offset of each live origin, INT_MAX until one is seen
+    int *first0 = (int *)(list1 + L), *first1 = first0 + L;
     for (int k = tid; k < L; k += kSweepThreads) {
         if (k == L - 1) {
             nxt[k] = L;
@@ -464,6 +465,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         } else {
             const int at = atomicAdd(&s_cnt[0], 1);
             list0[at] = make_int2(k, k + 1);
+            first0[at] = INT_MAX;
         }
     }
     __syncthreads();
@@ -474,16 +476,16 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
         const int n = s_cnt[cur];
         if (n == 0) break;
         int2 *lc = cur ? list1 : list0, *ln = cur ? list0 : list1;
-        int la = kSweepThreads / n;                  // look-ahead per live origin
-        if (la < 1) la = 1;
-        if (la > 64) la = 64;
+        int *first = cur ? first1 : first0, *firstn = cur ? first0 : first1;
+        const int la = max(kSweepThreads / n, 1);   // look-ahead per live origin
         const int items = n * la;
+        const float ila = frcp((float)la);
         for (int i = tid; i < items; i += kSweepThreads) {
             // i / la through FP32: (i + 1/2) / la is at least 1/(2 la) from an integer
-            const int sl = (int)(((float)i + 0.5f) * frcp((float)la)), p = i - sl * la;
+            const int sl = (int)(((float)i + 0.5f) * ila), p = i - sl * la;
             const int2 e = lc[sl];
             const int jpos = e.y + p;
-            int w = 0;
+            bool w = false;
             if (jpos < L && !(aval[e.x] == th[jpos])) {   // equal to the previous depth: loses
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
@@ -491,14 +493,13 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
                 const float s = chain_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
             }
-            win[i] = w;
+            if (!w) atomicMin(&first[sl], p);
         }
         if (tid == 0) s_cnt[cur ^ 1] = 0;
         __syncthreads();
         for (int sl = tid; sl < n; sl += kSweepThreads) {
             const int2 e = lc[sl];
-            int p = 0;
-            while (p < la && win[sl * la + p]) ++p;
+            const int p = first[sl];   // INT_MAX: survived the whole look-ahead
             if (p < la) {
                 nxt[e.x] = min(e.y + p, L);
             } else if (e.y + la >= L) {
@@ -506,6 +507,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
             } else {
                 const int at = atomicAdd(&s_cnt[cur ^ 1], 1);
                 ln[at] = make_int2(e.x, e.y + la);
+                firstn[at] = INT_MAX;
             }
         }
         __syncthreads();
