@@ -32,8 +32,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of one sweep launch on the indoor workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
+# counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
+# the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
+# profiles/k_sweep_indoor_hbm_traffic.md)
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25142.82421875 * 1024 * 1.99983,
+                        "write_bytes": 1266.16796875 * 1024 * 1.0}
+SWEEP_SOURCES_SHA = "6734fc834195be18"
+SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp", "vo_internal.hpp")
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # FP32 lane-instructions/s (non-packed), 39.3 T
 EMISSION_VALU_OPS = 182                      # VALU instructions of one emission evaluation (gfx950 ISA)
+
+
+def _sweep_traffic(workload):
+    """Measured HBM bytes per sweep launch, or None if not measured for this
+    workload or if the kernel changed since the counters were taken."""
+    import hashlib
+    if workload != "indoor":
+        return None
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_06789_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != SWEEP_SOURCES_SHA:
+        return None
+    return SWEEP_TRAFFIC_INDOOR["fetch_bytes"] + SWEEP_TRAFFIC_INDOOR["write_bytes"]
 
 
 def _pose_error(poses, gt):
@@ -129,7 +153,7 @@ def main():
         "phase_ms": ph,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload),
                      "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms,
                      "hbm_view": {"alg_bytes_per_launch": alg_bytes, "achieved_GBs": achieved_gbs,
                                   "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
