@@ -86,11 +86,10 @@ __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh
 __device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 
-// log(1 + e) for e in [0, 1]: series where 1 + e would round away e.
-__device__ __forceinline__ float log1p_unit(float e)
-{
-    return e < 1e-3f ? e * (1.0f - e * (0.5f - e * (1.0f / 3.0f))) : fast_log(1.0f + e);
-}
+// log(1 + e) for e in [0, 1] on the hardware log2 unit.  The rounding of 1 + e
+// costs at most half an ulp of 1 (6e-8) in absolute terms, which is what the
+// log-odds and the M-step scores need (they are compared in absolute terms).
+__device__ __forceinline__ float log1p_unit(float e) { return fast_log(1.0f + e); }
 
 __device__ __forceinline__ float softplus(float z)
 {
