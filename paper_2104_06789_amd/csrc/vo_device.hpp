@@ -262,13 +262,15 @@ __device__ inline void se3_exp(const double *p, double *R, double *t)
     mv3(V, p, t);
 }
 
-// se(3) log: R, t -> p = (V^-1 t, phi), |phi| in [0, pi]
-__device__ inline void se3_log(const double *R, const double *t, double *p)
+// se(3) log: R, t -> p = (V^-1 t, phi), |phi| in [0, pi]; *angle (optional)
+// receives |phi|, the same number rot_angle(R) gives
+__device__ inline void se3_log(const double *R, const double *t, double *p, double *angle = nullptr)
 {
     const double wx = R[7] - R[5], wy = R[2] - R[6], wz = R[3] - R[1];
     const double s = 0.5 * sqrt(wx * wx + wy * wy + wz * wz);
     const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
     const double th = atan2(s, c);
+    if (angle) *angle = th;
     double phi[3];
     if (th < 1e-5) {
         const double f = 0.5 + th * th * (1.0 / 12.0);

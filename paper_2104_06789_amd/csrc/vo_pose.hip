@@ -126,14 +126,16 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
     if (val)
         for (int k = 0; k < 3; ++k)
             val = val && R[6] * P[3 * k] + R[7] * P[3 * k + 1] + R[8] * P[3 * k + 2] + tv[2] > 0;
-    // canonical order among the group's roots: rotation angle, then t_x, t_y, t_z
+    // se(3) log of the root (its rotation angle is the first sort key)
     double key[4] = {0.0, 0.0, 0.0, 0.0};
+    double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (val) {
-        key[0] = rot_angle(R);
+        se3_log(R, tv, p, &key[0]);
         key[1] = tv[0];
         key[2] = tv[1];
         key[3] = tv[2];
     }
+    // canonical order among the group's roots: rotation angle, then t_x, t_y, t_z
     int rank = 0;
 #pragma unroll
     for (int q = 0; q < kGrpLanes; ++q) {
@@ -146,11 +148,8 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
         for (int c = 3; c >= 0; --c) cmp = kq[c] < key[c] ? -1 : (kq[c] > key[c] ? 1 : cmp);
         if (q != r && vq && (cmp < 0 || (cmp == 0 && q < r))) ++rank;
     }
-    double p[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (val) {
-        se3_log(R, tv, p);
+    if (val)
         for (int c = 0; c < 6; ++c) val = val && isfinite(p[c]);
-    }
     // valid samples fill the group's positions without gaps, in canonical order
     const unsigned long long vm = __ballot(val);
     int pos = 0;

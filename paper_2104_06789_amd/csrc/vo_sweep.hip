@@ -582,21 +582,48 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
     }
     double acc = 0.0, mass = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < HW; j += gridDim.x * blockDim.x) {
-        const int x = j % a.W, y = j / a.W;
+        const int y = j / a.W, x = j - y * a.W;
         const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
         const float th = a.theta[j];
         float px0 = 0.0f, py0 = 0.0f;
         bool ok0 = th > 0.0f;
-        for (int t = 1; t <= a.T; ++t) {
-            // same steps as frame_log_odds, keeping the pieces of log rho / log mu
-            float dx1, dy1;
-            const bool ok1 = displacement(fr[t], xh, yh, th, a.e.fx, a.e.fy, dx1, dy1);
-            float r = 0.5f, ell = -0.69314718055994531f, lr = 0.0f, lm = 0.0f;
-            if (ok0 && ok1) {
-                float vu, vv;
-                const float2 *X = a.flows + (size_t)(t - 1) * HW;
-                if (sample_flow(X, a.H, a.W, (float)x + px0, (float)y + py0, vu, vv)) {
-                    const float rx = (dx1 - px0) - vu, ry = (dy1 - py0) - vv;
+        // frames in chunks of four: the flow gathers of a chunk are in flight together
+        for (int t0 = 1; t0 <= a.T; t0 += 4) {
+            float dx1[4], dy1[4], bx[4], by[4], ax[4], ay[4];
+            bool val[4], ok1[4];
+            float2 ta[4], tb[4], tc[4], td[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u;
+                dx1[u] = 0.0f;
+                dy1[u] = 0.0f;
+                ok1[u] = t <= a.T && displacement(fr[t <= a.T ? t : a.T], xh, yh, th, a.e.fx, a.e.fy, dx1[u], dy1[u]);
+                bx[u] = u == 0 ? px0 : dx1[u - 1];
+                by[u] = u == 0 ? py0 : dy1[u - 1];
+                const bool bok = u == 0 ? ok0 : ok1[u - 1];
+                const float spx = (float)x + bx[u], spy = (float)y + by[u];
+                val[u] = bok && ok1[u] && spx >= 0.0f && spx <= (float)(a.W - 1) && spy >= 0.0f &&
+                         spy <= (float)(a.H - 1);
+                const float qx = val[u] ? spx : 0.0f, qy = val[u] ? spy : 0.0f;
+                const int x0 = min((int)floorf(qx), a.W - 2), y0 = min((int)floorf(qy), a.H - 2);
+                ax[u] = qx - (float)x0;
+                ay[u] = qy - (float)y0;
+                const float2 *r0 = a.flows + ((val[u] ? t - 1 : 0) * HW + y0 * a.W + x0);
+                ta[u] = r0[0];
+                tb[u] = r0[1];
+                tc[u] = r0[a.W];
+                td[u] = r0[a.W + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u;
+                if (t > a.T) break;
+                float r = 0.5f, ell = -0.69314718055994531f, lr = 0.0f, lm = 0.0f;
+                const float2 A = ta[u], B = tb[u], Cc = tc[u], D = td[u];
+                if (val[u] && isfinite(A.x + A.y + B.x + B.y + Cc.x + Cc.y + D.x + D.y)) {
+                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], B.x - A.x, A.x) + ay[u] * fmaf(ax[u], D.x - Cc.x, Cc.x);
+                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], B.y - A.y, A.y) + ay[u] * fmaf(ax[u], D.y - Cc.y, Cc.y);
+                    const float rx = (dx1[u] - bx[u]) - vu, ry = (dy1[u] - by[u]) - vv;
                     const float d = log_mu_over_rho(rx, ry, vu, vv, a.e);
                     const Emis m = emis_from_d(d);
                     r = m.r;
@@ -616,15 +643,15 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                         mass += fabs(term);
                     }
                 }
+                const int o = (t - 1) * HW + j;
+                if (a.r) a.r[o] = r;
+                if (a.ell) a.ell[o] = ell;
+                if (a.logrho) a.logrho[o] = lr;
+                if (a.logmu) a.logmu[o] = lm;
             }
-            px0 = dx1;
-            py0 = dy1;
-            ok0 = ok1;
-            const size_t o = (size_t)(t - 1) * HW + j;
-            if (a.r) a.r[o] = r;
-            if (a.ell) a.ell[o] = ell;
-            if (a.logrho) a.logrho[o] = lr;
-            if (a.logmu) a.logmu[o] = lm;
+            px0 = dx1[3];
+            py0 = dy1[3];
+            ok0 = ok1[3];
         }
         if (a.theta_gauge) a.theta_gauge[j] = (float)((double)th / gscale);
     }
