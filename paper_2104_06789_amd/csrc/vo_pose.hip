@@ -399,12 +399,14 @@ __device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
 
 // Gaussian mean-shift from the densest start candidate in one workgroup.
 // Wave w owns the sample blocks b = w, w + 8, ...; it lists their samples in
-// LDS and holds them as FP32 offsets from the current mean in whitened
-// coordinates (o_c = (p_c - m_c) s_c with s_c^2 = log2(e) / (2 sigma_c^2), so
-// that the kernel weight is 2^(-|o|^2)), re-centred after every step, and
-// their weights as log2 w; a running log2 density c2 keeps every weight in
-// FP32 range.  The mean itself is kept in FP64.  Every wave evaluates the
-// same totals, so the stop decision is uniform with one barrier per step.
+// LDS and holds them as FP32 offsets from the start point P0 in whitened
+// coordinates (o_c = (p_c - P0_c) s_c with s_c^2 = log2(e) / (2 sigma_c^2), so
+// that the kernel weight at mean m is 2^(-|o - m|^2)), together with
+// log2 w - |o|^2: the exponent at m is then that plus 2 o.m - |m|^2, six FMAs
+// per sample and no re-centring.  A running log2 density c2 keeps every
+// weight in FP32 range.  The mean itself is kept in FP64.  Every wave
+// evaluates the same totals, so the stop decision is uniform with one barrier
+// per step.
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
@@ -507,43 +509,54 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         for (int c = 0; c < 6; ++c) o[m][c] = in ? a.sampf[(size_t)c * a.ns + sl] : 0.0f;
         lw[m] = in ? a.sampf[(size_t)6 * a.ns + sl] : -INFINITY;
     }
+    // o: offset from the start point; lw becomes log2 w - |o|^2, so that the
+    // exponent at mean m is lw - |o|^2 + 2 o.m - |m|^2 with no re-centring
 #pragma unroll
-    for (int m = 0; m < kMsRegs; ++m)
+    for (int m = 0; m < kMsRegs; ++m) {
+        float n2 = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) o[m][c] -= (float)P0[c];
+        for (int c = 0; c < 6; ++c) {
+            o[m][c] -= (float)P0[c];
+            n2 = fmaf(o[m][c], o[m][c], n2);
+        }
+        lw[m] -= n2;
+    }
     // c2: log2 of the density at the current mean (starts at the candidate's)
     float c2 = D0 > 0.0 ? (float)log2(D0) : 0.0f;
     double cen[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // whitened mean - P0
     const double tol2 = a.tol * a.tol * 0.72134752044448170;
     int it = 0;
     for (; it < a.max_iters && D0 > 0.0; ++it) {
+        float cf[6], tc[6], cn2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            cf[c] = (float)cen[c];
+            tc[c] = 2.0f * cf[c];
+            cn2 = fmaf(cf[c], cf[c], cn2);
+        }
+        const float bias = -c2 - cn2;
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m = 0; m < kMsRegs; ++m) {
             if (lane + 64 * m < nreg) {
-                float q2 = 0.0f;
+                float e = lw[m] + bias;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) q2 = fmaf(o[m][c], o[m][c], q2);
-                const float k = __builtin_amdgcn_exp2f(lw[m] - c2 - q2);
+                for (int c = 0; c < 6; ++c) e = fmaf(tc[c], o[m][c], e);
+                const float k = __builtin_amdgcn_exp2f(e);
                 acc[6] += k;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) acc[c] = fmaf(k, o[m][c], acc[c]);
             }
         }
         if (Nw > kMsWaveCap) {
-            // the rest from memory, centred by a two-float split of the mean
-            float chi[6], clo[6];
-            for (int c = 0; c < 6; ++c) {
-                const double C = P0[c] + cen[c];
-                chi[c] = (float)C;
-                clo[c] = (float)(C - (double)chi[c]);
-            }
+            // the rest from memory: offsets from the start, centred distance
             for (int i = kMsWaveCap + lane; i < Nw; i += 64) {
                 const int sl = widx[wv][i];
                 float d[6], q2 = 0.0f;
                 for (int c = 0; c < 6; ++c) {
-                    d[c] = (a.sampf[(size_t)c * a.ns + sl] - chi[c]) - clo[c];
-                    q2 = fmaf(d[c], d[c], q2);
+                    d[c] = a.sampf[(size_t)c * a.ns + sl] - (float)P0[c];
+                    const float dc = d[c] - cf[c];
+                    q2 = fmaf(dc, dc, q2);
                 }
                 const float k = __builtin_amdgcn_exp2f(a.sampf[(size_t)6 * a.ns + sl] - c2 - q2);
                 acc[6] += k;
@@ -559,20 +572,14 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         if (!(den > 0.0)) break;
         const double iden = 1.0 / den;
         double step2 = 0.0;
-        float sf[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const double sh = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 8 * c)) * iden;
-            sf[c] = (float)sh;
-            cen[c] += (double)sf[c];
+            const double mc = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 8 * c)) * iden;
+            const double sh = mc - cen[c];
+            cen[c] = mc;
             step2 += sh * sh;
         }
         c2 += __builtin_amdgcn_logf((float)den);
-#pragma unroll
-        for (int m = 0; m < kMsRegs; ++m)
-            if (lane + 64 * m < nreg)
-#pragma unroll
-                for (int c = 0; c < 6; ++c) o[m][c] -= sf[c];
         if (step2 < tol2) { ++it; break; }
     }
     if (tid == 0) {
