@@ -101,13 +101,33 @@ int voldor_window(voldor_ctx *ctx, const float *flows, int T, int H, int W, cons
                   const voldor_params *p, double *poses, float *depth, float *rigidness,
                   double *loglik, void *stream);
 
-/* Phase timing of voldor_window with HIP events recorded on its stream.
- * voldor_set_timing(ctx, 1) creates the events (0 destroys them); after a
- * window, voldor_last_timing fills out[8] with milliseconds: [0] bootstrap,
- * [1] pose steps, [2] directional sweeps, [3] number of sweep launches,
- * [4] rigidness and gauge, [5] log-likelihood, [6] whole window, [7] unused. */
+/* The same window (Table 1), enqueued without waiting: windows submitted back
+ * to back on one stream run with no host round trip between them.
+ *   status_out  device int32, 4-byte aligned: receives the window's device
+ *               status (VOLDOR_OK or VOLDOR_EDEGENERATE) when its work is done
+ * Other arguments as voldor_window.  The return value covers only the host-side
+ * checks (VOLDOR_EINVAL, VOLDOR_EDEVICE for a failed launch); inputs and outputs
+ * must stay allocated until the stream reaches the end of the window.  All
+ * windows of one context must be enqueued on one stream (they share its
+ * workspace in stream order). */
+int voldor_window_async(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                        const voldor_params *p, double *poses, float *depth, float *rigidness,
+                        double *loglik, int32_t *status_out, void *stream);
+
+/* Phase timing of windows with HIP events recorded on their stream, kept for
+ * the last 32 windows.  voldor_set_timing(ctx, 1) creates the events (0
+ * destroys them).  Phases, in milliseconds: [0] bootstrap, [1] pose steps,
+ * [2] directional sweeps, [3] number of sweep launches, [4] rigidness and
+ * gauge, [5] log-likelihood, [6] whole window, [7] unused.
+ * voldor_last_timing: out[8] of the last voldor_window call (or of the last
+ * window a summary covered).
+ * voldor_timing_summary: waits for the stream of the last window, then fills
+ * out[8] with the mean over the windows enqueued since the previous summary
+ * (the last 32 of them at most) and their number in *n_windows (may be NULL);
+ * starts a new count.  VOLDOR_EINVAL when timing is off. */
 int voldor_set_timing(voldor_ctx *ctx, int enable);
 int voldor_last_timing(voldor_ctx *ctx, double *out);
+int voldor_timing_summary(voldor_ctx *ctx, double *out, int *n_windows);
 
 /* ---- step entry points: one step of the loop on explicit state ----------- */
 

@@ -61,6 +61,7 @@ def lib():
         "voldor_create": (i, [C.POINTER(vp), i, i, i, i]),
         "voldor_destroy": (None, [vp]),
         "voldor_window": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp]),
+        "voldor_window_async": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp]),
         "voldor_philox": (i, [vp, C.c_uint64, C.c_uint64, vp, i, vp]),
         "voldor_emission": (i, [vp, vp, vp, i, i, i, dp, P, dp, vp, vp, vp, vp, vp]),
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
@@ -68,6 +69,7 @@ def lib():
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
         "voldor_last_timing": (i, [vp, dp]),
+        "voldor_timing_summary": (i, [vp, dp, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -164,6 +166,23 @@ class Solver:
         _check(rc, "voldor_window")
         return poses, depth, rig, ll
 
+    def window_async(self, flows, K, params, out, status, stream=None, want_loglik=True):
+        """Enqueue one window without waiting.  out = (poses, depth, rigidness,
+        loglik or None) CUDA tensors as returned by window(); status: a CUDA
+        int32 tensor element (e.g. statuses[i]) that receives the device status.
+        The tensors must stay alive until the stream has run the window."""
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        if not (isinstance(status, torch.Tensor) and status.is_cuda and status.dtype == torch.int32):
+            raise TypeError("status must be a CUDA int32 tensor element")
+        poses, depth, rig, ll = out
+        Kd, Kp = _dbl(K)
+        rc = lib().voldor_window_async(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(poses),
+                                       _ptr(depth), _ptr(rig), _ptr(ll) if want_loglik else None,
+                                       _ptr(status), _stream(stream))
+        _check(rc, "voldor_window_async")
+
     def window_status(self, flows, K, params, stream=None):
         """Like window() but returns the status code instead of raising."""
         import torch
@@ -188,6 +207,17 @@ class Solver:
                "voldor_last_timing")
         keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window"]
         return dict(zip(keys, out[:7].tolist()))
+
+    def timing_summary(self):
+        """Wait for the last window's stream; mean phase milliseconds over the
+        windows enqueued since the previous summary (the last 32 at most), and
+        their number."""
+        out = np.zeros(8)
+        n = C.c_int(0)
+        _check(lib().voldor_timing_summary(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)),
+               "voldor_timing_summary")
+        keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window"]
+        return dict(zip(keys, out[:7].tolist())), n.value
 
     # -- single steps ---------------------------------------------------------
     def emission(self, theta, flows, K, params, M, stream=None):

@@ -112,27 +112,36 @@ enum { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseR
 
 void mark(voldor_ctx *c, hipStream_t s, int phase)
 {
-    if (!c->timing || c->n_ev >= 256) return;
-    if (hipEventRecord(c->ev[c->n_ev], s) != hipSuccess) return;
-    c->ev_phase[c->n_ev] = phase;
-    ++c->n_ev;
+    if (!c->timing) return;
+    // a full slot moves its last event forward: the whole-window time stays exact
+    const int i = c->n_ev < kEvPerWin ? c->n_ev : kEvPerWin - 1;
+    if (hipEventRecord(c->ev[c->tw_cur * kEvPerWin + i], s) != hipSuccess) return;
+    c->ev_phase[c->tw_cur][i] = phase;
+    c->n_ev = i + 1;
 }
 
-// last_ms: [0] bootstrap, [1] pose steps, [2] sweeps, [3] sweep launches,
+// phases of the window in ring slot w (its events complete):
+// [0] bootstrap, [1] pose steps, [2] sweeps, [3] sweep launches,
 // [4] rigidness + gauge, [5] log-likelihood, [6] whole window
-void collect_timing(voldor_ctx *c)
+void slot_timing(const voldor_ctx *c, int w, double *ms8)
 {
-    if (!c->timing) return;
-    for (int i = 0; i < 8; ++i) c->last_ms[i] = 0.0;
-    for (int i = 1; i < c->n_ev; ++i) {
+    for (int i = 0; i < 8; ++i) ms8[i] = 0.0;
+    const hipEvent_t *ev = c->ev + w * kEvPerWin;
+    const int n = c->ev_n[w];
+    for (int i = 1; i < n; ++i) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, c->ev[i - 1], c->ev[i]) != hipSuccess) continue;
-        const int ph = c->ev_phase[i];
-        if (ph >= 0 && ph < 6) c->last_ms[ph] += ms;
-        if (ph == kPhaseSweep) c->last_ms[3] += 1.0;
+        if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) != hipSuccess) continue;
+        const int ph = c->ev_phase[w][i];
+        if (ph >= 0 && ph < 6) ms8[ph] += ms;
+        if (ph == kPhaseSweep) ms8[3] += 1.0;
     }
     float tot = 0.0f;
-    if (c->n_ev > 1 && hipEventElapsedTime(&tot, c->ev[0], c->ev[c->n_ev - 1]) == hipSuccess) c->last_ms[6] = tot;
+    if (n > 1 && hipEventElapsedTime(&tot, ev[0], ev[n - 1]) == hipSuccess) ms8[6] = tot;
+}
+
+__global__ void k_copy_status(const int *status, int32_t *out)
+{
+    if (threadIdx.x == 0) *out = *status;
 }
 
 int upload_M(voldor_ctx *c, const double *M, int T, hipStream_t s)
@@ -260,19 +269,22 @@ void voldor_destroy(voldor_ctx *c)
     free(c);
 }
 
-int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
-                  const voldor_params *p, double *poses, float *depth, float *rigidness,
-                  double *loglik, void *stream)
+// enqueue one window on s; host-side argument errors are returned at once,
+// device-side ones end up in c->status (and in *status_out if given)
+static int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                          const voldor_params *p, double *poses, float *depth, float *rigidness,
+                          double *loglik, int32_t *status_out, hipStream_t s)
 {
     if (!c || !flows || !poses || !depth || !rigidness) return VOLDOR_EINVAL;
     if (((uintptr_t)flows & 7) != 0) return VOLDOR_EINVAL;
     if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
     if (p->n_pose_groups > c->S_max) return VOLDOR_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     const float2 *X = (const float2 *)flows;
     WinDims d = dims(T, H, W, K);
     const EmisParams e = emis(K, p);
     const PoseParams pp = pose_params(p);
+    c->last_stream = s;
+    c->tw_cur = (int)(c->tw_count % kTimingRing);
     c->n_ev = 0;
     mark(c, s, kPhaseNone);
     int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
@@ -300,23 +312,61 @@ int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const 
         rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, loglik, s);
         mark(c, s, kPhaseLL);
     }
+    if (rc == 0 && status_out) {
+        hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, c->status, status_out);
+        if (hipGetLastError() != hipSuccess) rc = VOLDOR_EDEVICE;
+    }
+    if (c->timing) {
+        c->ev_n[c->tw_cur] = c->n_ev;
+        ++c->tw_count;
+    }
+    return rc;
+}
+
+int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                  const voldor_params *p, double *poses, float *depth, float *rigidness,
+                  double *loglik, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, nullptr, s);
     if (rc != 0) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
-    collect_timing(c);
+    if (c->timing) slot_timing(c, c->tw_cur, c->last_ms);
     int st = 0;
     if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
     return st;
+}
+
+int voldor_window_async(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                        const voldor_params *p, double *poses, float *depth, float *rigidness,
+                        double *loglik, int32_t *status_out, void *stream)
+{
+    if (!status_out || ((uintptr_t)status_out & 3) != 0) return VOLDOR_EINVAL;
+    return window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, status_out,
+                          (hipStream_t)stream);
 }
 
 int voldor_set_timing(voldor_ctx *c, int enable)
 {
     if (!c) return VOLDOR_EINVAL;
     if (enable && !c->timing) {
-        for (int i = 0; i < 256; ++i)
-            if (hipEventCreate(&c->ev[i]) != hipSuccess) return VOLDOR_EDEVICE;
+        c->ev = (hipEvent_t *)calloc((size_t)kTimingRing * kEvPerWin, sizeof(hipEvent_t));
+        if (!c->ev) return VOLDOR_ENOMEM;
+        for (int i = 0; i < kTimingRing * kEvPerWin; ++i)
+            if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
+                free(c->ev);
+                c->ev = nullptr;
+                return VOLDOR_EDEVICE;
+            }
+        for (int w = 0; w < kTimingRing; ++w) c->ev_n[w] = 0;
+        c->tw_count = 0;
         c->timing = 1;
     } else if (!enable && c->timing) {
-        for (int i = 0; i < 256; ++i) (void)hipEventDestroy(c->ev[i]);
+        (void)hipDeviceSynchronize();
+        for (int i = 0; i < kTimingRing * kEvPerWin; ++i) (void)hipEventDestroy(c->ev[i]);
+        free(c->ev);
+        c->ev = nullptr;
         c->timing = 0;
     }
     return VOLDOR_OK;
@@ -326,6 +376,26 @@ int voldor_last_timing(voldor_ctx *c, double *out)
 {
     if (!c || !out) return VOLDOR_EINVAL;
     for (int i = 0; i < 8; ++i) out[i] = c->last_ms[i];
+    return VOLDOR_OK;
+}
+
+int voldor_timing_summary(voldor_ctx *c, double *out, int *n_windows)
+{
+    if (!c || !out) return VOLDOR_EINVAL;
+    for (int i = 0; i < 8; ++i) out[i] = 0.0;
+    if (n_windows) *n_windows = 0;
+    if (!c->timing) return VOLDOR_EINVAL;
+    if (c->tw_count == 0) return VOLDOR_OK;
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess) return VOLDOR_EDEVICE;
+    const long long n = c->tw_count < kTimingRing ? c->tw_count : kTimingRing;
+    for (long long k = c->tw_count - n; k < c->tw_count; ++k) {
+        double ms8[8];
+        slot_timing(c, (int)(k % kTimingRing), ms8);
+        for (int i = 0; i < 8; ++i) out[i] += ms8[i] / (double)n;
+    }
+    slot_timing(c, (int)((c->tw_count - 1) % kTimingRing), c->last_ms);
+    if (n_windows) *n_windows = (int)n;
+    c->tw_count = 0;
     return VOLDOR_OK;
 }
 

@@ -19,6 +19,8 @@ constexpr int kLLBlocks = 1024;     // partial sums of the log-likelihood
 
 // Device status word values (mirror voldor_status).
 enum : int { kStatusOk = 0, kStatusDegenerate = -4 };
+constexpr int kTimingRing = 32;   // windows whose phase events are kept
+constexpr int kEvPerWin = 128;    // events per window, at most
 
 // Window-level device parameters shared by all kernels of one call.
 struct WinDims {
@@ -65,12 +67,17 @@ struct voldor_ctx {
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
     float *theta_tmp;      // [H_max W_max]
-    // optional phase timing of voldor_window (HIP events on the caller's stream)
+    // optional phase timing of windows: HIP events on the caller's stream, one
+    // ring slot per window so that windows enqueued back to back keep theirs
     int timing;
-    int n_ev;
-    hipEvent_t ev[256];
-    int ev_phase[256];     // phase of the interval that ends at ev[i]
+    int n_ev;              // events of the window being recorded
+    int tw_cur;            // its ring slot
+    long long tw_count;    // windows recorded since the last summary
+    hipEvent_t *ev;        // [kTimingRing][kEvPerWin]
+    int ev_phase[vo::kTimingRing][vo::kEvPerWin];   // phase of the interval that ends at an event
+    int ev_n[vo::kTimingRing];
     double last_ms[8];
+    hipStream_t last_stream;
 };
 
 namespace vo {

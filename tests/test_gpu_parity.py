@@ -253,3 +253,37 @@ def test_window_parity_cpu_sized_workload(vo, torch):
     assert r["depth_med"] <= 1e-3
     assert r["rig_p999"] <= 1e-4
     assert r["ll"] <= 1e-5
+
+
+def test_window_async_matches_sync(vo, torch):
+    # two different windows enqueued back to back without a host wait equal the
+    # synchronous calls bit for bit; each reports its status, and the phase
+    # summary covers both
+    T, H, W = 4, 64, 96
+    kw = dict(n_iters=2, n_pose_groups=256)
+    p = vo.default_params(**kw)
+    ws = [synthflow.make_window("small", sd, T=T, H=H, W=W) for sd in (3, 4)]
+    fl = [torch.from_numpy(w["flows"]).cuda() for w in ws]
+    s = vo.Solver(T, H, W, 256)
+    ref = [tuple(x.clone() for x in s.window(f, w["K"], p)) for f, w in zip(fl, ws)]
+    s.set_timing(True)
+    outs = [(torch.empty((T, 12), dtype=torch.float64, device="cuda"),
+             torch.empty((H, W), dtype=torch.float32, device="cuda"),
+             torch.empty((T, H, W), dtype=torch.float32, device="cuda"),
+             torch.empty(2, dtype=torch.float64, device="cuda")) for _ in ws]
+    status = torch.full((2,), -99, dtype=torch.int32, device="cuda")
+    for k in range(2):
+        s.window_async(fl[k], ws[k]["K"], p, outs[k], status[k])
+    ph, n = s.timing_summary()
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0, 0]
+    assert n == 2 and ph["window"] > 0 and ph["sweep_launches"] == 4 * 2
+    for k in range(2):
+        for a, b in zip(outs[k], ref[k]):
+            assert torch.equal(a, b)
+    # a degenerate window (every flow missing) reports through its status element
+    bad = torch.full_like(fl[0], float("nan"))
+    s.window_async(bad, ws[0]["K"], p, outs[0], status[0])
+    torch.cuda.synchronize()
+    assert int(status[0]) == -4 == s.window_status(bad, ws[0]["K"], p)
+    s.set_timing(False)

@@ -1,0 +1,79 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/voldor.h declares, the Python binding knows each of them, and the
+host-only calls and argument checks answer before any device work."""
+import ctypes as C
+import os
+import re
+import shutil
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "voldor.h")
+
+
+def declared():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(voldor_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def vo():
+    import paper_2104_06789_amd as m
+    if not os.path.exists(m._LIB_PATH):
+        if shutil.which(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")) is None:
+            pytest.skip("libvoldor.so is not built and hipcc is not available")
+        from paper_2104_06789_amd import build
+        build.build()
+    m.lib()
+    return m
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ("voldor_window", "voldor_window_async", "voldor_sweep", "voldor_pose_step",
+              "voldor_bootstrap", "voldor_emission", "voldor_philox", "voldor_timing_summary"):
+        assert n in names
+
+
+def test_library_exports_every_declared_function(vo):
+    raw = C.CDLL(vo._LIB_PATH)
+    missing = [n for n in declared() if not hasattr(raw, n)]
+    assert not missing
+
+
+def test_binding_types_every_declared_function(vo):
+    lib = vo.lib()
+    for n in declared():
+        fn = getattr(lib, n)
+        assert fn.argtypes is not None, n
+
+
+def test_params_default_and_status_strings(vo):
+    p = vo.default_params()
+    assert p.struct_size == C.sizeof(vo.Params)
+    assert p.n_iters == 3 and p.sweeps_per_iter == 4 and p.gamma == 0.9
+    assert p.sigma2_trans == 0.1 and p.sigma2_rot == 0.004
+    assert vo.status_str(0) == "ok"
+    assert vo.status_str(-4) == "degenerate bootstrap"
+    assert vo.status_str(12345) == "unknown status"
+
+
+def test_host_argument_checks(vo):
+    lib = vo.lib()
+    ctx = C.c_void_p()
+    # sizes outside the context limits are refused before any device call
+    assert lib.voldor_create(C.byref(ctx), 0, 64, 64, 64) == vo.EINVAL
+    assert lib.voldor_create(C.byref(ctx), 17, 64, 64, 64) == vo.EINVAL
+    assert lib.voldor_create(C.byref(ctx), 4, 8, 64, 64) == vo.EINVAL
+    assert lib.voldor_create(C.byref(ctx), 4, 64, 64, 8193) == vo.EINVAL
+    assert lib.voldor_create(None, 4, 64, 64, 64) == vo.EINVAL
+    K = (C.c_double * 4)(100.0, 100.0, 32.0, 32.0)
+    p = vo.default_params()
+    args = (None, None, 2, 64, 64, K, C.byref(p), None, None, None, None)
+    assert lib.voldor_window(*args, None) == vo.EINVAL
+    assert lib.voldor_window_async(*args, None, None) == vo.EINVAL
+    out = (C.c_double * 8)()
+    assert lib.voldor_last_timing(None, out) == vo.EINVAL
+    assert lib.voldor_timing_summary(None, out, None) == vo.EINVAL
+    assert lib.voldor_set_timing(None, 1) == vo.EINVAL
