@@ -247,7 +247,7 @@ __host__ __device__ inline int sweep_region2_words(int T, int L)
     return w;
 }
 
-__global__ void __launch_bounds__(kSweepThreads) k_sweep(SweepArgs a)
+__global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
     extern __shared__ float lds[];
