@@ -74,14 +74,107 @@ def _pose_error(poses, gt):
     return float(np.mean(rot)), float(np.mean(tdir))
 
 
+BATCH_ITERS, BATCH_GROUPS = 4, 2048
+
+
+def run_batch(args):
+    """One step = one batch of windows of uneven shape and T solved by
+    voldor_window_batch over concurrent streams (one HIP graph per step)."""
+    import synthflow
+    # generated in forked workers before anything touches the GPU
+    wins = synthflow.make_batch(args.batch, args.seed, workers=min(16, os.cpu_count() or 1))
+    import numpy as np
+    import torch
+
+    import paper_2104_06789_amd as vo
+
+    dev = torch.device("cuda:0")
+    p = vo.default_params(n_iters=BATCH_ITERS, n_pose_groups=BATCH_GROUPS, seed=args.seed)
+    flows = [torch.from_numpy(w["flows"]).to(dev) for w in wins]
+    shapes = [tuple(f.shape[:3]) for f in flows]
+    outs = [vo.Batch.outputs(T, H, W) for T, H, W in shapes]
+    items = [(f, w["K"], o) for f, w, o in zip(flows, wins, outs)]
+    Tm, Hm, Wm = (max(x[k] for x in shapes) for k in range(3))
+    status = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.Stream()
+    solver = vo.Batch(args.lanes, Tm, Hm, Wm, BATCH_GROUPS, graph=not args.no_graph)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            solver.solve(items, p, status, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            solver.solve(items, p, status, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bad = [int(x) for x in status.cpu().tolist() if x != 0]
+    if bad:
+        print(f"window status {vo.status_str(bad[0])} in {len(bad)} of {len(wins)} windows", file=sys.stderr)
+        sys.exit(1)
+    ms = (t1 - t0) * 1e3 / max(args.steps, 1)
+    pf_win = [T * H * W for T, H, W in shapes]
+    pf = sum(pf_win) * BATCH_ITERS
+    value = pf / (ms * 1e-3)
+    # every sweep of the batch: 3 emission evaluations per pixel-frame
+    alg_ops = 3.0 * sum(pf_win) * EMISSION_VALU_OPS * BATCH_ITERS * p.sweeps_per_iter
+    achieved = alg_ops / (ms * 1e-3) / 1e12
+    errs = [_pose_error(o[0].cpu().numpy(), w["poses"]) for o, w in zip(outs, wins)]
+    mix = {}
+    for T, H, W in shapes:
+        mix[f"{W}x{H}"] = mix.get(f"{W}x{H}", 0) + 1
+    line = {
+        "metric": "pixel-frame EM updates/s",
+        "value": value,
+        "unit": "pixel-frame updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch: {len(wins)} windows of shapes drawn from 320x240, 640x480, "
+                               f"1242x375 and T from 4..8, {BATCH_ITERS} EM iterations, {BATCH_GROUPS} P3P "
+                               f"groups/frame, seed {args.seed}",
+                   "windows": len(wins), "shapes": mix, "frames": sum(x[0] for x in shapes),
+                   "lanes": args.lanes, "graph": not args.no_graph,
+                   "parallelism": "single GPU, one batch per step over concurrent streams"},
+        "windows_per_s": len(wins) * 1e3 / ms,
+        "pose_error_vs_gt": {"rot_rad": float(np.mean([e[0] for e in errs])),
+                             "tdir_rad": float(np.mean([e[1] for e in errs]))},
+        "roofline": {"bound": "alu", "kernel": "k_sweep (all sweeps of the batch over the whole step)",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "alg_ops_per_step": alg_ops},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k = int(np.argmin(pf_win))   # the smallest window of the batch
+        c0 = time.perf_counter()
+        st, *_ = oracle.window(wins[k]["flows"], wins[k]["K"],
+                               oracle.params(n_iters=BATCH_ITERS, n_pose_groups=BATCH_GROUPS, seed=args.seed))
+        c1 = time.perf_counter()
+        T, H, W = shapes[k]
+        line["cpu_baseline"] = {"value": pf_win[k] * BATCH_ITERS / (c1 - c0), "unit": "pixel-frame updates/s",
+                                "cores": 1, "kind": "oracle",
+                                "sample": f"window {k} of the batch (T={T}, {W}x{H}, {BATCH_ITERS} iterations), "
+                                          f"FP64 oracle, single thread, {c1 - c0:.1f} s, status {st}"}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small"])
+    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
+    ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
+    ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -89,6 +182,9 @@ def main():
         print("bench.py measures one GPU: windows are independent, so more GPUs would "
               "each solve their own share; runs with --gpus > 1 are not supported.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch

@@ -114,6 +114,46 @@ int voldor_window_async(voldor_ctx *ctx, const float *flows, int T, int H, int W
                         const voldor_params *p, double *poses, float *depth, float *rigidness,
                         double *loglik, int32_t *status_out, void *stream);
 
+/* ---- batches: many windows of uneven shape and T ------------------------- */
+
+/* One window of a batch: the arguments of voldor_window for that window. */
+typedef struct {
+    const float *flows;    /* device float32 [T][H][W][2], 8-byte aligned           */
+    int32_t T, H, W;
+    double K[4];           /* fx, fy, cx, cy (pixels)                                */
+    double *poses;         /* device double [T][12] (output)                         */
+    float *depth;          /* device float [H][W] (output)                           */
+    float *rigidness;      /* device float [T][H][W] (output)                        */
+    double *loglik;        /* device double [2] or NULL (output)                     */
+} voldor_window_desc;
+
+/* Batch solver: `lanes` (1..8) HIP streams, each with the workspace of a
+ * context sized T_max x H_max x W_max x S_max.  Windows are independent, so a
+ * batch is spread over the lanes (largest first, onto the least loaded lane)
+ * and the lanes run concurrently: one window's latency-bound pose steps
+ * overlap the sweeps of the others.  flags: VOLDOR_BATCH_GRAPH captures each
+ * distinct batch call into a HIP graph on first use and replays it when the
+ * same call (descriptors, count, parameters, status array, stream) comes again.
+ * Returns VOLDOR_EINVAL / VOLDOR_ENOMEM / VOLDOR_EDEVICE like voldor_create. */
+typedef struct voldor_batch voldor_batch;
+enum { VOLDOR_BATCH_GRAPH = 1 };
+int voldor_batch_create(voldor_batch **out, int lanes, int T_max, int H_max, int W_max, int S_max,
+                        int flags);
+void voldor_batch_destroy(voldor_batch *b);
+
+/* Solve n windows (Table 1 for each; the same parameters for all), enqueued
+ * on `stream` without waiting: the batch starts after the work already on
+ * `stream` and the stream continues after all of it.
+ *   wins        host array of n descriptors (read during the call only)
+ *   status_out  device int32 [n], 4-byte aligned: window i's device status
+ * Results are those of voldor_window on each window, bit for bit.  Host-side
+ * errors (VOLDOR_EINVAL for any bad descriptor, before anything is enqueued;
+ * VOLDOR_EDEVICE) are returned.  Batches of one batch object run one after
+ * another in stream order; calls must not overlap on the host.  Graph mode
+ * needs a stream other than the null stream. */
+int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
+                        int32_t *status_out, void *stream);
+
 /* Phase timing of windows with HIP events recorded on their stream, kept for
  * the last 32 windows.  voldor_set_timing(ctx, 1) creates the events (0
  * destroys them).  Phases, in milliseconds: [0] bootstrap, [1] pose steps,

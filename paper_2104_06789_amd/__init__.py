@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Params", "default_params", "Solver", "philox", "lib", "status_str", "VoldorError"]
+__all__ = ["Params", "WindowDesc", "default_params", "Solver", "Batch", "philox", "lib", "status_str",
+           "VoldorError"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libvoldor.so")
@@ -39,6 +40,17 @@ class Params(C.Structure):
         ("seed", C.c_uint64),
     ]
 
+
+class WindowDesc(C.Structure):
+    """Mirror of voldor_window_desc (include/voldor.h)."""
+    _fields_ = [
+        ("flows", C.c_void_p), ("T", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+        ("K", C.c_double * 4), ("poses", C.c_void_p), ("depth", C.c_void_p),
+        ("rigidness", C.c_void_p), ("loglik", C.c_void_p),
+    ]
+
+
+BATCH_GRAPH = 1
 
 _lib = None
 
@@ -70,6 +82,9 @@ def lib():
         "voldor_set_timing": (i, [vp, i]),
         "voldor_last_timing": (i, [vp, dp]),
         "voldor_timing_summary": (i, [vp, dp, ip]),
+        "voldor_batch_create": (i, [C.POINTER(vp), i, i, i, i, i, i]),
+        "voldor_batch_destroy": (None, [vp]),
+        "voldor_window_batch": (i, [vp, C.POINTER(WindowDesc), i, P, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -295,3 +310,55 @@ def philox(ctr, key0, key1, stream=None):
     _check(lib().voldor_philox(_ptr(ctr), int(key0), int(key1), _ptr(out), ctr.shape[0], _stream(stream)),
            "voldor_philox")
     return out
+
+
+class Batch:
+    """Batch solver over `lanes` concurrent streams (voldor_batch_* in the C ABI);
+    each lane owns a workspace for windows up to T_max x H_max x W_max."""
+
+    def __init__(self, lanes, T_max, H_max, W_max, S_max=4096, graph=False):
+        ctx = C.c_void_p()
+        _check(lib().voldor_batch_create(C.byref(ctx), lanes, T_max, H_max, W_max, S_max,
+                                         BATCH_GRAPH if graph else 0), "voldor_batch_create")
+        self._b = ctx
+        self._keep = None
+
+    def __del__(self):
+        if getattr(self, "_b", None):
+            lib().voldor_batch_destroy(self._b)
+            self._b = None
+
+    @staticmethod
+    def outputs(T, H, W, device="cuda"):
+        """Output tensors (poses, depth, rigidness, loglik) for one window."""
+        import torch
+        return (torch.empty((T, 12), dtype=torch.float64, device=device),
+                torch.empty((H, W), dtype=torch.float32, device=device),
+                torch.empty((T, H, W), dtype=torch.float32, device=device),
+                torch.empty(2, dtype=torch.float64, device=device))
+
+    def solve(self, windows, params, status, stream=None):
+        """Enqueue a batch.  windows: list of (flows [T,H,W,2] CUDA float32, K (fx, fy,
+        cx, cy), out) with out = (poses, depth, rigidness, loglik or None) as from
+        outputs(); status: CUDA int32 tensor of len(windows) elements.  Returns
+        without waiting; the tensors must stay alive until the stream has run it."""
+        import torch
+        n = len(windows)
+        if not (isinstance(status, torch.Tensor) and status.is_cuda and status.dtype == torch.int32
+                and status.is_contiguous() and status.numel() >= n):
+            raise TypeError("status must be a contiguous CUDA int32 tensor of len(windows) elements")
+        descs = (WindowDesc * n)()
+        for i, (flows, K, out) in enumerate(windows):
+            flows = _flows(flows)
+            T, H, W, _ = flows.shape
+            poses, depth, rig, ll = out
+            d = descs[i]
+            d.flows = flows.data_ptr()
+            d.T, d.H, d.W = T, H, W
+            for k in range(4):
+                d.K[k] = float(K[k])
+            d.poses, d.depth, d.rigidness = poses.data_ptr(), depth.data_ptr(), rig.data_ptr()
+            d.loglik = ll.data_ptr() if ll is not None else None
+        self._keep = (windows, status)
+        _check(lib().voldor_window_batch(self._b, descs, n, C.byref(params), _ptr(status), _stream(stream)),
+               "voldor_window_batch")

@@ -269,16 +269,27 @@ void voldor_destroy(voldor_ctx *c)
     free(c);
 }
 
+}  // extern "C"
+
+namespace vo {
+
+bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                    const voldor_params *p, const double *poses, const float *depth,
+                    const float *rigidness)
+{
+    if (!c || !flows || !poses || !depth || !rigidness) return false;
+    if (((uintptr_t)flows & 7) != 0) return false;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return false;
+    return p->n_pose_groups <= c->S_max;
+}
+
 // enqueue one window on s; host-side argument errors are returned at once,
 // device-side ones end up in c->status (and in *status_out if given)
-static int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
-                          const voldor_params *p, double *poses, float *depth, float *rigidness,
-                          double *loglik, int32_t *status_out, hipStream_t s)
+int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                   const voldor_params *p, double *poses, float *depth, float *rigidness,
+                   double *loglik, int32_t *status_out, hipStream_t s)
 {
-    if (!c || !flows || !poses || !depth || !rigidness) return VOLDOR_EINVAL;
-    if (((uintptr_t)flows & 7) != 0) return VOLDOR_EINVAL;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
-    if (p->n_pose_groups > c->S_max) return VOLDOR_EINVAL;
+    if (!window_args_ok(c, flows, T, H, W, K, p, poses, depth, rigidness)) return VOLDOR_EINVAL;
     const float2 *X = (const float2 *)flows;
     WinDims d = dims(T, H, W, K);
     const EmisParams e = emis(K, p);
@@ -322,6 +333,10 @@ static int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W
     }
     return rc;
 }
+
+}  // namespace vo
+
+extern "C" {
 
 int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                   const voldor_params *p, double *poses, float *depth, float *rigidness,

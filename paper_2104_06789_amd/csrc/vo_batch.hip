@@ -1,0 +1,202 @@
+// vo_batch.hip -- batches of independent windows (Table 1 per window) over
+// concurrent HIP streams.
+//
+// A window's pose steps are a chain of small, latency-bound launches (one
+// workgroup per mean-shift), while its sweeps fill the whole chip.  Windows
+// share nothing, so a batch is spread over `lanes` streams, each owning the
+// workspace of one context; the hardware queues run the lanes side by side and
+// one window's pose chain overlaps the sweeps of the others.  Windows of one
+// lane run in stream order and reuse its workspace.  Assignment is
+// longest-processing-time first: windows by decreasing cost, each onto the
+// lane with the least cost so far.  With VOLDOR_BATCH_GRAPH the whole
+// fork/lanes/join sequence is captured into a HIP graph once per distinct call
+// and replayed, so the host submits one graph instead of every launch.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "vo_internal.hpp"
+
+using namespace vo;
+
+namespace {
+
+constexpr int kMaxLanes = 8;
+
+// relative cost of a window: its pixel-frames (sweeps, rigidness) plus a
+// fixed share per frame for the pose chain (about 0.1 Mpixel-frames of sweep
+// time per frame and iteration)
+double window_cost(const voldor_window_desc &w)
+{
+    return (double)w.T * ((double)w.H * (double)w.W + 1.0e5);
+}
+
+}  // namespace
+
+struct voldor_batch {
+    int lanes;
+    int flags;
+    voldor_ctx *ctx[kMaxLanes];
+    hipStream_t st[kMaxLanes];
+    hipEvent_t fork;
+    hipEvent_t join[kMaxLanes];
+    // graph of the last captured call, with the bytes of that call
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    std::vector<unsigned char> key;
+};
+
+namespace {
+
+void drop_graph(voldor_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->key.clear();
+}
+
+void assign_lanes(const voldor_window_desc *w, int n, int lanes, std::vector<int> &order,
+                  std::vector<int> &lane_of)
+{
+    order.resize(n);
+    lane_of.resize(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return window_cost(w[a]) > window_cost(w[b]); });
+    double load[kMaxLanes] = {0};
+    for (int i : order) {
+        int l = 0;
+        for (int k = 1; k < lanes; ++k)
+            if (load[k] < load[l]) l = k;
+        lane_of[i] = l;
+        load[l] += window_cost(w[i]);
+    }
+}
+
+// fork the lanes off s, enqueue every window on its lane, join them back to s
+int batch_enqueue(voldor_batch *b, const voldor_window_desc *w, int n, const voldor_params *p,
+                  int32_t *status_out, hipStream_t s)
+{
+    const int used = std::min(b->lanes, n);
+    std::vector<int> order, lane_of;
+    assign_lanes(w, n, used, order, lane_of);
+    if (hipEventRecord(b->fork, s) != hipSuccess) return VOLDOR_EDEVICE;
+    for (int l = 0; l < used; ++l)
+        if (hipStreamWaitEvent(b->st[l], b->fork, 0) != hipSuccess) return VOLDOR_EDEVICE;
+    int rc = VOLDOR_OK;
+    for (int k = 0; k < n && rc == VOLDOR_OK; ++k) {
+        const int i = order[k], l = lane_of[i];
+        const voldor_window_desc &d = w[i];
+        rc = window_enqueue(b->ctx[l], d.flows, d.T, d.H, d.W, d.K, p, d.poses, d.depth, d.rigidness,
+                            d.loglik, status_out + i, b->st[l]);
+    }
+    // the join is recorded even after a failed launch, so that s never runs
+    // ahead of work that did get enqueued
+    for (int l = 0; l < used; ++l) {
+        if (hipEventRecord(b->join[l], b->st[l]) != hipSuccess) return VOLDOR_EDEVICE;
+        if (hipStreamWaitEvent(s, b->join[l], 0) != hipSuccess) return VOLDOR_EDEVICE;
+    }
+    return rc;
+}
+
+void call_key(const voldor_window_desc *w, int n, const voldor_params *p, const int32_t *status_out,
+              hipStream_t s, std::vector<unsigned char> &key)
+{
+    key.clear();
+    auto put = [&](const void *v, size_t bytes) {
+        const unsigned char *c = (const unsigned char *)v;
+        key.insert(key.end(), c, c + bytes);
+    };
+    put(&n, sizeof n);
+    put(&status_out, sizeof status_out);
+    put(&s, sizeof s);
+    put(p, sizeof *p);
+    put(w, sizeof(voldor_window_desc) * (size_t)n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int voldor_batch_create(voldor_batch **out, int lanes, int T_max, int H_max, int W_max, int S_max,
+                        int flags)
+{
+    if (!out) return VOLDOR_EINVAL;
+    *out = nullptr;
+    if (lanes < 1 || lanes > kMaxLanes || (flags & ~VOLDOR_BATCH_GRAPH) != 0) return VOLDOR_EINVAL;
+    voldor_batch *b = new (std::nothrow) voldor_batch();
+    if (!b) return VOLDOR_ENOMEM;
+    b->lanes = lanes;
+    b->flags = flags;
+    int rc = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+    for (int l = 0; l < lanes && rc == VOLDOR_OK; ++l) {
+        rc = voldor_create(&b->ctx[l], T_max, H_max, W_max, S_max);
+        if (rc == VOLDOR_OK && hipStreamCreateWithFlags(&b->st[l], hipStreamNonBlocking) != hipSuccess)
+            rc = VOLDOR_EDEVICE;
+        if (rc == VOLDOR_OK && hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming) != hipSuccess)
+            rc = VOLDOR_EDEVICE;
+    }
+    if (rc != VOLDOR_OK) {
+        voldor_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return VOLDOR_OK;
+}
+
+void voldor_batch_destroy(voldor_batch *b)
+{
+    if (!b) return;
+    for (int l = 0; l < b->lanes; ++l)
+        if (b->st[l]) (void)hipStreamSynchronize(b->st[l]);
+    drop_graph(b);
+    for (int l = 0; l < b->lanes; ++l) {
+        if (b->join[l]) (void)hipEventDestroy(b->join[l]);
+        if (b->st[l]) (void)hipStreamDestroy(b->st[l]);
+        voldor_destroy(b->ctx[l]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+}
+
+int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
+                        int32_t *status_out, void *stream)
+{
+    if (!b || !wins || n < 1 || !status_out || ((uintptr_t)status_out & 3) != 0) return VOLDOR_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const voldor_window_desc &d = wins[i];
+        if (!window_args_ok(b->ctx[0], d.flows, d.T, d.H, d.W, d.K, p, d.poses, d.depth, d.rigidness))
+            return VOLDOR_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!(b->flags & VOLDOR_BATCH_GRAPH) || s == nullptr) return batch_enqueue(b, wins, n, p, status_out, s);
+
+    std::vector<unsigned char> key;
+    call_key(wins, n, p, status_out, s, key);
+    if (b->exec && key == b->key) return hipGraphLaunch(b->exec, s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+    drop_graph(b);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLDOR_EDEVICE;
+    const int rc = batch_enqueue(b, wins, n, p, status_out, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (rc != VOLDOR_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != VOLDOR_OK ? rc : VOLDOR_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return VOLDOR_EDEVICE;
+    }
+    b->graph = g;
+    b->exec = ex;
+    b->key.swap(key);
+    return hipGraphLaunch(b->exec, s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+}  // extern "C"

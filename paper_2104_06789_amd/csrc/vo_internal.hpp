@@ -82,6 +82,14 @@ struct voldor_ctx {
 
 namespace vo {
 
+// ---- whole window (vo_api.hip)
+bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                    const voldor_params *p, const double *poses, const float *depth,
+                    const float *rigidness);
+int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                   const voldor_params *p, double *poses, float *depth, float *rigidness,
+                   double *loglik, int32_t *status_out, hipStream_t s);
+
 // ---- sweep / emission (vo_sweep.hip)
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
                  const WinDims &d, const EmisParams &e, float gamma, uint64_t seed,

@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["WindowSpec", "SPECS", "make_window", "rot_axis_angle"]
+__all__ = ["WindowSpec", "SPECS", "make_window", "make_batch", "BATCH_SHAPES", "rot_axis_angle"]
 
 
 @dataclass
@@ -200,12 +200,27 @@ def _driving_depth(spec, scene, M, rays, frame):
         sg = (scene["ground_y"] - o[1]) / d[..., 1]
     sg = np.where((sg > 0) & np.isfinite(sg), sg, np.inf)
     best = np.minimum(best, sg)
+    H, W = rays.shape[:2]
     for k, (lo, hi) in enumerate(scene["boxes"]):
         off = scene["vel"][k] * frame
-        s = _slab(o, d, lo + off, hi + off)
-        take = s < best
-        best = np.where(take, s, best)
-        obj = np.where(take, k, obj)
+        blo, bhi = lo + off, hi + off
+        # pixels whose rays can meet the box: for a box wholly in front of the
+        # camera, the bounding rectangle of its projected corners (plus a
+        # margin); the test itself is the same elementwise slab test
+        corners = np.array([[a, b, c] for a in (blo[0], bhi[0]) for b in (blo[1], bhi[1])
+                            for c in (blo[2], bhi[2])])
+        pc = corners @ R.T + t
+        y0, y1, x0, x1 = 0, H, 0, W
+        if np.all(pc[:, 2] > 1e-6):
+            u, v = _project(spec, pc)
+            x0, x1 = max(int(np.floor(u.min())) - 2, 0), min(int(np.ceil(u.max())) + 3, W)
+            y0, y1 = max(int(np.floor(v.min())) - 2, 0), min(int(np.ceil(v.max())) + 3, H)
+            if x0 >= x1 or y0 >= y1:
+                continue
+        s = _slab(o, d[y0:y1, x0:x1], blo, bhi)
+        take = s < best[y0:y1, x0:x1]
+        best[y0:y1, x0:x1] = np.where(take, s, best[y0:y1, x0:x1])
+        obj[y0:y1, x0:x1] = np.where(take, k, obj[y0:y1, x0:x1])
     with np.errstate(divide="ignore", invalid="ignore"):
         sb = (spec.d_max - o[2]) / d[..., 2]
     sb = np.where((sb > 0) & np.isfinite(sb), sb, 10.0 * spec.d_max)
@@ -367,3 +382,33 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
         "outlier": outlier,
         "spec": spec,
     }
+
+
+# shapes of a mixed batch: (generator, W, H); the 320x240 windows use the
+# indoor generator with its intrinsics scaled to the smaller image
+BATCH_SHAPES = (("indoor", 320, 240), ("indoor", 640, 480), ("driving", 1242, 375))
+
+
+def _batch_item(args):
+    name, sd, noise, outliers, T, H, W = args
+    return make_window(name, sd, noise=noise, outliers=outliers, T=T, H=H, W=W)
+
+
+def make_batch(n=32, seed=0, shapes=BATCH_SHAPES, T_range=(4, 8), noise=True, outliers=True, workers=1):
+    """n independent windows, each with a shape drawn uniformly from `shapes`
+    and T drawn uniformly from T_range (inclusive), generated as make_window
+    does for that shape; window i uses seed (seed << 16) + i.  Returns a list of
+    make_window dicts.  workers > 1 generates them in forked worker processes
+    (call it before the process touches a GPU)."""
+    rng = np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0xBA7C0000)))
+    jobs = []
+    for i in range(n):
+        name, W, H = shapes[int(rng.integers(len(shapes)))]
+        T = int(rng.integers(T_range[0], T_range[1] + 1))
+        jobs.append((name, (seed << 16) + i, noise, outliers, T, H, W))
+    if workers <= 1:
+        return [_batch_item(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(workers, n)) as pool:
+        return pool.map(_batch_item, jobs, chunksize=1)
+

@@ -77,3 +77,42 @@ def test_host_argument_checks(vo):
     assert lib.voldor_last_timing(None, out) == vo.EINVAL
     assert lib.voldor_timing_summary(None, out, None) == vo.EINVAL
     assert lib.voldor_set_timing(None, 1) == vo.EINVAL
+
+
+def test_batch_host_argument_checks(vo):
+    lib = vo.lib()
+    b = C.c_void_p()
+    assert lib.voldor_batch_create(C.byref(b), 0, 4, 64, 64, 64, 0) == vo.EINVAL
+    assert lib.voldor_batch_create(C.byref(b), 9, 4, 64, 64, 64, 0) == vo.EINVAL
+    assert lib.voldor_batch_create(C.byref(b), 2, 4, 64, 64, 64, 2) == vo.EINVAL   # unknown flag
+    assert lib.voldor_batch_create(None, 2, 4, 64, 64, 64, 0) == vo.EINVAL
+    p = vo.default_params()
+    descs = (vo.WindowDesc * 1)()
+    assert lib.voldor_window_batch(None, descs, 1, C.byref(p), None, None) == vo.EINVAL
+    lib.voldor_batch_destroy(None)
+
+
+def test_abi_struct_layout_matches_binding(tmp_path):
+    # the C compiler's view of the two structs the binding mirrors
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    import paper_2104_06789_amd as vo
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "voldor.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(voldor_window_desc),\n'
+        "    offsetof(voldor_window_desc, flows), offsetof(voldor_window_desc, T),\n"
+        "    offsetof(voldor_window_desc, K), offsetof(voldor_window_desc, poses),\n"
+        "    offsetof(voldor_window_desc, loglik), sizeof(voldor_params),\n"
+        "    offsetof(voldor_params, ms_tol), offsetof(voldor_params, depth_hi),\n"
+        "    offsetof(voldor_params, seed));\n  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    D, P = vo.WindowDesc, vo.Params
+    want = [C.sizeof(D), D.flows.offset, D.T.offset, D.K.offset, D.poses.offset, D.loglik.offset,
+            C.sizeof(P), P.ms_tol.offset, P.depth_hi.offset, P.seed.offset]
+    assert got == want
