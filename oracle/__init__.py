@@ -66,7 +66,8 @@ def lib():
         sig = {
             "or_params_size": (C.c_int, []),
             "or_philox4x64": (None, [u64p, u64p, u64p]),
-            "or_depth_sample": (C.c_double, [C.c_uint64, C.c_int64, C.c_int64, C.c_double, C.c_double]),
+            "or_depth_sample": (C.c_double, [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double,
+                                             C.c_double]),
             "or_fisk_logpdf": (C.c_double, [C.c_double, C.c_double, C.c_double]),
             "or_sym_eig": (None, [i, d, d, d]),
             "or_svd3": (None, [d, d, d, d]),
@@ -132,8 +133,8 @@ def philox(ctr, key):
     return o
 
 
-def depth_sample(seed, global_sweep, pixel, d_lo, d_hi):
-    return lib().or_depth_sample(seed, global_sweep, pixel, d_lo, d_hi)
+def depth_sample(seed, global_sweep, direction, x, y, d_lo, d_hi):
+    return lib().or_depth_sample(seed, global_sweep, direction, x, y, d_lo, d_hi)
 
 
 def fisk_logpdf(x, log_alpha, beta):

@@ -99,13 +99,21 @@ static int64_t index_from_u32(uint32_t u, int64_t n)
 }
 
 /* Random depth candidate (Sec. 5.1, sampling-propagation): log-uniform on
- * [d_lo, d_hi], one draw per pixel per sweep.  u = (u32 + 1/2) 2^-32. */
-double or_depth_sample(uint64_t seed, int64_t global_sweep, int64_t pixel,
+ * [d_lo, d_hi], one draw per pixel per sweep.  The pixel's coordinate along
+ * the sweep axis a (x for horizontal sweeps, dir 0/2; y for vertical ones)
+ * and across it b select the Philox block with counter (gsweep, b, a / 8, 0)
+ * and its 32-bit word a mod 8, words in the order hi(o0), lo(o0), hi(o1), ...;
+ * u = (word + 1/2) 2^-32. */
+double or_depth_sample(uint64_t seed, int64_t global_sweep, int dir, int x, int y,
                        double d_lo, double d_hi)
 {
     uint64_t o[4];
-    philox_draw(seed, PURPOSE_DEPTH, (uint64_t)global_sweep, (uint64_t)pixel, 0, 0, o);
-    double u = ((double)(uint32_t)(o[0] >> 32) + 0.5) * (1.0 / 4294967296.0);
+    const int a = (dir & 1) ? y : x, b = (dir & 1) ? x : y;
+    philox_draw(seed, PURPOSE_DEPTH, (uint64_t)global_sweep, (uint64_t)b, (uint64_t)(a / 8), 0, o);
+    const int m = a % 8;
+    const uint64_t v = o[m / 2];
+    const uint32_t word = (m % 2 == 0) ? (uint32_t)(v >> 32) : (uint32_t)v;
+    double u = ((double)word + 0.5) * (1.0 / 4294967296.0);
     return exp(log(d_lo) + u * (log(d_hi) - log(d_lo)));
 }
 
@@ -596,7 +604,7 @@ void or_sweep(const double *theta_in, double *theta_out, const float *flows, int
         for (int k = 0; k < L; ++k) {
             int j = chain_pixel(dir, H, W, c, k), x = j % W, y = j / W;
             double s_prev = mie_score(&F, p, M, q, x, y, prev[j]);
-            double smp = or_depth_sample(p->seed, global_sweep, j, d_lo, d_hi);
+            double smp = or_depth_sample(p->seed, global_sweep, dir, x, y, d_lo, d_hi);
             double s_smp = mie_score(&F, p, M, q, x, y, smp);
             double best = prev[j], s_best = s_prev;
             int ch = 0;
@@ -644,7 +652,7 @@ void or_sweep_check(const double *theta_in, const double *theta_cand, const floa
             int have[3] = {1, k > 0, 1};
             cand[0] = theta_in[j];
             cand[1] = k > 0 ? theta_cand[chain_pixel(dir, H, W, c, k - 1)] : 0;
-            cand[2] = or_depth_sample(p->seed, global_sweep, j, d_lo, d_hi);
+            cand[2] = or_depth_sample(p->seed, global_sweep, dir, x, y, d_lo, d_hi);
             double mass = 0;
             for (int i = 0; i < 3; ++i)
                 if (have[i]) {

@@ -282,13 +282,22 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     }
     const float llo = (float)log(a.range[0]);
     const float lrange = (float)(log(a.range[1]) - log(a.range[0]));
-    for (int k = tid; k < L; k += kSweepThreads) {
-        const int j = chain_pixel(dir, H, W, chain, k);
-        th[k] = a.theta_in[j];
-        uint64_t c[4] = {(uint64_t)a.gsweep, (uint64_t)j, 0ull, 0ull};
+    for (int k = tid; k < L; k += kSweepThreads) th[k] = a.theta_in[chain_pixel(dir, H, W, chain, k)];
+    // random depth, log-uniform: the 8 chain positions whose coordinate along
+    // the sweep axis is 8g .. 8g + 7 take the 32-bit words of the Philox block
+    // with counter (gsweep, chain, g, 0), hi before lo of each 64-bit output
+    for (int g = tid; g < (L + 7) / 8; g += kSweepThreads) {
+        uint64_t c[4] = {(uint64_t)a.gsweep, (uint64_t)chain, (uint64_t)g, 0ull};
         philox4x64_10(c, a.seed, kDepthStream);
-        const float u = ((float)(uint32_t)(c[0] >> 32) + 0.5f) * 2.3283064365386963e-10f;
-        sm[k] = expf(fmaf(u, lrange, llo));
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int ax = 8 * g + m;
+            if (ax < L) {
+                const uint32_t w = (m & 1) ? (uint32_t)c[m >> 1] : (uint32_t)(c[m >> 1] >> 32);
+                const float u = ((float)w + 0.5f) * 2.3283064365386963e-10f;
+                sm[dir >= 2 ? L - 1 - ax : ax] = expf(fmaf(u, lrange, llo));
+            }
+        }
     }
     __syncthreads();
 

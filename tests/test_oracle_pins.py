@@ -52,10 +52,36 @@ def test_philox_matches_numpy():
 
 def test_depth_sample_log_uniform():
     lo, hi = 0.5, 40.0
-    v = np.array([oracle.depth_sample(7, 3, j, lo, hi) for j in range(20000)])
+    v = np.array([oracle.depth_sample(7, 3, 0, x, y, lo, hi) for y in range(8) for x in range(2500)])
     assert v.min() >= lo and v.max() <= hi
     u = (np.log(v) - math.log(lo)) / (math.log(hi) - math.log(lo))
     assert scipy.stats.kstest(u, "uniform").pvalue > 1e-3
+    # the eight pixels that share a block draw different words
+    assert len(set(v[:8].tolist())) == 8
+
+
+def test_depth_sample_words_of_numpy_philox():
+    # pixel (x, y) of a sweep draws word a mod 8 (hi before lo of each 64-bit
+    # output) of the block with key (seed, 1) and counter (gsweep, b, a // 8, 0),
+    # a / b = coordinate along / across the sweep axis; numpy's Philox4x64-10
+    # supplies the block
+    lo, hi = 0.25, 64.0
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        seed, gs = int(rng.integers(0, 2**40)), int(rng.integers(0, 2**20))
+        d, x, y = int(rng.integers(4)), int(rng.integers(300)), int(rng.integers(300))
+        a, b = (y, x) if d & 1 else (x, y)
+        ctr = np.array([gs - 1 if gs > 0 else 2**64 - 1, b, a // 8, 0], dtype=np.uint64)
+        block = np.random.Philox(key=np.array([seed, 1], dtype=np.uint64), counter=ctr).random_raw(4)
+        w = int(block[(a % 8) // 2])
+        word = (w >> 32) if a % 2 == 0 else (w & 0xFFFFFFFF)
+        u = (word + 0.5) / 2.0**32
+        want = math.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))
+        assert oracle.depth_sample(seed, gs, d, x, y, lo, hi) == pytest.approx(want, rel=1e-14)
+    # the draw depends on the pixel and the sweep's axis, not on its sense
+    assert oracle.depth_sample(3, 9, 0, 17, 5, lo, hi) == oracle.depth_sample(3, 9, 2, 17, 5, lo, hi)
+    assert oracle.depth_sample(3, 9, 1, 17, 5, lo, hi) == oracle.depth_sample(3, 9, 3, 17, 5, lo, hi)
+    assert oracle.depth_sample(3, 9, 0, 17, 5, lo, hi) != oracle.depth_sample(3, 9, 1, 17, 5, lo, hi)
 
 
 # ---------------------------------------------------------------- Fisk (Eq. 5)
