@@ -164,17 +164,182 @@ def run_batch(args):
     print(json.dumps(line))
 
 
+LEARN_T, LEARN_H, LEARN_W = 6, 480, 640
+LEARN_PLAIN_ITERS, LEARN_ITERS, LEARN_GROUPS = 4, 2, 2048
+
+
+def _he_params(T, seed):
+    """He-normal weights in the proposal's packed layout (zero padded channels)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(6):
+        ci, co = 32, (16 if k == 5 else 32)
+        ci_real = 2 * T if k == 0 else ci
+        co_real = 1 + T if k == 5 else co
+        w = np.zeros((3, 3, ci, co), np.float32)
+        w[:, :, :ci_real, :co_real] = rng.normal(0.0, np.sqrt(2.0 / (9 * ci_real)), (3, 3, ci_real, co_real))
+        out.append(w.ravel())
+        out.append(np.zeros(co, np.float32))
+    return np.concatenate(out)
+
+
+def run_learned(args):
+    """The learned proposal: train it on windows labelled by the plain EM, then
+    compare EM at LEARN_ITERS iterations from the proposal (falling back to the
+    bootstrap's state where that explains the window better) against the plain
+    EM at LEARN_PLAIN_ITERS iterations on held-out windows."""
+    import synthflow
+    n_train, n_eval = args.train_windows, args.eval_windows
+    workers = min(16, os.cpu_count() or 1)
+    # the CPU-sized generator at 640x480 with its intrinsics scaled x4, in forked
+    # workers before anything touches the GPU
+    shapes = (("small", LEARN_W, LEARN_H),)
+    train = synthflow.make_batch(n_train, args.seed + 1, shapes=shapes, T_range=(LEARN_T, LEARN_T), workers=workers)
+    held = synthflow.make_batch(n_eval, args.seed + 2, shapes=shapes, T_range=(LEARN_T, LEARN_T), workers=workers)
+    import numpy as np
+    import torch
+
+    import paper_2104_06789_amd as vo
+
+    dev = torch.device("cuda:0")
+    T, H, W = LEARN_T, LEARN_H, LEARN_W
+    stream = torch.cuda.Stream()
+
+    def solve(wins, iters, props=None):
+        p = vo.default_params(n_iters=iters, n_pose_groups=LEARN_GROUPS, seed=args.seed)
+        flows = [torch.from_numpy(w["flows"]).to(dev) for w in wins]
+        outs = [vo.Batch.outputs(T, H, W) for _ in wins]
+        st = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
+        ch = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
+        items = []
+        for k, (f, w, o) in enumerate(zip(flows, wins, outs)):
+            items.append((f, w["K"], o) if props is None else (f, w["K"], o, (props[0][k], props[1][k], ch[k:k + 1])))
+        b = vo.Batch(4, T, H, W, LEARN_GROUPS, graph=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            b.solve(items, p, st, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if any(int(x) != 0 for x in st.cpu().tolist()):
+            print("a window reported a nonzero status", file=sys.stderr)
+            sys.exit(1)
+        return outs, ms, ch
+
+    # labels: the plain EM's depth and final rigidness
+    labels, label_ms, _ = solve(train, LEARN_PLAIN_ITERS)
+    net = vo.Net(T, args.learn_batch, H, W)
+    net.set_params(_he_params(T, args.seed))
+    tflows = torch.stack([torch.from_numpy(w["flows"]) for w in train]).to(dev)
+    tdepth = torch.stack([o[1] for o in labels])
+    trig = torch.stack([o[2] for o in labels])
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    nb = args.learn_batch
+    losses = []
+    t0 = time.perf_counter()
+    steps = 0
+    rng = np.random.default_rng(args.seed)
+    for ep in range(args.epochs):
+        order = rng.permutation(n_train)
+        ep_loss = []
+        for i in range(0, n_train - nb + 1, nb):
+            idx = torch.from_numpy(order[i:i + nb]).to(dev)
+            net.train_step(tflows[idx].contiguous(), tdepth[idx].contiguous(), trig[idx].contiguous(), args.lr,
+                           loss=loss)
+            ep_loss.append(loss.clone())
+            steps += 1
+        losses.append(float(torch.stack(ep_loss).mean()))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    # matrix-core rate of the forward pass on one training batch, HIP events on its stream
+    fb = tflows[:nb].contiguous()
+    with torch.cuda.stream(stream):
+        net.forward(fb, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 10
+        for _ in range(reps):
+            net.forward(fb, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    conv_flops = 2.0 * nb * H * W * 9 * 32 * (5 * 32 + 16)   # six layers, padded widths
+    achieved = conv_flops / (fwd_ms * 1e-3) / 1e12
+
+    # held-out windows: plain EM vs proposal + shorter EM
+    plain, plain_ms, _ = solve(held, LEARN_PLAIN_ITERS)
+    hflows = torch.stack([torch.from_numpy(w["flows"]) for w in held]).to(dev)
+    pdepth = torch.empty((n_eval, H, W), device=dev)
+    prig = torch.empty((n_eval, T, H, W), device=dev)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for i in range(0, n_eval, nb):
+        j = min(n_eval, i + nb)
+        net.forward(hflows[i:j].contiguous(), depth=pdepth[i:j], rig=prig[i:j])
+    torch.cuda.synchronize()
+    prop_ms = (time.perf_counter() - p0) * 1e3
+    learned, learned_ms, choice = solve(held, LEARN_ITERS, props=(pdepth, prig))
+    shorter, shorter_ms, _ = solve(held, LEARN_ITERS)
+
+    def errs(outs):
+        e = [_pose_error(o[0].cpu().numpy(), w["poses"]) for o, w in zip(outs, held)]
+        return {"rot_rad": float(np.mean([x[0] for x in e])), "tdir_rad": float(np.mean([x[1] for x in e]))}
+
+    ds = [float(np.median(np.abs(np.log(pdepth[k].cpu().numpy()) - np.log(plain[k][1].cpu().numpy()))))
+          for k in range(n_eval)]
+    learned_total = learned_ms + prop_ms
+    line = {
+        "metric": "windows/s at equal pose error, learned vs plain EM",
+        "value": n_eval * 1e3 / learned_total,
+        "unit": "windows/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": learned_total,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 network, f32 sweeps",
+        "data": "synthetic",
+        "config": {"workload": f"learned proposal: {n_train} training and {n_eval} held-out windows, T={T}, "
+                               f"{W}x{H}, CPU-sized scene generator with intrinsics x4; plain EM "
+                               f"{LEARN_PLAIN_ITERS} iterations vs proposal + EM {LEARN_ITERS} iterations, "
+                               f"{LEARN_GROUPS} P3P groups/frame, seed {args.seed}",
+                   "epochs": args.epochs, "batch": nb, "lr": args.lr,
+                   "parallelism": "single GPU, four stream lanes"},
+        "plain": {"windows_per_s": n_eval * 1e3 / plain_ms, "pose_error_vs_gt": errs(plain)},
+        "learned": {"windows_per_s": n_eval * 1e3 / learned_total, "pose_error_vs_gt": errs(learned),
+                    "proposal_used": float(np.mean(choice.cpu().numpy() == 1)),
+                    "proposal_ms": prop_ms, "em_ms": learned_ms,
+                    "median_abs_log_depth_vs_plain": float(np.mean(ds))},
+        "bootstrap_em_short": {"windows_per_s": n_eval * 1e3 / shorter_ms, "pose_error_vs_gt": errs(shorter)},
+        "training": {"loss_per_epoch": losses, "steps": steps, "seconds": train_s, "label_ms": label_ms},
+        "roofline": {"bound": "mfma", "kernel": "k_conv (six layers, forward)", "achieved": achieved,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                     "flops_per_pass": conv_flops, "pass_ms": fwd_ms},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch"])
+    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
     ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
+    ap.add_argument("--train-windows", type=int, default=256, help="(--workload learned)")
+    ap.add_argument("--eval-windows", type=int, default=64, help="(--workload learned)")
+    ap.add_argument("--epochs", type=int, default=8, help="(--workload learned)")
+    ap.add_argument("--learn-batch", type=int, default=4, help="(--workload learned)")
+    ap.add_argument("--lr", type=float, default=1e-3, help="(--workload learned)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -184,6 +349,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "learned":
+        run_learned(args)
         return
 
     import numpy as np
@@ -237,6 +405,32 @@ def main():
 
     rot_err, tdir_err = _pose_error(out[0].cpu().numpy(), w["poses"])
 
+    # the same windows solved LANES at a time (voldor_window_batch): independent
+    # windows overlap one window's latency-bound pose chain with the others' sweeps
+    lanes, per_batch = 4, 8
+    conc = vo.Batch(lanes, T, H, W, spec.n_groups, graph=True)
+    couts = [vo.Batch.outputs(T, H, W) for _ in range(per_batch)]
+    citems = [(flows, w["K"], o) for o in couts]
+    cstat = torch.full((per_batch,), -1, dtype=torch.int32, device=dev)
+    cstream = torch.cuda.Stream()
+    with torch.cuda.stream(cstream):
+        conc.solve(citems, p, cstat, stream=cstream)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // per_batch)
+    c0 = time.perf_counter()
+    with torch.cuda.stream(cstream):
+        for _ in range(reps):
+            conc.solve(citems, p, cstat, stream=cstream)
+    torch.cuda.synchronize()
+    cms = (time.perf_counter() - c0) * 1e3 / (reps * per_batch)
+    if any(int(x) != 0 for x in cstat.cpu().tolist()):
+        print("a concurrent window reported a nonzero status", file=sys.stderr)
+        sys.exit(1)
+    for o in couts:
+        if not all(torch.equal(a, b) for a, b in zip(o, out)):
+            print("a concurrent window differs from the sequential one", file=sys.stderr)
+            sys.exit(1)
+
     line = {
         "metric": "pixel-frame EM updates/s",
         "value": value,
@@ -257,6 +451,10 @@ def main():
         "windows_per_s": 1e3 / ms,
         "phase_ms": ph,
         "phase_windows": n_timed,
+        "concurrent": {"lanes": lanes, "windows_per_call": per_batch, "calls": reps, "value": pf / (cms * 1e-3),
+                       "unit": "pixel-frame updates/s", "windows_per_s": 1e3 / cms, "ms_per_window": cms,
+                       "note": "same workload, windows solved four at a time by voldor_window_batch "
+                               "(HIP graph); results equal the sequential windows bit for bit"},
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload),

@@ -69,7 +69,7 @@ typedef struct {
 } voldor_params;
 
 /* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
- * 100 mean-shift iterations, tol 1e-6, 512 hypotheses, 16384 eval pixels,
+ * 100 mean-shift iterations, tol 1e-5, 512 hypotheses, 16384 eval pixels,
  * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0). */
 void voldor_params_default(voldor_params *p);
 
@@ -114,6 +114,19 @@ int voldor_window_async(voldor_ctx *ctx, const float *flows, int T, int H, int W
                         const voldor_params *p, double *poses, float *depth, float *rigidness,
                         double *loglik, int32_t *status_out, void *stream);
 
+/* The window with a proposed initial state (an extension: Table 1 starts from
+ * the bootstrap).  The bootstrap still runs (T_1, depth range); the proposal's
+ * depth init_depth (device float [H][W], > 0, in the scale |t_1| = 1) and
+ * rigidness init_rig (device float [T][H][W]) replace the bootstrap's depth and
+ * W = 1 when the log-likelihood of X_1 under T_1 (Eq. 3 at the posterior
+ * rigidness) is higher with them; the pose steps of the first iteration then
+ * weigh by that rigidness.  choice_out (device int32 or NULL) receives 1 when
+ * the proposal was used.  Enqueued like voldor_window_async. */
+int voldor_window_init(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                       const voldor_params *p, const float *init_depth, const float *init_rig, double *poses,
+                       float *depth, float *rigidness, double *loglik, int32_t *status_out, int32_t *choice_out,
+                       void *stream);
+
 /* ---- batches: many windows of uneven shape and T ------------------------- */
 
 /* One window of a batch: the arguments of voldor_window for that window. */
@@ -125,6 +138,9 @@ typedef struct {
     float *depth;          /* device float [H][W] (output)                           */
     float *rigidness;      /* device float [T][H][W] (output)                        */
     double *loglik;        /* device double [2] or NULL (output)                     */
+    const float *init_depth;  /* device float [H][W] or NULL: proposed initial state, */
+    const float *init_rig;    /* device float [T][H][W] or NULL  as voldor_window_init */
+    int32_t *choice;          /* device int32 or NULL: 1 when the proposal was used    */
 } voldor_window_desc;
 
 /* Batch solver: `lanes` (1..8) HIP streams, each with the workspace of a
@@ -168,6 +184,53 @@ int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, 
 int voldor_set_timing(voldor_ctx *ctx, int enable);
 int voldor_last_timing(voldor_ctx *ctx, double *out);
 int voldor_timing_summary(voldor_ctx *ctx, double *out, int *n_windows);
+
+/* ---- learned proposal of the initial state ------------------------------- */
+
+/* An extension beyond the paper (whose EM starts from the bootstrap of
+ * Sec. 5.3): a small convolutional network maps the 2T flow channels of a
+ * window to an initial depth and T rigidness maps, which the plain EM then
+ * refines and judges.  Six 3x3 convolutions, stride 1, zero padding: input 32
+ * channels (channel 2(t-1)+c = component c of X_t / 16, non-finite as 0, the
+ * rest 0), layers 1-5 with 32 outputs and ReLU, layer 6 with 16 outputs of
+ * which 0 is log theta and 1..T the logits of W_t.  BF16 weights and
+ * activations, FP32 accumulation on the matrix cores, FP32 master weights.
+ * Loss: mean squared log-depth error + mean binary cross-entropy of W against
+ * targets; Adam (beta 0.9 / 0.999, eps 1e-8) with bias correction.
+ *
+ * Parameters, host float array of voldor_net_param_count() values, layer by
+ * layer: w[3][3][C_in][C_out] (dy, dx, in, out), then b[C_out]; C_in = 32,
+ * C_out = 32 (layer 6: 16).  Weights of padded channels must be 0.
+ * All tensors below are device memory; the calls enqueue on `stream` (except
+ * set/get params, which wait). */
+typedef struct voldor_net voldor_net;
+int voldor_net_create(voldor_net **out, int T, int N_max, int H_max, int W_max);   /* T <= 8 */
+void voldor_net_destroy(voldor_net *net);
+int voldor_net_param_count(const voldor_net *net);
+int voldor_net_set_params(voldor_net *net, const float *host_params);   /* also resets Adam */
+int voldor_net_get_params(voldor_net *net, float *host_params);
+
+/* Forward pass on N windows: flows float32 [N][T][H][W][2]; depth float
+ * [N][H][W] = exp(z_0) (or NULL); rig float [N][T][H][W] = sigmoid(z_t) (or
+ * NULL); z_out float [N][H][W][16] raw outputs (or NULL). */
+int voldor_net_forward(voldor_net *net, const float *flows, int N, int H, int W, float *depth, float *rig,
+                       float *z_out, void *stream);
+
+/* Loss and gradient at the current parameters against target depth float
+ * [N][H][W] (> 0) and rigidness float [N][T][H][W]: loss_out double[1] (or
+ * NULL), grad_out float [param_count] in the parameter layout (or NULL). */
+int voldor_net_gradient(voldor_net *net, const float *flows, int N, int H, int W, const float *depth,
+                        const float *rig, double *loss_out, float *grad_out, void *stream);
+
+/* One Adam step of learning rate lr on the same loss. */
+int voldor_net_train_step(voldor_net *net, const float *flows, int N, int H, int W, const float *depth,
+                          const float *rig, float lr, double *loss_out, void *stream);
+
+/* One layer k (0..5) on explicit BF16 tensors [N][H][W][32]: forward (out bf16
+ * [N][H][W][32], or float [N][H][W][16] for k = 5) or, with backward != 0 and
+ * k >= 1, the gradient to the layer's input times (mask > 0). */
+int voldor_net_layer(voldor_net *net, int k, int backward, const void *in, const void *mask, void *out, int N,
+                     int H, int W, void *stream);
 
 /* ---- step entry points: one step of the loop on explicit state ----------- */
 

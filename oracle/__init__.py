@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 DEFAULTS = dict(
     n_iters=3, sweeps_per_iter=4, n_pose_groups=256, n_seeds=64, ms_max_iters=100,
-    lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-6,
+    lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-5,
     a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
     sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
     depth_lo=0.0, depth_hi=0.0, seed=0,
@@ -85,6 +85,7 @@ def lib():
             "or_pose_step": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
             "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
             "or_window": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d]),
+            "or_window_init": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d, d, d, C.POINTER(C.c_int)]),
             "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
             "or_null_vector_8x9": (None, [d, d]),
         }
@@ -305,3 +306,21 @@ def window(flows, K, p):
     st = lib().or_window(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(poses),
                          _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag))
     return st, poses, depth, rig, (ll[0], ll[1]), diag
+
+
+def window_init(flows, K, p, init_depth, init_rig):
+    """window() from a proposed initial state (depth [H,W] > 0, rigidness [T,H,W]),
+    used where it explains X_1 better than the bootstrap.  Returns
+    (status, poses, depth, rigidness, (L, L1 mass), diag, choice)."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    poses = np.zeros((T, 12))
+    depth = np.zeros((H, W))
+    rig = np.zeros((T, H, W))
+    ll = np.zeros(2)
+    diag = np.zeros(8)
+    choice = C.c_int(-1)
+    st = lib().or_window_init(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(_d(init_depth)),
+                              _ptr(_d(init_rig)), _ptr(poses), _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag),
+                              C.byref(choice))
+    return st, poses, depth, rig, (ll[0], ll[1]), diag, choice.value

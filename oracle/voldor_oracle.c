@@ -1251,9 +1251,57 @@ static int params_ok(const or_params *p, int T, int H, int W, const double *K)
 
 /* poses_out [T][12] relative; depth_out [H][W]; rig_out [T][H][W];
  * loglik_out [2] = L and its L1 mass; diag_out optional [8]. */
-int or_window(const float *flows, int T, int H, int W, const double *K, const or_params *p,
-              double *poses_out, double *depth_out, double *rig_out, double *loglik_out,
-              double *diag_out)
+/* Log-likelihood of the window under relative poses rel (Eq. 3 with the
+ * posterior rigidness r of every observed pixel and frame): the score by which
+ * a proposed initial state is compared with the bootstrap's. */
+static double window_loglik(const or_frame_set *F, const or_params *p, const double *rel,
+                            const double *theta)
+{
+    double *M = (double *)malloc(sizeof(double) * 12 * (F->T + 1));
+    cumulative(rel, F->T, M);
+    double L = 0, Lc = 0;
+    for (int t = 1; t <= F->T; ++t)
+        for (int y = 0; y < F->H; ++y)
+            for (int x = 0; x < F->W; ++x) {
+                or_emis e = emission(F, p, M, t, x, y, theta[(size_t)y * F->W + x]);
+                if (!e.observed) continue;
+                double term = e.r * e.logrho + (1 - e.r) * e.logmu;
+                double yk = term - Lc, tk = L + yk;
+                Lc = (tk - L) - yk;
+                L = tk;
+            }
+    free(M);
+    return L;
+}
+
+/* One pass of pose steps t = 1..T of iteration `it` (Sec. 5.2) on the depth
+ * theta and rigidness rig (NULL: W = 1); rel is updated in place, M rebuilt. */
+static void pose_pass(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+                      const double *theta, const double *rig, int it, double *rel, double *M,
+                      int *fallbacks, int *ms_total)
+{
+    pose_identity(M);
+    for (int t = 1; t <= T; ++t) {
+        const double *prevT = NULL;
+        if (it > 0 || t == 1) prevT = rel + 12 * (t - 1);
+        else prevT = rel + 12 * (t - 2); /* first pass: previous frame's motion as fallback */
+        double Tn[12], prevcopy[12];
+        memcpy(prevcopy, prevT, sizeof prevcopy);
+        int dg[4];
+        or_pose_step(theta, rig, flows, T, H, W, K, p, M, t, it, (it > 0 || t == 1) ? prevcopy : NULL, Tn,
+                     NULL, dg);
+        if (dg[3]) memcpy(Tn, prevcopy, sizeof Tn);
+        *fallbacks += dg[3];
+        *ms_total += dg[2];
+        memcpy(rel + 12 * (t - 1), Tn, sizeof Tn);
+        pose_compose(rel + 12 * (t - 1), M + 12 * (t - 1), M + 12 * t);
+    }
+}
+
+static int window_core(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+                       const double *init_depth, const double *init_rig, double *poses_out,
+                       double *depth_out, double *rig_out, double *loglik_out, double *diag_out,
+                       int *choice_out)
 {
     if (!flows || !K || !p || !poses_out || !depth_out || !rig_out) return OR_EINVAL;
     if (!params_ok(p, T, H, W, K)) return OR_EINVAL;
@@ -1266,24 +1314,33 @@ int or_window(const float *flows, int T, int H, int W, const double *K, const or
     if (st != OR_OK) { free(M); return st; }
     for (int t = 2; t <= T; ++t) pose_identity(rel + 12 * (t - 1));
     int have_w = 0; /* W == 1 until the first unsmoothed update */
-    int fallbacks = 0, ms_total = 0;
+    int fallbacks = 0, ms_total = 0, first_pass_done = 0;
+    if (init_depth && init_rig) {
+        /* a proposed initial state (depth, W) against the bootstrap's (depth,
+         * W = 1): each gets the first pass of pose steps, and the one whose
+         * window log-likelihood is higher is kept, poses included */
+        double *rel_boot = (double *)malloc(sizeof(double) * 12 * T);
+        double *rel_a = (double *)malloc(sizeof(double) * 12 * T);
+        memcpy(rel_boot, rel, sizeof(double) * 12 * T);
+        pose_pass(flows, T, H, W, K, p, depth_out, NULL, 0, rel, M, &fallbacks, &ms_total);
+        const double La = window_loglik(&F, p, rel, depth_out);
+        memcpy(rel_a, rel, sizeof(double) * 12 * T);
+        memcpy(rel, rel_boot, sizeof(double) * 12 * T);
+        pose_pass(flows, T, H, W, K, p, init_depth, init_rig, 0, rel, M, &fallbacks, &ms_total);
+        const double Lb = window_loglik(&F, p, rel, init_depth);
+        const int use = Lb > La;
+        if (use) memcpy(depth_out, init_depth, HW * sizeof(double));
+        else memcpy(rel, rel_a, sizeof(double) * 12 * T);
+        cumulative(rel, T, M);
+        if (choice_out) *choice_out = use;
+        free(rel_boot);
+        free(rel_a);
+        first_pass_done = 1;
+    }
     for (int it = 0; it < p->n_iters; ++it) {
-        pose_identity(M);
-        for (int t = 1; t <= T; ++t) {
-            const double *prevT = NULL;
-            if (it > 0 || t == 1) prevT = rel + 12 * (t - 1);
-            else prevT = rel + 12 * (t - 2); /* first pass: previous frame's motion as fallback */
-            double Tn[12], prevcopy[12];
-            memcpy(prevcopy, prevT, sizeof prevcopy);
-            int dg[4];
-            or_pose_step(depth_out, have_w ? rig_out : NULL, flows, T, H, W, K, p, M, t, it,
-                         (it > 0 || t == 1) ? prevcopy : NULL, Tn, NULL, dg);
-            if (dg[3]) memcpy(Tn, prevcopy, sizeof Tn);
-            fallbacks += dg[3];
-            ms_total += dg[2];
-            memcpy(rel + 12 * (t - 1), Tn, sizeof Tn);
-            pose_compose(rel + 12 * (t - 1), M + 12 * (t - 1), M + 12 * t);
-        }
+        if (!(it == 0 && first_pass_done))
+            pose_pass(flows, T, H, W, K, p, depth_out, have_w ? rig_out : NULL, it, rel, M, &fallbacks,
+                      &ms_total);
         for (int s = 0; s < p->sweeps_per_iter; ++s) {
             int64_t gs = (int64_t)it * p->sweeps_per_iter + s;
             or_sweep(depth_out, depth_out, flows, T, H, W, K, p, M, range[0], range[1], gs,
@@ -1331,4 +1388,24 @@ int or_window(const float *flows, int T, int H, int W, const double *K, const or
     }
     free(M);
     return OR_OK;
+}
+
+int or_window(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+              double *poses_out, double *depth_out, double *rig_out, double *loglik_out,
+              double *diag_out)
+{
+    return window_core(flows, T, H, W, K, p, NULL, NULL, poses_out, depth_out, rig_out, loglik_out,
+                       diag_out, NULL);
+}
+
+/* The window from a proposed initial state (depth [H][W] > 0, rigidness
+ * [T][H][W]), used where it beats the bootstrap on X_1; *choice_out = 1 then. */
+int or_window_init(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+                   const double *init_depth, const double *init_rig, double *poses_out,
+                   double *depth_out, double *rig_out, double *loglik_out, double *diag_out,
+                   int *choice_out)
+{
+    if (!init_depth || !init_rig) return OR_EINVAL;
+    return window_core(flows, T, H, W, K, p, init_depth, init_rig, poses_out, depth_out, rig_out,
+                       loglik_out, diag_out, choice_out);
 }

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Params", "WindowDesc", "default_params", "Solver", "Batch", "philox", "lib", "status_str",
+__all__ = ["Params", "WindowDesc", "default_params", "Solver", "Batch", "Net", "philox", "lib", "status_str",
            "VoldorError"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +47,7 @@ class WindowDesc(C.Structure):
         ("flows", C.c_void_p), ("T", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
         ("K", C.c_double * 4), ("poses", C.c_void_p), ("depth", C.c_void_p),
         ("rigidness", C.c_void_p), ("loglik", C.c_void_p),
+        ("init_depth", C.c_void_p), ("init_rig", C.c_void_p), ("choice", C.c_void_p),
     ]
 
 
@@ -74,6 +75,7 @@ def lib():
         "voldor_destroy": (None, [vp]),
         "voldor_window": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp]),
         "voldor_window_async": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp]),
+        "voldor_window_init": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "voldor_philox": (i, [vp, C.c_uint64, C.c_uint64, vp, i, vp]),
         "voldor_emission": (i, [vp, vp, vp, i, i, i, dp, P, dp, vp, vp, vp, vp, vp]),
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
@@ -82,6 +84,15 @@ def lib():
         "voldor_set_timing": (i, [vp, i]),
         "voldor_last_timing": (i, [vp, dp]),
         "voldor_timing_summary": (i, [vp, dp, ip]),
+        "voldor_net_create": (i, [C.POINTER(vp), i, i, i, i]),
+        "voldor_net_destroy": (None, [vp]),
+        "voldor_net_param_count": (i, [vp]),
+        "voldor_net_set_params": (i, [vp, C.POINTER(f)]),
+        "voldor_net_get_params": (i, [vp, C.POINTER(f)]),
+        "voldor_net_forward": (i, [vp, vp, i, i, i, vp, vp, vp, vp]),
+        "voldor_net_gradient": (i, [vp, vp, i, i, i, vp, vp, vp, vp, vp]),
+        "voldor_net_train_step": (i, [vp, vp, i, i, i, vp, vp, f, vp, vp]),
+        "voldor_net_layer": (i, [vp, i, i, vp, vp, vp, i, i, i, vp]),
         "voldor_batch_create": (i, [C.POINTER(vp), i, i, i, i, i, i]),
         "voldor_batch_destroy": (None, [vp]),
         "voldor_window_batch": (i, [vp, C.POINTER(WindowDesc), i, P, vp, vp]),
@@ -197,6 +208,20 @@ class Solver:
                                        _ptr(depth), _ptr(rig), _ptr(ll) if want_loglik else None,
                                        _ptr(status), _stream(stream))
         _check(rc, "voldor_window_async")
+
+    def window_init(self, flows, K, params, init_depth, init_rig, out, status, choice=None, stream=None,
+                    want_loglik=True):
+        """Enqueue a window that starts from a proposed depth [H,W] and rigidness
+        [T,H,W] (CUDA float32) where they explain X_1 better than the bootstrap;
+        choice: CUDA int32 element set to 1 when the proposal was used."""
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        poses, depth, rig, ll = out
+        Kd, Kp = _dbl(K)
+        _check(lib().voldor_window_init(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(init_depth),
+                                        _ptr(init_rig), _ptr(poses), _ptr(depth), _ptr(rig),
+                                        _ptr(ll) if want_loglik else None, _ptr(status), _ptr(choice),
+                                        _stream(stream)), "voldor_window_init")
 
     def window_status(self, flows, K, params, stream=None):
         """Like window() but returns the status code instead of raising."""
@@ -348,7 +373,9 @@ class Batch:
                 and status.is_contiguous() and status.numel() >= n):
             raise TypeError("status must be a contiguous CUDA int32 tensor of len(windows) elements")
         descs = (WindowDesc * n)()
-        for i, (flows, K, out) in enumerate(windows):
+        for i, item in enumerate(windows):
+            flows, K, out = item[:3]
+            init = item[3] if len(item) > 3 else None
             flows = _flows(flows)
             T, H, W, _ = flows.shape
             poses, depth, rig, ll = out
@@ -359,6 +386,58 @@ class Batch:
                 d.K[k] = float(K[k])
             d.poses, d.depth, d.rigidness = poses.data_ptr(), depth.data_ptr(), rig.data_ptr()
             d.loglik = ll.data_ptr() if ll is not None else None
+            if init is not None:
+                idepth, irig, choice = init
+                d.init_depth, d.init_rig = idepth.data_ptr(), irig.data_ptr()
+                d.choice = choice.data_ptr() if choice is not None else None
         self._keep = (windows, status)
         _check(lib().voldor_window_batch(self._b, descs, n, C.byref(params), _ptr(status), _stream(stream)),
                "voldor_window_batch")
+
+
+class Net:
+    """The learned proposal (voldor_net_* in the C ABI) for windows of T frames."""
+
+    def __init__(self, T, N_max, H_max, W_max):
+        ctx = C.c_void_p()
+        _check(lib().voldor_net_create(C.byref(ctx), T, N_max, H_max, W_max), "voldor_net_create")
+        self._n = ctx
+        self.T = T
+        self.n_params = lib().voldor_net_param_count(self._n)
+
+    def __del__(self):
+        if getattr(self, "_n", None):
+            lib().voldor_net_destroy(self._n)
+            self._n = None
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(lib().voldor_net_set_params(self._n, a.ctypes.data_as(C.POINTER(C.c_float))), "voldor_net_set_params")
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().voldor_net_get_params(self._n, a.ctypes.data_as(C.POINTER(C.c_float))), "voldor_net_get_params")
+        return a
+
+    def forward(self, flows, depth=None, rig=None, z=None, stream=None):
+        """flows: CUDA float32 [N,T,H,W,2]; optional outputs as CUDA float32 tensors."""
+        N, T, H, W, _ = flows.shape
+        _check(lib().voldor_net_forward(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), _ptr(z),
+                                        _stream(stream)), "voldor_net_forward")
+
+    def gradient(self, flows, depth, rig, loss=None, grad=None, stream=None):
+        N, T, H, W, _ = flows.shape
+        _check(lib().voldor_net_gradient(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), _ptr(loss),
+                                         _ptr(grad), _stream(stream)), "voldor_net_gradient")
+
+    def train_step(self, flows, depth, rig, lr, loss=None, stream=None):
+        N, T, H, W, _ = flows.shape
+        _check(lib().voldor_net_train_step(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), float(lr),
+                                           _ptr(loss), _stream(stream)), "voldor_net_train_step")
+
+    def layer(self, k, x, out, mask=None, backward=False, stream=None):
+        N, H, W, _ = x.shape
+        _check(lib().voldor_net_layer(self._n, k, 1 if backward else 0, _ptr(x), _ptr(mask), _ptr(out), N, H, W,
+                                      _stream(stream)), "voldor_net_layer")

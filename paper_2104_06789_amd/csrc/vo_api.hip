@@ -144,6 +144,29 @@ __global__ void k_copy_status(const int *status, int32_t *out)
     if (threadIdx.x == 0) *out = *status;
 }
 
+// a proposed initial state against the bootstrap's: ll[0] and ll[2] are the
+// window log-likelihoods (Eq. 3 at the posterior rigidness) after each state's
+// first pass of pose steps; the proposal's poses are in rel, the bootstrap
+// state's in rel_a.  The proposal wins on a strictly higher likelihood: its
+// depth replaces the bootstrap's; otherwise the bootstrap state's poses return.
+__global__ void __launch_bounds__(256) k_init_select(const double *ll, const float *prop_depth, float *depth,
+                                                     const double *rel_a, double *rel, int HW, int T,
+                                                     int32_t *choice, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    const bool use = ll[2] > ll[0];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (choice && j == 0) *choice = use ? 1 : 0;
+    if (!use && j < 12 * T) rel[j] = rel_a[j];
+    if (use && j < HW) depth[j] = prop_depth[j];
+}
+
+__global__ void k_copy_d(const double *src, double *dst, int n, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 int upload_M(voldor_ctx *c, const double *M, int T, hipStream_t s)
 {
     if (hipMemcpyAsync(c->Mcum, M, sizeof(double) * 12 * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -167,7 +190,7 @@ void voldor_params_default(voldor_params *p)
     p->ms_max_iters = 100;
     p->lmeds_hypotheses = 512;
     p->lmeds_eval_pixels = 16384;
-    p->ms_tol = 1e-6;
+    p->ms_tol = 1e-5;
     p->a1 = 0.01;
     p->a2 = 0.09;
     p->b1 = -0.0022;
@@ -233,6 +256,8 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->hist, 3 * 256) == hipSuccess;
     ok = ok && dalloc(&c->sel, 16) == hipSuccess;
     ok = ok && dalloc(&c->ll_part, 2 * kLLBlocks) == hipSuccess;
+    ok = ok && dalloc(&c->init_ll, 4) == hipSuccess;
+    ok = ok && dalloc(&c->init_rel, 24 * T_max) == hipSuccess;
     ok = ok && dalloc(&c->sampf, (size_t)7 * pose_sample_slots(S_max)) == hipSuccess;
     ok = ok && dalloc(&c->gcnt, S_max) == hipSuccess;
     ok = ok && dalloc(&c->gpre, S_max) == hipSuccess;
@@ -263,7 +288,7 @@ void voldor_destroy(voldor_ctx *c)
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->boot_cand, c->boot_sub, c->dkeys, c->hist,
-                    c->sel, c->ll_part, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
+                    c->sel, c->ll_part, c->init_ll, c->init_rel, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(c);
@@ -287,7 +312,7 @@ bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W
 // device-side ones end up in c->status (and in *status_out if given)
 int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                    const voldor_params *p, double *poses, float *depth, float *rigidness,
-                   double *loglik, int32_t *status_out, hipStream_t s)
+                   double *loglik, int32_t *status_out, hipStream_t s, const WindowInit *init)
 {
     if (!window_args_ok(c, flows, T, H, W, K, p, poses, depth, rigidness)) return VOLDOR_EINVAL;
     const float2 *X = (const float2 *)flows;
@@ -301,12 +326,43 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
     int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
                               p->depth_lo, p->depth_hi, poses, depth, s);
     mark(c, s, kPhaseBoot);
-    for (int it = 0; it < p->n_iters && rc == 0; ++it) {
-        d.use_w = it > 0;
+    const bool proposed = init && init->depth && init->rig;
+    if (proposed && (!c->init_rel || !c->init_ll)) return VOLDOR_EDEVICE;
+    if (rc == 0 && proposed) {
+        // the bootstrap's state (its depth, W = 1) and the proposal's each get the
+        // first pass of pose steps from the bootstrap's T_1; the window
+        // log-likelihood after it picks one, poses included
+        double *rel_boot = c->init_rel, *rel_a = c->init_rel + 12 * c->T_max;
+        hipLaunchKernelGGL(k_copy_d, dim3(1), dim3(256), 0, s, poses, rel_boot, 12 * T, c->status);
+        d.use_w = 0;
         for (int t = 1; t <= T && rc == 0; ++t)
-            rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0,
-                                  poses, s);
+            rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, 0, t == 1 ? 1 : 0, poses, s);
+        if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, c->init_ll, s);
+        if (rc == 0) {
+            hipLaunchKernelGGL(k_copy_d, dim3(1), dim3(256), 0, s, poses, rel_a, 12 * T, c->status);
+            hipLaunchKernelGGL(k_copy_d, dim3(1), dim3(256), 0, s, rel_boot, poses, 12 * T, c->status);
+        }
+        d.use_w = 1;
+        for (int t = 1; t <= T && rc == 0; ++t)
+            rc = launch_pose_step(c, init->depth, init->rig, X, d, pp, t, 0, t == 1 ? 1 : 0, poses, s);
+        if (rc == 0)
+            rc = launch_rigidness(c, init->depth, X, d, e, nullptr, nullptr, nullptr, nullptr, c->init_ll + 2, s);
+        if (rc == 0) {
+            const int n = H * W > 12 * T ? H * W : 12 * T;
+            hipLaunchKernelGGL(k_init_select, dim3((n + 255) / 256), dim3(256), 0, s, c->init_ll, init->depth, depth,
+                               rel_a, poses, H * W, T, init->choice, c->status);
+            rc = hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+        }
+        if (rc == 0) rc = launch_cumulative(c, poses, T, s);
         mark(c, s, kPhasePose);
+    }
+    for (int it = 0; it < p->n_iters && rc == 0; ++it) {
+        d.use_w = it > 0 ? 1 : 0;
+        if (!(it == 0 && proposed)) {
+            for (int t = 1; t <= T && rc == 0; ++t)
+                rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0, poses, s);
+            mark(c, s, kPhasePose);
+        }
         for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw) {
             const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
             rc = launch_sweep(c, depth, depth, X, d, e, (float)p->gamma, p->seed, gs, (int)(gs % 4),
@@ -359,6 +415,18 @@ int voldor_window_async(voldor_ctx *c, const float *flows, int T, int H, int W, 
     if (!status_out || ((uintptr_t)status_out & 3) != 0) return VOLDOR_EINVAL;
     return window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, status_out,
                           (hipStream_t)stream);
+}
+
+int voldor_window_init(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                       const voldor_params *p, const float *init_depth, const float *init_rig, double *poses,
+                       float *depth, float *rigidness, double *loglik, int32_t *status_out, int32_t *choice_out,
+                       void *stream)
+{
+    if (!status_out || ((uintptr_t)status_out & 3) != 0 || !init_depth || !init_rig) return VOLDOR_EINVAL;
+    if (choice_out && ((uintptr_t)choice_out & 3) != 0) return VOLDOR_EINVAL;
+    const WindowInit in = {init_depth, init_rig, choice_out};
+    return window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, status_out,
+                          (hipStream_t)stream, &in);
 }
 
 int voldor_set_timing(voldor_ctx *c, int enable)

@@ -92,8 +92,9 @@ int batch_enqueue(voldor_batch *b, const voldor_window_desc *w, int n, const vol
     for (int k = 0; k < n && rc == VOLDOR_OK; ++k) {
         const int i = order[k], l = lane_of[i];
         const voldor_window_desc &d = w[i];
+        const WindowInit in = {d.init_depth, d.init_rig, d.choice};
         rc = window_enqueue(b->ctx[l], d.flows, d.T, d.H, d.W, d.K, p, d.poses, d.depth, d.rigidness,
-                            d.loglik, status_out + i, b->st[l]);
+                            d.loglik, status_out + i, b->st[l], (d.init_depth && d.init_rig) ? &in : nullptr);
     }
     // the join is recorded even after a failed launch, so that s never runs
     // ahead of work that did get enqueued

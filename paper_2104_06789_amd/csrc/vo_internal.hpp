@@ -57,6 +57,8 @@ struct voldor_ctx {
     uint32_t *hist;        // [3][256] radix histograms
     uint32_t *sel;         // [16] radix-select state (prefix, rank) x 3, valid count
     double *ll_part;       // [kLLBlocks][2] log-likelihood partial sums
+    double *init_ll;       // [4] window log-likelihoods (and L1 masses) of the bootstrap and a proposed state
+    double *init_rel;      // [2][T_max][12] bootstrap poses, first-pass poses of the bootstrap's state
     float *sampf;          // SoA [7][slots] whitened pose samples (FP32) for the mean-shift
     int *gcnt;             // [S_max] valid samples per group
     int *gpre;             // [S_max] first sample of each group inside its block
@@ -86,9 +88,16 @@ namespace vo {
 bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                     const voldor_params *p, const double *poses, const float *depth,
                     const float *rigidness);
+// optional initial state proposed for a window (depth [H][W], rigidness [T][H][W]);
+// choice (device int, may be NULL) receives 1 when it replaced the bootstrap's
+struct WindowInit {
+    const float *depth;
+    const float *rig;
+    int32_t *choice;
+};
 int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                    const voldor_params *p, double *poses, float *depth, float *rigidness,
-                   double *loglik, int32_t *status_out, hipStream_t s);
+                   double *loglik, int32_t *status_out, hipStream_t s, const WindowInit *init = nullptr);
 
 // ---- sweep / emission (vo_sweep.hip)
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,

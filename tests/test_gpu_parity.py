@@ -287,3 +287,55 @@ def test_window_async_matches_sync(vo, torch):
     torch.cuda.synchronize()
     assert int(status[0]) == -4 == s.window_status(bad, ws[0]["K"], p)
     s.set_timing(False)
+
+
+def test_window_init_against_oracle_and_plain(vo, torch):
+    # a proposed initial state: the bootstrap's own (a tie: the bootstrap is
+    # kept, bit-identical to voldor_window), an implausible one (rejected,
+    # identical too) and the converged state of a longer solve (accepted; the
+    # result matches the oracle's window_init to the window tolerances)
+    T, H, W = 3, 48, 64
+    w = synthflow.make_window("small", 4, T=T, H=H, W=W)
+    kw = dict(n_iters=2, n_pose_groups=128)
+    p = vo.default_params(**kw)
+    s = vo.Solver(T, H, W, 128)
+    fl = torch.from_numpy(w["flows"]).cuda()
+    ref = tuple(x.clone() for x in s.window(fl, w["K"], p))
+    st, rel, th, rng, info = s.bootstrap(fl, w["K"], p)
+    assert st == 0
+    ones = torch.ones((T, H, W), device="cuda")
+    status = torch.full((3,), -9, dtype=torch.int32, device="cuda")
+    choice = torch.full((3,), -9, dtype=torch.int32, device="cuda")
+    outs = [vo.Batch.outputs(T, H, W) for _ in range(3)]
+    s.window_init(fl, w["K"], p, th.clone(), ones, outs[0], status[0], choice[0])
+    s.window_init(fl, w["K"], p, torch.full((H, W), 1e3, device="cuda"), ones, outs[1], status[1], choice[1])
+    st4, op4, od4, orig4, oll4, _ = oracle.window(w["flows"], w["K"], oracle.params(n_iters=4, n_pose_groups=128))
+    d4 = torch.from_numpy(od4.astype(np.float32)).cuda()
+    r4 = torch.from_numpy(orig4.astype(np.float32)).cuda()
+    s.window_init(fl, w["K"], p, d4, r4, outs[2], status[2], choice[2])
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0, 0, 0]
+    assert choice.cpu().tolist() == [0, 0, 1]
+    for k in range(2):
+        for a, b in zip(outs[k], ref):
+            assert torch.equal(a, b), k
+    ost, op, od, orig, oll, _, och = oracle.window_init(w["flows"], w["K"], oracle.params(**kw),
+                                                        od4.astype(np.float32).astype(np.float64),
+                                                        orig4.astype(np.float32).astype(np.float64))
+    assert ost == 0 and och == 1
+    gp, gd = outs[2][0].cpu().numpy(), outs[2][1].cpu().numpy()
+    rot = max(_rot_angle(gp[t, :9].reshape(3, 3), op[t, :9].reshape(3, 3)) for t in range(T))
+    tdir = max(_tdir_angle(gp[t, 9:], op[t, 9:]) for t in range(T))
+    print(rot, tdir)
+    assert rot <= 1e-4 and tdir <= 1e-4
+    assert float(np.median(np.abs(gd - od) / od)) <= 1e-3
+    # the same proposal through a batch descriptor
+    b = vo.Batch(2, T, H, W, 128)
+    o2 = vo.Batch.outputs(T, H, W)
+    st2 = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    ch2 = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    b.solve([(fl, w["K"], o2, (d4, r4, ch2))], p, st2)
+    torch.cuda.synchronize()
+    assert int(st2) == 0 and int(ch2) == 1
+    for a, c in zip(o2, outs[2]):
+        assert torch.equal(a, c)

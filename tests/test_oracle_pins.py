@@ -505,3 +505,28 @@ def test_window_invalid_arguments():
     assert oracle.window(w["flows"], w["K"], oracle.params(gamma=1.0))[0] == -1
     small = np.zeros((1, 8, 8, 2), np.float32)
     assert oracle.window(small, w["K"], oracle.params())[0] == -1
+
+
+def test_window_init_selection():
+    # the proposal competes with the bootstrap's state after one pass of pose
+    # steps each, by window log-likelihood
+    w = synthflow.make_window("small", 4, T=3, H=48, W=64)
+    p = oracle.params(n_iters=2, n_pose_groups=128)
+    T, H, W = 3, 48, 64
+    st, op, od, orig, oll, _ = oracle.window(w["flows"], w["K"], p)
+    assert st == 0
+    sb, rel, th, rng, info = oracle.bootstrap(w["flows"], w["K"], p)
+    # the bootstrap's own state proposed: equal likelihoods, the bootstrap is kept
+    # and the result is the plain window's
+    r = oracle.window_init(w["flows"], w["K"], p, th, np.ones((T, H, W)))
+    assert r[0] == 0 and r[6] == 0
+    assert np.array_equal(r[1], op) and np.array_equal(r[2], od) and np.array_equal(r[3], orig)
+    # an implausible proposal loses
+    r = oracle.window_init(w["flows"], w["K"], p, np.full((H, W), 1e3), np.ones((T, H, W)))
+    assert r[6] == 0 and np.array_equal(r[1], op)
+    # the converged state of a longer solve wins, and the window it ends in is
+    # at least as likely as the plain one
+    st4, op4, od4, orig4, oll4, _ = oracle.window(w["flows"], w["K"], oracle.params(n_iters=4, n_pose_groups=128))
+    r = oracle.window_init(w["flows"], w["K"], p, od4, orig4)
+    assert r[0] == 0 and r[6] == 1
+    assert r[4][0] >= oll[0]
