@@ -324,6 +324,37 @@ def run_learned(args):
     print(json.dumps(line))
 
 
+def _concurrent(vo, torch, T, H, W, spec, flows, w, p, out, dev, args, pf, lanes=4, per_batch=8):
+    """The same windows solved `lanes` at a time (voldor_window_batch): independent
+    windows overlap one window's latency-bound pose chain with the others' sweeps."""
+    conc = vo.Batch(lanes, T, H, W, spec.n_groups, graph=True)
+    couts = [vo.Batch.outputs(T, H, W) for _ in range(per_batch)]
+    citems = [(flows, w["K"], o) for o in couts]
+    cstat = torch.full((per_batch,), -1, dtype=torch.int32, device=dev)
+    cstream = torch.cuda.Stream()
+    with torch.cuda.stream(cstream):
+        conc.solve(citems, p, cstat, stream=cstream)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // per_batch)
+    c0 = time.perf_counter()
+    with torch.cuda.stream(cstream):
+        for _ in range(reps):
+            conc.solve(citems, p, cstat, stream=cstream)
+    torch.cuda.synchronize()
+    cms = (time.perf_counter() - c0) * 1e3 / (reps * per_batch)
+    if any(int(x) != 0 for x in cstat.cpu().tolist()):
+        print("a concurrent window reported a nonzero status", file=sys.stderr)
+        sys.exit(1)
+    for o in couts:
+        if not all(torch.equal(a, b) for a, b in zip(o, out)):
+            print("a concurrent window differs from the sequential one", file=sys.stderr)
+            sys.exit(1)
+    return {"lanes": lanes, "windows_per_call": per_batch, "calls": reps, "value": pf / (cms * 1e-3),
+            "unit": "pixel-frame updates/s", "windows_per_s": 1e3 / cms, "ms_per_window": cms,
+            "note": "same workload, windows solved four at a time by voldor_window_batch "
+                    "(HIP graph); results equal the sequential windows bit for bit"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,9 +366,11 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
     ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
-    ap.add_argument("--train-windows", type=int, default=256, help="(--workload learned)")
-    ap.add_argument("--eval-windows", type=int, default=64, help="(--workload learned)")
-    ap.add_argument("--epochs", type=int, default=8, help="(--workload learned)")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the four-lane figure (profiles of the sequential windows alone)")
+    ap.add_argument("--train-windows", type=int, default=384, help="(--workload learned)")
+    ap.add_argument("--eval-windows", type=int, default=96, help="(--workload learned)")
+    ap.add_argument("--epochs", type=int, default=20, help="(--workload learned)")
     ap.add_argument("--learn-batch", type=int, default=4, help="(--workload learned)")
     ap.add_argument("--lr", type=float, default=1e-3, help="(--workload learned)")
     args = ap.parse_args()
@@ -407,29 +440,8 @@ def main():
 
     # the same windows solved LANES at a time (voldor_window_batch): independent
     # windows overlap one window's latency-bound pose chain with the others' sweeps
-    lanes, per_batch = 4, 8
-    conc = vo.Batch(lanes, T, H, W, spec.n_groups, graph=True)
-    couts = [vo.Batch.outputs(T, H, W) for _ in range(per_batch)]
-    citems = [(flows, w["K"], o) for o in couts]
-    cstat = torch.full((per_batch,), -1, dtype=torch.int32, device=dev)
-    cstream = torch.cuda.Stream()
-    with torch.cuda.stream(cstream):
-        conc.solve(citems, p, cstat, stream=cstream)
-    torch.cuda.synchronize()
-    reps = max(1, args.steps // per_batch)
-    c0 = time.perf_counter()
-    with torch.cuda.stream(cstream):
-        for _ in range(reps):
-            conc.solve(citems, p, cstat, stream=cstream)
-    torch.cuda.synchronize()
-    cms = (time.perf_counter() - c0) * 1e3 / (reps * per_batch)
-    if any(int(x) != 0 for x in cstat.cpu().tolist()):
-        print("a concurrent window reported a nonzero status", file=sys.stderr)
-        sys.exit(1)
-    for o in couts:
-        if not all(torch.equal(a, b) for a, b in zip(o, out)):
-            print("a concurrent window differs from the sequential one", file=sys.stderr)
-            sys.exit(1)
+    conc_line = None if args.no_concurrent else _concurrent(vo, torch, T, H, W, spec, flows, w, p, out, dev,
+                                                             args, pf)
 
     line = {
         "metric": "pixel-frame EM updates/s",
@@ -451,10 +463,7 @@ def main():
         "windows_per_s": 1e3 / ms,
         "phase_ms": ph,
         "phase_windows": n_timed,
-        "concurrent": {"lanes": lanes, "windows_per_call": per_batch, "calls": reps, "value": pf / (cms * 1e-3),
-                       "unit": "pixel-frame updates/s", "windows_per_s": 1e3 / cms, "ms_per_window": cms,
-                       "note": "same workload, windows solved four at a time by voldor_window_batch "
-                               "(HIP graph); results equal the sequential windows bit for bit"},
+        "concurrent": conc_line,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload),

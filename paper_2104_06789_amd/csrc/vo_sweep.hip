@@ -73,7 +73,7 @@ __device__ __forceinline__ bool item_log_odds(const FrameF *fr, const float2 *__
     return true;
 }
 
-// MIE score sum_t q_t ell_t(th) at chain position k, frames in chunks of four
+// MIE score sum_t q_t ell_t(th) at chain position k, frames in chunks of three
 // so that the flow gathers of a chunk are in flight together
 __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
                                              int T, int H, int W, const EmisParams &e, int x, int y,
@@ -84,21 +84,21 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     float pdx = 0.0f, pdy = 0.0f;
     bool pok = th > 0.0f;
     const int HW = H * W;   // T H W < 2^31 (frames <= 16, sides <= 4096)
-    for (int t0 = 1; t0 <= T; t0 += 4) {
-        float dx[4], dy[4];
-        bool ok[4];
+    for (int t0 = 1; t0 <= T; t0 += 3) {
+        float dx[3], dy[3];
+        bool ok[3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
             dx[u] = 0.0f;
             dy[u] = 0.0f;
             ok[u] = t <= T && th > 0.0f && displacement(fr[t <= T ? t : T], xh, yh, th, e.fx, e.fy, dx[u], dy[u]);
         }
-        float2 ta[4], tb[4], tc[4], td[4];
-        float ax[4], ay[4], lx[4], ly[4];
-        bool val[4];
+        float2 ta[3], tb[3], tc[3], td[3];
+        float ax[3], ay[3], lx[3], ly[3];
+        bool val[3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 3; ++u) {
             const float bdx = u == 0 ? pdx : dx[u - 1], bdy = u == 0 ? pdy : dy[u - 1];
             const bool bok = u == 0 ? pok : ok[u - 1];
             const float px = (float)x + bdx, py = (float)y + bdy;
@@ -118,7 +118,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             td[u] = r0[W + 1];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
             if (t > T) break;
             float ell = kLogHalf;
@@ -133,9 +133,9 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             }
             s = fmaf(q[(t - 1) * L + k], ell, s);
         }
-        pdx = dx[3];
-        pdy = dy[3];
-        pok = ok[3];
+        pdx = dx[2];
+        pdy = dy[2];
+        pok = ok[2];
     }
     return s;
 }
