@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
 # profiles/k_sweep_indoor_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25142.82421875 * 1024 * 1.99983,
-                        "write_bytes": 1266.16796875 * 1024 * 1.0}
-SWEEP_SOURCES_SHA = "6734fc834195be18"
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
+                        "write_bytes": 1249.0390625 * 1024 * 1.0}
+SWEEP_SOURCES_SHA = "cc59b63f802f019d"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp", "vo_internal.hpp")
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # FP32 lane-instructions/s (non-packed), 39.3 T
 EMISSION_VALU_OPS = 160                      # VALU instructions of one emission evaluation (gfx950 ISA),
