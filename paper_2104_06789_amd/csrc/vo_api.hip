@@ -107,16 +107,19 @@ hipError_t dalloc(T **p, size_t n)
 }
 
 // phase timing: an event after each phase; the interval ending at event i
-// belongs to ev_phase[i]
+// belongs to ev_phase[i] and, for the sweeps, holds ev_launches[i] launches.
+// Each record still idles the GPU for a few microseconds, so the sweeps of one
+// iteration share one interval: its mean is the time per launch.
 enum { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseRig = 4, kPhaseLL = 5 };
 
-void mark(voldor_ctx *c, hipStream_t s, int phase)
+void mark(voldor_ctx *c, hipStream_t s, int phase, int launches = 0)
 {
     if (!c->timing) return;
     // a full slot moves its last event forward: the whole-window time stays exact
     const int i = c->n_ev < kEvPerWin ? c->n_ev : kEvPerWin - 1;
     if (hipEventRecord(c->ev[c->tw_cur * kEvPerWin + i], s) != hipSuccess) return;
     c->ev_phase[c->tw_cur][i] = phase;
+    c->ev_launches[c->tw_cur][i] = launches;
     c->n_ev = i + 1;
 }
 
@@ -133,7 +136,7 @@ void slot_timing(const voldor_ctx *c, int w, double *ms8)
         if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) != hipSuccess) continue;
         const int ph = c->ev_phase[w][i];
         if (ph >= 0 && ph < 6) ms8[ph] += ms;
-        if (ph == kPhaseSweep) ms8[3] += 1.0;
+        if (ph == kPhaseSweep) ms8[3] += c->ev_launches[w][i];
     }
     float tot = 0.0f;
     if (n > 1 && hipEventElapsedTime(&tot, ev[0], ev[n - 1]) == hipSuccess) ms8[6] = tot;
@@ -363,12 +366,13 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
                 rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0, poses, s);
             mark(c, s, kPhasePose);
         }
-        for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw) {
+        int swn = 0;
+        for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw, ++swn) {
             const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
             rc = launch_sweep(c, depth, depth, X, d, e, (float)p->gamma, p->seed, gs, (int)(gs % 4),
                               c->range, nullptr, s);
-            mark(c, s, kPhaseSweep);
         }
+        mark(c, s, kPhaseSweep, swn);
         // unsmoothed W, then the scale gauge: depth rescaled in the same pass
         if (rc == 0)
             rc = launch_rigidness(c, depth, X, d, e, rigidness, nullptr, nullptr, nullptr, nullptr, s, depth, poses);
@@ -435,8 +439,11 @@ int voldor_set_timing(voldor_ctx *c, int enable)
     if (enable && !c->timing) {
         c->ev = (hipEvent_t *)calloc((size_t)kTimingRing * kEvPerWin, sizeof(hipEvent_t));
         if (!c->ev) return VOLDOR_ENOMEM;
+        // the events only time: without the system-scope fence a record costs a
+        // timestamp, not a writeback and invalidation of every L2 (~5 us of idle
+        // GPU at each phase boundary)
         for (int i = 0; i < kTimingRing * kEvPerWin; ++i)
-            if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableSystemFence) != hipSuccess) {
                 for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
                 free(c->ev);
                 c->ev = nullptr;

@@ -77,6 +77,7 @@ struct voldor_ctx {
     long long tw_count;    // windows recorded since the last summary
     hipEvent_t *ev;        // [kTimingRing][kEvPerWin]
     int ev_phase[vo::kTimingRing][vo::kEvPerWin];   // phase of the interval that ends at an event
+    int ev_launches[vo::kTimingRing][vo::kEvPerWin];   // kernel launches of a sweep interval
     int ev_n[vo::kTimingRing];
     double last_ms[8];
     hipStream_t last_stream;
