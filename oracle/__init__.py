@@ -24,7 +24,7 @@ DEFAULTS = dict(
     lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-5,
     a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
     sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
-    depth_lo=0.0, depth_hi=0.0, seed=0,
+    depth_lo=0.0, depth_hi=0.0, seed=0, criterion=0, reserved=0,
 )
 
 
@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
-        ("seed", C.c_uint64),
+        ("seed", C.c_uint64), ("criterion", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -81,6 +81,7 @@ def lib():
                                       i, C.c_double, C.c_double, i8, d]),
             "or_p3p": (C.c_int, [d, d, d, d]),
             "or_kde": (C.c_double, [d, d, i, d, C.c_double, C.c_double]),
+            "or_depth_score": (C.c_double, [d, f, i, i, i, d, P, d, i, i, C.c_double]),
             "or_meanshift": (C.c_int, [d, d, i, d, C.c_double, C.c_double, C.c_double, i, d]),
             "or_pose_step": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
             "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
@@ -222,6 +223,15 @@ def fb_map(r, direction, gamma):
     q = np.zeros_like(r)
     lib().or_fb_map(_ptr(r), T, H, W, direction, gamma, _ptr(q))
     return q
+
+
+def depth_score(q, flows, K, p, M, x, y, theta):
+    """Depth M-step objective sum_t term_t at pixel (x, y) for candidate depth
+    theta, q [T][H][W] (criterion from p: 0 MIE, 1 MLE)."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    return lib().or_depth_score(_ptr(_d(q)), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p),
+                                _ptr(_d(M)), x, y, theta)
 
 
 def sweep(theta, flows, K, p, M, d_lo, d_hi, global_sweep, direction):

@@ -17,7 +17,8 @@
  *                 (Sec. 5.2, Eq. 15-19); rigidness E-step by forward-backward
  *                 on 1-D chains (Eq. 11-14); depth M-step by the maximum-
  *                 inlier criterion with sampling + propagation (Eq. 10,
- *                 Fig. 5); rigidness without smoothing.
+ *                 Fig. 5) or, as a variant, the maximum-likelihood criterion
+ *                 it relaxes (Eq. 9); rigidness without smoothing.
  * The residual model is the Fisk (log-logistic) density of the squared
  * end-point error with flow-dependent scale/shape (Eq. 4-8).
  *
@@ -54,6 +55,8 @@ typedef struct {
     double x_floor;            /* floor of the squared residual                  */
     double depth_lo, depth_hi; /* >0: caller-fixed sampling range                */
     uint64_t seed;
+    int32_t criterion;         /* depth M-step: 0 MIE (Eq. 10), 1 MLE (Eq. 9)    */
+    int32_t reserved;          /* must be 0                                      */
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EDEGENERATE = -4 };
@@ -556,6 +559,21 @@ void or_fb_map(const double *r, int T, int H, int W, int dir, double gamma, doub
 /* the previous depth, the neighbour's new depth (k>0), a random sample.    */
 /* Ties prefer previous, then neighbour, then sample.                       */
 /* ------------------------------------------------------------------------ */
+/* Term of frame t in the depth M-step objective at a candidate depth, given
+ * the E-step's q = q(W_t = 1):
+ *   MIE (Eq. 10): q log(rho / (rho + mu)) = q ell; a missing observation has
+ *                 ell = log 1/2 (r = 1/2, no evidence either way);
+ *   MLE (Eq. 9, the estimator that Eq. 10 relaxes): the expectation over
+ *                 W_t of log P(X_t | theta, W_t), q log rho + (1 - q) log mu.
+ *                 mu depends on theta through the flow it is evaluated on
+ *                 (sampled at pi_{t-1}(theta)), so the W = 0 term stays.  A
+ *                 missing observation has no likelihood factor: term 0. */
+static double depth_term(const or_params *p, const or_emis *e, double q)
+{
+    if (p->criterion == 1) return e->observed ? q * e->logrho + (1 - q) * e->logmu : 0.0;
+    return q * e->ell;
+}
+
 static double mie_score(const or_frame_set *F, const or_params *p, const double *M,
                         const double *q, int x, int y, double theta)
 {
@@ -563,7 +581,7 @@ static double mie_score(const or_frame_set *F, const or_params *p, const double 
     size_t j = (size_t)y * F->W + x;
     for (int t = 1; t <= F->T; ++t) {
         or_emis e = emission(F, p, M, t, x, y, theta);
-        s += q[(size_t)(t - 1) * F->H * F->W + j] * e.ell;
+        s += depth_term(p, &e, q[(size_t)(t - 1) * F->H * F->W + j]);
     }
     return s;
 }
@@ -575,9 +593,20 @@ static double mie_mass(const or_frame_set *F, const or_params *p, const double *
     size_t j = (size_t)y * F->W + x;
     for (int t = 1; t <= F->T; ++t) {
         or_emis e = emission(F, p, M, t, x, y, theta);
-        s += fabs(q[(size_t)(t - 1) * F->H * F->W + j] * e.ell);
+        const double qt = q[(size_t)(t - 1) * F->H * F->W + j];
+        /* per-item magnitude of the objective's terms (the near-tie scale) */
+        s += p->criterion == 1 ? (e.observed ? qt * fabs(e.logrho) + (1 - qt) * fabs(e.logmu) : 0.0)
+                               : fabs(qt * e.ell);
     }
     return s;
+}
+
+/* test hook: the depth M-step objective sum_t term_t at pixel (x, y) */
+double or_depth_score(const double *q, const float *flows, int T, int H, int W, const double *K,
+                      const or_params *p, const double *M, int x, int y, double theta)
+{
+    or_frame_set F = {flows, T, H, W, K[0], K[1], K[2], K[3]};
+    return mie_score(&F, p, M, q, x, y, theta);
 }
 
 /* theta_in -> theta_out (may alias); q_out [T][H][W] optional;
@@ -1246,6 +1275,8 @@ static int params_ok(const or_params *p, int T, int H, int W, const double *K)
     if (p->n_pose_groups < 1 || p->n_iters < 1 || p->sweeps_per_iter < 1) return 0;
     if (p->lmeds_hypotheses < 1 || p->lmeds_eval_pixels < 8 || p->n_seeds < 0) return 0;
     if (!(p->sigma2_trans > 0) || !(p->sigma2_rot > 0) || !(p->beta_min > 0) || !(p->x_floor > 0)) return 0;
+    if (p->criterion != 0 && p->criterion != 1) return 0;
+    if (p->reserved != 0) return 0;
     return 1;
 }
 

@@ -186,6 +186,73 @@ def test_emission_missing_cases():
     assert not obs[0, 3, 4] and not obs[0, 2, 3] and obs[0, 10, 10]
 
 
+def _three_frame_world(f=100.0, W=24, H=16, shift=6.0, theta=5.0):
+    """T=3, camera translating along x by `shift` px of disparity per frame at
+    depth theta, identity rotation; constant observed flows (exact bilinear)."""
+    K = (f, f, W / 2, H / 2)
+    M = np.zeros((4, 12))
+    M[:, [0, 4, 8]] = 1
+    M[:, 9] = np.arange(4) * shift * theta / f
+    u = np.array([5.0, 7.5, 4.0])
+    fl = np.zeros((3, H, W, 2), np.float32)
+    for t in range(3):
+        fl[t, ..., 0] = u[t]
+        fl[t, ..., 1] = 0.5 * t
+    return K, M, fl, u
+
+
+@pytest.mark.parametrize("crit", [0, 1])
+def test_depth_objective_against_scipy(crit):
+    # Eq. 9 (MLE): sum_t q log rho + (1 - q) log mu over observed frames; Eq. 10
+    # (MIE): sum_t q log(rho / (rho + mu)), log 1/2 where missing.  The rigid flow
+    # is restated from the pinhole projection, the densities come from scipy.
+    p = oracle.params(criterion=crit)
+    K, M, fl, u = _three_frame_world()
+    f, cx = K[0], K[2]
+    rng = np.random.default_rng(5)
+    q = rng.uniform(0.05, 0.95, (3, 16, 24))
+    for x, y, th in [(5, 4, 5.0), (10, 7, 5.0), (14, 3, 5.0), (9, 8, 3.7), (2, 12, 9.0)]:
+        got = oracle.depth_score(q, fl, K, p, M, x, y, th)
+        want = 0.0
+        for t in range(1, 4):
+            prev_u = x + f * M[t - 1, 9] / th          # pi_{t-1}: lookup location of X_t
+            xi = f * (M[t, 9] - M[t - 1, 9]) / th      # rigid flow pi_t - pi_{t-1} along x
+            qt = q[t - 1, y, x]
+            if not (0 <= prev_u <= 23):
+                want += 0.0 if crit == 1 else qt * math.log(0.5)
+                continue
+            v = np.array([u[t - 1], 0.5 * (t - 1)])
+            x2 = max((xi - v[0]) ** 2 + v[1] ** 2, p.x_floor)
+            vn = np.linalg.norm(v)
+            fk = scipy.stats.fisk(c=max(p.b1 * vn + p.b2, p.beta_min), scale=p.a1 * math.exp(p.a2 * vn))
+            lr, lm = fk.logpdf(x2), fk.logpdf((p.lam * vn) ** 2)
+            if crit == 1:
+                want += qt * lr + (1 - qt) * lm
+            else:
+                want += qt * (lr - np.logaddexp(lr, lm))
+        assert got == pytest.approx(want, rel=1e-10, abs=1e-12), (x, y, th)
+
+
+def test_mle_objective_peaks_at_ground_truth():
+    # noise-free flow, q = 1: log rho is largest at zero residual (B(v) <= 1
+    # makes the Fisk density decreasing), so the true depth beats scaled depths
+    # at every pixel.  Frame 1 only: X_1 is looked up at the pixel itself, with
+    # no interpolation across depth edges (frames t >= 2 sample X_t at
+    # pi_{t-1}, where bilinear interpolation leaves a residual at the truth)
+    w = synthflow.make_window("small", 2, noise=False, outliers=False, T=1, H=40, W=56)
+    R, t = w["poses"][0]
+    M = oracle.cumulative(np.concatenate([R.ravel(), t])[None])
+    p = oracle.params(criterion=1)
+    q = np.ones((1, 40, 56))
+    rng = np.random.default_rng(1)
+    for _ in range(25):
+        x, y = int(rng.integers(4, 52)), int(rng.integers(4, 36))
+        g = float(w["depth"][y, x])
+        s0 = oracle.depth_score(q, w["flows"], w["K"], p, M, x, y, g)
+        for k in (0.8, 0.95, 0.99, 1.01, 1.05, 1.25):
+            assert oracle.depth_score(q, w["flows"], w["K"], p, M, x, y, g * k) < s0
+
+
 def test_identity_projection_and_gt_flow():
     # pi_0 is the pixel itself, and the generator's ground-truth flow equals the
     # rigid flow pi_1 - pi_0 at ground-truth depth and pose.
@@ -484,6 +551,18 @@ def test_window_noise_free_recovery():
     assert np.median(rig) > 0.99
 
 
+def test_window_noise_free_recovery_mle():
+    # the maximum-likelihood depth criterion (Eq. 9) recovers the same truth
+    w = synthflow.make_window("small", 0, noise=False, outliers=False)
+    st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"], oracle.params(n_iters=2, criterion=1))
+    assert st == 0
+    rot, tdir, s = _pose_errors(poses, w["poses"])
+    assert rot.max() < 1e-3 and tdir.max() < 2e-2
+    rel = np.abs(depth * s - w["depth"]) / w["depth"]
+    assert np.median(rel) < 1e-2
+    assert np.median(rig) > 0.99
+
+
 def test_window_outliers_flagged():
     w = synthflow.make_window("small", 0, noise=True, outliers=True)
     st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"], oracle.params(n_iters=3))
@@ -502,6 +581,8 @@ def test_window_invalid_arguments():
     p.struct_size = 3
     assert oracle.window(w["flows"], w["K"], p)[0] == -1
     assert oracle.window(w["flows"], (0, 1, 1, 1), oracle.params())[0] == -1
+    assert oracle.window(w["flows"], w["K"], oracle.params(criterion=2))[0] == -1
+    assert oracle.window(w["flows"], w["K"], oracle.params(reserved=1))[0] == -1
     assert oracle.window(w["flows"], w["K"], oracle.params(gamma=1.0))[0] == -1
     small = np.zeros((1, 8, 8, 2), np.float32)
     assert oracle.window(small, w["K"], oracle.params())[0] == -1
