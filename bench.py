@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--criterion", default="mie", choices=["mie", "mle"],
+                    help="depth M-step: maximum inlier (Eq. 10) or maximum likelihood (Eq. 9)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
@@ -397,7 +399,8 @@ def main():
     spec = w["spec"]
     T, H, W = spec.T, spec.H, spec.W
     flows = torch.from_numpy(w["flows"]).to("cuda:0")
-    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed)
+    crit = 1 if args.criterion == "mle" else 0
+    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit)
     solver = vo.Solver(T, H, W, spec.n_groups)
     solver.set_timing(True)
     dev = flows.device
@@ -457,7 +460,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: T={T}, {W}x{H}, {spec.n_iters} EM iterations, "
-                               f"{spec.n_groups} P3P groups/frame, seed {args.seed}",
+                               f"{spec.n_groups} P3P groups/frame, seed {args.seed}"
+                               + (", depth criterion MLE (Eq. 9)" if crit else ""),
+                   "criterion": args.criterion,
                    "T": T, "H": H, "W": W, "n_iters": spec.n_iters, "n_pose_groups": spec.n_groups,
                    "parallelism": "single GPU, one window per step, enqueued back to back on one stream"},
         "windows_per_s": 1e3 / ms,
@@ -466,7 +471,7 @@ def main():
         "concurrent": conc_line,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload),
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload) if not crit else None,
                      "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms,
                      "hbm_view": {"alg_bytes_per_launch": alg_bytes, "achieved_GBs": achieved_gbs,
                                   "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
@@ -474,7 +479,7 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed)
+        kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit)
         c0 = time.perf_counter()
         st, *_ = oracle.window(w["flows"], w["K"], oracle.params(**kw))
         c1 = time.perf_counter()

@@ -66,11 +66,17 @@ typedef struct {
     double x_floor;            /* floor applied to squared residuals (px^2)           */
     double depth_lo, depth_hi; /* > 0: fixed depth sampling range; 0: from bootstrap */
     uint64_t seed;             /* Philox4x64-10 key word 0 of every random draw      */
+    int32_t criterion;         /* depth M-step: VOLDOR_CRITERION_MIE (Eq. 10) or     */
+                               /* VOLDOR_CRITERION_MLE (Eq. 9, expected log-likelihood */
+                               /* sum_t q log rho + (1-q) log mu; a missing frame adds 0)*/
+    int32_t reserved;          /* must be 0                                           */
 } voldor_params;
+
+enum { VOLDOR_CRITERION_MIE = 0, VOLDOR_CRITERION_MLE = 1 };
 
 /* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
  * 100 mean-shift iterations, tol 1e-5, 512 hypotheses, 16384 eval pixels,
- * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0). */
+ * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0, MIE). */
 void voldor_params_default(voldor_params *p);
 
 /* Static description of a status code. */

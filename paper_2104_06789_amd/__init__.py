@@ -37,8 +37,11 @@ class Params(C.Structure):
         ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
-        ("seed", C.c_uint64),
+        ("seed", C.c_uint64), ("criterion", C.c_int32), ("reserved", C.c_int32),
     ]
+
+
+CRITERION_MIE, CRITERION_MLE = 0, 1
 
 
 class WindowDesc(C.Structure):

@@ -34,14 +34,19 @@ bool params_ok(const voldor_params *p)
     if (!(p->beta_min > 0) || !(p->x_floor > 0) || !(p->ms_tol >= 0)) return false;
     if (!(p->depth_lo >= 0) || !(p->depth_hi >= 0)) return false;
     if (p->depth_lo > 0 && p->depth_hi > 0 && !(p->depth_hi > p->depth_lo)) return false;
+    if (p->criterion != VOLDOR_CRITERION_MIE && p->criterion != VOLDOR_CRITERION_MLE) return false;
+    if (p->reserved != 0) return false;
     return true;
 }
 
-bool dims_ok(const voldor_ctx *c, int T, int H, int W)
+// a window fits the context, and a chain of either direction fits the LDS of
+// one workgroup under the depth criterion in use
+bool dims_ok(const voldor_ctx *c, int T, int H, int W, int criterion)
 {
     if (!c) return false;
     if (T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max) return false;
-    if ((int)sweep_lds_bytes(T, W) > c->max_lds || (int)sweep_lds_bytes(T, H) > c->max_lds) return false;
+    if ((int)sweep_lds_bytes(T, W, criterion) > c->max_lds || (int)sweep_lds_bytes(T, H, criterion) > c->max_lds)
+        return false;
     return true;
 }
 
@@ -207,6 +212,8 @@ void voldor_params_default(voldor_params *p)
     p->depth_lo = 0.0;
     p->depth_hi = 0.0;
     p->seed = 0;
+    p->criterion = VOLDOR_CRITERION_MIE;
+    p->reserved = 0;
 }
 
 const char *voldor_status_str(int status)
@@ -307,7 +314,7 @@ bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W
 {
     if (!c || !flows || !poses || !depth || !rigidness) return false;
     if (((uintptr_t)flows & 7) != 0) return false;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return false;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W, p->criterion)) return false;
     return p->n_pose_groups <= c->S_max;
 }
 
@@ -370,7 +377,7 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
         for (int sw = 0; sw < p->sweeps_per_iter && rc == 0; ++sw, ++swn) {
             const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
             rc = launch_sweep(c, depth, depth, X, d, e, (float)p->gamma, p->seed, gs, (int)(gs % 4),
-                              c->range, nullptr, s);
+                              c->range, nullptr, s, p->criterion);
         }
         mark(c, s, kPhaseSweep, swn);
         // unsmoothed W, then the scale gauge: depth rescaled in the same pass
@@ -502,7 +509,7 @@ int voldor_emission(voldor_ctx *c, const float *theta, const float *flows, int T
                     float *logrho, float *logmu, void *stream)
 {
     if (!c || !theta || !flows || !M) return VOLDOR_EINVAL;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W, p->criterion)) return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
     int rc = upload_M(c, M, T, s);
@@ -518,7 +525,7 @@ int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
                  double d_hi, int64_t global_sweep, int dir, float *q_out, void *stream)
 {
     if (!c || !theta_in || !theta_out || !flows || !M) return VOLDOR_EINVAL;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W, p->criterion)) return VOLDOR_EINVAL;
     if (dir < 0 || dir > 3 || !(d_lo > 0) || !(d_hi > d_lo) || global_sweep < 0) return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     double rng[4] = {d_lo, d_hi, 1.0, 0.0};
@@ -527,7 +534,7 @@ int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     int rc = upload_M(c, M, T, s);
     if (rc == 0)
         rc = launch_sweep(c, theta_in, theta_out, (const float2 *)flows, dims(T, H, W, K), emis(K, p),
-                          (float)p->gamma, p->seed, global_sweep, dir, c->range, q_out, s);
+                          (float)p->gamma, p->seed, global_sweep, dir, c->range, q_out, s, p->criterion);
     if (rc) return rc;
     return hipStreamSynchronize(s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
@@ -538,7 +545,7 @@ int voldor_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
                      void *stream)
 {
     if (!c || !theta || !flows || !M || !T_out) return VOLDOR_EINVAL;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W, p->criterion)) return VOLDOR_EINVAL;
     if (t < 1 || t > T || it < 0 || p->n_pose_groups > c->S_max) return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
@@ -570,7 +577,7 @@ int voldor_bootstrap(voldor_ctx *c, const float *flows, int T, int H, int W, con
                      void *stream)
 {
     if (!c || !flows || !relT || !theta || !range) return VOLDOR_EINVAL;
-    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W)) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || !dims_ok(c, T, H, W, p->criterion)) return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int rc = launch_bootstrap(c, (const float2 *)flows, dims(T, H, W, K), p->lmeds_hypotheses,
                               p->lmeds_eval_pixels, p->seed, p->depth_lo, p->depth_hi, c->rel_tmp, theta, s);

@@ -138,6 +138,25 @@ __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, f
     return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
 }
 
+// The same d = log(mu / rho), and log mu itself (Eq. 8: the Fisk density at
+// squared EPE lambda^2 |v|^2, log(beta) - log(alpha) included), for the
+// maximum-likelihood depth criterion (Eq. 9), whose per-frame term is
+// q log rho + (1 - q) log mu = log mu - q d.
+__device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, float vy, const EmisParams &e,
+                                              float &lmu)
+{
+    const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
+    const float vn2 = fmaf(vx, vx, vy * vy);
+    const float vn = __builtin_amdgcn_sqrtf(vn2);
+    const float la = fmaf(e.a2, vn, e.log_a1);
+    const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+    const float lx = fast_log(x2);
+    const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+    const float z1 = beta * (lx - la), z2 = beta * (lm - la);
+    lmu = (fast_log(beta) - la) + (beta - 1.0f) * (lm - la) - 2.0f * softplus(z2);
+    return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+}
+
 __device__ __forceinline__ Emis emis_from_d(float d)
 {
     const float e = fast_exp(-fabsf(d));

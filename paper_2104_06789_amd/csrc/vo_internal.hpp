@@ -103,7 +103,8 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
 // ---- sweep / emission (vo_sweep.hip)
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
                  const WinDims &d, const EmisParams &e, float gamma, uint64_t seed,
-                 int64_t gsweep, int dir, const double *range_dev, float *q_out, hipStream_t s);
+                 int64_t gsweep, int dir, const double *range_dev, float *q_out, hipStream_t s,
+                 int criterion);
 // theta_gauge (with rel_poses): also writes theta / |t_1| there, after use
 int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, const WinDims &d,
                      const EmisParams &e, float *r, float *ell, float *logrho, float *logmu,
@@ -111,7 +112,7 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
                      const double *rel_poses = nullptr);
 int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
                   hipStream_t s);
-size_t sweep_lds_bytes(int T, int L);
+size_t sweep_lds_bytes(int T, int L, int criterion);
 
 // ---- pose (vo_pose.hip)
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,

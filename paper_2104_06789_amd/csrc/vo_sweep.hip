@@ -73,8 +73,11 @@ __device__ __forceinline__ bool item_log_odds(const FrameF *fr, const float2 *__
     return true;
 }
 
-// MIE score sum_t q_t ell_t(th) at chain position k, frames in chunks of three
-// so that the flow gathers of a chunk are in flight together
+// Depth score at chain position k, frames in chunks of three so that the flow
+// gathers of a chunk are in flight together: MIE (Eq. 10) sum_t q_t ell_t(th),
+// a missing frame log 1/2; MLE (Eq. 9) sum_t log mu_t - q_t d_t, a missing
+// frame 0
+template <int CRIT>
 __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
                                              int T, int H, int W, const EmisParams &e, int x, int y,
                                              float xh, float yh, float th, const float *q, int L,
@@ -121,17 +124,30 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
         for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
             if (t > T) break;
-            float ell = kLogHalf;
-            if (val[u]) {
-                const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
-                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
-                    const float dd = log_mu_over_rho((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
-                    ell = emis_from_d(dd).ell;
+            if constexpr (CRIT == 0) {
+                float ell = kLogHalf;
+                if (val[u]) {
+                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
+                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
+                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                        const float dd = log_mu_over_rho((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                        ell = emis_from_d(dd).ell;
+                    }
+                }
+                s = fmaf(q[(t - 1) * L + k], ell, s);
+            } else {
+                if (val[u]) {
+                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
+                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
+                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                        float lmu;
+                        const float dd = log_mu_and_d((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
+                        s += fmaf(-q[(t - 1) * L + k], dd, lmu);
+                    }
                 }
             }
-            s = fmaf(q[(t - 1) * L + k], ell, s);
         }
         pdx = dx[2];
         pdy = dy[2];
@@ -142,12 +158,12 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
 
 // log(mu/rho) for a batch of B independent (pixel, frame, depth) items; the
 // flow gathers of the whole batch are issued before any of them is used.
-// ok[b] false: missing observation (or inactive item).
-template <int B>
+// ok[b] false: missing observation (or inactive item).  MU: log mu as well.
+template <int B, bool MU = false>
 __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *__restrict__ flows, int H,
                                                int W, const EmisParams &e, const int *x, const int *y,
                                                const float *th, const int *t, const bool *act, float *d,
-                                               bool *ok)
+                                               bool *ok, float *lmu = nullptr)
 {
     const int HW = H * W;
     float dx0[B], dy0[B], dx1[B], dy1[B], ax[B], ay[B];
@@ -180,7 +196,13 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         ok[b] = ok[b] && isfinite(A.x + A.y + Bv.x + Bv.y + Cv.x + Cv.y + Dv.x + Dv.y);
         const float vu = (1.0f - ay[b]) * fmaf(ax[b], Bv.x - A.x, A.x) + ay[b] * fmaf(ax[b], Dv.x - Cv.x, Cv.x);
         const float vv = (1.0f - ay[b]) * fmaf(ax[b], Bv.y - A.y, A.y) + ay[b] * fmaf(ax[b], Dv.y - Cv.y, Cv.y);
-        d[b] = ok[b] ? log_mu_over_rho((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+        if constexpr (MU) {
+            float lm = 0.0f;
+            d[b] = ok[b] ? log_mu_and_d((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e, lm) : 0.0f;
+            lmu[b] = ok[b] ? lm : 0.0f;
+        } else {
+            d[b] = ok[b] ? log_mu_over_rho((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+        }
     }
 }
 
@@ -238,7 +260,8 @@ __device__ __forceinline__ Mat2 shfl_down_m(const Mat2 &m, int d)
     return r;
 }
 
-// LDS words of the dynamic area for a chain of length L and T frames
+// LDS words of the dynamic area for a chain of length L and T frames (the MLE
+// criterion adds log mu of the previous depth, T L words after region 2)
 __host__ __device__ inline int sweep_region2_words(int T, int L)
 {
     int w = T * L;
@@ -247,6 +270,8 @@ __host__ __device__ inline int sweep_region2_words(int T, int L)
     return w;
 }
 
+// CRIT 0: maximum-inlier depth criterion (Eq. 10); 1: maximum likelihood (Eq. 9)
+template <int CRIT>
 __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
@@ -274,6 +299,8 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     int *nxt = flg + L;                                // [L]   next(k)
     float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
     float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
+    // MLE: region 2 holds d = log(mu/rho) of the previous depth, lmq its log mu
+    float *lmq = lq + sweep_region2_words(T, L);       // [T][L] (MLE only)
 
     load_frames(a.Mcum, T, fr);
     if (tid == 0) {
@@ -319,19 +346,33 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
             k += kSweepThreads;
             while (k >= L) { k -= L; ++t; }
         }
-        batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+        if constexpr (CRIT == 0) {
+            batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = i0 + b * kSweepThreads;
-            if (!act[b]) continue;
-            float ell = kLogHalf, r = 0.5f;
-            if (ok[b]) {
-                const Emis m = emis_from_d(dd[b]);
-                ell = m.ell;
-                r = m.r;
+            for (int b = 0; b < 4; ++b) {
+                const int i = i0 + b * kSweepThreads;
+                if (!act[b]) continue;
+                float ell = kLogHalf, r = 0.5f;
+                if (ok[b]) {
+                    const Emis m = emis_from_d(dd[b]);
+                    ell = m.ell;
+                    r = m.r;
+                }
+                lq[i] = ell;
+                fq[i] = r;
             }
-            lq[i] = ell;
-            fq[i] = r;
+        } else {
+            float lm[4];
+            batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = i0 + b * kSweepThreads;
+                if (!act[b]) continue;
+                // missing: d = 0 (r = 1/2 in the E-step) and log mu = 0 (term 0)
+                lq[i] = dd[b];
+                lmq[i] = lm[b];
+                fq[i] = ok[b] ? emis_from_d(dd[b]).r : 0.5f;
+            }
         }
     }
     __syncthreads();
@@ -401,7 +442,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
                 const float n1 = ff1 * b1, n0 = ff0 * b0;
                 rq[k] = n1 * frcp(n1 + n0);
                 if (k > s0) {
-                    const float r1 = fast_exp(ll[k]), r0 = 1.0f - r1;
+                    const float r1 = CRIT == 0 ? fast_exp(ll[k]) : frcp(1.0f + fast_exp(ll[k])), r0 = 1.0f - r1;
                     const float e1 = r1 * b1, e0 = r0 * b0;
                     const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
                     const float inv = frcp(m1 + m0);
@@ -422,7 +463,11 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     // ---- S: score of the previous depth
     for (int k = tid; k < L; k += kSweepThreads) {
         float s = 0.0f;
-        for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        if constexpr (CRIT == 0) {
+            for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        } else {
+            for (int t = 0; t < T; ++t) s += fmaf(-fq[t * L + k], lq[t * L + k], lmq[t * L + k]);
+        }
         sa[k] = s;
     }
     __syncthreads();
@@ -443,17 +488,32 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
             k += kSweepThreads;
             while (k >= L) { k -= L; ++t; }
         }
-        batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+        if constexpr (CRIT == 0) {
+            batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = i0 + b * kSweepThreads;
-            if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+            for (int b = 0; b < 4; ++b) {
+                const int i = i0 + b * kSweepThreads;
+                if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+            }
+        } else {
+            // the sample's whole term log mu - q d (0 where missing)
+            float lm[4];
+            batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = i0 + b * kSweepThreads;
+                if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b], lm[b]) : 0.0f;
+            }
         }
     }
     __syncthreads();
     for (int k = tid; k < L; k += kSweepThreads) {
         float s = 0.0f;
-        for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        if constexpr (CRIT == 0) {
+            for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
+        } else {
+            for (int t = 0; t < T; ++t) s += lq[t * L + k];
+        }
         const bool smp = s > sa[k];
         aval[k] = smp ? sm[k] : th[k];
         if (smp) sa[k] = s;
@@ -499,7 +559,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
-                const float s = chain_score(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
+                const float s = chain_score<CRIT>(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
             }
             if (!w) atomicMin(&first[sl], p);
@@ -718,18 +778,19 @@ __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-size_t sweep_lds_bytes(int T, int L)
+size_t sweep_lds_bytes(int T, int L, int criterion)
 {
-    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L)) * sizeof(float);
+    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L) + (criterion ? (size_t)T * L : 0)) *
+           sizeof(float);
 }
 
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
                  const WinDims &d, const EmisParams &e, float gamma, uint64_t seed, int64_t gsweep,
-                 int dir, const double *range_dev, float *q_out, hipStream_t s)
+                 int dir, const double *range_dev, float *q_out, hipStream_t s, int criterion)
 {
     const int L = (dir & 1) ? d.H : d.W;
     const int nchain = (dir & 1) ? d.W : d.H;
-    const size_t lds = sweep_lds_bytes(d.T, L);
+    const size_t lds = sweep_lds_bytes(d.T, L, criterion);
     if (L < 16) return VOLDOR_EINVAL;
     SweepArgs a;
     a.theta_in = theta_in;
@@ -747,10 +808,13 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.gamma = gamma;
     a.seed = seed;
     a.gsweep = gsweep;
-    if (lds > 65536 &&
-        hipFuncSetAttribute((const void *)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    const void *kern = criterion ? (const void *)k_sweep<1> : (const void *)k_sweep<0>;
+    if (lds > 65536 && hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return VOLDOR_EDEVICE;
-    hipLaunchKernelGGL(k_sweep, dim3(nchain), dim3(kSweepThreads), lds, s, a);
+    if (criterion)
+        hipLaunchKernelGGL(k_sweep<1>, dim3(nchain), dim3(kSweepThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_sweep<0>, dim3(nchain), dim3(kSweepThreads), lds, s, a);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 

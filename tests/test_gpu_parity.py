@@ -75,21 +75,23 @@ def test_emission_parity(vo, torch):
     assert np.all(np.abs(lr[m] - olr[m]) <= 2e-4 * (1 + np.abs(olr[m])))
 
 
+@pytest.mark.parametrize("criterion", [0, 1])
 @pytest.mark.parametrize("direction", [0, 1, 2, 3])
-def test_sweep_parity(vo, torch, direction):
-    # ragged sizes: rows of 83, columns of 45, several FB segments per chain
+def test_sweep_parity(vo, torch, direction, criterion):
+    # ragged sizes: rows of 83, columns of 45, several FB segments per chain;
+    # depth criterion MIE (Eq. 10) and MLE (Eq. 9)
     T, H, W = 4, 45, 83
     w, rel, M, gt = _world(20 + direction, T, H, W)
     rng = np.random.default_rng(direction)
     theta = (gt * np.exp(rng.normal(0, 0.15, gt.shape))).astype(np.float32)
     d_lo, d_hi = 0.5 * float(gt.min()), 2.0 * float(gt.max())
-    p = vo.default_params()
+    p = vo.default_params(criterion=criterion)
     s = vo.Solver(T, H, W, 256)
     gs = 7 + direction
     out, q = s.sweep(torch.from_numpy(theta).cuda(), torch.from_numpy(w["flows"]).cuda(), w["K"], p, M,
                      d_lo, d_hi, gs, direction, want_q=True)
     out, q = out.cpu().numpy(), q.cpu().numpy()
-    op = oracle.params()
+    op = oracle.params(criterion=criterion)
     # E-step: smoothed rigidness of the previous depth
     orr, *_ = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"], op, M)
     oq = oracle.fb_map(orr, direction, op.gamma)
@@ -196,6 +198,8 @@ def test_invalid_arguments(vo, torch):
     big = torch.zeros((3, 32, 32, 2), device="cuda")
     assert s.window_status(big, (40.0, 40.0, 16.0, 16.0), vo.default_params()) == -1
     assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(gamma=0.3)) == -1
+    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(criterion=2)) == -1
+    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(reserved=1)) == -1
 
 
 def _window_compare(vo, torch, w, kw, T, H, W, S):
@@ -253,6 +257,22 @@ def test_window_parity_cpu_sized_workload(vo, torch):
     assert r["depth_med"] <= 1e-3
     assert r["rig_p999"] <= 1e-4
     assert r["ll"] <= 1e-5
+
+
+def test_window_parity_mle(vo, torch):
+    # the maximum-likelihood depth criterion (Eq. 9) on the T=5 160x120
+    # workload, 3 iterations, 256 groups per frame: the window tolerances, or
+    # twice the oracle's own response to 1e-5 px of flow noise where larger
+    w = synthflow.make_window("small", 0)
+    spec = w["spec"]
+    kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, criterion=1)
+    r = _window_compare(vo, torch, w, kw, spec.T, spec.H, spec.W, 256)
+    sens = [_oracle_sensitivity(w, kw, seed=k) for k in range(2)]
+    print(r, sens)
+    assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
+    assert r["depth_med"] <= 1e-3
+    assert r["rig_p99"] <= max(1e-4, 2 * max(x["rig_p99"] for x in sens))
+    assert r["ll"] <= max(1e-5, 2 * max(x["ll"] for x in sens))
 
 
 def test_window_async_matches_sync(vo, torch):
