@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_sweep_indoor_hbm_traffic.md)
 SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
                         "write_bytes": 1249.0390625 * 1024 * 1.0}
-SWEEP_SOURCES_SHA = "64a1d83d07f1b852"
+SWEEP_SOURCES_SHA = "a876d4c9e6dd8ce3"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp", "vo_internal.hpp")
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # FP32 lane-instructions/s (non-packed), 39.3 T
 EMISSION_VALU_OPS = 160                      # VALU instructions of one emission evaluation (gfx950 ISA),
