@@ -24,7 +24,7 @@ DEFAULTS = dict(
     lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-5,
     a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
     sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
-    depth_lo=0.0, depth_hi=0.0, seed=0, criterion=0, reserved=0,
+    depth_lo=0.0, depth_hi=0.0, seed=0, criterion=0, pose_start=0,
 )
 
 
@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
-        ("seed", C.c_uint64), ("criterion", C.c_int32), ("reserved", C.c_int32),
+        ("seed", C.c_uint64), ("criterion", C.c_int32), ("pose_start", C.c_int32),
     ]
 
 
@@ -84,6 +84,7 @@ def lib():
             "or_depth_score": (C.c_double, [d, f, i, i, i, d, P, d, i, i, C.c_double]),
             "or_meanshift": (C.c_int, [d, d, i, d, C.c_double, C.c_double, C.c_double, i, d]),
             "or_pose_step": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
+            "or_pose_step_scores": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
             "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
             "or_window": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d]),
             "or_window_init": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d, d, d, C.POINTER(C.c_int)]),
@@ -290,6 +291,21 @@ def pose_step(theta, Wmap, flows, K, p, M, t, it, prevT=None, want_samples=False
     lib().or_pose_step(_ptr(_d(theta)), _ptr(Wm), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)),
                        C.byref(p), _ptr(_d(M)), t, it, _ptr(pv), _ptr(out), _ptr(samples), diag)
     return out, samples, list(diag)
+
+
+def pose_scores(theta, Wmap, flows, K, p, M, t, it, prevT=None):
+    """All-pixel scores of the pose-step candidates: ([0] previous pose or -inf,
+    [1..n] valid samples in (group, root) order) and the step's T_t."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    out = np.zeros(12)
+    sc = np.zeros(1 + 4 * p.n_pose_groups)
+    n = C.c_int(0)
+    Wm = _d(Wmap) if Wmap is not None else None
+    pv = _d(prevT) if prevT is not None else None
+    lib().or_pose_step_scores(_ptr(_d(theta)), _ptr(Wm), _ptr(flows, C.c_float), T, H, W, _ptr(_d(K)),
+                              C.byref(p), _ptr(_d(M)), t, it, _ptr(pv), _ptr(out), _ptr(sc), C.byref(n))
+    return sc[:n.value], out
 
 
 def bootstrap(flows, K, p):

@@ -56,7 +56,8 @@ typedef struct {
     double depth_lo, depth_hi; /* >0: caller-fixed sampling range                */
     uint64_t seed;
     int32_t criterion;         /* depth M-step: 0 MIE (Eq. 10), 1 MLE (Eq. 9)    */
-    int32_t reserved;          /* must be 0                                      */
+    int32_t pose_start;        /* mean-shift start: 0 densest of n_seeds samples */
+                               /* and the previous pose, 1 best all-pixel score  */
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EDEGENERATE = -4 };
@@ -937,9 +938,54 @@ static int pose_group_pixels(uint64_t seed, int it, int t, int g, int64_t HW, in
 /* theta [H][W]; Wmap [T][H][W] or NULL (all ones); M cumulative [T+1][12]
  * (M[t-1] used); prevT [12] or NULL; T_out [12].
  * samples_out optional [4S][8]: p(6), w, valid. */
+/* All-pixel score of a candidate relative pose Tc of frame t: the sum over
+ * every pixel j of W_t^j ell_t^j(theta_j) with M_t = Tc o M_{t-1} (W = 1 when
+ * no rigidness is given; a missing item has ell = log 1/2, as in Eq. 10's
+ * criterion).  Mtmp: scratch of T+1 poses. */
+static double allpix_score(const or_frame_set *F, const or_params *p, const double *M, int t,
+                           const double *theta, const double *Wmap, const double *Tc, double *Mtmp)
+{
+    memcpy(Mtmp, M, sizeof(double) * 12 * t);
+    pose_compose(Tc, M + 12 * (t - 1), Mtmp + 12 * t);
+    const int64_t HW = (int64_t)F->H * F->W;
+    double s = 0;
+    for (int y = 0; y < F->H; ++y)
+        for (int x = 0; x < F->W; ++x) {
+            const int64_t j = (int64_t)y * F->W + x;
+            const or_emis e = emission(F, p, Mtmp, t, x, y, theta[j]);
+            s += (Wmap ? Wmap[(int64_t)(t - 1) * HW + j] : 1.0) * e.ell;
+        }
+    return s;
+}
+
+static int pose_step_core(const double *theta, const double *Wmap, const float *flows, int T, int H,
+                          int W, const double *K, const or_params *p, const double *M, int t, int it,
+                          const double *prevT, double *T_out, double *samples_out, int *diag,
+                          double *scores_out, int *n_scores);
+
 int or_pose_step(const double *theta, const double *Wmap, const float *flows, int T, int H,
                  int W, const double *K, const or_params *p, const double *M, int t, int it,
                  const double *prevT, double *T_out, double *samples_out, int *diag)
+{
+    return pose_step_core(theta, Wmap, flows, T, H, W, K, p, M, t, it, prevT, T_out, samples_out, diag,
+                          NULL, NULL);
+}
+
+/* test hook: the pose step with p->pose_start = 1, also returning the
+ * all-pixel scores: [0] the previous pose (-inf if none), [1..n] the valid
+ * samples in (group, root) order; *n_scores = 1 + n. */
+int or_pose_step_scores(const double *theta, const double *Wmap, const float *flows, int T, int H,
+                        int W, const double *K, const or_params *p, const double *M, int t, int it,
+                        const double *prevT, double *T_out, double *scores_out, int *n_scores)
+{
+    return pose_step_core(theta, Wmap, flows, T, H, W, K, p, M, t, it, prevT, T_out, NULL, NULL,
+                          scores_out, n_scores);
+}
+
+static int pose_step_core(const double *theta, const double *Wmap, const float *flows, int T, int H,
+                          int W, const double *K, const or_params *p, const double *M, int t, int it,
+                          const double *prevT, double *T_out, double *samples_out, int *diag,
+                          double *scores_out, int *n_scores)
 {
     or_frame_set F = {flows, T, H, W, K[0], K[1], K[2], K[3]};
     int S = p->n_pose_groups;
@@ -1021,6 +1067,18 @@ int or_pose_step(const double *theta, const double *Wmap, const float *flows, in
     double wsum = 0;
     for (int i = 0; i < n; ++i) wsum += wts[i];
     int ms_iters = 0, fallback = 0;
+    if (scores_out) {
+        /* every candidate's all-pixel score, whether or not the step uses it */
+        double *Mtmp = (double *)malloc(sizeof(double) * 12 * (t + 1));
+        scores_out[0] = prevT ? allpix_score(&F, p, M, t, theta, Wmap, prevT, Mtmp) : -INFINITY;
+        for (int i = 0; i < n; ++i) {
+            double Tc[12];
+            or_se3_exp(smp + 6 * i, Tc, Tc + 9);
+            scores_out[1 + i] = allpix_score(&F, p, M, t, theta, Wmap, Tc, Mtmp);
+        }
+        free(Mtmp);
+        if (n_scores) *n_scores = 1 + n;
+    }
     if (n == 0 || !(wsum > 0)) {
         fallback = 1;
         if (prevT) memcpy(T_out, prevT, 12 * sizeof(double));
@@ -1030,7 +1088,25 @@ int or_pose_step(const double *theta, const double *Wmap, const float *flows, in
          * pose (if any) and the first n_seeds samples in (group, root) order */
         double best_p[6], best_d = -1;
         int have = 0;
-        if (prevT) {
+        if (p->pose_start == 1) {
+            /* the literal reading of scoring every hypothesis over all pixels:
+             * the start is the candidate (previous pose first, then every
+             * sample in (group, root) order) of highest all-pixel score, the
+             * first on ties */
+            double *Mtmp = (double *)malloc(sizeof(double) * 12 * (t + 1));
+            if (prevT) {
+                or_se3_log(prevT, prevT + 9, best_p);
+                best_d = allpix_score(&F, p, M, t, theta, Wmap, prevT, Mtmp);
+                have = 1;
+            }
+            for (int i = 0; i < n; ++i) {
+                double Tc[12];
+                or_se3_exp(smp + 6 * i, Tc, Tc + 9);
+                const double dd = allpix_score(&F, p, M, t, theta, Wmap, Tc, Mtmp);
+                if (!have || dd > best_d) { best_d = dd; memcpy(best_p, smp + 6 * i, sizeof best_p); have = 1; }
+            }
+            free(Mtmp);
+        } else if (prevT) {
             double pp[6];
             or_se3_log(prevT, prevT + 9, pp);
             double dd = or_kde(smp, wts, n, pp, p->sigma2_trans, p->sigma2_rot);
@@ -1038,7 +1114,7 @@ int or_pose_step(const double *theta, const double *Wmap, const float *flows, in
             best_d = dd;
             have = 1;
         }
-        int ns = n < p->n_seeds ? n : p->n_seeds;
+        int ns = p->pose_start == 1 ? 0 : (n < p->n_seeds ? n : p->n_seeds);
         for (int i = 0; i < ns; ++i) {
             double dd = or_kde(smp, wts, n, smp + 6 * i, p->sigma2_trans, p->sigma2_rot);
             if (!have || dd > best_d) { best_d = dd; memcpy(best_p, smp + 6 * i, sizeof best_p); have = 1; }
@@ -1276,7 +1352,7 @@ static int params_ok(const or_params *p, int T, int H, int W, const double *K)
     if (p->lmeds_hypotheses < 1 || p->lmeds_eval_pixels < 8 || p->n_seeds < 0) return 0;
     if (!(p->sigma2_trans > 0) || !(p->sigma2_rot > 0) || !(p->beta_min > 0) || !(p->x_floor > 0)) return 0;
     if (p->criterion != 0 && p->criterion != 1) return 0;
-    if (p->reserved != 0) return 0;
+    if (p->pose_start != 0 && p->pose_start != 1) return 0;
     return 1;
 }
 

@@ -435,6 +435,57 @@ def test_meanshift_zero_weights_ignored():
 
 
 # ---------------------------------------------------------------- bootstrap (Sec. 5.3)
+def test_allpixel_scores_are_rigidness_weighted_ell_sums():
+    # each candidate's score is sum_j W_t^j ell_t^j over every pixel at
+    # M_t = T_c o M_{t-1}: restated from the emission map (pinned to scipy above)
+    w = synthflow.make_window("small", 6, T=3, H=24, W=32)
+    R, t = w["poses"][0]
+    rel = np.array([np.concatenate([R_.ravel(), t_ / np.linalg.norm(t)]) for R_, t_ in w["poses"]])
+    M = oracle.cumulative(rel)
+    th = w["depth"] / np.linalg.norm(t)
+    rig = np.random.default_rng(2).uniform(0.1, 1.0, (3, 24, 32))
+    p = oracle.params(n_pose_groups=24, pose_start=1)
+    t_ = 2
+    sc, _ = oracle.pose_scores(th, rig, w["flows"], w["K"], p, M, t_, 1, prevT=rel[t_ - 1])
+    _, smp, diag = oracle.pose_step(th, rig, w["flows"], w["K"], p, M, t_, 1, prevT=rel[t_ - 1], want_samples=True)
+    valid = smp[smp[:, 7] > 0]
+    assert len(sc) == 1 + len(valid) == 1 + diag[0]
+    cands = [rel[t_ - 1]] + [np.concatenate([a.ravel(), b]) for a, b in (oracle.se3_exp(v[:6]) for v in valid)]
+    for i in range(0, len(cands), max(1, len(cands) // 8)):
+        Rc, tc = cands[i][:9].reshape(3, 3), cands[i][9:]
+        Rm, tm = M[t_ - 1][:9].reshape(3, 3), M[t_ - 1][9:]
+        Mi = M.copy()
+        Mi[t_] = np.concatenate([(Rc @ Rm).ravel(), Rc @ tm + tc])
+        r, ell, lr, lm, obs = oracle.emission_map(th, w["flows"], w["K"], p, Mi)
+        assert sc[i] == pytest.approx(float(np.sum(rig[t_ - 1] * ell[t_ - 1])), rel=1e-12), i
+
+
+def test_allpixel_score_peaks_at_true_pose():
+    # noise-free X_1, W = 1: the true pose scores above every perturbed one
+    w = synthflow.make_window("small", 3, noise=False, outliers=False, T=1, H=40, W=56)
+    R, t = w["poses"][0]
+    gt = np.concatenate([R.ravel(), t])
+    M = oracle.cumulative(gt[None])
+    p = oracle.params(n_pose_groups=8, pose_start=1)
+    s0 = oracle.pose_scores(w["depth"], None, w["flows"], w["K"], p, M, 1, 0, prevT=gt)[0][0]
+    rng = np.random.default_rng(4)
+    for _ in range(8):
+        dR = Rotation.from_rotvec(rng.normal(0, 2e-3, 3)).as_matrix()
+        cand = np.concatenate([(dR @ R).ravel(), t + rng.normal(0, 2e-3, 3)])
+        s1 = oracle.pose_scores(w["depth"], None, w["flows"], w["K"], p, M, 1, 0, prevT=cand)[0][0]
+        assert s1 < s0
+
+
+def test_window_noise_free_recovery_allpixel_start():
+    w = synthflow.make_window("small", 0, noise=False, outliers=False, T=3, H=48, W=64)
+    st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"],
+                                                    oracle.params(n_iters=2, n_pose_groups=32, pose_start=1))
+    assert st == 0
+    rot, tdir, s = _pose_errors(poses, w["poses"])
+    assert rot.max() < 1e-3 and tdir.max() < 2e-2
+    assert np.median(np.abs(depth * s - w["depth"]) / w["depth"]) < 1e-2
+
+
 def test_bootstrap_noise_free_recovers_pose_and_depth():
     w = synthflow.make_window("small", 1, noise=False, outliers=False, T=1)
     p = oracle.params()
@@ -582,7 +633,7 @@ def test_window_invalid_arguments():
     assert oracle.window(w["flows"], w["K"], p)[0] == -1
     assert oracle.window(w["flows"], (0, 1, 1, 1), oracle.params())[0] == -1
     assert oracle.window(w["flows"], w["K"], oracle.params(criterion=2))[0] == -1
-    assert oracle.window(w["flows"], w["K"], oracle.params(reserved=1))[0] == -1
+    assert oracle.window(w["flows"], w["K"], oracle.params(pose_start=2))[0] == -1
     assert oracle.window(w["flows"], w["K"], oracle.params(gamma=1.0))[0] == -1
     small = np.zeros((1, 8, 8, 2), np.float32)
     assert oracle.window(small, w["K"], oracle.params())[0] == -1
