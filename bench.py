@@ -14,8 +14,10 @@ The roofline object reports the dominant GPU kernel, the fused directional
 sweep, against the VALU issue rate it is bound by.  Algorithmic work per
 launch = 3 emission evaluations per pixel-frame (previous depth, random sample,
 propagated neighbour: what the serial walk needs) x EMISSION_VALU_OPS FP32
-VALU lane-instructions each, divided by the mean sweep duration measured with
-HIP events on the solver's stream; the peak is 256 CUs x 64 lanes x 2.4 GHz.
+non-transcendental VALU lane-instructions each, divided by the mean sweep
+duration measured with HIP events on the solver's stream; the peak is 256 CUs x
+64 lanes x 2.4 GHz.  With --pose-start allpixel the dominant kernel is the
+candidate scoring, reported the same way.
 The HBM view of the same launch (flow stack read + depth read/write) is kept
 alongside for reference.  The cpu_baseline object times the FP64 CPU oracle on
 one window of the same workload.
@@ -41,9 +43,14 @@ SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
                         "write_bytes": 1249.0390625 * 1024 * 1.0}
 SWEEP_SOURCES_SHA = "a876d4c9e6dd8ce3"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp", "vo_internal.hpp")
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # FP32 lane-instructions/s (non-packed), 39.3 T
-EMISSION_VALU_OPS = 160                      # VALU instructions of one emission evaluation (gfx950 ISA),
-                                             # 12 of them transcendental
+# Issue peak of non-packed FP32 VALU instructions: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3 T lane-instructions/s (independent v_fma_f32 chains sustain
+# 36.2 T on MI355X).  Transcendental instructions (v_exp/v_log/v_rcp) issue on
+# their own unit beside it, so the algorithmic counts below are the other VALU
+# instructions of one evaluation, read from the gfx950 ISA.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+EMISSION_VALU_OPS = 148                      # one emission evaluation of the sweep (160 VALU, 12 of them
+                                             # transcendental)
 
 
 def _sweep_traffic(workload):
@@ -59,6 +66,58 @@ def _sweep_traffic(workload):
     if h.hexdigest()[:16] != SWEEP_SOURCES_SHA:
         return None
     return SWEEP_TRAFFIC_INDOOR["fetch_bytes"] + SWEEP_TRAFFIC_INDOOR["write_bytes"]
+
+
+CAND_EVAL_VALU_OPS = 46    # one (candidate, pixel) evaluation of k_cand_score: 1484 of the 1676 VALU
+                           # instructions of its 32-evaluation candidate loop are not transcendental
+
+
+def _cumulative(rel):
+    import numpy as np
+    M = [np.concatenate([np.eye(3).ravel(), np.zeros(3)])]
+    for r in np.asarray(rel, dtype=np.float64).reshape(-1, 12):
+        R, t = r[:9].reshape(3, 3), r[9:]
+        Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
+        M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
+    return np.array(M)
+
+
+def _allpixel_roofline(vo, torch, solver, w, spec, p_ap, out, reps=3):
+    """Live figure of the all-pixel candidate scoring (k_cand_score): every
+    frame's pose step at the window's final state, through the step entry point
+    on the current stream, timed with HIP events once with the all-pixel start
+    and once with the KDE start; the difference is the scoring's time, and the
+    candidates x pixels it scored come from the step's own score list."""
+    import numpy as np
+    T, H, W = spec.T, spec.H, spec.W
+    poses = out[0].cpu().numpy()
+    M = _cumulative(poses)
+    p_kde = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=p_ap.seed,
+                              criterion=p_ap.criterion, pose_start=0)
+    flows = torch.from_numpy(w["flows"]).cuda()
+    ms = {0: 0.0, 1: 0.0}
+    evals = 0
+    for rep in range(reps + 1):
+        for t in range(1, T + 1):
+            for key, pp in ((1, p_ap), (0, p_kde)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solver.pose_step(out[1], out[2], flows, w["K"], pp, M, t, spec.n_iters - 1, prevT=poses[t - 1])
+                e1.record()
+                torch.cuda.synchronize()
+                if rep > 0:   # the first pass warms up
+                    ms[key] += e0.elapsed_time(e1)
+                    if key == 1:
+                        evals += len(solver.pose_scores()) * H * W
+    launches = reps * T
+    launch_ms = (ms[1] - ms[0]) / launches
+    ops = evals / launches * CAND_EVAL_VALU_OPS
+    achieved = ops / (launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "k_cand_score", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+            "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+            "alg_ops_per_launch": ops, "evals_per_launch": evals / launches, "launch_ms": launch_ms,
+            "note": "k_cand_score time = pose step with the all-pixel start minus the same step with the "
+                    "KDE start, HIP events on the stream; ops = candidates x pixels x 46 non-transcendental VALU instructions"}
 
 
 def _pose_error(poses, gt):
@@ -364,6 +423,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--criterion", default="mie", choices=["mie", "mle"],
                     help="depth M-step: maximum inlier (Eq. 10) or maximum likelihood (Eq. 9)")
+    ap.add_argument("--pose-start", default="kde", choices=["kde", "allpixel"],
+                    help="mean-shift start: densest of 64 seeds, or every candidate scored over all pixels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
@@ -400,7 +461,9 @@ def main():
     T, H, W = spec.T, spec.H, spec.W
     flows = torch.from_numpy(w["flows"]).to("cuda:0")
     crit = 1 if args.criterion == "mle" else 0
-    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit)
+    pstart = 1 if args.pose_start == "allpixel" else 0
+    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit,
+                          pose_start=pstart)
     solver = vo.Solver(T, H, W, spec.n_groups)
     solver.set_timing(True)
     dev = flows.device
@@ -461,8 +524,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: T={T}, {W}x{H}, {spec.n_iters} EM iterations, "
                                f"{spec.n_groups} P3P groups/frame, seed {args.seed}"
-                               + (", depth criterion MLE (Eq. 9)" if crit else ""),
-                   "criterion": args.criterion,
+                               + (", depth criterion MLE (Eq. 9)" if crit else "")
+                               + (", all-pixel mean-shift start" if pstart else ""),
+                   "criterion": args.criterion, "pose_start": args.pose_start,
                    "T": T, "H": H, "W": W, "n_iters": spec.n_iters, "n_pose_groups": spec.n_groups,
                    "parallelism": "single GPU, one window per step, enqueued back to back on one stream"},
         "windows_per_s": 1e3 / ms,
@@ -477,9 +541,20 @@ def main():
                                   "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
     }
 
-    if not args.no_cpu_baseline:
+    if pstart:
+        # the dominant kernel of this variant is the candidate scoring
+        line["roofline_sweep"] = line["roofline"]
+        line["roofline"] = _allpixel_roofline(vo, torch, solver, w, spec, p, out)
+
+    if pstart and not args.no_cpu_baseline:
+        # the FP64 oracle scores ~10^9 candidate-pixel pairs per pose step here:
+        # hours per window, far beyond a bounded sample of the same workload
+        line["cpu_baseline"] = None
+        line["cpu_baseline_note"] = "not run for the all-pixel start (hours of FP64 work per window)"
+    elif not args.no_cpu_baseline:
         import oracle
-        kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit)
+        kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit,
+                  pose_start=pstart)
         c0 = time.perf_counter()
         st, *_ = oracle.window(w["flows"], w["K"], oracle.params(**kw))
         c1 = time.perf_counter()

@@ -69,14 +69,17 @@ typedef struct {
     int32_t criterion;         /* depth M-step: VOLDOR_CRITERION_MIE (Eq. 10) or     */
                                /* VOLDOR_CRITERION_MLE (Eq. 9, expected log-likelihood */
                                /* sum_t q log rho + (1-q) log mu; a missing frame adds 0)*/
-    int32_t reserved;          /* must be 0                                           */
+    int32_t pose_start;        /* mean-shift start: 0 the densest (kernel density) of */
+                               /* the previous pose and the first n_seeds samples;    */
+                               /* 1 the candidate (previous pose, then every sample)  */
+                               /* of highest sum over all pixels of W_t ell_t        */
 } voldor_params;
 
 enum { VOLDOR_CRITERION_MIE = 0, VOLDOR_CRITERION_MLE = 1 };
 
 /* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
  * 100 mean-shift iterations, tol 1e-5, 512 hypotheses, 16384 eval pixels,
- * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0, MIE). */
+ * beta_min 0.01, x_floor 1e-12, automatic depth range, seed 0, MIE, KDE start). */
 void voldor_params_default(voldor_params *p);
 
 /* Static description of a status code. */
@@ -280,6 +283,17 @@ int voldor_pose_step(voldor_ctx *ctx, const float *theta, const float *rig, cons
                      int T, int H, int W, const double *K, const voldor_params *p, const double *M,
                      int t, int it, const double *prevT, double *T_out, double *samples, int *diag,
                      void *stream);
+
+/* All-pixel candidate scores of the last pose step run with pose_start = 1 on
+ * this context (voldor_pose_step, or the last pose step of a window), for
+ * the reading of hypotheses scored over every pixel (Sec. 5.2):
+ *   scores  host double[max_n]: [0] the previous pose (-inf if there was
+ *           none), [1..] every valid sample in (group, root) order, each the
+ *           sum over all pixels of W_t ell_t at M_t = T_c o M_{t-1}
+ *   n_out   host int: 1 + the number of samples
+ * Waits for the device.  VOLDOR_EINVAL when max_n is too small or no such step
+ * has run. */
+int voldor_pose_scores(voldor_ctx *ctx, double *scores, int max_n, int *n_out);
 
 /* Bootstrap (Sec. 5.3): T_1 by least median of squares over 8-point
  * essential-matrix hypotheses of X_1, depth by two-view triangulation, the

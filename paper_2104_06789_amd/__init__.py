@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("b2", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
-        ("seed", C.c_uint64), ("criterion", C.c_int32), ("reserved", C.c_int32),
+        ("seed", C.c_uint64), ("criterion", C.c_int32), ("pose_start", C.c_int32),
     ]
 
 
@@ -83,6 +83,7 @@ def lib():
         "voldor_emission": (i, [vp, vp, vp, i, i, i, dp, P, dp, vp, vp, vp, vp, vp]),
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
         "voldor_pose_step": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, i, i, dp, dp, vp, ip, vp]),
+        "voldor_pose_scores": (i, [vp, dp, i, ip]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
         "voldor_last_timing": (i, [vp, dp]),
@@ -314,6 +315,16 @@ class Solver:
                                     _ptr(samples), diag, _stream(stream))
         _check(rc, "voldor_pose_step")
         return Tout, samples, list(diag)
+
+    def pose_scores(self):
+        """All-pixel candidate scores of the last pose step run with pose_start=1:
+        [0] the previous pose (-inf if none), [1..] the valid samples in (group,
+        root) order."""
+        buf = np.zeros(1 + 4 * 8192 + 64)
+        n = C.c_int(0)
+        _check(lib().voldor_pose_scores(self._ctx, buf.ctypes.data_as(C.POINTER(C.c_double)), buf.size,
+                                        C.byref(n)), "voldor_pose_scores")
+        return buf[:n.value].copy()
 
     def bootstrap(self, flows, K, params, stream=None):
         """Returns (status, relT [12], theta [H,W] CUDA f32, range [2], info [4])."""

@@ -35,7 +35,7 @@ bool params_ok(const voldor_params *p)
     if (!(p->depth_lo >= 0) || !(p->depth_hi >= 0)) return false;
     if (p->depth_lo > 0 && p->depth_hi > 0 && !(p->depth_hi > p->depth_lo)) return false;
     if (p->criterion != VOLDOR_CRITERION_MIE && p->criterion != VOLDOR_CRITERION_MLE) return false;
-    if (p->reserved != 0) return false;
+    if (p->pose_start != 0 && p->pose_start != 1) return false;
     return true;
 }
 
@@ -97,7 +97,7 @@ PoseParams pose_params(const voldor_params *p)
     pp.S = p->n_pose_groups;
     pp.n_seeds = p->n_seeds;
     pp.ms_max_iters = p->ms_max_iters;
-    pp.pad = 0;
+    pp.pose_start = p->pose_start;
     pp.ms_tol = p->ms_tol;
     pp.s2t = p->sigma2_trans;
     pp.s2r = p->sigma2_rot;
@@ -213,7 +213,7 @@ void voldor_params_default(voldor_params *p)
     p->depth_hi = 0.0;
     p->seed = 0;
     p->criterion = VOLDOR_CRITERION_MIE;
-    p->reserved = 0;
+    p->pose_start = 0;
 }
 
 const char *voldor_status_str(int status)
@@ -278,6 +278,13 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->pose_tmp, 16) == hipSuccess;
     ok = ok && dalloc(&c->rel_tmp, 12 * T_max) == hipSuccess;
     ok = ok && dalloc(&c->theta_tmp, HW) == hipSuccess;
+    const size_t ncand = 1 + pose_sample_slots(S_max);
+    ok = ok && dalloc(&c->cand_F, 12 * ncand) == hipSuccess;
+    ok = ok && dalloc(&c->cand_slot, ncand) == hipSuccess;
+    ok = ok && dalloc(&c->cand_n, 4) == hipSuccess;
+    ok = ok && dalloc(&c->cand_part, ncand * kCandTiles) == hipSuccess;
+    ok = ok && dalloc(&c->cand_score, ncand) == hipSuccess;
+    ok = ok && dalloc(&c->cand_start, 8) == hipSuccess;
     if (!ok) {
         voldor_destroy(c);
         return VOLDOR_ENOMEM;
@@ -298,7 +305,8 @@ void voldor_destroy(voldor_ctx *c)
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->boot_cand, c->boot_sub, c->dkeys, c->hist,
-                    c->sel, c->ll_part, c->init_ll, c->init_rel, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp};
+                    c->sel, c->ll_part, c->init_ll, c->init_rel, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp,
+                    c->cand_F, c->cand_slot, c->cand_n, c->cand_part, c->cand_score, c->cand_start};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(c);
@@ -346,7 +354,7 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
         hipLaunchKernelGGL(k_copy_d, dim3(1), dim3(256), 0, s, poses, rel_boot, 12 * T, c->status);
         d.use_w = 0;
         for (int t = 1; t <= T && rc == 0; ++t)
-            rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, 0, t == 1 ? 1 : 0, poses, s);
+            rc = launch_pose_step(c, depth, rigidness, X, d, e, pp, t, 0, t == 1 ? 1 : 0, poses, s);
         if (rc == 0) rc = launch_rigidness(c, depth, X, d, e, nullptr, nullptr, nullptr, nullptr, c->init_ll, s);
         if (rc == 0) {
             hipLaunchKernelGGL(k_copy_d, dim3(1), dim3(256), 0, s, poses, rel_a, 12 * T, c->status);
@@ -354,7 +362,7 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
         }
         d.use_w = 1;
         for (int t = 1; t <= T && rc == 0; ++t)
-            rc = launch_pose_step(c, init->depth, init->rig, X, d, pp, t, 0, t == 1 ? 1 : 0, poses, s);
+            rc = launch_pose_step(c, init->depth, init->rig, X, d, e, pp, t, 0, t == 1 ? 1 : 0, poses, s);
         if (rc == 0)
             rc = launch_rigidness(c, init->depth, X, d, e, nullptr, nullptr, nullptr, nullptr, c->init_ll + 2, s);
         if (rc == 0) {
@@ -370,7 +378,7 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
         d.use_w = it > 0 ? 1 : 0;
         if (!(it == 0 && proposed)) {
             for (int t = 1; t <= T && rc == 0; ++t)
-                rc = launch_pose_step(c, depth, rigidness, X, d, pp, t, it, (it > 0 || t == 1) ? 1 : 0, poses, s);
+                rc = launch_pose_step(c, depth, rigidness, X, d, e, pp, t, it, (it > 0 || t == 1) ? 1 : 0, poses, s);
             mark(c, s, kPhasePose);
         }
         int swn = 0;
@@ -539,6 +547,19 @@ int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     return hipStreamSynchronize(s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
 
+int voldor_pose_scores(voldor_ctx *c, double *scores, int max_n, int *n_out)
+{
+    if (!c || !scores || !n_out || max_n < 1) return VOLDOR_EINVAL;
+    int n = 0;
+    if (hipDeviceSynchronize() != hipSuccess) return VOLDOR_EDEVICE;
+    if (hipMemcpy(&n, c->cand_n, sizeof n, hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
+    if (n < 1 || n > max_n) return VOLDOR_EINVAL;
+    if (hipMemcpy(scores, c->cand_score, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    *n_out = n;
+    return VOLDOR_OK;
+}
+
 int voldor_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float *flows, int T,
                      int H, int W, const double *K, const voldor_params *p, const double *M, int t,
                      int it, const double *prevT, double *T_out, double *samples, int *diag,
@@ -560,7 +581,7 @@ int voldor_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
         return VOLDOR_EDEVICE;
     WinDims d = dims(T, H, W, K);
     d.use_w = rig ? 1 : 0;
-    int rc = launch_pose_step(c, theta, rig, (const float2 *)flows, d, pose_params(p), t, it,
+    int rc = launch_pose_step(c, theta, rig, (const float2 *)flows, d, emis(K, p), pose_params(p), t, it,
                               prevT ? 1 : 0, c->rel_tmp, s);
     if (rc) return rc;
     if (samples && launch_samples_aos(c, p->n_pose_groups, samples, s) != 0) return VOLDOR_EDEVICE;

@@ -16,6 +16,7 @@ constexpr int kEvalThreads = 512;   // threads of the bootstrap scoring kernel
 constexpr int kEvalPerThread = 32;  // residuals held per thread (16384 max)
 constexpr int kMaxGroups = 8192;    // P3P groups per frame
 constexpr int kLLBlocks = 1024;     // partial sums of the log-likelihood
+constexpr int kCandTiles = 256;     // pixel ranges of the all-pixel candidate scores
 
 // Device status word values (mirror voldor_status).
 enum : int { kStatusOk = 0, kStatusDegenerate = -4 };
@@ -30,7 +31,7 @@ struct WinDims {
 };
 
 struct PoseParams {
-    int S, n_seeds, ms_max_iters, pad;
+    int S, n_seeds, ms_max_iters, pose_start;
     double ms_tol, s2t, s2r;
     uint64_t seed;
 };
@@ -69,6 +70,13 @@ struct voldor_ctx {
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
     float *theta_tmp;      // [H_max W_max]
+    // all-pixel start candidates (pose_start = 1), n = 1 + sample slots at most
+    float *cand_F;         // [n][12] FP32 frames of M_t = T_c o M_{t-1}
+    int *cand_slot;        // [n] sample slot, -1 previous pose, -2 none
+    int *cand_n;           // [4] candidate count
+    float *cand_part;      // [n][kCandTiles] partial scores
+    double *cand_score;    // [n] scores, dense order
+    double *cand_start;    // [8] start point p (6), valid
     // optional phase timing of windows: HIP events on the caller's stream, one
     // ring slot per window so that windows enqueued back to back keep theirs
     int timing;
@@ -116,8 +124,8 @@ size_t sweep_lds_bytes(int T, int L, int criterion);
 
 // ---- pose (vo_pose.hip)
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
-                     const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
-                     double *rel_poses, hipStream_t s);
+                     const WinDims &d, const EmisParams &e, const PoseParams &pp, int t, int it,
+                     int have_prev, double *rel_poses, hipStream_t s);
 int launch_samples_aos(voldor_ctx *c, int S, double *out, hipStream_t s);
 size_t pose_sample_slots(int S_max);
 size_t pose_seed_parts();

@@ -232,6 +232,7 @@ struct SeedArgs {
     double *seed_score;    // [n_seeds + 1][8]: p (6), unused, valid
     double *seed_part;     // [n_seeds + 1][kSeedParts] partial densities
     const double *prev;    // previous relative pose T_t
+    const double *start_p; // or NULL: candidate 0 is this se(3) point instead (p (6), valid)
     const int *status;
     int ns, nb, have_prev;
     double is2t, is2r;
@@ -274,7 +275,9 @@ __global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a)
     };
     load_batch(0);
     if (tid < 64) {
-        if (cand == 0) {
+        if (cand == 0 && a.start_p) {
+            if (tid < 7) seed[tid] = a.start_p[tid];
+        } else if (cand == 0) {
             if (tid == 0) {
                 seed[6] = a.have_prev ? 1.0 : 0.0;
                 if (a.have_prev) {
@@ -596,6 +599,226 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// All-pixel start (pose_start = 1): every candidate -- the previous pose, then
+// each valid sample in (group, root) order -- is scored by sum_j W_t^j ell_t^j
+// over every pixel with M_t = T_c o M_{t-1} (a missing item counts log 1/2);
+// the first maximum starts the mean-shift.  The flow lookup at pi_{t-1}(theta)
+// and the terms that depend only on the observed flow do not depend on the
+// candidate: they are computed once per pixel and block, and the candidate
+// loop is arithmetic only.
+// ---------------------------------------------------------------------------
+constexpr int kCandChunk = 64;     // candidates per scoring workgroup
+constexpr float kLogHalfF = -0.69314718055994531f;
+constexpr int kCandThreads = 256;
+constexpr int kCandPix = 4;        // pixels per thread per pass
+
+struct CandFrameArgs {
+    const double *samples;   // SoA [7][ns] block-compacted
+    const int *bcnt;         // [nb][2]
+    const double *prev;      // previous relative pose T_t (if have_prev)
+    const double *Mprev;     // M_{t-1}
+    float *cF;               // [n][12] FP32 frames (R - I, t) of M_t = T_c o M_{t-1}
+    int *cslot;              // [n] sample slot; -1 previous pose; -2 no candidate
+    int *cn;                 // candidates 1 + valid samples
+    const int *status;
+    int nb, ns, have_prev;
+};
+
+// block 0: the previous pose and the count; block b + 1: the samples of
+// sample block b at dense indices 1 + (samples of blocks before b) + lane
+__global__ void __launch_bounds__(64) k_cand_frames(CandFrameArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    const int lane = threadIdx.x;
+    const int b = (int)blockIdx.x - 1;
+    int pre = 0;
+    for (int q = lane; q < (b < 0 ? a.nb : b); q += 64) pre += a.bcnt[2 * q];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    double T[12];
+    int dense = -1, slot = -2;
+    if (b < 0) {
+        if (lane == 0) {
+            *a.cn = 1 + pre;
+            dense = 0;
+            slot = a.have_prev ? -1 : -2;
+            for (int k = 0; k < 12; ++k) T[k] = a.have_prev ? a.prev[k] : ((k == 0 || k == 4 || k == 8) ? 1.0 : 0.0);
+        }
+    } else if (lane < a.bcnt[2 * b]) {
+        slot = kSlotsPerBlk * b + lane;
+        dense = 1 + pre + lane;
+        double pv[6];
+        for (int c = 0; c < 6; ++c) pv[c] = a.samples[(size_t)c * a.ns + slot];
+        se3_exp(pv, T, T + 9);
+    }
+    if (dense < 0) return;
+    double Mt[12];
+    pose_mul(T, a.Mprev, Mt);
+    float *f = a.cF + (size_t)12 * dense;
+    for (int i = 0; i < 9; ++i) f[i] = (float)(Mt[i] - ((i == 0 || i == 4 || i == 8) ? 1.0 : 0.0));
+    for (int i = 0; i < 3; ++i) f[9 + i] = (float)Mt[9 + i];
+    a.cslot[dense] = slot;
+}
+
+struct CandScoreArgs {
+    const float *theta;
+    const float *rig;        // W_t of frame t (or NULL: 1)
+    const float2 *flows;
+    const double *Mprev;     // M_{t-1}
+    const float *cF;
+    const int *cslot;
+    const int *cn;
+    float *part;             // [candidate][kCandTiles] partial scores
+    const int *status;
+    EmisParams e;
+    int T, H, W, t;
+};
+
+// grid (kCandTiles pixel ranges, candidate chunks of kCandChunk)
+__global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
+{
+    if (a.status && *a.status != kStatusOk) return;
+    const int n = *a.cn;
+    const int c0 = blockIdx.y * kCandChunk;
+    if (c0 >= n) return;
+    __shared__ FrameF hf[kCandChunk];
+    __shared__ int hv[kCandChunk];
+    __shared__ FrameF pf;
+    __shared__ float ws[kCandThreads / 64][kCandChunk];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = min(kCandChunk, n - c0);
+    for (int i = tid; i < m * 12; i += kCandThreads) (&hf[0].D[0])[i] = a.cF[(size_t)12 * c0 + i];
+    if (tid < kCandChunk) hv[tid] = tid < m && a.cslot[c0 + tid] != -2;
+    for (int i = tid; i < (kCandThreads / 64) * kCandChunk; i += kCandThreads) (&ws[0][0])[i] = 0.0f;
+    if (tid == 0) {
+        for (int i = 0; i < 9; ++i) pf.D[i] = (float)(a.Mprev[i] - ((i == 0 || i == 4 || i == 8) ? 1.0 : 0.0));
+        for (int i = 0; i < 3; ++i) pf.t[i] = (float)a.Mprev[9 + i];
+    }
+    __syncthreads();
+    const EmisParams &e = a.e;
+    const int64_t HW = (int64_t)a.H * a.W;
+    const int64_t j0 = HW * blockIdx.x / kCandTiles, j1 = HW * (blockIdx.x + 1) / kCandTiles;
+    const float2 *X = a.flows + (size_t)(a.t - 1) * HW;
+    for (int64_t pb = j0; pb < j1; pb += kCandThreads * kCandPix) {
+        // the pixels' candidate-free terms
+        float xh[kCandPix], yh[kCandPix], th[kCandPix], w[kCandPix], dx0[kCandPix], dy0[kCandPix];
+        float vu[kCandPix], vv[kCandPix], la[kCandPix], beta[kCandPix], k0[kCandPix];
+        bool ok[kCandPix];
+#pragma unroll
+        for (int k = 0; k < kCandPix; ++k) {
+            const int64_t j = pb + tid + (int64_t)k * kCandThreads;
+            const bool in = j < j1;
+            const int jj = in ? (int)j : 0;
+            const int y = jj / a.W, x = jj - y * a.W;
+            xh[k] = ((float)x - e.cx) * e.ifx;
+            yh[k] = ((float)y - e.cy) * e.ify;
+            th[k] = a.theta[jj];
+            w[k] = in ? (a.rig ? a.rig[(size_t)(a.t - 1) * HW + jj] : 1.0f) : 0.0f;
+            dx0[k] = 0.0f;
+            dy0[k] = 0.0f;
+            bool v = in && th[k] > 0.0f;
+            if (a.t > 1) v = v && displacement(pf, xh[k], yh[k], th[k], e.fx, e.fy, dx0[k], dy0[k]);
+            float fu = 0.0f, fv = 0.0f;
+            v = v && sample_flow(X, a.H, a.W, (float)x + dx0[k], (float)y + dy0[k], fu, fv);
+            ok[k] = v;
+            vu[k] = fu;
+            vv[k] = fv;
+            const float vn2 = fmaf(fu, fu, fv * fv);
+            const float vn = __builtin_amdgcn_sqrtf(vn2);
+            la[k] = fmaf(e.a2, vn, e.log_a1);
+            beta[k] = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+            const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+            // d = log(mu/rho) = k0 - (beta - 1) log x + 2 softplus(beta (log x - log alpha))
+            k0[k] = (beta[k] - 1.0f) * lm - 2.0f * softplus(beta[k] * (lm - la[k]));
+        }
+        for (int h0 = 0; h0 < kCandChunk; h0 += 8) {
+            float acc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                acc[u] = 0.0f;
+                if (!hv[h0 + u]) continue;
+                const FrameF f = hf[h0 + u];
+#pragma unroll
+                for (int k = 0; k < kCandPix; ++k) {
+                    float ell = kLogHalfF;
+                    float dx1, dy1;
+                    if (ok[k] && displacement(f, xh[k], yh[k], th[k], e.fx, e.fy, dx1, dy1)) {
+                        const float rx = (dx1 - dx0[k]) - vu[k], ry = (dy1 - dy0[k]) - vv[k];
+                        const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
+                        const float lx = fast_log(x2);
+                        const float d = k0[k] - (beta[k] - 1.0f) * lx + 2.0f * softplus(beta[k] * (lx - la[k]));
+                        ell = emis_from_d(d).ell;
+                    }
+                    acc[u] = fmaf(w[k], ell, acc[u]);
+                }
+            }
+            // lanes 8u .. 8u + 7 get the wave total of candidate h0 + u
+            const float tot = wave_sum8_t(acc, lane);
+            if ((lane & 7) == 0) ws[wv][h0 + (lane >> 3)] += tot;
+        }
+    }
+    __syncthreads();
+    if (tid < m) {
+        float sum = 0.0f;
+        for (int q = 0; q < kCandThreads / 64; ++q) sum += ws[q][tid];
+        a.part[(size_t)(c0 + tid) * kCandTiles + blockIdx.x] = sum;
+    }
+}
+
+// one wave per candidate: FP64 total of its tile partials in a fixed order
+__global__ void __launch_bounds__(256) k_cand_sum(const float *part, const int *cslot, const int *cn,
+                                                  double *score, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= *cn) return;
+    double s = 0.0;
+    for (int q = lane; q < kCandTiles; q += 64) s += (double)part[(size_t)c * kCandTiles + q];
+    s = wave_sum_d(s);
+    if (lane == 0) score[c] = cslot[c] == -2 ? -INFINITY : s;
+}
+
+// first maximum over the candidates -> the start's se(3) point (p (6), valid)
+__global__ void __launch_bounds__(1024) k_cand_pick(const double *score, const int *cslot, const int *cn,
+                                                    const double *samples, int ns, const double *prev,
+                                                    double *start_p, const int *status)
+{
+    if (status && *status != kStatusOk) return;
+    __shared__ double bs[16];
+    __shared__ int bi[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = *cn;
+    double best = -INFINITY;
+    int idx = 1 << 30;
+    for (int c = tid; c < n; c += 1024) {
+        const double v = score[c];
+        if (v > best) { best = v; idx = c; }   // ascending c: the first maximum stays
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double so = __shfl_xor(best, o, 64);
+        const int io = __shfl_xor(idx, o, 64);
+        if (so > best || (so == best && io < idx)) { best = so; idx = io; }
+    }
+    if (lane == 0) { bs[wv] = best; bi[wv] = idx; }
+    __syncthreads();
+    if (tid == 0) {
+        best = bs[0];
+        idx = bi[0];
+        for (int q = 1; q < 16; ++q)
+            if (bs[q] > best || (bs[q] == best && bi[q] < idx)) { best = bs[q]; idx = bi[q]; }
+        const bool ok = idx < n && best > -INFINITY;
+        start_p[6] = ok ? 1.0 : 0.0;
+        if (ok) {
+            const int sl = cslot[idx];
+            if (sl == -1) {
+                se3_log(prev, prev + 9, start_p);
+            } else {
+                for (int c = 0; c < 6; ++c) start_p[c] = samples[(size_t)c * ns + sl];
+            }
+        }
+    }
+}
+
 // scale gauge |t_1| = 1: translations, depth range, cumulative poses (the
 // depth map is rescaled by the rigidness pass that precedes this kernel)
 __global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, const int *status)
@@ -624,8 +847,8 @@ __global__ void k_cumulative(const double *rel, double *Mcum, int T)
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
-                     const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
-                     double *rel_poses, hipStream_t s)
+                     const WinDims &d, const EmisParams &e, const PoseParams &pp, int t, int it,
+                     int have_prev, double *rel_poses, hipStream_t s)
 {
     const int nb = (pp.S + kGrpPerBlk - 1) / kGrpPerBlk;
     const int ns = kSlotsPerBlk * nb;
@@ -650,19 +873,59 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.ns = ns;
     g.seed = pp.seed;
     hipLaunchKernelGGL(k_pose_groups, dim3(nb), dim3(64), 0, s, g);
+    const bool allpix = pp.pose_start == 1;
+    if (allpix) {
+        CandFrameArgs cf;
+        cf.samples = c->samples;
+        cf.bcnt = c->bcnt;
+        cf.prev = rel_poses + 12 * (t - 1);
+        cf.Mprev = c->Mcum + 12 * (t - 1);
+        cf.cF = c->cand_F;
+        cf.cslot = c->cand_slot;
+        cf.cn = c->cand_n;
+        cf.status = c->status;
+        cf.nb = nb;
+        cf.ns = ns;
+        cf.have_prev = have_prev;
+        hipLaunchKernelGGL(k_cand_frames, dim3(nb + 1), dim3(64), 0, s, cf);
+        CandScoreArgs cs;
+        cs.theta = theta;
+        cs.rig = d.use_w ? rig : nullptr;
+        cs.flows = flows;
+        cs.Mprev = c->Mcum + 12 * (t - 1);
+        cs.cF = c->cand_F;
+        cs.cslot = c->cand_slot;
+        cs.cn = c->cand_n;
+        cs.part = c->cand_part;
+        cs.status = c->status;
+        cs.e = e;
+        cs.T = d.T;
+        cs.H = d.H;
+        cs.W = d.W;
+        cs.t = t;
+        const int ncand = 1 + ns;   // upper bound; chunks past the count exit
+        hipLaunchKernelGGL(k_cand_score, dim3(kCandTiles, (ncand + kCandChunk - 1) / kCandChunk), dim3(kCandThreads),
+                           0, s, cs);
+        hipLaunchKernelGGL(k_cand_sum, dim3((ncand + 3) / 4), dim3(256), 0, s, c->cand_part, c->cand_slot,
+                           c->cand_n, c->cand_score, c->status);
+        hipLaunchKernelGGL(k_cand_pick, dim3(1), dim3(1024), 0, s, c->cand_score, c->cand_slot, c->cand_n,
+                           c->samples, ns, rel_poses + 12 * (t - 1), c->cand_start, c->status);
+    }
     SeedArgs sa;
     sa.samples = c->samples;
     sa.bcnt = c->bcnt;
     sa.seed_score = c->seed_score;
     sa.seed_part = c->seed_part;
     sa.prev = rel_poses + 12 * (t - 1);
+    sa.start_p = allpix ? c->cand_start : nullptr;
     sa.status = c->status;
     sa.ns = ns;
     sa.nb = nb;
     sa.have_prev = have_prev;
     sa.is2t = 1.0 / pp.s2t;
     sa.is2r = 1.0 / pp.s2r;
-    hipLaunchKernelGGL(k_pose_seed, dim3((pp.n_seeds + 1) * kSeedParts), dim3(kSeedThreads), 0, s, sa);
+    const int n_seeds = allpix ? 0 : pp.n_seeds;
+    hipLaunchKernelGGL(k_pose_seed, dim3((n_seeds + 1) * kSeedParts), dim3(kSeedThreads), 0, s, sa);
     MsArgs m;
     m.sampf = c->sampf;
     m.bcnt = c->bcnt;
@@ -675,7 +938,7 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     m.status = c->status;
     m.ns = ns;
     m.nb = nb;
-    m.n_seeds = pp.n_seeds;
+    m.n_seeds = n_seeds;
     m.t = t;
     m.max_iters = pp.ms_max_iters;
     m.fallback_prev_frame = (!have_prev && t >= 2) ? 1 : 0;

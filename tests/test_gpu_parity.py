@@ -165,6 +165,68 @@ def test_pose_step_many_groups(vo, torch):
         assert np.abs(Tg[9:] - To[9:]).max() < 1e-5
 
 
+def _dense_rank(valid):
+    r = np.cumsum(valid) - 1
+    return np.where(valid, r, -1)
+
+
+def test_pose_step_allpixel_start(vo, torch):
+    # pose_start = 1: every candidate scored by sum_j W_t^j ell_t^j over all
+    # pixels; scores matched by (group, root) slot (a boundary root may be
+    # accepted on one side only), the chosen start, and the pose from it
+    T, H, W = 3, 40, 56
+    w, rel, M, gt = _world(33, T, H, W)
+    theta = gt.astype(np.float32)
+    rig = np.random.default_rng(6).uniform(0.1, 1.0, (T, H, W)).astype(np.float32)
+    S, t = 96, 2
+    s = vo.Solver(T, H, W, S)
+    p = vo.default_params(n_pose_groups=S, seed=3, pose_start=1)
+    Tg, smp, diag = s.pose_step(torch.from_numpy(theta).cuda(), torch.from_numpy(rig).cuda(),
+                                torch.from_numpy(w["flows"]).cuda(), w["K"], p, M, t, 1, prevT=rel[t - 1],
+                                want_samples=True)
+    gsc = s.pose_scores()
+    op = oracle.params(n_pose_groups=S, seed=3, pose_start=1)
+    osc, To = oracle.pose_scores(theta.astype(np.float64), rig.astype(np.float64), w["flows"], w["K"], op, M, t, 1,
+                                 prevT=rel[t - 1])
+    _, osmp, odiag = oracle.pose_step(theta.astype(np.float64), rig.astype(np.float64), w["flows"], w["K"], op, M,
+                                      t, 1, prevT=rel[t - 1], want_samples=True)
+    smp = smp.cpu().numpy()
+    gv, ov = smp[:, 7] > 0, osmp[:, 7] > 0
+    assert len(gsc) == 1 + gv.sum() and len(osc) == 1 + ov.sum()
+    both = gv & ov
+    gs = np.concatenate([[gsc[0]], gsc[1 + _dense_rank(gv)[both]]])
+    os_ = np.concatenate([[osc[0]], osc[1 + _dense_rank(ov)[both]]])
+    rel_err = np.abs(gs - os_) / np.abs(os_)
+    print("scores", len(gs), "median", np.median(rel_err), "max", rel_err.max(), "diag", diag, odiag)
+    assert np.median(rel_err) < 1e-6 and rel_err.max() < 1e-3
+    # the GPU's start is the oracle's best or within a near tie of it
+    g_best, o_best = int(np.argmax(gsc)), int(np.argmax(osc))
+    g_best_slot = -1 if g_best == 0 else np.flatnonzero(gv)[g_best - 1]
+    o_best_slot = -1 if o_best == 0 else np.flatnonzero(ov)[o_best - 1]
+    print("best", g_best_slot, o_best_slot, gsc[g_best], osc[o_best])
+    if g_best_slot != o_best_slot:
+        o_of_g = osc[0] if g_best_slot == -1 else osc[1 + _dense_rank(ov)[g_best_slot]]
+        assert osc[o_best] - o_of_g <= 1e-4 * abs(osc[o_best])
+    else:
+        assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-6
+        assert np.abs(Tg[9:] - To[9:]).max() < 1e-5
+
+
+def test_window_parity_allpixel_start(vo, torch):
+    # whole window with the all-pixel start: the window tolerances, or twice
+    # the oracle's own response to 1e-5 px of flow noise where larger
+    T, H, W = 3, 48, 64
+    w = synthflow.make_window("small", 9, T=T, H=H, W=W)
+    kw = dict(n_iters=2, n_pose_groups=48, pose_start=1)
+    r = _window_compare(vo, torch, w, kw, T, H, W, 64)
+    sens = [_oracle_sensitivity(w, kw, seed=k) for k in range(2)]
+    print(r, sens)
+    assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
+    assert r["depth_med"] <= 1e-3
+    assert r["rig_p99"] <= max(1e-4, 2 * max(x["rig_p99"] for x in sens))
+    assert r["ll"] <= max(1e-5, 2 * max(x["ll"] for x in sens))
+
+
 def test_bootstrap_parity(vo, torch):
     w = synthflow.make_window("small", 41, T=2, H=72, W=100)
     s = vo.Solver(2, 72, 100, 256)
@@ -199,7 +261,7 @@ def test_invalid_arguments(vo, torch):
     assert s.window_status(big, (40.0, 40.0, 16.0, 16.0), vo.default_params()) == -1
     assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(gamma=0.3)) == -1
     assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(criterion=2)) == -1
-    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(reserved=1)) == -1
+    assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(pose_start=2)) == -1
 
 
 def _window_compare(vo, torch, w, kw, T, H, W, S):
