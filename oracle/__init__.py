@@ -87,6 +87,8 @@ def lib():
             "or_pose_step_scores": (C.c_int, [d, d, f, i, i, i, d, P, d, i, i, d, d, d, C.POINTER(C.c_int)]),
             "or_bootstrap": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
             "or_window": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d]),
+            "or_window_seeded": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d, d]),
+            "or_bootstrap_seeded": (C.c_int, [f, i, i, i, d, P, d, d, d, d]),
             "or_window_init": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d, d, d, C.POINTER(C.c_int)]),
             "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
             "or_null_vector_8x9": (None, [d, d]),
@@ -332,6 +334,80 @@ def window(flows, K, p):
     st = lib().or_window(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(poses),
                          _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag))
     return st, poses, depth, rig, (ll[0], ll[1]), diag
+
+
+def window_seeded(flows, K, p, T1):
+    """One window whose T_1 is given (12 values, R row-major then t); returns
+    (status, poses, depth, rigidness, loglik, diag) like window()."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    poses = np.zeros((T, 12))
+    depth = np.zeros((H, W))
+    rig = np.zeros((T, H, W))
+    ll = np.zeros(2)
+    diag = np.zeros(8)
+    st = lib().or_window_seeded(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(_d(T1)),
+                                _ptr(poses), _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag))
+    return st, poses, depth, rig, ll, diag
+
+
+def bootstrap_seeded(flows, K, p, T1):
+    """The bootstrap with T_1 given: (status, relT [12], theta [H][W], range [2])."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    rel = np.zeros(12)
+    th = np.zeros((H, W))
+    rng = np.zeros(2)
+    st = lib().or_bootstrap_seeded(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), _ptr(_d(T1)),
+                                   _ptr(rel), _ptr(th), _ptr(rng))
+    return st, rel, th, rng
+
+
+def window_starts(N, T, stride):
+    """First frames of the windows over N flows: 0, stride, 2 stride, ... and a
+    last window ending at flow N."""
+    s, out = 0, [0]
+    while s + T < N:
+        s = min(s + stride, N - T)
+        out.append(s)
+    return out
+
+
+def vo_sequence(flows, K, p, T, stride):
+    """Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.4): windows
+    of T flows start every `stride` frames; the first is bootstrapped from X_1,
+    every later one takes T_1 from the previous window's estimate of the same
+    frame pair.  Each window fixes its own scale by |t_1| = 1; the trajectory
+    chains them: the scale of window i relative to window i - 1 is the length,
+    in window i - 1's units, of the translation that window i normalised.
+    Relative pose of frame pair (k, k + 1) comes from the latest window that
+    starts at or before frame k.  Returns (status, M [N + 1][12] camera poses
+    x_k = M_k x_0 in window 0's scale, per-window poses)."""
+    flows = _flows(flows)
+    N = flows.shape[0]
+    starts = window_starts(N, T, stride)
+    wposes = []
+    for i, s in enumerate(starts):
+        fl = flows[s:s + T]
+        if i == 0:
+            st, poses, *_ = window(fl, K, p)
+        else:
+            prev = wposes[-1]
+            st, poses, *_ = window_seeded(fl, K, p, prev[s - starts[i - 1]])
+        if st != 0:
+            return st, None, wposes
+        wposes.append(poses)
+    scale = [1.0]
+    for i in range(1, len(starts)):
+        scale.append(scale[-1] * np.linalg.norm(wposes[i - 1][starts[i] - starts[i - 1]][9:]))
+    M = [np.concatenate([np.eye(3).ravel(), np.zeros(3)])]
+    for k in range(N):
+        i = max(j for j, s in enumerate(starts) if s <= k)
+        r = wposes[i][k - starts[i]]
+        R, t = r[:9].reshape(3, 3), r[9:] * scale[i]
+        Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
+        M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
+    return 0, np.array(M), wposes
 
 
 def window_init(flows, K, p, init_depth, init_rig):

@@ -1198,6 +1198,9 @@ static double triangulate(const double *R, const double *t, double xn, double yn
 
 /* relT_out [12]; theta_out [H][W]; range_out [2] = d_lo, d_hi;
  * info_out optional [4]: best hypothesis, its median, valid pixels, cheirality count */
+static int depth_from_T1(const float *X1, int H, int W, const double *K, const or_params *p,
+                         const double *R1, const double *t1, double *theta_out, double *range_out, double *nv_out);
+
 int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const or_params *p,
                  double *relT_out, double *theta_out, double *range_out, double *info_out)
 {
@@ -1306,6 +1309,22 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
     for (int k = 0; k < 3; ++k) t1[k] /= tn;
     memcpy(relT_out, R1, sizeof R1);
     memcpy(relT_out + 9, t1, sizeof t1);
+    double nvd = 0;
+    const int st = depth_from_T1(X1, H, W, K, p, R1, t1, theta_out, range_out, &nvd);
+    if (info_out) { info_out[0] = best_h; info_out[1] = best_score; info_out[2] = nvd; info_out[3] = best_cnt; }
+    free(ev); free(res);
+    return st;
+}
+
+/* Depth of frame 0 by two-view triangulation from T_1 = (R1, t1) and X_1
+ * (Table 1, third row): every pixel with a present flow; the sampling range
+ * [d_lo, d_hi] = [P1 / 2, 2 P99] of the valid depths (unless fixed by p);
+ * invalid pixels take the median, and all depths are clamped to the range. */
+static int depth_from_T1(const float *X1, int H, int W, const double *K, const or_params *p,
+                         const double *R1, const double *t1, double *theta_out, double *range_out, double *nv_out)
+{
+    int64_t HW = (int64_t)H * W;
+    double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
     /* triangulation of every pixel; percentiles of the valid depths */
     double *vals = (double *)malloc(sizeof(double) * HW);
     uint8_t *val = (uint8_t *)malloc(HW);
@@ -1320,7 +1339,8 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
         theta_out[j] = th;
         if (ok) vals[nv++] = th;
     }
-    if (nv == 0) { free(ev); free(res); free(vals); free(val); return OR_EDEGENERATE; }
+    *nv_out = (double)nv;
+    if (nv == 0) { free(vals); free(val); return OR_EDEGENERATE; }
     qsort(vals, nv, sizeof(double), cmp_double);
     double P1 = vals[(int64_t)floor(0.01 * (nv - 1))], P50 = vals[(int64_t)floor(0.50 * (nv - 1))],
            P99 = vals[(int64_t)floor(0.99 * (nv - 1))];
@@ -1334,9 +1354,28 @@ int or_bootstrap(const float *flows, int T, int H, int W, const double *K, const
     }
     range_out[0] = d_lo;
     range_out[1] = d_hi;
-    if (info_out) { info_out[0] = best_h; info_out[1] = best_score; info_out[2] = (double)nv; info_out[3] = best_cnt; }
-    free(ev); free(res); free(vals); free(val);
+    free(vals); free(val);
     return OR_OK;
+}
+
+/* The bootstrap with T_1 given instead of estimated: the paper's alternative
+ * for overlapping consecutive batches (Sec. 5.4), T_1 from the previous
+ * window's estimate.  Its translation is rescaled to unit length (the gauge);
+ * the depth follows by triangulation as above.  A zero translation is
+ * degenerate. */
+int or_bootstrap_seeded(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+                        const double *T1, double *relT_out, double *theta_out, double *range_out)
+{
+    (void)T;
+    const double tn = norm3(T1 + 9);
+    if (!(tn > 0) || !isfinite(tn)) return OR_EDEGENERATE;
+    double R1[9], t1[3];
+    memcpy(R1, T1, sizeof R1);
+    for (int k = 0; k < 3; ++k) t1[k] = T1[9 + k] / tn;
+    memcpy(relT_out, R1, sizeof R1);
+    memcpy(relT_out + 9, t1, sizeof t1);
+    double nv = 0;
+    return depth_from_T1(flows, H, W, K, p, R1, t1, theta_out, range_out, &nv);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1408,7 +1447,7 @@ static void pose_pass(const float *flows, int T, int H, int W, const double *K, 
 static int window_core(const float *flows, int T, int H, int W, const double *K, const or_params *p,
                        const double *init_depth, const double *init_rig, double *poses_out,
                        double *depth_out, double *rig_out, double *loglik_out, double *diag_out,
-                       int *choice_out)
+                       int *choice_out, const double *T1_seed)
 {
     if (!flows || !K || !p || !poses_out || !depth_out || !rig_out) return OR_EINVAL;
     if (!params_ok(p, T, H, W, K)) return OR_EINVAL;
@@ -1417,7 +1456,13 @@ static int window_core(const float *flows, int T, int H, int W, const double *K,
     double *rel = poses_out;
     double *M = (double *)malloc(sizeof(double) * 12 * (T + 1));
     double range[2], binfo[4];
-    int st = or_bootstrap(flows, T, H, W, K, p, rel, depth_out, range, binfo);
+    int st;
+    if (T1_seed) {
+        st = or_bootstrap_seeded(flows, T, H, W, K, p, T1_seed, rel, depth_out, range);
+        binfo[0] = -1; binfo[1] = 0; binfo[2] = 0; binfo[3] = 0;
+    } else {
+        st = or_bootstrap(flows, T, H, W, K, p, rel, depth_out, range, binfo);
+    }
     if (st != OR_OK) { free(M); return st; }
     for (int t = 2; t <= T; ++t) pose_identity(rel + 12 * (t - 1));
     int have_w = 0; /* W == 1 until the first unsmoothed update */
@@ -1502,7 +1547,17 @@ int or_window(const float *flows, int T, int H, int W, const double *K, const or
               double *diag_out)
 {
     return window_core(flows, T, H, W, K, p, NULL, NULL, poses_out, depth_out, rig_out, loglik_out,
-                       diag_out, NULL);
+                       diag_out, NULL, NULL);
+}
+
+/* One window whose T_1 is given (overlapping consecutive batches, Sec. 5.4). */
+int or_window_seeded(const float *flows, int T, int H, int W, const double *K, const or_params *p,
+                     const double *T1, double *poses_out, double *depth_out, double *rig_out,
+                     double *loglik_out, double *diag_out)
+{
+    if (!T1) return OR_EINVAL;
+    return window_core(flows, T, H, W, K, p, NULL, NULL, poses_out, depth_out, rig_out, loglik_out,
+                       diag_out, NULL, T1);
 }
 
 /* The window from a proposed initial state (depth [H][W] > 0, rigidness
@@ -1514,5 +1569,5 @@ int or_window_init(const float *flows, int T, int H, int W, const double *K, con
 {
     if (!init_depth || !init_rig) return OR_EINVAL;
     return window_core(flows, T, H, W, K, p, init_depth, init_rig, poses_out, depth_out, rig_out,
-                       loglik_out, diag_out, choice_out);
+                       loglik_out, diag_out, choice_out, NULL);
 }

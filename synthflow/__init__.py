@@ -245,7 +245,8 @@ def _fisk_noise(rng, flow, c1, c0, beta):
     return np.stack([e * np.cos(ang), e * np.sin(ang)], axis=-1)
 
 
-def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None, keep_focal=False):
+def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None, keep_focal=False,
+                speed_range=None):
     """Generate one window.
 
     Returns a dict with
@@ -255,6 +256,9 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
       depth     float64 [H,W] ground-truth z-depth of frame 0
       outlier   bool [T,H,W] independently-moving pixels on frame t-1's grid
       spec      the WindowSpec used (with T/H/W overrides applied)
+    speed_range (lo, hi): each frame's translation is scaled by a factor drawn
+    uniformly from [lo, hi] by a generator of its own (the default draws
+    nothing and leaves every other stream unchanged).
     """
     if isinstance(spec, str):
         spec = SPECS[spec]
@@ -290,6 +294,9 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
             R = rot_axis_angle(_unit_sphere(rng), math.radians(rng.uniform(0.0, spec.rot_deg)))
             t = spec.trans * _unit_sphere(rng)
         poses.append((R, t))
+    if speed_range is not None:
+        srng = np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0x5BEED000)))
+        poses = [(R, t * srng.uniform(*speed_range)) for R, t in poses]
     Ms = _cumulative(poses)
 
     xs, ys, rays = _rays(spec, Hn, Wn)

@@ -614,6 +614,55 @@ def test_window_noise_free_recovery_mle():
     assert np.median(rig) > 0.99
 
 
+def test_bootstrap_seeded_matches_bootstrap_and_truth():
+    # given the LMedS T_1, the seeded bootstrap is the bootstrap; given the true
+    # T_1 (any scale) on noise-free flow, the depth is the truth in the unit gauge
+    w = synthflow.make_window("small", 4, noise=False, outliers=False, T=2, H=48, W=64)
+    p = oracle.params()
+    st, rel, th, rng, info = oracle.bootstrap(w["flows"], w["K"], p)
+    st2, rel2, th2, rng2 = oracle.bootstrap_seeded(w["flows"], w["K"], p, rel * np.r_[np.ones(9), 3.0 * np.ones(3)])
+    assert st == st2 == 0
+    assert np.allclose(rel2, rel, atol=1e-15) and np.allclose(th2, th, rtol=1e-13) and np.allclose(rng2, rng)
+    R, t = w["poses"][0]
+    st3, rel3, th3, _ = oracle.bootstrap_seeded(w["flows"], w["K"], p, np.concatenate([R.ravel(), 7.0 * t]))
+    assert st3 == 0 and np.allclose(rel3[9:], t / np.linalg.norm(t), atol=1e-15)
+    ok = (th3 > rng2[0] * 1.0001) & (th3 < rng2[1] * 0.9999)
+    rel_err = np.abs(th3 * np.linalg.norm(t) - w["depth"]) / w["depth"]
+    assert np.median(rel_err[ok]) < 1e-4
+    assert oracle.bootstrap_seeded(w["flows"], w["K"], p, np.r_[R.ravel(), 0, 0, 0])[0] == -4
+
+
+def test_window_starts():
+    assert oracle.window_starts(12, 5, 1) == [0, 1, 2, 3, 4, 5, 6, 7]
+    assert oracle.window_starts(12, 5, 3) == [0, 3, 6, 7]
+    assert oracle.window_starts(5, 5, 2) == [0]
+    assert oracle.window_starts(9, 4, 5) == [0, 5]
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_vo_sequence_noise_free_trajectory(stride):
+    # noise-free flows over a 9-frame sequence whose per-frame speed varies by
+    # 3x, so that every window has its own scale: each step of the chained
+    # trajectory is the true relative pose in the first window's scale.  The
+    # bounds are a few times the single-window noise-free limits (float32
+    # flows, bilinear lookup, 96x128 pixels), since each window inherits the
+    # previous one's T_1; dropping or inverting the chaining factor moves the
+    # steps' lengths by tens of percent
+    N, T = 9, 4
+    w = synthflow.make_window("small", 5, noise=False, outliers=False, T=N, H=96, W=128, speed_range=(0.5, 1.5))
+    p = oracle.params(n_iters=2, n_pose_groups=128)
+    st, M, wp = oracle.vo_sequence(w["flows"], w["K"], p, T, stride)
+    assert st == 0 and M.shape == (N + 1, 12)
+    scale = np.linalg.norm(w["poses"][0][1])
+    for k in range(N):
+        Ra = M[k + 1][:9].reshape(3, 3) @ M[k][:9].reshape(3, 3).T
+        ta = M[k + 1][9:] - Ra @ M[k][9:]
+        Rg, tg = w["poses"][k][0], w["poses"][k][1] / scale
+        ang = math.acos(max(-1.0, min(1.0, (np.trace(Ra @ Rg.T) - 1) / 2)))
+        assert ang < 6e-3, (k, ang)
+        assert np.linalg.norm(ta - tg) < 0.1 * np.linalg.norm(tg), (k, ta, tg)
+
+
 def test_window_outliers_flagged():
     w = synthflow.make_window("small", 0, noise=True, outliers=True)
     st, poses, depth, rig, ll, diag = oracle.window(w["flows"], w["K"], oracle.params(n_iters=3))
