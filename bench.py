@@ -243,6 +243,126 @@ def _he_params(T, seed):
     return np.concatenate(out)
 
 
+def _vo_starts(N, T, stride):
+    s, out = 0, [0]
+    while s + T < N:
+        s = min(s + stride, N - T)
+        out.append(s)
+    return out
+
+
+def _vo_chain(wposes, starts, N):
+    """Trajectory from per-window relative poses, each window in its own gauge:
+    window i's scale relative to window i - 1 is the length, in window i - 1's
+    units, of the frame pair window i starts with."""
+    import numpy as np
+    scale = [1.0]
+    for i in range(1, len(starts)):
+        scale.append(scale[-1] * np.linalg.norm(wposes[i - 1][starts[i] - starts[i - 1]][9:]))
+    M = [np.concatenate([np.eye(3).ravel(), np.zeros(3)])]
+    for k in range(N):
+        i = max(j for j, st in enumerate(starts) if st <= k)
+        r = wposes[i][k - starts[i]]
+        R, t = r[:9].reshape(3, 3), r[9:] * scale[i]
+        Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
+        M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
+    return np.array(M)
+
+
+def _trajectory_error(M, gt_rel):
+    """Mean rotation error (rad) of the camera poses, and the RMS camera-centre
+    error after the least-squares scale, relative to the mean distance travelled."""
+    import numpy as np
+    G = [np.eye(4)]
+    for R, t in gt_rel:
+        A = np.eye(4)
+        A[:3, :3], A[:3, 3] = R, t
+        G.append(A @ G[-1])
+    rot, ce, cg = [], [], []
+    for k in range(1, len(M)):
+        Re, te = M[k][:9].reshape(3, 3), M[k][9:]
+        Rg, tg = G[k][:3, :3], G[k][:3, 3]
+        D = Re @ Rg.T
+        rot.append(float(np.arccos(np.clip((np.trace(D) - 1) / 2, -1, 1))))
+        ce.append(-Re.T @ te)
+        cg.append(-Rg.T @ tg)
+    ce, cg = np.array(ce), np.array(cg)
+    s = float((ce * cg).sum() / (ce * ce).sum())
+    ate = float(np.sqrt(((s * ce - cg) ** 2).sum(axis=1).mean()) / np.linalg.norm(cg, axis=1).mean())
+    return float(np.mean(rot)), ate
+
+
+def run_vo(args):
+    """Sliding-window VO over an indoor-shaped sequence (640x480, windows of T=6,
+    per-frame speed varying in [0.6, 1.4] x 5 cm): windows seeded from the
+    previous window's estimate on the device (voldor_vo_sequence), against the
+    same windows each bootstrapped on its own and chained the same way."""
+    import numpy as np
+    import torch
+
+    import paper_2104_06789_amd as vo
+    import synthflow
+
+    N, T, stride = args.vo_flows, 6, args.vo_stride
+    w = synthflow.make_window("indoor", args.seed, T=N, speed_range=(0.6, 1.4))
+    spec = w["spec"]
+    H, W = spec.H, spec.W
+    flows = torch.from_numpy(w["flows"]).to("cuda:0")
+    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed)
+    solver = vo.Solver(T, H, W, spec.n_groups)
+    solver.set_timing(True)
+    for _ in range(max(args.warmup, 1)):
+        traj, wposes, wst, depth, rig = solver.vo_sequence(flows, w["K"], p, T, stride)
+    torch.cuda.synchronize()
+    solver.timing_summary()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        traj, wposes, wst, depth, rig = solver.vo_sequence(flows, w["K"], p, T, stride)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    if not (wst.cpu().numpy() == 0).all():
+        print(f"vo: window statuses {wst.cpu().tolist()}", file=sys.stderr)
+        sys.exit(1)
+    phases, n_timed = solver.timing_summary()
+    starts = _vo_starts(N, T, stride)
+    rot_s, ate_s = _trajectory_error(traj.cpu().numpy(), w["poses"])
+    # the same windows, each bootstrapped from its own first flow
+    outs = []
+    status = torch.full((len(starts),), -1, dtype=torch.int32, device=flows.device)
+    for i, s0 in enumerate(starts):
+        o = (torch.empty((T, 12), dtype=torch.float64, device=flows.device),
+             torch.empty((H, W), dtype=torch.float32, device=flows.device),
+             torch.empty((T, H, W), dtype=torch.float32, device=flows.device), None)
+        solver.window_async(flows[s0:s0 + T], w["K"], p, o, status[i], want_loglik=False)
+        outs.append(o)
+    torch.cuda.synchronize()
+    plain = _vo_chain([o[0].cpu().numpy() for o in outs], starts, N)
+    rot_p, ate_p = _trajectory_error(plain, w["poses"])
+    launches = float(phases["sweep_launches"])
+    sweep_ms = float(phases["sweeps"]) / max(launches, 1.0)
+    alg_ops = 3.0 * T * H * W * EMISSION_VALU_OPS
+    achieved = alg_ops / (sweep_ms * 1e-3) / 1e12
+    line = {
+        "metric": "frames/s of sliding-window VO",
+        "value": N / (ms * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"vo: indoor-shaped sequence of {N} flows ({W}x{H}), windows of T={T} every "
+                               f"{stride} frame(s), {spec.n_iters} EM iterations, {spec.n_groups} P3P groups/frame, "
+                               f"per-frame speed x[0.6, 1.4], seed {args.seed}",
+                   "windows": len(starts), "parallelism": "single GPU, windows seeded in sequence on one stream"},
+        "seeded": {"rot_err_rad": rot_s, "ate_rel": ate_s},
+        "bootstrapped_each": {"rot_err_rad": rot_p, "ate_rel": ate_p},
+        "phase_ms": {k: float(phases[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness", "window"]},
+        "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms},
+    }
+    print(json.dumps(line))
+
+
 def run_learned(args):
     """The learned proposal: train it on windows labelled by the plain EM, then
     compare EM at LEARN_ITERS iterations from the proposal (falling back to the
@@ -419,7 +539,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned"])
+    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned", "vo"])
+    ap.add_argument("--vo-flows", type=int, default=18, help="flows of the sequence (--workload vo)")
+    ap.add_argument("--vo-stride", type=int, default=1, help="frames between window starts (--workload vo)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--criterion", default="mie", choices=["mie", "mle"],
                     help="depth M-step: maximum inlier (Eq. 10) or maximum likelihood (Eq. 9)")
@@ -448,6 +570,9 @@ def main():
         return
     if args.workload == "learned":
         run_learned(args)
+        return
+    if args.workload == "vo":
+        run_vo(args)
         return
 
     import numpy as np

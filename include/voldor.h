@@ -136,6 +136,38 @@ int voldor_window_init(voldor_ctx *ctx, const float *flows, int T, int H, int W,
                        float *depth, float *rigidness, double *loglik, int32_t *status_out, int32_t *choice_out,
                        void *stream);
 
+/* The same window with T_1 given instead of estimated: the paper's
+ * alternative for overlapping consecutive batches (Sec. 5.4), where T_1 comes
+ * from the previous window's estimate of the same frame pair.
+ *   T1  device double[12] (R row-major, t), 8-byte aligned; read when the
+ *       window's work runs, so it may be an earlier window's pose output on the
+ *       same stream.  Its translation is rescaled to unit length (the gauge);
+ *       the depth follows by two-view triangulation from T_1 and X_1.  A
+ *       non-finite pose or zero translation gives VOLDOR_EDEGENERATE.
+ * Enqueued without waiting, like voldor_window_async. */
+int voldor_window_seeded(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                         const voldor_params *p, const double *T1, double *poses, float *depth, float *rigidness,
+                         double *loglik, int32_t *status_out, void *stream);
+
+/* Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.4): windows of
+ * T flows start at frames 0, stride, 2 stride, ..., with a last one ending at
+ * flow N (voldor_vo_windows gives their count: 2 <= T <= 16, T <= N,
+ * 1 <= stride < T).  The first window is bootstrapped from X_1; every later one
+ * takes T_1 from the previous window's estimate of the same frame pair, on the
+ * device, with no host round trip.  Each window fixes its own scale (|t_1| = 1);
+ * the trajectory chains them.
+ *   flows     device float32 [N][H][W][2]
+ *   wposes    device double [windows][T][12]: every window's relative poses
+ *   depth, rigidness  device float [H][W], [T][H][W]: the last window's results
+ *   wstatus   device int32 [windows]: each window's status
+ *   traj      device double [N+1][12]: camera poses M_k (x_k = M_k x_0) in the
+ *             first window's scale; all NaN if any window failed
+ * Enqueued without waiting.  Returns VOLDOR_EINVAL for bad sizes. */
+int voldor_vo_windows(int N, int T, int stride);
+int voldor_vo_sequence(voldor_ctx *ctx, const float *flows, int N, int H, int W, const double *K,
+                       const voldor_params *p, int T, int stride, double *wposes, float *depth, float *rigidness,
+                       int32_t *wstatus, double *traj, void *stream);
+
 /* ---- batches: many windows of uneven shape and T ------------------------- */
 
 /* One window of a batch: the arguments of voldor_window for that window. */

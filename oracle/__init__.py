@@ -385,6 +385,8 @@ def vo_sequence(flows, K, p, T, stride):
     x_k = M_k x_0 in window 0's scale, per-window poses)."""
     flows = _flows(flows)
     N = flows.shape[0]
+    if not (2 <= T <= N and 1 <= stride < T):
+        raise ValueError("need 2 <= T <= N and 1 <= stride < T (the next T_1 must lie in the window)")
     starts = window_starts(N, T, stride)
     wposes = []
     for i, s in enumerate(starts):
@@ -397,17 +399,23 @@ def vo_sequence(flows, K, p, T, stride):
         if st != 0:
             return st, None, wposes
         wposes.append(poses)
+    return 0, vo_chain(wposes, starts, N), wposes
+
+
+def vo_chain(wposes, starts, N):
+    """The trajectory M [N + 1][12] of a sequence from its windows' relative
+    poses (each window in its own gauge |t_1| = 1), as in vo_sequence."""
     scale = [1.0]
     for i in range(1, len(starts)):
-        scale.append(scale[-1] * np.linalg.norm(wposes[i - 1][starts[i] - starts[i - 1]][9:]))
+        scale.append(scale[-1] * np.linalg.norm(np.asarray(wposes[i - 1])[starts[i] - starts[i - 1]][9:]))
     M = [np.concatenate([np.eye(3).ravel(), np.zeros(3)])]
     for k in range(N):
         i = max(j for j, s in enumerate(starts) if s <= k)
-        r = wposes[i][k - starts[i]]
+        r = np.asarray(wposes[i])[k - starts[i]]
         R, t = r[:9].reshape(3, 3), r[9:] * scale[i]
         Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
         M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
-    return 0, np.array(M), wposes
+    return np.array(M)
 
 
 def window_init(flows, K, p, init_depth, init_rig):

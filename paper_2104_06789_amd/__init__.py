@@ -84,6 +84,9 @@ def lib():
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
         "voldor_pose_step": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, i, i, dp, dp, vp, ip, vp]),
         "voldor_pose_scores": (i, [vp, dp, i, ip]),
+        "voldor_window_seeded": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp, vp]),
+        "voldor_vo_windows": (i, [i, i, i]),
+        "voldor_vo_sequence": (i, [vp, vp, i, i, i, dp, P, i, i, vp, vp, vp, vp, vp, vp]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
         "voldor_last_timing": (i, [vp, dp]),
@@ -315,6 +318,41 @@ class Solver:
                                     _ptr(samples), diag, _stream(stream))
         _check(rc, "voldor_pose_step")
         return Tout, samples, list(diag)
+
+    def window_seeded(self, flows, K, params, T1, out, status, stream=None, want_loglik=True):
+        """Enqueue one window whose T_1 is the CUDA float64 tensor T1 [12] (it may
+        be a view of an earlier window's poses); out and status as window_async."""
+        import torch
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        if not (isinstance(T1, torch.Tensor) and T1.is_cuda and T1.dtype == torch.float64):
+            raise TypeError("T1 must be a CUDA float64 tensor")
+        poses, depth, rig, ll = out
+        Kd, Kp = _dbl(K)
+        _check(lib().voldor_window_seeded(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(T1),
+                                          _ptr(poses), _ptr(depth), _ptr(rig), _ptr(ll) if want_loglik else None,
+                                          _ptr(status), _stream(stream)), "voldor_window_seeded")
+
+    def vo_sequence(self, flows, K, params, T, stride, stream=None):
+        """Sliding-window VO over flows [N][H][W][2] (CUDA): returns (trajectory
+        [N+1][12], per-window poses [windows][T][12], window statuses, last
+        window's depth and rigidness) as CUDA tensors, enqueued without waiting."""
+        import torch
+        flows = _flows(flows)
+        N, H, W, _ = flows.shape
+        nwin = lib().voldor_vo_windows(N, T, stride)
+        _check(nwin if nwin < 0 else 0, "voldor_vo_windows")
+        dev = flows.device
+        wposes = torch.empty((nwin, T, 12), dtype=torch.float64, device=dev)
+        traj = torch.empty((N + 1, 12), dtype=torch.float64, device=dev)
+        wstatus = torch.full((nwin,), -99, dtype=torch.int32, device=dev)
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        rig = torch.empty((T, H, W), dtype=torch.float32, device=dev)
+        Kd, Kp = _dbl(K)
+        _check(lib().voldor_vo_sequence(self._ctx, _ptr(flows), N, H, W, Kp, C.byref(params), T, stride,
+                                        _ptr(wposes), _ptr(depth), _ptr(rig), _ptr(wstatus), _ptr(traj),
+                                        _stream(stream)), "voldor_vo_sequence")
+        return traj, wposes, wstatus, depth, rig
 
     def pose_scores(self):
         """All-pixel candidate scores of the last pose step run with pose_start=1:

@@ -342,7 +342,7 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
     c->n_ev = 0;
     mark(c, s, kPhaseNone);
     int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
-                              p->depth_lo, p->depth_hi, poses, depth, s);
+                              p->depth_lo, p->depth_hi, poses, depth, s, init ? init->T1 : nullptr);
     mark(c, s, kPhaseBoot);
     const bool proposed = init && init->depth && init->rig;
     if (proposed && (!c->init_rel || !c->init_ll)) return VOLDOR_EDEVICE;
@@ -443,9 +443,101 @@ int voldor_window_init(voldor_ctx *c, const float *flows, int T, int H, int W, c
 {
     if (!status_out || ((uintptr_t)status_out & 3) != 0 || !init_depth || !init_rig) return VOLDOR_EINVAL;
     if (choice_out && ((uintptr_t)choice_out & 3) != 0) return VOLDOR_EINVAL;
-    const WindowInit in = {init_depth, init_rig, choice_out};
+    const WindowInit in = {init_depth, init_rig, choice_out, nullptr};
     return window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, status_out,
                           (hipStream_t)stream, &in);
+}
+
+int voldor_window_seeded(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                         const voldor_params *p, const double *T1, double *poses, float *depth, float *rigidness,
+                         double *loglik, int32_t *status_out, void *stream)
+{
+    if (!T1 || ((uintptr_t)T1 & 7) != 0) return VOLDOR_EINVAL;
+    if (!status_out || ((uintptr_t)status_out & 3) != 0) return VOLDOR_EINVAL;
+    const WindowInit in = {nullptr, nullptr, nullptr, T1};
+    return window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, status_out,
+                          (hipStream_t)stream, &in);
+}
+
+// first frames of the windows of a sequence of N flows: 0, stride, ..., and a
+// last one ending at flow N
+static int vo_starts(int N, int T, int stride, int *out, int cap)
+{
+    int n = 0, s = 0;
+    if (cap > 0) out[0] = 0;
+    n = 1;
+    while (s + T < N) {
+        s = s + stride < N - T ? s + stride : N - T;
+        if (n < cap) out[n] = s;
+        ++n;
+    }
+    return n;
+}
+
+int voldor_vo_windows(int N, int T, int stride)
+{
+    if (T < 2 || T > 16 || N < T || stride < 1 || stride >= T) return VOLDOR_EINVAL;
+    return vo_starts(N, T, stride, nullptr, 0);
+}
+
+// one thread: the trajectory of the sequence from the windows' relative poses
+// (every window in its own gauge |t_1| = 1).  Window i's scale relative to
+// window i - 1 is the length, in window i - 1's units, of the frame pair that
+// seeded window i's T_1; the pose of frame pair (k, k + 1) comes from the
+// latest window starting at or before k.  Any failed window: all NaN.
+__global__ void k_vo_chain(const double *wposes, const int32_t *wstatus, int nwin, int N, int T, int stride,
+                           double *traj)
+{
+    if (threadIdx.x != 0) return;
+    bool ok = true;
+    for (int i = 0; i < nwin; ++i) ok = ok && wstatus[i] == kStatusOk;
+    if (!ok) {
+        for (int k = 0; k < 12 * (N + 1); ++k) traj[k] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    for (int k = 0; k < 12; ++k) traj[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+    int i = 0, s_i = 0, s_next = T < N ? (stride < N - T ? stride : N - T) : N;
+    double scale = 1.0;
+    for (int k = 0; k < N; ++k) {
+        while (i + 1 < nwin && s_next <= k) {
+            // window i + 1 starts at s_next: its T_1 is window i's pair s_next
+            const double *tp = wposes + (size_t)12 * ((size_t)i * T + (s_next - s_i)) + 9;
+            scale *= sqrt(tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2]);
+            ++i;
+            s_i = s_next;
+            s_next = s_i + stride < N - T ? s_i + stride : N - T;
+        }
+        const double *r = wposes + (size_t)12 * ((size_t)i * T + (k - s_i));
+        double step[12];
+        for (int q = 0; q < 9; ++q) step[q] = r[q];
+        for (int q = 0; q < 3; ++q) step[9 + q] = r[9 + q] * scale;
+        pose_mul(step, traj + 12 * k, traj + 12 * (k + 1));
+    }
+}
+
+int voldor_vo_sequence(voldor_ctx *c, const float *flows, int N, int H, int W, const double *K,
+                       const voldor_params *p, int T, int stride, double *wposes, float *depth, float *rigidness,
+                       int32_t *wstatus, double *traj, void *stream)
+{
+    const int nwin = voldor_vo_windows(N, T, stride);
+    if (nwin < 1 || !flows || !wposes || !depth || !rigidness || !wstatus || !traj) return VOLDOR_EINVAL;
+    if (((uintptr_t)wstatus & 3) != 0 || ((uintptr_t)wposes & 7) != 0 || ((uintptr_t)traj & 7) != 0)
+        return VOLDOR_EINVAL;
+    if (!window_args_ok(c, flows, T, H, W, K, p, wposes, depth, rigidness)) return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int starts[4096];
+    if (nwin > 4096) return VOLDOR_EINVAL;
+    vo_starts(N, T, stride, starts, nwin);
+    const size_t fstride = (size_t)H * W * 2;
+    for (int i = 0; i < nwin; ++i) {
+        const WindowInit in = {nullptr, nullptr, nullptr,
+                               i == 0 ? nullptr : wposes + (size_t)12 * ((size_t)(i - 1) * T + (starts[i] - starts[i - 1]))};
+        const int rc = window_enqueue(c, flows + fstride * starts[i], T, H, W, K, p, wposes + (size_t)12 * T * i,
+                                      depth, rigidness, nullptr, wstatus + i, s, i == 0 ? nullptr : &in);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_vo_chain, dim3(1), dim3(64), 0, s, wposes, wstatus, nwin, N, T, stride, traj);
+    return hipGetLastError() == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
 
 int voldor_set_timing(voldor_ctx *c, int enable)

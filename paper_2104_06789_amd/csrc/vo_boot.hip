@@ -737,22 +737,49 @@ __global__ void k_boot_init(int *status, uint32_t *sel)
     if (threadIdx.x < 16) sel[threadIdx.x] = 0;
 }
 
+// T_1 given instead of estimated (overlapping consecutive batches, Sec. 5.4):
+// the pose becomes decomposition candidate 0 with the only vote, so that the
+// triangulation and depth-range passes run unchanged (k_boot_tri rescales its
+// translation to unit length); a non-finite pose or a zero translation is
+// degenerate
+__global__ void k_boot_seed(const double *T1, double *cand, uint32_t *sel, double *info, int *status)
+{
+    if (threadIdx.x != 0 || *status != kStatusOk) return;
+    bool fin = true;
+    for (int k = 0; k < 12; ++k) fin = fin && isfinite(T1[k]);
+    const double tn = sqrt(T1[9] * T1[9] + T1[10] * T1[10] + T1[11] * T1[11]);
+    if (!fin || !(tn > 0.0)) {
+        *status = kStatusDegenerate;
+        return;
+    }
+    for (int k = 0; k < 9; ++k) cand[k] = T1[k];
+    for (int k = 0; k < 3; ++k) cand[18 + k] = T1[9 + k];
+    sel[kSelVotes] = 1;
+    info[0] = -1.0;
+    info[1] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
                      uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
-                     float *theta, hipStream_t s)
+                     float *theta, hipStream_t s, const double *T1_seed)
 {
     const int64_t HW = (int64_t)d.H * d.W;
     const int Ne = (int)(n_eval < HW ? n_eval : HW);
     hipLaunchKernelGGL(k_boot_init, dim3(1), dim3(64), 0, s, c->status, c->sel);
-    HypArgs h{flows, c->hyp, c->hyp_score, c->boot_sub, d.H, d.W, n_hyp, Ne, d.fx, d.fy, d.cx, d.cy, seed};
-    hipLaunchKernelGGL(k_boot_hyp, dim3((n_hyp + 63) / 64 + (Ne + 63) / 64), dim3(64), 0, s, h);
-    ScoreArgs sc{c->boot_sub, c->hyp, c->hyp_score, Ne};
-    hipLaunchKernelGGL(k_boot_score, dim3(n_hyp), dim3(kEvalThreads), 0, s, sc);
-    PickArgs pk{c->hyp, c->hyp_score, c->boot_cand, c->boot_info, c->status, n_hyp};
-    hipLaunchKernelGGL(k_boot_pick, dim3(1), dim3(256), 0, s, pk);
-    VoteArgs va{flows, c->boot_cand, c->sel, c->status, d.H, d.W, Ne, d.fx, d.fy, d.cx, d.cy};
-    hipLaunchKernelGGL(k_boot_vote, dim3((Ne + 255) / 256), dim3(256), 0, s, va);
+    if (T1_seed) {
+        hipLaunchKernelGGL(k_boot_seed, dim3(1), dim3(64), 0, s, T1_seed, c->boot_cand, c->sel, c->boot_info,
+                           c->status);
+    } else {
+        HypArgs h{flows, c->hyp, c->hyp_score, c->boot_sub, d.H, d.W, n_hyp, Ne, d.fx, d.fy, d.cx, d.cy, seed};
+        hipLaunchKernelGGL(k_boot_hyp, dim3((n_hyp + 63) / 64 + (Ne + 63) / 64), dim3(64), 0, s, h);
+        ScoreArgs sc{c->boot_sub, c->hyp, c->hyp_score, Ne};
+        hipLaunchKernelGGL(k_boot_score, dim3(n_hyp), dim3(kEvalThreads), 0, s, sc);
+        PickArgs pk{c->hyp, c->hyp_score, c->boot_cand, c->boot_info, c->status, n_hyp};
+        hipLaunchKernelGGL(k_boot_pick, dim3(1), dim3(256), 0, s, pk);
+        VoteArgs va{flows, c->boot_cand, c->sel, c->status, d.H, d.W, Ne, d.fx, d.fy, d.cx, d.cy};
+        hipLaunchKernelGGL(k_boot_vote, dim3((Ne + 255) / 256), dim3(256), 0, s, va);
+    }
     TriArgs tr{flows, c->boot_cand, rel_poses, c->Mcum, c->boot_info, theta, c->dkeys, c->sel, c->status,
                d.H, d.W, d.T, d.fx, d.fy, d.cx, d.cy};
     hipLaunchKernelGGL(k_boot_tri, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, tr);

@@ -99,10 +99,13 @@ bool window_args_ok(const voldor_ctx *c, const float *flows, int T, int H, int W
                     const float *rigidness);
 // optional initial state proposed for a window (depth [H][W], rigidness [T][H][W]);
 // choice (device int, may be NULL) receives 1 when it replaced the bootstrap's
+// T1 (device double[12], may be NULL): T_1 given instead of the bootstrap's
+// estimate (overlapping consecutive windows)
 struct WindowInit {
     const float *depth;
     const float *rig;
     int32_t *choice;
+    const double *T1;
 };
 int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                    const voldor_params *p, double *poses, float *depth, float *rigidness,
@@ -133,8 +136,9 @@ int launch_gauge_poses(voldor_ctx *c, double *rel_poses, const WinDims &d, hipSt
 int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t s);
 
 // ---- bootstrap (vo_boot.hip)
+// T1_seed (device double[12], or NULL): T_1 given instead of estimated
 int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
                      uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
-                     float *theta, hipStream_t s);
+                     float *theta, hipStream_t s, const double *T1_seed = nullptr);
 
 }  // namespace vo

@@ -92,6 +92,17 @@ def test_batch_host_argument_checks(vo):
     lib.voldor_batch_destroy(None)
 
 
+def test_vo_window_count_matches_the_oracle_starts(vo):
+    # host-side window schedule of voldor_vo_sequence against the oracle's
+    # window_starts; strides that would leave the next T_1 outside a window fail
+    import oracle
+    lib = vo.lib()
+    for N, T, stride in [(12, 5, 1), (12, 5, 3), (5, 5, 2), (9, 4, 3), (30, 6, 1), (31, 6, 4), (16, 16, 15)]:
+        assert lib.voldor_vo_windows(N, T, stride) == len(oracle.window_starts(N, T, stride)), (N, T, stride)
+    for N, T, stride in [(12, 5, 5), (12, 5, 0), (4, 5, 1), (12, 1, 1), (40, 17, 2)]:
+        assert lib.voldor_vo_windows(N, T, stride) == vo.EINVAL, (N, T, stride)
+
+
 def test_abi_struct_layout_matches_binding(tmp_path):
     # the C compiler's view of the two structs the binding mirrors
     gcc = shutil.which("gcc")
