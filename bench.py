@@ -503,10 +503,11 @@ def run_learned(args):
     print(json.dumps(line))
 
 
-def _concurrent(vo, torch, T, H, W, spec, flows, w, p, out, dev, args, pf, lanes=4, per_batch=8):
+def _concurrent(vo, torch, T, H, W, spec, flows, w, p, out, dev, args, pf, lanes=4, per_batch=8, widths=(0, 0)):
     """The same windows solved `lanes` at a time (voldor_window_batch): independent
     windows overlap one window's latency-bound pose chain with the others' sweeps."""
     conc = vo.Batch(lanes, T, H, W, spec.n_groups, graph=True)
+    conc.set_sweep_threads(*widths)
     couts = [vo.Batch.outputs(T, H, W) for _ in range(per_batch)]
     citems = [(flows, w["K"], o) for o in couts]
     cstat = torch.full((per_batch,), -1, dtype=torch.int32, device=dev)
@@ -590,6 +591,8 @@ def main():
     p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit,
                           pose_start=pstart)
     solver = vo.Solver(T, H, W, spec.n_groups)
+    # sweep widths for this shape (every width gives the same result)
+    widths = solver.autotune(flows, w["K"], p)
     solver.set_timing(True)
     dev = flows.device
     out = (torch.empty((T, 12), dtype=torch.float64, device=dev),
@@ -632,7 +635,7 @@ def main():
     # the same windows solved LANES at a time (voldor_window_batch): independent
     # windows overlap one window's latency-bound pose chain with the others' sweeps
     conc_line = None if args.no_concurrent else _concurrent(vo, torch, T, H, W, spec, flows, w, p, out, dev,
-                                                             args, pf)
+                                                             args, pf, widths=widths)
 
     line = {
         "metric": "pixel-frame EM updates/s",
@@ -652,6 +655,7 @@ def main():
                                + (", depth criterion MLE (Eq. 9)" if crit else "")
                                + (", all-pixel mean-shift start" if pstart else ""),
                    "criterion": args.criterion, "pose_start": args.pose_start,
+                   "sweep_threads": {"rows": widths[0], "cols": widths[1]},
                    "T": T, "H": H, "W": W, "n_iters": spec.n_iters, "n_pose_groups": spec.n_groups,
                    "parallelism": "single GPU, one window per step, enqueued back to back on one stream"},
         "windows_per_s": 1e3 / ms,

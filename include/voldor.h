@@ -168,6 +168,22 @@ int voldor_vo_sequence(voldor_ctx *ctx, const float *flows, int N, int H, int W,
                        const voldor_params *p, int T, int stride, double *wposes, float *depth, float *rigidness,
                        int32_t *wstatus, double *traj, void *stream);
 
+/* Threads per chain of the depth sweeps (256, 512 or 1024; 0 = 512), row
+ * sweeps and column sweeps apart.  The width changes how a chain's work is
+ * spread over a workgroup and how many chains fit a CU, never the result: all
+ * widths give the same depth bit for bit.  Windows whose chains would not fit
+ * the LDS at the chosen width are rejected with VOLDOR_EINVAL. */
+int voldor_set_sweep_threads(voldor_ctx *ctx, int rows, int cols);
+int voldor_get_sweep_threads(const voldor_ctx *ctx, int *rows, int *cols);
+
+/* Autotuner: bootstraps the given window (device flows as voldor_window), then
+ * times the row and the column sweeps at every width that fits and keeps the
+ * fastest in the context (also returned in *rows_out, *cols_out if not NULL).
+ * Waits for the device.  VOLDOR_EDEGENERATE if the bootstrap fails (the
+ * widths are then unchanged). */
+int voldor_autotune(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
+                    const voldor_params *p, int *rows_out, int *cols_out, void *stream);
+
 /* ---- batches: many windows of uneven shape and T ------------------------- */
 
 /* One window of a batch: the arguments of voldor_window for that window. */
@@ -210,6 +226,9 @@ void voldor_batch_destroy(voldor_batch *b);
  * needs a stream other than the null stream. */
 int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
                         int32_t *status_out, void *stream);
+
+/* Sweep widths of every lane of the batch (as voldor_set_sweep_threads). */
+int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols);
 
 /* Phase timing of windows with HIP events recorded on their stream, kept for
  * the last 32 windows.  voldor_set_timing(ctx, 1) creates the events (0

@@ -86,6 +86,10 @@ def lib():
         "voldor_pose_scores": (i, [vp, dp, i, ip]),
         "voldor_window_seeded": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp, vp]),
         "voldor_vo_windows": (i, [i, i, i]),
+        "voldor_set_sweep_threads": (i, [vp, i, i]),
+        "voldor_get_sweep_threads": (i, [vp, ip, ip]),
+        "voldor_autotune": (i, [vp, vp, i, i, i, dp, P, ip, ip, vp]),
+        "voldor_batch_set_sweep_threads": (i, [vp, i, i]),
         "voldor_vo_sequence": (i, [vp, vp, i, i, i, dp, P, i, i, vp, vp, vp, vp, vp, vp]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
@@ -354,6 +358,26 @@ class Solver:
                                         _stream(stream)), "voldor_vo_sequence")
         return traj, wposes, wstatus, depth, rig
 
+    def set_sweep_threads(self, rows, cols):
+        """Threads per chain of row and column sweeps (256, 512, 1024; 0 = 512)."""
+        _check(lib().voldor_set_sweep_threads(self._ctx, int(rows), int(cols)), "voldor_set_sweep_threads")
+
+    def sweep_threads(self):
+        r, c = C.c_int(0), C.c_int(0)
+        _check(lib().voldor_get_sweep_threads(self._ctx, C.byref(r), C.byref(c)), "voldor_get_sweep_threads")
+        return r.value, c.value
+
+    def autotune(self, flows, K, params, stream=None):
+        """Time every sweep width on this window's shape and keep the fastest;
+        returns (row threads, column threads)."""
+        flows = _flows(flows)
+        T, H, W, _ = flows.shape
+        Kd, Kp = _dbl(K)
+        r, c = C.c_int(0), C.c_int(0)
+        _check(lib().voldor_autotune(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), C.byref(r), C.byref(c),
+                                     _stream(stream)), "voldor_autotune")
+        return r.value, c.value
+
     def pose_scores(self):
         """All-pixel candidate scores of the last pose step run with pose_start=1:
         [0] the previous pose (-inf if none), [1..] the valid samples in (group,
@@ -413,6 +437,10 @@ class Batch:
                 torch.empty((H, W), dtype=torch.float32, device=device),
                 torch.empty((T, H, W), dtype=torch.float32, device=device),
                 torch.empty(2, dtype=torch.float64, device=device))
+
+    def set_sweep_threads(self, rows, cols):
+        """Sweep widths of every lane (as Solver.set_sweep_threads)."""
+        _check(lib().voldor_batch_set_sweep_threads(self._b, int(rows), int(cols)), "voldor_batch_set_sweep_threads")
 
     def solve(self, windows, params, status, stream=None):
         """Enqueue a batch.  windows: list of (flows [T,H,W,2] CUDA float32, K (fx, fy,

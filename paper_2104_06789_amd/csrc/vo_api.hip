@@ -45,7 +45,8 @@ bool dims_ok(const voldor_ctx *c, int T, int H, int W, int criterion)
 {
     if (!c) return false;
     if (T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max) return false;
-    if ((int)sweep_lds_bytes(T, W, criterion) > c->max_lds || (int)sweep_lds_bytes(T, H, criterion) > c->max_lds)
+    if ((int)sweep_lds_bytes(T, W, criterion, c->sweep_nt[0]) > c->max_lds ||
+        (int)sweep_lds_bytes(T, H, criterion, c->sweep_nt[1]) > c->max_lds)
         return false;
     return true;
 }
@@ -245,6 +246,7 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     }
     // static LDS of the sweep kernel (frames, list counters) comes off the top
     c->max_lds = lds - (int)(sizeof(FrameF) * (kTMax + 1)) - 256;
+    c->sweep_nt[0] = c->sweep_nt[1] = 512;
     c->T_max = T_max;
     c->H_max = H_max;
     c->W_max = W_max;
@@ -538,6 +540,89 @@ int voldor_vo_sequence(voldor_ctx *c, const float *flows, int N, int H, int W, c
     }
     hipLaunchKernelGGL(k_vo_chain, dim3(1), dim3(64), 0, s, wposes, wstatus, nwin, N, T, stride, traj);
     return hipGetLastError() == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+int voldor_set_sweep_threads(voldor_ctx *c, int rows, int cols)
+{
+    if (!c) return VOLDOR_EINVAL;
+    const int v[2] = {rows ? rows : 512, cols ? cols : 512};
+    for (int a = 0; a < 2; ++a)
+        if (v[a] != 256 && v[a] != 512 && v[a] != 1024) return VOLDOR_EINVAL;
+    c->sweep_nt[0] = v[0];
+    c->sweep_nt[1] = v[1];
+    return VOLDOR_OK;
+}
+
+int voldor_get_sweep_threads(const voldor_ctx *c, int *rows, int *cols)
+{
+    if (!c || !rows || !cols) return VOLDOR_EINVAL;
+    *rows = c->sweep_nt[0];
+    *cols = c->sweep_nt[1];
+    return VOLDOR_OK;
+}
+
+// Times the sweep at every width that fits (256, 512, 1024 threads per chain)
+// on this window's shape, row and column sweeps apart, from the bootstrap's
+// state, and keeps the fastest in the context.  Every width gives the same
+// result, so the choice changes speed only.
+int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
+                    const voldor_params *p, int *rows_out, int *cols_out, void *stream)
+{
+    if (!c || !flows || ((uintptr_t)flows & 7) != 0) return VOLDOR_EINVAL;
+    if (!params_ok(p) || !K_ok(K) || T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max)
+        return VOLDOR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const float2 *X = (const float2 *)flows;
+    WinDims d = dims(T, H, W, K);
+    const EmisParams e = emis(K, p);
+    int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
+                              p->depth_hi, c->rel_tmp, c->theta_tmp, s);
+    if (rc == 0) rc = launch_cumulative(c, c->rel_tmp, T, s);
+    int st = 0;
+    if (rc == 0 && (hipStreamSynchronize(s) != hipSuccess ||
+                    hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = VOLDOR_EDEVICE;
+    if (rc) return rc;
+    if (st != kStatusOk) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return VOLDOR_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return VOLDOR_EDEVICE;
+    }
+    const int widths[3] = {256, 512, 1024};
+    const int keep[2] = {c->sweep_nt[0], c->sweep_nt[1]};
+    int best[2] = {keep[0], keep[1]};
+    for (int axis = 0; axis < 2 && rc == 0; ++axis) {
+        const int L = axis ? H : W;
+        float best_ms = 1e30f;
+        for (int wi = 0; wi < 3 && rc == 0; ++wi) {
+            const int nt = widths[wi];
+            if ((int)sweep_lds_bytes(T, L, p->criterion, nt) > c->max_lds) continue;
+            c->sweep_nt[axis] = nt;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 4 && rc == 0; ++rep) {   // the first sweep warms up
+                if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VOLDOR_EDEVICE;
+                if (rc == 0)
+                    rc = launch_sweep(c, c->theta_tmp, c->theta_tmp, X, d, e, (float)p->gamma, p->seed, rep, axis,
+                                      c->range, nullptr, s, p->criterion);
+            }
+            if (rc == 0 && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = VOLDOR_EDEVICE;
+            if (rc == 0 && ms < best_ms) {
+                best_ms = ms;
+                best[axis] = nt;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->sweep_nt[0] = rc == 0 ? best[0] : keep[0];
+    c->sweep_nt[1] = rc == 0 ? best[1] : keep[1];
+    if (rows_out) *rows_out = c->sweep_nt[0];
+    if (cols_out) *cols_out = c->sweep_nt[1];
+    return rc;
 }
 
 int voldor_set_timing(voldor_ctx *c, int enable)

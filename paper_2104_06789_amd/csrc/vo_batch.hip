@@ -150,6 +150,17 @@ int voldor_batch_create(voldor_batch **out, int lanes, int T_max, int H_max, int
     return VOLDOR_OK;
 }
 
+int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols)
+{
+    if (!b) return VOLDOR_EINVAL;
+    for (int l = 0; l < b->lanes; ++l) {
+        const int rc = voldor_set_sweep_threads(b->ctx[l], rows, cols);
+        if (rc) return rc;
+    }
+    drop_graph(b);   // a captured graph holds the old launches
+    return VOLDOR_OK;
+}
+
 void voldor_batch_destroy(voldor_batch *b)
 {
     if (!b) return;

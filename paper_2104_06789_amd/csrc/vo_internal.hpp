@@ -42,6 +42,7 @@ struct voldor_ctx {
     int device;
     int T_max, H_max, W_max, S_max;
     int max_lds;           // bytes of LDS one workgroup may allocate
+    int sweep_nt[2];       // threads per chain of row (directions 0/2) and column (1/3) sweeps
     // persistent device state
     double *Mcum;          // [(T_max+1)][12] cumulative poses M_0..M_T
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
@@ -123,7 +124,8 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
                      const double *rel_poses = nullptr);
 int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
                   hipStream_t s);
-size_t sweep_lds_bytes(int T, int L, int criterion);
+// LDS bytes of one chain of length L with nt threads (256, 512 or 1024)
+size_t sweep_lds_bytes(int T, int L, int criterion, int nt);
 
 // ---- pose (vo_pose.hip)
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,

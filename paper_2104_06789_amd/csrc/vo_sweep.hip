@@ -262,17 +262,20 @@ __device__ __forceinline__ Mat2 shfl_down_m(const Mat2 &m, int d)
 
 // LDS words of the dynamic area for a chain of length L and T frames (the MLE
 // criterion adds log mu of the previous depth, T L words after region 2)
-__host__ __device__ inline int sweep_region2_words(int T, int L)
+__host__ __device__ inline int sweep_region2_words(int T, int L, int nt = kSweepThreads)
 {
     int w = T * L;
     if (w < 8 * L) w = 8 * L;
-    if (w < 4 * L + kSweepThreads) w = 4 * L + kSweepThreads;
+    if (w < 4 * L + nt) w = 4 * L + nt;
     return w;
 }
 
-// CRIT 0: maximum-inlier depth criterion (Eq. 10); 1: maximum likelihood (Eq. 9)
-template <int CRIT>
-__global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
+// CRIT 0: maximum-inlier depth criterion (Eq. 10); 1: maximum likelihood (Eq. 9).
+// NT threads per chain (256, 512 or 1024): every item is the same function of
+// its inputs whatever NT is, so all widths give the same result bit for bit;
+// NT only sets how a chain's work is spread (and how many chains fit a CU)
+template <int CRIT, int NT>
+__global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
     extern __shared__ float lds[];
@@ -300,7 +303,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
     float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
     // MLE: region 2 holds d = log(mu/rho) of the previous depth, lmq its log mu
-    float *lmq = lq + sweep_region2_words(T, L);       // [T][L] (MLE only)
+    float *lmq = lq + sweep_region2_words(T, L, NT);       // [T][L] (MLE only)
 
     load_frames(a.Mcum, T, fr);
     if (tid == 0) {
@@ -309,11 +312,11 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     }
     const float llo = (float)log(a.range[0]);
     const float lrange = (float)(log(a.range[1]) - log(a.range[0]));
-    for (int k = tid; k < L; k += kSweepThreads) th[k] = a.theta_in[chain_pixel(dir, H, W, chain, k)];
+    for (int k = tid; k < L; k += NT) th[k] = a.theta_in[chain_pixel(dir, H, W, chain, k)];
     // random depth, log-uniform: the 8 chain positions whose coordinate along
     // the sweep axis is 8g .. 8g + 7 take the 32-bit words of the Philox block
     // with counter (gsweep, chain, g, 0), hi before lo of each 64-bit output
-    for (int g = tid; g < (L + 7) / 8; g += kSweepThreads) {
+    for (int g = tid; g < (L + 7) / 8; g += NT) {
         uint64_t c[4] = {(uint64_t)a.gsweep, (uint64_t)chain, (uint64_t)g, 0ull};
         philox4x64_10(c, a.seed, kDepthStream);
 #pragma unroll
@@ -330,27 +333,27 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
 
     // ---- A: ell and r of the previous depth, one item per (position, frame),
     // four items per thread in flight
-    for (int i0 = tid; i0 < T * L; i0 += 4 * kSweepThreads) {
+    for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
         int xs[4], ys[4], ts[4];
         float ths[4], dd[4];
         bool act[4], ok[4];
-        // item i = (t - 1) L + k; the thread's items are kSweepThreads apart
+        // item i = (t - 1) L + k; the thread's items are NT apart
         int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            act[b] = i0 + b * kSweepThreads < T * L;
+            act[b] = i0 + b * NT < T * L;
             const int kk = act[b] ? k : 0;
             chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
             ts[b] = act[b] ? t : 1;
             ths[b] = th[kk];
-            k += kSweepThreads;
+            k += NT;
             while (k >= L) { k -= L; ++t; }
         }
         if constexpr (CRIT == 0) {
             batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * kSweepThreads;
+                const int i = i0 + b * NT;
                 if (!act[b]) continue;
                 float ell = kLogHalf, r = 0.5f;
                 if (ok[b]) {
@@ -366,7 +369,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
             batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * kSweepThreads;
+                const int i = i0 + b * NT;
                 if (!act[b]) continue;
                 // missing: d = 0 (r = 1/2 in the E-step) and log mu = 0 (term 0)
                 lq[i] = dd[b];
@@ -384,7 +387,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
         const int seglen = ((L + 63) / 64) | 1;
         const float g = a.gamma, gc = 1.0f - a.gamma;
         const int s0 = min(lane * seglen, L), s1 = min(s0 + seglen, L);
-        for (int t = wv; t < T; t += kSweepWaves) {
+        for (int t = wv; t < T; t += (NT / 64)) {
             float *rq = fq + t * L;
             const float *ll = lq + t * L;
             // segment transfer matrices: forward A_k = diag(r,1-r) Gamma,
@@ -454,14 +457,14 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     }
     __syncthreads();
     if (a.q_out) {
-        for (int i = tid; i < T * L; i += kSweepThreads) {
+        for (int i = tid; i < T * L; i += NT) {
             const int t = i / L, k = i - t * L;
             a.q_out[(size_t)t * H * W + chain_pixel(dir, H, W, chain, k)] = fq[i];
         }
     }
 
     // ---- S: score of the previous depth
-    for (int k = tid; k < L; k += kSweepThreads) {
+    for (int k = tid; k < L; k += NT) {
         float s = 0.0f;
         if constexpr (CRIT == 0) {
             for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
@@ -472,27 +475,27 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     }
     __syncthreads();
     // ell of the random sample, one item per (position, frame)
-    for (int i0 = tid; i0 < T * L; i0 += 4 * kSweepThreads) {
+    for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
         int xs[4], ys[4], ts[4];
         float ths[4], dd[4];
         bool act[4], ok[4];
-        // item i = (t - 1) L + k; the thread's items are kSweepThreads apart
+        // item i = (t - 1) L + k; the thread's items are NT apart
         int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            act[b] = i0 + b * kSweepThreads < T * L;
+            act[b] = i0 + b * NT < T * L;
             const int kk = act[b] ? k : 0;
             chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
             ts[b] = act[b] ? t : 1;
             ths[b] = sm[kk];
-            k += kSweepThreads;
+            k += NT;
             while (k >= L) { k -= L; ++t; }
         }
         if constexpr (CRIT == 0) {
             batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * kSweepThreads;
+                const int i = i0 + b * NT;
                 if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
             }
         } else {
@@ -501,13 +504,13 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
             batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * kSweepThreads;
+                const int i = i0 + b * NT;
                 if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b], lm[b]) : 0.0f;
             }
         }
     }
     __syncthreads();
-    for (int k = tid; k < L; k += kSweepThreads) {
+    for (int k = tid; k < L; k += NT) {
         float s = 0.0f;
         if constexpr (CRIT == 0) {
             for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
@@ -526,7 +529,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     int2 *list0 = (int2 *)lq, *list1 = list0 + L;
     // first losing offset of each live origin, INT_MAX until one is seen
     int *first0 = (int *)(list1 + L), *first1 = first0 + L;
-    for (int k = tid; k < L; k += kSweepThreads) {
+    for (int k = tid; k < L; k += NT) {
         if (k == L - 1) {
             nxt[k] = L;
         } else if (aval[k] == th[k + 1]) {
@@ -546,10 +549,10 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
         if (n == 0) break;
         int2 *lc = cur ? list1 : list0, *ln = cur ? list0 : list1;
         int *first = cur ? first1 : first0, *firstn = cur ? first0 : first1;
-        const int la = max(kSweepThreads / n, 1);   // look-ahead per live origin
+        const int la = max(NT / n, 1);   // look-ahead per live origin
         const int items = n * la;
         const float ila = frcp((float)la);
-        for (int i = tid; i < items; i += kSweepThreads) {
+        for (int i = tid; i < items; i += NT) {
             // i / la through FP32: (i + 1/2) / la is at least 1/(2 la) from an integer
             const int sl = (int)(((float)i + 0.5f) * ila), p = i - sl * la;
             const int2 e = lc[sl];
@@ -566,7 +569,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
         }
         if (tid == 0) s_cnt[cur ^ 1] = 0;
         __syncthreads();
-        for (int sl = tid; sl < n; sl += kSweepThreads) {
+        for (int sl = tid; sl < n; sl += NT) {
             const int2 e = lc[sl];
             const int p = first[sl];   // INT_MAX: survived the whole look-ahead
             if (p < la) {
@@ -586,19 +589,19 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
     // ---- D: nodes reachable from 0 through next(), by pointer doubling
     int *J0 = (int *)lq, *J1 = J0 + L, *mark = J1 + L;
     float *thn = (float *)(mark + L);
-    for (int k = tid; k < L; k += kSweepThreads) {
+    for (int k = tid; k < L; k += NT) {
         J0[k] = nxt[k];
         mark[k] = k == 0;
     }
     __syncthreads();
     int *Jc = J0, *Jn = J1;
     for (int span = 1; span < L; span <<= 1) {
-        for (int k = tid; k < L; k += kSweepThreads) {
+        for (int k = tid; k < L; k += NT) {
             const int to = Jc[k];
             if (mark[k] && to < L) mark[to] = 1;
         }
         __syncthreads();
-        for (int k = tid; k < L; k += kSweepThreads) {
+        for (int k = tid; k < L; k += NT) {
             const int to = Jc[k];
             Jn[k] = to < L ? Jc[to] : L;
         }
@@ -607,7 +610,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
         Jc = Jn;
         Jn = tmp;
     }
-    for (int k = tid; k < L; k += kSweepThreads) {
+    for (int k = tid; k < L; k += NT) {
         if (mark[k]) {
             const int e = nxt[k];
             const float v = aval[k];
@@ -615,7 +618,7 @@ __global__ void __launch_bounds__(kSweepThreads, 6) k_sweep(SweepArgs a)
         }
     }
     __syncthreads();
-    for (int k = tid; k < L; k += kSweepThreads) a.theta_out[chain_pixel(dir, H, W, chain, k)] = thn[k];
+    for (int k = tid; k < L; k += NT) a.theta_out[chain_pixel(dir, H, W, chain, k)] = thn[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -778,10 +781,21 @@ __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-size_t sweep_lds_bytes(int T, int L, int criterion)
+size_t sweep_lds_bytes(int T, int L, int criterion, int nt)
 {
-    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L) + (criterion ? (size_t)T * L : 0)) *
+    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L, nt) + (criterion ? (size_t)T * L : 0)) *
            sizeof(float);
+}
+
+template <int CRIT, int NT>
+static int launch_sweep_nt(const SweepArgs &a, int nchain, size_t lds, hipStream_t s)
+{
+    if (lds > 65536 &&
+        hipFuncSetAttribute((const void *)k_sweep<CRIT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+        return VOLDOR_EDEVICE;
+    hipLaunchKernelGGL((k_sweep<CRIT, NT>), dim3(nchain), dim3(NT), lds, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
 int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
@@ -790,7 +804,8 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
 {
     const int L = (dir & 1) ? d.H : d.W;
     const int nchain = (dir & 1) ? d.W : d.H;
-    const size_t lds = sweep_lds_bytes(d.T, L, criterion);
+    const int nt = c->sweep_nt[dir & 1];
+    const size_t lds = sweep_lds_bytes(d.T, L, criterion, nt);
     if (L < 16) return VOLDOR_EINVAL;
     SweepArgs a;
     a.theta_in = theta_in;
@@ -808,14 +823,15 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.gamma = gamma;
     a.seed = seed;
     a.gsweep = gsweep;
-    const void *kern = criterion ? (const void *)k_sweep<1> : (const void *)k_sweep<0>;
-    if (lds > 65536 && hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return VOLDOR_EDEVICE;
-    if (criterion)
-        hipLaunchKernelGGL(k_sweep<1>, dim3(nchain), dim3(kSweepThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_sweep<0>, dim3(nchain), dim3(kSweepThreads), lds, s, a);
-    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+    switch (nt * 2 + (criterion ? 1 : 0)) {
+    case 512: return launch_sweep_nt<0, 256>(a, nchain, lds, s);
+    case 513: return launch_sweep_nt<1, 256>(a, nchain, lds, s);
+    case 1024: return launch_sweep_nt<0, 512>(a, nchain, lds, s);
+    case 1025: return launch_sweep_nt<1, 512>(a, nchain, lds, s);
+    case 2048: return launch_sweep_nt<0, 1024>(a, nchain, lds, s);
+    case 2049: return launch_sweep_nt<1, 1024>(a, nchain, lds, s);
+    default: return VOLDOR_EINVAL;
+    }
 }
 
 int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, const WinDims &d,
