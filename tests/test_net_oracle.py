@@ -153,3 +153,4 @@ def test_adam_first_step_and_convergence():
     for s in range(1, 4001):
         p, m, v = net.adam_step(p, 2 * (p - target), m, v, s, lr=0.01)
     assert np.allclose(p, target, atol=1e-3)
+
