@@ -363,6 +363,62 @@ def run_vo(args):
     print(json.dumps(line))
 
 
+def run_resfit(args):
+    """Regression of the Fisk laws on residuals (Fig. 4b procedure): the noisy
+    flows of an indoor window (T=6, 640x480, no moving objects) against the same
+    scene's exact flows, 40 bins of |v|.  The binning pass streams both flow
+    fields once (16 bytes per item): HBM-bound."""
+    import numpy as np
+    import torch
+
+    import paper_2104_06789_amd as vo
+    import synthflow
+
+    w = synthflow.make_window("indoor", args.seed, outliers=False)
+    g = synthflow.make_window("indoor", args.seed, noise=False, outliers=False)
+    X = torch.from_numpy(w["flows"]).cuda()
+    G = torch.from_numpy(g["flows"]).cuda()
+    n = X.numel() // 2
+    nb = 40
+    v_max = float(np.ceil(np.nanpercentile(np.linalg.norm(w["flows"].reshape(-1, 2), axis=1), 99.5)))
+    work = torch.empty(int(vo.lib().voldor_residual_workspace(n, nb)), dtype=torch.float64, device="cuda")
+    out = torch.empty((nb, 4), dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        vo.residual_bins(X, G, nb, v_max, work=work, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        vo.residual_bins(X, G, nb, v_max, work=work, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    launch_ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    laws, bins = vo.residual_fit(X, G, nb, v_max)
+    spec = w["spec"]
+    alg_bytes = 16.0 * n
+    gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    line = {
+        "metric": "residual items/s binned for the Fisk-law regression",
+        "value": n / (ms * 1e-3), "unit": "items/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 sums of f32 flows",
+        "data": "synthetic",
+        "config": {"workload": f"resfit: indoor window T=6 640x480 noisy vs exact flows, {nb} bins over |v| < {v_max}, "
+                               f"seed {args.seed}", "items": n},
+        "laws": {"a1": laws[0], "a2": laws[1], "b1": laws[2], "b2": laws[3]},
+        # the generator draws the end-point error from Fisk(c1 |v| + c0, beta), so
+        # its square follows Fisk((c1 |v| + c0)^2, beta / 2)
+        "generator_law_of_squared_epe": {"A": f"({spec.noise_c1} |v| + {spec.noise_c0})^2",
+                                         "B": spec.noise_beta / 2},
+        "roofline": {"bound": "hbm", "kernel": "k_resid_bins + k_resid_reduce", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "launch_ms": launch_ms},
+    }
+    print(json.dumps(line))
+
+
 def run_learned(args):
     """The learned proposal: train it on windows labelled by the plain EM, then
     compare EM at LEARN_ITERS iterations from the proposal (falling back to the
@@ -540,7 +596,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned", "vo"])
+    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned", "vo", "resfit"])
     ap.add_argument("--vo-flows", type=int, default=18, help="flows of the sequence (--workload vo)")
     ap.add_argument("--vo-stride", type=int, default=1, help="frames between window starts (--workload vo)")
     ap.add_argument("--seed", type=int, default=0)
@@ -574,6 +630,9 @@ def main():
         return
     if args.workload == "vo":
         run_vo(args)
+        return
+    if args.workload == "resfit":
+        run_resfit(args)
         return
 
     import numpy as np

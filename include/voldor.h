@@ -184,6 +184,29 @@ int voldor_get_sweep_threads(const voldor_ctx *ctx, int *rows, int *cols);
 int voldor_autotune(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
                     const voldor_params *p, int *rows_out, int *cols_out, void *stream);
 
+/* Regression of the Fisk laws of Eq. 6-7 on optical-flow residuals (the
+ * procedure behind Fig. 4b).  Items x = |X - G|^2 (floored at x_floor) are
+ * binned by |X| in nbins equal bins over [0, v_max); each bin with at least
+ * min_count items is fitted by the moments of log x (log of a Fisk variable is
+ * logistic with location log A and scale 1/B); log A and B are then fitted
+ * against the bins' mean |X| by least squares weighted by the counts.
+ *   X, G    device float [n][2]: observed flows and reference flows, 8-byte
+ *           aligned; items with a non-finite component are skipped
+ *   laws    host double[4]: a1, a2, b1, b2 (output)
+ *   bins    host double [nbins][4] or NULL: count, sum |X|, sum log x,
+ *           sum (log x)^2 per bin (output)
+ * 2 <= nbins <= 256.  Waits for the device.  VOLDOR_EDEGENERATE if fewer than
+ * two bins qualify.  Allocates its own scratch. */
+int voldor_residual_fit(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
+                        int min_count, double *laws, double *bins, void *stream);
+
+/* The binning pass of voldor_residual_fit alone, enqueued without waiting:
+ *   work  device double[voldor_residual_workspace(n, nbins)]: scratch
+ *   bins  device double [nbins][4]: count, sum |X|, sum log x, sum (log x)^2 */
+int64_t voldor_residual_workspace(int64_t n, int nbins);
+int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
+                         double *work, double *bins, void *stream);
+
 /* ---- batches: many windows of uneven shape and T ------------------------- */
 
 /* One window of a batch: the arguments of voldor_window for that window. */

@@ -42,7 +42,9 @@ def bin_stats(X, G, nbins, v_max, x_floor=1e-12):
 def fit(stats, min_count=64):
     """(a1, a2, b1, b2) from per-bin statistics, and the per-bin (vbar, alpha, beta)."""
     n, sv, sy, syy = stats.T
-    use = n >= min_count
+    nn = np.maximum(n, 1)
+    # bins with too few items, or with no spread (no finite Fisk shape), are left out
+    use = (n >= min_count) & (syy / nn - (sy / nn) ** 2 > 0)
     vbar = sv[use] / n[use]
     mean = sy[use] / n[use]
     var = syy[use] / n[use] - mean ** 2

@@ -90,6 +90,9 @@ def lib():
         "voldor_get_sweep_threads": (i, [vp, ip, ip]),
         "voldor_autotune": (i, [vp, vp, i, i, i, dp, P, ip, ip, vp]),
         "voldor_batch_set_sweep_threads": (i, [vp, i, i]),
+        "voldor_residual_fit": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, i, dp, dp, vp]),
+        "voldor_residual_workspace": (C.c_int64, [C.c_int64, i]),
+        "voldor_residual_bins": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, vp, vp, vp]),
         "voldor_vo_sequence": (i, [vp, vp, i, i, i, dp, P, i, i, vp, vp, vp, vp, vp, vp]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
@@ -160,6 +163,36 @@ def _flows(flows):
     if flows.dim() != 4 or flows.shape[3] != 2 or not flows.is_contiguous():
         raise ValueError("flows must be contiguous [T,H,W,2]")
     return flows
+
+
+def residual_fit(X, G, nbins=40, v_max=40.0, x_floor=1e-12, min_count=64, stream=None):
+    """Fisk laws (a1, a2, b1, b2) of Eq. 6-7 fitted to the residuals |X - G|^2
+    binned by |X| (CUDA float32 flows [..., 2]); returns (laws, bins [nbins][4])."""
+    import torch
+    X = X.to(torch.float32).contiguous()
+    G = G.to(torch.float32).contiguous()
+    if not (X.is_cuda and G.is_cuda and X.shape == G.shape and X.shape[-1] == 2):
+        raise ValueError("X and G must be CUDA tensors of the same shape [..., 2]")
+    laws = np.zeros(4)
+    bins = np.zeros((nbins, 4))
+    _check(lib().voldor_residual_fit(_ptr(X), _ptr(G), X.numel() // 2, nbins, v_max, x_floor, min_count,
+                                     laws.ctypes.data_as(C.POINTER(C.c_double)),
+                                     bins.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)),
+           "voldor_residual_fit")
+    return laws, bins
+
+
+def residual_bins(X, G, nbins=40, v_max=40.0, x_floor=1e-12, work=None, out=None, stream=None):
+    """The binning pass alone, enqueued: returns the CUDA float64 [nbins][4] bins."""
+    import torch
+    n = X.numel() // 2
+    if work is None:
+        work = torch.empty(int(lib().voldor_residual_workspace(n, nbins)), dtype=torch.float64, device=X.device)
+    if out is None:
+        out = torch.empty((nbins, 4), dtype=torch.float64, device=X.device)
+    _check(lib().voldor_residual_bins(_ptr(X), _ptr(G), n, nbins, v_max, x_floor, _ptr(work), _ptr(out),
+                                      _stream(stream)), "voldor_residual_bins")
+    return out
 
 
 class Solver:
