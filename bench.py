@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_sweep_indoor_hbm_traffic.md)
 SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
                         "write_bytes": 1249.0390625 * 1024 * 1.0}
-SWEEP_SOURCES_SHA = "73a3fafa5a12d21f"
+SWEEP_SOURCES_SHA = "50e8a0e4a8891cb3"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU instructions: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz = 39.3 T lane-instructions/s (independent v_fma_f32 chains sustain
