@@ -5,9 +5,10 @@
 // location log(alpha) and scale 1/beta), and count-weighted least squares of
 // log(alpha) = log(a1) + a2 v and beta = b1 v + b2 over the bins.
 //
-// k_resid_bins streams the two flow fields once (16 bytes per item, HBM
-// bound) and accumulates per-bin count, sum |v|, sum log x and sum (log x)^2
-// in FP64; per-workgroup partials are then summed over workgroups in a fixed
+// k_resid_bins streams the two flow fields once (16 bytes per item) and
+// accumulates per-bin count, sum |v|, sum log x and sum (log x)^2 in FP64;
+// its cost is the VALU work of the per-bin row reductions and of the log, not
+// HBM.  Per-workgroup partials are then summed over workgroups in a fixed
 // order, so the result does not depend on scheduling.
 #include "vo_internal.hpp"
 
@@ -18,9 +19,10 @@
 
 namespace vo {
 
-constexpr int kFitThreads = 256;
+constexpr int kFitThreads = 512;
 constexpr int kFitMaxBins = 256;
 constexpr int kFitBlocks = 1024;
+constexpr int kFitK = 4;   // items per lane and round
 
 // FP64 cross-lane moves without the LDS crossbar, on the two 32-bit halves:
 // DPP row rotation within 16 lanes, and the gfx950 lane-half swaps, which give
@@ -52,68 +54,158 @@ __device__ __forceinline__ double partner32_d(double v, int lane)
     return __longlong_as_double((long long)(((unsigned long long)hi[k] << 32) | lo[k]));
 }
 
-// wave total (every lane; lane 0's is the one used, in a fixed order)
-__device__ __forceinline__ double fit_wave_sum(double v, int lane)
+// Natural log of a positive finite x to a few ulp: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), and log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...)
+// with s = (m - 1) / (m + 1), |s| <= 0.1716; eleven terms leave a remainder
+// below 1e-20.  The log only enters sums (no bin decision depends on it).
+__device__ __forceinline__ double fit_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);   // m in [0.5, 1)
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+    double p = 1.0 / 23.0;
+#pragma unroll
+    for (int k = 21; k >= 3; k -= 2) p = fma(p, s2, 1.0 / k);
+    const double t = 2.0 * s;
+    return fma((double)e, 0.69314718055994530942, fma(t * s2, p, t));
+}
+
+// total over the 16 lanes of a row, in every lane of the row
+__device__ __forceinline__ double fit_row_sum(double v)
 {
     v += dpp_d<0x128>(v);   // row_ror:8
     v += dpp_d<0x124>(v);   // row_ror:4
     v += dpp_d<0x122>(v);   // row_ror:2
     v += dpp_d<0x121>(v);   // row_ror:1
-    v += partner16_d(v, lane);
-    v += partner32_d(v, lane);
     return v;
 }
 
-// Each wave keeps its own histogram in LDS.  A wave takes 64 consecutive
-// items at a time; flows are smooth, so its lanes fall in few bins: for each
-// bin present, the four sums over the lanes in it are wave reductions, and
-// lane 0 adds them to the wave's histogram (no atomics, a fixed order).  The
-// four waves' histograms are added in wave order at the end.
+__device__ __forceinline__ int fit_row_sum_i(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, true);
+    return v;
+}
+
+// A wave takes kFitK x 64 consecutive items at a time (item k of lane l is
+// l + 64 k: coalesced loads).  Flows are smooth, so the items fall in few bins;
+// for each bin present, every lane adds its items in it, the four sums are
+// reduced over each 16-lane row, and in every row the lane that owns the bin
+// (lane b % 16 of the row, register slot b / 16) adds them to its running
+// sums.  No atomics and no shared-memory traffic in the loop, a fixed order.
+// At the end the four rows are added (rows 0 + 1, 2 + 3, then the halves),
+// each wave writes its sums to LDS, and the waves are added in wave order.
+template <int NS>
 __global__ void __launch_bounds__(kFitThreads) k_resid_bins(const float2 *X, const float2 *G, int64_t n, int nbins,
                                                             double inv_width, double x_floor, double *part)
 {
-    __shared__ double hist[kFitThreads / 64][kFitMaxBins * 4];
+    extern __shared__ double hist[];   // [waves][nbins][4]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double *h = hist[wv];
-    for (int i = lane; i < nbins * 4; i += 64) h[i] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kFitThreads;
-    for (int64_t j0 = (int64_t)blockIdx.x * kFitThreads + 64 * wv; j0 < n; j0 += stride) {
-        const int64_t j = j0 + lane;
-        int b = -1;
-        double v = 0.0, y = 0.0;
-        if (j < n) {
-            const float2 x = X[j], g = G[j];
-            if (isfinite(x.x + x.y + g.x + g.y)) {
-                const double vx = x.x, vy = x.y;
-                v = sqrt(vx * vx + vy * vy);
-                const int bb = (int)floor(v * inv_width);
-                if (bb >= 0 && bb < nbins) {
-                    const double dx = vx - (double)g.x, dy = vy - (double)g.y;
-                    y = log(fmax(dx * dx + dy * dy, x_floor));
-                    b = bb;
+    int cnt[NS];
+    double sv[NS], sy[NS], syy[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        cnt[k] = 0;
+        sv[k] = sy[k] = syy[k] = 0.0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kFitThreads * kFitK;
+    for (int64_t j0 = ((int64_t)blockIdx.x * (kFitThreads / 64) + wv) * 64 * kFitK; j0 < n; j0 += stride) {
+        int b[kFitK];
+        double v[kFitK], y[kFitK];
+        float2 xs[kFitK], gs[kFitK];
+#pragma unroll
+        for (int k = 0; k < kFitK; ++k) {   // all loads first (index clamped, n >= 1)
+            const int64_t j = min(j0 + lane + 64 * k, n - 1);
+            xs[k] = X[j];
+            gs[k] = G[j];
+        }
+#pragma unroll
+        for (int k = 0; k < kFitK; ++k) {
+            b[k] = -1;
+            v[k] = y[k] = 0.0;
+            if (j0 + lane + 64 * k < n) {
+                const float2 x = xs[k], g = gs[k];
+                if (isfinite(x.x + x.y + g.x + g.y)) {
+                    const double vx = x.x, vy = x.y;
+                    const double m = sqrt(vx * vx + vy * vy);
+                    const int bb = (int)floor(m * inv_width);
+                    if (bb >= 0 && bb < nbins) {
+                        const double dx = vx - (double)g.x, dy = vy - (double)g.y;
+                        y[k] = fit_log(fmax(dx * dx + dy * dy, x_floor));
+                        v[k] = m;
+                        b[k] = bb;
+                    }
                 }
             }
         }
-        uint64_t pending = __ballot(b >= 0);
+        int first = b[kFitK - 1];
+#pragma unroll
+        for (int k = kFitK - 2; k >= 0; --k) first = b[k] >= 0 ? b[k] : first;
+        uint64_t pending = __ballot(first >= 0);
         while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int bin = __shfl(b, leader, 64);
-            const bool mine = b == bin;
-            const double c = fit_wave_sum(mine ? 1.0 : 0.0, lane), sv = fit_wave_sum(mine ? v : 0.0, lane);
-            const double sy = fit_wave_sum(mine ? y : 0.0, lane), syy = fit_wave_sum(mine ? y * y : 0.0, lane);
-            if (lane == 0) {
-                h[4 * bin + 0] += c;
-                h[4 * bin + 1] += sv;
-                h[4 * bin + 2] += sy;
-                h[4 * bin + 3] += syy;
+            const int bin = __builtin_amdgcn_readlane(first, (int)__builtin_ctzll(pending));
+            int c = 0;
+            double tv = 0.0, ty = 0.0, tyy = 0.0;
+#pragma unroll
+            for (int k = 0; k < kFitK; ++k) {
+                const bool m = b[k] == bin;
+                const double mv = m ? v[k] : 0.0, my = m ? y[k] : 0.0;
+                c += m ? 1 : 0;
+                tv += mv;
+                ty += my;
+                tyy = fma(my, my, tyy);
+                b[k] = m ? -1 : b[k];
             }
-            pending &= ~__ballot(mine);
+            c = fit_row_sum_i(c);
+            tv = fit_row_sum(tv);
+            ty = fit_row_sum(ty);
+            tyy = fit_row_sum(tyy);
+            const bool own = (lane & 15) == (bin & 15);
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                if (own && (bin >> 4) == k) {
+                    cnt[k] += c;
+                    sv[k] += tv;
+                    sy[k] += ty;
+                    syy[k] += tyy;
+                }
+            first = b[kFitK - 1];
+#pragma unroll
+            for (int k = kFitK - 2; k >= 0; --k) first = b[k] >= 0 ? b[k] : first;
+            pending = __ballot(first >= 0);
+        }
+    }
+    double *h = hist + (size_t)wv * nbins * 4;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        // rows: lane l and l ^ 16 first, then l and l ^ 32 (the same order in every lane)
+        double c = (double)cnt[k], a = sv[k], e = sy[k], f = syy[k];
+        c += partner16_d(c, lane);
+        a += partner16_d(a, lane);
+        e += partner16_d(e, lane);
+        f += partner16_d(f, lane);
+        c += partner32_d(c, lane);
+        a += partner32_d(a, lane);
+        e += partner32_d(e, lane);
+        f += partner32_d(f, lane);
+        const int bin = lane + 16 * k;
+        if (lane < 16 && bin < nbins) {
+            h[4 * bin + 0] = c;
+            h[4 * bin + 1] = a;
+            h[4 * bin + 2] = e;
+            h[4 * bin + 3] = f;
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbins * 4; i += kFitThreads) {
         double t = 0.0;
-        for (int w = 0; w < kFitThreads / 64; ++w) t += hist[w][i];
+        for (int w = 0; w < kFitThreads / 64; ++w) t += hist[(size_t)w * nbins * 4 + i];
         part[(size_t)blockIdx.x * nbins * 4 + i] = t;
     }
 }
@@ -142,7 +234,7 @@ extern "C" {
 int64_t voldor_residual_workspace(int64_t n, int nbins)
 {
     if (n < 1 || nbins < 2 || nbins > vo::kFitMaxBins) return VOLDOR_EINVAL;
-    const int64_t blocks = std::min<int64_t>(vo::kFitBlocks, (n + vo::kFitThreads - 1) / vo::kFitThreads);
+    const int64_t blocks = std::min<int64_t>(vo::kFitBlocks, (n + vo::kFitThreads * vo::kFitK - 1) / (vo::kFitThreads * vo::kFitK));
     return blocks * nbins * 4;
 }
 
@@ -155,9 +247,19 @@ int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, d
         ((uintptr_t)bins & 7) != 0)
         return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const int blocks = (int)std::min<int64_t>(kFitBlocks, (n + kFitThreads - 1) / kFitThreads);
-    hipLaunchKernelGGL(k_resid_bins, dim3(blocks), dim3(kFitThreads), 0, s, (const float2 *)X, (const float2 *)G, n,
-                       nbins, nbins / v_max, x_floor, work);
+    const int blocks = (int)std::min<int64_t>(kFitBlocks, (n + kFitThreads * kFitK - 1) / (kFitThreads * kFitK));
+    const size_t lds = sizeof(double) * (kFitThreads / 64) * nbins * 4;
+    const auto *x2 = (const float2 *)X, *g2 = (const float2 *)G;
+    const double iw = nbins / v_max;
+    const int ns = (nbins + 15) / 16;
+#define FIT_LAUNCH(NS) hipLaunchKernelGGL(k_resid_bins<NS>, dim3(blocks), dim3(kFitThreads), lds, s, x2, g2, n, nbins, iw, x_floor, work)
+    if (ns <= 1) FIT_LAUNCH(1);
+    else if (ns <= 2) FIT_LAUNCH(2);
+    else if (ns <= 3) FIT_LAUNCH(3);
+    else if (ns <= 4) FIT_LAUNCH(4);
+    else if (ns <= 8) FIT_LAUNCH(8);
+    else FIT_LAUNCH(16);
+#undef FIT_LAUNCH
     hipLaunchKernelGGL(k_resid_reduce, dim3(nbins * 4), dim3(256), 0, s, work, blocks, nbins, bins);
     return hipGetLastError() == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }

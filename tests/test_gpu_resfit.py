@@ -62,3 +62,17 @@ def test_residual_fit_rejects_bad_arguments(vo, torch):
     for kw in [dict(nbins=1), dict(nbins=300), dict(v_max=0.0), dict(min_count=1)]:
         with pytest.raises(vo.VoldorError):
             vo.residual_fit(X, X, **{**dict(nbins=40, v_max=40.0, min_count=64), **kw})
+
+
+@pytest.mark.parametrize("nb", [2, 64, 65, 256])
+def test_residual_bins_every_register_slot(vo, torch, nb):
+    # bin counts that fill one, two and four register slots per lane (b = 64 k
+    # + lane), the maximum included; flows over the whole range and beyond
+    # v_max, a ragged tail of a wave and of a workgroup
+    n = 3 * 512 * 1024 + 77
+    X, G = _sample(n, 1000 + nb)
+    vmax = 37.5
+    bins = vo.residual_bins(torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda(), nb, vmax).cpu().numpy()
+    ref = resfit.bin_stats(X, G, nb, vmax)
+    assert np.array_equal(bins[:, 0], ref[:, 0])
+    assert np.allclose(bins[:, 1:], ref[:, 1:], rtol=1e-12, atol=1e-9)
