@@ -24,7 +24,7 @@ DEFAULTS = dict(
     lmeds_hypotheses=512, lmeds_eval_pixels=16384, ms_tol=1e-5,
     a1=0.01, a2=0.09, b1=-0.0022, b2=1.0, lam=0.15, gamma=0.9,
     sigma2_trans=0.1, sigma2_rot=0.004, beta_min=0.01, x_floor=1e-12,
-    depth_lo=0.0, depth_hi=0.0, seed=0, criterion=0, pose_start=0,
+    depth_lo=0.0, depth_hi=0.0, seed=0, criterion=0, pose_start=0, residual_model=0,
 )
 
 
@@ -38,6 +38,7 @@ class Params(C.Structure):
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
         ("seed", C.c_uint64), ("criterion", C.c_int32), ("pose_start", C.c_int32),
+        ("residual_model", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -69,6 +70,7 @@ def lib():
             "or_depth_sample": (C.c_double, [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double,
                                              C.c_double]),
             "or_fisk_logpdf": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+            "or_gauss_logpdf": (C.c_double, [C.c_double, C.c_double]),
             "or_sym_eig": (None, [i, d, d, d]),
             "or_svd3": (None, [d, d, d, d]),
             "or_se3_exp": (None, [d, d, d]),
@@ -144,6 +146,12 @@ def depth_sample(seed, global_sweep, direction, x, y, d_lo, d_hi):
 
 def fisk_logpdf(x, log_alpha, beta):
     return lib().or_fisk_logpdf(float(x), float(log_alpha), float(beta))
+
+
+def gauss_logpdf(x, log_alpha):
+    """Log density of the squared EPE under the Gaussian residual model: the
+    exponential with mean s = alpha / ln 2 (the Fisk's median alpha)."""
+    return lib().or_gauss_logpdf(float(x), float(log_alpha))
 
 
 def sym_eig(A):

@@ -20,7 +20,9 @@
  *                 Fig. 5) or, as a variant, the maximum-likelihood criterion
  *                 it relaxes (Eq. 9); rigidness without smoothing.
  * The residual model is the Fisk (log-logistic) density of the squared
- * end-point error with flow-dependent scale/shape (Eq. 4-8).
+ * end-point error with flow-dependent scale/shape (Eq. 4-8), or, as the
+ * variant of the paper's ablations, the density of the squared error under
+ * an isotropic Gaussian flow error with the same median.
  *
  * All floating point is double.  Flows arrive as float32 [T][H][W][2].
  * Readings of points the paper leaves open are listed at each function.
@@ -58,6 +60,9 @@ typedef struct {
     int32_t criterion;         /* depth M-step: 0 MIE (Eq. 10), 1 MLE (Eq. 9)    */
     int32_t pose_start;        /* mean-shift start: 0 densest of n_seeds samples */
                                /* and the previous pose, 1 best all-pixel score  */
+    int32_t residual_model;    /* density of rho (Eq. 4) and mu (Eq. 8): 0 Fisk  */
+                               /* (Eq. 5), 1 Gaussian flow error (or_gauss_logpdf)*/
+    int32_t pad;
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EDEGENERATE = -4 };
@@ -131,6 +136,18 @@ double or_fisk_logpdf(double x, double log_alpha, double beta)
 {
     double lx = log(x) - log_alpha;           /* log(x/alpha) */
     return log(beta) - log_alpha + (beta - 1.0) * lx - 2.0 * log1pexp(beta * lx);
+}
+
+/* The Gaussian residual model of the paper's ablations (Sec. 6, Fig. 8):
+ * an isotropic two-dimensional Gaussian flow error makes the squared EPE x
+ * exponential, density exp(-x/s)/s.  Reading: its mean s is tied to the Fisk
+ * scale law A(v) of Eq. 6 by equal medians, s ln 2 = alpha (the Fisk median
+ * is alpha), so the same a1, a2 parameterise both models and b1, b2 are
+ * unused. */
+double or_gauss_logpdf(double x, double log_alpha)
+{
+    double log_s = log_alpha - log(log(2.0));
+    return -x * exp(-log_s) - log_s;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -462,8 +479,13 @@ static or_emis emission(const or_frame_set *F, const or_params *p, const double 
     double m = p->lambda * p->lambda * vn2;               /* Eq. 8 argument */
     if (m < p->x_floor) m = p->x_floor;
     e.observed = 1;
-    e.logrho = or_fisk_logpdf(x2, log_alpha, beta);       /* Eq. 4 */
-    e.logmu = or_fisk_logpdf(m, log_alpha, beta);         /* Eq. 8 */
+    if (p->residual_model == 1) {
+        e.logrho = or_gauss_logpdf(x2, log_alpha);        /* Eq. 4, Gaussian model */
+        e.logmu = or_gauss_logpdf(m, log_alpha);          /* Eq. 8, same density */
+    } else {
+        e.logrho = or_fisk_logpdf(x2, log_alpha, beta);   /* Eq. 4 */
+        e.logmu = or_fisk_logpdf(m, log_alpha, beta);     /* Eq. 8 */
+    }
     double d = e.logmu - e.logrho;                        /* log(mu/rho) */
     e.r = 1.0 / (1.0 + exp(d));
     e.ell = -log1pexp(d);
@@ -1392,6 +1414,7 @@ static int params_ok(const or_params *p, int T, int H, int W, const double *K)
     if (!(p->sigma2_trans > 0) || !(p->sigma2_rot > 0) || !(p->beta_min > 0) || !(p->x_floor > 0)) return 0;
     if (p->criterion != 0 && p->criterion != 1) return 0;
     if (p->pose_start != 0 && p->pose_start != 1) return 0;
+    if (p->residual_model != 0 && p->residual_model != 1) return 0;
     return 1;
 }
 
