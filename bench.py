@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_sweep_indoor_hbm_traffic.md)
 SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
                         "write_bytes": 1249.0390625 * 1024 * 1.0}
-SWEEP_SOURCES_SHA = "50e8a0e4a8891cb3"
+SWEEP_SOURCES_SHA = "2874f55bd8b6a519"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU instructions: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz = 39.3 T lane-instructions/s (independent v_fma_f32 chains sustain
@@ -51,6 +51,8 @@ SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 EMISSION_VALU_OPS = 148                      # one emission evaluation of the sweep (160 VALU, 12 of them
                                              # transcendental)
+EMISSION_VALU_OPS_GAUSS = 127                # the same with the Gaussian residual model: 21 fewer (its
+                                             # d = (x - m) ln2 / alpha replaces beta, two logs, two softplus)
 
 
 def _sweep_traffic(workload):
@@ -93,7 +95,7 @@ def _allpixel_roofline(vo, torch, solver, w, spec, p_ap, out, reps=3):
     poses = out[0].cpu().numpy()
     M = _cumulative(poses)
     p_kde = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=p_ap.seed,
-                              criterion=p_ap.criterion, pose_start=0)
+                              criterion=p_ap.criterion, pose_start=0, residual_model=p_ap.residual_model)
     flows = torch.from_numpy(w["flows"]).cuda()
     ms = {0: 0.0, 1: 0.0}
     evals = 0
@@ -602,6 +604,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--criterion", default="mie", choices=["mie", "mle"],
                     help="depth M-step: maximum inlier (Eq. 10) or maximum likelihood (Eq. 9)")
+    ap.add_argument("--residual-model", default="fisk", choices=["fisk", "gauss"],
+                    help="density of rho and mu: Fisk (Eq. 5) or the Gaussian flow error of the ablations")
     ap.add_argument("--pose-start", default="kde", choices=["kde", "allpixel"],
                     help="mean-shift start: densest of 64 seeds, or every candidate scored over all pixels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -647,8 +651,9 @@ def main():
     flows = torch.from_numpy(w["flows"]).to("cuda:0")
     crit = 1 if args.criterion == "mle" else 0
     pstart = 1 if args.pose_start == "allpixel" else 0
+    rmodel = 1 if args.residual_model == "gauss" else 0
     p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit,
-                          pose_start=pstart)
+                          pose_start=pstart, residual_model=rmodel)
     solver = vo.Solver(T, H, W, spec.n_groups)
     # sweep widths for this shape (every width gives the same result)
     widths = solver.autotune(flows, w["K"], p)
@@ -686,7 +691,7 @@ def main():
     sweep_ms = ph["sweeps"] / max(launches, 1.0)
     alg_bytes = 8.0 * T * H * W + 8.0 * H * W
     achieved_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    alg_ops = 3.0 * T * H * W * EMISSION_VALU_OPS
+    alg_ops = 3.0 * T * H * W * (EMISSION_VALU_OPS_GAUSS if rmodel else EMISSION_VALU_OPS)
     achieved = alg_ops / (sweep_ms * 1e-3) / 1e12
 
     rot_err, tdir_err = _pose_error(out[0].cpu().numpy(), w["poses"])
@@ -712,8 +717,10 @@ def main():
         "config": {"workload": f"{args.workload}: T={T}, {W}x{H}, {spec.n_iters} EM iterations, "
                                f"{spec.n_groups} P3P groups/frame, seed {args.seed}"
                                + (", depth criterion MLE (Eq. 9)" if crit else "")
-                               + (", all-pixel mean-shift start" if pstart else ""),
+                               + (", all-pixel mean-shift start" if pstart else "")
+                               + (", Gaussian residual model" if rmodel else ""),
                    "criterion": args.criterion, "pose_start": args.pose_start,
+                   "residual_model": args.residual_model,
                    "sweep_threads": {"rows": widths[0], "cols": widths[1]},
                    "T": T, "H": H, "W": W, "n_iters": spec.n_iters, "n_pose_groups": spec.n_groups,
                    "parallelism": "single GPU, one window per step, enqueued back to back on one stream"},
@@ -723,7 +730,7 @@ def main():
         "concurrent": conc_line,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload) if not crit else None,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload) if not (crit or rmodel) else None,
                      "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms,
                      "hbm_view": {"alg_bytes_per_launch": alg_bytes, "achieved_GBs": achieved_gbs,
                                   "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
@@ -742,7 +749,7 @@ def main():
     elif not args.no_cpu_baseline:
         import oracle
         kw = dict(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=args.seed, criterion=crit,
-                  pose_start=pstart)
+                  pose_start=pstart, residual_model=rmodel)
         c0 = time.perf_counter()
         st, *_ = oracle.window(w["flows"], w["K"], oracle.params(**kw))
         c1 = time.perf_counter()

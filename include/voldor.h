@@ -73,9 +73,17 @@ typedef struct {
                                /* the previous pose and the first n_seeds samples;    */
                                /* 1 the candidate (previous pose, then every sample)  */
                                /* of highest sum over all pixels of W_t ell_t        */
+    int32_t residual_model;    /* density of rho (Eq. 4) and mu (Eq. 8):             */
+                               /* VOLDOR_RESIDUAL_FISK (Eq. 5, scale and shape by     */
+                               /* Eq. 6-7) or VOLDOR_RESIDUAL_GAUSS, the Gaussian      */
+                               /* model of the paper's ablations (Sec. 6, Fig. 8-9):  */
+                               /* squared EPE exponential with mean A(v) / ln 2, the  */
+                               /* Fisk's median; b1, b2, beta_min unused              */
+    int32_t pad;               /* 0                                                   */
 } voldor_params;
 
 enum { VOLDOR_CRITERION_MIE = 0, VOLDOR_CRITERION_MLE = 1 };
+enum { VOLDOR_RESIDUAL_FISK = 0, VOLDOR_RESIDUAL_GAUSS = 1 };
 
 /* Fill *p with the defaults above (n_iters 3, 4 sweeps, S 256, 64 seeds,
  * 100 mean-shift iterations, tol 1e-5, 512 hypotheses, 16384 eval pixels,

@@ -38,10 +38,12 @@ class Params(C.Structure):
         ("sigma2_trans", C.c_double), ("sigma2_rot", C.c_double), ("beta_min", C.c_double),
         ("x_floor", C.c_double), ("depth_lo", C.c_double), ("depth_hi", C.c_double),
         ("seed", C.c_uint64), ("criterion", C.c_int32), ("pose_start", C.c_int32),
+        ("residual_model", C.c_int32), ("pad", C.c_int32),
     ]
 
 
 CRITERION_MIE, CRITERION_MLE = 0, 1
+RESIDUAL_FISK, RESIDUAL_GAUSS = 0, 1
 
 
 class WindowDesc(C.Structure):

@@ -36,6 +36,7 @@ bool params_ok(const voldor_params *p)
     if (p->depth_lo > 0 && p->depth_hi > 0 && !(p->depth_hi > p->depth_lo)) return false;
     if (p->criterion != VOLDOR_CRITERION_MIE && p->criterion != VOLDOR_CRITERION_MLE) return false;
     if (p->pose_start != 0 && p->pose_start != 1) return false;
+    if (p->residual_model != VOLDOR_RESIDUAL_FISK && p->residual_model != VOLDOR_RESIDUAL_GAUSS) return false;
     return true;
 }
 
@@ -85,7 +86,7 @@ EmisParams emis(const double *K, const voldor_params *p)
     e.lam2 = (float)(p->lambda * p->lambda);
     e.beta_min = (float)p->beta_min;
     e.x_floor = (float)p->x_floor;
-    e.pad = 0.0f;
+    e.model = p->residual_model;
     e.ifx = (float)(1.0 / K[0]);
     e.ify = (float)(1.0 / K[1]);
     e.pad2 = e.pad3 = 0.0f;
@@ -215,6 +216,8 @@ void voldor_params_default(voldor_params *p)
     p->seed = 0;
     p->criterion = VOLDOR_CRITERION_MIE;
     p->pose_start = 0;
+    p->residual_model = VOLDOR_RESIDUAL_FISK;
+    p->pad = 0;
 }
 
 const char *voldor_status_str(int status)

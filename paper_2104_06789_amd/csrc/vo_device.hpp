@@ -55,7 +55,8 @@ struct FrameF {
 struct EmisParams {
     float fx, fy, cx, cy;
     float log_a1, a2, b1, b2;
-    float lam2, beta_min, x_floor, pad;
+    float lam2, beta_min, x_floor;
+    int model;                    // residual model: 0 Fisk (Eq. 5), 1 Gaussian flow error
     float ifx, ify, pad2, pad3;   // 1/fx, 1/fy
 };
 
@@ -120,9 +121,17 @@ struct Emis {
 };
 
 // Emission given the residual (rx, ry) = xi - v and the observed flow v:
-// d = log(mu / rho) with the Fisk densities of Eq. 4 and Eq. 8 sharing
-// log(alpha) = log a1 + a2 |v| and beta = max(b1 |v| + b2, beta_min);
-// the common log(beta) - log(alpha) term cancels in the ratio.
+// d = log(mu / rho) with the densities of Eq. 4 and Eq. 8 sharing
+// log(alpha) = log a1 + a2 |v|.
+// MODEL 0, Fisk (Eq. 5) with beta = max(b1 |v| + b2, beta_min): the common
+// log(beta) - log(alpha) term cancels in the ratio.
+// MODEL 1, Gaussian flow error: the squared EPE is exponential with mean
+// s = alpha / ln 2 (the Fisk's median alpha), so d = (x - m) / s for the
+// squared residual x and the Eq. 8 argument m = lambda^2 |v|^2.
+constexpr float kLn2F = 0.69314718055994531f;
+constexpr float kLogLn2F = -0.36651292058166432f;   // log(ln 2)
+
+template <int MODEL = 0>
 __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, float vy,
                                                   const EmisParams &e)
 {
@@ -131,17 +140,23 @@ __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, f
     const float vn2 = fmaf(vx, vx, vy * vy);
     const float vn = __builtin_amdgcn_sqrtf(vn2);
     const float la = fmaf(e.a2, vn, e.log_a1);
-    const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-    const float lx = fast_log(x2);
-    const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
-    const float z1 = beta * (lx - la), z2 = beta * (lm - la);
-    return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+    if constexpr (MODEL == 1) {
+        const float m = fmaxf(e.lam2 * vn2, e.x_floor);
+        return (x2 - m) * (kLn2F * fast_exp(-la));
+    } else {
+        const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+        const float lx = fast_log(x2);
+        const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+        const float z1 = beta * (lx - la), z2 = beta * (lm - la);
+        return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+    }
 }
 
-// The same d = log(mu / rho), and log mu itself (Eq. 8: the Fisk density at
-// squared EPE lambda^2 |v|^2, log(beta) - log(alpha) included), for the
+// The same d = log(mu / rho), and log mu itself (Eq. 8: the model's density
+// at squared EPE lambda^2 |v|^2, normalisation included), for the
 // maximum-likelihood depth criterion (Eq. 9), whose per-frame term is
 // q log rho + (1 - q) log mu = log mu - q d.
+template <int MODEL = 0>
 __device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, float vy, const EmisParams &e,
                                               float &lmu)
 {
@@ -149,12 +164,19 @@ __device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, floa
     const float vn2 = fmaf(vx, vx, vy * vy);
     const float vn = __builtin_amdgcn_sqrtf(vn2);
     const float la = fmaf(e.a2, vn, e.log_a1);
-    const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-    const float lx = fast_log(x2);
-    const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
-    const float z1 = beta * (lx - la), z2 = beta * (lm - la);
-    lmu = (fast_log(beta) - la) + (beta - 1.0f) * (lm - la) - 2.0f * softplus(z2);
-    return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+    if constexpr (MODEL == 1) {
+        const float m = fmaxf(e.lam2 * vn2, e.x_floor);
+        const float is = kLn2F * fast_exp(-la);   // 1 / s
+        lmu = fmaf(-m, is, kLogLn2F - la);         // -m / s - log s
+        return (x2 - m) * is;
+    } else {
+        const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+        const float lx = fast_log(x2);
+        const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+        const float z1 = beta * (lx - la), z2 = beta * (lm - la);
+        lmu = (fast_log(beta) - la) + (beta - 1.0f) * (lm - la) - 2.0f * softplus(z2);
+        return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+    }
 }
 
 __device__ __forceinline__ Emis emis_from_d(float d)

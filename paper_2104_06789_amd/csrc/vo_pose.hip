@@ -674,7 +674,9 @@ struct CandScoreArgs {
     int T, H, W, t;
 };
 
-// grid (kCandTiles pixel ranges, candidate chunks of kCandChunk)
+// grid (kCandTiles pixel ranges, candidate chunks of kCandChunk); MODEL 0 Fisk
+// residual model (Eq. 5), 1 Gaussian flow error
+template <int MODEL>
 __global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
@@ -726,10 +728,16 @@ __global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
             const float vn2 = fmaf(fu, fu, fv * fv);
             const float vn = __builtin_amdgcn_sqrtf(vn2);
             la[k] = fmaf(e.a2, vn, e.log_a1);
-            beta[k] = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-            const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
-            // d = log(mu/rho) = k0 - (beta - 1) log x + 2 softplus(beta (log x - log alpha))
-            k0[k] = (beta[k] - 1.0f) * lm - 2.0f * softplus(beta[k] * (lm - la[k]));
+            if constexpr (MODEL == 1) {
+                // d = log(mu/rho) = (x - m) / s: k0 = m, beta = 1 / s = ln 2 / alpha
+                k0[k] = fmaxf(e.lam2 * vn2, e.x_floor);
+                beta[k] = kLn2F * fast_exp(-la[k]);
+            } else {
+                beta[k] = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
+                const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+                // d = log(mu/rho) = k0 - (beta - 1) log x + 2 softplus(beta (log x - log alpha))
+                k0[k] = (beta[k] - 1.0f) * lm - 2.0f * softplus(beta[k] * (lm - la[k]));
+            }
         }
         for (int h0 = 0; h0 < kCandChunk; h0 += 8) {
             float acc[8];
@@ -745,8 +753,13 @@ __global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
                     if (ok[k] && displacement(f, xh[k], yh[k], th[k], e.fx, e.fy, dx1, dy1)) {
                         const float rx = (dx1 - dx0[k]) - vu[k], ry = (dy1 - dy0[k]) - vv[k];
                         const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
-                        const float lx = fast_log(x2);
-                        const float d = k0[k] - (beta[k] - 1.0f) * lx + 2.0f * softplus(beta[k] * (lx - la[k]));
+                        float d;
+                        if constexpr (MODEL == 1) {
+                            d = (x2 - k0[k]) * beta[k];
+                        } else {
+                            const float lx = fast_log(x2);
+                            d = k0[k] - (beta[k] - 1.0f) * lx + 2.0f * softplus(beta[k] * (lx - la[k]));
+                        }
                         ell = emis_from_d(d).ell;
                     }
                     acc[u] = fmaf(w[k], ell, acc[u]);
@@ -904,8 +917,11 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
         cs.W = d.W;
         cs.t = t;
         const int ncand = 1 + ns;   // upper bound; chunks past the count exit
-        hipLaunchKernelGGL(k_cand_score, dim3(kCandTiles, (ncand + kCandChunk - 1) / kCandChunk), dim3(kCandThreads),
-                           0, s, cs);
+        const dim3 cgrid(kCandTiles, (ncand + kCandChunk - 1) / kCandChunk);
+        if (e.model)
+            hipLaunchKernelGGL(k_cand_score<1>, cgrid, dim3(kCandThreads), 0, s, cs);
+        else
+            hipLaunchKernelGGL(k_cand_score<0>, cgrid, dim3(kCandThreads), 0, s, cs);
         hipLaunchKernelGGL(k_cand_sum, dim3((ncand + 3) / 4), dim3(256), 0, s, c->cand_part, c->cand_slot,
                            c->cand_n, c->cand_score, c->status);
         hipLaunchKernelGGL(k_cand_pick, dim3(1), dim3(1024), 0, s, c->cand_score, c->cand_slot, c->cand_n,

@@ -57,27 +57,11 @@ __device__ __forceinline__ void chain_xy(int dir, int H, int W, int c, int k, in
     y = (dir & 1) ? (dir == 1 ? k : H - 1 - k) : c;
 }
 
-// log(mu/rho) of depth th at pixel (x, y) for frame t; false if missing
-__device__ __forceinline__ bool item_log_odds(const FrameF *fr, const float2 *__restrict__ flows,
-                                              int H, int W, const EmisParams &e, int x, int y,
-                                              float xh, float yh, float th, int t, float &d)
-{
-    if (!(th > 0.0f)) return false;
-    float dx0 = 0.0f, dy0 = 0.0f, dx1, dy1;
-    if (t > 1 && !displacement(fr[t - 1], xh, yh, th, e.fx, e.fy, dx0, dy0)) return false;
-    if (!displacement(fr[t], xh, yh, th, e.fx, e.fy, dx1, dy1)) return false;
-    float vu, vv;
-    if (!sample_flow(flows + (size_t)(t - 1) * H * W, H, W, (float)x + dx0, (float)y + dy0, vu, vv))
-        return false;
-    d = log_mu_over_rho((dx1 - dx0) - vu, (dy1 - dy0) - vv, vu, vv, e);
-    return true;
-}
-
 // Depth score at chain position k, frames in chunks of three so that the flow
 // gathers of a chunk are in flight together: MIE (Eq. 10) sum_t q_t ell_t(th),
 // a missing frame log 1/2; MLE (Eq. 9) sum_t log mu_t - q_t d_t, a missing
 // frame 0
-template <int CRIT>
+template <int CRIT, int MODEL>
 __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
                                              int T, int H, int W, const EmisParams &e, int x, int y,
                                              float xh, float yh, float th, const float *q, int L,
@@ -131,7 +115,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
                     if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
                         const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
                         const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
-                        const float dd = log_mu_over_rho((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                        const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
                         ell = emis_from_d(dd).ell;
                     }
                 }
@@ -143,7 +127,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
                         const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
                         const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
                         float lmu;
-                        const float dd = log_mu_and_d((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
+                        const float dd = log_mu_and_d<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
                         s += fmaf(-q[(t - 1) * L + k], dd, lmu);
                     }
                 }
@@ -159,7 +143,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
 // log(mu/rho) for a batch of B independent (pixel, frame, depth) items; the
 // flow gathers of the whole batch are issued before any of them is used.
 // ok[b] false: missing observation (or inactive item).  MU: log mu as well.
-template <int B, bool MU = false>
+template <int B, int MODEL, bool MU = false>
 __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *__restrict__ flows, int H,
                                                int W, const EmisParams &e, const int *x, const int *y,
                                                const float *th, const int *t, const bool *act, float *d,
@@ -198,10 +182,10 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         const float vv = (1.0f - ay[b]) * fmaf(ax[b], Bv.y - A.y, A.y) + ay[b] * fmaf(ax[b], Dv.y - Cv.y, Cv.y);
         if constexpr (MU) {
             float lm = 0.0f;
-            d[b] = ok[b] ? log_mu_and_d((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e, lm) : 0.0f;
+            d[b] = ok[b] ? log_mu_and_d<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e, lm) : 0.0f;
             lmu[b] = ok[b] ? lm : 0.0f;
         } else {
-            d[b] = ok[b] ? log_mu_over_rho((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+            d[b] = ok[b] ? log_mu_over_rho<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
         }
     }
 }
@@ -271,10 +255,11 @@ __host__ __device__ inline int sweep_region2_words(int T, int L, int nt = kSweep
 }
 
 // CRIT 0: maximum-inlier depth criterion (Eq. 10); 1: maximum likelihood (Eq. 9).
+// MODEL 0: Fisk residual model (Eq. 5); 1: Gaussian flow error.
 // NT threads per chain (256, 512 or 1024): every item is the same function of
 // its inputs whatever NT is, so all widths give the same result bit for bit;
 // NT only sets how a chain's work is spread (and how many chains fit a CU)
-template <int CRIT, int NT>
+template <int CRIT, int NT, int MODEL>
 __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
@@ -350,7 +335,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             while (k >= L) { k -= L; ++t; }
         }
         if constexpr (CRIT == 0) {
-            batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+            batch_log_odds<4, MODEL>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
@@ -366,7 +351,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             }
         } else {
             float lm[4];
-            batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
@@ -492,7 +477,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             while (k >= L) { k -= L; ++t; }
         }
         if constexpr (CRIT == 0) {
-            batch_log_odds<4>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
+            batch_log_odds<4, MODEL>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
@@ -501,7 +486,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
         } else {
             // the sample's whole term log mu - q d (0 where missing)
             float lm[4];
-            batch_log_odds<4, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
@@ -562,7 +547,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
-                const float s = chain_score<CRIT>(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
+                const float s = chain_score<CRIT, MODEL>(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
             }
             if (!w) atomicMin(&first[sl], p);
@@ -696,18 +681,23 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                     const float vu = (1.0f - ay[u]) * fmaf(ax[u], B.x - A.x, A.x) + ay[u] * fmaf(ax[u], D.x - Cc.x, Cc.x);
                     const float vv = (1.0f - ay[u]) * fmaf(ax[u], B.y - A.y, A.y) + ay[u] * fmaf(ax[u], D.y - Cc.y, Cc.y);
                     const float rx = (dx1[u] - bx[u]) - vu, ry = (dy1[u] - by[u]) - vv;
-                    const float d = log_mu_over_rho(rx, ry, vu, vv, a.e);
+                    const float d = a.e.model ? log_mu_over_rho<1>(rx, ry, vu, vv, a.e)
+                                              : log_mu_over_rho<0>(rx, ry, vu, vv, a.e);
                     const Emis m = emis_from_d(d);
                     r = m.r;
                     ell = m.ell;
                     if (a.logrho || a.logmu || a.ll_part) {
                         const float vn = __builtin_amdgcn_sqrtf(fmaf(vu, vu, vv * vv));
                         const float la = fmaf(a.e.a2, vn, a.e.log_a1);
-                        const float beta = fmaxf(fmaf(a.e.b1, vn, a.e.b2), a.e.beta_min);
                         const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), a.e.x_floor), 1e30f);
-                        const float s1 = fast_log(x2) - la;
-                        const float lb = fast_log(beta) - la;
-                        lr = lb + (beta - 1.0f) * s1 - 2.0f * softplus(beta * s1);
+                        if (a.e.model) {   // exponential with mean s = alpha / ln 2
+                            lr = fmaf(-x2, kLn2F * fast_exp(-la), kLogLn2F - la);
+                        } else {           // Fisk (Eq. 5)
+                            const float beta = fmaxf(fmaf(a.e.b1, vn, a.e.b2), a.e.beta_min);
+                            const float s1 = fast_log(x2) - la;
+                            const float lb = fast_log(beta) - la;
+                            lr = lb + (beta - 1.0f) * s1 - 2.0f * softplus(beta * s1);
+                        }
                         lm = lr + d;
                         const double w = r;
                         const double term = w * (double)lr + (1.0 - w) * (double)lm;
@@ -787,14 +777,14 @@ size_t sweep_lds_bytes(int T, int L, int criterion, int nt)
            sizeof(float);
 }
 
-template <int CRIT, int NT>
+template <int CRIT, int NT, int MODEL>
 static int launch_sweep_nt(const SweepArgs &a, int nchain, size_t lds, hipStream_t s)
 {
     if (lds > 65536 &&
-        hipFuncSetAttribute((const void *)k_sweep<CRIT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess)
+        hipFuncSetAttribute((const void *)k_sweep<CRIT, NT, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
         return VOLDOR_EDEVICE;
-    hipLaunchKernelGGL((k_sweep<CRIT, NT>), dim3(nchain), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_sweep<CRIT, NT, MODEL>), dim3(nchain), dim3(NT), lds, s, a);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
@@ -823,13 +813,19 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.gamma = gamma;
     a.seed = seed;
     a.gsweep = gsweep;
-    switch (nt * 2 + (criterion ? 1 : 0)) {
-    case 512: return launch_sweep_nt<0, 256>(a, nchain, lds, s);
-    case 513: return launch_sweep_nt<1, 256>(a, nchain, lds, s);
-    case 1024: return launch_sweep_nt<0, 512>(a, nchain, lds, s);
-    case 1025: return launch_sweep_nt<1, 512>(a, nchain, lds, s);
-    case 2048: return launch_sweep_nt<0, 1024>(a, nchain, lds, s);
-    case 2049: return launch_sweep_nt<1, 1024>(a, nchain, lds, s);
+    switch ((nt * 2 + (criterion ? 1 : 0)) * 2 + (e.model ? 1 : 0)) {
+    case 1024: return launch_sweep_nt<0, 256, 0>(a, nchain, lds, s);
+    case 1025: return launch_sweep_nt<0, 256, 1>(a, nchain, lds, s);
+    case 1026: return launch_sweep_nt<1, 256, 0>(a, nchain, lds, s);
+    case 1027: return launch_sweep_nt<1, 256, 1>(a, nchain, lds, s);
+    case 2048: return launch_sweep_nt<0, 512, 0>(a, nchain, lds, s);
+    case 2049: return launch_sweep_nt<0, 512, 1>(a, nchain, lds, s);
+    case 2050: return launch_sweep_nt<1, 512, 0>(a, nchain, lds, s);
+    case 2051: return launch_sweep_nt<1, 512, 1>(a, nchain, lds, s);
+    case 4096: return launch_sweep_nt<0, 1024, 0>(a, nchain, lds, s);
+    case 4097: return launch_sweep_nt<0, 1024, 1>(a, nchain, lds, s);
+    case 4098: return launch_sweep_nt<1, 1024, 0>(a, nchain, lds, s);
+    case 4099: return launch_sweep_nt<1, 1024, 1>(a, nchain, lds, s);
     default: return VOLDOR_EINVAL;
     }
 }

@@ -113,18 +113,20 @@ def test_abi_struct_layout_matches_binding(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "voldor.h"\n'
         "int main(void) {\n"
-        '  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(voldor_window_desc),\n'
+        '  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(voldor_window_desc),\n'
         "    offsetof(voldor_window_desc, flows), offsetof(voldor_window_desc, T),\n"
         "    offsetof(voldor_window_desc, K), offsetof(voldor_window_desc, poses),\n"
         "    offsetof(voldor_window_desc, loglik), offsetof(voldor_window_desc, init_depth),\n"
         "    offsetof(voldor_window_desc, choice), sizeof(voldor_params),\n"
         "    offsetof(voldor_params, ms_tol), offsetof(voldor_params, depth_hi),\n"
-        "    offsetof(voldor_params, seed));\n  return 0;\n}\n")
+        "    offsetof(voldor_params, seed), offsetof(voldor_params, criterion),\n"
+        "    offsetof(voldor_params, residual_model));\n  return 0;\n}\n")
     exe = tmp_path / "layout"
     import subprocess
     subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     D, P = vo.WindowDesc, vo.Params
     want = [C.sizeof(D), D.flows.offset, D.T.offset, D.K.offset, D.poses.offset, D.loglik.offset,
-            D.init_depth.offset, D.choice.offset, C.sizeof(P), P.ms_tol.offset, P.depth_hi.offset, P.seed.offset]
+            D.init_depth.offset, D.choice.offset, C.sizeof(P), P.ms_tol.offset, P.depth_hi.offset, P.seed.offset,
+            P.criterion.offset, P.residual_model.offset]
     assert got == want
