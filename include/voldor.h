@@ -209,7 +209,8 @@ int voldor_residual_fit(const float *X, const float *G, int64_t n, int nbins, do
                         int min_count, double *laws, double *bins, void *stream);
 
 /* The binning pass of voldor_residual_fit alone, enqueued without waiting:
- *   work  device double[voldor_residual_workspace(n, nbins)]: scratch
+ *   work  device double[voldor_residual_workspace(n, nbins)]: scratch (the query
+ *         returns VOLDOR_EINVAL, negative, for n < 1 or nbins outside [2, 256])
  *   bins  device double [nbins][4]: count, sum |X|, sum log x, sum (log x)^2 */
 int64_t voldor_residual_workspace(int64_t n, int nbins);
 int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
