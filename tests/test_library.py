@@ -54,6 +54,7 @@ def test_params_default_and_status_strings(vo):
     assert p.struct_size == C.sizeof(vo.Params)
     assert p.n_iters == 3 and p.sweeps_per_iter == 4 and p.gamma == 0.9
     assert p.sigma2_trans == 0.1 and p.sigma2_rot == 0.004
+    assert p.criterion == vo.CRITERION_MIE and p.pose_start == 0 and p.residual_model == vo.RESIDUAL_FISK
     assert vo.status_str(0) == "ok"
     assert vo.status_str(-4) == "degenerate bootstrap"
     assert vo.status_str(12345) == "unknown status"
@@ -130,3 +131,13 @@ def test_abi_struct_layout_matches_binding(tmp_path):
             D.init_depth.offset, D.choice.offset, C.sizeof(P), P.ms_tol.offset, P.depth_hi.offset, P.seed.offset,
             P.criterion.offset, P.residual_model.offset]
     assert got == want
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU's share is what bench.py measures; --gpus N > 1 exits with a message
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
