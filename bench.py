@@ -70,6 +70,21 @@ def _sweep_traffic(workload):
     return SWEEP_TRAFFIC_INDOOR["fetch_bytes"] + SWEEP_TRAFFIC_INDOOR["write_bytes"]
 
 
+# HBM traffic of one residual-binning pass (k_resid_bins + k_resid_reduce) on the
+# indoor window flows, 40 bins: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+# scaled by the copy calibration above; valid while vo_resfit.hip hashes to
+# RESFIT_SOURCE_SHA (profile: profiles/k_resid_bins_indoor_hbm_traffic.md)
+RESFIT_TRAFFIC = ((14454.046875 + 1140.5) * 1.99980 + 1125.0 + 1.25) * 1024
+RESFIT_SOURCE_SHA = "40f42a8ae96ba6f1"
+
+
+def _resfit_traffic():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2104_06789_amd", "csrc", "vo_resfit.hip"), "rb") as fh:
+        ok = hashlib.sha256(fh.read()).hexdigest()[:16] == RESFIT_SOURCE_SHA
+    return RESFIT_TRAFFIC if ok else None
+
+
 CAND_EVAL_VALU_OPS = 46    # one (candidate, pixel) evaluation of k_cand_score: 1484 of the 1676 VALU
                            # instructions of its 32-evaluation candidate loop are not transcendental
 
@@ -415,9 +430,18 @@ def run_resfit(args):
         "generator_law_of_squared_epe": {"A": f"({spec.noise_c1} |v| + {spec.noise_c0})^2",
                                          "B": spec.noise_beta / 2},
         "roofline": {"bound": "hbm", "kernel": "k_resid_bins + k_resid_reduce", "achieved": gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": _resfit_traffic(),
                      "alg_bytes_per_launch": alg_bytes, "launch_ms": launch_ms},
     }
+    if not args.no_cpu_baseline:
+        from oracle import resfit as oracle_resfit
+        c0 = time.perf_counter()
+        ref = oracle_resfit.bin_stats(w["flows"].reshape(-1, 2), g["flows"].reshape(-1, 2), nb, v_max)
+        oracle_resfit.fit(ref, min_count=64)
+        c1 = time.perf_counter()
+        line["cpu_baseline"] = {"value": n / (c1 - c0), "unit": "items/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the whole workload ({n} items): FP64 binning and fit with numpy, "
+                                          f"{c1 - c0:.2f} s"}
     print(json.dumps(line))
 
 

@@ -210,21 +210,34 @@ __global__ void __launch_bounds__(kFitThreads) k_resid_bins(const float2 *X, con
     }
 }
 
-// one workgroup per (bin, statistic): thread t adds the partials of
-// workgroups t, t + 256, ... in order, then a fixed tree over the threads
-__global__ void __launch_bounds__(256) k_resid_reduce(const double *part, int nblocks, int nbins, double *out)
+// Sum of the workgroup partials, one workgroup per 8 consecutive (bin,
+// statistic) columns, so that the 8 threads reading a partial row take one
+// whole 64-byte line.  Thread t takes column c0 + (t & 7) of the rows
+// g = t / 8, g + 128, g + 256, ... into two running sums (rows g + 256 k and
+// g + 128 + 256 k, so that two loads are in flight), added in a fixed order;
+// then a fixed tree over the 128 row groups.
+constexpr int kRedThreads = 1024;
+constexpr int kRedGroups = kRedThreads / 8;
+__global__ void __launch_bounds__(kRedThreads) k_resid_reduce(const double *part, int nblocks, int ncol, double *out)
 {
-    __shared__ double red[256];
-    const int i = blockIdx.x, t = threadIdx.x;
-    double s = 0.0;
-    for (int b = t; b < nblocks; b += 256) s += part[(size_t)b * nbins * 4 + i];
-    red[t] = s;
+    __shared__ double red[kRedThreads];
+    const int t = threadIdx.x, c = blockIdx.x * 8 + (t & 7);
+    double s0 = 0.0, s1 = 0.0;
+    if (c < ncol) {
+        int b = t >> 3;
+        for (; b + kRedGroups < nblocks; b += 2 * kRedGroups) {
+            s0 += part[(size_t)b * ncol + c];
+            s1 += part[(size_t)(b + kRedGroups) * ncol + c];
+        }
+        if (b < nblocks) s0 += part[(size_t)b * ncol + c];
+    }
+    red[t] = s0 + s1;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kRedThreads / 2; h >= 8; h >>= 1) {   // h is a multiple of 8: t and t + h share a column
         if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
-    if (t == 0) out[i] = red[0];
+    if (t < 8 && c < ncol) out[c] = red[t];
 }
 
 }  // namespace vo
@@ -260,7 +273,8 @@ int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, d
     else if (ns <= 8) FIT_LAUNCH(8);
     else FIT_LAUNCH(16);
 #undef FIT_LAUNCH
-    hipLaunchKernelGGL(k_resid_reduce, dim3(nbins * 4), dim3(256), 0, s, work, blocks, nbins, bins);
+    hipLaunchKernelGGL(k_resid_reduce, dim3((nbins * 4 + 7) / 8), dim3(kRedThreads), 0, s, work, blocks, nbins * 4,
+                       bins);
     return hipGetLastError() == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
 
