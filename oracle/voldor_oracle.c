@@ -833,6 +833,43 @@ static void triangle_align(const double *P, const double *Q, double *R, double *
     for (int k = 0; k < 3; ++k) t[k] = Q[k] - rp[k];
 }
 
+/* Newton's method on the three law-of-cosines equations of P3P,
+ *   s2^2 + s3^2 - 2 s2 s3 ca = a2,  s1^2 + s3^2 - 2 s1 s3 cb = b2,
+ *   s1^2 + s2^2 - 2 s1 s2 cg = c2,
+ * from the distances one root of the quartic gives.  Where two solutions
+ * share (nearly) one value of v the quartic has a (near) double root, which
+ * a root finder resolves only to about half the digits; the distances are
+ * then brought to the solution of the equations themselves.  A step is kept
+ * only while it lowers the residual. */
+static void p3p_refine(double *s, double a2, double b2, double c2, double ca, double cb, double cg)
+{
+    double F[3], r0 = 0;
+    for (int it = 0; it < 8; ++it) {
+        F[0] = s[1] * s[1] + s[2] * s[2] - 2 * s[1] * s[2] * ca - a2;
+        F[1] = s[0] * s[0] + s[2] * s[2] - 2 * s[0] * s[2] * cb - b2;
+        F[2] = s[0] * s[0] + s[1] * s[1] - 2 * s[0] * s[1] * cg - c2;
+        double r = fabs(F[0]) + fabs(F[1]) + fabs(F[2]);
+        if (it == 0) r0 = r;
+        if (r == 0) return;
+        double J[9] = {0, 2 * (s[1] - s[2] * ca), 2 * (s[2] - s[1] * ca),
+                       2 * (s[0] - s[2] * cb), 0, 2 * (s[2] - s[0] * cb),
+                       2 * (s[0] - s[1] * cg), 2 * (s[1] - s[0] * cg), 0};
+        double mF[3] = {-F[0], -F[1], -F[2]}, d[3];
+        if (!solve3(J, mF, d)) return;
+        double sn[3] = {s[0] + d[0], s[1] + d[1], s[2] + d[2]};
+        double G0 = sn[1] * sn[1] + sn[2] * sn[2] - 2 * sn[1] * sn[2] * ca - a2;
+        double G1 = sn[0] * sn[0] + sn[2] * sn[2] - 2 * sn[0] * sn[2] * cb - b2;
+        double G2 = sn[0] * sn[0] + sn[1] * sn[1] - 2 * sn[0] * sn[1] * cg - c2;
+        double rn = fabs(G0) + fabs(G1) + fabs(G2);
+        if (!(rn < r) || !(sn[0] > 0 && sn[1] > 0 && sn[2] > 0)) return;
+        s[0] = sn[0];
+        s[1] = sn[1];
+        s[2] = sn[2];
+        if (fabs(d[0]) + fabs(d[1]) + fabs(d[2]) <= 1e-16 * (s[0] + s[1] + s[2])) return;
+    }
+    (void)r0;
+}
+
 int or_p3p(const double *Pw, const double *f_in, double *Rs, double *ts)
 {
     double f[9];
@@ -873,7 +910,11 @@ int or_p3p(const double *Pw, const double *f_in, double *Rs, double *ts)
         if (!(v > 0) || fabs(D) < 1e-14 * b2 || !(Q > 0)) continue;
         double u = poly_eval(Np, 2, v) / D;
         if (!(u > 0)) continue;
-        double s1 = sqrt(b2 / Q), s2 = u * s1, s3 = v * s1;
+        double sd[3] = {sqrt(b2 / Q), 0, 0};
+        sd[1] = u * sd[0];
+        sd[2] = v * sd[0];
+        p3p_refine(sd, a2, b2, c2, ca, cb, cg);
+        double s1 = sd[0], s2 = sd[1], s3 = sd[2];
         double Qc[9];
         for (int k = 0; k < 3; ++k) { Qc[k] = s1 * f[k]; Qc[3 + k] = s2 * f[3 + k]; Qc[6 + k] = s3 * f[6 + k]; }
         double R[9], t[3];
@@ -1381,7 +1422,7 @@ static int depth_from_T1(const float *X1, int H, int W, const double *K, const o
 }
 
 /* The bootstrap with T_1 given instead of estimated: the paper's alternative
- * for overlapping consecutive batches (Sec. 5.4), T_1 from the previous
+ * for overlapping consecutive batches (Sec. 5.3), T_1 from the previous
  * window's estimate.  Its translation is rescaled to unit length (the gauge);
  * the depth follows by triangulation as above.  A zero translation is
  * degenerate. */
@@ -1573,7 +1614,7 @@ int or_window(const float *flows, int T, int H, int W, const double *K, const or
                        diag_out, NULL, NULL);
 }
 
-/* One window whose T_1 is given (overlapping consecutive batches, Sec. 5.4). */
+/* One window whose T_1 is given (overlapping consecutive batches, Sec. 5.3). */
 int or_window_seeded(const float *flows, int T, int H, int W, const double *K, const or_params *p,
                      const double *T1, double *poses_out, double *depth_out, double *rig_out,
                      double *loglik_out, double *diag_out)

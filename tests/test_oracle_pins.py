@@ -377,7 +377,7 @@ def test_sym_eig_and_svd():
     A = rng.normal(size=(3, 3))
     U, S, V = oracle.svd3(A)
     assert np.allclose(S, np.linalg.svd(A, compute_uv=False), atol=1e-10)
-    assert np.allclose(U[:, :2] * S[:2] @ V[:, :2].T + S[2] * np.outer(U[:, 2], V[:, 2]) * np.sign(np.linalg.det(A)), A, atol=1e-9) or True
+    assert np.allclose(U[:, :2] * S[:2] @ V[:, :2].T + S[2] * np.outer(U[:, 2], V[:, 2]) * np.sign(np.linalg.det(A)), A, atol=1e-9)
     assert abs(np.linalg.det(U) - 1) < 1e-10 and abs(np.linalg.det(V) - 1) < 1e-10
     E = U @ np.diag([1.3, 0.7, 0]) @ V.T                   # rank 2 round trip
     U2, S2, V2 = oracle.svd3(E)
@@ -431,13 +431,15 @@ def test_p3p_recovers_known_poses():
         sols = oracle.p3p(Pw, f)
         assert len(sols) <= 4
         best = min((np.abs(Rs - R).max() + np.abs(ts - t).max() for Rs, ts in sols), default=np.inf)
-        hits += best < 1e-7
+        hits += best < 1e-9
         for Rs, ts in sols:                              # every root satisfies the bearings
             Qs = Pw @ Rs.T + ts
             Qs /= np.linalg.norm(Qs, axis=1, keepdims=True)
             assert np.allclose(np.abs(np.sum(Qs * f, axis=1)), 1, atol=1e-7)
             assert abs(np.linalg.det(Rs) - 1) < 1e-9
-    assert hits >= 297      # near-degenerate draws may lose precision
+    # every draw, near-degenerate ones included: the roots are refined on the
+    # law-of-cosines equations themselves
+    assert hits == 300
 
 
 # ---------------------------------------------------------------- mean-shift (Eq. 18-19)
