@@ -94,6 +94,7 @@ def lib():
             "or_window_init": (C.c_int, [f, i, i, i, d, P, d, d, d, d, d, d, d, C.POINTER(C.c_int)]),
             "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
             "or_null_vector_8x9": (None, [d, d]),
+            "or_set_f32_range": (None, [i]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -200,6 +201,19 @@ def cumulative(rel):
         Rm, tm = M[-1][:9].reshape(3, 3), M[-1][9:]
         M.append(np.concatenate([(R @ Rm).ravel(), R @ tm + t]))
     return np.array(M)
+
+
+class f32_range:
+    """Context: the posterior r below the smallest normal FP32 number is 0
+    inside it (a test hook of the oracle; see or_set_f32_range), so that the
+    depth M-step's argmax is taken with the posterior in FP32's range."""
+
+    def __enter__(self):
+        lib().or_set_f32_range(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_set_f32_range(0)
 
 
 def emission_map(theta, flows, K, p, M):
@@ -382,7 +396,7 @@ def window_starts(N, T, stride):
 
 
 def vo_sequence(flows, K, p, T, stride):
-    """Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.4): windows
+    """Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.3): windows
     of T flows start every `stride` frames; the first is bootstrapped from X_1,
     every later one takes T_1 from the previous window's estimate of the same
     frame pair.  Each window fixes its own scale by |t_1| = 1; the trajectory

@@ -456,6 +456,16 @@ typedef struct {
     double logrho, logmu;
 } or_emis;
 
+/* Test hook: when on, a posterior r below the smallest normal FP32 number
+ * (2^-126) is 0.  Where floating point decides the depth M-step's argmax, both
+ * sides then take it with the posterior in FP32's range: under the light-tailed
+ * Gaussian residual model an outlier observation has r = e^-d with d up to
+ * several hundred, and FP64 still orders the depth candidates of pixels that
+ * are outliers in every frame by such posteriors, where FP32 holds exact
+ * zeros.  Off by default; no other part of the arithmetic changes. */
+static int g_f32_range = 0;
+void or_set_f32_range(int on) { g_f32_range = on ? 1 : 0; }
+
 static or_emis emission(const or_frame_set *F, const or_params *p, const double *M,
                         int t, int x, int y, double theta)
 {
@@ -488,6 +498,7 @@ static or_emis emission(const or_frame_set *F, const or_params *p, const double 
     }
     double d = e.logmu - e.logrho;                        /* log(mu/rho) */
     e.r = 1.0 / (1.0 + exp(d));
+    if (g_f32_range && e.r < 1.1754943508222875e-38) e.r = 0.0;
     e.ell = -log1pexp(d);
     return e;
 }

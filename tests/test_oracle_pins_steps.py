@@ -336,3 +336,26 @@ def test_emission_beta_min_clamp(u_obs):
     fl[0, ..., 0] = u_obs
     _, _, lr2, _, _ = oracle.emission_map(np.full((H, W), theta), fl, K, p2, M)
     assert np.allclose(lr2, scipy.stats.fisk(c=0.05, scale=alpha).logpdf(1.0), rtol=1e-9)
+
+
+def test_f32_range_hook_only_zeroes_posteriors_below_the_fp32_range():
+    # the test hook under which the oracle takes the depth argmax with the
+    # posterior in FP32's range: a posterior below 2^-126 becomes 0, nothing
+    # else changes (log densities and ell of every item, larger posteriors)
+    w = synthflow.make_window("small", 6, T=2, H=32, W=40)
+    R, t = w["poses"][0]
+    s = np.linalg.norm(t)
+    rel = np.array([np.concatenate([R_.ravel(), t_ / s]) for R_, t_ in w["poses"]])
+    M = oracle.cumulative(rel)
+    theta = w["depth"] / s * np.exp(np.random.default_rng(0).normal(0, 0.3, w["depth"].shape))
+    p = oracle.params(residual_model=1)
+    a = oracle.emission_map(theta, w["flows"], w["K"], p, M)
+    with oracle.f32_range():
+        b = oracle.emission_map(theta, w["flows"], w["K"], p, M)
+    c = oracle.emission_map(theta, w["flows"], w["K"], p, M)     # off again
+    tiny = a[0] < 2.0 ** -126
+    assert (a[0][tiny] > 0).sum() > 10            # FP64 keeps them (some underflow there too)
+    assert np.all(b[0][tiny] == 0) and np.array_equal(b[0][~tiny], a[0][~tiny])
+    for k in (1, 2, 3, 4):
+        assert np.array_equal(a[k], b[k])
+    assert all(np.array_equal(x, y) for x, y in zip(a, c))
