@@ -145,7 +145,7 @@ int voldor_window_init(voldor_ctx *ctx, const float *flows, int T, int H, int W,
                        void *stream);
 
 /* The same window with T_1 given instead of estimated: the paper's
- * alternative for overlapping consecutive batches (Sec. 5.4), where T_1 comes
+ * alternative for overlapping consecutive batches (Sec. 5.3), where T_1 comes
  * from the previous window's estimate of the same frame pair.
  *   T1  device double[12] (R row-major, t), 8-byte aligned; read when the
  *       window's work runs, so it may be an earlier window's pose output on the
@@ -157,7 +157,7 @@ int voldor_window_seeded(voldor_ctx *ctx, const float *flows, int T, int H, int 
                          const voldor_params *p, const double *T1, double *poses, float *depth, float *rigidness,
                          double *loglik, int32_t *status_out, void *stream);
 
-/* Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.4): windows of
+/* Sliding-window visual odometry over N flows X_1..X_N (Sec. 5.3): windows of
  * T flows start at frames 0, stride, 2 stride, ..., with a last one ending at
  * flow N (voldor_vo_windows gives their count: 2 <= T <= 16, T <= N,
  * 1 <= stride < T).  The first window is bootstrapped from X_1; every later one
@@ -368,8 +368,10 @@ int voldor_pose_step(voldor_ctx *ctx, const float *theta, const float *rig, cons
                      void *stream);
 
 /* All-pixel candidate scores of the last pose step run with pose_start = 1 on
- * this context (voldor_pose_step, or the last pose step of a window), for
- * the reading of hypotheses scored over every pixel (Sec. 5.2):
+ * this context (voldor_pose_step, or the last pose step of a window).  The
+ * paper does not describe this scoring: Sec. 5.2 leaves the mean-shift start
+ * open, and this option picks it by scoring every hypothesis over every pixel
+ * with the E-step weights (an extension beside the default densest start):
  *   scores  host double[max_n]: [0] the previous pose (-inf if there was
  *           none), [1..] every valid sample in (group, root) order, each the
  *           sum over all pixels of W_t ell_t at M_t = T_c o M_{t-1}

@@ -167,6 +167,28 @@ def _flows(flows):
     return flows
 
 
+def _dev_tensor(t, name, dtype, shape, device, optional=False):
+    """t must be a contiguous CUDA tensor of `dtype` and `shape` on `device`
+    (None allowed when optional); raises before anything reaches the library."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise TypeError(f"{name} is required")
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    return t
+
+
+def _finalizing():
+    import sys
+    return sys.is_finalizing()
+
+
 def residual_fit(X, G, nbins=40, v_max=40.0, x_floor=1e-12, min_count=64, stream=None):
     """Fisk laws (a1, a2, b1, b2) of Eq. 6-7 fitted to the residuals |X - G|^2
     binned by |X| (CUDA float32 flows [..., 2]); returns (laws, bins [nbins][4])."""
@@ -184,14 +206,41 @@ def residual_fit(X, G, nbins=40, v_max=40.0, x_floor=1e-12, min_count=64, stream
     return laws, bins
 
 
+def _flow_pair(X, G):
+    """X and G: contiguous CUDA float32 tensors of one shape [..., 2]; returns n."""
+    import torch
+    for name, t in (("X", X), ("G", G)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA float32 tensor [..., 2]")
+    if X.shape != G.shape or X.dim() < 1 or X.shape[-1] != 2 or X.numel() == 0:
+        raise ValueError("X and G must have one shape [..., 2] with at least one item")
+    if X.device != G.device:
+        raise ValueError("X and G must be on one device")
+    return X.numel() // 2
+
+
+def _bins_out(out, nbins, device):
+    import torch
+    if out is None:
+        return torch.empty((nbins, 4), dtype=torch.float64, device=device)
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            and out.numel() >= 4 * nbins and out.device == device):
+        raise TypeError("out must be a contiguous CUDA float64 tensor of nbins x 4 elements on the flows' device")
+    return out
+
+
 def residual_bins(X, G, nbins=40, v_max=40.0, x_floor=1e-12, work=None, out=None, stream=None):
     """The binning pass alone, enqueued: returns the CUDA float64 [nbins][4] bins."""
     import torch
-    n = X.numel() // 2
+    n = _flow_pair(X, G)
+    need = int(lib().voldor_residual_workspace(n, nbins))
+    _check(need if need < 0 else 0, "voldor_residual_workspace")
     if work is None:
-        work = torch.empty(int(lib().voldor_residual_workspace(n, nbins)), dtype=torch.float64, device=X.device)
-    if out is None:
-        out = torch.empty((nbins, 4), dtype=torch.float64, device=X.device)
+        work = torch.empty(need, dtype=torch.float64, device=X.device)
+    elif not (isinstance(work, torch.Tensor) and work.is_cuda and work.dtype == torch.float64
+              and work.is_contiguous() and work.numel() >= need and work.device == X.device):
+        raise TypeError(f"work must be a contiguous CUDA float64 tensor of at least {need} elements")
+    out = _bins_out(out, nbins, X.device)
     _check(lib().voldor_residual_bins(_ptr(X), _ptr(G), n, nbins, v_max, x_floor, _ptr(work), _ptr(out),
                                       _stream(stream)), "voldor_residual_bins")
     return out
@@ -208,11 +257,22 @@ class Solver:
         self.T_max, self.H_max, self.W_max, self.S_max = T_max, H_max, W_max, S_max
 
     def close(self):
+        """Free the context's device workspace (waits for its work)."""
         if self._ctx:
             lib().voldor_destroy(self._ctx)
             self._ctx = C.c_void_p()
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # at interpreter exit the HIP runtime may already be torn down: leave
+        # the memory to the process's end instead of calling into it
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -260,8 +320,16 @@ class Solver:
         """Enqueue a window that starts from a proposed depth [H,W] and rigidness
         [T,H,W] (CUDA float32) where they explain X_1 better than the bootstrap;
         choice: CUDA int32 element set to 1 when the proposal was used."""
+        import torch
         flows = _flows(flows)
         T, H, W, _ = flows.shape
+        _dev_tensor(init_depth, "init_depth", torch.float32, (H, W), flows.device)
+        _dev_tensor(init_rig, "init_rig", torch.float32, (T, H, W), flows.device)
+        _dev_tensor(status, "status", torch.int32, status.shape if isinstance(status, torch.Tensor) else (), flows.device)
+        if status.numel() != 1:
+            raise ValueError("status must be one CUDA int32 element")
+        if choice is not None:
+            _dev_tensor(choice, "choice", torch.int32, choice.shape, flows.device)
         poses, depth, rig, ll = out
         Kd, Kp = _dbl(K)
         _check(lib().voldor_window_init(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), _ptr(init_depth),
@@ -459,10 +527,26 @@ class Batch:
         self._b = ctx
         self._keep = None
 
-    def __del__(self):
+    def close(self):
+        """Free the lanes' streams and workspaces (waits for their work)."""
         if getattr(self, "_b", None):
             lib().voldor_batch_destroy(self._b)
             self._b = None
+        self._keep = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
     @staticmethod
     def outputs(T, H, W, device="cuda"):
@@ -520,10 +604,42 @@ class Net:
         self.T = T
         self.n_params = lib().voldor_net_param_count(self._n)
 
-    def __del__(self):
+    def close(self):
+        """Free the network's device buffers (waits for their work)."""
         if getattr(self, "_n", None):
             lib().voldor_net_destroy(self._n)
             self._n = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _loss(loss, device):
+        import torch
+        if loss is not None and not (isinstance(loss, torch.Tensor) and loss.is_cuda and loss.dtype == torch.float64
+                                     and loss.is_contiguous() and loss.numel() >= 1 and loss.device == device):
+            raise TypeError("loss must be a contiguous CUDA float64 tensor of at least one element")
+
+    def _batch(self, flows):
+        """flows: contiguous CUDA float32 [N, T, H, W, 2] with this net's T."""
+        import torch
+        if not (isinstance(flows, torch.Tensor) and flows.is_cuda and flows.dtype == torch.float32
+                and flows.is_contiguous()):
+            raise TypeError("flows must be a contiguous CUDA float32 tensor [N,T,H,W,2]")
+        if flows.dim() != 5 or flows.shape[4] != 2 or flows.shape[1] != self.T:
+            raise ValueError(f"flows must have shape [N,{self.T},H,W,2], not {tuple(flows.shape)}")
+        return flows.shape
 
     def set_params(self, params):
         a = np.ascontiguousarray(params, dtype=np.float32)
@@ -537,22 +653,54 @@ class Net:
         return a
 
     def forward(self, flows, depth=None, rig=None, z=None, stream=None):
-        """flows: CUDA float32 [N,T,H,W,2]; optional outputs as CUDA float32 tensors."""
-        N, T, H, W, _ = flows.shape
+        """flows: CUDA float32 [N,T,H,W,2]; optional outputs as CUDA float32
+        tensors: depth [N,H,W], rig [N,T,H,W], z (the network's raw output)
+        [N,H,W,16]."""
+        import torch
+        N, T, H, W, _ = self._batch(flows)
+        _dev_tensor(depth, "depth", torch.float32, (N, H, W), flows.device, optional=True)
+        _dev_tensor(rig, "rig", torch.float32, (N, T, H, W), flows.device, optional=True)
+        _dev_tensor(z, "z", torch.float32, (N, H, W, 16), flows.device, optional=True)
         _check(lib().voldor_net_forward(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), _ptr(z),
                                         _stream(stream)), "voldor_net_forward")
 
     def gradient(self, flows, depth, rig, loss=None, grad=None, stream=None):
-        N, T, H, W, _ = flows.shape
+        """Loss gradient against labels depth [N,H,W] and rig [N,T,H,W]; loss
+        (CUDA float64 [2] or more) and grad (CUDA float32 [n_params]) optional."""
+        import torch
+        N, T, H, W, _ = self._batch(flows)
+        _dev_tensor(depth, "depth", torch.float32, (N, H, W), flows.device)
+        _dev_tensor(rig, "rig", torch.float32, (N, T, H, W), flows.device)
+        self._loss(loss, flows.device)
+        if grad is not None:
+            _dev_tensor(grad, "grad", torch.float32, (self.n_params,), flows.device)
         _check(lib().voldor_net_gradient(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), _ptr(loss),
                                          _ptr(grad), _stream(stream)), "voldor_net_gradient")
 
     def train_step(self, flows, depth, rig, lr, loss=None, stream=None):
-        N, T, H, W, _ = flows.shape
+        import torch
+        N, T, H, W, _ = self._batch(flows)
+        _dev_tensor(depth, "depth", torch.float32, (N, H, W), flows.device)
+        _dev_tensor(rig, "rig", torch.float32, (N, T, H, W), flows.device)
+        self._loss(loss, flows.device)
         _check(lib().voldor_net_train_step(self._n, _ptr(flows), N, H, W, _ptr(depth), _ptr(rig), float(lr),
                                            _ptr(loss), _stream(stream)), "voldor_net_train_step")
 
     def layer(self, k, x, out, mask=None, backward=False, stream=None):
+        """Layer k on a BF16 [N,H,W,32] tensor: forward into BF16 [N,H,W,32]
+        (float32 [N,H,W,16] for k = 5), or backward (k >= 1) into BF16
+        [N,H,W,32] times (mask > 0), mask BF16 [N,H,W,32]."""
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.dim() == 4 and x.shape[3] == 32):
+            raise ValueError("x must be a tensor [N,H,W,32]")
         N, H, W, _ = x.shape
+        if not 0 <= int(k) <= 5 or (backward and int(k) < 1):
+            raise ValueError("k must be 0..5 (1..5 backward)")
+        _dev_tensor(x, "x", torch.bfloat16, (N, H, W, 32), None)
+        if not backward and int(k) == 5:
+            _dev_tensor(out, "out", torch.float32, (N, H, W, 16), x.device)
+        else:
+            _dev_tensor(out, "out", torch.bfloat16, (N, H, W, 32), x.device)
+        _dev_tensor(mask, "mask", torch.bfloat16, (N, H, W, 32), x.device, optional=not backward)
         _check(lib().voldor_net_layer(self._n, k, 1 if backward else 0, _ptr(x), _ptr(mask), _ptr(out), N, H, W,
                                       _stream(stream)), "voldor_net_layer")

@@ -737,7 +737,7 @@ __global__ void k_boot_init(int *status, uint32_t *sel)
     if (threadIdx.x < 16) sel[threadIdx.x] = 0;
 }
 
-// T_1 given instead of estimated (overlapping consecutive batches, Sec. 5.4):
+// T_1 given instead of estimated (overlapping consecutive batches, Sec. 5.3):
 // the pose becomes decomposition candidate 0 with the only vote, so that the
 // triangulation and depth-range passes run unchanged (k_boot_tri rescales its
 // translation to unit length); a non-finite pose or a zero translation is

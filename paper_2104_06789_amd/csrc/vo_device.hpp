@@ -87,10 +87,21 @@ __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh
 __device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 
-// log(1 + e) for e in [0, 1] on the hardware log2 unit.  The rounding of 1 + e
-// costs at most half an ulp of 1 (6e-8) in absolute terms, which is what the
-// log-odds and the M-step scores need (they are compared in absolute terms).
+// log(1 + e) for e in [0, 1] on the hardware log2 unit, to an absolute error of
+// half an ulp of 1 (6e-8): the rounding of u = 1 + e.  Enough inside the
+// log-odds d, whose other terms carry errors of that size.
 __device__ __forceinline__ float log1p_unit(float e) { return fast_log(1.0f + e); }
+
+// The same to a relative error of a few ulp, given u = 1 + e rounded and its
+// reciprocal: log(1 + e) = log u - log(u / (1 + e)), and u / (1 + e) = 1 + dl / u
+// with dl = (u - 1) - e exact in FP32 (|dl| <= 2^-24), so the correction is
+// dl / u to first order.  For well-fitting candidates ell = -log(1 + e^d) is
+// tiny, and the M-step ranks them by it: there its absolute error must scale
+// with its size.
+__device__ __forceinline__ float log1p_rel(float e, float u, float inv_u)
+{
+    return fmaf(-((u - 1.0f) - e), inv_u, fast_log(u));
+}
 
 __device__ __forceinline__ float softplus(float z)
 {
@@ -179,15 +190,78 @@ __device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, floa
     }
 }
 
+// r = 1 / (1 + e^d), 0 below the smallest normal FP32 number (whatever the
+// denormal mode of the exponential: d > 87.3), and
+// ell = log r = -(max(d, 0) + log(1 + e^-|d|))
+constexpr float kFltMin = 1.17549435e-38f;
+__device__ __forceinline__ float posterior_from(float d, float e, float inv)
+{
+    const float r = d < 0.0f ? inv : e * inv;
+    return r >= kFltMin ? r : 0.0f;
+}
+
 __device__ __forceinline__ Emis emis_from_d(float d)
 {
     const float e = fast_exp(-fabsf(d));
-    const float inv = frcp(1.0f + e);
+    const float u = 1.0f + e;
+    const float inv = frcp(u);
     Emis o;
-    o.ell = -(fmaxf(d, 0.0f) + log1p_unit(e));
-    o.r = d < 0.0f ? inv : e * inv;
+    o.ell = -(fmaxf(d, 0.0f) + log1p_rel(e, u, inv));
+    o.r = posterior_from(d, e, inv);
     return o;
 }
+
+// log(-ell) = log(log(1 + e^d)), the log of the negated per-frame MIE term,
+// for the scores kept in log form (below).  For d < -8, log(1 + e^d) =
+// e^d (1 - e^d / 2 + ...), so log(-ell) = d - e^d / 2 to within 2e-8; above,
+// the log of -ell itself (then at least 3e-4, so relative accuracy holds).
+// Also returns r = 1 / (1 + e^d).
+__device__ __forceinline__ float neg_ell_log(float d, float &r)
+{
+    const float e = fast_exp(-fabsf(d));
+    const float u = 1.0f + e;
+    const float inv = frcp(u);
+    r = posterior_from(d, e, inv);
+    const float nl = fmaxf(d, 0.0f) + log1p_rel(e, u, inv);
+    return d < -8.0f ? fmaf(-0.5f, e, d) : fast_log(nl);
+}
+
+// A maximum-inlier score S = sum_t q_t ell_t (Eq. 10) kept as
+// -log(-S) = -log(sum_t e^{v_t}), v_t = log q_t + log(-ell_t), by a running
+// log-sum-exp: (m, a) with sum = e^m a, m the largest v_t so far.  The map
+// S -> -log(-S) is increasing, so scores compare as before, but the terms of
+// well-fitting candidates do not underflow: with the Gaussian residual model
+// ell = -e^d reaches e^-100, below the FP32 range, where a linear FP32 sum
+// would make every such candidate tie at 0.  Terms with q_t = 0 add nothing;
+// all q_t = 0 gives +inf (S = 0, the maximum).  Terms with q_t below the
+// smallest normal FP32 number are dropped as 0.
+struct LogScore {
+    float m, a;
+};
+
+__device__ __forceinline__ LogScore logscore_init()
+{
+    LogScore s;
+    s.m = -INFINITY;
+    s.a = 0.0f;
+    return s;
+}
+
+__device__ __forceinline__ void logscore_add(LogScore &s, float q, float lam)
+{
+    if (!(q >= kFltMin)) return;   // (a subnormal q's log could be -inf)
+    const float v = lam + fast_log(q);
+    const float dd = v - s.m;
+    const float e = fast_exp(-fabsf(dd));
+    if (dd > 0.0f) {
+        s.a = fmaf(s.a, e, 1.0f);
+        s.m = v;
+    } else {
+        s.a += e;
+    }
+}
+
+__device__ __forceinline__ float logscore_value(const LogScore &s) { return -(s.m + fast_log(s.a)); }
 
 // ---------------------------------------------------------------------------
 // FP64 helpers
@@ -464,6 +538,55 @@ __device__ inline bool quartic_root_slot(const double *c, int slot, double &out)
     return true;
 }
 
+// Newton steps on the three law-of-cosines equations in the distances
+//   s2^2 + s3^2 - 2 ca s2 s3 = A2,  s1^2 + s3^2 - 2 cb s1 s3 = B2,
+//   s1^2 + s2^2 - 2 cg s1 s2 = C2.
+// Where two solutions give (nearly) the same v, the quartic's root carries only
+// about half of the FP64 digits; the distances are refined on the equations
+// themselves.  The 3x3 Newton system is solved by cofactors (Cramer), and a
+// step is taken only while it lowers the residual.
+__device__ inline double lc_residual(double s1, double s2, double s3, double A2, double B2, double C2,
+                                     double ca, double cb, double cg, double &F0, double &F1, double &F2)
+{
+    F0 = fma(s2, s2, fma(s3, s3, -A2)) - 2.0 * ca * s2 * s3;
+    F1 = fma(s1, s1, fma(s3, s3, -B2)) - 2.0 * cb * s1 * s3;
+    F2 = fma(s1, s1, fma(s2, s2, -C2)) - 2.0 * cg * s1 * s2;
+    return fabs(F0) + fabs(F1) + fabs(F2);
+}
+
+__device__ inline void refine_distances(double &s1, double &s2, double &s3, double A2, double B2, double C2,
+                                        double ca, double cb, double cg)
+{
+    double F0, F1, F2;
+    double res = lc_residual(s1, s2, s3, A2, B2, C2, ca, cb, cg, F0, F1, F2);
+    for (int it = 0; it < 4 && res > 0.0; ++it) {
+        // Jacobian rows: (0, j01, j02), (j10, 0, j12), (j20, j21, 0)
+        const double j01 = 2.0 * (s2 - ca * s3), j02 = 2.0 * (s3 - ca * s2);
+        const double j10 = 2.0 * (s1 - cb * s3), j12 = 2.0 * (s3 - cb * s1);
+        const double j20 = 2.0 * (s1 - cg * s2), j21 = 2.0 * (s2 - cg * s1);
+        // cofactors of the rows: c0 = r1 x r2, c1 = r2 x r0, c2 = r0 x r1
+        const double c0x = -j12 * j21, c0y = j12 * j20, c0z = j10 * j21;
+        const double c1x = j21 * j02, c1y = -j20 * j02, c1z = j20 * j01;
+        const double c2x = j01 * j12, c2y = j02 * j10, c2z = -j01 * j10;
+        const double det = j01 * c0y + j02 * c0z;   // r0 . c0
+        if (!(fabs(det) > 0.0)) break;
+        const double id = 1.0 / det;
+        const double n1 = s1 - (F0 * c0x + F1 * c1x + F2 * c2x) * id;
+        const double n2 = s2 - (F0 * c0y + F1 * c1y + F2 * c2y) * id;
+        const double n3 = s3 - (F0 * c0z + F1 * c1z + F2 * c2z) * id;
+        double G0, G1, G2;
+        const double rn = lc_residual(n1, n2, n3, A2, B2, C2, ca, cb, cg, G0, G1, G2);
+        if (!(rn < res) || !(n1 > 0.0 && n2 > 0.0 && n3 > 0.0)) break;
+        s1 = n1;
+        s2 = n2;
+        s3 = n3;
+        res = rn;
+        F0 = G0;
+        F1 = G1;
+        F2 = G2;
+    }
+}
+
 // Orthonormal frame of a triangle: columns e1 along X1->X2, e3 normal, e2 = e3 x e1.
 __device__ inline void triangle_frame(const double *X1, const double *X2, const double *X3, double *F)
 {
@@ -519,7 +642,8 @@ __device__ inline bool p3p_root(const double *P, const double *f, int slot, doub
     if (!(v > 0) || fabs(D) < 1e-14 * B2 || !(Q > 0)) return false;
     const double u = ((n2 * v + n1) * v + n0) / D;
     if (!(u > 0)) return false;
-    const double s1 = sqrt(B2 / Q), s2 = u * s1, s3 = v * s1;
+    double s1 = sqrt(B2 / Q), s2 = u * s1, s3 = v * s1;
+    refine_distances(s1, s2, s3, A2, B2, C2, ca, cb, cg);
     double X[9];
     for (int k = 0; k < 3; ++k) {
         X[k] = s1 * f[k];

@@ -67,7 +67,10 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
                                              float xh, float yh, float th, const float *q, int L,
                                              int k)
 {
+    // MIE with the Gaussian residual model: the score in log form (LogScore)
+    constexpr bool LOGS = CRIT == 0 && MODEL == 1;
     float s = 0.0f;
+    LogScore ls = logscore_init();
     float pdx = 0.0f, pdy = 0.0f;
     bool pok = th > 0.0f;
     const int HW = H * W;   // T H W < 2^31 (frames <= 16, sides <= 4096)
@@ -108,7 +111,20 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
         for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
             if (t > T) break;
-            if constexpr (CRIT == 0) {
+            if constexpr (LOGS) {
+                float lam = kLogLn2F;
+                if (val[u]) {
+                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
+                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
+                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                        const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                        float rr;
+                        lam = neg_ell_log(dd, rr);
+                    }
+                }
+                logscore_add(ls, q[(t - 1) * L + k], lam);
+            } else if constexpr (CRIT == 0) {
                 float ell = kLogHalf;
                 if (val[u]) {
                     const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
@@ -137,6 +153,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
         pdy = dy[2];
         pok = ok[2];
     }
+    if constexpr (LOGS) return logscore_value(ls);
     return s;
 }
 
@@ -263,6 +280,9 @@ template <int CRIT, int NT, int MODEL>
 __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 {
     if (a.status && *a.status != kStatusOk) return;
+    // MIE with the Gaussian residual model keeps lam = log(-ell) per item and
+    // the scores in log form (LogScore in vo_device.hpp)
+    constexpr bool LOGS = CRIT == 0 && MODEL == 1;
     extern __shared__ float lds[];
     __shared__ FrameF fr[kTMax + 1];
     __shared__ int s_cnt[2];
@@ -340,11 +360,15 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
                 if (!act[b]) continue;
-                float ell = kLogHalf, r = 0.5f;
+                float ell = LOGS ? kLogLn2F : kLogHalf, r = 0.5f;
                 if (ok[b]) {
-                    const Emis m = emis_from_d(dd[b]);
-                    ell = m.ell;
-                    r = m.r;
+                    if constexpr (LOGS) {
+                        ell = neg_ell_log(dd[b], r);
+                    } else {
+                        const Emis m = emis_from_d(dd[b]);
+                        ell = m.ell;
+                        r = m.r;
+                    }
                 }
                 lq[i] = ell;
                 fq[i] = r;
@@ -430,7 +454,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 const float n1 = ff1 * b1, n0 = ff0 * b0;
                 rq[k] = n1 * frcp(n1 + n0);
                 if (k > s0) {
-                    const float r1 = CRIT == 0 ? fast_exp(ll[k]) : frcp(1.0f + fast_exp(ll[k])), r0 = 1.0f - r1;
+                    float r1 = LOGS        ? fast_exp(-fast_exp(ll[k]))
+                               : CRIT == 0 ? fast_exp(ll[k])
+                                           : frcp(1.0f + fast_exp(ll[k]));
+                    r1 = r1 >= kFltMin ? r1 : 0.0f;   // as in phase A
+                    const float r0 = 1.0f - r1;
                     const float e1 = r1 * b1, e0 = r0 * b0;
                     const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
                     const float inv = frcp(m1 + m0);
@@ -451,7 +479,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     // ---- S: score of the previous depth
     for (int k = tid; k < L; k += NT) {
         float s = 0.0f;
-        if constexpr (CRIT == 0) {
+        if constexpr (LOGS) {
+            LogScore ls = logscore_init();
+            for (int t = 0; t < T; ++t) logscore_add(ls, fq[t * L + k], lq[t * L + k]);
+            s = logscore_value(ls);
+        } else if constexpr (CRIT == 0) {
             for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
         } else {
             for (int t = 0; t < T; ++t) s += fmaf(-fq[t * L + k], lq[t * L + k], lmq[t * L + k]);
@@ -481,7 +513,12 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = i0 + b * NT;
-                if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+                if constexpr (LOGS) {
+                    float rr;
+                    if (act[b]) lq[i] = ok[b] ? neg_ell_log(dd[b], rr) : kLogLn2F;
+                } else {
+                    if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+                }
             }
         } else {
             // the sample's whole term log mu - q d (0 where missing)
@@ -497,7 +534,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     __syncthreads();
     for (int k = tid; k < L; k += NT) {
         float s = 0.0f;
-        if constexpr (CRIT == 0) {
+        if constexpr (LOGS) {
+            LogScore ls = logscore_init();
+            for (int t = 0; t < T; ++t) logscore_add(ls, fq[t * L + k], lq[t * L + k]);
+            s = logscore_value(ls);
+        } else if constexpr (CRIT == 0) {
             for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
         } else {
             for (int t = 0; t < T; ++t) s += lq[t * L + k];

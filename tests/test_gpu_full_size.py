@@ -219,14 +219,16 @@ def test_full_pose_step(vo, torch, name):
     To, osmp, odiag = oracle.pose_step(theta.astype(np.float64), rig.astype(np.float64), w["flows"], w["K"],
                                        p, M, t, 1, prevT=rel[t - 1], want_samples=True)
     assert odiag[3] == 0 and diag[3] == 0
-    # samples: P3P in FP64 on both sides; a few roots sit on an acceptance
-    # boundary, and ~1 % of the triples are near-degenerate, where the quartic's
-    # roots are ill-conditioned and the two solvers part beyond 1e-6
+    # samples: P3P in FP64 on both sides, each root refined on the
+    # law-of-cosines equations (a near-double root of the quartic alone keeps
+    # only half the digits); a few roots sit on an acceptance boundary
     assert abs(diag[0] - odiag[0]) <= 4 and abs(diag[1] - odiag[1]) <= 4
     smp = smp.cpu().numpy()
     both = (smp[:, 7] > 0) & (osmp[:, 7] > 0)
     dif = np.abs(smp[both, :6] - osmp[both, :6]).max(axis=1)
-    assert np.median(dif) < 1e-9 and np.mean(dif < 1e-6) > 0.98
+    print("samples", both.sum(), "median", np.median(dif), "share < 1e-6", np.mean(dif < 1e-6),
+          "share < 1e-9", np.mean(dif < 1e-9), "max", dif.max())
+    assert np.median(dif) < 1e-9 and np.mean(dif < 1e-6) > 0.999
     # mean-shift: the oracle's start selection (densest of the previous pose and
     # the first n_seeds samples, earliest on ties) and FP64 mean-shift on the
     # GPU's own samples reach the GPU's pose
@@ -239,9 +241,8 @@ def test_full_pose_step(vo, torch, name):
     Rm, tm = oracle.se3_exp(mode)
     assert _rot_angle(Tg[:9].reshape(3, 3), Rm) < 1e-6
     assert np.abs(Tg[9:] - tm).max() < 1e-5
-    # and the oracle's own step, whose samples differ in the ill-conditioned ~1 %:
-    # dropping a random 1 % of the oracle's samples moves its mode by ~2e-5 rad
-    # in rotation and 5e-4 .. 8e-4 rad in translation direction (medians over
-    # 30 draws, both workloads), so those are the bounds' scale
+    # and the oracle's own step, at the window tolerances
+    print("vs the oracle's step: rot", _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)),
+          "tdir", _tdir_angle(Tg[9:], To[9:]))
     assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-4
-    assert _tdir_angle(Tg[9:], To[9:]) < 1e-3
+    assert _tdir_angle(Tg[9:], To[9:]) < 1e-4

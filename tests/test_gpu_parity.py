@@ -9,6 +9,7 @@ window tests run the whole loop.  Tolerances:
     relative depth <= 1e-3, rigidness <= 1e-4 at the 99th percentile,
     log-likelihood <= 1e-5 relative to its L1 mass.
 """
+import contextlib
 import math
 
 import numpy as np
@@ -96,34 +97,41 @@ def test_sweep_parity(vo, torch, direction, criterion, model):
                      d_lo, d_hi, gs, direction, want_q=True)
     out, q = out.cpu().numpy(), q.cpu().numpy()
     op = oracle.params(criterion=criterion, residual_model=model)
-    # E-step: smoothed rigidness of the previous depth
-    orr, *_ = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"], op, M)
-    oq = oracle.fb_map(orr, direction, op.gamma)
-    assert np.abs(q - oq).max() < 2e-3
-    assert np.median(np.abs(q - oq)) < 1e-5
-    # M-step: every decision valid under FP64 scoring, up to FP32 near ties
-    st, gap = oracle.sweep_check(theta.astype(np.float64), out.astype(np.float64), w["flows"], w["K"], op,
-                                 M, d_lo, d_hi, gs, direction, vtol=2e-6, stol=1e-4)
-    # the kernel resolves each frame's ell = -log(1 + e^-|d|) - max(d, 0) to
-    # 6e-8 absolute (the rounding of 1 + e), so score gaps below 1e-6 over
-    # T = 4 frames are ties for it.  With the Gaussian residual model many
-    # well-fitting depths have ell between -1e-7 and -1e-44 (d from -16 to
-    # -100), which FP64 still orders
+    # with the light-tailed Gaussian model an outlier observation's posterior
+    # r = e^-d falls below FP32's range (d > 87), and FP64 orders the depths of
+    # pixels that are outliers in every frame by such posteriors: the oracle
+    # then takes the argmax with r in FP32's range (its f32_range hook); the
+    # Fisk's posteriors stay far inside it
+    rng_ctx = oracle.f32_range() if model == 1 else contextlib.nullcontext()
+    with rng_ctx:
+        # E-step: smoothed rigidness of the previous depth
+        orr, *_ = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"], op, M)
+        oq = oracle.fb_map(orr, direction, op.gamma)
+        assert np.abs(q - oq).max() < 2e-3
+        assert np.median(np.abs(q - oq)) < 1e-5
+        # M-step: every decision valid under FP64 scoring, up to FP32 near ties
+        st, gap = oracle.sweep_check(theta.astype(np.float64), out.astype(np.float64), w["flows"], w["K"], op,
+                                     M, d_lo, d_hi, gs, direction, vtol=2e-6, stol=1e-4)
+        ref, _, _ = oracle.sweep(theta.astype(np.float64), w["flows"], w["K"], op, M, d_lo, d_hi, gs, direction)
+    # the kernel's ell = -log(1 + e^d) carries a relative error of ~1e-5 (the
+    # absolute FP32 error of d), so a decision is exact unless its gap is a
+    # near tie of the score mass (stol above).  With the Gaussian residual
+    # model well-fitting depths have ell = -e^d down to e^-100, below the FP32
+    # range: the kernel keeps those scores as -log(-S), which FP32 resolves
     print(np.unique(st, return_counts=True), gap[st == 3])
-    st = np.where((st == 3) & (gap < 1e-6), 1, st)
+    # a q below FP32's smallest normal number is 0 for the kernel: where the
+    # scores then differ only by terms of that size (gap < 1e-30), both
+    # decisions are ties in FP32
+    st = np.where((st == 3) & (gap < 1e-30), 1, st)
     assert (st <= 1).all(), np.unique(st, return_counts=True)
-    # (the share of exact decisions counts ties, frequent with the Gaussian)
-    assert (st == 0).mean() > (0.995 if model == 0 else 0.95)
-    # the oracle's own walk from the same state agrees almost everywhere.  (Not
-    # asserted for the Gaussian: its FP32 ties among well-fitting depths are
-    # frequent, and a tie taken the other way changes the propagated neighbour
-    # down the chain, 91 % agreement bottom to top; every decision is checked
-    # above.)
-    ref, _, _ = oracle.sweep(theta.astype(np.float64), w["flows"], w["K"], op, M, d_lo, d_hi, gs, direction)
-    same = np.abs(out - ref) <= 2e-6 * ref
+    # near ties: 0.1 % of the decisions with the Fisk model; with the
+    # light-tailed Gaussian, d = (x - m) / s reaches -100 and its FP32 error
+    # (~1e-5 absolute) is a relative error of e^d, so candidates closer than
+    # that tie for the kernel (up to 2.5 % of the decisions, bottom to top)
+    assert (st == 0).mean() > (0.995 if model == 0 else 0.97)
+    # the oracle's own walk from the same state agrees almost everywhere
     print("same as the oracle's walk", same.mean())
-    if model == 0:
-        assert same.mean() > 0.99
+    assert same.mean() > (0.99 if model == 0 else 0.95)
 
 
 def test_pose_step_parity(vo, torch):
@@ -289,12 +297,19 @@ def test_invalid_arguments(vo, torch):
     assert s.window_status(fl, (40.0, 40.0, 16.0, 16.0), vo.default_params(pose_start=2)) == -1
 
 
+def _oracle_window(w, kw):
+    # the Gaussian residual model's argmax with the posterior in FP32's range
+    # (see test_sweep_parity)
+    with (oracle.f32_range() if kw.get("residual_model", 0) == 1 else contextlib.nullcontext()):
+        return oracle.window(w["flows"], w["K"], oracle.params(**kw))
+
+
 def _window_compare(vo, torch, w, kw, T, H, W, S):
     p = vo.default_params(**kw)
     s = vo.Solver(T, H, W, S)
     poses, depth, rig, ll = s.window(torch.from_numpy(w["flows"]).cuda(), w["K"], p)
     gp, gd, gr, gl = (x.cpu().numpy() for x in (poses, depth, rig, ll))
-    st, op, od, orig, oll, diag = oracle.window(w["flows"], w["K"], oracle.params(**kw))
+    st, op, od, orig, oll, diag = _oracle_window(w, kw)
     assert st == 0
     rot = [_rot_angle(gp[t, :9].reshape(3, 3), op[t, :9].reshape(3, 3)) for t in range(T)]
     tdir = [_tdir_angle(gp[t, 9:], op[t, 9:]) for t in range(T)]
@@ -310,9 +325,9 @@ def _oracle_sensitivity(w, kw, eps=1e-5, seed=0):
     FP32 evaluation of the residual is a perturbation of that size, so on windows
     whose near-tie depth decisions cascade (small images, early iterations) this
     is the floor any FP32 implementation can reach."""
-    st, op, od, orig, oll, _ = oracle.window(w["flows"], w["K"], oracle.params(**kw))
+    st, op, od, orig, oll, _ = _oracle_window(w, kw)
     f2 = (w["flows"] + np.random.default_rng(seed).normal(0, eps, w["flows"].shape)).astype(np.float32)
-    st2, op2, od2, orig2, oll2, _ = oracle.window(f2, w["K"], oracle.params(**kw))
+    st2, op2, od2, orig2, oll2, _ = _oracle_window(dict(w, flows=f2), kw)
     dr = np.abs(orig2 - orig)
     return dict(rig_p99=float(np.percentile(dr, 99)), ll=abs(oll2[0] - oll[0]) / oll[1])
 
@@ -362,16 +377,16 @@ def test_window_parity_mle(vo, torch):
     assert r["ll"] <= max(1e-5, 2 * max(x["ll"] for x in sens))
 
 
-def test_window_gauss_model_matches_oracle_accuracy(vo, torch):
+def test_window_gauss_model(vo, torch):
     # the Gaussian residual model on the T=5 160x120 workload, 3 iterations,
-    # 256 groups per frame.  Its components match the oracle (emission, every
-    # sweep decision, all-pixel scores, above); the whole window is compared by
-    # accuracy against the ground truth, not value by value: where every
-    # candidate depth fits, the kernel's ell rounds to 0 (6e-8 resolution,
-    # underflow below e^-87) and it keeps the previous depth as a tie, while
-    # FP64 still orders the candidates by gaps down to 1e-44.  Those
-    # different-but-valid depths move the poses by ~7e-4 rad after 3
-    # iterations, far beyond the oracle's response to 1e-5 px of flow noise.
+    # 256 groups per frame.  Parity partial: every component matches the
+    # oracle (emission, every sweep decision valid with the posterior in FP32's
+    # range, all-pixel scores, above), but the whole window differs from the
+    # oracle's by ~4e-4 rad in rotation (printed).  With this light-tailed
+    # density, up to 2.5 % of a sweep's decisions are ties at FP32 resolution
+    # (0.1 % with the Fisk), and the ties taken the other way spread through
+    # propagation.  The window is held to the oracle's accuracy against the
+    # ground truth instead.
     w = synthflow.make_window("small", 0)
     spec = w["spec"]
     T, H, W = spec.T, spec.H, spec.W
@@ -379,8 +394,10 @@ def test_window_gauss_model_matches_oracle_accuracy(vo, torch):
     s = vo.Solver(T, H, W, 256)
     poses, depth, rig, ll = s.window(torch.from_numpy(w["flows"]).cuda(), w["K"], vo.default_params(**kw))
     gp, gd = poses.cpu().numpy(), depth.cpu().numpy()
-    st, op, od, orig, oll, _ = oracle.window(w["flows"], w["K"], oracle.params(**kw))
+    st, op, od, orig, oll, _ = _oracle_window(w, kw)
     assert st == 0
+    print("gpu vs oracle: rot", max(_rot_angle(gp[t, :9].reshape(3, 3), op[t, :9].reshape(3, 3)) for t in range(T)),
+          "tdir", max(_tdir_angle(gp[t, 9:], op[t, 9:]) for t in range(T)))
 
     def errors(P, D):
         R = [_rot_angle(P[t, :9].reshape(3, 3), w["poses"][t][0]) for t in range(T)]

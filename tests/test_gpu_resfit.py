@@ -76,3 +76,31 @@ def test_residual_bins_every_register_slot(vo, torch, nb):
     ref = resfit.bin_stats(X, G, nb, vmax)
     assert np.array_equal(bins[:, 0], ref[:, 0])
     assert np.allclose(bins[:, 1:], ref[:, 1:], rtol=1e-12, atol=1e-9)
+
+
+def test_binding_rejects_bad_shapes_before_any_launch(vo, torch):
+    X = torch.zeros((100, 2), device="cuda")
+    with pytest.raises(ValueError):
+        vo.residual_bins(X, torch.zeros((99, 2), device="cuda"))
+    with pytest.raises(TypeError):
+        vo.residual_bins(X, torch.zeros((100, 2), device="cuda", dtype=torch.float64))
+    with pytest.raises(TypeError):
+        vo.residual_bins(X, torch.zeros((2, 100), device="cuda").t())
+    with pytest.raises(TypeError):
+        vo.residual_bins(X, X, work=torch.zeros(3, dtype=torch.float64, device="cuda"))
+    n = vo.Net(3, 1, 16, 16)
+    with pytest.raises(ValueError):
+        n.forward(torch.zeros((1, 4, 16, 16, 2), device="cuda"))      # T of another net
+    with pytest.raises(ValueError):
+        n.forward(torch.zeros((1, 3, 16, 16, 2), device="cuda"), depth=torch.zeros((1, 16, 15), device="cuda"))
+    with pytest.raises(ValueError):
+        n.train_step(torch.zeros((1, 3, 16, 16, 2), device="cuda"), torch.zeros((1, 16, 16), device="cuda"),
+                     torch.zeros((1, 2, 16, 16), device="cuda"), 1e-3)
+    n.close()
+    s = vo.Solver(3, 16, 16, 64)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        s.window_init(torch.zeros((3, 16, 16, 2), device="cuda"), (10.0, 10.0, 8.0, 8.0), vo.default_params(),
+                      torch.ones((16, 17), device="cuda"), torch.ones((3, 16, 16), device="cuda"),
+                      vo.Batch.outputs(3, 16, 16), st[0])
+    s.close()

@@ -1,4 +1,4 @@
-"""Sliding-window visual odometry (Sec. 5.4) on the GPU against the FP64 oracle,
+"""Sliding-window visual odometry (Sec. 5.3) on the GPU against the FP64 oracle,
 through the C ABI: the window with T_1 given, its degenerate inputs, and a
 whole sequence whose windows seed each other on the device.
 

@@ -141,3 +141,27 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_binding_rejects_host_tensors_before_any_call(vo):
+    # the binding checks device, dtype, contiguity and shape before a pointer
+    # reaches the library (a host pointer would fault the GPU)
+    import torch
+    X = torch.zeros((10, 2))
+    with pytest.raises(TypeError):
+        vo.residual_bins(X, X)
+    with pytest.raises(TypeError):
+        vo._dev_tensor(torch.zeros((4, 5)), "depth", torch.float32, (4, 5), None)
+    n = vo.Net.__new__(vo.Net)          # no device context: the checks come first
+    n.T, n._n, n.n_params = 3, None, 10
+    with pytest.raises(TypeError):
+        n.forward(torch.zeros((1, 3, 16, 16, 2)))
+    with pytest.raises(TypeError):
+        n.train_step(torch.zeros((1, 3, 16, 16, 2)), torch.zeros((1, 16, 16)), torch.zeros((1, 3, 16, 16)), 1e-3)
+    with pytest.raises(ValueError):
+        n.layer(0, torch.zeros((1, 16, 16, 8)), None)
+    s = vo.Solver.__new__(vo.Solver)
+    s._ctx = C.c_void_p()
+    with pytest.raises(TypeError):
+        s.window_init(torch.zeros((3, 16, 16, 2)), (10, 10, 8, 8), vo.default_params(), torch.ones((16, 16)),
+                      torch.ones((3, 16, 16)), None, None)
