@@ -216,6 +216,23 @@ int64_t voldor_residual_workspace(int64_t n, int nbins);
 int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
                          double *work, double *bins, void *stream);
 
+/* voldor_residual_bins for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and result, bit for bit, with the partials in a
+ * static device array of VOLDOR_RESIDUAL_SCRATCH_DOUBLES doubles (2 MiB) that
+ * every device the library runs on holds until the process ends.  Nothing is
+ * allocated and no part of the array needs to start at zero (every partial is
+ * written before it is read).  VOLDOR_EINVAL when the partials,
+ * voldor_residual_workspace(n, nbins) doubles, exceed the array (e.g. more
+ * than 64 bins at n >= 2^21 items), or for the arguments voldor_residual_bins
+ * rejects; VOLDOR_EDEVICE when the runtime cannot give the array's address on
+ * the current device.  All calls on one device share its array: calls that
+ * overlap on one device (two streams, or two host threads) race.  Enqueued
+ * without waiting. */
+#define VOLDOR_RESIDUAL_SCRATCH_DOUBLES 262144
+int voldor_residual_bins_noalloc(const float *X, const float *G, int64_t n, int nbins, double v_max,
+                                 double x_floor, double *bins, void *stream);
+
 /* ---- batches: many windows of uneven shape and T ------------------------- */
 
 /* One window of a batch: the arguments of voldor_window for that window. */

@@ -95,6 +95,7 @@ def lib():
         "voldor_residual_fit": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, i, dp, dp, vp]),
         "voldor_residual_workspace": (C.c_int64, [C.c_int64, i]),
         "voldor_residual_bins": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, vp, vp, vp]),
+        "voldor_residual_bins_noalloc": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, vp, vp]),
         "voldor_vo_sequence": (i, [vp, vp, i, i, i, dp, P, i, i, vp, vp, vp, vp, vp, vp]),
         "voldor_bootstrap": (i, [vp, vp, i, i, i, dp, P, dp, vp, dp, dp, vp]),
         "voldor_set_timing": (i, [vp, i]),
@@ -243,6 +244,16 @@ def residual_bins(X, G, nbins=40, v_max=40.0, x_floor=1e-12, work=None, out=None
     out = _bins_out(out, nbins, X.device)
     _check(lib().voldor_residual_bins(_ptr(X), _ptr(G), n, nbins, v_max, x_floor, _ptr(work), _ptr(out),
                                       _stream(stream)), "voldor_residual_bins")
+    return out
+
+
+def residual_bins_noalloc(X, G, out, nbins=40, v_max=40.0, x_floor=1e-12, stream=None):
+    """residual_bins without any device allocation (the library's static
+    scratch): out is a preallocated CUDA float64 [nbins][4] tensor."""
+    n = _flow_pair(X, G)
+    out = _bins_out(out, nbins, X.device)
+    _check(lib().voldor_residual_bins_noalloc(_ptr(X), _ptr(G), n, nbins, v_max, x_floor, _ptr(out),
+                                              _stream(stream)), "voldor_residual_bins_noalloc")
     return out
 
 

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace vo {
 
@@ -240,26 +241,12 @@ __global__ void __launch_bounds__(kRedThreads) k_resid_reduce(const double *part
     if (t < 8 && c < ncol) out[c] = red[t];
 }
 
-}  // namespace vo
-
-extern "C" {
-
-int64_t voldor_residual_workspace(int64_t n, int nbins)
+// The binning pass into the partials buffer `work` (blocks x nbins x 4
+// doubles, every entry written by its workgroup before the reduction reads
+// it), then the fixed-order reduction into bins.
+static int resid_bins_launch(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
+                             double *work, double *bins, hipStream_t s)
 {
-    if (n < 1 || nbins < 2 || nbins > vo::kFitMaxBins) return VOLDOR_EINVAL;
-    const int64_t blocks = std::min<int64_t>(vo::kFitBlocks, (n + vo::kFitThreads * vo::kFitK - 1) / (vo::kFitThreads * vo::kFitK));
-    return blocks * nbins * 4;
-}
-
-int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
-                         double *work, double *bins, void *stream)
-{
-    using namespace vo;
-    if (!X || !G || !work || !bins || n < 1 || nbins < 2 || nbins > kFitMaxBins || !(v_max > 0.0) ||
-        !(x_floor > 0.0) || ((uintptr_t)X & 7) != 0 || ((uintptr_t)G & 7) != 0 || ((uintptr_t)work & 7) != 0 ||
-        ((uintptr_t)bins & 7) != 0)
-        return VOLDOR_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     const int blocks = (int)std::min<int64_t>(kFitBlocks, (n + kFitThreads * kFitK - 1) / (kFitThreads * kFitK));
     const size_t lds = sizeof(double) * (kFitThreads / 64) * nbins * 4;
     const auto *x2 = (const float2 *)X, *g2 = (const float2 *)G;
@@ -276,6 +263,73 @@ int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, d
     hipLaunchKernelGGL(k_resid_reduce, dim3((nbins * 4 + 7) / 8), dim3(kRedThreads), 0, s, work, blocks, nbins * 4,
                        bins);
     return hipGetLastError() == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+}
+
+static bool resid_args_ok(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
+                          const double *bins)
+{
+    return X && G && bins && n >= 1 && nbins >= 2 && nbins <= kFitMaxBins && v_max > 0.0 && x_floor > 0.0 &&
+           ((uintptr_t)X & 7) == 0 && ((uintptr_t)G & 7) == 0 && ((uintptr_t)bins & 7) == 0;
+}
+
+// Partials of the binning pass for callers that cannot allocate: one
+// file-scope device array, VOLDOR_RESIDUAL_SCRATCH_DOUBLES doubles (2 MiB),
+// held by every device the library runs on until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in, not
+// a device address): its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) double scratch[VOLDOR_RESIDUAL_SCRATCH_DOUBLES];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kScratchDevices];
+
+// the device address of `scratch` on the current device; VOLDOR_EDEVICE if the
+// runtime cannot give it
+static int scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return VOLDOR_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VOLDOR_EDEVICE;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VOLDOR_OK;
+}
+
+}  // namespace vo
+
+extern "C" {
+
+int64_t voldor_residual_workspace(int64_t n, int nbins)
+{
+    if (n < 1 || nbins < 2 || nbins > vo::kFitMaxBins) return VOLDOR_EINVAL;
+    const int64_t blocks = std::min<int64_t>(vo::kFitBlocks, (n + vo::kFitThreads * vo::kFitK - 1) / (vo::kFitThreads * vo::kFitK));
+    return blocks * nbins * 4;
+}
+
+int voldor_residual_bins(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,
+                         double *work, double *bins, void *stream)
+{
+    using namespace vo;
+    if (!resid_args_ok(X, G, n, nbins, v_max, x_floor, bins) || !work || ((uintptr_t)work & 7) != 0)
+        return VOLDOR_EINVAL;
+    return resid_bins_launch(X, G, n, nbins, v_max, x_floor, work, bins, (hipStream_t)stream);
+}
+
+int voldor_residual_bins_noalloc(const float *X, const float *G, int64_t n, int nbins, double v_max,
+                                 double x_floor, double *bins, void *stream)
+{
+    using namespace vo;
+    if (!resid_args_ok(X, G, n, nbins, v_max, x_floor, bins)) return VOLDOR_EINVAL;
+    const int64_t need = voldor_residual_workspace(n, nbins);
+    if (need < 1 || need > VOLDOR_RESIDUAL_SCRATCH_DOUBLES) return VOLDOR_EINVAL;
+    double *work = nullptr;
+    const int rc = scratch_on_current_device(&work);
+    if (rc) return rc;
+    return resid_bins_launch(X, G, n, nbins, v_max, x_floor, work, bins, (hipStream_t)stream);
 }
 
 int voldor_residual_fit(const float *X, const float *G, int64_t n, int nbins, double v_max, double x_floor,

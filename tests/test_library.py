@@ -151,6 +151,8 @@ def test_binding_rejects_host_tensors_before_any_call(vo):
     with pytest.raises(TypeError):
         vo.residual_bins(X, X)
     with pytest.raises(TypeError):
+        vo.residual_bins_noalloc(X, X, torch.zeros((40, 4), dtype=torch.float64))
+    with pytest.raises(TypeError):
         vo._dev_tensor(torch.zeros((4, 5)), "depth", torch.float32, (4, 5), None)
     n = vo.Net.__new__(vo.Net)          # no device context: the checks come first
     n.T, n._n, n.n_params = 3, None, 10
