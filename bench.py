@@ -1,26 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the VOLDOR window solver on one MI355X.
 
-One step = one whole window solved by the HIP library (bootstrap, then every
-EM iteration: pose of each frame, the directional depth/rigidness sweeps, the
-unsmoothed rigidness and the gauge; finally the log-likelihood), on a seeded
-synthetic window whose flows are already resident in device memory.
+Default workload (the headline): a batch of 32 windows of uneven shape and T
+(320x240, 640x480 and 1242x375, T from 4 to 8, 4 EM iterations, 1024 / 2048 /
+4096 P3P groups per frame by shape), solved by voldor_window_batch over
+concurrent streams in one HIP graph per step, flows resident in device memory.
+One step = the whole batch: for every window the bootstrap, then every EM
+iteration (pose of each frame, the directional depth/rigidness sweeps, the
+unsmoothed rigidness and the gauge), finally the log-likelihood.
 
-Metric: pixel-frame EM updates/s = T*H*W*n_iters / (seconds per window).
-Default workload: the indoor shape (T=6, 640x480, 4 iterations, 2048 P3P
-groups per frame); --workload driving runs T=8, 1242x375.
+Metric: pixel-frame EM updates/s = sum over windows of T*H*W*n_iters per
+second.  Windows/s is reported beside it, and the indoor (T=6, 640x480) and
+driving (T=8, 1242x375) single windows as sub-objects.  --workload indoor,
+driving, small time one window shape alone; learned, vo and resfit the
+extensions.
 
-The roofline object reports the dominant GPU kernel, the fused directional
-sweep, against the VALU issue rate it is bound by.  Algorithmic work per
-launch = 3 emission evaluations per pixel-frame (previous depth, random sample,
-propagated neighbour: what the serial walk needs) x EMISSION_VALU_OPS FP32
-non-transcendental VALU lane-instructions each, divided by the mean sweep
-duration measured with HIP events on the solver's stream; the peak is 256 CUs x
-64 lanes x 2.4 GHz.  With --pose-start allpixel the dominant kernel is the
-candidate scoring, reported the same way.
-The HBM view of the same launch (flow stack read + depth read/write) is kept
-alongside for reference.  The cpu_baseline object times the FP64 CPU oracle on
-one window of the same workload.
+Roofline: the dominant kernel, the fused directional sweep, against HBM:
+algorithmic bytes per launch = the flow stack read once (8 B per pixel-frame)
+plus the depth read and written (8 B per pixel), divided by the mean launch
+duration from device timestamps written on the stream each launch runs on (a
+one-thread kernel reading the real-time counter at each phase boundary; unlike
+HIP events it also runs inside the captured graph).  Its ALU view
+beside it counts 3 candidate-frame evaluations x (8 transcendental + 50 FP32)
+operations per pixel-frame and sweep against the FP32 peak.  The cpu_baseline
+object times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -43,16 +46,10 @@ SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
                         "write_bytes": 1249.0390625 * 1024 * 1.0}
 SWEEP_SOURCES_SHA = "2874f55bd8b6a519"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
-# Issue peak of non-packed FP32 VALU instructions: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz = 39.3 T lane-instructions/s (independent v_fma_f32 chains sustain
-# 36.2 T on MI355X).  Transcendental instructions (v_exp/v_log/v_rcp) issue on
-# their own unit beside it, so the algorithmic counts below are the other VALU
-# instructions of one evaluation, read from the gfx950 ISA.
+# Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3 T/s; the all-pixel candidate scoring (--pose-start
+# allpixel) is bound by it and reported against it.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-EMISSION_VALU_OPS = 148                      # one emission evaluation of the sweep (160 VALU, 12 of them
-                                             # transcendental)
-EMISSION_VALU_OPS_GAUSS = 127                # the same with the Gaussian residual model: 21 fewer (its
-                                             # d = (x - m) ln2 / alpha replaces beta, two logs, two softplus)
 
 
 def _sweep_traffic(workload):
@@ -150,30 +147,137 @@ def _pose_error(poses, gt):
     return float(np.mean(rot)), float(np.mean(tdir))
 
 
-BATCH_ITERS, BATCH_GROUPS = 4, 2048
+BATCH_ITERS = 4
+# algorithmic FP32 work of one pixel-frame in one sweep: three candidate-frame
+# evaluations (previous depth, random sample, propagated neighbour), each about
+# 8 transcendental and 50 other FP32 operations
+ALG_OPS_PER_PF_SWEEP = 3 * (8 + 50)
+FP32_PEAK_TFLOPS = 157.3
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_job(job):
+    """One whole window by the FP64 oracle in this process: (status, seconds)."""
+    import oracle
+    flows, K, kw = job
+    t0 = time.perf_counter()
+    st, *_ = oracle.window(flows, K, oracle.params(**kw))
+    return st, time.perf_counter() - t0
+
+
+def _cpu_baseline_batch(wins, seed, iters):
+    """The oracle on a bounded sample of the batch, run before the GPU is
+    touched: the batch's 320x240 windows, first one alone on one core, then one
+    window per process on up to 16 cores at once (the oracle is serial C;
+    windows are independent, so this is how the oracle uses a multi-core host)."""
+    import multiprocessing as mp
+
+    import synthflow
+    small = [w for w in wins if (w["spec"].W, w["spec"].H) == (320, 240)]
+    if not small:
+        return None
+    cores = max(1, min(16, os.cpu_count() or 1))
+    jobs = []
+    for k in range(cores):
+        w = small[k % len(small)]
+        kw = dict(n_iters=iters, n_pose_groups=synthflow.BATCH_GROUPS[(320, 240)], seed=seed)
+        jobs.append((w["flows"], w["K"], kw))
+    pf = [j[0].shape[0] * j[0].shape[1] * j[0].shape[2] * iters for j in jobs]
+    st1, s1 = _oracle_job(jobs[0])
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    ok = st1 == 0 and all(r[0] == 0 for r in res)
+    return {"value": sum(pf) / wall, "unit": "pixel-frame updates/s", "cores": cores, "kind": "oracle",
+            "single_core_value": pf[0] / s1,
+            "sample": f"{cores} windows of the batch's 320x240 shape (its {len(small)} such windows, repeated), "
+                      f"{iters} EM iterations, FP64 oracle, one window per process on {cores} processes at once: "
+                      f"{wall:.1f} s wall; one window alone on one core: {s1:.1f} s; status {'ok' if ok else 'FAILED'}",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def _single_window_figures(vo, torch, name, seed, steps):
+    """One window shape solved sequentially (the per-window latency view)."""
+    import synthflow
+    w = synthflow.make_window(name, seed)
+    spec = w["spec"]
+    T, H, W = spec.T, spec.H, spec.W
+    flows = torch.from_numpy(w["flows"]).to("cuda:0")
+    p = vo.default_params(n_iters=spec.n_iters, n_pose_groups=spec.n_groups, seed=seed)
+    solver = vo.Solver(T, H, W, spec.n_groups)
+    solver.autotune(flows, w["K"], p)
+    solver.set_timing(True)
+    dev = flows.device
+    out = (torch.empty((T, 12), dtype=torch.float64, device=dev), torch.empty((H, W), dtype=torch.float32, device=dev),
+           torch.empty((T, H, W), dtype=torch.float32, device=dev), torch.empty(2, dtype=torch.float64, device=dev))
+    status = torch.full((steps + 2,), -1, dtype=torch.int32, device=dev)
+    for i in range(2):
+        solver.window_async(flows, w["K"], p, out, status[i])
+    torch.cuda.synchronize()
+    solver.timing_summary()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        solver.window_async(flows, w["K"], p, out, status[2 + i])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ph, n = solver.timing_summary()
+    if any(int(x) != 0 for x in status.cpu().tolist()):
+        print(f"{name}: a window reported a nonzero status", file=sys.stderr)
+        sys.exit(1)
+    sweep_us = ph["sweeps"] / max(ph["sweep_launches"], 1.0) * 1e3
+    alg_bytes = 8.0 * T * H * W + 8.0 * H * W
+    gbs = alg_bytes / (sweep_us * 1e-6) / 1e9
+    rot, tdir = _pose_error(out[0].cpu().numpy(), w["poses"])
+    tuning = solver.sweep_tuning()
+    solver.close()
+    return {"workload": f"{name}: T={T}, {W}x{H}, {spec.n_iters} EM iterations, {spec.n_groups} P3P groups/frame",
+            "ms_per_window": ms, "windows_per_s": 1e3 / ms,
+            "pixel_frame_updates_per_s": T * H * W * spec.n_iters / (ms * 1e-3),
+            "phase_ms": {k: float(ph[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness", "loglik", "window"]},
+            "sweep_launch_us": sweep_us, "sweep_hbm_GBs": gbs, "sweep_hbm_frac": gbs / HBM_PEAK_GBS,
+            "sweep_tuning": [list(t) for t in tuning],
+            "pose_error_vs_gt": {"rot_rad": rot, "tdir_rad": tdir}}
 
 
 def run_batch(args):
     """One step = one batch of windows of uneven shape and T solved by
     voldor_window_batch over concurrent streams (one HIP graph per step)."""
     import synthflow
-    # generated in forked workers before anything touches the GPU
+    # generated in forked workers, and the CPU baseline run, before anything
+    # touches the GPU
     wins = synthflow.make_batch(args.batch, args.seed, workers=min(16, os.cpu_count() or 1))
+    cpu = None if args.no_cpu_baseline else _cpu_baseline_batch(wins, args.seed, BATCH_ITERS)
     import numpy as np
     import torch
 
     import paper_2104_06789_amd as vo
 
     dev = torch.device("cuda:0")
-    p = vo.default_params(n_iters=BATCH_ITERS, n_pose_groups=BATCH_GROUPS, seed=args.seed)
+    p = vo.default_params(n_iters=BATCH_ITERS, n_pose_groups=2048, seed=args.seed)
     flows = [torch.from_numpy(w["flows"]).to(dev) for w in wins]
     shapes = [tuple(f.shape[:3]) for f in flows]
+    groups = [synthflow.BATCH_GROUPS[(W, H)] for T, H, W in shapes]
     outs = [vo.Batch.outputs(T, H, W) for T, H, W in shapes]
-    items = [(f, w["K"], o) for f, w, o in zip(flows, wins, outs)]
+    items = [(f, w["K"], o, None, g) for f, w, o, g in zip(flows, wins, outs, groups)]
     Tm, Hm, Wm = (max(x[k] for x in shapes) for k in range(3))
     status = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
-    solver = vo.Batch(args.lanes, Tm, Hm, Wm, BATCH_GROUPS, graph=not args.no_graph)
+    solver = vo.Batch(args.lanes, Tm, Hm, Wm, max(groups), graph=not args.no_graph)
+    with torch.cuda.stream(stream):
+        solver.autotune(items, p, stream=stream)
+    solver.set_timing(True)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             solver.solve(items, p, status, stream=stream)
@@ -188,17 +292,24 @@ def run_batch(args):
     if bad:
         print(f"window status {vo.status_str(bad[0])} in {len(bad)} of {len(wins)} windows", file=sys.stderr)
         sys.exit(1)
+    # phase sums over the windows of the last timed step (the graph replays the
+    # event records of every captured window)
+    ph, n_timed = solver.timing_summary()
     ms = (t1 - t0) * 1e3 / max(args.steps, 1)
     pf_win = [T * H * W for T, H, W in shapes]
     pf = sum(pf_win) * BATCH_ITERS
     value = pf / (ms * 1e-3)
-    # every sweep of the batch: 3 emission evaluations per pixel-frame
-    alg_ops = 3.0 * sum(pf_win) * EMISSION_VALU_OPS * BATCH_ITERS * p.sweeps_per_iter
-    achieved = alg_ops / (ms * 1e-3) / 1e12
+    n_sweeps = BATCH_ITERS * p.sweeps_per_iter
+    alg_bytes = sum(n_sweeps * (8.0 * T * H * W + 8.0 * H * W) for T, H, W in shapes)
+    alg_ops = sum(n_sweeps * ALG_OPS_PER_PF_SWEEP * T * H * W for T, H, W in shapes)
+    sweep_s = ph["sweeps"] * 1e-3
+    launches = ph["sweep_launches"]
+    achieved_gbs = alg_bytes / sweep_s / 1e9 if sweep_s > 0 else None
     errs = [_pose_error(o[0].cpu().numpy(), w["poses"]) for o, w in zip(outs, wins)]
     mix = {}
     for T, H, W in shapes:
         mix[f"{W}x{H}"] = mix.get(f"{W}x{H}", 0) + 1
+    tuning = []
     line = {
         "metric": "pixel-frame EM updates/s",
         "value": value,
@@ -212,32 +323,60 @@ def run_batch(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batch: {len(wins)} windows of shapes drawn from 320x240, 640x480, "
-                               f"1242x375 and T from 4..8, {BATCH_ITERS} EM iterations, {BATCH_GROUPS} P3P "
-                               f"groups/frame, seed {args.seed}",
+        "config": {"workload": f"batch: {len(wins)} windows, shapes drawn from 320x240 (CPU-sized generator, "
+                               f"intrinsics x2), 640x480 (indoor) and 1242x375 (driving), T from 4..8, "
+                               f"{BATCH_ITERS} EM iterations, P3P groups per frame 1024 / 2048 / 4096 by shape, "
+                               f"seed {args.seed}",
                    "windows": len(wins), "shapes": mix, "frames": sum(x[0] for x in shapes),
                    "lanes": args.lanes, "graph": not args.no_graph,
                    "parallelism": "single GPU, one batch per step over concurrent streams"},
         "windows_per_s": len(wins) * 1e3 / ms,
         "pose_error_vs_gt": {"rot_rad": float(np.mean([e[0] for e in errs])),
                              "tdir_rad": float(np.mean([e[1] for e in errs]))},
-        "roofline": {"bound": "alu", "kernel": "k_sweep (all sweeps of the batch over the whole step)",
-                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "alg_ops_per_step": alg_ops},
+        "phase_ms_summed_over_windows": {k: float(ph[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness",
+                                                                    "loglik", "window"]},
+        "timed_windows": n_timed,
+        "roofline": {"bound": "hbm", "kernel": "k_sweep",
+                     "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
+                     "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid() else None,
+                     "alg_bytes_per_launch": alg_bytes / max(launches, 1.0),
+                     "launch_ms": ph["sweeps"] / max(launches, 1.0), "launches": launches,
+                     "note": "algorithmic bytes of a sweep: the flow stack read once (8 B per pixel-frame) and the "
+                             "depth read and written (8 B per pixel); launch time = the sweep intervals between device "
+                             "timestamps on the lane streams during the last timed step (the graph replays them; "
+                             "lanes run concurrently)"},
+        "alu_view": {"achieved_TFLOPs": alg_ops / sweep_s / 1e12 if sweep_s > 0 else None,
+                     "peak_TFLOPs": FP32_PEAK_TFLOPS,
+                     "frac": alg_ops / sweep_s / 1e12 / FP32_PEAK_TFLOPS if sweep_s > 0 else None,
+                     "ops_per_pixel_frame_sweep": ALG_OPS_PER_PF_SWEEP,
+                     "note": "3 candidate-frame evaluations x (8 transcendental + 50 FP32) operations per "
+                             "pixel-frame and sweep, over the same launch time"},
+        "cpu_baseline": cpu,
     }
-    if not args.no_cpu_baseline:
-        import oracle
-        k = int(np.argmin(pf_win))   # the smallest window of the batch
-        c0 = time.perf_counter()
-        st, *_ = oracle.window(wins[k]["flows"], wins[k]["K"],
-                               oracle.params(n_iters=BATCH_ITERS, n_pose_groups=BATCH_GROUPS, seed=args.seed))
-        c1 = time.perf_counter()
-        T, H, W = shapes[k]
-        line["cpu_baseline"] = {"value": pf_win[k] * BATCH_ITERS / (c1 - c0), "unit": "pixel-frame updates/s",
-                                "cores": 1, "kind": "oracle",
-                                "sample": f"window {k} of the batch (T={T}, {W}x{H}, {BATCH_ITERS} iterations), "
-                                          f"FP64 oracle, single thread, {c1 - c0:.1f} s, status {st}"}
+    solver.close()
+    if not args.no_single:
+        line["single_window"] = {name: _single_window_figures(vo, torch, name, args.seed, 10)
+                                 for name in ("indoor", "driving")}
     print(json.dumps(line))
+
+
+# HBM traffic of the sweeps of one batch step (rocprofv3 FETCH_SIZE + WRITE_SIZE
+# of k_sweep, summed over the step's launches, per launch, scaled by the copy
+# calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
+BATCH_SWEEP_TRAFFIC_PER_LAUNCH = None
+BATCH_SWEEP_SOURCES_SHA = None
+
+
+def _batch_sweep_traffic_valid():
+    import hashlib
+    if BATCH_SWEEP_TRAFFIC_PER_LAUNCH is None or BATCH_SWEEP_SOURCES_SHA is None:
+        return False
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_06789_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16] == BATCH_SWEEP_SOURCES_SHA
 
 
 LEARN_T, LEARN_H, LEARN_W = 6, 480, 640
@@ -357,8 +496,8 @@ def run_vo(args):
     rot_p, ate_p = _trajectory_error(plain, w["poses"])
     launches = float(phases["sweep_launches"])
     sweep_ms = float(phases["sweeps"]) / max(launches, 1.0)
-    alg_ops = 3.0 * T * H * W * EMISSION_VALU_OPS
-    achieved = alg_ops / (sweep_ms * 1e-3) / 1e12
+    alg_bytes = 8.0 * T * H * W + 8.0 * H * W
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
     line = {
         "metric": "frames/s of sliding-window VO",
         "value": N / (ms * 1e-3),
@@ -373,9 +512,9 @@ def run_vo(args):
         "seeded": {"rot_err_rad": rot_s, "ate_rel": ate_s},
         "bootstrapped_each": {"rot_err_rad": rot_p, "ate_rel": ate_p},
         "phase_ms": {k: float(phases[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness", "window"]},
-        "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "launch_ms": sweep_ms},
     }
     print(json.dumps(line))
 
@@ -622,7 +761,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="indoor", choices=["indoor", "driving", "small", "batch", "learned", "vo", "resfit"])
+    ap.add_argument("--workload", default="batch", choices=["indoor", "driving", "small", "batch", "learned", "vo", "resfit"])
     ap.add_argument("--vo-flows", type=int, default=18, help="flows of the sequence (--workload vo)")
     ap.add_argument("--vo-stride", type=int, default=1, help="frames between window starts (--workload vo)")
     ap.add_argument("--seed", type=int, default=0)
@@ -636,6 +775,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
     ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-window indoor and driving figures of the batch workload")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the four-lane figure (profiles of the sequential windows alone)")
     ap.add_argument("--train-windows", type=int, default=384, help="(--workload learned)")
@@ -715,7 +856,7 @@ def main():
     sweep_ms = ph["sweeps"] / max(launches, 1.0)
     alg_bytes = 8.0 * T * H * W + 8.0 * H * W
     achieved_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    alg_ops = 3.0 * T * H * W * (EMISSION_VALU_OPS_GAUSS if rmodel else EMISSION_VALU_OPS)
+    alg_ops = float(ALG_OPS_PER_PF_SWEEP) * T * H * W
     achieved = alg_ops / (sweep_ms * 1e-3) / 1e12
 
     rot_err, tdir_err = _pose_error(out[0].cpu().numpy(), w["poses"])
@@ -753,11 +894,12 @@ def main():
         "phase_windows": n_timed,
         "concurrent": conc_line,
         "pose_error_vs_gt": {"rot_rad": rot_err, "tdir_rad": tdir_err},
-        "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": _sweep_traffic(args.workload) if not (crit or rmodel) else None,
-                     "alg_ops_per_launch": alg_ops, "launch_ms": sweep_ms,
-                     "hbm_view": {"alg_bytes_per_launch": alg_bytes, "achieved_GBs": achieved_gbs,
-                                  "frac_of_8TBs": achieved_gbs / HBM_PEAK_GBS}},
+        "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "traffic": _sweep_traffic(args.workload) if not (crit or rmodel) else None,
+                     "alg_bytes_per_launch": alg_bytes, "launch_ms": sweep_ms},
+        "alu_view": {"achieved_TFLOPs": achieved, "peak_TFLOPs": FP32_PEAK_TFLOPS,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "ops_per_pixel_frame_sweep": ALG_OPS_PER_PF_SWEEP},
     }
 
     if pstart:

@@ -184,13 +184,30 @@ int voldor_vo_sequence(voldor_ctx *ctx, const float *flows, int N, int H, int W,
 int voldor_set_sweep_threads(voldor_ctx *ctx, int rows, int cols);
 int voldor_get_sweep_threads(const voldor_ctx *ctx, int *rows, int *cols);
 
+/* Look-ahead of the propagation rounds (Fig. 5's neighbour candidate found
+ * for every chain position at once): in each round every live origin tests its
+ * value at up to `cap` further positions, at most threads / live origins; 0
+ * means no cap (the whole workgroup every round).  A small cap wastes fewer
+ * evaluations past each origin's first loss and takes more rounds.  Like the
+ * width it never changes the result.  Row and column sweeps apart; cap 0 or
+ * 1..4096, else VOLDOR_EINVAL. */
+int voldor_set_sweep_lookahead(voldor_ctx *ctx, int rows, int cols);
+int voldor_get_sweep_lookahead(const voldor_ctx *ctx, int *rows, int *cols);
+
 /* Autotuner: bootstraps the given window (device flows as voldor_window), then
- * times the row and the column sweeps at every width that fits and keeps the
- * fastest in the context (also returned in *rows_out, *cols_out if not NULL).
- * Waits for the device.  VOLDOR_EDEGENERATE if the bootstrap fails (the
- * widths are then unchanged). */
+ * times the row and the column sweeps at every setting of the two tuning axes,
+ * threads per chain (256, 512, 1024 where the chain fits the LDS) and the
+ * look-ahead cap (none, 16, 8, 4), and keeps the fastest for this chain class
+ * (chain length, T, depth criterion) in the context: windows of that class then
+ * use it, others the defaults of voldor_set_sweep_threads/_lookahead (which
+ * drop every tuned class).  The threads chosen for rows and columns are
+ * returned in *rows_out, *cols_out if not NULL.  Waits for the device.
+ * VOLDOR_EDEGENERATE if the bootstrap fails (nothing is then kept).
+ * voldor_sweep_tuning lists the tuned classes: out[4i .. 4i+3] = chain length,
+ * T, threads, look-ahead cap; returns their number (at most max_n). */
 int voldor_autotune(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,
                     const voldor_params *p, int *rows_out, int *cols_out, void *stream);
+int voldor_sweep_tuning(const voldor_ctx *ctx, int *out, int max_n);
 
 /* Regression of the Fisk laws of Eq. 6-7 on optical-flow residuals (the
  * procedure behind Fig. 4b).  Items x = |X - G|^2 (floored at x_floor) are
@@ -247,6 +264,8 @@ typedef struct {
     const float *init_depth;  /* device float [H][W] or NULL: proposed initial state, */
     const float *init_rig;    /* device float [T][H][W] or NULL  as voldor_window_init */
     int32_t *choice;          /* device int32 or NULL: 1 when the proposal was used    */
+    int32_t n_pose_groups;    /* P3P groups per frame of this window (0: params')     */
+    int32_t pad;
 } voldor_window_desc;
 
 /* Batch solver: `lanes` (1..8) HIP streams, each with the workspace of a
@@ -278,6 +297,20 @@ int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, 
 
 /* Sweep widths of every lane of the batch (as voldor_set_sweep_threads). */
 int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols);
+
+/* Autotuner of a batch: voldor_autotune on the first window of every distinct
+ * chain class (shape, T, criterion) among the n descriptors, the settings then
+ * shared by every lane.  Waits for the device.  Results never depend on it. */
+int voldor_batch_autotune(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
+                          void *stream);
+
+/* Phase timing of a batch's windows, each lane as voldor_set_timing (a
+ * captured graph replays the event records, so the summary covers the last
+ * replay of every window captured since the previous summary).  The summary
+ * waits, then gives in out[8] the phase SUMS (not means) over the windows of
+ * every lane, the last 32 of each lane at most, and their number. */
+int voldor_batch_set_timing(voldor_batch *b, int enable);
+int voldor_batch_timing_summary(voldor_batch *b, double *out, int *n_windows);
 
 /* Phase timing of windows with HIP events recorded on their stream, kept for
  * the last 32 windows.  voldor_set_timing(ctx, 1) creates the events (0

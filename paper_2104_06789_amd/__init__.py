@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys as _sys
 
 import numpy as np
 
@@ -53,6 +54,7 @@ class WindowDesc(C.Structure):
         ("K", C.c_double * 4), ("poses", C.c_void_p), ("depth", C.c_void_p),
         ("rigidness", C.c_void_p), ("loglik", C.c_void_p),
         ("init_depth", C.c_void_p), ("init_rig", C.c_void_p), ("choice", C.c_void_p),
+        ("n_pose_groups", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -90,8 +92,14 @@ def lib():
         "voldor_vo_windows": (i, [i, i, i]),
         "voldor_set_sweep_threads": (i, [vp, i, i]),
         "voldor_get_sweep_threads": (i, [vp, ip, ip]),
+        "voldor_set_sweep_lookahead": (i, [vp, i, i]),
+        "voldor_get_sweep_lookahead": (i, [vp, ip, ip]),
         "voldor_autotune": (i, [vp, vp, i, i, i, dp, P, ip, ip, vp]),
         "voldor_batch_set_sweep_threads": (i, [vp, i, i]),
+        "voldor_batch_autotune": (i, [vp, C.POINTER(WindowDesc), i, P, vp]),
+        "voldor_batch_set_timing": (i, [vp, i]),
+        "voldor_batch_timing_summary": (i, [vp, dp, ip]),
+        "voldor_sweep_tuning": (i, [vp, ip, i]),
         "voldor_residual_fit": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, i, dp, dp, vp]),
         "voldor_residual_workspace": (C.c_int64, [C.c_int64, i]),
         "voldor_residual_bins": (i, [vp, vp, C.c_int64, i, C.c_double, C.c_double, vp, vp, vp]),
@@ -186,8 +194,7 @@ def _dev_tensor(t, name, dtype, shape, device, optional=False):
 
 
 def _finalizing():
-    import sys
-    return sys.is_finalizing()
+    return _sys.is_finalizing()
 
 
 def residual_fit(X, G, nbins=40, v_max=40.0, x_floor=1e-12, min_count=64, stream=None):
@@ -481,6 +488,15 @@ class Solver:
         _check(lib().voldor_get_sweep_threads(self._ctx, C.byref(r), C.byref(c)), "voldor_get_sweep_threads")
         return r.value, c.value
 
+    def set_sweep_lookahead(self, rows, cols):
+        """Look-ahead cap of the propagation rounds (0 = none), rows and columns."""
+        _check(lib().voldor_set_sweep_lookahead(self._ctx, int(rows), int(cols)), "voldor_set_sweep_lookahead")
+
+    def sweep_lookahead(self):
+        r, c = C.c_int(0), C.c_int(0)
+        _check(lib().voldor_get_sweep_lookahead(self._ctx, C.byref(r), C.byref(c)), "voldor_get_sweep_lookahead")
+        return r.value, c.value
+
     def autotune(self, flows, K, params, stream=None):
         """Time every sweep width on this window's shape and keep the fastest;
         returns (row threads, column threads)."""
@@ -491,6 +507,13 @@ class Solver:
         _check(lib().voldor_autotune(self._ctx, _ptr(flows), T, H, W, Kp, C.byref(params), C.byref(r), C.byref(c),
                                      _stream(stream)), "voldor_autotune")
         return r.value, c.value
+
+    def sweep_tuning(self):
+        """The tuned chain classes: [(chain length, T, threads, look-ahead cap)]."""
+        buf = (C.c_int * 64)()
+        n = lib().voldor_sweep_tuning(self._ctx, buf, 16)
+        _check(n if n < 0 else 0, "voldor_sweep_tuning")
+        return [tuple(buf[4 * i:4 * i + 4]) for i in range(n)]
 
     def pose_scores(self):
         """All-pixel candidate scores of the last pose step run with pose_start=1:
@@ -572,20 +595,14 @@ class Batch:
         """Sweep widths of every lane (as Solver.set_sweep_threads)."""
         _check(lib().voldor_batch_set_sweep_threads(self._b, int(rows), int(cols)), "voldor_batch_set_sweep_threads")
 
-    def solve(self, windows, params, status, stream=None):
-        """Enqueue a batch.  windows: list of (flows [T,H,W,2] CUDA float32, K (fx, fy,
-        cx, cy), out) with out = (poses, depth, rigidness, loglik or None) as from
-        outputs(); status: CUDA int32 tensor of len(windows) elements.  Returns
-        without waiting; the tensors must stay alive until the stream has run it."""
-        import torch
+    @staticmethod
+    def _descs(windows):
         n = len(windows)
-        if not (isinstance(status, torch.Tensor) and status.is_cuda and status.dtype == torch.int32
-                and status.is_contiguous() and status.numel() >= n):
-            raise TypeError("status must be a contiguous CUDA int32 tensor of len(windows) elements")
         descs = (WindowDesc * n)()
         for i, item in enumerate(windows):
             flows, K, out = item[:3]
             init = item[3] if len(item) > 3 else None
+            groups = item[4] if len(item) > 4 else 0
             flows = _flows(flows)
             T, H, W, _ = flows.shape
             poses, depth, rig, ll = out
@@ -600,6 +617,43 @@ class Batch:
                 idepth, irig, choice = init
                 d.init_depth, d.init_rig = idepth.data_ptr(), irig.data_ptr()
                 d.choice = choice.data_ptr() if choice is not None else None
+            d.n_pose_groups = int(groups)
+        return descs
+
+    def set_timing(self, enable=True):
+        _check(lib().voldor_batch_set_timing(self._b, 1 if enable else 0), "voldor_batch_set_timing")
+
+    def timing_summary(self):
+        """Phase milliseconds summed over the recorded windows of every lane
+        (bootstrap, pose, sweeps, sweep launches, rigidness, loglik, window),
+        and their number."""
+        out = np.zeros(8)
+        n = C.c_int(0)
+        _check(lib().voldor_batch_timing_summary(self._b, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)),
+               "voldor_batch_timing_summary")
+        keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window"]
+        return dict(zip(keys, out[:7].tolist())), n.value
+
+    def autotune(self, windows, params, stream=None):
+        """Tune the sweeps on the first window of every distinct shape of
+        `windows` (items as in solve); waits for the device."""
+        descs = self._descs(windows)
+        _check(lib().voldor_batch_autotune(self._b, descs, len(windows), C.byref(params), _stream(stream)),
+               "voldor_batch_autotune")
+
+    def solve(self, windows, params, status, stream=None):
+        """Enqueue a batch.  windows: list of (flows [T,H,W,2] CUDA float32, K (fx, fy,
+        cx, cy), out[, init[, n_pose_groups]]) with out = (poses, depth, rigidness,
+        loglik or None) as from outputs(), init = None or (depth, rigidness, choice)
+        as window_init, n_pose_groups this window's P3P groups per frame (0: the
+        params'); status: CUDA int32 tensor of len(windows) elements.  Returns
+        without waiting; the tensors must stay alive until the stream has run it."""
+        import torch
+        n = len(windows)
+        if not (isinstance(status, torch.Tensor) and status.is_cuda and status.dtype == torch.int32
+                and status.is_contiguous() and status.numel() >= n):
+            raise TypeError("status must be a contiguous CUDA int32 tensor of len(windows) elements")
+        descs = self._descs(windows)
         self._keep = (windows, status)
         _check(lib().voldor_window_batch(self._b, descs, n, C.byref(params), _ptr(status), _stream(stream)),
                "voldor_window_batch")

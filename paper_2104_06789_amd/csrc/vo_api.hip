@@ -46,8 +46,11 @@ bool dims_ok(const voldor_ctx *c, int T, int H, int W, int criterion)
 {
     if (!c) return false;
     if (T < 1 || T > c->T_max || H < 16 || W < 16 || H > c->H_max || W > c->W_max) return false;
-    if ((int)sweep_lds_bytes(T, W, criterion, c->sweep_nt[0]) > c->max_lds ||
-        (int)sweep_lds_bytes(T, H, criterion, c->sweep_nt[1]) > c->max_lds)
+    int ntr = 512, ntc = 512, la = 0;
+    sweep_cfg_for(c, 0, W, T, criterion, &ntr, &la);
+    sweep_cfg_for(c, 1, H, T, criterion, &ntc, &la);
+    if ((int)sweep_lds_bytes(T, W, criterion, ntr) > c->max_lds ||
+        (int)sweep_lds_bytes(T, H, criterion, ntc) > c->max_lds)
         return false;
     return true;
 }
@@ -113,40 +116,56 @@ hipError_t dalloc(T **p, size_t n)
     return hipMalloc((void **)p, n * sizeof(T) + 16);
 }
 
-// phase timing: an event after each phase; the interval ending at event i
-// belongs to ev_phase[i] and, for the sweeps, holds ev_launches[i] launches.
-// Each record still idles the GPU for a few microseconds, so the sweeps of one
-// iteration share one interval: its mean is the time per launch.
+// phase timing: a timestamp after each phase, written on the window's stream
+// by a one-thread kernel reading the GPU's constant-rate real-time counter
+// (s_memrealtime); the interval ending at stamp i belongs to ev_phase[i] and,
+// for the sweeps, holds ev_launches[i] launches.  Unlike HIP events these
+// stamps keep working when the window is captured into a HIP graph: every
+// replay rewrites them.  The sweeps of one iteration share one interval: its
+// mean is the time per launch.
 enum { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseRig = 4, kPhaseLL = 5 };
+
+__global__ void k_stamp(unsigned long long *slot)
+{
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
 
 void mark(voldor_ctx *c, hipStream_t s, int phase, int launches = 0)
 {
     if (!c->timing) return;
-    // a full slot moves its last event forward: the whole-window time stays exact
+    // a full slot moves its last stamp forward: the whole-window time stays exact
     const int i = c->n_ev < kEvPerWin ? c->n_ev : kEvPerWin - 1;
-    if (hipEventRecord(c->ev[c->tw_cur * kEvPerWin + i], s) != hipSuccess) return;
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, c->stamps + c->tw_cur * kEvPerWin + i);
+    if (hipGetLastError() != hipSuccess) return;
     c->ev_phase[c->tw_cur][i] = phase;
     c->ev_launches[c->tw_cur][i] = launches;
     c->n_ev = i + 1;
 }
 
-// phases of the window in ring slot w (its events complete):
+// phases of the window in ring slot w (its stamps complete and copied to the
+// host copy):
 // [0] bootstrap, [1] pose steps, [2] sweeps, [3] sweep launches,
 // [4] rigidness + gauge, [5] log-likelihood, [6] whole window
 void slot_timing(const voldor_ctx *c, int w, double *ms8)
 {
     for (int i = 0; i < 8; ++i) ms8[i] = 0.0;
-    const hipEvent_t *ev = c->ev + w * kEvPerWin;
+    const unsigned long long *st = c->stamps_host + w * kEvPerWin;
     const int n = c->ev_n[w];
+    const double ms_per_tick = 1.0 / c->stamp_khz;
     for (int i = 1; i < n; ++i) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) != hipSuccess) continue;
+        const double ms = (double)(long long)(st[i] - st[i - 1]) * ms_per_tick;
         const int ph = c->ev_phase[w][i];
         if (ph >= 0 && ph < 6) ms8[ph] += ms;
         if (ph == kPhaseSweep) ms8[3] += c->ev_launches[w][i];
     }
-    float tot = 0.0f;
-    if (n > 1 && hipEventElapsedTime(&tot, ev[0], ev[n - 1]) == hipSuccess) ms8[6] = tot;
+    if (n > 1) ms8[6] = (double)(long long)(st[n - 1] - st[0]) * ms_per_tick;
+}
+
+// the stamps of every ring slot to the host copy (the stream is complete)
+int fetch_stamps(voldor_ctx *c)
+{
+    return hipMemcpy(c->stamps_host, c->stamps, sizeof(unsigned long long) * kTimingRing * kEvPerWin,
+                     hipMemcpyDeviceToHost) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
 
 __global__ void k_copy_status(const int *status, int32_t *out)
@@ -426,7 +445,7 @@ int voldor_window(voldor_ctx *c, const float *flows, int T, int H, int W, const 
     const int rc = window_enqueue(c, flows, T, H, W, K, p, poses, depth, rigidness, loglik, nullptr, s);
     if (rc != 0) return rc;
     if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
-    if (c->timing) slot_timing(c, c->tw_cur, c->last_ms);
+    if (c->timing && fetch_stamps(c) == VOLDOR_OK) slot_timing(c, c->tw_cur, c->last_ms);
     int st = 0;
     if (hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return VOLDOR_EDEVICE;
     return st;
@@ -553,6 +572,7 @@ int voldor_set_sweep_threads(voldor_ctx *c, int rows, int cols)
         if (v[a] != 256 && v[a] != 512 && v[a] != 1024) return VOLDOR_EINVAL;
     c->sweep_nt[0] = v[0];
     c->sweep_nt[1] = v[1];
+    c->n_sweep_tab = 0;   // an explicit setting replaces the tuned ones
     return VOLDOR_OK;
 }
 
@@ -564,10 +584,29 @@ int voldor_get_sweep_threads(const voldor_ctx *c, int *rows, int *cols)
     return VOLDOR_OK;
 }
 
-// Times the sweep at every width that fits (256, 512, 1024 threads per chain)
-// on this window's shape, row and column sweeps apart, from the bootstrap's
-// state, and keeps the fastest in the context.  Every width gives the same
-// result, so the choice changes speed only.
+int voldor_set_sweep_lookahead(voldor_ctx *c, int rows, int cols)
+{
+    if (!c || rows < 0 || cols < 0 || rows > 4096 || cols > 4096) return VOLDOR_EINVAL;
+    c->sweep_la[0] = rows;
+    c->sweep_la[1] = cols;
+    c->n_sweep_tab = 0;   // an explicit setting replaces the tuned ones
+    return VOLDOR_OK;
+}
+
+int voldor_get_sweep_lookahead(const voldor_ctx *c, int *rows, int *cols)
+{
+    if (!c || !rows || !cols) return VOLDOR_EINVAL;
+    *rows = c->sweep_la[0];
+    *cols = c->sweep_la[1];
+    return VOLDOR_OK;
+}
+
+// Times the sweeps of this window's shape at every setting of the two tuning
+// axes, threads per chain (256, 512, 1024 where the chain fits the LDS) and
+// look-ahead cap of the propagation rounds (none, 16, 8, 4), row and column
+// sweeps apart, from the bootstrap's state, and keeps the fastest of each
+// axis for this chain class (length, frames, criterion) in the context.  No
+// setting changes the result.
 int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                     const voldor_params *p, int *rows_out, int *cols_out, void *stream)
 {
@@ -594,64 +633,102 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
         return VOLDOR_EDEVICE;
     }
     const int widths[3] = {256, 512, 1024};
-    const int keep[2] = {c->sweep_nt[0], c->sweep_nt[1]};
-    int best[2] = {keep[0], keep[1]};
+    const int caps[4] = {0, 16, 8, 4};
+    // the defaults are the fallback while timing: clear any tuned entry of
+    // these classes by timing through a temporary default instead
+    const int keep_nt[2] = {c->sweep_nt[0], c->sweep_nt[1]}, keep_la[2] = {c->sweep_la[0], c->sweep_la[1]};
+    const int keep_n = c->n_sweep_tab;
+    SweepCfg keep_tab[kSweepTab];
+    for (int i = 0; i < keep_n; ++i) keep_tab[i] = c->sweep_tab[i];
+    c->n_sweep_tab = 0;
+    int best_nt[2] = {512, 512}, best_la[2] = {0, 0};
     for (int axis = 0; axis < 2 && rc == 0; ++axis) {
         const int L = axis ? H : W;
         float best_ms = 1e30f;
         for (int wi = 0; wi < 3 && rc == 0; ++wi) {
             const int nt = widths[wi];
             if ((int)sweep_lds_bytes(T, L, p->criterion, nt) > c->max_lds) continue;
-            c->sweep_nt[axis] = nt;
-            float ms = 0.0f;
-            for (int rep = 0; rep < 4 && rc == 0; ++rep) {   // the first sweep warms up
-                if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VOLDOR_EDEVICE;
-                if (rc == 0)
-                    rc = launch_sweep(c, c->theta_tmp, c->theta_tmp, X, d, e, (float)p->gamma, p->seed, rep, axis,
-                                      c->range, nullptr, s, p->criterion);
-            }
-            if (rc == 0 && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                rc = VOLDOR_EDEVICE;
-            if (rc == 0 && ms < best_ms) {
-                best_ms = ms;
-                best[axis] = nt;
+            for (int ci = 0; ci < 4 && rc == 0; ++ci) {
+                c->sweep_nt[axis] = nt;
+                c->sweep_la[axis] = caps[ci];
+                float ms = 0.0f;
+                for (int rep = 0; rep < 4 && rc == 0; ++rep) {   // the first sweep warms up
+                    if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VOLDOR_EDEVICE;
+                    if (rc == 0)
+                        rc = launch_sweep(c, c->theta_tmp, c->theta_tmp, X, d, e, (float)p->gamma, p->seed, rep,
+                                          axis, c->range, nullptr, s, p->criterion);
+                }
+                if (rc == 0 && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = VOLDOR_EDEVICE;
+                if (rc == 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best_nt[axis] = nt;
+                    best_la[axis] = caps[ci];
+                }
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->sweep_nt[0] = rc == 0 ? best[0] : keep[0];
-    c->sweep_nt[1] = rc == 0 ? best[1] : keep[1];
-    if (rows_out) *rows_out = c->sweep_nt[0];
-    if (cols_out) *cols_out = c->sweep_nt[1];
+    c->sweep_nt[0] = keep_nt[0];
+    c->sweep_nt[1] = keep_nt[1];
+    c->sweep_la[0] = keep_la[0];
+    c->sweep_la[1] = keep_la[1];
+    for (int i = 0; i < keep_n; ++i) c->sweep_tab[i] = keep_tab[i];
+    c->n_sweep_tab = keep_n;
+    if (rc == 0) {
+        sweep_cfg_store(c, W, T, p->criterion, best_nt[0], best_la[0]);
+        sweep_cfg_store(c, H, T, p->criterion, best_nt[1], best_la[1]);
+    }
+    int r = 512, la = 0, cc = 512;
+    sweep_cfg_for(c, 0, W, T, p->criterion, &r, &la);
+    sweep_cfg_for(c, 1, H, T, p->criterion, &cc, &la);
+    if (rows_out) *rows_out = r;
+    if (cols_out) *cols_out = cc;
     return rc;
+}
+
+// The tuned settings of this context's chain classes: out[4 i + 0..3] = (chain
+// length, frames, threads, look-ahead cap) of entry i (criterion MIE and MLE
+// entries alike); returns the number of entries (at most max_n).
+int voldor_sweep_tuning(const voldor_ctx *c, int *out, int max_n)
+{
+    if (!c || (!out && max_n > 0) || max_n < 0) return VOLDOR_EINVAL;
+    const int n = c->n_sweep_tab < max_n ? c->n_sweep_tab : max_n;
+    for (int i = 0; i < n; ++i) {
+        out[4 * i] = c->sweep_tab[i].L;
+        out[4 * i + 1] = c->sweep_tab[i].T;
+        out[4 * i + 2] = c->sweep_tab[i].nt;
+        out[4 * i + 3] = c->sweep_tab[i].la;
+    }
+    return n;
 }
 
 int voldor_set_timing(voldor_ctx *c, int enable)
 {
     if (!c) return VOLDOR_EINVAL;
     if (enable && !c->timing) {
-        c->ev = (hipEvent_t *)calloc((size_t)kTimingRing * kEvPerWin, sizeof(hipEvent_t));
-        if (!c->ev) return VOLDOR_ENOMEM;
-        // the events only time: without the system-scope fence a record costs a
-        // timestamp, not a writeback and invalidation of every L2 (~5 us of idle
-        // GPU at each phase boundary)
-        for (int i = 0; i < kTimingRing * kEvPerWin; ++i)
-            if (hipEventCreateWithFlags(&c->ev[i], hipEventDisableSystemFence) != hipSuccess) {
-                for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
-                free(c->ev);
-                c->ev = nullptr;
-                return VOLDOR_EDEVICE;
-            }
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
+            return VOLDOR_EDEVICE;
+        c->stamp_khz = (double)khz;
+        c->stamps_host = (unsigned long long *)calloc((size_t)kTimingRing * kEvPerWin, sizeof(unsigned long long));
+        if (!c->stamps_host) return VOLDOR_ENOMEM;
+        if (hipMalloc((void **)&c->stamps, sizeof(unsigned long long) * kTimingRing * kEvPerWin) != hipSuccess) {
+            free(c->stamps_host);
+            c->stamps_host = nullptr;
+            return VOLDOR_ENOMEM;
+        }
         for (int w = 0; w < kTimingRing; ++w) c->ev_n[w] = 0;
         c->tw_count = 0;
         c->timing = 1;
     } else if (!enable && c->timing) {
         (void)hipDeviceSynchronize();
-        for (int i = 0; i < kTimingRing * kEvPerWin; ++i) (void)hipEventDestroy(c->ev[i]);
-        free(c->ev);
-        c->ev = nullptr;
+        (void)hipFree(c->stamps);
+        free(c->stamps_host);
+        c->stamps = nullptr;
+        c->stamps_host = nullptr;
         c->timing = 0;
     }
     return VOLDOR_OK;
@@ -672,6 +749,7 @@ int voldor_timing_summary(voldor_ctx *c, double *out, int *n_windows)
     if (!c->timing) return VOLDOR_EINVAL;
     if (c->tw_count == 0) return VOLDOR_OK;
     if (hipStreamSynchronize(c->last_stream) != hipSuccess) return VOLDOR_EDEVICE;
+    if (fetch_stamps(c) != VOLDOR_OK) return VOLDOR_EDEVICE;
     const long long n = c->tw_count < kTimingRing ? c->tw_count : kTimingRing;
     for (long long k = c->tw_count - n; k < c->tw_count; ++k) {
         double ms8[8];

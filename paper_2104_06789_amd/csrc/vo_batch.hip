@@ -93,7 +93,9 @@ int batch_enqueue(voldor_batch *b, const voldor_window_desc *w, int n, const vol
         const int i = order[k], l = lane_of[i];
         const voldor_window_desc &d = w[i];
         const WindowInit in = {d.init_depth, d.init_rig, d.choice};
-        rc = window_enqueue(b->ctx[l], d.flows, d.T, d.H, d.W, d.K, p, d.poses, d.depth, d.rigidness,
+        voldor_params pw = *p;
+        if (d.n_pose_groups > 0) pw.n_pose_groups = d.n_pose_groups;
+        rc = window_enqueue(b->ctx[l], d.flows, d.T, d.H, d.W, d.K, &pw, d.poses, d.depth, d.rigidness,
                             d.loglik, status_out + i, b->st[l], (d.init_depth && d.init_rig) ? &in : nullptr);
     }
     // the join is recorded even after a failed launch, so that s never runs
@@ -161,6 +163,56 @@ int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols)
     return VOLDOR_OK;
 }
 
+int voldor_batch_autotune(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
+                          void *stream)
+{
+    if (!b || !wins || n < 1 || !p) return VOLDOR_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        bool seen = false;
+        for (int k = 0; k < i && !seen; ++k)
+            seen = wins[k].T == wins[i].T && wins[k].H == wins[i].H && wins[k].W == wins[i].W;
+        if (seen) continue;
+        const voldor_window_desc &d = wins[i];
+        const int rc = voldor_autotune(b->ctx[0], d.flows, d.T, d.H, d.W, d.K, p, nullptr, nullptr, stream);
+        if (rc) return rc;
+    }
+    for (int l = 1; l < b->lanes; ++l) {
+        voldor_ctx *c = b->ctx[l];
+        c->n_sweep_tab = b->ctx[0]->n_sweep_tab;
+        for (int k = 0; k < c->n_sweep_tab; ++k) c->sweep_tab[k] = b->ctx[0]->sweep_tab[k];
+    }
+    drop_graph(b);   // a captured graph holds the old launches
+    return VOLDOR_OK;
+}
+
+int voldor_batch_set_timing(voldor_batch *b, int enable)
+{
+    if (!b) return VOLDOR_EINVAL;
+    for (int l = 0; l < b->lanes; ++l) {
+        const int rc = voldor_set_timing(b->ctx[l], enable);
+        if (rc) return rc;
+    }
+    drop_graph(b);   // a captured graph holds (or lacks) the event records
+    return VOLDOR_OK;
+}
+
+int voldor_batch_timing_summary(voldor_batch *b, double *out, int *n_windows)
+{
+    if (!b || !out) return VOLDOR_EINVAL;
+    for (int i = 0; i < 8; ++i) out[i] = 0.0;
+    int total = 0;
+    for (int l = 0; l < b->lanes; ++l) {
+        double m[8];
+        int n = 0;
+        const int rc = voldor_timing_summary(b->ctx[l], m, &n);
+        if (rc) return rc;
+        for (int i = 0; i < 7; ++i) out[i] += m[i] * n;
+        total += n;
+    }
+    if (n_windows) *n_windows = total;
+    return VOLDOR_OK;
+}
+
 void voldor_batch_destroy(voldor_batch *b)
 {
     if (!b) return;
@@ -180,9 +232,13 @@ int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, 
                         int32_t *status_out, void *stream)
 {
     if (!b || !wins || n < 1 || !status_out || ((uintptr_t)status_out & 3) != 0) return VOLDOR_EINVAL;
+    if (!p) return VOLDOR_EINVAL;
     for (int i = 0; i < n; ++i) {
         const voldor_window_desc &d = wins[i];
-        if (!window_args_ok(b->ctx[0], d.flows, d.T, d.H, d.W, d.K, p, d.poses, d.depth, d.rigidness))
+        if (d.n_pose_groups < 0) return VOLDOR_EINVAL;
+        voldor_params pw = *p;
+        if (d.n_pose_groups > 0) pw.n_pose_groups = d.n_pose_groups;
+        if (!window_args_ok(b->ctx[0], d.flows, d.T, d.H, d.W, d.K, &pw, d.poses, d.depth, d.rigidness))
             return VOLDOR_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;

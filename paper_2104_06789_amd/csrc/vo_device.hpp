@@ -63,22 +63,45 @@ struct EmisParams {
 // hardware reciprocal (v_rcp_f32, about 1 ulp) instead of an IEEE division
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// The depth-independent part of the displacement of a frame-0 pixel with
+// normalised coordinates (xh, yh) in frame f: with P = M (th r),
+// pi(th) - (x, y) = (fx (th ax + bx), fy (th ay + by)) / (th az + tz).
+struct Geo {
+    float ax, ay, az, bx, by, tz;
+};
+
+__device__ __forceinline__ Geo pixel_geometry(const FrameF &f, float xh, float yh)
+{
+    const float e0 = fmaf(f.D[0], xh, fmaf(f.D[1], yh, f.D[2]));
+    const float e1 = fmaf(f.D[3], xh, fmaf(f.D[4], yh, f.D[5]));
+    const float e2 = fmaf(f.D[6], xh, fmaf(f.D[7], yh, f.D[8]));
+    Geo g;
+    g.ax = fmaf(-xh, e2, e0);
+    g.ay = fmaf(-yh, e2, e1);
+    g.az = 1.0f + e2;
+    g.bx = fmaf(-xh, f.t[2], f.t[0]);
+    g.by = fmaf(-yh, f.t[2], f.t[1]);
+    g.tz = f.t[2];
+    return g;
+}
+
+// the displacement at depth th; false if the point is not in front
+__device__ __forceinline__ bool displacement_at(const Geo &g, float th, float fx, float fy, float &dx, float &dy)
+{
+    const float pz = fmaf(th, g.az, g.tz);
+    if (!(pz > 0.0f)) return false;
+    const float inv = frcp(pz);
+    dx = fx * fmaf(th, g.ax, g.bx) * inv;
+    dy = fy * fmaf(th, g.ay, g.by) * inv;
+    return true;
+}
+
 // Displacement pi_t(theta) - (x, y) of the frame-0 pixel with normalised
 // coordinates (xh, yh) at depth th.  False if the point is not in front.
 __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh, float th,
                                              float fx, float fy, float &dx, float &dy)
 {
-    const float e0 = fmaf(f.D[0], xh, fmaf(f.D[1], yh, f.D[2]));
-    const float e1 = fmaf(f.D[3], xh, fmaf(f.D[4], yh, f.D[5]));
-    const float e2 = fmaf(f.D[6], xh, fmaf(f.D[7], yh, f.D[8]));
-    const float ax = fmaf(-xh, e2, e0), ay = fmaf(-yh, e2, e1), az = 1.0f + e2;
-    const float bx = fmaf(-xh, f.t[2], f.t[0]), by = fmaf(-yh, f.t[2], f.t[1]);
-    const float pz = fmaf(th, az, f.t[2]);
-    if (!(pz > 0.0f)) return false;
-    const float inv = frcp(pz);
-    dx = fx * fmaf(th, ax, bx) * inv;
-    dy = fy * fmaf(th, ay, by) * inv;
-    return true;
+    return displacement_at(pixel_geometry(f, xh, yh), th, fx, fy, dx, dy);
 }
 
 // Natural log / exp on the hardware base-2 units (v_log_f32, v_exp_f32):
@@ -107,6 +130,14 @@ __device__ __forceinline__ float softplus(float z)
 {
     return fmaxf(z, 0.0f) + log1p_unit(fast_exp(-fabsf(z)));
 }
+
+// taps_finite: all four taps of a bilinear lookup are finite iff the
+// interpolated u + v is.  Each tap component enters u (or v) through
+// w a + (1 - w) b forms evaluated as fma(w, b - a, a) and sums: a NaN tap
+// propagates, and an infinite one gives +-inf where its weight is nonzero and
+// inf - inf or 0 * inf = NaN where it is zero, whatever the weights; finite
+// taps (flows far below 1e38) give finite u and v.  So the kernels test the
+// interpolated values instead of the eight taps.
 
 // Bilinear sample of flow X (one frame, float2 [H][W]) at (px, py).
 // Domain [0, W-1] x [0, H-1]; all four taps must be finite.

@@ -23,6 +23,13 @@ enum : int { kStatusOk = 0, kStatusDegenerate = -4 };
 constexpr int kTimingRing = 32;   // windows whose phase events are kept
 constexpr int kEvPerWin = 128;    // events per window, at most
 
+// Tuned launch settings of the sweeps for one chain class (chain length,
+// frames, depth criterion): threads per chain and look-ahead cap.
+struct SweepCfg {
+    int L, T, crit, nt, la;
+};
+constexpr int kSweepTab = 16;
+
 // Window-level device parameters shared by all kernels of one call.
 struct WinDims {
     int T, H, W;
@@ -43,6 +50,10 @@ struct voldor_ctx {
     int T_max, H_max, W_max, S_max;
     int max_lds;           // bytes of LDS one workgroup may allocate
     int sweep_nt[2];       // threads per chain of row (directions 0/2) and column (1/3) sweeps
+    int sweep_la[2];       // look-ahead cap of the propagation rounds (0: none), rows and columns
+    // autotuned settings per chain class (override the two defaults above)
+    vo::SweepCfg sweep_tab[vo::kSweepTab];
+    int n_sweep_tab;
     // persistent device state
     double *Mcum;          // [(T_max+1)][12] cumulative poses M_0..M_T
     double *range;         // [4]: d_lo, d_hi, gauge scale, spare
@@ -78,14 +89,17 @@ struct voldor_ctx {
     float *cand_part;      // [n][kCandTiles] partial scores
     double *cand_score;    // [n] scores, dense order
     double *cand_start;    // [8] start point p (6), valid
-    // optional phase timing of windows: HIP events on the caller's stream, one
-    // ring slot per window so that windows enqueued back to back keep theirs
+    // optional phase timing of windows: device timestamps written on the
+    // window's stream, one ring slot per window so that windows enqueued back
+    // to back keep theirs
     int timing;
-    int n_ev;              // events of the window being recorded
+    int n_ev;              // stamps of the window being recorded
     int tw_cur;            // its ring slot
     long long tw_count;    // windows recorded since the last summary
-    hipEvent_t *ev;        // [kTimingRing][kEvPerWin]
-    int ev_phase[vo::kTimingRing][vo::kEvPerWin];   // phase of the interval that ends at an event
+    unsigned long long *stamps;        // device [kTimingRing][kEvPerWin]
+    unsigned long long *stamps_host;   // host copy
+    double stamp_khz;                  // rate of the real-time counter
+    int ev_phase[vo::kTimingRing][vo::kEvPerWin];   // phase of the interval that ends at a stamp
     int ev_launches[vo::kTimingRing][vo::kEvPerWin];   // kernel launches of a sweep interval
     int ev_n[vo::kTimingRing];
     double last_ms[8];
@@ -126,6 +140,10 @@ int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, 
                   hipStream_t s);
 // LDS bytes of one chain of length L with nt threads (256, 512 or 1024)
 size_t sweep_lds_bytes(int T, int L, int criterion, int nt);
+// threads per chain and look-ahead cap of chains of length L (axis 0 rows, 1
+// columns): the tuned entry of this class, else the axis default
+void sweep_cfg_for(const voldor_ctx *c, int axis, int L, int T, int crit, int *nt, int *la);
+void sweep_cfg_store(voldor_ctx *c, int L, int T, int crit, int nt, int la);
 
 // ---- pose (vo_pose.hip)
 int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,

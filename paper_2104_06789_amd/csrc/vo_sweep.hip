@@ -5,7 +5,10 @@
 //
 // One workgroup of kSweepThreads owns one chain (an image row for directions
 // 0/2, a column for 1/3) for all T frames; every phase runs out of LDS:
-//   A  ell_t and r_t of the previous depth, one thread per (position, frame);
+//   A  ell_t and r_t of the previous depth and, for the maximum-inlier
+//      criterion, ell_t of the random sample: one item per (position, frame)
+//      evaluated at both depths, sharing the frame geometry (MLE: log-odds and
+//      log mu of the previous depth; its sample follows phase B);
 //   B  forward-backward per frame: one wave per frame, one chain segment per
 //      lane, 2x2 transfer matrices combined by wave shuffles (prefix and
 //      suffix scans), then each lane replays its segment;
@@ -25,6 +28,10 @@
 namespace vo {
 
 constexpr int kSweepThreads = 512;
+#ifndef VO_PAIR_ITEMS
+#define VO_PAIR_ITEMS 1
+#endif
+constexpr int kPairItems = VO_PAIR_ITEMS;   // items per thread in flight in the paired pass
 constexpr int kSweepWaves = kSweepThreads / 64;
 constexpr float kLogHalf = -0.69314718055994531f;
 
@@ -115,9 +122,9 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
                 float lam = kLogLn2F;
                 if (val[u]) {
                     const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
-                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
                         const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
                         float rr;
                         lam = neg_ell_log(dd, rr);
@@ -128,9 +135,9 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
                 float ell = kLogHalf;
                 if (val[u]) {
                     const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
-                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
                         const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
                         ell = emis_from_d(dd).ell;
                     }
@@ -139,9 +146,9 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             } else {
                 if (val[u]) {
                     const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    if (isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y)) {
-                        const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                        const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
                         float lmu;
                         const float dd = log_mu_and_d<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
                         s += fmaf(-q[(t - 1) * L + k], dd, lmu);
@@ -194,15 +201,84 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const float2 A = ta[b], Bv = tb[b], Cv = tc[b], Dv = td[b];
-        ok[b] = ok[b] && isfinite(A.x + A.y + Bv.x + Bv.y + Cv.x + Cv.y + Dv.x + Dv.y);
         const float vu = (1.0f - ay[b]) * fmaf(ax[b], Bv.x - A.x, A.x) + ay[b] * fmaf(ax[b], Dv.x - Cv.x, Cv.x);
         const float vv = (1.0f - ay[b]) * fmaf(ax[b], Bv.y - A.y, A.y) + ay[b] * fmaf(ax[b], Dv.y - Cv.y, Cv.y);
+        ok[b] = ok[b] && isfinite(vu + vv);   // every tap finite (see taps_finite)
         if constexpr (MU) {
             float lm = 0.0f;
             d[b] = ok[b] ? log_mu_and_d<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e, lm) : 0.0f;
             lmu[b] = ok[b] ? lm : 0.0f;
         } else {
             d[b] = ok[b] ? log_mu_over_rho<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+        }
+    }
+}
+
+// The maximum-inlier pass over B (pixel, frame) items, each evaluated at the
+// previous depth thp and at the random sample ths: the frame geometry of an
+// item is computed once for both depths, and for frame 1 (lookup at the pixel
+// itself) its flow taps are loaded once.  Every log-odds is the same FP32
+// function of (pixel, frame, depth) as in batch_log_odds and chain_score.
+template <int B, int MODEL>
+__device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const float2 *__restrict__ flows, int H,
+                                                    int W, const EmisParams &e, const int *x, const int *y,
+                                                    const float *thp, const float *ths, const int *t,
+                                                    const bool *act, float *dp, float *ds, bool *okp, bool *oks)
+{
+    const int HW = H * W;
+    float dx0[2 * B], dy0[2 * B], dx1[2 * B], dy1[2 * B], ax[2 * B], ay[2 * B];
+    float2 ta[2 * B], tb[2 * B], tc[2 * B], td[2 * B];
+    bool v[2 * B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float xh = ((float)x[b] - e.cx) * e.ifx, yh = ((float)y[b] - e.cy) * e.ify;
+        const int tt = act[b] ? t[b] : 1;
+        const Geo g1 = pixel_geometry(fr[tt], xh, yh);
+        const Geo g0 = pixel_geometry(fr[tt > 1 ? tt - 1 : 0], xh, yh);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = 2 * b + c;
+            const float th = c ? ths[b] : thp[b];
+            bool ok = act[b] && th > 0.0f;
+            dx0[i] = 0.0f;
+            dy0[i] = 0.0f;
+            if (tt > 1) ok = ok && displacement_at(g0, th, e.fx, e.fy, dx0[i], dy0[i]);
+            ok = ok && displacement_at(g1, th, e.fx, e.fy, dx1[i], dy1[i]);
+            const float px = (float)x[b] + dx0[i], py = (float)y[b] + dy0[i];
+            ok = ok && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1);
+            v[i] = ok;
+            const float spx = ok ? px : 0.0f, spy = ok ? py : 0.0f;
+            const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
+            ax[i] = spx - (float)x0;
+            ay[i] = spy - (float)y0;
+            if (c == 1 && tt == 1 && v[2 * b]) {
+                // frame 1: both depths look the flow up at the pixel itself
+                ta[i] = ta[2 * b];
+                tb[i] = tb[2 * b];
+                tc[i] = tc[2 * b];
+                td[i] = td[2 * b];
+            } else {
+                const float2 *r0 = flows + ((ok ? tt - 1 : 0) * HW + y0 * W + x0);
+                ta[i] = r0[0];
+                tb[i] = r0[1];
+                tc[i] = r0[W];
+                td[i] = r0[W + 1];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * B; ++i) {
+        const float2 A = ta[i], Bv = tb[i], Cv = tc[i], Dv = td[i];
+        const float vu = (1.0f - ay[i]) * fmaf(ax[i], Bv.x - A.x, A.x) + ay[i] * fmaf(ax[i], Dv.x - Cv.x, Cv.x);
+        const float vv = (1.0f - ay[i]) * fmaf(ax[i], Bv.y - A.y, A.y) + ay[i] * fmaf(ax[i], Dv.y - Cv.y, Cv.y);
+        const bool ok = v[i] && isfinite(vu + vv);   // every tap finite (see taps_finite)
+        const float d = ok ? log_mu_over_rho<MODEL>((dx1[i] - dx0[i]) - vu, (dy1[i] - dy0[i]) - vv, vu, vv, e) : 0.0f;
+        if (i & 1) {
+            ds[i >> 1] = d;
+            oks[i >> 1] = ok;
+        } else {
+            dp[i >> 1] = d;
+            okp[i >> 1] = ok;
         }
     }
 }
@@ -220,6 +296,7 @@ struct SweepArgs {
     float gamma;
     uint64_t seed;
     int64_t gsweep;
+    int la_cap;            // look-ahead cap of the propagation rounds (0: none)
 };
 
 struct Mat2 {
@@ -306,9 +383,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     int *flg = (int *)(sa + L);                        // [L]   1 if the sample is the local best
     int *nxt = flg + L;                                // [L]   next(k)
     float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
-    float *lq = fq + T * L;                            // region 2: ell(prev), ell(sample), lists, doubling
-    // MLE: region 2 holds d = log(mu/rho) of the previous depth, lmq its log mu
-    float *lmq = lq + sweep_region2_words(T, L, NT);       // [T][L] (MLE only)
+    float *lq = fq + T * L;                            // region 2: ell(prev) (MLE: then the sample's terms), lists, doubling
+    // MIE: ell of the random sample; MLE: region 2 holds d = log(mu/rho) of
+    // the previous depth and lmq its log mu
+    float *lmq = lq + sweep_region2_words(T, L, NT);   // [T][L]
+    float *ls = lmq;
 
     load_frames(a.Mcum, T, fr);
     if (tid == 0) {
@@ -336,8 +415,55 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     }
     __syncthreads();
 
-    // ---- A: ell and r of the previous depth, one item per (position, frame),
-    // four items per thread in flight
+    // ---- A (MIE): ell and r of the previous depth and ell of the random
+    // sample, one item per (position, frame) evaluated at both depths, two
+    // items per thread in flight
+    if constexpr (CRIT == 0) {
+        constexpr int PB = kPairItems;
+        for (int i0 = tid; i0 < T * L; i0 += PB * NT) {
+            int xs[PB], ys[PB], ts[PB];
+            float thp[PB], ths[PB], dp[PB], ds[PB];
+            bool act[PB], okp[PB], oks[PB];
+            // item i = (t - 1) L + k; the thread's items are NT apart
+            int t = i0 / L + 1, k = i0 - (t - 1) * L;
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                act[b] = i0 + b * NT < T * L;
+                const int kk = act[b] ? k : 0;
+                chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
+                ts[b] = act[b] ? t : 1;
+                thp[b] = th[kk];
+                ths[b] = sm[kk];
+                k += NT;
+                while (k >= L) { k -= L; ++t; }
+            }
+            batch_log_odds_pair<PB, MODEL>(fr, a.flows, H, W, a.e, xs, ys, thp, ths, ts, act, dp, ds, okp, oks);
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                const int i = i0 + b * NT;
+                if (!act[b]) continue;
+                float ell = LOGS ? kLogLn2F : kLogHalf, r = 0.5f, els = LOGS ? kLogLn2F : kLogHalf;
+                if constexpr (LOGS) {
+                    if (okp[b]) ell = neg_ell_log(dp[b], r);
+                    float rs;
+                    if (oks[b]) els = neg_ell_log(ds[b], rs);
+                } else {
+                    if (okp[b]) {
+                        const Emis m = emis_from_d(dp[b]);
+                        ell = m.ell;
+                        r = m.r;
+                    }
+                    if (oks[b]) els = emis_from_d(ds[b]).ell;
+                }
+                lq[i] = ell;
+                fq[i] = r;
+                ls[i] = els;
+            }
+        }
+    }
+    // ---- A (MLE): log-odds and log mu of the previous depth, four items per
+    // thread in flight (the sample follows the E-step: its terms need q)
+    if constexpr (CRIT == 1)
     for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
         int xs[4], ys[4], ts[4];
         float ths[4], dd[4];
@@ -354,26 +480,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             k += NT;
             while (k >= L) { k -= L; ++t; }
         }
-        if constexpr (CRIT == 0) {
-            batch_log_odds<4, MODEL>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * NT;
-                if (!act[b]) continue;
-                float ell = LOGS ? kLogLn2F : kLogHalf, r = 0.5f;
-                if (ok[b]) {
-                    if constexpr (LOGS) {
-                        ell = neg_ell_log(dd[b], r);
-                    } else {
-                        const Emis m = emis_from_d(dd[b]);
-                        ell = m.ell;
-                        r = m.r;
-                    }
-                }
-                lq[i] = ell;
-                fq[i] = r;
-            }
-        } else {
+        {
             float lm[4];
             batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
@@ -476,53 +583,54 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
         }
     }
 
-    // ---- S: score of the previous depth
-    for (int k = tid; k < L; k += NT) {
-        float s = 0.0f;
-        if constexpr (LOGS) {
-            LogScore ls = logscore_init();
-            for (int t = 0; t < T; ++t) logscore_add(ls, fq[t * L + k], lq[t * L + k]);
-            s = logscore_value(ls);
-        } else if constexpr (CRIT == 0) {
-            for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
-        } else {
-            for (int t = 0; t < T; ++t) s += fmaf(-fq[t * L + k], lq[t * L + k], lmq[t * L + k]);
-        }
-        sa[k] = s;
-    }
-    __syncthreads();
-    // ell of the random sample, one item per (position, frame)
-    for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
-        int xs[4], ys[4], ts[4];
-        float ths[4], dd[4];
-        bool act[4], ok[4];
-        // item i = (t - 1) L + k; the thread's items are NT apart
-        int t = i0 / L + 1, k = i0 - (t - 1) * L;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            act[b] = i0 + b * NT < T * L;
-            const int kk = act[b] ? k : 0;
-            chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
-            ts[b] = act[b] ? t : 1;
-            ths[b] = sm[kk];
-            k += NT;
-            while (k >= L) { k -= L; ++t; }
-        }
-        if constexpr (CRIT == 0) {
-            batch_log_odds<4, MODEL>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = i0 + b * NT;
-                if constexpr (LOGS) {
-                    float rr;
-                    if (act[b]) lq[i] = ok[b] ? neg_ell_log(dd[b], rr) : kLogLn2F;
-                } else {
-                    if (act[b]) lq[i] = ok[b] ? emis_from_d(dd[b]).ell : kLogHalf;
+    // ---- S: scores of the previous depth and of the sample; the local best
+    if constexpr (CRIT == 0) {
+        for (int k = tid; k < L; k += NT) {
+            float sp = 0.0f, ss = 0.0f;
+            if constexpr (LOGS) {
+                LogScore lp = logscore_init(), lz = logscore_init();
+                for (int t = 0; t < T; ++t) {
+                    logscore_add(lp, fq[t * L + k], lq[t * L + k]);
+                    logscore_add(lz, fq[t * L + k], ls[t * L + k]);
+                }
+                sp = logscore_value(lp);
+                ss = logscore_value(lz);
+            } else {
+                for (int t = 0; t < T; ++t) {
+                    sp = fmaf(fq[t * L + k], lq[t * L + k], sp);
+                    ss = fmaf(fq[t * L + k], ls[t * L + k], ss);
                 }
             }
-        } else {
-            // the sample's whole term log mu - q d (0 where missing)
-            float lm[4];
+            const bool smp = ss > sp;
+            aval[k] = smp ? sm[k] : th[k];
+            sa[k] = smp ? ss : sp;
+            flg[k] = smp ? 1 : 0;
+        }
+    } else {
+        for (int k = tid; k < L; k += NT) {
+            float s = 0.0f;
+            for (int t = 0; t < T; ++t) s += fmaf(-fq[t * L + k], lq[t * L + k], lmq[t * L + k]);
+            sa[k] = s;
+        }
+        __syncthreads();
+        // the sample's whole term log mu - q d (0 where missing), one item per
+        // (position, frame)
+        for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
+            int xs[4], ys[4], ts[4];
+            float ths[4], dd[4], lm[4];
+            bool act[4], ok[4];
+            // item i = (t - 1) L + k; the thread's items are NT apart
+            int t = i0 / L + 1, k = i0 - (t - 1) * L;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                act[b] = i0 + b * NT < T * L;
+                const int kk = act[b] ? k : 0;
+                chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
+                ts[b] = act[b] ? t : 1;
+                ths[b] = sm[kk];
+                k += NT;
+                while (k >= L) { k -= L; ++t; }
+            }
             batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -530,25 +638,17 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b], lm[b]) : 0.0f;
             }
         }
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += NT) {
-        float s = 0.0f;
-        if constexpr (LOGS) {
-            LogScore ls = logscore_init();
-            for (int t = 0; t < T; ++t) logscore_add(ls, fq[t * L + k], lq[t * L + k]);
-            s = logscore_value(ls);
-        } else if constexpr (CRIT == 0) {
-            for (int t = 0; t < T; ++t) s = fmaf(fq[t * L + k], lq[t * L + k], s);
-        } else {
+        __syncthreads();
+        for (int k = tid; k < L; k += NT) {
+            float s = 0.0f;
             for (int t = 0; t < T; ++t) s += lq[t * L + k];
+            const bool smp = s > sa[k];
+            aval[k] = smp ? sm[k] : th[k];
+            if (smp) sa[k] = s;
+            flg[k] = smp ? 1 : 0;
         }
-        const bool smp = s > sa[k];
-        aval[k] = smp ? sm[k] : th[k];
-        if (smp) sa[k] = s;
-        flg[k] = smp ? 1 : 0;
     }
-    __syncthreads();   // the live lists below reuse the sample's ell area
+    __syncthreads();   // the live lists below reuse region 2
     // live origins (origin, next position to test), starting at k+1; a local
     // best equal to the previous depth at k+1 scores exactly that depth there
     // and loses (the previous depth wins ties), so next(k) = k+1 at once
@@ -575,7 +675,8 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
         if (n == 0) break;
         int2 *lc = cur ? list1 : list0, *ln = cur ? list0 : list1;
         int *first = cur ? first1 : first0, *firstn = cur ? first0 : first1;
-        const int la = max(NT / n, 1);   // look-ahead per live origin
+        int la = max(NT / n, 1);   // look-ahead per live origin
+        if (a.la_cap > 0 && la > a.la_cap) la = a.la_cap;
         const int items = n * la;
         const float ila = frcp((float)la);
         for (int i = tid; i < items; i += NT) {
@@ -584,7 +685,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             const int2 e = lc[sl];
             const int jpos = e.y + p;
             bool w = false;
-            if (jpos < L && !(aval[e.x] == th[jpos])) {   // equal to the previous depth: loses
+            if (jpos < L && flg[jpos] && aval[e.x] == sm[jpos]) {
+                // the sample of jpos is its local best and has this very value:
+                // the same score, and the neighbour wins the tie
+                w = true;
+            } else if (jpos < L && !(aval[e.x] == th[jpos])) {   // equal to the previous depth: loses
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
@@ -718,9 +823,9 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                 if (t > a.T) break;
                 float r = 0.5f, ell = -0.69314718055994531f, lr = 0.0f, lm = 0.0f;
                 const float2 A = ta[u], B = tb[u], Cc = tc[u], D = td[u];
-                if (val[u] && isfinite(A.x + A.y + B.x + B.y + Cc.x + Cc.y + D.x + D.y)) {
-                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], B.x - A.x, A.x) + ay[u] * fmaf(ax[u], D.x - Cc.x, Cc.x);
-                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], B.y - A.y, A.y) + ay[u] * fmaf(ax[u], D.y - Cc.y, Cc.y);
+                const float vu = (1.0f - ay[u]) * fmaf(ax[u], B.x - A.x, A.x) + ay[u] * fmaf(ax[u], D.x - Cc.x, Cc.x);
+                const float vv = (1.0f - ay[u]) * fmaf(ax[u], B.y - A.y, A.y) + ay[u] * fmaf(ax[u], D.y - Cc.y, Cc.y);
+                if (val[u] && isfinite(vu + vv)) {   // every tap finite (see taps_finite)
                     const float rx = (dx1[u] - bx[u]) - vu, ry = (dy1[u] - by[u]) - vv;
                     const float d = a.e.model ? log_mu_over_rho<1>(rx, ry, vu, vv, a.e)
                                               : log_mu_over_rho<0>(rx, ry, vu, vv, a.e);
@@ -814,8 +919,39 @@ __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t
 // ---------------------------------------------------------------------------
 size_t sweep_lds_bytes(int T, int L, int criterion, int nt)
 {
-    return ((size_t)(6 + T) * L + (size_t)sweep_region2_words(T, L, nt) + (criterion ? (size_t)T * L : 0)) *
-           sizeof(float);
+    // both criteria hold a third [T][L] array: MIE the sample's ell, MLE log mu
+    (void)criterion;
+    return ((size_t)(6 + 2 * T) * L + (size_t)sweep_region2_words(T, L, nt)) * sizeof(float);
+}
+
+void sweep_cfg_for(const voldor_ctx *c, int axis, int L, int T, int crit, int *nt, int *la)
+{
+    *nt = c->sweep_nt[axis];
+    *la = c->sweep_la[axis];
+    for (int i = 0; i < c->n_sweep_tab; ++i) {
+        const SweepCfg &e = c->sweep_tab[i];
+        if (e.L == L && e.T == T && e.crit == crit) {
+            *nt = e.nt;
+            *la = e.la;
+            return;
+        }
+    }
+}
+
+void sweep_cfg_store(voldor_ctx *c, int L, int T, int crit, int nt, int la)
+{
+    int slot = -1;
+    for (int i = 0; i < c->n_sweep_tab; ++i)
+        if (c->sweep_tab[i].L == L && c->sweep_tab[i].T == T && c->sweep_tab[i].crit == crit) slot = i;
+    if (slot < 0) {
+        if (c->n_sweep_tab < kSweepTab) {
+            slot = c->n_sweep_tab++;
+        } else {   // full: drop the oldest entry
+            for (int i = 1; i < kSweepTab; ++i) c->sweep_tab[i - 1] = c->sweep_tab[i];
+            slot = kSweepTab - 1;
+        }
+    }
+    c->sweep_tab[slot] = SweepCfg{L, T, crit, nt, la};
 }
 
 template <int CRIT, int NT, int MODEL>
@@ -835,7 +971,8 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
 {
     const int L = (dir & 1) ? d.H : d.W;
     const int nchain = (dir & 1) ? d.W : d.H;
-    const int nt = c->sweep_nt[dir & 1];
+    int nt = 512, la = 0;
+    sweep_cfg_for(c, dir & 1, L, d.T, criterion, &nt, &la);
     const size_t lds = sweep_lds_bytes(d.T, L, criterion, nt);
     if (L < 16) return VOLDOR_EINVAL;
     SweepArgs a;
@@ -854,6 +991,7 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.gamma = gamma;
     a.seed = seed;
     a.gsweep = gsweep;
+    a.la_cap = la;
     switch ((nt * 2 + (criterion ? 1 : 0)) * 2 + (e.model ? 1 : 0)) {
     case 1024: return launch_sweep_nt<0, 256, 0>(a, nchain, lds, s);
     case 1025: return launch_sweep_nt<0, 256, 1>(a, nchain, lds, s);

@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["WindowSpec", "SPECS", "make_window", "make_batch", "BATCH_SHAPES", "rot_axis_angle"]
+__all__ = ["WindowSpec", "SPECS", "make_window", "make_batch", "BATCH_SHAPES", "BATCH_GROUPS", "rot_axis_angle"]
 
 
 @dataclass
@@ -392,8 +392,11 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
 
 
 # shapes of a mixed batch: (generator, W, H); the 320x240 windows use the
-# indoor generator with its intrinsics scaled to the smaller image
-BATCH_SHAPES = (("indoor", 320, 240), ("indoor", 640, 480), ("driving", 1242, 375))
+# CPU-sized generator with its intrinsics scaled x2, 640x480 the indoor one,
+# 1242x375 the driving one
+BATCH_SHAPES = (("small", 320, 240), ("indoor", 640, 480), ("driving", 1242, 375))
+# P3P groups per frame of a batch window, by shape
+BATCH_GROUPS = {(320, 240): 1024, (640, 480): 2048, (1242, 375): 4096}
 
 
 def _batch_item(args):

@@ -1,9 +1,11 @@
-"""Sweep widths (threads per chain) and the autotuner, through the C ABI.
+"""Sweep widths (threads per chain), look-ahead caps and the autotuner, through
+the C ABI.
 
-Every width (256, 512, 1024 threads per chain) computes each item with the same
-FP32 function and the propagation's first losses exactly, so the depth of a
-sweep, and a whole window, must be the same bit for bit at every width; the
-autotuner only picks the fastest.
+Every width (256, 512, 1024 threads per chain) and every look-ahead cap of the
+propagation rounds computes each item with the same FP32 function and the
+propagation's first losses exactly, so the depth of a sweep, and a whole
+window, must be the same bit for bit at every setting; the autotuner only
+picks the fastest, per chain class.
 """
 import numpy as np
 import pytest
@@ -46,17 +48,18 @@ def test_sweep_widths_bit_identical(vo, torch, criterion):
     s = vo.Solver(T, H, W, 256)
     d_lo, d_hi = 0.5 * float(gt.min()), 2.0 * float(gt.max())
     ref = {}
-    for nt in (512, 256, 1024):
+    for nt, cap in ((512, 0), (256, 0), (1024, 0), (512, 1), (256, 3), (1024, 16)):
         s.set_sweep_threads(nt, nt)
-        assert s.sweep_threads() == (nt, nt)
+        s.set_sweep_lookahead(cap, cap)
+        assert s.sweep_threads() == (nt, nt) and s.sweep_lookahead() == (cap, cap)
         for direction in range(4):
             out, q = s.sweep(theta, fl, w["K"], p, M, d_lo, d_hi, 3 + direction, direction, want_q=True)
             torch.cuda.synchronize()
-            if nt == 512:
+            if (nt, cap) == (512, 0):
                 ref[direction] = (out.clone(), q.clone())
             else:
-                assert torch.equal(out, ref[direction][0]), (nt, direction)
-                assert torch.equal(q, ref[direction][1]), (nt, direction)
+                assert torch.equal(out, ref[direction][0]), (nt, cap, direction)
+                assert torch.equal(q, ref[direction][1]), (nt, cap, direction)
 
 
 def test_window_widths_and_autotune(vo, torch):
@@ -72,13 +75,54 @@ def test_window_widths_and_autotune(vo, torch):
         out = s.window(fl, w["K"], p)
         for a, b in zip(out, ref):
             assert torch.equal(a, b), (rows, cols)
+    s.set_sweep_lookahead(2, 5)
+    out = s.window(fl, w["K"], p)
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
     rows, cols = s.autotune(fl, w["K"], p)
     assert rows in (256, 512, 1024) and cols in (256, 512, 1024)
-    assert s.sweep_threads() == (rows, cols)
+    tab = s.sweep_tuning()
+    print(tab)
+    assert (W, T, rows) == tab[0][:3] and (H, T, cols) == tab[1][:3]
+    assert tab[0][3] in (0, 4, 8, 16) and tab[1][3] in (0, 4, 8, 16)
     out = s.window(fl, w["K"], p)
     for a, b in zip(out, ref):
         assert torch.equal(a, b)
     with pytest.raises(vo.VoldorError):
         s.set_sweep_threads(384, 512)
+    with pytest.raises(vo.VoldorError):
+        s.set_sweep_lookahead(-1, 0)
     s.set_sweep_threads(0, 0)
-    assert s.sweep_threads() == (512, 512)
+    assert s.sweep_threads() == (512, 512) and s.sweep_tuning() == []
+
+
+def test_batch_autotune_keeps_results(vo, torch):
+    # per-window P3P groups and the batch autotuner: results equal the single
+    # windows solved with those groups, before and after tuning
+    wins = [synthflow.make_window("small", sd, T=T, H=H, W=W) for sd, T, H, W in
+            ((1, 3, 48, 64), (2, 4, 40, 72), (3, 3, 48, 64))]
+    groups = (96, 128, 64)
+    p = vo.default_params(n_iters=2, n_pose_groups=200)
+    flows = [torch.from_numpy(w["flows"]).cuda() for w in wins]
+    refs = []
+    for f, w, g in zip(flows, wins, groups):
+        T, H, W = f.shape[:3]
+        s = vo.Solver(T, H, W, 256)
+        refs.append([x.clone() for x in s.window(f, w["K"], vo.default_params(n_iters=2, n_pose_groups=g))])
+        s.close()
+    b = vo.Batch(2, 4, 48, 72, 256, graph=True)
+    outs = [vo.Batch.outputs(*f.shape[:3]) for f in flows]
+    items = [(f, w["K"], o, None, g) for f, w, o, g in zip(flows, wins, outs, groups)]
+    st = torch.full((3,), -9, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    for tune in (False, True):
+        if tune:
+            b.autotune(items, p, stream=stream)
+        with torch.cuda.stream(stream):
+            b.solve(items, p, st, stream=stream)
+        torch.cuda.synchronize()
+        assert st.cpu().tolist() == [0, 0, 0]
+        for o, r in zip(outs, refs):
+            for a, c in zip(o, r):
+                assert torch.equal(a, c), tune
+    b.close()
