@@ -41,10 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
-# profiles/k_sweep_indoor_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 25909.9453125 * 1024 * 1.99980,
-                        "write_bytes": 1249.0390625 * 1024 * 1.0}
-SWEEP_SOURCES_SHA = "2874f55bd8b6a519"
+# profiles/k_sweep_hbm_traffic.md)
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 42.11e6, "write_bytes": 1.23e6}
+SWEEP_SOURCES_SHA = "e28cd4b197fcc2d0"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz = 39.3 T/s; the all-pixel candidate scoring (--pose-start
@@ -342,6 +341,7 @@ def run_batch(args):
                      "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid() else None,
                      "alg_bytes_per_launch": alg_bytes / max(launches, 1.0),
                      "launch_ms": ph["sweeps"] / max(launches, 1.0), "launches": launches,
+                     "step_aggregate_GBs": alg_bytes / (ms * 1e-3) / 1e9,
                      "note": "algorithmic bytes of a sweep: the flow stack read once (8 B per pixel-frame) and the "
                              "depth read and written (8 B per pixel); launch time = the sweep intervals between device "
                              "timestamps on the lane streams during the last timed step (the graph replays them; "
@@ -364,8 +364,8 @@ def run_batch(args):
 # HBM traffic of the sweeps of one batch step (rocprofv3 FETCH_SIZE + WRITE_SIZE
 # of k_sweep, summed over the step's launches, per launch, scaled by the copy
 # calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
-BATCH_SWEEP_TRAFFIC_PER_LAUNCH = None
-BATCH_SWEEP_SOURCES_SHA = None
+BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (34.70 + 1.37) * 1e6   # profiles/k_sweep_hbm_traffic.md
+BATCH_SWEEP_SOURCES_SHA = "e28cd4b197fcc2d0"
 
 
 def _batch_sweep_traffic_valid():
