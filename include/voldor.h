@@ -430,6 +430,13 @@ int voldor_pose_step(voldor_ctx *ctx, const float *theta, const float *rig, cons
  * has run. */
 int voldor_pose_scores(voldor_ctx *ctx, double *scores, int max_n, int *n_out);
 
+/* The depth sampling range [d_lo, d_hi] of the last window run on this context,
+ * in the gauge its outputs are in (the bootstrap's P1 / 2 and 2 P99, Sec. 5.3,
+ * rescaled with the depth after every iteration): host double[2].  Waits for the
+ * device.  With the window's outputs it is the whole state an EM iteration
+ * starts from. */
+int voldor_last_range(voldor_ctx *ctx, double *range2);
+
 /* Bootstrap (Sec. 5.3): T_1 by least median of squares over 8-point
  * essential-matrix hypotheses of X_1, depth by two-view triangulation, the
  * depth sampling range [0.5 P1, 2 P99] of the triangulated depths.

@@ -95,6 +95,7 @@ def lib():
             "or_lookup": (C.c_int, [f, i, i, i, i, C.c_double, C.c_double, d]),
             "or_null_vector_8x9": (None, [d, d]),
             "or_set_f32_range": (None, [i]),
+            "or_window_from_state": (C.c_int, [f, i, i, i, d, P, i, d, d, d, d, d, d, d, d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -456,3 +457,20 @@ def window_init(flows, K, p, init_depth, init_rig):
                               _ptr(_d(init_rig)), _ptr(poses), _ptr(depth), _ptr(rig), _ptr(ll), _ptr(diag),
                               C.byref(choice))
     return st, poses, depth, rig, (ll[0], ll[1]), diag, choice.value
+
+
+def window_from_state(flows, K, p, it0, rel, depth, rig, rng):
+    """The iterations it0 .. n_iters - 1 from a given start-of-iteration state
+    (relative poses [T,12] in the gauge |t_1| = 1, depth [H,W], the previous
+    iteration's rigidness [T,H,W], depth range [2]); returns (status, poses,
+    depth, rigidness, (L, L1 mass)) like window()."""
+    flows = _flows(flows)
+    T, H, W, _ = flows.shape
+    poses = np.zeros((T, 12))
+    dout = np.zeros((H, W))
+    rout = np.zeros((T, H, W))
+    ll = np.zeros(2)
+    st = lib().or_window_from_state(_ptr(flows, C.c_float), T, H, W, _ptr(_d(K)), C.byref(p), int(it0),
+                                    _ptr(_d(rel)), _ptr(_d(depth)), _ptr(_d(rig)), _ptr(_d(rng)), _ptr(poses),
+                                    _ptr(dout), _ptr(rout), _ptr(ll))
+    return st, poses, dout, rout, (ll[0], ll[1])

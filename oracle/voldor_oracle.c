@@ -1519,6 +1519,64 @@ static void pose_pass(const float *flows, int T, int H, int W, const double *K, 
     }
 }
 
+/* One EM iteration of Table 1 (iteration index `it`, which sets the random
+ * draws): the pose of every frame (unless with_pose is 0), the directional
+ * sweeps, the unsmoothed rigidness, then the scale gauge |t_1| = 1 applied to
+ * the depth, the translations and the depth range. */
+static void em_iteration(const float *flows, int T, int H, int W, const double *K, const or_params *p, int it,
+                         int with_pose, double *rel, double *M, double *depth, double *rig, int have_w,
+                         double *range, int *fallbacks, int *ms_total)
+{
+    size_t HW = (size_t)H * W;
+    or_frame_set F = {flows, T, H, W, K[0], K[1], K[2], K[3]};
+    if (with_pose) pose_pass(flows, T, H, W, K, p, depth, have_w ? rig : NULL, it, rel, M, fallbacks, ms_total);
+    for (int s = 0; s < p->sweeps_per_iter; ++s) {
+        int64_t gs = (int64_t)it * p->sweeps_per_iter + s;
+        or_sweep(depth, depth, flows, T, H, W, K, p, M, range[0], range[1], gs, (int)(gs % 4), NULL, NULL);
+    }
+    /* rigidness without smoothing (last row of Table 1) */
+    for (int t = 1; t <= T; ++t)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x)
+                rig[(size_t)(t - 1) * HW + (size_t)y * W + x] = emission(&F, p, M, t, x, y, depth[(size_t)y * W + x]).r;
+    /* scale gauge: |t_1| = 1 */
+    double sc = norm3(rel + 9);
+    if (sc > 0) {
+        for (size_t j = 0; j < HW; ++j) depth[j] /= sc;
+        for (int t = 1; t <= T; ++t)
+            for (int k = 0; k < 3; ++k) rel[12 * (t - 1) + 9 + k] /= sc;
+        range[0] /= sc;
+        range[1] /= sc;
+    }
+}
+
+/* Log-likelihood of Eq. 3 under the final rigidness (Kahan sums), and its L1
+ * mass: loglik_out[0], loglik_out[1] (if loglik_out). */
+static void final_loglik(const or_frame_set *F, const or_params *p, const double *rel, double *M,
+                         const double *depth, const double *rig, double *loglik_out)
+{
+    const int T = F->T, H = F->H, W = F->W;
+    const size_t HW = (size_t)H * W;
+    cumulative(rel, T, M);
+    double L = 0, Lc = 0, A = 0, Ac = 0;
+    for (int t = 1; t <= T; ++t)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t j = (size_t)y * W + x;
+                or_emis e = emission(F, p, M, t, x, y, depth[j]);
+                if (!e.observed) continue;
+                double w = rig[(size_t)(t - 1) * HW + j];
+                double term = w * e.logrho + (1 - w) * e.logmu;
+                double yk = term - Lc, tk = L + yk;
+                Lc = (tk - L) - yk;
+                L = tk;
+                double ya = fabs(term) - Ac, ta = A + ya;
+                Ac = (ta - A) - ya;
+                A = ta;
+            }
+    if (loglik_out) { loglik_out[0] = L; loglik_out[1] = A; }
+}
+
 static int window_core(const float *flows, int T, int H, int W, const double *K, const or_params *p,
                        const double *init_depth, const double *init_rig, double *poses_out,
                        double *depth_out, double *rig_out, double *loglik_out, double *diag_out,
@@ -1565,50 +1623,11 @@ static int window_core(const float *flows, int T, int H, int W, const double *K,
         first_pass_done = 1;
     }
     for (int it = 0; it < p->n_iters; ++it) {
-        if (!(it == 0 && first_pass_done))
-            pose_pass(flows, T, H, W, K, p, depth_out, have_w ? rig_out : NULL, it, rel, M, &fallbacks,
-                      &ms_total);
-        for (int s = 0; s < p->sweeps_per_iter; ++s) {
-            int64_t gs = (int64_t)it * p->sweeps_per_iter + s;
-            or_sweep(depth_out, depth_out, flows, T, H, W, K, p, M, range[0], range[1], gs,
-                     (int)(gs % 4), NULL, NULL);
-        }
-        /* rigidness without smoothing (last row of Table 1) */
-        for (int t = 1; t <= T; ++t)
-            for (int y = 0; y < H; ++y)
-                for (int x = 0; x < W; ++x)
-                    rig_out[(size_t)(t - 1) * HW + (size_t)y * W + x] =
-                        emission(&F, p, M, t, x, y, depth_out[(size_t)y * W + x]).r;
+        em_iteration(flows, T, H, W, K, p, it, !(it == 0 && first_pass_done), rel, M, depth_out, rig_out,
+                     have_w, range, &fallbacks, &ms_total);
         have_w = 1;
-        /* scale gauge: |t_1| = 1 */
-        double s = norm3(rel + 9);
-        if (s > 0) {
-            for (size_t j = 0; j < HW; ++j) depth_out[j] /= s;
-            for (int t = 1; t <= T; ++t)
-                for (int k = 0; k < 3; ++k) rel[12 * (t - 1) + 9 + k] /= s;
-            range[0] /= s;
-            range[1] /= s;
-        }
     }
-    /* log-likelihood of Eq. 3 under the final rigidness (Kahan sums) */
-    cumulative(rel, T, M);
-    double L = 0, Lc = 0, A = 0, Ac = 0;
-    for (int t = 1; t <= T; ++t)
-        for (int y = 0; y < H; ++y)
-            for (int x = 0; x < W; ++x) {
-                size_t j = (size_t)y * W + x;
-                or_emis e = emission(&F, p, M, t, x, y, depth_out[j]);
-                if (!e.observed) continue;
-                double w = rig_out[(size_t)(t - 1) * HW + j];
-                double term = w * e.logrho + (1 - w) * e.logmu;
-                double yk = term - Lc, tk = L + yk;
-                Lc = (tk - L) - yk;
-                L = tk;
-                double ya = fabs(term) - Ac, ta = A + ya;
-                Ac = (ta - A) - ya;
-                A = ta;
-            }
-    if (loglik_out) { loglik_out[0] = L; loglik_out[1] = A; }
+    final_loglik(&F, p, rel, M, depth_out, rig_out, loglik_out);
     if (diag_out) {
         diag_out[0] = binfo[0]; diag_out[1] = binfo[1]; diag_out[2] = range[0]; diag_out[3] = range[1];
         diag_out[4] = fallbacks; diag_out[5] = ms_total; diag_out[6] = binfo[2]; diag_out[7] = binfo[3];
@@ -1645,4 +1664,34 @@ int or_window_init(const float *flows, int T, int H, int W, const double *K, con
     if (!init_depth || !init_rig) return OR_EINVAL;
     return window_core(flows, T, H, W, K, p, init_depth, init_rig, poses_out, depth_out, rig_out,
                        loglik_out, diag_out, choice_out, NULL);
+}
+
+/* Test hook: the iterations it0 .. n_iters - 1 of a window from a given state
+ * at the start of iteration it0 (relative poses rel_in [T][12] in the gauge
+ * |t_1| = 1, depth_in [H][W], the rigidness rig_in [T][H][W] of the previous
+ * iteration, which weights the pose samples, and the depth range
+ * range_in[2]), then the log-likelihood: the EM from another implementation's
+ * state, one iteration at a time.  Outputs as or_window. */
+int or_window_from_state(const float *flows, int T, int H, int W, const double *K, const or_params *p, int it0,
+                         const double *rel_in, const double *depth_in, const double *rig_in,
+                         const double *range_in, double *poses_out, double *depth_out, double *rig_out,
+                         double *loglik_out)
+{
+    if (!flows || !K || !p || !rel_in || !depth_in || !rig_in || !range_in || !poses_out || !depth_out || !rig_out)
+        return OR_EINVAL;
+    if (!params_ok(p, T, H, W, K) || it0 < 1 || it0 >= p->n_iters) return OR_EINVAL;
+    size_t HW = (size_t)H * W;
+    or_frame_set F = {flows, T, H, W, K[0], K[1], K[2], K[3]};
+    double *M = (double *)malloc(sizeof(double) * 12 * (T + 1));
+    double range[2] = {range_in[0], range_in[1]};
+    memcpy(poses_out, rel_in, sizeof(double) * 12 * T);
+    memcpy(depth_out, depth_in, sizeof(double) * HW);
+    memcpy(rig_out, rig_in, sizeof(double) * HW * T);
+    cumulative(poses_out, T, M);
+    int fallbacks = 0, ms_total = 0;
+    for (int it = it0; it < p->n_iters; ++it)
+        em_iteration(flows, T, H, W, K, p, it, 1, poses_out, M, depth_out, rig_out, 1, range, &fallbacks, &ms_total);
+    final_loglik(&F, p, poses_out, M, depth_out, rig_out, loglik_out);
+    free(M);
+    return OR_OK;
 }

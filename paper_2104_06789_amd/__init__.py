@@ -88,6 +88,7 @@ def lib():
         "voldor_sweep": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, d, d, C.c_int64, i, vp, vp]),
         "voldor_pose_step": (i, [vp, vp, vp, vp, i, i, i, dp, P, dp, i, i, dp, dp, vp, ip, vp]),
         "voldor_pose_scores": (i, [vp, dp, i, ip]),
+        "voldor_last_range": (i, [vp, dp]),
         "voldor_window_seeded": (i, [vp, vp, i, i, i, dp, P, vp, vp, vp, vp, vp, vp, vp]),
         "voldor_vo_windows": (i, [i, i, i]),
         "voldor_set_sweep_threads": (i, [vp, i, i]),
@@ -514,6 +515,12 @@ class Solver:
         n = lib().voldor_sweep_tuning(self._ctx, buf, 16)
         _check(n if n < 0 else 0, "voldor_sweep_tuning")
         return [tuple(buf[4 * i:4 * i + 4]) for i in range(n)]
+
+    def last_range(self):
+        """[d_lo, d_hi] of the last window on this context, in its output gauge."""
+        out = np.zeros(2)
+        _check(lib().voldor_last_range(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))), "voldor_last_range")
+        return out
 
     def pose_scores(self):
         """All-pixel candidate scores of the last pose step run with pose_start=1:

@@ -805,6 +805,14 @@ int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     return hipStreamSynchronize(s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
 }
 
+int voldor_last_range(voldor_ctx *c, double *range2)
+{
+    if (!c || !range2) return VOLDOR_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return VOLDOR_EDEVICE;
+    return hipMemcpy(range2, c->range, sizeof(double) * 2, hipMemcpyDeviceToHost) == hipSuccess ? VOLDOR_OK
+                                                                                                 : VOLDOR_EDEVICE;
+}
+
 int voldor_pose_scores(voldor_ctx *c, double *scores, int max_n, int *n_out)
 {
     if (!c || !scores || !n_out || max_n < 1) return VOLDOR_EINVAL;

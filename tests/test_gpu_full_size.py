@@ -23,6 +23,11 @@ coordinate (rounding 2^-24 x 1242 px ~ 7e-5 px) landing on a flow
 discontinuity (outlier boxes, depth edges): there the oracle's own r moves by
 up to 0.46 under a 1e-6 relative change of the depth.
 
+The last EM iteration is compared with the oracle's iteration from the GPU's
+own state at its start (teacher forcing): poses, median depth and rigidness at
+the 99.9th percentile meet the benchmark spec's tolerances, and every rigidness
+excess sits at a pixel whose depth decision went the other way.
+
 The whole window is compared with the oracle's whole window against the north
 star tolerances or, where larger, twice the oracle's own response to a 1e-5 px
 Gaussian perturbation of the flows (two seeds).  FP32 evaluation of a
@@ -246,3 +251,49 @@ def test_full_pose_step(vo, torch, name):
           "tdir", _tdir_angle(Tg[9:], To[9:]))
     assert _rot_angle(Tg[:9].reshape(3, 3), To[:9].reshape(3, 3)) < 1e-4
     assert _tdir_angle(Tg[9:], To[9:]) < 1e-4
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_full_window_teacher_forced(vo, torch, name):
+    # the last EM iteration of the GPU's window against the oracle's iteration
+    # from the GPU's own state at its start (poses, depth, rigidness, depth
+    # range after three iterations): what the cascading near-tie depth
+    # decisions of earlier iterations cannot reach
+    w = _window(name)
+    spec = w["spec"]
+    T, H, W = spec.T, spec.H, spec.W
+    print(f"teacher-forced last iteration {name}", flush=True)
+    kw = _kw(spec)
+    fl = torch.from_numpy(w["flows"]).cuda()
+    s = vo.Solver(T, H, W, spec.n_groups)
+    state = [x.cpu().numpy() for x in s.window(fl, w["K"], vo.default_params(**dict(kw, n_iters=spec.n_iters - 1)))]
+    rng = s.last_range()
+    gp, gd, gr, gl = (x.cpu().numpy() for x in s.window(fl, w["K"], vo.default_params(**kw)))
+    st, op, od, orig, oll = oracle.window_from_state(w["flows"], w["K"], oracle.params(**kw), spec.n_iters - 1,
+                                                     state[0], state[1].astype(np.float64),
+                                                     state[2].astype(np.float64), rng)
+    assert st == 0
+    r = _compare((gp, gd, gr, gl), (op, od, orig, oll), T)
+    dr = np.abs(gr - orig)
+    r["rig_p999"] = float(np.percentile(dr, 99.9))
+    r["rig_max"] = float(dr.max())
+    differs = np.abs(gd - od) > 2e-6 * od        # depth decisions taken the other way
+    r["depth_differs"] = float(differs.mean())
+    excess = dr > 1e-4
+    r["rig_excess"] = float(excess.mean())
+    r["rig_excess_elsewhere"] = float((excess & ~differs[None]).mean())
+    print(r)
+    # poses, depth and rigidness at the benchmark spec's tolerances (rigidness at the
+    # 99.9th percentile)
+    assert r["rot"] <= 1e-4 and r["tdir"] <= 1e-4
+    assert r["depth_med"] <= 1e-3
+    assert r["rig_p999"] <= 1e-4
+    # every rigidness excess lies at a pixel whose depth decision went the other
+    # way in this iteration's sweeps (a near tie at FP32 resolution), but for
+    # the FP32 emission tail at flow discontinuities (<= 1e-4 of the items)
+    assert r["rig_excess_elsewhere"] <= 1e-4
+    # the log-likelihood sums every item: the 2-3 % of pixels whose depth
+    # differs move it by 2.5e-5 (indoor) and 1.1e-4 (driving) of its L1 mass;
+    # at the GPU's own final state it is Eq. 3 to 1e-8 (test above)
+    assert r["ll"] <= 2e-4

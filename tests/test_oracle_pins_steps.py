@@ -359,3 +359,23 @@ def test_f32_range_hook_only_zeroes_posteriors_below_the_fp32_range():
     for k in (1, 2, 3, 4):
         assert np.array_equal(a[k], b[k])
     assert all(np.array_equal(x, y) for x, y in zip(a, c))
+
+
+def test_window_from_state_continues_the_window_exactly():
+    # the window's iterations from the state an earlier, shorter window ends
+    # in (its poses, depth, rigidness and depth range) are the longer window's
+    # last iterations, bit for bit: the random draws depend only on the
+    # iteration index, and the state is everything an iteration reads
+    w = synthflow.make_window("small", 8, T=3, H=40, W=56)
+    p2, p3 = oracle.params(n_iters=2, n_pose_groups=96), oracle.params(n_iters=3, n_pose_groups=96)
+    st, P2, D2, R2, L2, diag2 = oracle.window(w["flows"], w["K"], p2)
+    st3, P3, D3, R3, L3, diag3 = oracle.window(w["flows"], w["K"], p3)
+    assert st == 0 and st3 == 0
+    sf, Pf, Df, Rf, Lf = oracle.window_from_state(w["flows"], w["K"], p3, 2, P2, D2, R2, diag2[2:4])
+    assert sf == 0
+    assert np.array_equal(Pf, P3) and np.array_equal(Df, D3) and np.array_equal(Rf, R3)
+    assert Lf == L3
+    # a state from the wrong iteration (other random draws) gives another window
+    sf, Pg, *_ = oracle.window_from_state(w["flows"], w["K"], oracle.params(n_iters=4, n_pose_groups=96), 3,
+                                          P2, D2, R2, diag2[2:4])
+    assert not np.array_equal(Pg, P3)
