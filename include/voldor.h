@@ -176,7 +176,7 @@ int voldor_vo_sequence(voldor_ctx *ctx, const float *flows, int N, int H, int W,
                        const voldor_params *p, int T, int stride, double *wposes, float *depth, float *rigidness,
                        int32_t *wstatus, double *traj, void *stream);
 
-/* Threads per chain of the depth sweeps (256, 512 or 1024; 0 = 512), row
+/* Threads per chain of the depth sweeps (256, 512, 768 or 1024; 0 = 512), row
  * sweeps and column sweeps apart.  The width changes how a chain's work is
  * spread over a workgroup and how many chains fit a CU, never the result: all
  * widths give the same depth bit for bit.  Windows whose chains would not fit
@@ -194,15 +194,17 @@ int voldor_get_sweep_threads(const voldor_ctx *ctx, int *rows, int *cols);
 int voldor_set_sweep_lookahead(voldor_ctx *ctx, int rows, int cols);
 int voldor_get_sweep_lookahead(const voldor_ctx *ctx, int *rows, int *cols);
 
-/* Autotuner: bootstraps the given window (device flows as voldor_window), then
- * times the row and the column sweeps at every setting of the two tuning axes,
- * threads per chain (256, 512, 1024 where the chain fits the LDS) and the
- * look-ahead cap (none, 16, 8, 4), and keeps the fastest for this chain class
+/* Autotuner: solves the given window once (device flows as voldor_window),
+ * then times the row and the column sweeps from its final state at every
+ * setting of the two tuning axes, threads per chain (256, 512, 768, 1024 where
+ * the chain fits the LDS) and the look-ahead cap (none, 32, 16, 8), and keeps
+ * the fastest for this chain class
  * (chain length, T, depth criterion) in the context: windows of that class then
  * use it, others the defaults of voldor_set_sweep_threads/_lookahead (which
  * drop every tuned class).  The threads chosen for rows and columns are
  * returned in *rows_out, *cols_out if not NULL.  Waits for the device.
- * VOLDOR_EDEGENERATE if the bootstrap fails (nothing is then kept).
+ * VOLDOR_EDEGENERATE if the bootstrap fails (nothing is then kept); allocates
+ * (and frees) one rigidness map of scratch.
  * voldor_sweep_tuning lists the tuned classes: out[4i .. 4i+3] = chain length,
  * T, threads, look-ahead cap; returns their number (at most max_n). */
 int voldor_autotune(voldor_ctx *ctx, const float *flows, int T, int H, int W, const double *K,

@@ -481,7 +481,7 @@ class Solver:
         return traj, wposes, wstatus, depth, rig
 
     def set_sweep_threads(self, rows, cols):
-        """Threads per chain of row and column sweeps (256, 512, 1024; 0 = 512)."""
+        """Threads per chain of row and column sweeps (256, 512, 768, 1024; 0 = 512)."""
         _check(lib().voldor_set_sweep_threads(self._ctx, int(rows), int(cols)), "voldor_set_sweep_threads")
 
     def sweep_threads(self):

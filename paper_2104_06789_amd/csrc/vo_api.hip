@@ -569,7 +569,7 @@ int voldor_set_sweep_threads(voldor_ctx *c, int rows, int cols)
     if (!c) return VOLDOR_EINVAL;
     const int v[2] = {rows ? rows : 512, cols ? cols : 512};
     for (int a = 0; a < 2; ++a)
-        if (v[a] != 256 && v[a] != 512 && v[a] != 1024) return VOLDOR_EINVAL;
+        if (v[a] != 256 && v[a] != 512 && v[a] != 768 && v[a] != 1024) return VOLDOR_EINVAL;
     c->sweep_nt[0] = v[0];
     c->sweep_nt[1] = v[1];
     c->n_sweep_tab = 0;   // an explicit setting replaces the tuned ones
@@ -602,11 +602,11 @@ int voldor_get_sweep_lookahead(const voldor_ctx *c, int *rows, int *cols)
 }
 
 // Times the sweeps of this window's shape at every setting of the two tuning
-// axes, threads per chain (256, 512, 1024 where the chain fits the LDS) and
-// look-ahead cap of the propagation rounds (none, 16, 8, 4), row and column
-// sweeps apart, from the bootstrap's state, and keeps the fastest of each
-// axis for this chain class (length, frames, criterion) in the context.  No
-// setting changes the result.
+// axes, threads per chain (256, 512, 768, 1024 where the chain fits the LDS) and
+// look-ahead cap of the propagation rounds (none, 32, 16, 8), row and column
+// sweeps apart, from the state the window ends in, and keeps the fastest of
+// each axis for this chain class (length, frames, criterion) in the context.
+// No setting changes the result.
 int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, const double *K,
                     const voldor_params *p, int *rows_out, int *cols_out, void *stream)
 {
@@ -617,13 +617,18 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
     const float2 *X = (const float2 *)flows;
     WinDims d = dims(T, H, W, K);
     const EmisParams e = emis(K, p);
-    int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
-                              p->depth_hi, c->rel_tmp, c->theta_tmp, s);
-    if (rc == 0) rc = launch_cumulative(c, c->rel_tmp, T, s);
+    // the state the timed sweeps start from: the window solved once with the
+    // current settings (its later iterations, three in four, are where the
+    // sweeps spend their time; from the bootstrap's noisier depth the
+    // propagation runs are shorter and favour small look-aheads)
+    float *rig_tmp = nullptr;
+    if (hipMalloc((void **)&rig_tmp, sizeof(float) * (size_t)T * H * W) != hipSuccess) return VOLDOR_ENOMEM;
+    int rc = window_enqueue(c, flows, T, H, W, K, p, c->rel_tmp, c->theta_tmp, rig_tmp, nullptr, nullptr, s);
     int st = 0;
     if (rc == 0 && (hipStreamSynchronize(s) != hipSuccess ||
                     hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess))
         rc = VOLDOR_EDEVICE;
+    (void)hipFree(rig_tmp);
     if (rc) return rc;
     if (st != kStatusOk) return st;
     hipEvent_t e0, e1;
@@ -632,8 +637,8 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
         (void)hipEventDestroy(e0);
         return VOLDOR_EDEVICE;
     }
-    const int widths[3] = {256, 512, 1024};
-    const int caps[4] = {0, 16, 8, 4};
+    const int widths[4] = {256, 512, 768, 1024};
+    const int caps[4] = {0, 32, 16, 8};
     // the defaults are the fallback while timing: clear any tuned entry of
     // these classes by timing through a temporary default instead
     const int keep_nt[2] = {c->sweep_nt[0], c->sweep_nt[1]}, keep_la[2] = {c->sweep_la[0], c->sweep_la[1]};
@@ -645,18 +650,19 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
     for (int axis = 0; axis < 2 && rc == 0; ++axis) {
         const int L = axis ? H : W;
         float best_ms = 1e30f;
-        for (int wi = 0; wi < 3 && rc == 0; ++wi) {
+        for (int wi = 0; wi < 4 && rc == 0; ++wi) {
             const int nt = widths[wi];
             if ((int)sweep_lds_bytes(T, L, p->criterion, nt) > c->max_lds) continue;
             for (int ci = 0; ci < 4 && rc == 0; ++ci) {
                 c->sweep_nt[axis] = nt;
                 c->sweep_la[axis] = caps[ci];
                 float ms = 0.0f;
-                for (int rep = 0; rep < 4 && rc == 0; ++rep) {   // the first sweep warms up
+                for (int rep = 0; rep < 5 && rc == 0; ++rep) {   // the first sweep warms up
                     if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VOLDOR_EDEVICE;
+                    const int64_t gs = (int64_t)p->n_iters * p->sweeps_per_iter + rep;
                     if (rc == 0)
-                        rc = launch_sweep(c, c->theta_tmp, c->theta_tmp, X, d, e, (float)p->gamma, p->seed, rep,
-                                          axis, c->range, nullptr, s, p->criterion);
+                        rc = launch_sweep(c, c->theta_tmp, c->theta_tmp, X, d, e, (float)p->gamma, p->seed, gs,
+                                          axis + 2 * (rep & 1), c->range, nullptr, s, p->criterion);
                 }
                 if (rc == 0 && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))

@@ -138,7 +138,7 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
                      const double *rel_poses = nullptr);
 int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
                   hipStream_t s);
-// LDS bytes of one chain of length L with nt threads (256, 512 or 1024)
+// LDS bytes of one chain of length L with nt threads (256, 512, 768 or 1024)
 size_t sweep_lds_bytes(int T, int L, int criterion, int nt);
 // threads per chain and look-ahead cap of chains of length L (axis 0 rows, 1
 // columns): the tuned entry of this class, else the axis default

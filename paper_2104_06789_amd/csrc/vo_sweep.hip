@@ -350,7 +350,7 @@ __host__ __device__ inline int sweep_region2_words(int T, int L, int nt = kSweep
 
 // CRIT 0: maximum-inlier depth criterion (Eq. 10); 1: maximum likelihood (Eq. 9).
 // MODEL 0: Fisk residual model (Eq. 5); 1: Gaussian flow error.
-// NT threads per chain (256, 512 or 1024): every item is the same function of
+// NT threads per chain (256, 512, 768 or 1024): every item is the same function of
 // its inputs whatever NT is, so all widths give the same result bit for bit;
 // NT only sets how a chain's work is spread (and how many chains fit a CU)
 template <int CRIT, int NT, int MODEL>
@@ -1001,6 +1001,10 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     case 2049: return launch_sweep_nt<0, 512, 1>(a, nchain, lds, s);
     case 2050: return launch_sweep_nt<1, 512, 0>(a, nchain, lds, s);
     case 2051: return launch_sweep_nt<1, 512, 1>(a, nchain, lds, s);
+    case 3072: return launch_sweep_nt<0, 768, 0>(a, nchain, lds, s);
+    case 3073: return launch_sweep_nt<0, 768, 1>(a, nchain, lds, s);
+    case 3074: return launch_sweep_nt<1, 768, 0>(a, nchain, lds, s);
+    case 3075: return launch_sweep_nt<1, 768, 1>(a, nchain, lds, s);
     case 4096: return launch_sweep_nt<0, 1024, 0>(a, nchain, lds, s);
     case 4097: return launch_sweep_nt<0, 1024, 1>(a, nchain, lds, s);
     case 4098: return launch_sweep_nt<1, 1024, 0>(a, nchain, lds, s);

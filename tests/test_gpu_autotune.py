@@ -1,7 +1,7 @@
 """Sweep widths (threads per chain), look-ahead caps and the autotuner, through
 the C ABI.
 
-Every width (256, 512, 1024 threads per chain) and every look-ahead cap of the
+Every width (256, 512, 768, 1024 threads per chain) and every look-ahead cap of the
 propagation rounds computes each item with the same FP32 function and the
 propagation's first losses exactly, so the depth of a sweep, and a whole
 window, must be the same bit for bit at every setting; the autotuner only
@@ -48,7 +48,7 @@ def test_sweep_widths_bit_identical(vo, torch, criterion):
     s = vo.Solver(T, H, W, 256)
     d_lo, d_hi = 0.5 * float(gt.min()), 2.0 * float(gt.max())
     ref = {}
-    for nt, cap in ((512, 0), (256, 0), (1024, 0), (512, 1), (256, 3), (1024, 16)):
+    for nt, cap in ((512, 0), (256, 0), (768, 0), (1024, 0), (512, 1), (256, 3), (768, 2), (1024, 16)):
         s.set_sweep_threads(nt, nt)
         s.set_sweep_lookahead(cap, cap)
         assert s.sweep_threads() == (nt, nt) and s.sweep_lookahead() == (cap, cap)
@@ -80,11 +80,11 @@ def test_window_widths_and_autotune(vo, torch):
     for a, b in zip(out, ref):
         assert torch.equal(a, b)
     rows, cols = s.autotune(fl, w["K"], p)
-    assert rows in (256, 512, 1024) and cols in (256, 512, 1024)
+    assert rows in (256, 512, 768, 1024) and cols in (256, 512, 768, 1024)
     tab = s.sweep_tuning()
     print(tab)
     assert (W, T, rows) == tab[0][:3] and (H, T, cols) == tab[1][:3]
-    assert tab[0][3] in (0, 4, 8, 16) and tab[1][3] in (0, 4, 8, 16)
+    assert tab[0][3] in (0, 8, 16, 32) and tab[1][3] in (0, 8, 16, 32)
     out = s.window(fl, w["K"], p)
     for a, b in zip(out, ref):
         assert torch.equal(a, b)
