@@ -197,7 +197,7 @@ int voldor_get_sweep_lookahead(const voldor_ctx *ctx, int *rows, int *cols);
 /* Autotuner: solves the given window once (device flows as voldor_window),
  * then times the row and the column sweeps from its final state at every
  * setting of the two tuning axes, threads per chain (256, 512, 768, 1024 where
- * the chain fits the LDS) and the look-ahead cap (none, 32, 16, 8), and keeps
+ * the chain fits the LDS) and the look-ahead cap (none, 32, 16, 8, 4, 2), and keeps
  * the fastest for this chain class
  * (chain length, T, depth criterion) in the context: windows of that class then
  * use it, others the defaults of voldor_set_sweep_threads/_lookahead (which

@@ -194,10 +194,6 @@ def _dev_tensor(t, name, dtype, shape, device, optional=False):
     return t
 
 
-def _finalizing():
-    return _sys.is_finalizing()
-
-
 def residual_fit(X, G, nbins=40, v_max=40.0, x_floor=1e-12, min_count=64, stream=None):
     """Fisk laws (a1, a2, b1, b2) of Eq. 6-7 fitted to the residuals |X - G|^2
     binned by |X| (CUDA float32 flows [..., 2]); returns (laws, bins [nbins][4])."""
@@ -287,10 +283,11 @@ class Solver:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _fin=_sys.is_finalizing):
         # at interpreter exit the HIP runtime may already be torn down: leave
-        # the memory to the process's end instead of calling into it
-        if _finalizing():
+        # the memory to the process's end instead of calling into it (the
+        # check is bound here: module globals may be gone by then)
+        if _fin():
             return
         try:
             self.close()
@@ -581,8 +578,8 @@ class Batch:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _fin=_sys.is_finalizing):
+        if _fin():   # as Solver.__del__
             return
         try:
             self.close()
@@ -688,8 +685,8 @@ class Net:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _fin=_sys.is_finalizing):
+        if _fin():   # as Solver.__del__
             return
         try:
             self.close()

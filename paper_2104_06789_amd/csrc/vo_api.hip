@@ -603,7 +603,7 @@ int voldor_get_sweep_lookahead(const voldor_ctx *c, int *rows, int *cols)
 
 // Times the sweeps of this window's shape at every setting of the two tuning
 // axes, threads per chain (256, 512, 768, 1024 where the chain fits the LDS) and
-// look-ahead cap of the propagation rounds (none, 32, 16, 8), row and column
+// look-ahead cap of the propagation rounds (none, 32, 16, 8, 4, 2), row and column
 // sweeps apart, from the state the window ends in, and keeps the fastest of
 // each axis for this chain class (length, frames, criterion) in the context.
 // No setting changes the result.
@@ -625,20 +625,26 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
     if (hipMalloc((void **)&rig_tmp, sizeof(float) * (size_t)T * H * W) != hipSuccess) return VOLDOR_ENOMEM;
     int rc = window_enqueue(c, flows, T, H, W, K, p, c->rel_tmp, c->theta_tmp, rig_tmp, nullptr, nullptr, s);
     int st = 0;
+    // the end state is kept (in the rigidness buffer, no longer needed) and
+    // every setting is timed from it: timed sweeps move the depth on, and
+    // settings timed later would otherwise start from later states
+    float *theta_keep = rig_tmp;
+    const size_t HW = (size_t)H * W;
     if (rc == 0 && (hipStreamSynchronize(s) != hipSuccess ||
-                    hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess))
+                    hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess ||
+                    hipMemcpy(theta_keep, c->theta_tmp, HW * sizeof(float), hipMemcpyDeviceToDevice) != hipSuccess))
         rc = VOLDOR_EDEVICE;
-    (void)hipFree(rig_tmp);
-    if (rc) return rc;
-    if (st != kStatusOk) return st;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return VOLDOR_EDEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return VOLDOR_EDEVICE;
+    if (rc == 0 && st != kStatusOk) rc = st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == 0 && hipEventCreate(&e0) != hipSuccess) rc = VOLDOR_EDEVICE;
+    if (rc == 0 && hipEventCreate(&e1) != hipSuccess) rc = VOLDOR_EDEVICE;
+    if (rc) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(rig_tmp);
+        return rc;
     }
     const int widths[4] = {256, 512, 768, 1024};
-    const int caps[4] = {0, 32, 16, 8};
+    const int caps[6] = {0, 32, 16, 8, 4, 2};
     // the defaults are the fallback while timing: clear any tuned entry of
     // these classes by timing through a temporary default instead
     const int keep_nt[2] = {c->sweep_nt[0], c->sweep_nt[1]}, keep_la[2] = {c->sweep_la[0], c->sweep_la[1]};
@@ -653,9 +659,12 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
         for (int wi = 0; wi < 4 && rc == 0; ++wi) {
             const int nt = widths[wi];
             if ((int)sweep_lds_bytes(T, L, p->criterion, nt) > c->max_lds) continue;
-            for (int ci = 0; ci < 4 && rc == 0; ++ci) {
+            for (int ci = 0; ci < 6 && rc == 0; ++ci) {
                 c->sweep_nt[axis] = nt;
                 c->sweep_la[axis] = caps[ci];
+                if (hipMemcpyAsync(c->theta_tmp, theta_keep, HW * sizeof(float), hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                    rc = VOLDOR_EDEVICE;
                 float ms = 0.0f;
                 for (int rep = 0; rep < 5 && rc == 0; ++rep) {   // the first sweep warms up
                     if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VOLDOR_EDEVICE;
@@ -677,6 +686,8 @@ int voldor_autotune(voldor_ctx *c, const float *flows, int T, int H, int W, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == 0) rc = VOLDOR_EDEVICE;
+    (void)hipFree(rig_tmp);
     c->sweep_nt[0] = keep_nt[0];
     c->sweep_nt[1] = keep_nt[1];
     c->sweep_la[0] = keep_la[0];

@@ -96,6 +96,19 @@ __device__ __forceinline__ bool displacement_at(const Geo &g, float th, float fx
     return true;
 }
 
+// The same without a branch: dx, dy are written whatever pz is (not finite
+// or meaningless behind the camera) and the result says whether the point is
+// in front.  For callers that mask the values they use; with the same
+// arithmetic, the in-front values equal displacement_at's bit for bit.
+__device__ __forceinline__ bool displacement_any(const Geo &g, float th, float fx, float fy, float &dx, float &dy)
+{
+    const float pz = fmaf(th, g.az, g.tz);
+    const float inv = frcp(pz);
+    dx = fx * fmaf(th, g.ax, g.bx) * inv;
+    dy = fy * fmaf(th, g.ay, g.by) * inv;
+    return pz > 0.0f;
+}
+
 // Displacement pi_t(theta) - (x, y) of the frame-0 pixel with normalised
 // coordinates (xh, yh) at depth th.  False if the point is not in front.
 __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh, float th,

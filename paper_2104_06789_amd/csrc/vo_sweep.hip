@@ -32,6 +32,7 @@ constexpr int kSweepThreads = 512;
 #define VO_PAIR_ITEMS 1
 #endif
 constexpr int kPairItems = VO_PAIR_ITEMS;   // items per thread in flight in the paired pass
+constexpr int kMleItems = 2;                // items per thread in flight in the MLE passes
 constexpr int kSweepWaves = kSweepThreads / 64;
 constexpr float kLogHalf = -0.69314718055994531f;
 
@@ -82,14 +83,15 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     bool pok = th > 0.0f;
     const int HW = H * W;   // T H W < 2^31 (frames <= 16, sides <= 4096)
     for (int t0 = 1; t0 <= T; t0 += 3) {
-        float dx[3], dy[3];
+        float dx[3], dy[3], qv[3];
         bool ok[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) qv[u] = q[(min(t0 + u, T) - 1) * L + k];   // issued with the gathers
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
-            dx[u] = 0.0f;
-            dy[u] = 0.0f;
-            ok[u] = t <= T && th > 0.0f && displacement(fr[t <= T ? t : T], xh, yh, th, e.fx, e.fy, dx[u], dy[u]);
+            const bool f = displacement_any(pixel_geometry(fr[t <= T ? t : T], xh, yh), th, e.fx, e.fy, dx[u], dy[u]);
+            ok[u] = (t <= T) & (th > 0.0f) & f;
         }
         float2 ta[3], tb[3], tc[3], td[3];
         float ax[3], ay[3], lx[3], ly[3];
@@ -99,8 +101,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             const float bdx = u == 0 ? pdx : dx[u - 1], bdy = u == 0 ? pdy : dy[u - 1];
             const bool bok = u == 0 ? pok : ok[u - 1];
             const float px = (float)x + bdx, py = (float)y + bdy;
-            val[u] = bok && ok[u] && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f &&
-                     py <= (float)(H - 1);
+            val[u] = bok & ok[u] & (px >= 0.0f) & (px <= (float)(W - 1)) & (py >= 0.0f) & (py <= (float)(H - 1));
             lx[u] = bdx;
             ly[u] = bdy;
             const float spx = val[u] ? px : 0.0f, spy = val[u] ? py : 0.0f;
@@ -118,42 +119,27 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
         for (int u = 0; u < 3; ++u) {
             const int t = t0 + u;
             if (t > T) break;
+            // computed for every frame (branch-free), kept where observed
+            const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
+            const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
+            const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+            const bool obs = val[u] & isfinite(vu + vv);   // every tap finite (see taps_finite)
             if constexpr (LOGS) {
                 float lam = kLogLn2F;
-                if (val[u]) {
-                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
-                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
-                        const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
-                        float rr;
-                        lam = neg_ell_log(dd, rr);
-                    }
+                if (obs) {
+                    const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                    float rr;
+                    lam = neg_ell_log(dd, rr);
                 }
-                logscore_add(ls, q[(t - 1) * L + k], lam);
+                logscore_add(ls, qv[u], lam);
             } else if constexpr (CRIT == 0) {
-                float ell = kLogHalf;
-                if (val[u]) {
-                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
-                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
-                        const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
-                        ell = emis_from_d(dd).ell;
-                    }
-                }
-                s = fmaf(q[(t - 1) * L + k], ell, s);
+                const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                const float ell = emis_from_d(dd).ell;
+                s = fmaf(qv[u], obs ? ell : kLogHalf, s);
             } else {
-                if (val[u]) {
-                    const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-                    const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-                    const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
-                    if (isfinite(vu + vv)) {   // every tap finite (see taps_finite)
-                        float lmu;
-                        const float dd = log_mu_and_d<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
-                        s += fmaf(-q[(t - 1) * L + k], dd, lmu);
-                    }
-                }
+                float lmu;
+                const float dd = log_mu_and_d<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
+                if (obs) s += fmaf(-qv[u], dd, lmu);
             }
         }
         pdx = dx[2];
@@ -216,8 +202,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
 
 // The maximum-inlier pass over B (pixel, frame) items, each evaluated at the
 // previous depth thp and at the random sample ths: the frame geometry of an
-// item is computed once for both depths, and for frame 1 (lookup at the pixel
-// itself) its flow taps are loaded once.  Every log-odds is the same FP32
+// item is computed once for both depths.  Every log-odds is the same FP32
 // function of (pixel, frame, depth) as in batch_log_odds and chain_score.
 template <int B, int MODEL>
 __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const float2 *__restrict__ flows, int H,
@@ -237,33 +222,27 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
         const Geo g0 = pixel_geometry(fr[tt > 1 ? tt - 1 : 0], xh, yh);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+            // branch-free: every value is computed and the flags mask them
             const int i = 2 * b + c;
             const float th = c ? ths[b] : thp[b];
-            bool ok = act[b] && th > 0.0f;
-            dx0[i] = 0.0f;
-            dy0[i] = 0.0f;
-            if (tt > 1) ok = ok && displacement_at(g0, th, e.fx, e.fy, dx0[i], dy0[i]);
-            ok = ok && displacement_at(g1, th, e.fx, e.fy, dx1[i], dy1[i]);
+            float ex, ey;
+            const bool f0 = displacement_any(g0, th, e.fx, e.fy, ex, ey);
+            const bool f1 = displacement_any(g1, th, e.fx, e.fy, dx1[i], dy1[i]);
+            dx0[i] = tt > 1 ? ex : 0.0f;
+            dy0[i] = tt > 1 ? ey : 0.0f;
             const float px = (float)x[b] + dx0[i], py = (float)y[b] + dy0[i];
-            ok = ok && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1);
+            const bool ok = act[b] & (th > 0.0f) & (f0 | (tt <= 1)) & f1 & (px >= 0.0f) & (px <= (float)(W - 1)) &
+                            (py >= 0.0f) & (py <= (float)(H - 1));
             v[i] = ok;
             const float spx = ok ? px : 0.0f, spy = ok ? py : 0.0f;
             const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
             ax[i] = spx - (float)x0;
             ay[i] = spy - (float)y0;
-            if (c == 1 && tt == 1 && v[2 * b]) {
-                // frame 1: both depths look the flow up at the pixel itself
-                ta[i] = ta[2 * b];
-                tb[i] = tb[2 * b];
-                tc[i] = tc[2 * b];
-                td[i] = td[2 * b];
-            } else {
-                const float2 *r0 = flows + ((ok ? tt - 1 : 0) * HW + y0 * W + x0);
-                ta[i] = r0[0];
-                tb[i] = r0[1];
-                tc[i] = r0[W];
-                td[i] = r0[W + 1];
-            }
+            const float2 *r0 = flows + ((ok ? tt - 1 : 0) * HW + y0 * W + x0);
+            ta[i] = r0[0];
+            tb[i] = r0[1];
+            tc[i] = r0[W];
+            td[i] = r0[W + 1];
         }
     }
 #pragma unroll
@@ -271,8 +250,9 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
         const float2 A = ta[i], Bv = tb[i], Cv = tc[i], Dv = td[i];
         const float vu = (1.0f - ay[i]) * fmaf(ax[i], Bv.x - A.x, A.x) + ay[i] * fmaf(ax[i], Dv.x - Cv.x, Cv.x);
         const float vv = (1.0f - ay[i]) * fmaf(ax[i], Bv.y - A.y, A.y) + ay[i] * fmaf(ax[i], Dv.y - Cv.y, Cv.y);
-        const bool ok = v[i] && isfinite(vu + vv);   // every tap finite (see taps_finite)
-        const float d = ok ? log_mu_over_rho<MODEL>((dx1[i] - dx0[i]) - vu, (dy1[i] - dy0[i]) - vv, vu, vv, e) : 0.0f;
+        const bool ok = v[i] & isfinite(vu + vv);   // every tap finite (see taps_finite)
+        const float dv = log_mu_over_rho<MODEL>((dx1[i] - dx0[i]) - vu, (dy1[i] - dy0[i]) - vv, vu, vv, e);
+        const float d = ok ? dv : 0.0f;
         if (i & 1) {
             ds[i >> 1] = d;
             oks[i >> 1] = ok;
@@ -336,6 +316,122 @@ __device__ __forceinline__ Mat2 shfl_down_m(const Mat2 &m, int d)
     r.c = __shfl_down(m.c, d, 64);
     r.d = __shfl_down(m.d, d, 64);
     return r;
+}
+
+// Forward-backward over one frame's chain by one wave, one segment [s0, s1)
+// of at most SEG positions per lane held in registers: the segment's forward
+// and backward transfer products, their prefix and suffix over the lanes by
+// shuffles, then the forward and the backward replay, which leave q in rq.
+// Every register index is static after unrolling and positions past s1 are
+// masked by selects (branches there make the allocator spill).  The products
+// with Gamma are formed from the running matrix, so that per position only r
+// and the forward message stay live (products of r and gamma shared by the
+// two passes would each stay live across both).  r stays in registers from
+// its first read, so both replays take the E-step's own r.
+template <int SEG>
+__device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float g, float gc, int lane)
+{
+    const int n = s1 - s0;
+    // positions past s1 read whatever follows (the next frame, or the first
+    // words of region 2, which holds at least 8 L >= SEG words); unused
+    float rr[SEG];
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) rr[i] = rq[s0 + i];
+    // forward A_k = diag(r, 1-r) Gamma, product A_{s1-1}..A_{s0}: Gamma F,
+    // rows scaled by r and 1-r
+    Mat2 F = {1, 0, 0, 1};
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) {
+        const float r1 = rr[i];
+        const float ua = g * F.a + gc * F.c, ub = g * F.b + gc * F.d;
+        const float uc = gc * F.a + g * F.c, ud = gc * F.b + g * F.d;
+        Mat2 Fn = {r1 * ua, r1 * ub, fmaf(-r1, uc, uc), fmaf(-r1, ud, ud)};
+        const float inv = frcp(Fn.a + Fn.b + Fn.c + Fn.d);
+        Fn.a *= inv;
+        Fn.b *= inv;
+        Fn.c *= inv;
+        Fn.d *= inv;
+        const bool on = i < n;
+        F.a = on ? Fn.a : F.a;
+        F.b = on ? Fn.b : F.b;
+        F.c = on ? Fn.c : F.c;
+        F.d = on ? Fn.d : F.d;
+    }
+    // backward G_k = Gamma diag(r, 1-r), product G_{s0}..G_{s1-1}: rows of B
+    // scaled by r and 1-r, then Gamma
+    Mat2 B = {1, 0, 0, 1};
+#pragma unroll
+    for (int i = SEG - 1; i >= 0; --i) {
+        const float r1 = rr[i];
+        const float va = r1 * B.a, vb = r1 * B.b, vc = fmaf(-r1, B.c, B.c), vd = fmaf(-r1, B.d, B.d);
+        Mat2 Bn = {g * va + gc * vc, g * vb + gc * vd, gc * va + g * vc, gc * vb + g * vd};
+        const float inv = frcp(Bn.a + Bn.b + Bn.c + Bn.d);
+        Bn.a *= inv;
+        Bn.b *= inv;
+        Bn.c *= inv;
+        Bn.d *= inv;
+        const bool on = i < n;
+        B.a = on ? Bn.a : B.a;
+        B.b = on ? Bn.b : B.b;
+        B.c = on ? Bn.c : B.c;
+        B.d = on ? Bn.d : B.d;
+    }
+    // inclusive prefix of forward products (later segments on the left),
+    // inclusive suffix of backward products (earlier segments on the left)
+    Mat2 P = F;
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const Mat2 Q = shfl_up_m(P, dd);
+        if (lane >= dd) P = mul_norm(P, Q);
+    }
+    Mat2 Sx = B;
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const Mat2 Q = shfl_down_m(Sx, dd);
+        if (lane + dd < 64) Sx = mul_norm(Sx, Q);
+    }
+    const Mat2 Pp = shfl_up_m(P, 1), Sn = shfl_down_m(Sx, 1);
+    float f1 = 0.5f, f0 = 0.5f;   // m_f before the segment
+    if (lane > 0) {
+        const float n1 = 0.5f * (Pp.a + Pp.b), n0 = 0.5f * (Pp.c + Pp.d);
+        const float inv = frcp(n1 + n0);
+        f1 = n1 * inv;
+        f0 = n0 * inv;
+    }
+    float b1 = 0.5f, b0 = 0.5f;   // m_b at the segment's last position
+    if (lane < 63) {
+        const float n1 = 0.5f * (Sn.a + Sn.b), n0 = 0.5f * (Sn.c + Sn.d);
+        const float inv = frcp(n1 + n0);
+        b1 = n1 * inv;
+        b0 = n0 * inv;
+    }
+    // forward messages: in registers for short segments, else through rq
+    constexpr bool FREG = SEG <= 11;
+    float ff[FREG ? SEG : 1];
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) {
+        const float r1 = rr[i];
+        const float p1 = g * f1 + gc * f0, p0 = gc * f1 + g * f0;
+        const float n1 = r1 * p1, n0 = fmaf(-r1, p0, p0);
+        const float inv = frcp(n1 + n0);
+        f1 = n1 * inv;
+        f0 = n0 * inv;
+        if constexpr (FREG) ff[i] = f1;
+        else if (i < n) rq[s0 + i] = f1;
+    }
+    if constexpr (!FREG) asm volatile("" ::: "memory");   // read back below, not kept live
+#pragma unroll
+    for (int i = SEG - 1; i >= 0; --i) {
+        const float ff1 = FREG ? ff[FREG ? i : 0] : rq[s0 + i], ff0 = 1.0f - ff1;
+        const float n1 = ff1 * b1, n0 = ff0 * b0;
+        if (i < n) rq[s0 + i] = n1 * frcp(n1 + n0);
+        if (i > 0) {
+            const float r1 = rr[i];
+            const float e1 = r1 * b1, e0 = fmaf(-r1, b0, b0);
+            const float m1 = g * e1 + gc * e0, m0 = gc * e1 + g * e0;
+            const float inv = frcp(m1 + m0);
+            b1 = i < n ? m1 * inv : b1;
+            b0 = i < n ? m0 * inv : b0;
+        }
+    }
 }
 
 // LDS words of the dynamic area for a chain of length L and T frames (the MLE
@@ -442,18 +538,20 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             for (int b = 0; b < PB; ++b) {
                 const int i = i0 + b * NT;
                 if (!act[b]) continue;
-                float ell = LOGS ? kLogLn2F : kLogHalf, r = 0.5f, els = LOGS ? kLogLn2F : kLogHalf;
+                // computed for every item, kept where observed
+                constexpr float miss = LOGS ? kLogLn2F : kLogHalf;
+                float ell, r, els;
                 if constexpr (LOGS) {
-                    if (okp[b]) ell = neg_ell_log(dp[b], r);
-                    float rs;
-                    if (oks[b]) els = neg_ell_log(ds[b], rs);
+                    float rp, rs;
+                    const float lp = neg_ell_log(dp[b], rp), lz = neg_ell_log(ds[b], rs);
+                    ell = okp[b] ? lp : miss;
+                    r = okp[b] ? rp : 0.5f;
+                    els = oks[b] ? lz : miss;
                 } else {
-                    if (okp[b]) {
-                        const Emis m = emis_from_d(dp[b]);
-                        ell = m.ell;
-                        r = m.r;
-                    }
-                    if (oks[b]) els = emis_from_d(ds[b]).ell;
+                    const Emis mp = emis_from_d(dp[b]), mz = emis_from_d(ds[b]);
+                    ell = okp[b] ? mp.ell : miss;
+                    r = okp[b] ? mp.r : 0.5f;
+                    els = oks[b] ? mz.ell : miss;
                 }
                 lq[i] = ell;
                 fq[i] = r;
@@ -461,17 +559,17 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             }
         }
     }
-    // ---- A (MLE): log-odds and log mu of the previous depth, four items per
+    // ---- A (MLE): log-odds and log mu of the previous depth, two items per
     // thread in flight (the sample follows the E-step: its terms need q)
     if constexpr (CRIT == 1)
-    for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
-        int xs[4], ys[4], ts[4];
-        float ths[4], dd[4];
-        bool act[4], ok[4];
+    for (int i0 = tid; i0 < T * L; i0 += kMleItems * NT) {
+        int xs[kMleItems], ys[kMleItems], ts[kMleItems];
+        float ths[kMleItems], dd[kMleItems];
+        bool act[kMleItems], ok[kMleItems];
         // item i = (t - 1) L + k; the thread's items are NT apart
         int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < kMleItems; ++b) {
             act[b] = i0 + b * NT < T * L;
             const int kk = act[b] ? k : 0;
             chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
@@ -481,10 +579,10 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
             while (k >= L) { k -= L; ++t; }
         }
         {
-            float lm[4];
-            batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            float lm[kMleItems];
+            batch_log_odds<kMleItems, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < kMleItems; ++b) {
                 const int i = i0 + b * NT;
                 if (!act[b]) continue;
                 // missing: d = 0 (r = 1/2 in the E-step) and log mu = 0 (term 0)
@@ -499,13 +597,19 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     // ---- B: forward-backward, one wave per frame, one segment per lane
     {
         const int lane = tid & 63, wv = tid >> 6;
-        // odd segment length: lanes then read LDS with an odd stride (no bank conflicts)
+        // segment length: a function of L alone (the same segments, and so
+        // the same rounding, whatever NT is)
         const int seglen = ((L + 63) / 64) | 1;
         const float g = a.gamma, gc = 1.0f - a.gamma;
         const int s0 = min(lane * seglen, L), s1 = min(s0 + seglen, L);
         for (int t = wv; t < T; t += (NT / 64)) {
             float *rq = fq + t * L;
             const float *ll = lq + t * L;
+            // segments held in registers up to 21 positions (chains of 1344)
+            if (seglen <= 5) { fb_segment_regs<5>(rq, s0, s1, g, gc, lane); continue; }
+            if (seglen <= 7) { fb_segment_regs<7>(rq, s0, s1, g, gc, lane); continue; }
+            if (seglen <= 11) { fb_segment_regs<11>(rq, s0, s1, g, gc, lane); continue; }
+            if (seglen <= 21) { fb_segment_regs<21>(rq, s0, s1, g, gc, lane); continue; }
             // segment transfer matrices: forward A_k = diag(r,1-r) Gamma,
             // product A_{s1-1}..A_{s0}; backward G_k = Gamma diag(r,1-r),
             // product G_{s0}..G_{s1-1}
@@ -596,9 +700,23 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 sp = logscore_value(lp);
                 ss = logscore_value(lz);
             } else {
-                for (int t = 0; t < T; ++t) {
-                    sp = fmaf(fq[t * L + k], lq[t * L + k], sp);
-                    ss = fmaf(fq[t * L + k], ls[t * L + k], ss);
+                // frames four at a time: their loads in flight together
+                for (int t0 = 0; t0 < T; t0 += 4) {
+                    float qv[4], pv[4], sv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = min(t0 + u, T - 1) * L + k;
+                        qv[u] = fq[i];
+                        pv[u] = lq[i];
+                        sv[u] = ls[i];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (t0 + u < T) {
+                            sp = fmaf(qv[u], pv[u], sp);
+                            ss = fmaf(qv[u], sv[u], ss);
+                        }
+                    }
                 }
             }
             const bool smp = ss > sp;
@@ -615,14 +733,14 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
         __syncthreads();
         // the sample's whole term log mu - q d (0 where missing), one item per
         // (position, frame)
-        for (int i0 = tid; i0 < T * L; i0 += 4 * NT) {
-            int xs[4], ys[4], ts[4];
-            float ths[4], dd[4], lm[4];
-            bool act[4], ok[4];
+        for (int i0 = tid; i0 < T * L; i0 += kMleItems * NT) {
+            int xs[kMleItems], ys[kMleItems], ts[kMleItems];
+            float ths[kMleItems], dd[kMleItems], lm[kMleItems];
+            bool act[kMleItems], ok[kMleItems];
             // item i = (t - 1) L + k; the thread's items are NT apart
             int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < kMleItems; ++b) {
                 act[b] = i0 + b * NT < T * L;
                 const int kk = act[b] ? k : 0;
                 chain_xy(dir, H, W, chain, kk, xs[b], ys[b]);
@@ -631,9 +749,9 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 k += NT;
                 while (k >= L) { k -= L; ++t; }
             }
-            batch_log_odds<4, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            batch_log_odds<kMleItems, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < kMleItems; ++b) {
                 const int i = i0 + b * NT;
                 if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b], lm[b]) : 0.0f;
             }
@@ -720,26 +838,25 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     // ---- D: nodes reachable from 0 through next(), by pointer doubling
     int *J0 = (int *)lq, *J1 = J0 + L, *mark = J1 + L;
     float *thn = (float *)(mark + L);
-    for (int k = tid; k < L; k += NT) {
-        J0[k] = nxt[k];
-        mark[k] = k == 0;
-    }
+    for (int k = tid; k < L; k += NT) mark[k] = k == 0;
     __syncthreads();
-    int *Jc = J0, *Jn = J1;
+    // round i follows jumps of 2^i hops (Jc = next^(2^i)): a node h hops from
+    // 0 is marked once the rounds of the set bits of h have run.  Marks only
+    // grow and only reach nodes reachable from 0, so a mark that another
+    // thread sets during the same round changes nothing at the end; the jump
+    // table of the next round goes to the other buffer, so one barrier per
+    // round suffices.
+    const int *Jc = nxt;
+    int *Jn = J0;
     for (int span = 1; span < L; span <<= 1) {
         for (int k = tid; k < L; k += NT) {
             const int to = Jc[k];
             if (mark[k] && to < L) mark[to] = 1;
-        }
-        __syncthreads();
-        for (int k = tid; k < L; k += NT) {
-            const int to = Jc[k];
             Jn[k] = to < L ? Jc[to] : L;
         }
         __syncthreads();
-        int *tmp = Jc;
         Jc = Jn;
-        Jn = tmp;
+        Jn = Jn == J0 ? J1 : J0;
     }
     for (int k = tid; k < L; k += NT) {
         if (mark[k]) {

@@ -85,7 +85,18 @@ def test_sweep_parity(vo, torch, direction, criterion, model):
     # ragged sizes: rows of 83, columns of 45, several FB segments per chain;
     # depth criterion MIE (Eq. 10) and MLE (Eq. 9), residual model Fisk and
     # Gaussian
-    T, H, W = 4, 45, 83
+    _sweep_case(vo, torch, 4, 45, 83, direction, criterion, model)
+
+
+@pytest.mark.parametrize("W", [1300, 1500])
+@pytest.mark.parametrize("direction", [0, 2])
+def test_sweep_parity_long_rows(vo, torch, W, direction):
+    # rows of 1300 (forward-backward segments of 21 positions, the longest held
+    # in registers) and of 1500 (segments of 25, walked in LDS)
+    _sweep_case(vo, torch, 2, 20, W, direction, 0, 0)
+
+
+def _sweep_case(vo, torch, T, H, W, direction, criterion, model):
     w, rel, M, gt = _world(20 + direction, T, H, W)
     rng = np.random.default_rng(direction)
     theta = (gt * np.exp(rng.normal(0, 0.15, gt.shape))).astype(np.float32)
