@@ -105,9 +105,10 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             lx[u] = bdx;
             ly[u] = bdy;
             const float spx = val[u] ? px : 0.0f, spy = val[u] ? py : 0.0f;
-            const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
-            ax[u] = spx - (float)x0;
-            ay[u] = spy - (float)y0;
+            const float fx0 = fminf(floorf(spx), (float)(W - 2)), fy0 = fminf(floorf(spy), (float)(H - 2));
+            const int x0 = (int)fx0, y0 = (int)fy0;
+            ax[u] = spx - fx0;
+            ay[u] = spy - fy0;
             const int tf = val[u] ? t0 + u - 1 : 0;
             const float2 *r0 = flows + (tf * HW + y0 * W + x0);
             ta[u] = r0[0];
@@ -235,9 +236,10 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
                             (py >= 0.0f) & (py <= (float)(H - 1));
             v[i] = ok;
             const float spx = ok ? px : 0.0f, spy = ok ? py : 0.0f;
-            const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
-            ax[i] = spx - (float)x0;
-            ay[i] = spy - (float)y0;
+            const float fx0 = fminf(floorf(spx), (float)(W - 2)), fy0 = fminf(floorf(spy), (float)(H - 2));
+            const int x0 = (int)fx0, y0 = (int)fy0;
+            ax[i] = spx - fx0;
+            ay[i] = spy - fy0;
             const float2 *r0 = flows + ((ok ? tt - 1 : 0) * HW + y0 * W + x0);
             ta[i] = r0[0];
             tb[i] = r0[1];
@@ -512,16 +514,17 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     __syncthreads();
 
     // ---- A (MIE): ell and r of the previous depth and ell of the random
-    // sample, one item per (position, frame) evaluated at both depths, two
-    // items per thread in flight
+    // sample, one item per (position, frame) evaluated at both depths,
+    // kPairItems items per thread in flight
     if constexpr (CRIT == 0) {
         constexpr int PB = kPairItems;
+        // item i = (t - 1) L + k; the thread's items are NT apart, (t, k)
+        // carried from one item to the next
+        int t = tid / L + 1, k = tid - (t - 1) * L;
         for (int i0 = tid; i0 < T * L; i0 += PB * NT) {
             int xs[PB], ys[PB], ts[PB];
             float thp[PB], ths[PB], dp[PB], ds[PB];
             bool act[PB], okp[PB], oks[PB];
-            // item i = (t - 1) L + k; the thread's items are NT apart
-            int t = i0 / L + 1, k = i0 - (t - 1) * L;
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
                 act[b] = i0 + b * NT < T * L;
