@@ -301,7 +301,11 @@ def run_batch(args):
     n_sweeps = BATCH_ITERS * p.sweeps_per_iter
     alg_bytes = sum(n_sweeps * (8.0 * T * H * W + 8.0 * H * W) for T, H, W in shapes)
     alg_ops = sum(n_sweeps * ALG_OPS_PER_PF_SWEEP * T * H * W for T, H, W in shapes)
-    sweep_s = ph["sweeps"] * 1e-3
+    # the sweep kernels' device time: the union of every window's sweep
+    # intervals over the lanes (the chip ran at least one sweep), which a
+    # kernel trace's per-dispatch durations add up to when sweeps do not
+    # overlap; the lanes' own interval sums count overlapping time once per lane
+    sweep_s = ph["sweeps_busy"] * 1e-3
     launches = ph["sweep_launches"]
     achieved_gbs = alg_bytes / sweep_s / 1e9 if sweep_s > 0 else None
     errs = [_pose_error(o[0].cpu().numpy(), w["poses"]) for o, w in zip(outs, wins)]
@@ -340,12 +344,14 @@ def run_batch(args):
                      "frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
                      "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid() else None,
                      "alg_bytes_per_launch": alg_bytes / max(launches, 1.0),
-                     "launch_ms": ph["sweeps"] / max(launches, 1.0), "launches": launches,
+                     "launch_ms": ph["sweeps_busy"] / max(launches, 1.0), "launches": launches,
+                     "launch_ms_concurrent": ph["sweeps"] / max(launches, 1.0),
                      "step_aggregate_GBs": alg_bytes / (ms * 1e-3) / 1e9,
                      "note": "algorithmic bytes of a sweep: the flow stack read once (8 B per pixel-frame) and the "
-                             "depth read and written (8 B per pixel); launch time = the sweep intervals between device "
-                             "timestamps on the lane streams during the last timed step (the graph replays them; "
-                             "lanes run concurrently)"},
+                             "depth read and written (8 B per pixel); launch_ms = the time during which the chip ran "
+                             "sweeps in the last timed step (union of the windows' sweep intervals between device "
+                             "timestamps on the lane streams) per launch; launch_ms_concurrent = the mean interval "
+                             "per launch on its own lane, stretched where lanes overlap"},
         "alu_view": {"achieved_TFLOPs": alg_ops / sweep_s / 1e12 if sweep_s > 0 else None,
                      "peak_TFLOPs": FP32_PEAK_TFLOPS,
                      "frac": alg_ops / sweep_s / 1e12 / FP32_PEAK_TFLOPS if sweep_s > 0 else None,

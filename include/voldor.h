@@ -309,8 +309,10 @@ int voldor_batch_autotune(voldor_batch *b, const voldor_window_desc *wins, int n
 /* Phase timing of a batch's windows, each lane as voldor_set_timing (a
  * captured graph replays the event records, so the summary covers the last
  * replay of every window captured since the previous summary).  The summary
- * waits, then gives in out[8] the phase SUMS (not means) over the windows of
- * every lane, the last 32 of each lane at most, and their number. */
+ * waits, then gives in out[0..6] the phase SUMS (not means) over the windows
+ * of every lane, the last 32 of each lane at most, in out[7] the time during
+ * which at least one lane ran sweeps (the union of the windows' sweep
+ * intervals on the device's real-time counter), and their number. */
 int voldor_batch_set_timing(voldor_batch *b, int enable);
 int voldor_batch_timing_summary(voldor_batch *b, double *out, int *n_windows);
 

@@ -630,13 +630,14 @@ class Batch:
     def timing_summary(self):
         """Phase milliseconds summed over the recorded windows of every lane
         (bootstrap, pose, sweeps, sweep launches, rigidness, loglik, window),
-        and their number."""
+        the milliseconds during which any lane ran sweeps (sweeps_busy), and
+        the number of windows."""
         out = np.zeros(8)
         n = C.c_int(0)
         _check(lib().voldor_batch_timing_summary(self._b, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)),
                "voldor_batch_timing_summary")
-        keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window"]
-        return dict(zip(keys, out[:7].tolist())), n.value
+        keys = ["bootstrap", "pose", "sweeps", "sweep_launches", "rigidness", "loglik", "window", "sweeps_busy"]
+        return dict(zip(keys, out.tolist())), n.value
 
     def autotune(self, windows, params, stream=None):
         """Tune the sweeps on the first window of every distinct shape of

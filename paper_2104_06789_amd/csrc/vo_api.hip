@@ -123,7 +123,6 @@ hipError_t dalloc(T **p, size_t n)
 // stamps keep working when the window is captured into a HIP graph: every
 // replay rewrites them.  The sweeps of one iteration share one interval: its
 // mean is the time per launch.
-enum { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseRig = 4, kPhaseLL = 5 };
 
 __global__ void k_stamp(unsigned long long *slot)
 {

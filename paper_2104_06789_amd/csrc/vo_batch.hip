@@ -200,6 +200,43 @@ int voldor_batch_timing_summary(voldor_batch *b, double *out, int *n_windows)
 {
     if (!b || !out) return VOLDOR_EINVAL;
     for (int i = 0; i < 8; ++i) out[i] = 0.0;
+    // out[7]: the time during which at least one lane ran sweeps, from the
+    // sweep intervals of every recorded window (the real-time counter is one
+    // clock for the whole device, so intervals of different lanes compare)
+    std::vector<std::pair<unsigned long long, unsigned long long>> iv;
+    double khz = 0.0;
+    for (int l = 0; l < b->lanes; ++l) {
+        voldor_ctx *c = b->ctx[l];
+        if (!c->timing) return VOLDOR_EINVAL;
+        if (c->tw_count == 0) continue;
+        if (hipStreamSynchronize(c->last_stream) != hipSuccess ||
+            hipMemcpy(c->stamps_host, c->stamps, sizeof(unsigned long long) * kTimingRing * kEvPerWin,
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return VOLDOR_EDEVICE;
+        khz = c->stamp_khz;
+        const long long n = c->tw_count < kTimingRing ? c->tw_count : kTimingRing;
+        for (long long k = c->tw_count - n; k < c->tw_count; ++k) {
+            const int w = (int)(k % kTimingRing);
+            const unsigned long long *st = c->stamps_host + w * kEvPerWin;
+            for (int i = 1; i < c->ev_n[w]; ++i)
+                if (c->ev_phase[w][i] == kPhaseSweep && st[i] > st[i - 1]) iv.emplace_back(st[i - 1], st[i]);
+        }
+    }
+    std::sort(iv.begin(), iv.end());
+    unsigned long long covered = 0, lo = 0, hi = 0;
+    bool open = false;
+    for (const auto &x : iv) {
+        if (open && x.first <= hi) {
+            if (x.second > hi) hi = x.second;
+        } else {
+            if (open) covered += hi - lo;
+            lo = x.first;
+            hi = x.second;
+            open = true;
+        }
+    }
+    if (open) covered += hi - lo;
+    const double union_ms = khz > 0.0 ? (double)covered / khz : 0.0;
     int total = 0;
     for (int l = 0; l < b->lanes; ++l) {
         double m[8];
@@ -209,6 +246,7 @@ int voldor_batch_timing_summary(voldor_batch *b, double *out, int *n_windows)
         for (int i = 0; i < 7; ++i) out[i] += m[i] * n;
         total += n;
     }
+    out[7] = union_ms;
     if (n_windows) *n_windows = total;
     return VOLDOR_OK;
 }

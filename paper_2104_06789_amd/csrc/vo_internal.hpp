@@ -20,6 +20,8 @@ constexpr int kCandTiles = 256;     // pixel ranges of the all-pixel candidate s
 
 // Device status word values (mirror voldor_status).
 enum : int { kStatusOk = 0, kStatusDegenerate = -4 };
+// phase of a timing interval (the interval that ends at a stamp)
+enum : int { kPhaseNone = -1, kPhaseBoot = 0, kPhasePose = 1, kPhaseSweep = 2, kPhaseRig = 4, kPhaseLL = 5 };
 constexpr int kTimingRing = 32;   // windows whose phase events are kept
 constexpr int kEvPerWin = 128;    // events per window, at most
 
