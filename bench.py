@@ -594,15 +594,28 @@ def run_learned(args):
     """The learned proposal: train it on windows labelled by the plain EM, then
     compare EM at LEARN_ITERS iterations from the proposal (falling back to the
     bootstrap's state where that explains the window better) against the plain
-    EM at LEARN_PLAIN_ITERS iterations on held-out windows."""
+    EM at LEARN_PLAIN_ITERS iterations on held-out windows.
+
+    --gen cpu: every window generated on the host before the GPU is touched,
+    labelled once, trained over for --epochs.  --gen gpu: windows generated on
+    the device (synthflow.torchgen, the same scene and noise laws) in chunks of
+    --chunk, each chunk labelled, trained over once per epoch and dropped, so
+    that training sets far larger than device memory stream through."""
     import synthflow
     n_train, n_eval = args.train_windows, args.eval_windows
-    workers = min(16, os.cpu_count() or 1)
-    # the CPU-sized generator at 640x480 with its intrinsics scaled x4, in forked
-    # workers before anything touches the GPU
+    gen_gpu = args.gen == "gpu"
     shapes = (("small", LEARN_W, LEARN_H),)
-    train = synthflow.make_batch(n_train, args.seed + 1, shapes=shapes, T_range=(LEARN_T, LEARN_T), workers=workers)
-    held = synthflow.make_batch(n_eval, args.seed + 2, shapes=shapes, T_range=(LEARN_T, LEARN_T), workers=workers)
+    train_seeds = [((args.seed + 1) << 16) + i for i in range(n_train)]
+    held_seeds = [((args.seed + 2) << 16) + i for i in range(n_eval)]
+    train = held = None
+    if not gen_gpu:
+        # the CPU-sized generator at 640x480 with its intrinsics scaled x4, in
+        # forked workers before anything touches the GPU
+        workers = min(16, os.cpu_count() or 1)
+        train = synthflow.make_batch(n_train, args.seed + 1, shapes=shapes, T_range=(LEARN_T, LEARN_T),
+                                     workers=workers)
+        held = synthflow.make_batch(n_eval, args.seed + 2, shapes=shapes, T_range=(LEARN_T, LEARN_T),
+                                    workers=workers)
     import numpy as np
     import torch
 
@@ -611,10 +624,27 @@ def run_learned(args):
     dev = torch.device("cuda:0")
     T, H, W = LEARN_T, LEARN_H, LEARN_W
     stream = torch.cuda.Stream()
+    gen_ms = [0.0]
+
+    def generate(seeds):
+        from synthflow.torchgen import make_window_torch
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        out = []
+        for sd in seeds:
+            w = make_window_torch("small", sd, dev, T=T, H=H, W=W)
+            out.append({"flows": w["flows"], "K": w["K"], "poses": w["poses"]})
+        torch.cuda.synchronize()
+        gen_ms[0] += (time.perf_counter() - g0) * 1e3
+        return out
+
+    def dev_flows(w):
+        f = w["flows"]
+        return f if isinstance(f, torch.Tensor) else torch.from_numpy(f).to(dev)
 
     def solve(wins, iters, props=None):
         p = vo.default_params(n_iters=iters, n_pose_groups=LEARN_GROUPS, seed=args.seed)
-        flows = [torch.from_numpy(w["flows"]).to(dev) for w in wins]
+        flows = [dev_flows(w) for w in wins]
         outs = [vo.Batch.outputs(T, H, W) for _ in wins]
         st = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
         ch = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
@@ -628,39 +658,67 @@ def run_learned(args):
             b.solve(items, p, st, stream=stream)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
+        b.close()
         if any(int(x) != 0 for x in st.cpu().tolist()):
             print("a window reported a nonzero status", file=sys.stderr)
             sys.exit(1)
         return outs, ms, ch
 
-    # labels: the plain EM's depth and final rigidness
-    labels, label_ms, _ = solve(train, LEARN_PLAIN_ITERS)
     net = vo.Net(T, args.learn_batch, H, W)
     net.set_params(_he_params(T, args.seed))
-    tflows = torch.stack([torch.from_numpy(w["flows"]) for w in train]).to(dev)
-    tdepth = torch.stack([o[1] for o in labels])
-    trig = torch.stack([o[2] for o in labels])
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     nb = args.learn_batch
     losses = []
-    t0 = time.perf_counter()
     steps = 0
+    train_s = 0.0
+    label_ms = 0.0
     rng = np.random.default_rng(args.seed)
-    for ep in range(args.epochs):
-        order = rng.permutation(n_train)
+
+    def train_over(tflows, tdepth, trig):
+        # one pass over the given windows in a random order, nb per Adam step
+        nonlocal steps, train_s
         ep_loss = []
-        for i in range(0, n_train - nb + 1, nb):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        order = rng.permutation(tflows.shape[0])
+        for i in range(0, tflows.shape[0] - nb + 1, nb):
             idx = torch.from_numpy(order[i:i + nb]).to(dev)
             net.train_step(tflows[idx].contiguous(), tdepth[idx].contiguous(), trig[idx].contiguous(), args.lr,
                            loss=loss)
             ep_loss.append(loss.clone())
             steps += 1
-        losses.append(float(torch.stack(ep_loss).mean()))
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        train_s += time.perf_counter() - t0
+        return ep_loss
+
+    if not gen_gpu:
+        # labels: the plain EM's depth and final rigidness
+        labels, label_ms, _ = solve(train, LEARN_PLAIN_ITERS)
+        tflows = torch.stack([torch.from_numpy(w["flows"]) for w in train]).to(dev)
+        tdepth = torch.stack([o[1] for o in labels])
+        trig = torch.stack([o[2] for o in labels])
+        for ep in range(args.epochs):
+            losses.append(float(torch.stack(train_over(tflows, tdepth, trig)).mean()))
+    else:
+        for ep in range(args.epochs):
+            ep_loss = []
+            for c0 in range(0, n_train, args.chunk):
+                wins = generate(train_seeds[c0:c0 + args.chunk])
+                labels, ms, _ = solve(wins, LEARN_PLAIN_ITERS)
+                if ep == 0:
+                    label_ms += ms
+                tflows = torch.stack([w["flows"] for w in wins])
+                tdepth = torch.stack([o[1] for o in labels])
+                trig = torch.stack([o[2] for o in labels])
+                ep_loss += train_over(tflows, tdepth, trig)
+                del wins, labels, tflows, tdepth, trig
+                print(f"epoch {ep} windows {min(c0 + args.chunk, n_train)}/{n_train} "
+                      f"loss {float(torch.stack(ep_loss[-16:]).mean()):.4f}", file=sys.stderr, flush=True)
+            losses.append(float(torch.stack(ep_loss).mean()))
+        held = generate(held_seeds)
 
     # matrix-core rate of the forward pass on one training batch, HIP events on its stream
-    fb = tflows[:nb].contiguous()
+    fb = torch.stack([dev_flows(w) for w in held[:nb]]).contiguous()
     with torch.cuda.stream(stream):
         net.forward(fb, stream=stream)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -677,7 +735,7 @@ def run_learned(args):
 
     # held-out windows: plain EM vs proposal + shorter EM
     plain, plain_ms, _ = solve(held, LEARN_PLAIN_ITERS)
-    hflows = torch.stack([torch.from_numpy(w["flows"]) for w in held]).to(dev)
+    hflows = torch.stack([dev_flows(w) for w in held])
     pdepth = torch.empty((n_eval, H, W), device=dev)
     prig = torch.empty((n_eval, T, H, W), device=dev)
     torch.cuda.synchronize()
@@ -722,7 +780,9 @@ def run_learned(args):
                     "proposal_ms": prop_ms, "em_ms": learned_ms,
                     "median_abs_log_depth_vs_plain": float(np.mean(ds))},
         "bootstrap_em_short": {"windows_per_s": n_eval * 1e3 / shorter_ms, "pose_error_vs_gt": errs(shorter)},
-        "training": {"loss_per_epoch": losses, "steps": steps, "seconds": train_s, "label_ms": label_ms},
+        "training": {"loss_per_epoch": losses, "steps": steps, "seconds": train_s, "label_ms": label_ms,
+                     "generator": ("device (synthflow.torchgen), chunks of %d windows" % args.chunk) if gen_gpu
+                     else "host (synthflow.make_batch)", "generate_ms": gen_ms[0]},
         "roofline": {"bound": "mfma", "kernel": "k_conv (six layers, forward)", "achieved": achieved,
                      "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
                      "flops_per_pass": conv_flops, "pass_ms": fwd_ms},
@@ -790,6 +850,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="(--workload learned)")
     ap.add_argument("--learn-batch", type=int, default=4, help="(--workload learned)")
     ap.add_argument("--lr", type=float, default=1e-3, help="(--workload learned)")
+    ap.add_argument("--gen", default="cpu", choices=["cpu", "gpu"],
+                    help="(--workload learned) where the windows are generated; gpu streams the training set "
+                         "in chunks")
+    ap.add_argument("--chunk", type=int, default=256, help="(--workload learned --gen gpu) windows per chunk")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -245,21 +245,9 @@ def _fisk_noise(rng, flow, c1, c0, beta):
     return np.stack([e * np.cos(ang), e * np.sin(ang)], axis=-1)
 
 
-def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None, keep_focal=False,
-                speed_range=None):
-    """Generate one window.
-
-    Returns a dict with
-      flows     float32 [T,H,W,2]
-      K         (fx, fy, cx, cy)
-      poses     list of T (R 3x3, t 3) relative ground-truth poses
-      depth     float64 [H,W] ground-truth z-depth of frame 0
-      outlier   bool [T,H,W] independently-moving pixels on frame t-1's grid
-      spec      the WindowSpec used (with T/H/W overrides applied)
-    speed_range (lo, hi): each frame's translation is scaled by a factor drawn
-    uniformly from [lo, hi] by a generator of its own (the default draws
-    nothing and leaves every other stream unchanged).
-    """
+def resolve_spec(spec, T=None, H=None, W=None, keep_focal=False):
+    """A copy of the spec (or the named one) with T/H/W overrides applied; a
+    new size scales the intrinsics (keep_focal: only the principal point)."""
     if isinstance(spec, str):
         spec = SPECS[spec]
     spec = WindowSpec(**{**spec.__dict__})
@@ -279,12 +267,18 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
             spec.cx *= sx
             spec.fy *= sy
             spec.cy *= sy
-    rng = np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0x5EED0000)))
-    Tn, Hn, Wn = spec.T, spec.H, spec.W
+    return spec
 
-    # ---- camera motion
+
+def window_rng(seed):
+    """The generator of window `seed` (scene, motion, outliers and noise draws)."""
+    return np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0x5EED0000)))
+
+
+def camera_motion(spec, rng, seed=0, speed_range=None):
+    """The T relative ground-truth poses (R, t) of a window, drawn from rng."""
     poses = []
-    for _ in range(Tn):
+    for _ in range(spec.T):
         if spec.scene == "driving":
             yaw = math.radians(rng.uniform(-spec.rot_deg, spec.rot_deg))
             R = rot_axis_angle([0.0, 1.0, 0.0], yaw)
@@ -297,6 +291,28 @@ def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None,
     if speed_range is not None:
         srng = np.random.Generator(np.random.Philox(key=np.uint64(seed) + np.uint64(0x5BEED000)))
         poses = [(R, t * srng.uniform(*speed_range)) for R, t in poses]
+    return poses
+
+
+def make_window(spec, seed=0, noise=True, outliers=True, T=None, H=None, W=None, keep_focal=False,
+                speed_range=None):
+    """Generate one window.
+
+    Returns a dict with
+      flows     float32 [T,H,W,2]
+      K         (fx, fy, cx, cy)
+      poses     list of T (R 3x3, t 3) relative ground-truth poses
+      depth     float64 [H,W] ground-truth z-depth of frame 0
+      outlier   bool [T,H,W] independently-moving pixels on frame t-1's grid
+      spec      the WindowSpec used (with T/H/W overrides applied)
+    speed_range (lo, hi): each frame's translation is scaled by a factor drawn
+    uniformly from [lo, hi] by a generator of its own (the default draws
+    nothing and leaves every other stream unchanged).
+    """
+    spec = resolve_spec(spec, T, H, W, keep_focal)
+    rng = window_rng(seed)
+    Tn, Hn, Wn = spec.T, spec.H, spec.W
+    poses = camera_motion(spec, rng, seed, speed_range)
     Ms = _cumulative(poses)
 
     xs, ys, rays = _rays(spec, Hn, Wn)
