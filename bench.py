@@ -845,15 +845,15 @@ def main():
                     help="skip the single-window indoor and driving figures of the batch workload")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the four-lane figure (profiles of the sequential windows alone)")
-    ap.add_argument("--train-windows", type=int, default=384, help="(--workload learned)")
-    ap.add_argument("--eval-windows", type=int, default=96, help="(--workload learned)")
-    ap.add_argument("--epochs", type=int, default=20, help="(--workload learned)")
+    ap.add_argument("--train-windows", type=int, default=20000, help="(--workload learned)")
+    ap.add_argument("--eval-windows", type=int, default=512, help="(--workload learned)")
+    ap.add_argument("--epochs", type=int, default=1, help="(--workload learned)")
     ap.add_argument("--learn-batch", type=int, default=4, help="(--workload learned)")
     ap.add_argument("--lr", type=float, default=1e-3, help="(--workload learned)")
-    ap.add_argument("--gen", default="cpu", choices=["cpu", "gpu"],
+    ap.add_argument("--gen", default="gpu", choices=["cpu", "gpu"],
                     help="(--workload learned) where the windows are generated; gpu streams the training set "
                          "in chunks")
-    ap.add_argument("--chunk", type=int, default=256, help="(--workload learned --gen gpu) windows per chunk")
+    ap.add_argument("--chunk", type=int, default=500, help="(--workload learned --gen gpu) windows per chunk")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
