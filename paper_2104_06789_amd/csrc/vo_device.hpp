@@ -109,6 +109,23 @@ __device__ __forceinline__ bool displacement_any(const Geo &g, float th, float f
     return pz > 0.0f;
 }
 
+// a + b and a - b never fused with a product that feeds them.  Which product
+// the compiler would fuse depends on the code around the expression, so the
+// kernels that evaluate the same emission (the sweep's passes, the rigidness
+// pass, the pose step) would round it differently; these sums keep every
+// kernel on one FP32 function of its inputs.
+__device__ __forceinline__ float add_nc(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+
+__device__ __forceinline__ float sub_nc(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a - b;
+}
+
 // Displacement pi_t(theta) - (x, y) of the frame-0 pixel with normalised
 // coordinates (xh, yh) at depth th.  False if the point is not in front.
 __device__ __forceinline__ bool displacement(const FrameF &f, float xh, float yh, float th,
@@ -141,7 +158,7 @@ __device__ __forceinline__ float log1p_rel(float e, float u, float inv_u)
 
 __device__ __forceinline__ float softplus(float z)
 {
-    return fmaxf(z, 0.0f) + log1p_unit(fast_exp(-fabsf(z)));
+    return add_nc(fmaxf(z, 0.0f), log1p_unit(fast_exp(-fabsf(z))));
 }
 
 // taps_finite: all four taps of a bilinear lookup are finite iff the
@@ -151,6 +168,16 @@ __device__ __forceinline__ float softplus(float z)
 // inf - inf or 0 * inf = NaN where it is zero, whatever the weights; finite
 // taps (flows far below 1e38) give finite u and v.  So the kernels test the
 // interpolated values instead of the eight taps.
+
+// Bilinear interpolation of taps a (x0, y0), b (x0 + 1, y0), c (x0, y0 + 1),
+// d (x0 + 1, y0 + 1) at fractions (ax, ay).  The fused multiply-adds are
+// written out, so that no kernel is left a choice of which product to fuse:
+// every kernel evaluates the same FP32 function.
+__device__ __forceinline__ float bilerp(float a, float b, float c, float d, float ax, float ay)
+{
+    const float top = fmaf(ax, b - a, a), bot = fmaf(ax, d - c, c);
+    return fmaf(ay, bot, (1.0f - ay) * top);
+}
 
 // Bilinear sample of flow X (one frame, float2 [H][W]) at (px, py).
 // Domain [0, W-1] x [0, H-1]; all four taps must be finite.
@@ -165,8 +192,8 @@ __device__ __forceinline__ bool sample_flow(const float2 *__restrict__ X, int H,
     const float2 *row0 = X + (size_t)y0 * W + x0;
     const float2 *row1 = row0 + W;
     const float2 a = row0[0], b = row0[1], c = row1[0], d = row1[1];
-    u = (1.0f - ay) * fmaf(ax, b.x - a.x, a.x) + ay * fmaf(ax, d.x - c.x, c.x);
-    v = (1.0f - ay) * fmaf(ax, b.y - a.y, a.y) + ay * fmaf(ax, d.y - c.y, c.y);
+    u = bilerp(a.x, b.x, c.x, d.x, ax, ay);
+    v = bilerp(a.y, b.y, c.y, d.y, ax, ay);
     return isfinite(a.x + a.y + b.x + b.y + c.x + c.y + d.x + d.y);
 }
 
@@ -202,8 +229,8 @@ __device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, f
         const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
         const float lx = fast_log(x2);
         const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
-        const float z1 = beta * (lx - la), z2 = beta * (lm - la);
-        return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+        const float z1 = beta * sub_nc(lx, la), z2 = beta * sub_nc(lm, la);
+        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus(z2) - softplus(z1)));
     }
 }
 
@@ -228,9 +255,9 @@ __device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, floa
         const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
         const float lx = fast_log(x2);
         const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
-        const float z1 = beta * (lx - la), z2 = beta * (lm - la);
-        lmu = (fast_log(beta) - la) + (beta - 1.0f) * (lm - la) - 2.0f * softplus(z2);
-        return (beta - 1.0f) * (lm - lx) - 2.0f * (softplus(z2) - softplus(z1));
+        const float z1 = beta * sub_nc(lx, la), z2 = beta * sub_nc(lm, la);
+        lmu = fmaf(beta - 1.0f, sub_nc(lm, la), sub_nc(fast_log(beta), la)) - 2.0f * softplus(z2);
+        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus(z2) - softplus(z1)));
     }
 }
 

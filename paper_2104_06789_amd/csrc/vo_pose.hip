@@ -721,7 +721,7 @@ __global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
             bool v = in && th[k] > 0.0f;
             if (a.t > 1) v = v && displacement(pf, xh[k], yh[k], th[k], e.fx, e.fy, dx0[k], dy0[k]);
             float fu = 0.0f, fv = 0.0f;
-            v = v && sample_flow(X, a.H, a.W, (float)x + dx0[k], (float)y + dy0[k], fu, fv);
+            v = v && sample_flow(X, a.H, a.W, add_nc((float)x, dx0[k]), add_nc((float)y, dy0[k]), fu, fv);
             ok[k] = v;
             vu[k] = fu;
             vv[k] = fv;
@@ -751,7 +751,7 @@ __global__ void __launch_bounds__(kCandThreads) k_cand_score(CandScoreArgs a)
                     float ell = kLogHalfF;
                     float dx1, dy1;
                     if (ok[k] && displacement(f, xh[k], yh[k], th[k], e.fx, e.fy, dx1, dy1)) {
-                        const float rx = (dx1 - dx0[k]) - vu[k], ry = (dy1 - dy0[k]) - vv[k];
+                        const float rx = sub_nc(sub_nc(dx1, dx0[k]), vu[k]), ry = sub_nc(sub_nc(dy1, dy0[k]), vv[k]);
                         const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
                         float d;
                         if constexpr (MODEL == 1) {

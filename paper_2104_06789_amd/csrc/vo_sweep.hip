@@ -65,10 +65,10 @@ __device__ __forceinline__ void chain_xy(int dir, int H, int W, int c, int k, in
     y = (dir & 1) ? (dir == 1 ? k : H - 1 - k) : c;
 }
 
-// Depth score at chain position k, frames in chunks of three so that the flow
-// gathers of a chunk are in flight together: MIE (Eq. 10) sum_t q_t ell_t(th),
-// a missing frame log 1/2; MLE (Eq. 9) sum_t log mu_t - q_t d_t, a missing
-// frame 0
+// Depth score at chain position k, frames in chunks (three; two for the
+// log-form score) so that the flow gathers of a chunk are in flight together:
+// MIE (Eq. 10) sum_t q_t ell_t(th), a missing frame log 1/2; MLE (Eq. 9)
+// sum_t log mu_t - q_t d_t, a missing frame 0
 template <int CRIT, int MODEL>
 __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
                                              int T, int H, int W, const EmisParams &e, int x, int y,
@@ -82,25 +82,28 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     float pdx = 0.0f, pdy = 0.0f;
     bool pok = th > 0.0f;
     const int HW = H * W;   // T H W < 2^31 (frames <= 16, sides <= 4096)
-    for (int t0 = 1; t0 <= T; t0 += 3) {
-        float dx[3], dy[3], qv[3];
-        bool ok[3];
+    // frames per chunk (their gathers in flight together); the log-form
+    // score of the Gaussian model holds more state, so two
+    constexpr int FC = LOGS ? 2 : 3;
+    for (int t0 = 1; t0 <= T; t0 += FC) {
+        float dx[FC], dy[FC], qv[FC];
+        bool ok[FC];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) qv[u] = q[(min(t0 + u, T) - 1) * L + k];   // issued with the gathers
+        for (int u = 0; u < FC; ++u) qv[u] = q[(min(t0 + u, T) - 1) * L + k];   // issued with the gathers
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < FC; ++u) {
             const int t = t0 + u;
             const bool f = displacement_any(pixel_geometry(fr[t <= T ? t : T], xh, yh), th, e.fx, e.fy, dx[u], dy[u]);
             ok[u] = (t <= T) & (th > 0.0f) & f;
         }
-        float2 ta[3], tb[3], tc[3], td[3];
-        float ax[3], ay[3], lx[3], ly[3];
-        bool val[3];
+        float2 ta[FC], tb[FC], tc[FC], td[FC];
+        float ax[FC], ay[FC], lx[FC], ly[FC];
+        bool val[FC];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < FC; ++u) {
             const float bdx = u == 0 ? pdx : dx[u - 1], bdy = u == 0 ? pdy : dy[u - 1];
             const bool bok = u == 0 ? pok : ok[u - 1];
-            const float px = (float)x + bdx, py = (float)y + bdy;
+            const float px = add_nc((float)x, bdx), py = add_nc((float)y, bdy);
             val[u] = bok & ok[u] & (px >= 0.0f) & (px <= (float)(W - 1)) & (py >= 0.0f) & (py <= (float)(H - 1));
             lx[u] = bdx;
             ly[u] = bdy;
@@ -117,35 +120,35 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             td[u] = r0[W + 1];
         }
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < FC; ++u) {
             const int t = t0 + u;
             if (t > T) break;
             // computed for every frame (branch-free), kept where observed
             const float2 a = ta[u], b = tb[u], c = tc[u], d = td[u];
-            const float vu = (1.0f - ay[u]) * fmaf(ax[u], b.x - a.x, a.x) + ay[u] * fmaf(ax[u], d.x - c.x, c.x);
-            const float vv = (1.0f - ay[u]) * fmaf(ax[u], b.y - a.y, a.y) + ay[u] * fmaf(ax[u], d.y - c.y, c.y);
+            const float vu = bilerp(a.x, b.x, c.x, d.x, ax[u], ay[u]);
+            const float vv = bilerp(a.y, b.y, c.y, d.y, ax[u], ay[u]);
             const bool obs = val[u] & isfinite(vu + vv);   // every tap finite (see taps_finite)
             if constexpr (LOGS) {
                 float lam = kLogLn2F;
                 if (obs) {
-                    const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                    const float dd = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
                     float rr;
                     lam = neg_ell_log(dd, rr);
                 }
                 logscore_add(ls, qv[u], lam);
             } else if constexpr (CRIT == 0) {
-                const float dd = log_mu_over_rho<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e);
+                const float dd = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
                 const float ell = emis_from_d(dd).ell;
                 s = fmaf(qv[u], obs ? ell : kLogHalf, s);
             } else {
                 float lmu;
-                const float dd = log_mu_and_d<MODEL>((dx[u] - lx[u]) - vu, (dy[u] - ly[u]) - vv, vu, vv, e, lmu);
+                const float dd = log_mu_and_d<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e, lmu);
                 if (obs) s += fmaf(-qv[u], dd, lmu);
             }
         }
-        pdx = dx[2];
-        pdy = dy[2];
-        pok = ok[2];
+        pdx = dx[FC - 1];
+        pdy = dy[FC - 1];
+        pok = ok[FC - 1];
     }
     if constexpr (LOGS) return logscore_value(ls);
     return s;
@@ -172,7 +175,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         dy0[b] = 0.0f;
         if (tt > 1) v = v && displacement(fr[tt - 1], xh, yh, th[b], e.fx, e.fy, dx0[b], dy0[b]);
         v = v && displacement(fr[tt], xh, yh, th[b], e.fx, e.fy, dx1[b], dy1[b]);
-        const float px = (float)x[b] + dx0[b], py = (float)y[b] + dy0[b];
+        const float px = add_nc((float)x[b], dx0[b]), py = add_nc((float)y[b], dy0[b]);
         v = v && px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1);
         ok[b] = v;
         const float spx = v ? px : 0.0f, spy = v ? py : 0.0f;
@@ -188,15 +191,15 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const float2 A = ta[b], Bv = tb[b], Cv = tc[b], Dv = td[b];
-        const float vu = (1.0f - ay[b]) * fmaf(ax[b], Bv.x - A.x, A.x) + ay[b] * fmaf(ax[b], Dv.x - Cv.x, Cv.x);
-        const float vv = (1.0f - ay[b]) * fmaf(ax[b], Bv.y - A.y, A.y) + ay[b] * fmaf(ax[b], Dv.y - Cv.y, Cv.y);
+        const float vu = bilerp(A.x, Bv.x, Cv.x, Dv.x, ax[b], ay[b]);
+        const float vv = bilerp(A.y, Bv.y, Cv.y, Dv.y, ax[b], ay[b]);
         ok[b] = ok[b] && isfinite(vu + vv);   // every tap finite (see taps_finite)
         if constexpr (MU) {
             float lm = 0.0f;
-            d[b] = ok[b] ? log_mu_and_d<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e, lm) : 0.0f;
+            d[b] = ok[b] ? log_mu_and_d<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e, lm) : 0.0f;
             lmu[b] = ok[b] ? lm : 0.0f;
         } else {
-            d[b] = ok[b] ? log_mu_over_rho<MODEL>((dx1[b] - dx0[b]) - vu, (dy1[b] - dy0[b]) - vv, vu, vv, e) : 0.0f;
+            d[b] = ok[b] ? log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e) : 0.0f;
         }
     }
 }
@@ -231,7 +234,7 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
             const bool f1 = displacement_any(g1, th, e.fx, e.fy, dx1[i], dy1[i]);
             dx0[i] = tt > 1 ? ex : 0.0f;
             dy0[i] = tt > 1 ? ey : 0.0f;
-            const float px = (float)x[b] + dx0[i], py = (float)y[b] + dy0[i];
+            const float px = add_nc((float)x[b], dx0[i]), py = add_nc((float)y[b], dy0[i]);
             const bool ok = act[b] & (th > 0.0f) & (f0 | (tt <= 1)) & f1 & (px >= 0.0f) & (px <= (float)(W - 1)) &
                             (py >= 0.0f) & (py <= (float)(H - 1));
             v[i] = ok;
@@ -250,10 +253,10 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
 #pragma unroll
     for (int i = 0; i < 2 * B; ++i) {
         const float2 A = ta[i], Bv = tb[i], Cv = tc[i], Dv = td[i];
-        const float vu = (1.0f - ay[i]) * fmaf(ax[i], Bv.x - A.x, A.x) + ay[i] * fmaf(ax[i], Dv.x - Cv.x, Cv.x);
-        const float vv = (1.0f - ay[i]) * fmaf(ax[i], Bv.y - A.y, A.y) + ay[i] * fmaf(ax[i], Dv.y - Cv.y, Cv.y);
+        const float vu = bilerp(A.x, Bv.x, Cv.x, Dv.x, ax[i], ay[i]);
+        const float vv = bilerp(A.y, Bv.y, Cv.y, Dv.y, ax[i], ay[i]);
         const bool ok = v[i] & isfinite(vu + vv);   // every tap finite (see taps_finite)
-        const float dv = log_mu_over_rho<MODEL>((dx1[i] - dx0[i]) - vu, (dy1[i] - dy0[i]) - vv, vu, vv, e);
+        const float dv = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx1[i], dx0[i]), vu), sub_nc(sub_nc(dy1[i], dy0[i]), vv), vu, vv, e);
         const float d = ok ? dv : 0.0f;
         if (i & 1) {
             ds[i >> 1] = d;
@@ -405,9 +408,7 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
         b1 = n1 * inv;
         b0 = n0 * inv;
     }
-    // forward messages: in registers for short segments, else through rq
-    constexpr bool FREG = SEG <= 11;
-    float ff[FREG ? SEG : 1];
+    float ff[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
         const float r1 = rr[i];
@@ -416,13 +417,11 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
         const float inv = frcp(n1 + n0);
         f1 = n1 * inv;
         f0 = n0 * inv;
-        if constexpr (FREG) ff[i] = f1;
-        else if (i < n) rq[s0 + i] = f1;
+        ff[i] = f1;
     }
-    if constexpr (!FREG) asm volatile("" ::: "memory");   // read back below, not kept live
 #pragma unroll
     for (int i = SEG - 1; i >= 0; --i) {
-        const float ff1 = FREG ? ff[FREG ? i : 0] : rq[s0 + i], ff0 = 1.0f - ff1;
+        const float ff1 = ff[i], ff0 = 1.0f - ff1;
         const float n1 = ff1 * b1, n0 = ff0 * b0;
         if (i < n) rq[s0 + i] = n1 * frcp(n1 + n0);
         if (i > 0) {
@@ -608,11 +607,10 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
         for (int t = wv; t < T; t += (NT / 64)) {
             float *rq = fq + t * L;
             const float *ll = lq + t * L;
-            // segments held in registers up to 21 positions (chains of 1344)
+            // segments held in registers up to 11 positions (chains of 704)
             if (seglen <= 5) { fb_segment_regs<5>(rq, s0, s1, g, gc, lane); continue; }
             if (seglen <= 7) { fb_segment_regs<7>(rq, s0, s1, g, gc, lane); continue; }
             if (seglen <= 11) { fb_segment_regs<11>(rq, s0, s1, g, gc, lane); continue; }
-            if (seglen <= 21) { fb_segment_regs<21>(rq, s0, s1, g, gc, lane); continue; }
             // segment transfer matrices: forward A_k = diag(r,1-r) Gamma,
             // product A_{s1-1}..A_{s0}; backward G_k = Gamma diag(r,1-r),
             // product G_{s0}..G_{s1-1}
@@ -924,7 +922,7 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                 bx[u] = u == 0 ? px0 : dx1[u - 1];
                 by[u] = u == 0 ? py0 : dy1[u - 1];
                 const bool bok = u == 0 ? ok0 : ok1[u - 1];
-                const float spx = (float)x + bx[u], spy = (float)y + by[u];
+                const float spx = add_nc((float)x, bx[u]), spy = add_nc((float)y, by[u]);
                 val[u] = bok && ok1[u] && spx >= 0.0f && spx <= (float)(a.W - 1) && spy >= 0.0f &&
                          spy <= (float)(a.H - 1);
                 const float qx = val[u] ? spx : 0.0f, qy = val[u] ? spy : 0.0f;
@@ -943,10 +941,10 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                 if (t > a.T) break;
                 float r = 0.5f, ell = -0.69314718055994531f, lr = 0.0f, lm = 0.0f;
                 const float2 A = ta[u], B = tb[u], Cc = tc[u], D = td[u];
-                const float vu = (1.0f - ay[u]) * fmaf(ax[u], B.x - A.x, A.x) + ay[u] * fmaf(ax[u], D.x - Cc.x, Cc.x);
-                const float vv = (1.0f - ay[u]) * fmaf(ax[u], B.y - A.y, A.y) + ay[u] * fmaf(ax[u], D.y - Cc.y, Cc.y);
+                const float vu = bilerp(A.x, B.x, Cc.x, D.x, ax[u], ay[u]);
+                const float vv = bilerp(A.y, B.y, Cc.y, D.y, ax[u], ay[u]);
                 if (val[u] && isfinite(vu + vv)) {   // every tap finite (see taps_finite)
-                    const float rx = (dx1[u] - bx[u]) - vu, ry = (dy1[u] - by[u]) - vv;
+                    const float rx = sub_nc(sub_nc(dx1[u], bx[u]), vu), ry = sub_nc(sub_nc(dy1[u], by[u]), vv);
                     const float d = a.e.model ? log_mu_over_rho<1>(rx, ry, vu, vv, a.e)
                                               : log_mu_over_rho<0>(rx, ry, vu, vv, a.e);
                     const Emis m = emis_from_d(d);

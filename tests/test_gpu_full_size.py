@@ -192,7 +192,9 @@ def test_full_sweep(vo, torch, name, direction):
     # E-step: the emission, the FB arithmetic on the GPU's own r, and q overall
     r, _, _, _, obs = oracle.emission_map(theta.astype(np.float64), w["flows"], w["K"], op, M)
     _emission_close(gr, r, obs)
-    assert np.abs(q - oracle.fb_map(gr.astype(np.float64), direction, op.gamma)).max() <= 1e-5
+    dfb = np.abs(q - oracle.fb_map(gr.astype(np.float64), direction, op.gamma))
+    print("FB of the GPU's own r: max", dfb.max(), "99.9999th percentile", np.percentile(dfb, 99.9999))
+    assert dfb.max() <= 1e-5
     dq = np.abs(q - oracle.fb_map(r, direction, op.gamma))
     assert np.median(dq) <= 1e-5 and np.percentile(dq, 99.99) <= 2e-3
     # M-step: every decision valid under FP64 scoring, up to FP32 near ties

@@ -91,8 +91,9 @@ def test_sweep_parity(vo, torch, direction, criterion, model):
 @pytest.mark.parametrize("W", [1300, 1500])
 @pytest.mark.parametrize("direction", [0, 2])
 def test_sweep_parity_long_rows(vo, torch, W, direction):
-    # rows of 1300 (forward-backward segments of 21 positions, the longest held
-    # in registers) and of 1500 (segments of 25, walked in LDS)
+    # rows of 1300 and 1500 (forward-backward segments of 21 and 25
+    # positions, walked in LDS; segments of up to 11 live in registers and the
+    # ragged rows of 83 above cover them)
     _sweep_case(vo, torch, 2, 20, W, direction, 0, 0)
 
 
