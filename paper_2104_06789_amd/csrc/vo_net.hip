@@ -151,6 +151,127 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// The whole forward pass on one output tile of kFuseTH x kFuseTW pixels, every
+// intermediate activation in LDS: the tile's input region (6 pixels of halo,
+// one per layer) is staged once, and each layer reads one LDS buffer and
+// writes the other, its output region one pixel smaller on every side.
+// Output pixels of a region are taken 16 at a time in row-major order (a group
+// may span two rows), so no MFMA lane idles at row ends.  Positions outside
+// the image hold 0 in every buffer (the zero padding of each layer).  Every
+// output is computed as k_conv computes it (the same taps in the same order,
+// the same bias, ReLU and BF16 rounding), so the result equals the per-layer
+// pass bit for bit.
+constexpr int kFuseTW = 32, kFuseTH = 16, kFuseHalo = 6;
+constexpr int kFuseInW = kFuseTW + 2 * kFuseHalo, kFuseInH = kFuseTH + 2 * kFuseHalo;
+constexpr int kFuseBufA = kFuseInW * kFuseInH * kNetC;                   // BF16 elements
+constexpr int kFuseBufB = (kFuseInW - 2) * (kFuseInH - 2) * kNetC;
+constexpr int kFuseThreads = 512;
+
+struct FusedArgs {
+    const __bf16 *x;      // [N][H][W][32] network input
+    const __bf16 *w[6];   // [9][16 MT][32] per layer
+    const float *b[6];    // [16 MT] per layer
+    float *z;             // [N][H][W][16]
+    int N, H, W;
+    int tiles_x, tiles_y;
+};
+
+template <int MT, bool LAST>
+__device__ __forceinline__ void fused_layer(const FusedArgs &a, int k, const __bf16 *in, __bf16 *out, int win,
+                                            int hin, int oy, int ox, int n, int lane, int wave)
+{
+    const int r = lane & 15, q = lane >> 4;
+    const int wout = win - 2, hout = hin - 2, npx = wout * hout;
+    bf16x8 wr[9][MT];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) wr[tap][mt] = load8(a.w[k] + ((tap * 16 * MT) + 16 * mt + r) * kNetC + 8 * q);
+    // two groups of 16 pixels per step: their accumulation chains interleave
+    // on the matrix core (each chain's nine taps depend on one another)
+    constexpr int G = 2;
+    for (int g0 = G * wave; g0 * 16 < npx; g0 += G * (kFuseThreads / 64)) {
+        int pix[G], prow[G], pcol[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            pix[j] = (g0 + j) * 16 + r;
+            const int pc = pix[j] < npx ? pix[j] : npx - 1;   // idle lanes read a valid pixel
+            prow[j] = pc / wout;
+            pcol[j] = pc - prow[j] * wout;
+        }
+        f32x4 acc[G][MT];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[j][mt] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const bf16x8 bv = load8(in + ((prow[j] + tap / 3) * win + pcol[j] + tap % 3) * kNetC + 8 * q);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[j][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[tap][mt], bv, acc[j][mt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (pix[j] >= npx) continue;
+            const int gy = oy + prow[j], gx = ox + pcol[j];   // the output pixel in the image
+            const bool inside = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int m = 16 * mt + 4 * q;
+                float v[4] = {acc[j][mt][0], acc[j][mt][1], acc[j][mt][2], acc[j][mt][3]};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] += a.b[k][m + i];
+                if constexpr (LAST) {
+                    if (inside)
+                        *(float4 *)(a.z + (((int64_t)n * a.H + gy) * a.W + gx) * kNetCo6 + m) =
+                            make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(v[i], 0.0f) : 0.0f;
+                    store4(out + pix[j] * kNetC + m, v[0], v[1], v[2], v[3]);
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kFuseThreads) k_net_fused(FusedArgs a)
+{
+    extern __shared__ __bf16 fl[];
+    __bf16 *bufA = fl, *bufB = fl + kFuseBufA;
+    const int per = a.tiles_x * a.tiles_y;
+    const int n = blockIdx.x / per, t = blockIdx.x - n * per;
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int y0 = ty * kFuseTH - kFuseHalo, x0 = tx * kFuseTW - kFuseHalo;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the input region, 16 bytes (eight channels) per item, zero outside the image
+    for (int i = threadIdx.x; i < kFuseInW * kFuseInH * 4; i += kFuseThreads) {
+        const int pix = i >> 2, c = i & 3;
+        const int row = pix / kFuseInW, col = pix - row * kFuseInW;
+        const int gy = y0 + row, gx = x0 + col;
+        uint4 u = {0u, 0u, 0u, 0u};
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+            u = *(const uint4 *)(a.x + (((int64_t)n * a.H + gy) * a.W + gx) * kNetC + 8 * c);
+        *(uint4 *)(bufA + pix * kNetC + 8 * c) = u;
+    }
+    __syncthreads();
+    int win = kFuseInW, hin = kFuseInH;
+    for (int k = 0; k < 5; ++k) {
+        const __bf16 *in = (k & 1) ? bufB : bufA;
+        __bf16 *out = (k & 1) ? bufA : bufB;
+        fused_layer<2, false>(a, k, in, out, win, hin, y0 + k + 1, x0 + k + 1, n, lane, wave);
+        __syncthreads();
+        win -= 2;
+        hin -= 2;
+    }
+    fused_layer<1, true>(a, 5, bufB, nullptr, win, hin, y0 + 6, x0 + 6, n, lane, wave);
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient of one layer: partial[blk][tap][m][k] = sum over the block's
 // pixels of dy[p][m] x[p + off(tap)][k], partial bias sums pb[blk][m]
 struct WgradArgs {
@@ -471,6 +592,33 @@ int conv_launch(int mode, int MT, const __bf16 *in, const __bf16 *w, const float
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
+// the forward pass for inference: the input channels, then all six layers in
+// one launch with the activations in LDS (k_net_fused)
+int forward_fused_launch(voldor_net *nt, const float *flows, int N, int H, int W, hipStream_t s)
+{
+    const int64_t npx = (int64_t)N * H * W;
+    hipLaunchKernelGGL(k_net_input, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, (const float2 *)flows,
+                       nt->act[0], N, nt->T, H, W, 1.0f / 16.0f);
+    FusedArgs a;
+    a.x = nt->act[0];
+    for (int k = 0; k < 6; ++k) {
+        a.w[k] = nt->wf[k];
+        a.b[k] = nt->p + nt->off[k] + 9 * kNetC * nt->CO[k];
+    }
+    a.z = nt->z;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    a.tiles_x = (W + kFuseTW - 1) / kFuseTW;
+    a.tiles_y = (H + kFuseTH - 1) / kFuseTH;
+    const size_t lds = sizeof(__bf16) * (size_t)(kFuseBufA + kFuseBufB);
+    if (hipFuncSetAttribute((const void *)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        return VOLDOR_EDEVICE;
+    hipLaunchKernelGGL(k_net_fused, dim3((unsigned)(N * a.tiles_x * a.tiles_y)), dim3(kFuseThreads), lds, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
 int forward_launch(voldor_net *nt, const float *flows, int N, int H, int W, hipStream_t s)
 {
     const int64_t npx = (int64_t)N * H * W;
@@ -638,7 +786,7 @@ int voldor_net_forward(voldor_net *nt, const float *flows, int N, int H, int W, 
 {
     if (!flows || !net_dims_ok(nt, N, H, W) || ((uintptr_t)flows & 7) != 0) return VOLDOR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int rc = forward_launch(nt, flows, N, H, W, s);
+    int rc = forward_fused_launch(nt, flows, N, H, W, s);
     const int64_t npx = (int64_t)N * H * W;
     if (rc == 0 && (depth || rig)) {
         hipLaunchKernelGGL(k_net_outputs, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, nt->z, depth, rig, N,

@@ -162,6 +162,28 @@ def test_network_gradient_parity(vo, torch):
         assert rel <= 12 * U and cos >= 0.999, (k, rel, cos)
 
 
+@pytest.mark.parametrize("N,H,W", [(2, 37, 71), (1, 5, 9), (1, 48, 96)])
+def test_fused_forward_equals_layers(vo, torch, N, H, W):
+    # the one-launch forward pass (all six layers on LDS tiles of 16 x 32
+    # output pixels with a 6-pixel halo) against the six single-layer launches,
+    # bit for bit: ragged tiles, an image smaller than one tile, whole tiles
+    T = 3
+    n, ps = _net(vo, T, N, H, W, seed=3)
+    flows, _, _ = _window_batch(T, N, H, W, 3)
+    ft = torch.from_numpy(flows).cuda()
+    z = torch.zeros((N, H, W, 16), dtype=torch.float32, device="cuda")
+    n.forward(ft, z=z)
+    x = torch.from_numpy(onet.net_input(flows.astype(np.float64)).astype(np.float32)).to(torch.bfloat16).cuda()
+    for k in range(5):
+        y = torch.empty((N, H, W, 32), dtype=torch.bfloat16, device="cuda")
+        n.layer(k, x.contiguous(), y)
+        x = y
+    zl = torch.empty((N, H, W, 16), dtype=torch.float32, device="cuda")
+    n.layer(5, x.contiguous(), zl)
+    torch.cuda.synchronize()
+    assert torch.equal(z, zl), float((z - zl).abs().max())
+
+
 def test_adam_step_and_training_descends(vo, torch):
     T, N, H, W = 2, 2, 20, 33
     n, ps = _net(vo, T, N, H, W, seed=3)
