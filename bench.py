@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
 # profiles/k_sweep_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 48.12e6, "write_bytes": 1.24e6}
-SWEEP_SOURCES_SHA = "aa7764e3a1827e9f"
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 47.83e6, "write_bytes": 1.25e6}
+SWEEP_SOURCES_SHA = "517abd8cdb26fb77"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz = 39.3 T/s; the all-pixel candidate scoring (--pose-start
@@ -370,8 +370,8 @@ def run_batch(args):
 # HBM traffic of the sweeps of one batch step (rocprofv3 FETCH_SIZE + WRITE_SIZE
 # of k_sweep, summed over the step's launches, per launch, scaled by the copy
 # calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
-BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (35.58 + 1.38) * 1e6   # profiles/k_sweep_hbm_traffic.md
-BATCH_SWEEP_SOURCES_SHA = "aa7764e3a1827e9f"
+BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (35.64 + 1.37) * 1e6   # profiles/k_sweep_hbm_traffic.md
+BATCH_SWEEP_SOURCES_SHA = "517abd8cdb26fb77"
 
 
 def _batch_sweep_traffic_valid():
@@ -783,7 +783,7 @@ def run_learned(args):
         "training": {"loss_per_epoch": losses, "steps": steps, "seconds": train_s, "label_ms": label_ms,
                      "generator": ("device (synthflow.torchgen), chunks of %d windows" % args.chunk) if gen_gpu
                      else "host (synthflow.make_batch)", "generate_ms": gen_ms[0]},
-        "roofline": {"bound": "mfma", "kernel": "k_conv (six layers, forward)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "k_net_input + k_net_fused (six layers, forward)", "achieved": achieved,
                      "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
                      "flops_per_pass": conv_flops, "pass_ms": fwd_ms},
     }
