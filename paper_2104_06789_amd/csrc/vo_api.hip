@@ -92,7 +92,8 @@ EmisParams emis(const double *K, const voldor_params *p)
     e.model = p->residual_model;
     e.ifx = (float)(1.0 / K[0]);
     e.ify = (float)(1.0 / K[1]);
-    e.pad2 = e.pad3 = 0.0f;
+    e.l2a1 = (float)log2(p->a1);
+    e.a2l = (float)(p->a2 * 1.4426950408889634);
     return e;
 }
 

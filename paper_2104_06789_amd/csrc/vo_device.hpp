@@ -57,7 +57,8 @@ struct EmisParams {
     float log_a1, a2, b1, b2;
     float lam2, beta_min, x_floor;
     int model;                    // residual model: 0 Fisk (Eq. 5), 1 Gaussian flow error
-    float ifx, ify, pad2, pad3;   // 1/fx, 1/fy
+    float ifx, ify;               // 1/fx, 1/fy
+    float l2a1, a2l;              // log2 a1, a2 / ln 2: log2 alpha = a2l |v| + l2a1
 };
 
 // hardware reciprocal (v_rcp_f32, about 1 ulp) instead of an IEEE division
@@ -213,51 +214,61 @@ struct Emis {
 constexpr float kLn2F = 0.69314718055994531f;
 constexpr float kLogLn2F = -0.36651292058166432f;   // log(ln 2)
 
+// The sweep and the rigidness pass take the log-odds in base 2,
+// D = d / ln 2 = log2(mu / rho): the hardware units are log2 and exp2, so
+// neither scales between the two bases inside the emission (with alpha in
+// base 2, la = log2 alpha = a2 |v| / ln 2 + log2 a1).
+// softplus2(z) = log2(1 + 2^z), the base-2 form of softplus.
+__device__ __forceinline__ float softplus2(float z)
+{
+    return add_nc(fmaxf(z, 0.0f), __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-fabsf(z))));
+}
+
 template <int MODEL = 0>
-__device__ __forceinline__ float log_mu_over_rho(float rx, float ry, float vx, float vy,
-                                                  const EmisParams &e)
+__device__ __forceinline__ float log2_odds(float rx, float ry, float vx, float vy, const EmisParams &e)
 {
     // squared residual clamped to [x_floor, 1e30] so every exponent below stays finite
     const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
     const float vn2 = fmaf(vx, vx, vy * vy);
     const float vn = __builtin_amdgcn_sqrtf(vn2);
-    const float la = fmaf(e.a2, vn, e.log_a1);
+    const float la = fmaf(e.a2l, vn, e.l2a1);
     if constexpr (MODEL == 1) {
+        // d = (x - m) ln 2 / alpha, so D = (x - m) / alpha
         const float m = fmaxf(e.lam2 * vn2, e.x_floor);
-        return (x2 - m) * (kLn2F * fast_exp(-la));
+        return (x2 - m) * __builtin_amdgcn_exp2f(-la);
     } else {
         const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-        const float lx = fast_log(x2);
-        const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+        const float lx = __builtin_amdgcn_logf(x2);
+        const float lm = __builtin_amdgcn_logf(fmaxf(e.lam2 * vn2, e.x_floor));
         const float z1 = beta * sub_nc(lx, la), z2 = beta * sub_nc(lm, la);
-        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus(z2) - softplus(z1)));
+        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus2(z2) - softplus2(z1)));
     }
 }
 
-// The same d = log(mu / rho), and log mu itself (Eq. 8: the model's density
-// at squared EPE lambda^2 |v|^2, normalisation included), for the
+// The same D, and log mu itself (natural log; Eq. 8: the model's density at
+// squared EPE lambda^2 |v|^2, normalisation included), for the
 // maximum-likelihood depth criterion (Eq. 9), whose per-frame term is
 // q log rho + (1 - q) log mu = log mu - q d.
 template <int MODEL = 0>
-__device__ __forceinline__ float log_mu_and_d(float rx, float ry, float vx, float vy, const EmisParams &e,
+__device__ __forceinline__ float log2_odds_mu(float rx, float ry, float vx, float vy, const EmisParams &e,
                                               float &lmu)
 {
     const float x2 = fminf(fmaxf(fmaf(rx, rx, ry * ry), e.x_floor), 1e30f);
     const float vn2 = fmaf(vx, vx, vy * vy);
     const float vn = __builtin_amdgcn_sqrtf(vn2);
-    const float la = fmaf(e.a2, vn, e.log_a1);
+    const float la = fmaf(e.a2l, vn, e.l2a1);
     if constexpr (MODEL == 1) {
         const float m = fmaxf(e.lam2 * vn2, e.x_floor);
-        const float is = kLn2F * fast_exp(-la);   // 1 / s
-        lmu = fmaf(-m, is, kLogLn2F - la);         // -m / s - log s
-        return (x2 - m) * is;
+        const float ia = __builtin_amdgcn_exp2f(-la);   // 1 / alpha = (1 / s) / ln 2
+        lmu = fmaf(kLn2F, fmaf(-m, ia, -la), kLogLn2F);   // -m / s - log s
+        return (x2 - m) * ia;
     } else {
         const float beta = fmaxf(fmaf(e.b1, vn, e.b2), e.beta_min);
-        const float lx = fast_log(x2);
-        const float lm = fast_log(fmaxf(e.lam2 * vn2, e.x_floor));
+        const float lx = __builtin_amdgcn_logf(x2);
+        const float lm = __builtin_amdgcn_logf(fmaxf(e.lam2 * vn2, e.x_floor));
         const float z1 = beta * sub_nc(lx, la), z2 = beta * sub_nc(lm, la);
-        lmu = fmaf(beta - 1.0f, sub_nc(lm, la), sub_nc(fast_log(beta), la)) - 2.0f * softplus(z2);
-        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus(z2) - softplus(z1)));
+        lmu = kLn2F * (fmaf(beta - 1.0f, sub_nc(lm, la), sub_nc(__builtin_amdgcn_logf(beta), la)) - 2.0f * softplus2(z2));
+        return fmaf(beta - 1.0f, sub_nc(lm, lx), -2.0f * (softplus2(z2) - softplus2(z1)));
     }
 }
 
@@ -282,19 +293,34 @@ __device__ __forceinline__ Emis emis_from_d(float d)
     return o;
 }
 
-// log(-ell) = log(log(1 + e^d)), the log of the negated per-frame MIE term,
-// for the scores kept in log form (below).  For d < -8, log(1 + e^d) =
+// The same from the base-2 log-odds D: e = 2^-|D| = e^-|d|, and
+// log(1 + e) = ln 2 log2 u - ((u - 1) - e) / u with u = 1 + e rounded, so
+// ell = ((u - 1) - e) / u - ln 2 (max(D, 0) + log2 u).
+__device__ __forceinline__ Emis emis_from_D(float D)
+{
+    const float e = __builtin_amdgcn_exp2f(-fabsf(D));
+    const float u = 1.0f + e;
+    const float inv = frcp(u);
+    Emis o;
+    o.ell = fmaf((u - 1.0f) - e, inv, -kLn2F * (fmaxf(D, 0.0f) + __builtin_amdgcn_logf(u)));
+    o.r = posterior_from(D, e, inv);
+    return o;
+}
+
+// log(-ell) = log(log(1 + e^d)) from D, the log of the negated per-frame MIE
+// term, for the scores kept in log form (below).  For d < -8, log(1 + e^d) =
 // e^d (1 - e^d / 2 + ...), so log(-ell) = d - e^d / 2 to within 2e-8; above,
 // the log of -ell itself (then at least 3e-4, so relative accuracy holds).
 // Also returns r = 1 / (1 + e^d).
-__device__ __forceinline__ float neg_ell_log(float d, float &r)
+constexpr float kLog2Minus8F = -11.541560327111707f;   // -8 / ln 2
+__device__ __forceinline__ float neg_ell_log2(float D, float &r)
 {
-    const float e = fast_exp(-fabsf(d));
+    const float e = __builtin_amdgcn_exp2f(-fabsf(D));
     const float u = 1.0f + e;
     const float inv = frcp(u);
-    r = posterior_from(d, e, inv);
-    const float nl = fmaxf(d, 0.0f) + log1p_rel(e, u, inv);
-    return d < -8.0f ? fmaf(-0.5f, e, d) : fast_log(nl);
+    r = posterior_from(D, e, inv);
+    const float nl = fmaf(-((u - 1.0f) - e), inv, kLn2F * (fmaxf(D, 0.0f) + __builtin_amdgcn_logf(u)));
+    return D < kLog2Minus8F ? fmaf(-0.5f, e, D * kLn2F) : fast_log(nl);
 }
 
 // A maximum-inlier score S = sum_t q_t ell_t (Eq. 10) kept as

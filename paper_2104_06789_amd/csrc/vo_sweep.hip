@@ -131,19 +131,19 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             if constexpr (LOGS) {
                 float lam = kLogLn2F;
                 if (obs) {
-                    const float dd = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
+                    const float dd = log2_odds<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
                     float rr;
-                    lam = neg_ell_log(dd, rr);
+                    lam = neg_ell_log2(dd, rr);
                 }
                 logscore_add(ls, qv[u], lam);
             } else if constexpr (CRIT == 0) {
-                const float dd = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
-                const float ell = emis_from_d(dd).ell;
+                const float dd = log2_odds<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e);
+                const float ell = emis_from_D(dd).ell;
                 s = fmaf(qv[u], obs ? ell : kLogHalf, s);
             } else {
                 float lmu;
-                const float dd = log_mu_and_d<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e, lmu);
-                if (obs) s += fmaf(-qv[u], dd, lmu);
+                const float dd = log2_odds_mu<MODEL>(sub_nc(sub_nc(dx[u], lx[u]), vu), sub_nc(sub_nc(dy[u], ly[u]), vv), vu, vv, e, lmu);
+                if (obs) s += fmaf(-qv[u], dd * kLn2F, lmu);
             }
         }
         pdx = dx[FC - 1];
@@ -154,8 +154,8 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
     return s;
 }
 
-// log(mu/rho) for a batch of B independent (pixel, frame, depth) items; the
-// flow gathers of the whole batch are issued before any of them is used.
+// D = log2(mu/rho) for a batch of B independent (pixel, frame, depth) items;
+// the flow gathers of the whole batch are issued before any of them is used.
 // ok[b] false: missing observation (or inactive item).  MU: log mu as well.
 template <int B, int MODEL, bool MU = false>
 __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *__restrict__ flows, int H,
@@ -196,10 +196,10 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         ok[b] = ok[b] && isfinite(vu + vv);   // every tap finite (see taps_finite)
         if constexpr (MU) {
             float lm = 0.0f;
-            d[b] = ok[b] ? log_mu_and_d<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e, lm) : 0.0f;
+            d[b] = ok[b] ? log2_odds_mu<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e, lm) : 0.0f;
             lmu[b] = ok[b] ? lm : 0.0f;
         } else {
-            d[b] = ok[b] ? log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e) : 0.0f;
+            d[b] = ok[b] ? log2_odds<MODEL>(sub_nc(sub_nc(dx1[b], dx0[b]), vu), sub_nc(sub_nc(dy1[b], dy0[b]), vv), vu, vv, e) : 0.0f;
         }
     }
 }
@@ -256,7 +256,7 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
         const float vu = bilerp(A.x, Bv.x, Cv.x, Dv.x, ax[i], ay[i]);
         const float vv = bilerp(A.y, Bv.y, Cv.y, Dv.y, ax[i], ay[i]);
         const bool ok = v[i] & isfinite(vu + vv);   // every tap finite (see taps_finite)
-        const float dv = log_mu_over_rho<MODEL>(sub_nc(sub_nc(dx1[i], dx0[i]), vu), sub_nc(sub_nc(dy1[i], dy0[i]), vv), vu, vv, e);
+        const float dv = log2_odds<MODEL>(sub_nc(sub_nc(dx1[i], dx0[i]), vu), sub_nc(sub_nc(dy1[i], dy0[i]), vv), vu, vv, e);
         const float d = ok ? dv : 0.0f;
         if (i & 1) {
             ds[i >> 1] = d;
@@ -545,12 +545,12 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 float ell, r, els;
                 if constexpr (LOGS) {
                     float rp, rs;
-                    const float lp = neg_ell_log(dp[b], rp), lz = neg_ell_log(ds[b], rs);
+                    const float lp = neg_ell_log2(dp[b], rp), lz = neg_ell_log2(ds[b], rs);
                     ell = okp[b] ? lp : miss;
                     r = okp[b] ? rp : 0.5f;
                     els = oks[b] ? lz : miss;
                 } else {
-                    const Emis mp = emis_from_d(dp[b]), mz = emis_from_d(ds[b]);
+                    const Emis mp = emis_from_D(dp[b]), mz = emis_from_D(ds[b]);
                     ell = okp[b] ? mp.ell : miss;
                     r = okp[b] ? mp.r : 0.5f;
                     els = oks[b] ? mz.ell : miss;
@@ -588,9 +588,9 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
                 const int i = i0 + b * NT;
                 if (!act[b]) continue;
                 // missing: d = 0 (r = 1/2 in the E-step) and log mu = 0 (term 0)
-                lq[i] = dd[b];
+                lq[i] = dd[b] * kLn2F;   // d = log(mu / rho)
                 lmq[i] = lm[b];
-                fq[i] = ok[b] ? emis_from_d(dd[b]).r : 0.5f;
+                fq[i] = ok[b] ? emis_from_D(dd[b]).r : 0.5f;
             }
         }
     }
@@ -754,7 +754,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 #pragma unroll
             for (int b = 0; b < kMleItems; ++b) {
                 const int i = i0 + b * NT;
-                if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b], lm[b]) : 0.0f;
+                if (act[b]) lq[i] = ok[b] ? fmaf(-fq[i], dd[b] * kLn2F, lm[b]) : 0.0f;
             }
         }
         __syncthreads();
@@ -945,9 +945,8 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                 const float vv = bilerp(A.y, B.y, Cc.y, D.y, ax[u], ay[u]);
                 if (val[u] && isfinite(vu + vv)) {   // every tap finite (see taps_finite)
                     const float rx = sub_nc(sub_nc(dx1[u], bx[u]), vu), ry = sub_nc(sub_nc(dy1[u], by[u]), vv);
-                    const float d = a.e.model ? log_mu_over_rho<1>(rx, ry, vu, vv, a.e)
-                                              : log_mu_over_rho<0>(rx, ry, vu, vv, a.e);
-                    const Emis m = emis_from_d(d);
+                    const float d2 = a.e.model ? log2_odds<1>(rx, ry, vu, vv, a.e) : log2_odds<0>(rx, ry, vu, vv, a.e);
+                    const Emis m = emis_from_D(d2);
                     r = m.r;
                     ell = m.ell;
                     if (a.logrho || a.logmu || a.ll_part) {
@@ -962,7 +961,7 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
                             const float lb = fast_log(beta) - la;
                             lr = lb + (beta - 1.0f) * s1 - 2.0f * softplus(beta * s1);
                         }
-                        lm = lr + d;
+                        lm = fmaf(d2, kLn2F, lr);
                         const double w = r;
                         const double term = w * (double)lr + (1.0 - w) * (double)lm;
                         acc += term;
