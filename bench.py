@@ -273,7 +273,7 @@ def run_batch(args):
     Tm, Hm, Wm = (max(x[k] for x in shapes) for k in range(3))
     status = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
-    solver = vo.Batch(args.lanes, Tm, Hm, Wm, max(groups), graph=not args.no_graph)
+    solver = vo.Batch(args.lanes, Tm, Hm, Wm, max(groups), graph=not args.no_graph, lockstep=args.lockstep)
     with torch.cuda.stream(stream):
         solver.autotune(items, p, stream=stream)
     solver.set_timing(True)
@@ -332,6 +332,7 @@ def run_batch(args):
                                f"seed {args.seed}",
                    "windows": len(wins), "shapes": mix, "frames": sum(x[0] for x in shapes),
                    "lanes": args.lanes, "graph": not args.no_graph,
+                   "mode": "lockstep" if args.lockstep else "windows in stream order per lane",
                    "parallelism": "single GPU, one batch per step over concurrent streams"},
         "windows_per_s": len(wins) * 1e3 / ms,
         "pose_error_vs_gt": {"rot_rad": float(np.mean([e[0] for e in errs])),
@@ -840,6 +841,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
+    ap.add_argument("--lockstep", action="store_true",
+                    help="the windows of each lane advance together, one launch per kernel over all of them")
     ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-window indoor and driving figures of the batch workload")

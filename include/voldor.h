@@ -279,7 +279,18 @@ typedef struct {
  * same call (descriptors, count, parameters, status array, stream) comes again.
  * Returns VOLDOR_EINVAL / VOLDOR_ENOMEM / VOLDOR_EDEVICE like voldor_create. */
 typedef struct voldor_batch voldor_batch;
-enum { VOLDOR_BATCH_GRAPH = 1 };
+/* VOLDOR_BATCH_LOCKSTEP: the windows of each lane advance together, with one
+ * workspace per window (allocated on the first call with that many windows):
+ * each of a pose step's three kernels is one launch over the (window, frame)
+ * items of the lane's windows, each sweep one launch over their (window,
+ * chain) items per threads-per-chain class, each rigidness pass one launch
+ * over their pixels: the work-list form of a batch of Table 1 runs.  The launch
+ * arguments are built on the host and uploaded once per distinct call; a call
+ * with new descriptors waits for the stream and the lanes first.  Results are
+ * still those of voldor_window on each window, bit for bit.  Needs the KDE
+ * pose start (pose_start 0) and no proposed initial state; VOLDOR_EINVAL
+ * otherwise. */
+enum { VOLDOR_BATCH_GRAPH = 1, VOLDOR_BATCH_LOCKSTEP = 2 };
 int voldor_batch_create(voldor_batch **out, int lanes, int T_max, int H_max, int W_max, int S_max,
                         int flags);
 void voldor_batch_destroy(voldor_batch *b);

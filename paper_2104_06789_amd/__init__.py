@@ -59,6 +59,7 @@ class WindowDesc(C.Structure):
 
 
 BATCH_GRAPH = 1
+BATCH_LOCKSTEP = 2
 
 _lib = None
 
@@ -556,12 +557,15 @@ def philox(ctr, key0, key1, stream=None):
 
 class Batch:
     """Batch solver over `lanes` concurrent streams (voldor_batch_* in the C ABI);
-    each lane owns a workspace for windows up to T_max x H_max x W_max."""
+    each lane owns a workspace for windows up to T_max x H_max x W_max.
+    lockstep: the windows of a lane advance together, one launch per kernel
+    over all of them (VOLDOR_BATCH_LOCKSTEP)."""
 
-    def __init__(self, lanes, T_max, H_max, W_max, S_max=4096, graph=False):
+    def __init__(self, lanes, T_max, H_max, W_max, S_max=4096, graph=False, lockstep=False):
         ctx = C.c_void_p()
-        _check(lib().voldor_batch_create(C.byref(ctx), lanes, T_max, H_max, W_max, S_max,
-                                         BATCH_GRAPH if graph else 0), "voldor_batch_create")
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_LOCKSTEP if lockstep else 0)
+        _check(lib().voldor_batch_create(C.byref(ctx), lanes, T_max, H_max, W_max, S_max, flags),
+               "voldor_batch_create")
         self._b = ctx
         self._keep = None
 

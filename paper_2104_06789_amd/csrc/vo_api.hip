@@ -433,6 +433,146 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
     return rc;
 }
 
+// Lockstep lane: the window_enqueue sequence of several windows at once.  The
+// bootstraps run one after another; then per iteration one pose step per
+// frame index over the windows that have that frame, the sweeps over all
+// chains of all windows, the rigidness pass with the gauge; finally the
+// log-likelihood.  Each window sees the launches, arguments and order of its
+// own window_enqueue, so its results are the same bit for bit.
+void lockstep_plan(voldor_ctx *const *wc, const voldor_window_desc *w, const std::vector<int> &idx,
+                   const voldor_params *p, Plan &plan, std::vector<WinRef> &refs, std::vector<LockStep> &steps)
+{
+    const int n = (int)idx.size();
+    refs.resize(n);
+    int Tmax = 0;
+    for (int k = 0; k < n; ++k) {
+        const voldor_window_desc &d = w[idx[k]];
+        voldor_params pw = *p;
+        if (d.n_pose_groups > 0) pw.n_pose_groups = d.n_pose_groups;
+        WinRef &r = refs[k];
+        r.c = wc[k];
+        r.X = (const float2 *)d.flows;
+        r.d = dims(d.T, d.H, d.W, d.K);
+        r.e = emis(d.K, &pw);
+        r.pp = pose_params(&pw);
+        r.depth = d.depth;
+        r.rig = d.rigidness;
+        r.poses = d.poses;
+        Tmax = d.T > Tmax ? d.T : Tmax;
+    }
+    auto stamp = [&](int phase, int launches) {
+        LockStep st = {};
+        st.kind = kStepStamp;
+        st.phase = phase;
+        st.launches = launches;
+        steps.push_back(st);
+    };
+    auto multi = [&](const std::vector<MultiLaunch> &ms) {
+        for (const MultiLaunch &m : ms) {
+            LockStep st = {};
+            st.kind = kStepMulti;
+            st.m = m;
+            steps.push_back(st);
+        }
+    };
+    std::vector<int> all(n);
+    for (int k = 0; k < n; ++k) all[k] = k;
+    for (int k = 0; k < n; ++k) {
+        LockStep st = {};
+        st.kind = kStepBoot;
+        st.win = k;
+        steps.push_back(st);
+    }
+    stamp(kPhaseBoot, 0);
+    std::vector<MultiLaunch> ms;
+    for (int it = 0; it < p->n_iters; ++it) {
+        for (int t = 1; t <= Tmax; ++t) {
+            std::vector<int> act;
+            for (int k = 0; k < n; ++k)
+                if (refs[k].d.T >= t) act.push_back(k);
+            ms.clear();
+            plan_pose_step(plan, ms, refs, act, t, it);
+            multi(ms);
+        }
+        stamp(kPhasePose, 0);
+        for (int sw = 0; sw < p->sweeps_per_iter; ++sw) {
+            const int64_t gs = (int64_t)it * p->sweeps_per_iter + sw;
+            ms.clear();
+            plan_sweep(plan, ms, refs, all, (float)p->gamma, p->seed, gs, (int)(gs % 4), p->criterion);
+            multi(ms);
+        }
+        stamp(kPhaseSweep, p->sweeps_per_iter * n);
+        ms.clear();
+        plan_rigidness(plan, ms, refs, all, true, std::vector<double *>());
+        plan_gauge_poses(plan, ms, refs, all);
+        multi(ms);
+        stamp(kPhaseRig, 0);
+    }
+    std::vector<int> with_ll;
+    std::vector<double *> ll;
+    for (int k = 0; k < n; ++k)
+        if (w[idx[k]].loglik) {
+            with_ll.push_back(k);
+            ll.push_back(w[idx[k]].loglik);
+        }
+    if (!with_ll.empty()) {
+        ms.clear();
+        plan_rigidness(plan, ms, refs, with_ll, false, ll);
+        multi(ms);
+        stamp(kPhaseLL, 0);
+    }
+    for (int k = 0; k < n; ++k) {
+        LockStep st = {};
+        st.kind = kStepStatus;
+        st.win = k;
+        steps.push_back(st);
+    }
+}
+
+int lockstep_run(voldor_ctx *lane, const std::vector<WinRef> &refs, const std::vector<LockStep> &steps,
+                 const voldor_window_desc *w, const std::vector<int> &idx, const voldor_params *p,
+                 const unsigned char *plan_dev, int32_t *status_out, hipStream_t s)
+{
+    lane->last_stream = s;
+    lane->tw_cur = (int)(lane->tw_count % kTimingRing);
+    lane->n_ev = 0;
+    mark(lane, s, kPhaseNone);
+    int rc = 0;
+    for (const LockStep &st : steps) {
+        if (rc) break;
+        switch (st.kind) {
+        case kStepBoot: {
+            const WinRef &r = refs[st.win];
+            r.c->last_stream = s;
+            rc = launch_bootstrap(r.c, r.X, r.d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
+                                  p->depth_hi, r.poses, r.depth, s, nullptr);
+            break;
+        }
+        case kStepMulti:
+            rc = (st.m.kind == kMultiSweep || st.m.kind == kMultiRig || st.m.kind == kMultiLL)
+                     ? launch_sweep_multi(st.m, plan_dev, s)
+                     : launch_pose_multi(st.m, plan_dev, s);
+            break;
+        case kStepStamp:
+            mark(lane, s, st.phase, st.launches);
+            break;
+        case kStepStatus:
+            hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, refs[st.win].c->status,
+                               status_out + idx[st.win]);
+            rc = hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+            break;
+        default:
+            rc = VOLDOR_EINVAL;
+        }
+    }
+    (void)w;
+    if (lane->timing) {
+        lane->ev_n[lane->tw_cur] = lane->n_ev;
+        ++lane->tw_count;
+    }
+    return rc;
+}
+
 }  // namespace vo
 
 extern "C" {

@@ -39,7 +39,18 @@ double window_cost(const voldor_window_desc &w)
 struct voldor_batch {
     int lanes;
     int flags;
+    int T_max, H_max, W_max, S_max;
     voldor_ctx *ctx[kMaxLanes];
+    // lockstep mode: a context per window (windows of a lane are in flight
+    // together), the plan of the last call (argument arrays on the device,
+    // every lane's windows and steps) and the bytes of that call
+    std::vector<voldor_ctx *> wctx;
+    unsigned char *plan_dev;
+    size_t plan_cap;
+    std::vector<std::vector<int>> lane_idx;
+    std::vector<std::vector<WinRef>> lane_refs;
+    std::vector<std::vector<LockStep>> lane_steps;
+    std::vector<unsigned char> plan_key;
     hipStream_t st[kMaxLanes];
     hipEvent_t fork;
     hipEvent_t join[kMaxLanes];
@@ -58,6 +69,18 @@ void drop_graph(voldor_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->key.clear();
+    b->plan_key.clear();   // a plan holds the tuned launch settings of its call
+}
+
+// sweep settings of the lanes' first context onto a window context
+void copy_tuning(const voldor_ctx *from, voldor_ctx *to)
+{
+    to->sweep_nt[0] = from->sweep_nt[0];
+    to->sweep_nt[1] = from->sweep_nt[1];
+    to->sweep_la[0] = from->sweep_la[0];
+    to->sweep_la[1] = from->sweep_la[1];
+    to->n_sweep_tab = from->n_sweep_tab;
+    for (int k = 0; k < from->n_sweep_tab; ++k) to->sweep_tab[k] = from->sweep_tab[k];
 }
 
 void assign_lanes(const voldor_window_desc *w, int n, int lanes, std::vector<int> &order,
@@ -107,6 +130,71 @@ int batch_enqueue(voldor_batch *b, const voldor_window_desc *w, int n, const vol
     return rc;
 }
 
+// Lockstep mode: the lanes as above, the windows of each lane advancing
+// together (vo_api.hip, lockstep_plan).  The plan of a call is built on the
+// host and uploaded before anything is enqueued; it is kept, with the call's
+// bytes, for the next call with the same bytes (a captured graph reads it).
+int lockstep_prepare(voldor_batch *b, const voldor_window_desc *w, int n, const voldor_params *p,
+                     const std::vector<unsigned char> &key, hipStream_t s)
+{
+    if (!b->plan_key.empty() && key == b->plan_key) return VOLDOR_OK;
+    // nothing enqueued before may still read the plan buffer or use the contexts
+    if (hipStreamSynchronize(s) != hipSuccess) return VOLDOR_EDEVICE;
+    for (int l = 0; l < b->lanes; ++l)
+        if (hipStreamSynchronize(b->st[l]) != hipSuccess) return VOLDOR_EDEVICE;
+    drop_graph(b);   // a captured graph reads the plan buffer rewritten below
+    while ((int)b->wctx.size() < n) {
+        voldor_ctx *c = nullptr;
+        const int rc = voldor_create(&c, b->T_max, b->H_max, b->W_max, b->S_max);
+        if (rc) return rc;
+        b->wctx.push_back(c);
+    }
+    for (int i = 0; i < n; ++i) copy_tuning(b->ctx[0], b->wctx[i]);
+    const int used = std::min(b->lanes, n);
+    std::vector<int> order, lane_of;
+    assign_lanes(w, n, used, order, lane_of);
+    b->lane_idx.assign(used, std::vector<int>());
+    for (int k = 0; k < n; ++k) b->lane_idx[lane_of[order[k]]].push_back(order[k]);
+    b->lane_refs.assign(used, std::vector<WinRef>());
+    b->lane_steps.assign(used, std::vector<LockStep>());
+    Plan plan;
+    for (int l = 0; l < used; ++l) {
+        std::vector<voldor_ctx *> wc;
+        for (int i : b->lane_idx[l]) wc.push_back(b->wctx[i]);
+        lockstep_plan(wc.data(), w, b->lane_idx[l], p, plan, b->lane_refs[l], b->lane_steps[l]);
+    }
+    if (plan.host.size() > b->plan_cap) {
+        if (b->plan_dev) (void)hipFree(b->plan_dev);
+        b->plan_dev = nullptr;
+        b->plan_cap = 0;
+        if (hipMalloc((void **)&b->plan_dev, plan.host.size()) != hipSuccess) return VOLDOR_ENOMEM;
+        b->plan_cap = plan.host.size();
+    }
+    if (!plan.host.empty() &&
+        hipMemcpy(b->plan_dev, plan.host.data(), plan.host.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    b->plan_key = key;
+    return VOLDOR_OK;
+}
+
+int lockstep_enqueue(voldor_batch *b, const voldor_window_desc *w, const voldor_params *p,
+                     int32_t *status_out, hipStream_t s)
+{
+    const int used = (int)b->lane_idx.size();
+    if (hipEventRecord(b->fork, s) != hipSuccess) return VOLDOR_EDEVICE;
+    for (int l = 0; l < used; ++l)
+        if (hipStreamWaitEvent(b->st[l], b->fork, 0) != hipSuccess) return VOLDOR_EDEVICE;
+    int rc = VOLDOR_OK;
+    for (int l = 0; l < used && rc == VOLDOR_OK; ++l)
+        rc = lockstep_run(b->ctx[l], b->lane_refs[l], b->lane_steps[l], w, b->lane_idx[l], p, b->plan_dev,
+                          status_out, b->st[l]);
+    for (int l = 0; l < used; ++l) {
+        if (hipEventRecord(b->join[l], b->st[l]) != hipSuccess) return VOLDOR_EDEVICE;
+        if (hipStreamWaitEvent(s, b->join[l], 0) != hipSuccess) return VOLDOR_EDEVICE;
+    }
+    return rc;
+}
+
 void call_key(const voldor_window_desc *w, int n, const voldor_params *p, const int32_t *status_out,
               hipStream_t s, std::vector<unsigned char> &key)
 {
@@ -131,11 +219,16 @@ int voldor_batch_create(voldor_batch **out, int lanes, int T_max, int H_max, int
 {
     if (!out) return VOLDOR_EINVAL;
     *out = nullptr;
-    if (lanes < 1 || lanes > kMaxLanes || (flags & ~VOLDOR_BATCH_GRAPH) != 0) return VOLDOR_EINVAL;
+    if (lanes < 1 || lanes > kMaxLanes || (flags & ~(VOLDOR_BATCH_GRAPH | VOLDOR_BATCH_LOCKSTEP)) != 0)
+        return VOLDOR_EINVAL;
     voldor_batch *b = new (std::nothrow) voldor_batch();
     if (!b) return VOLDOR_ENOMEM;
     b->lanes = lanes;
     b->flags = flags;
+    b->T_max = T_max;
+    b->H_max = H_max;
+    b->W_max = W_max;
+    b->S_max = S_max;
     int rc = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
     for (int l = 0; l < lanes && rc == VOLDOR_OK; ++l) {
         rc = voldor_create(&b->ctx[l], T_max, H_max, W_max, S_max);
@@ -262,6 +355,8 @@ void voldor_batch_destroy(voldor_batch *b)
         if (b->st[l]) (void)hipStreamDestroy(b->st[l]);
         voldor_destroy(b->ctx[l]);
     }
+    for (voldor_ctx *c : b->wctx) voldor_destroy(c);
+    if (b->plan_dev) (void)hipFree(b->plan_dev);
     if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
 }
@@ -280,14 +375,28 @@ int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, 
             return VOLDOR_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
-    if (!(b->flags & VOLDOR_BATCH_GRAPH) || s == nullptr) return batch_enqueue(b, wins, n, p, status_out, s);
-
+    const bool lock = (b->flags & VOLDOR_BATCH_LOCKSTEP) != 0;
+    if (lock) {
+        // lockstep windows start from their own bootstrap with the KDE pose start
+        if (p->pose_start != 0) return VOLDOR_EINVAL;
+        for (int i = 0; i < n; ++i)
+            if (wins[i].init_depth || wins[i].init_rig) return VOLDOR_EINVAL;
+    }
+    const bool graph = (b->flags & VOLDOR_BATCH_GRAPH) && s != nullptr;
     std::vector<unsigned char> key;
-    call_key(wins, n, p, status_out, s, key);
-    if (b->exec && key == b->key) return hipGraphLaunch(b->exec, s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
-    drop_graph(b);
+    if (lock || graph) call_key(wins, n, p, status_out, s, key);
+    if (graph && b->exec && key == b->key)
+        return hipGraphLaunch(b->exec, s) == hipSuccess ? VOLDOR_OK : VOLDOR_EDEVICE;
+    if (graph) drop_graph(b);
+    if (lock) {
+        const int rc = lockstep_prepare(b, wins, n, p, key, s);
+        if (rc) return rc;
+    }
+    if (!graph)
+        return lock ? lockstep_enqueue(b, wins, p, status_out, s) : batch_enqueue(b, wins, n, p, status_out, s);
+
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return VOLDOR_EDEVICE;
-    const int rc = batch_enqueue(b, wins, n, p, status_out, s);
+    const int rc = lock ? lockstep_enqueue(b, wins, p, status_out, s) : batch_enqueue(b, wins, n, p, status_out, s);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (rc != VOLDOR_OK || ec != hipSuccess || !g) {

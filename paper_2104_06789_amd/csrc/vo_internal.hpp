@@ -4,6 +4,9 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <vector>
 
 #include "voldor.h"
 #include "vo_device.hpp"
@@ -162,5 +165,79 @@ int launch_cumulative(voldor_ctx *c, const double *rel_poses, int T, hipStream_t
 int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
                      uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
                      float *theta, hipStream_t s, const double *T1_seed = nullptr);
+
+// ---- lockstep batches: the windows of one batch lane advance together, and
+// each pose-step kernel, sweep and rigidness pass is one launch over the
+// (window, frame) or (window, chain) items of all of them.  A plan holds the
+// argument arrays of those launches, built on the host once per distinct
+// batch call and uploaded to device memory; the launches read their window's
+// arguments from it.
+struct WinRef {
+    voldor_ctx *c;          // the window's own workspace
+    const float2 *X;
+    WinDims d;
+    EmisParams e;
+    PoseParams pp;
+    float *depth, *rig;
+    double *poses;
+};
+
+struct MultiLaunch {
+    int kind;          // kernel (kMulti*)
+    int variant;       // template variant of a sweep: ((nt / 256) * 2 + criterion) * 2 + model
+    size_t off, off2;  // byte offsets of its argument arrays in the plan
+    int nwin;          // windows (grid y; a sweep's window count)
+    int gx;            // grid x
+    size_t lds;        // dynamic LDS bytes
+};
+enum : int { kMultiPoseGroups = 1, kMultiPoseSeed, kMultiPoseMs, kMultiGauge, kMultiSweep, kMultiRig, kMultiLL };
+
+struct Plan {
+    std::vector<unsigned char> host;
+    // append n records, 256-byte aligned; returns their byte offset
+    template <typename A>
+    size_t put(const A *a, size_t n)
+    {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + sizeof(A) * n);
+        memcpy(host.data() + off, a, sizeof(A) * n);
+        return off;
+    }
+};
+
+// the pose step of frame t, iteration it, for windows w[idx[k]] (every one has
+// T >= t): its three kernels, arguments as launch_pose_step (KDE start only)
+void plan_pose_step(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, int t, int it);
+void plan_gauge_poses(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                      const std::vector<int> &idx);
+int launch_pose_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s);
+// one sweep (direction dir, global sweep index gsweep) of every chain of the
+// windows: one launch per class of threads per chain and LDS bytes
+void plan_sweep(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                const std::vector<int> &idx, float gamma, uint64_t seed, int64_t gsweep, int dir,
+                int criterion);
+// the rigidness pass of the windows: W and the scale gauge (gauge), or the
+// log-likelihood into ll[k] (device double[2] per window) through ll_part
+void plan_rigidness(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, bool gauge, const std::vector<double *> &ll);
+int launch_sweep_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s);
+
+// the steps of one lockstep lane, in stream order
+struct LockStep {
+    int kind;          // kStep*
+    MultiLaunch m;     // kStepMulti
+    int win;           // window (index into the lane's WinRef list) of a bootstrap or status copy
+    int phase, launches;   // timing stamp
+};
+enum : int { kStepMulti = 0, kStepBoot, kStepStamp, kStepStatus };
+// plans the lockstep schedule of windows w[idx[k]] (contexts wc[k]) under
+// parameters p: the lane's WinRef list, its steps, the argument arrays in plan
+void lockstep_plan(voldor_ctx *const *wc, const voldor_window_desc *w, const std::vector<int> &idx,
+                   const voldor_params *p, Plan &plan, std::vector<WinRef> &refs, std::vector<LockStep> &steps);
+// enqueues a planned lane on s (plan_dev: the uploaded plan; timing stamps on lane)
+int lockstep_run(voldor_ctx *lane, const std::vector<WinRef> &refs, const std::vector<LockStep> &steps,
+                 const voldor_window_desc *w, const std::vector<int> &idx, const voldor_params *p,
+                 const unsigned char *plan_dev, int32_t *status_out, hipStream_t s);
 
 }  // namespace vo

@@ -8,6 +8,8 @@
 //   k_pose_ms      densest candidate, Gaussian mean-shift to the mode,
 //                  T_t = exp(p*), M_t = T_t o M_{t-1};
 // plus the scale gauge |t_1| = 1.
+#include <algorithm>
+
 #include "vo_internal.hpp"
 
 
@@ -58,7 +60,7 @@ __device__ __forceinline__ bool flow_bilinear_d(const float2 *X, int H, int W, d
     return true;
 }
 
-__global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
+__device__ __forceinline__ void pose_groups_body(const GroupArgs &a)
 {
     if (a.status && *a.status != kStatusOk) return;
     const int lane = threadIdx.x, r = lane & (kGrpLanes - 1), base = lane & ~(kGrpLanes - 1);
@@ -186,6 +188,18 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a)
     }
 }
 
+__global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a) { pose_groups_body(a); }
+
+// the kernels of a pose step over several windows at once (a lockstep batch
+// lane): blockIdx.y selects a window's arguments, which are those of a single
+// window's launch, so every window gets exactly its own result
+__global__ void __launch_bounds__(64) k_pose_groups_multi(const GroupArgs *args)
+{
+    const GroupArgs a = args[blockIdx.y];
+    if ((int)blockIdx.x * kGrpPerBlk >= a.S) return;   // past this window's blocks
+    pose_groups_body(a);
+}
+
 // AoS copy [4S][8] of the samples in per-group slots 4g + r (p, weight, valid;
 // zero where a group has fewer samples): test hook of the pose step
 __global__ void k_samples_aos(const double *soa, const int *gcnt, const int *gpre, int S, int ns,
@@ -247,7 +261,7 @@ constexpr int kSeedBatch = 4;                                  // sample blocks 
 // pose; candidate k: the (k-1)-th sample in group order) over the sample
 // blocks b = w, w + 32, ... of wave w of the candidate's eight workgroups,
 // FP64 throughout.  The partials are added in a fixed order by the mean-shift.
-__global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a)
+__device__ __forceinline__ void pose_seed_body(const SeedArgs &a)
 {
     if (a.status && *a.status != kStatusOk) return;
     __shared__ double seed[8];
@@ -337,6 +351,14 @@ __global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a)
     }
 }
 
+__global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a) { pose_seed_body(a); }
+
+__global__ void __launch_bounds__(kSeedThreads) k_pose_seed_multi(const SeedArgs *args)
+{
+    const SeedArgs a = args[blockIdx.y];
+    pose_seed_body(a);
+}
+
 struct MsArgs {
     const float *sampf;     // SoA [7][ns], block-compacted: whitened p, log2 weight
     const int *bcnt;        // [nb][2]
@@ -410,7 +432,7 @@ __device__ __forceinline__ float wave_sum8_t(const float *v, int lane)
 // weight in FP32 range.  The mean itself is kept in FP64.  Every wave
 // evaluates the same totals, so the stop decision is uniform with one barrier
 // per step.
-__global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
+__device__ __forceinline__ void pose_ms_body(const MsArgs &a)
 {
     if (a.status && *a.status != kStatusOk) return;
     __shared__ unsigned short widx[kMsWaves][kMsListCap];
@@ -597,6 +619,14 @@ __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a)
         a.diag[2] = it;
         a.diag[3] = 0;
     }
+}
+
+__global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a) { pose_ms_body(a); }
+
+__global__ void __launch_bounds__(kMsThreads) k_pose_ms_multi(const MsArgs *args)
+{
+    const MsArgs a = args[blockIdx.y];
+    pose_ms_body(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,7 +864,7 @@ __global__ void __launch_bounds__(1024) k_cand_pick(const double *score, const i
 
 // scale gauge |t_1| = 1: translations, depth range, cumulative poses (the
 // depth map is rescaled by the rigidness pass that precedes this kernel)
-__global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, const int *status)
+__device__ __forceinline__ void gauge_poses_body(double *rel, double *Mcum, double *range, int T, const int *status)
 {
     if (status && *status != kStatusOk) return;
     if (threadIdx.x != 0) return;
@@ -850,6 +880,23 @@ __global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, c
     for (int t = 1; t <= T; ++t) pose_mul(rel + 12 * (t - 1), Mcum + 12 * (t - 1), Mcum + 12 * t);
 }
 
+__global__ void k_gauge_poses(double *rel, double *Mcum, double *range, int T, const int *status)
+{
+    gauge_poses_body(rel, Mcum, range, T, status);
+}
+
+struct GaugeArgs {
+    double *rel, *Mcum, *range;
+    const int *status;
+    int T;
+};
+
+__global__ void k_gauge_poses_multi(const GaugeArgs *args)
+{
+    const GaugeArgs a = args[blockIdx.y];
+    gauge_poses_body(a.rel, a.Mcum, a.range, a.T, a.status);
+}
+
 __global__ void k_cumulative(const double *rel, double *Mcum, int T)
 {
     if (threadIdx.x != 0) return;
@@ -858,14 +905,14 @@ __global__ void k_cumulative(const double *rel, double *Mcum, int T)
 }
 
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
-                     const WinDims &d, const EmisParams &e, const PoseParams &pp, int t, int it,
-                     int have_prev, double *rel_poses, hipStream_t s)
+// Arguments of the three kernels of a pose step (the start candidates of the
+// KDE start; the all-pixel start replaces candidate 0 and drops the others)
+static void pose_step_args(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
+                           const WinDims &d, const PoseParams &pp, int t, int it, int have_prev,
+                           double *rel_poses, GroupArgs &g, SeedArgs &sa, MsArgs &m)
 {
     const int nb = (pp.S + kGrpPerBlk - 1) / kGrpPerBlk;
     const int ns = kSlotsPerBlk * nb;
-    GroupArgs g;
     g.theta = theta;
     g.rig = d.use_w ? rig : nullptr;
     g.flows = flows;
@@ -885,6 +932,47 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
     g.it = it;
     g.ns = ns;
     g.seed = pp.seed;
+    sa.samples = c->samples;
+    sa.bcnt = c->bcnt;
+    sa.seed_score = c->seed_score;
+    sa.seed_part = c->seed_part;
+    sa.prev = rel_poses + 12 * (t - 1);
+    sa.start_p = nullptr;
+    sa.status = c->status;
+    sa.ns = ns;
+    sa.nb = nb;
+    sa.have_prev = have_prev;
+    sa.is2t = 1.0 / pp.s2t;
+    sa.is2r = 1.0 / pp.s2r;
+    m.sampf = c->sampf;
+    m.bcnt = c->bcnt;
+    m.bws = c->bws;
+    m.seed_score = c->seed_score;
+    m.seed_part = c->seed_part;
+    m.rel = rel_poses;
+    m.Mcum = c->Mcum;
+    m.diag = c->pose_diag + 4 * (t - 1);
+    m.status = c->status;
+    m.ns = ns;
+    m.nb = nb;
+    m.n_seeds = pp.n_seeds;
+    m.t = t;
+    m.max_iters = pp.ms_max_iters;
+    m.fallback_prev_frame = (!have_prev && t >= 2) ? 1 : 0;
+    m.wt = g.wt;
+    m.wr = g.wr;
+    m.tol = pp.ms_tol;
+}
+
+int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const float2 *flows,
+                     const WinDims &d, const EmisParams &e, const PoseParams &pp, int t, int it,
+                     int have_prev, double *rel_poses, hipStream_t s)
+{
+    GroupArgs g;
+    SeedArgs sa;
+    MsArgs m;
+    pose_step_args(c, theta, rig, flows, d, pp, t, it, have_prev, rel_poses, g, sa, m);
+    const int nb = sa.nb, ns = sa.ns;
     hipLaunchKernelGGL(k_pose_groups, dim3(nb), dim3(64), 0, s, g);
     const bool allpix = pp.pose_start == 1;
     if (allpix) {
@@ -926,42 +1014,89 @@ int launch_pose_step(voldor_ctx *c, const float *theta, const float *rig, const 
                            c->cand_n, c->cand_score, c->status);
         hipLaunchKernelGGL(k_cand_pick, dim3(1), dim3(1024), 0, s, c->cand_score, c->cand_slot, c->cand_n,
                            c->samples, ns, rel_poses + 12 * (t - 1), c->cand_start, c->status);
+        sa.start_p = c->cand_start;
+        m.n_seeds = 0;
     }
-    SeedArgs sa;
-    sa.samples = c->samples;
-    sa.bcnt = c->bcnt;
-    sa.seed_score = c->seed_score;
-    sa.seed_part = c->seed_part;
-    sa.prev = rel_poses + 12 * (t - 1);
-    sa.start_p = allpix ? c->cand_start : nullptr;
-    sa.status = c->status;
-    sa.ns = ns;
-    sa.nb = nb;
-    sa.have_prev = have_prev;
-    sa.is2t = 1.0 / pp.s2t;
-    sa.is2r = 1.0 / pp.s2r;
-    const int n_seeds = allpix ? 0 : pp.n_seeds;
-    hipLaunchKernelGGL(k_pose_seed, dim3((n_seeds + 1) * kSeedParts), dim3(kSeedThreads), 0, s, sa);
-    MsArgs m;
-    m.sampf = c->sampf;
-    m.bcnt = c->bcnt;
-    m.bws = c->bws;
-    m.seed_score = c->seed_score;
-    m.seed_part = c->seed_part;
-    m.rel = rel_poses;
-    m.Mcum = c->Mcum;
-    m.diag = c->pose_diag + 4 * (t - 1);
-    m.status = c->status;
-    m.ns = ns;
-    m.nb = nb;
-    m.n_seeds = n_seeds;
-    m.t = t;
-    m.max_iters = pp.ms_max_iters;
-    m.fallback_prev_frame = (!have_prev && t >= 2) ? 1 : 0;
-    m.wt = g.wt;
-    m.wr = g.wr;
-    m.tol = pp.ms_tol;
+    hipLaunchKernelGGL(k_pose_seed, dim3((m.n_seeds + 1) * kSeedParts), dim3(kSeedThreads), 0, s, sa);
     hipLaunchKernelGGL(k_pose_ms, dim3(1), dim3(kMsThreads), 0, s, m);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+void plan_pose_step(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, int t, int it)
+{
+    const int n = (int)idx.size();
+    std::vector<GroupArgs> g(n);
+    std::vector<SeedArgs> sa(n);
+    std::vector<MsArgs> m(n);
+    int nb_max = 0;
+    for (int k = 0; k < n; ++k) {
+        const WinRef &r = w[idx[k]];
+        WinDims d = r.d;
+        d.use_w = it > 0 ? 1 : 0;
+        pose_step_args(r.c, r.depth, r.rig, r.X, d, r.pp, t, it, (it > 0 || t == 1) ? 1 : 0, r.poses, g[k],
+                       sa[k], m[k]);
+        nb_max = std::max(nb_max, sa[k].nb);
+    }
+    // every window of a batch has the same number of start candidates
+    const int n_seeds = n ? m[0].n_seeds : 0;
+    MultiLaunch l = {};
+    l.nwin = n;
+    l.kind = kMultiPoseGroups;
+    l.off = p.put(g.data(), n);
+    l.gx = nb_max;
+    out.push_back(l);
+    l.kind = kMultiPoseSeed;
+    l.off = p.put(sa.data(), n);
+    l.gx = (n_seeds + 1) * kSeedParts;
+    out.push_back(l);
+    l.kind = kMultiPoseMs;
+    l.off = p.put(m.data(), n);
+    l.gx = 1;
+    out.push_back(l);
+}
+
+void plan_gauge_poses(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                      const std::vector<int> &idx)
+{
+    const int n = (int)idx.size();
+    std::vector<GaugeArgs> g(n);
+    for (int k = 0; k < n; ++k) {
+        const WinRef &r = w[idx[k]];
+        g[k].rel = r.poses;
+        g[k].Mcum = r.c->Mcum;
+        g[k].range = r.c->range;
+        g[k].status = r.c->status;
+        g[k].T = r.d.T;
+    }
+    MultiLaunch l = {};
+    l.kind = kMultiGauge;
+    l.nwin = n;
+    l.off = p.put(g.data(), n);
+    l.gx = 1;
+    out.push_back(l);
+}
+
+int launch_pose_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s)
+{
+    if (m.nwin < 1) return 0;
+    const dim3 grid(m.gx, m.nwin);
+    switch (m.kind) {
+    case kMultiPoseGroups:
+        hipLaunchKernelGGL(k_pose_groups_multi, grid, dim3(64), 0, s, (const GroupArgs *)(dev + m.off));
+        break;
+    case kMultiPoseSeed:
+        hipLaunchKernelGGL(k_pose_seed_multi, grid, dim3(kSeedThreads), 0, s, (const SeedArgs *)(dev + m.off));
+        break;
+    case kMultiPoseMs:
+        hipLaunchKernelGGL(k_pose_ms_multi, grid, dim3(kMsThreads), 0, s, (const MsArgs *)(dev + m.off));
+        break;
+    case kMultiGauge:
+        hipLaunchKernelGGL(k_gauge_poses_multi, grid, dim3(64), 0, s, (const GaugeArgs *)(dev + m.off));
+        break;
+    default:
+        return VOLDOR_EINVAL;
+    }
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 

@@ -23,6 +23,8 @@
 //      or before it.
 // C/D give exactly the result of the serial walk along the chain: each score
 // is the same FP32 function of (position, value) in every phase.
+#include <algorithm>
+
 #include "vo_internal.hpp"
 
 namespace vo {
@@ -450,28 +452,31 @@ __host__ __device__ inline int sweep_region2_words(int T, int L, int nt = kSweep
 // NT threads per chain (256, 512, 768 or 1024): every item is the same function of
 // its inputs whatever NT is, so all widths give the same result bit for bit;
 // NT only sets how a chain's work is spread (and how many chains fit a CU)
+// XCD-aware item order: workgroups are dealt round-robin to the 8 XCDs, so
+// give each XCD a contiguous range of items (neighbouring chains share flow
+// cache lines in that XCD's L2)
+__device__ __forceinline__ int xcd_item(int block, int nitems)
+{
+    const int xcd = block & 7, slot = block >> 3;
+    const int per = (nitems + 7) >> 3;
+    const int full = nitems - (per - 1) * 8;
+    return xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
+}
+
+// The sweep of one chain by one workgroup; lds is the dynamic area, fr and
+// s_cnt the workgroup's frames and list counters.
 template <int CRIT, int NT, int MODEL>
-__global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
+__device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain, float *lds, FrameF *fr,
+                                            int *s_cnt)
 {
     if (a.status && *a.status != kStatusOk) return;
     // MIE with the Gaussian residual model keeps lam = log(-ell) per item and
     // the scores in log form (LogScore in vo_device.hpp)
     constexpr bool LOGS = CRIT == 0 && MODEL == 1;
-    extern __shared__ float lds[];
-    __shared__ FrameF fr[kTMax + 1];
-    __shared__ int s_cnt[2];
 
     const int T = a.T, H = a.H, W = a.W, dir = a.dir;
     const int L = (dir & 1) ? H : W;
     const int tid = threadIdx.x;
-    // XCD-aware chain order: workgroups are dealt round-robin to the 8 XCDs,
-    // so give each XCD a contiguous range of chains (neighbouring chains
-    // share flow cache lines in that XCD's L2)
-    const int nchain = gridDim.x;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int per = (nchain + 7) >> 3;
-    const int full = nchain - (per - 1) * 8;
-    const int chain = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
 
     float *th = lds;                                   // [L]   previous depth
     float *sm = th + L;                                // [L]   random sample
@@ -870,6 +875,32 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     for (int k = tid; k < L; k += NT) a.theta_out[chain_pixel(dir, H, W, chain, k)] = thn[k];
 }
 
+template <int CRIT, int NT, int MODEL>
+__global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
+{
+    extern __shared__ float lds[];
+    __shared__ FrameF fr[kTMax + 1];
+    __shared__ int s_cnt[2];
+    sweep_chain<CRIT, NT, MODEL>(a, xcd_item(blockIdx.x, gridDim.x), lds, fr, s_cnt);
+}
+
+// One sweep of the chains of several windows (a lockstep batch lane): item u
+// is chain u - first[w] of window w, first[] the windows' chain offsets
+// (first[nwin] = gridDim.x); each window's arguments are those of its single
+// launch, so every chain gets exactly its single-window result.
+template <int CRIT, int NT, int MODEL>
+__global__ void __launch_bounds__(NT, 6) k_sweep_multi(const SweepArgs *args, const int *first, int nwin)
+{
+    extern __shared__ float lds[];
+    __shared__ FrameF fr[kTMax + 1];
+    __shared__ int s_cnt[2];
+    const int u = xcd_item(blockIdx.x, gridDim.x);
+    int w = 0;
+    while (w + 1 < nwin && u >= first[w + 1]) ++w;
+    const SweepArgs a = args[w];
+    sweep_chain<CRIT, NT, MODEL>(a, u - first[w], lds, fr, s_cnt);
+}
+
 // ---------------------------------------------------------------------------
 // unsmoothed rigidness W_t = r_t(theta) (last row of Table 1), optional dense
 // emission maps, optional log-likelihood partial sums of Eq. 3
@@ -884,10 +915,11 @@ struct RigArgs {
     float *r, *ell, *logrho, *logmu;
     double *ll_part;
     int T, H, W;
+    int nblk;               // workgroups over the window's pixels
     EmisParams e;
 };
 
-__global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
+__device__ __forceinline__ void rigidness_body(const RigArgs &a)
 {
     if (a.status && *a.status != kStatusOk) return;
     __shared__ FrameF fr[kTMax + 1];
@@ -902,7 +934,7 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
         gscale = g > 0 ? g : 1.0;
     }
     double acc = 0.0, mass = 0.0;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < HW; j += gridDim.x * blockDim.x) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < HW; j += a.nblk * blockDim.x) {
         const int y = j / a.W, x = j - y * a.W;
         const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
         const float th = a.theta[j];
@@ -998,8 +1030,19 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a)
     }
 }
 
+__global__ void __launch_bounds__(256) k_rigidness(RigArgs a) { rigidness_body(a); }
+
+// the rigidness pass of several windows (a lockstep batch lane), blockIdx.y
+// selecting a window's arguments
+__global__ void __launch_bounds__(256) k_rigidness_multi(const RigArgs *args)
+{
+    const RigArgs a = args[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk) return;   // past this window's workgroups
+    rigidness_body(a);
+}
+
 // fixed-order sum of the per-block partial sums
-__global__ void k_ll_reduce(const double *part, int n, const int *status, double *out)
+__device__ __forceinline__ void ll_reduce_body(const double *part, int n, const int *status, double *out)
 {
     if (status && *status != kStatusOk) return;
     __shared__ double red[2][256];
@@ -1022,6 +1065,24 @@ __global__ void k_ll_reduce(const double *part, int n, const int *status, double
         out[0] = red[0][0];
         out[1] = red[1][0];
     }
+}
+
+__global__ void k_ll_reduce(const double *part, int n, const int *status, double *out)
+{
+    ll_reduce_body(part, n, status, out);
+}
+
+struct LLArgs {
+    const double *part;
+    const int *status;
+    double *out;
+    int n;
+};
+
+__global__ void k_ll_reduce_multi(const LLArgs *args)
+{
+    const LLArgs a = args[blockIdx.y];
+    ll_reduce_body(a.part, a.n, a.status, a.out);
 }
 
 __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n)
@@ -1082,17 +1143,17 @@ static int launch_sweep_nt(const SweepArgs &a, int nchain, size_t lds, hipStream
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
-int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
-                 const WinDims &d, const EmisParams &e, float gamma, uint64_t seed, int64_t gsweep,
-                 int dir, const double *range_dev, float *q_out, hipStream_t s, int criterion)
+// arguments, threads per chain and LDS bytes of one sweep of a window
+static void sweep_args(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
+                       const WinDims &d, const EmisParams &e, float gamma, uint64_t seed, int64_t gsweep,
+                       int dir, const double *range_dev, float *q_out, int criterion, SweepArgs &a, int &nt,
+                       size_t &lds)
 {
     const int L = (dir & 1) ? d.H : d.W;
-    const int nchain = (dir & 1) ? d.W : d.H;
-    int nt = 512, la = 0;
+    int la = 0;
+    nt = 512;
     sweep_cfg_for(c, dir & 1, L, d.T, criterion, &nt, &la);
-    const size_t lds = sweep_lds_bytes(d.T, L, criterion, nt);
-    if (L < 16) return VOLDOR_EINVAL;
-    SweepArgs a;
+    lds = sweep_lds_bytes(d.T, L, criterion, nt);
     a.theta_in = theta_in;
     a.theta_out = theta_out;
     a.flows = flows;
@@ -1109,6 +1170,20 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     a.seed = seed;
     a.gsweep = gsweep;
     a.la_cap = la;
+}
+
+int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const float2 *flows,
+                 const WinDims &d, const EmisParams &e, float gamma, uint64_t seed, int64_t gsweep,
+                 int dir, const double *range_dev, float *q_out, hipStream_t s, int criterion)
+{
+    const int L = (dir & 1) ? d.H : d.W;
+    const int nchain = (dir & 1) ? d.W : d.H;
+    if (L < 16) return VOLDOR_EINVAL;
+    SweepArgs a;
+    int nt = 512;
+    size_t lds = 0;
+    sweep_args(c, theta_in, theta_out, flows, d, e, gamma, seed, gsweep, dir, range_dev, q_out, criterion, a, nt,
+               lds);
     switch ((nt * 2 + (criterion ? 1 : 0)) * 2 + (e.model ? 1 : 0)) {
     case 1024: return launch_sweep_nt<0, 256, 0>(a, nchain, lds, s);
     case 1025: return launch_sweep_nt<0, 256, 1>(a, nchain, lds, s);
@@ -1126,6 +1201,138 @@ int launch_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     case 4097: return launch_sweep_nt<0, 1024, 1>(a, nchain, lds, s);
     case 4098: return launch_sweep_nt<1, 1024, 0>(a, nchain, lds, s);
     case 4099: return launch_sweep_nt<1, 1024, 1>(a, nchain, lds, s);
+    default: return VOLDOR_EINVAL;
+    }
+}
+
+void plan_sweep(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                const std::vector<int> &idx, float gamma, uint64_t seed, int64_t gsweep, int dir,
+                int criterion)
+{
+    const int n = (int)idx.size();
+    std::vector<SweepArgs> a(n);
+    std::vector<int> nt(n);
+    std::vector<size_t> lds(n);
+    for (int k = 0; k < n; ++k) {
+        const WinRef &r = w[idx[k]];
+        sweep_args(r.c, r.depth, r.depth, r.X, r.d, r.e, gamma, seed, gsweep, dir, r.c->range, nullptr, criterion,
+                   a[k], nt[k], lds[k]);
+    }
+    // one launch per (threads per chain, LDS bytes) class: a launch's LDS is
+    // that of every chain in it, so no chain holds more than its own
+    std::vector<bool> done(n, false);
+    for (int k0 = 0; k0 < n; ++k0) {
+        if (done[k0]) continue;
+        std::vector<SweepArgs> sel;
+        std::vector<int> first(1, 0);
+        const int cls = nt[k0];
+        const size_t lmax = lds[k0];
+        for (int k = k0; k < n; ++k) {
+            if (done[k] || nt[k] != cls || lds[k] != lmax) continue;
+            done[k] = true;
+            sel.push_back(a[k]);
+            first.push_back(first.back() + ((dir & 1) ? a[k].W : a[k].H));
+        }
+        MultiLaunch l = {};
+        l.kind = kMultiSweep;
+        l.variant = (cls * 2 + (criterion ? 1 : 0)) * 2 + (sel[0].e.model ? 1 : 0);
+        l.nwin = (int)sel.size();
+        l.off = p.put(sel.data(), sel.size());
+        l.off2 = p.put(first.data(), first.size());
+        l.gx = first.back();
+        l.lds = lmax;
+        out.push_back(l);
+    }
+}
+
+template <int CRIT, int NT, int MODEL>
+static int launch_sweep_multi_nt(const MultiLaunch &m, const unsigned char *dev, hipStream_t s)
+{
+    if (m.lds > 65536 &&
+        hipFuncSetAttribute((const void *)k_sweep_multi<CRIT, NT, MODEL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)m.lds) != hipSuccess)
+        return VOLDOR_EDEVICE;
+    hipLaunchKernelGGL((k_sweep_multi<CRIT, NT, MODEL>), dim3(m.gx), dim3(NT), m.lds, s,
+                       (const SweepArgs *)(dev + m.off), (const int *)(dev + m.off2), m.nwin);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+void plan_rigidness(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, bool gauge, const std::vector<double *> &ll)
+{
+    const int n = (int)idx.size();
+    std::vector<RigArgs> a(n);
+    std::vector<LLArgs> r(n);
+    int gx = 0;
+    for (int k = 0; k < n; ++k) {
+        const WinRef &wr = w[idx[k]];
+        RigArgs &x = a[k];
+        x.theta = wr.depth;
+        x.theta_gauge = gauge ? wr.depth : nullptr;
+        x.rel = gauge ? wr.poses : nullptr;
+        x.flows = wr.X;
+        x.Mcum = wr.c->Mcum;
+        x.status = wr.c->status;
+        x.r = gauge ? wr.rig : nullptr;
+        x.ell = nullptr;
+        x.logrho = nullptr;
+        x.logmu = nullptr;
+        x.ll_part = gauge ? nullptr : wr.c->ll_part;
+        x.T = wr.d.T;
+        x.H = wr.d.H;
+        x.W = wr.d.W;
+        x.e = wr.e;
+        const int HW = wr.d.H * wr.d.W;
+        x.nblk = std::min((HW + 255) / 256, kLLBlocks);
+        gx = std::max(gx, x.nblk);
+        r[k].part = wr.c->ll_part;
+        r[k].status = wr.c->status;
+        r[k].out = gauge ? nullptr : ll[k];
+        r[k].n = x.nblk;
+    }
+    MultiLaunch l = {};
+    l.kind = kMultiRig;
+    l.nwin = n;
+    l.off = p.put(a.data(), n);
+    l.gx = gx;
+    out.push_back(l);
+    if (!gauge) {
+        l.kind = kMultiLL;
+        l.off = p.put(r.data(), n);
+        l.gx = 1;
+        out.push_back(l);
+    }
+}
+
+int launch_sweep_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s)
+{
+    if (m.nwin < 1) return 0;
+    if (m.kind == kMultiRig) {
+        hipLaunchKernelGGL(k_rigidness_multi, dim3(m.gx, m.nwin), dim3(256), 0, s, (const RigArgs *)(dev + m.off));
+        return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+    }
+    if (m.kind == kMultiLL) {
+        hipLaunchKernelGGL(k_ll_reduce_multi, dim3(1, m.nwin), dim3(256), 0, s, (const LLArgs *)(dev + m.off));
+        return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+    }
+    if (m.kind != kMultiSweep) return VOLDOR_EINVAL;
+    switch (m.variant) {
+    case 1024: return launch_sweep_multi_nt<0, 256, 0>(m, dev, s);
+    case 1025: return launch_sweep_multi_nt<0, 256, 1>(m, dev, s);
+    case 1026: return launch_sweep_multi_nt<1, 256, 0>(m, dev, s);
+    case 1027: return launch_sweep_multi_nt<1, 256, 1>(m, dev, s);
+    case 2048: return launch_sweep_multi_nt<0, 512, 0>(m, dev, s);
+    case 2049: return launch_sweep_multi_nt<0, 512, 1>(m, dev, s);
+    case 2050: return launch_sweep_multi_nt<1, 512, 0>(m, dev, s);
+    case 2051: return launch_sweep_multi_nt<1, 512, 1>(m, dev, s);
+    case 3072: return launch_sweep_multi_nt<0, 768, 0>(m, dev, s);
+    case 3073: return launch_sweep_multi_nt<0, 768, 1>(m, dev, s);
+    case 3074: return launch_sweep_multi_nt<1, 768, 0>(m, dev, s);
+    case 3075: return launch_sweep_multi_nt<1, 768, 1>(m, dev, s);
+    case 4096: return launch_sweep_multi_nt<0, 1024, 0>(m, dev, s);
+    case 4097: return launch_sweep_multi_nt<0, 1024, 1>(m, dev, s);
+    case 4098: return launch_sweep_multi_nt<1, 1024, 0>(m, dev, s);
+    case 4099: return launch_sweep_multi_nt<1, 1024, 1>(m, dev, s);
     default: return VOLDOR_EINVAL;
     }
 }
@@ -1153,6 +1360,7 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
     const int HW = d.H * d.W;
     int blocks = (HW + 255) / 256;
     if (blocks > kLLBlocks) blocks = kLLBlocks;
+    a.nblk = blocks;
     hipLaunchKernelGGL(k_rigidness, dim3(blocks), dim3(256), 0, s, a);
     if (ll_out) hipLaunchKernelGGL(k_ll_reduce, dim3(1), dim3(256), 0, s, c->ll_part, blocks, c->status, ll_out);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;

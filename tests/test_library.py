@@ -85,7 +85,7 @@ def test_batch_host_argument_checks(vo):
     b = C.c_void_p()
     assert lib.voldor_batch_create(C.byref(b), 0, 4, 64, 64, 64, 0) == vo.EINVAL
     assert lib.voldor_batch_create(C.byref(b), 9, 4, 64, 64, 64, 0) == vo.EINVAL
-    assert lib.voldor_batch_create(C.byref(b), 2, 4, 64, 64, 64, 2) == vo.EINVAL   # unknown flag
+    assert lib.voldor_batch_create(C.byref(b), 2, 4, 64, 64, 64, 4) == vo.EINVAL   # unknown flag
     assert lib.voldor_batch_create(None, 2, 4, 64, 64, 64, 0) == vo.EINVAL
     p = vo.default_params()
     descs = (vo.WindowDesc * 1)()
