@@ -147,6 +147,10 @@ def _pose_error(poses, gt):
 
 
 BATCH_ITERS = 4
+# lanes of the batch workload per mode (measured: lockstep 32.2 ms per step at
+# 12 lanes, 32.4 at 8; stream-order lanes 34.7 ms at 4)
+BATCH_LOCKSTEP_LANES = 12
+BATCH_STREAM_LANES = 4
 # algorithmic FP32 work of one pixel-frame in one sweep: three candidate-frame
 # evaluations (previous depth, random sample, propagated neighbour), each about
 # 8 transcendental and 50 other FP32 operations
@@ -273,7 +277,9 @@ def run_batch(args):
     Tm, Hm, Wm = (max(x[k] for x in shapes) for k in range(3))
     status = torch.full((len(wins),), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
-    solver = vo.Batch(args.lanes, Tm, Hm, Wm, max(groups), graph=not args.no_graph, lockstep=args.lockstep)
+    lockstep = args.batch_mode == "lockstep"
+    lanes = args.lanes or (BATCH_LOCKSTEP_LANES if lockstep else BATCH_STREAM_LANES)
+    solver = vo.Batch(lanes, Tm, Hm, Wm, max(groups), graph=not args.no_graph, lockstep=lockstep)
     with torch.cuda.stream(stream):
         solver.autotune(items, p, stream=stream)
     solver.set_timing(True)
@@ -331,28 +337,32 @@ def run_batch(args):
                                f"{BATCH_ITERS} EM iterations, P3P groups per frame 1024 / 2048 / 4096 by shape, "
                                f"seed {args.seed}",
                    "windows": len(wins), "shapes": mix, "frames": sum(x[0] for x in shapes),
-                   "lanes": args.lanes, "graph": not args.no_graph,
-                   "mode": "lockstep" if args.lockstep else "windows in stream order per lane",
+                   "lanes": lanes, "graph": not args.no_graph,
+                   "mode": ("lockstep: the windows of a lane advance together, one launch per kernel over "
+                            "their (window, frame) and (window, chain) items") if lockstep
+                   else "windows in stream order per lane",
                    "parallelism": "single GPU, one batch per step over concurrent streams"},
         "windows_per_s": len(wins) * 1e3 / ms,
         "pose_error_vs_gt": {"rot_rad": float(np.mean([e[0] for e in errs])),
                              "tdir_rad": float(np.mean([e[1] for e in errs]))},
-        "phase_ms_summed_over_windows": {k: float(ph[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness",
-                                                                    "loglik", "window"]},
-        "timed_windows": n_timed,
-        "roofline": {"bound": "hbm", "kernel": "k_sweep",
+        ("phase_ms_summed_over_lanes" if lockstep else "phase_ms_summed_over_windows"):
+            {k: float(ph[k]) for k in ["bootstrap", "pose", "sweeps", "rigidness", "loglik", "window"]},
+        ("timed_lanes" if lockstep else "timed_windows"): n_timed,
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_multi" if lockstep else "k_sweep",
                      "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
-                     "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid() else None,
+                     "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid(lockstep) else None,
                      "alg_bytes_per_launch": alg_bytes / max(launches, 1.0),
                      "launch_ms": ph["sweeps_busy"] / max(launches, 1.0), "launches": launches,
                      "launch_ms_concurrent": ph["sweeps"] / max(launches, 1.0),
                      "step_aggregate_GBs": alg_bytes / (ms * 1e-3) / 1e9,
-                     "note": "algorithmic bytes of a sweep: the flow stack read once (8 B per pixel-frame) and the "
-                             "depth read and written (8 B per pixel); launch_ms = the time during which the chip ran "
-                             "sweeps in the last timed step (union of the windows' sweep intervals between device "
-                             "timestamps on the lane streams) per launch; launch_ms_concurrent = the mean interval "
-                             "per launch on its own lane, stretched where lanes overlap"},
+                     "note": "a launch here is one window's sweep of one direction (in lockstep mode one kernel "
+                             "launch serves those of several windows); algorithmic bytes of a sweep: the flow stack "
+                             "read once (8 B per pixel-frame) and the depth read and written (8 B per pixel); "
+                             "launch_ms = the time during which the chip ran sweeps in the last timed step (union of "
+                             "the lanes' sweep intervals between device timestamps on the lane streams) per launch; "
+                             "launch_ms_concurrent = the lanes' sweep intervals summed, per launch, stretched where "
+                             "lanes overlap"},
         "alu_view": {"achieved_TFLOPs": alg_ops / sweep_s / 1e12 if sweep_s > 0 else None,
                      "peak_TFLOPs": FP32_PEAK_TFLOPS,
                      "frac": alg_ops / sweep_s / 1e12 / FP32_PEAK_TFLOPS if sweep_s > 0 else None,
@@ -373,11 +383,14 @@ def run_batch(args):
 # calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
 BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (35.64 + 1.37) * 1e6   # profiles/k_sweep_hbm_traffic.md
 BATCH_SWEEP_SOURCES_SHA = "517abd8cdb26fb77"
+BATCH_SWEEP_TRAFFIC_LOCKSTEP = False   # the batch mode the counters were taken in
 
 
-def _batch_sweep_traffic_valid():
+def _batch_sweep_traffic_valid(lockstep):
     import hashlib
     if BATCH_SWEEP_TRAFFIC_PER_LAUNCH is None or BATCH_SWEEP_SOURCES_SHA is None:
+        return False
+    if lockstep != BATCH_SWEEP_TRAFFIC_LOCKSTEP:
         return False
     h = hashlib.sha256()
     for f in SWEEP_SOURCES:
@@ -840,9 +853,11 @@ def main():
                     help="mean-shift start: densest of 64 seeds, or every candidate scored over all pixels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
-    ap.add_argument("--lanes", type=int, default=4, help="concurrent streams (--workload batch)")
-    ap.add_argument("--lockstep", action="store_true",
-                    help="the windows of each lane advance together, one launch per kernel over all of them")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="concurrent streams of --workload batch (default: 12 in lockstep mode, 4 otherwise)")
+    ap.add_argument("--batch-mode", choices=["lockstep", "lanes"], default="lockstep",
+                    help="lockstep: the windows of each lane advance together, one launch per kernel over all "
+                         "of them; lanes: each lane solves its windows one after another")
     ap.add_argument("--no-graph", action="store_true", help="enqueue launches instead of a HIP graph")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-window indoor and driving figures of the batch workload")

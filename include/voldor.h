@@ -270,7 +270,7 @@ typedef struct {
     int32_t pad;
 } voldor_window_desc;
 
-/* Batch solver: `lanes` (1..8) HIP streams, each with the workspace of a
+/* Batch solver: `lanes` (1..16) HIP streams, each with the workspace of a
  * context sized T_max x H_max x W_max x S_max.  Windows are independent, so a
  * batch is spread over the lanes (largest first, onto the least loaded lane)
  * and the lanes run concurrently: one window's latency-bound pose steps

@@ -24,7 +24,7 @@ using namespace vo;
 
 namespace {
 
-constexpr int kMaxLanes = 8;
+constexpr int kMaxLanes = 16;
 
 // relative cost of a window: its pixel-frames (sweeps, rigidness) plus a
 // fixed share per frame for the pose chain (about 0.1 Mpixel-frames of sweep

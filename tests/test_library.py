@@ -84,7 +84,7 @@ def test_batch_host_argument_checks(vo):
     lib = vo.lib()
     b = C.c_void_p()
     assert lib.voldor_batch_create(C.byref(b), 0, 4, 64, 64, 64, 0) == vo.EINVAL
-    assert lib.voldor_batch_create(C.byref(b), 9, 4, 64, 64, 64, 0) == vo.EINVAL
+    assert lib.voldor_batch_create(C.byref(b), 17, 4, 64, 64, 64, 0) == vo.EINVAL
     assert lib.voldor_batch_create(C.byref(b), 2, 4, 64, 64, 64, 4) == vo.EINVAL   # unknown flag
     assert lib.voldor_batch_create(None, 2, 4, 64, 64, 64, 0) == vo.EINVAL
     p = vo.default_params()
