@@ -308,8 +308,10 @@ void voldor_batch_destroy(voldor_batch *b);
 int voldor_window_batch(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
                         int32_t *status_out, void *stream);
 
-/* Sweep widths of every lane of the batch (as voldor_set_sweep_threads). */
+/* Sweep widths and look-ahead caps of every lane of the batch (as
+ * voldor_set_sweep_threads and voldor_set_sweep_lookahead). */
 int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols);
+int voldor_batch_set_sweep_lookahead(voldor_batch *b, int rows, int cols);
 
 /* Autotuner of a batch: voldor_autotune on the first window of every distinct
  * chain class (shape, T, criterion) among the n descriptors, the settings then

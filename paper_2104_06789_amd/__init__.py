@@ -98,6 +98,7 @@ def lib():
         "voldor_get_sweep_lookahead": (i, [vp, ip, ip]),
         "voldor_autotune": (i, [vp, vp, i, i, i, dp, P, ip, ip, vp]),
         "voldor_batch_set_sweep_threads": (i, [vp, i, i]),
+        "voldor_batch_set_sweep_lookahead": (i, [vp, i, i]),
         "voldor_batch_autotune": (i, [vp, C.POINTER(WindowDesc), i, P, vp]),
         "voldor_batch_set_timing": (i, [vp, i]),
         "voldor_batch_timing_summary": (i, [vp, dp, ip]),
@@ -602,6 +603,11 @@ class Batch:
     def set_sweep_threads(self, rows, cols):
         """Sweep widths of every lane (as Solver.set_sweep_threads)."""
         _check(lib().voldor_batch_set_sweep_threads(self._b, int(rows), int(cols)), "voldor_batch_set_sweep_threads")
+
+    def set_sweep_lookahead(self, rows, cols):
+        """Look-ahead caps of every lane (as Solver.set_sweep_lookahead)."""
+        _check(lib().voldor_batch_set_sweep_lookahead(self._b, int(rows), int(cols)),
+               "voldor_batch_set_sweep_lookahead")
 
     @staticmethod
     def _descs(windows):

@@ -256,6 +256,17 @@ int voldor_batch_set_sweep_threads(voldor_batch *b, int rows, int cols)
     return VOLDOR_OK;
 }
 
+int voldor_batch_set_sweep_lookahead(voldor_batch *b, int rows, int cols)
+{
+    if (!b) return VOLDOR_EINVAL;
+    for (int l = 0; l < b->lanes; ++l) {
+        const int rc = voldor_set_sweep_lookahead(b->ctx[l], rows, cols);
+        if (rc) return rc;
+    }
+    drop_graph(b);   // a captured graph holds the old launches
+    return VOLDOR_OK;
+}
+
 int voldor_batch_autotune(voldor_batch *b, const voldor_window_desc *wins, int n, const voldor_params *p,
                           void *stream)
 {
