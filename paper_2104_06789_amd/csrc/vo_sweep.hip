@@ -340,7 +340,7 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
 {
     const int n = s1 - s0;
     // positions past s1 read whatever follows (the next frame, or the first
-    // words of region 2, which holds at least 8 L >= SEG words); unused
+    // words of region 2, which holds at least 6 L >= SEG words); unused
     float rr[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) rr[i] = rq[s0 + i];
@@ -437,12 +437,12 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
     }
 }
 
-// LDS words of the dynamic area for a chain of length L and T frames (the MLE
-// criterion adds log mu of the previous depth, T L words after region 2)
+// LDS words of region 2 of a chain of length L and T frames: the previous
+// depth's ell (MLE: d) in phases A-S, the live lists in C, the jump tables in D
 __host__ __device__ inline int sweep_region2_words(int T, int L, int nt = kSweepThreads)
 {
     int w = T * L;
-    if (w < 8 * L) w = 8 * L;
+    if (w < 6 * L) w = 6 * L;   // the live lists: two of (origin, position) pairs, two of first losses
     if (w < 4 * L + nt) w = 4 * L + nt;
     return w;
 }
@@ -480,16 +480,19 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
 
     float *th = lds;                                   // [L]   previous depth
     float *sm = th + L;                                // [L]   random sample
-    float *aval = sm + L;                              // [L]   local best value
+    float *fq = sm + L;                                // [T][L] r -> forward message -> q
+    float *lq = fq + T * L;                            // region 2: ell(prev) (MLE: then the sample's terms), lists, doubling
+    // region 3, [max(T, 4)][L]: MIE ell of the random sample; MLE (region 2
+    // then holds d = log(mu/rho) of the previous depth) its log mu.  Phase S
+    // reads a position's rows and then writes that position's local best,
+    // its score, the sample flag and (later) next() over rows 0-3: each
+    // thread only over the rows of its own positions, read before written
+    float *lmq = lq + sweep_region2_words(T, L, NT);
+    float *ls = lmq;
+    float *aval = lmq;                                 // [L]   local best value
     float *sa = aval + L;                              // [L]   score: previous, then local best
     int *flg = (int *)(sa + L);                        // [L]   1 if the sample is the local best
     int *nxt = flg + L;                                // [L]   next(k)
-    float *fq = (float *)(nxt + L);                    // [T][L] r -> forward message -> q
-    float *lq = fq + T * L;                            // region 2: ell(prev) (MLE: then the sample's terms), lists, doubling
-    // MIE: ell of the random sample; MLE: region 2 holds d = log(mu/rho) of
-    // the previous depth and lmq its log mu
-    float *lmq = lq + sweep_region2_words(T, L, NT);   // [T][L]
-    float *ls = lmq;
 
     load_frames(a.Mcum, T, fr);
     if (tid == 0) {
@@ -1097,9 +1100,10 @@ __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t
 // ---------------------------------------------------------------------------
 size_t sweep_lds_bytes(int T, int L, int criterion, int nt)
 {
-    // both criteria hold a third [T][L] array: MIE the sample's ell, MLE log mu
+    // th, sm, fq, region 2, region 3 (both criteria hold a third [T][L] array:
+    // MIE the sample's ell, MLE log mu; at least 4 rows for the local bests)
     (void)criterion;
-    return ((size_t)(6 + 2 * T) * L + (size_t)sweep_region2_words(T, L, nt)) * sizeof(float);
+    return ((size_t)(2 + T + (T > 4 ? T : 4)) * L + (size_t)sweep_region2_words(T, L, nt)) * sizeof(float);
 }
 
 void sweep_cfg_for(const voldor_ctx *c, int axis, int L, int T, int crit, int *nt, int *la)
