@@ -147,9 +147,9 @@ def _pose_error(poses, gt):
 
 
 BATCH_ITERS = 4
-# lanes of the batch workload per mode (measured: lockstep 32.2 ms per step at
-# 12 lanes, 32.4 at 8; stream-order lanes 34.7 ms at 4)
-BATCH_LOCKSTEP_LANES = 12
+# lanes of the batch workload per mode (measured on one box: lockstep 31.1 ms
+# per step at 8 lanes, 31.3 at 12, 31.5 at 16; stream-order lanes 34.7 ms at 4)
+BATCH_LOCKSTEP_LANES = 8
 BATCH_STREAM_LANES = 4
 # algorithmic FP32 work of one pixel-frame in one sweep: three candidate-frame
 # evaluations (previous depth, random sample, propagated neighbour), each about
@@ -854,7 +854,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=0,
-                    help="concurrent streams of --workload batch (default: 12 in lockstep mode, 4 otherwise)")
+                    help="concurrent streams of --workload batch (default: 8 in lockstep mode, 4 otherwise)")
     ap.add_argument("--batch-mode", choices=["lockstep", "lanes"], default="lockstep",
                     help="lockstep: the windows of each lane advance together, one launch per kernel over all "
                          "of them; lanes: each lane solves its windows one after another")
