@@ -302,6 +302,7 @@ int voldor_create(voldor_ctx **out, int T_max, int H_max, int W_max, int S_max)
     ok = ok && dalloc(&c->pose_tmp, 16) == hipSuccess;
     ok = ok && dalloc(&c->rel_tmp, 12 * T_max) == hipSuccess;
     ok = ok && dalloc(&c->theta_tmp, HW) == hipSuccess;
+    ok = ok && dalloc(&c->flows_t, (size_t)T_max * HW) == hipSuccess;
     const size_t ncand = 1 + pose_sample_slots(S_max);
     ok = ok && dalloc(&c->cand_F, 12 * ncand) == hipSuccess;
     ok = ok && dalloc(&c->cand_slot, ncand) == hipSuccess;
@@ -329,7 +330,7 @@ void voldor_destroy(voldor_ctx *c)
     voldor_set_timing(c, 0);
     void *bufs[] = {c->Mcum, c->range, c->status, c->samples, c->seed_score,
                     c->pose_diag, c->hyp, c->hyp_score, c->boot_info, c->boot_cand, c->boot_sub, c->dkeys, c->hist,
-                    c->sel, c->ll_part, c->init_ll, c->init_rel, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp,
+                    c->sel, c->ll_part, c->init_ll, c->init_rel, c->sampf, c->gcnt, c->gpre, c->bcnt, c->bws, c->seed_part, c->prev_pose, c->pose_tmp, c->rel_tmp, c->theta_tmp, c->flows_t,
                     c->cand_F, c->cand_slot, c->cand_n, c->cand_part, c->cand_score, c->cand_start};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -365,8 +366,10 @@ int window_enqueue(voldor_ctx *c, const float *flows, int T, int H, int W, const
     c->tw_cur = (int)(c->tw_count % kTimingRing);
     c->n_ev = 0;
     mark(c, s, kPhaseNone);
-    int rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
-                              p->depth_lo, p->depth_hi, poses, depth, s, init ? init->T1 : nullptr);
+    int rc = launch_transpose_flows(c, X, T, H, W, s);
+    if (rc == 0)
+        rc = launch_bootstrap(c, X, d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
+                              p->depth_hi, poses, depth, s, init ? init->T1 : nullptr);
     mark(c, s, kPhaseBoot);
     const bool proposed = init && init->depth && init->rig;
     if (proposed && (!c->init_rel || !c->init_ll)) return VOLDOR_EDEVICE;
@@ -544,8 +547,10 @@ int lockstep_run(voldor_ctx *lane, const std::vector<WinRef> &refs, const std::v
         case kStepBoot: {
             const WinRef &r = refs[st.win];
             r.c->last_stream = s;
-            rc = launch_bootstrap(r.c, r.X, r.d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
-                                  p->depth_hi, r.poses, r.depth, s, nullptr);
+            rc = launch_transpose_flows(r.c, r.X, r.d.T, r.d.H, r.d.W, s);
+            if (rc == 0)
+                rc = launch_bootstrap(r.c, r.X, r.d, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed,
+                                      p->depth_lo, p->depth_hi, r.poses, r.depth, s, nullptr);
             break;
         }
         case kStepMulti:
@@ -955,6 +960,7 @@ int voldor_sweep(voldor_ctx *c, const float *theta_in, float *theta_out, const f
     hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, c->status);
     if (hipMemcpyAsync(c->range, rng, sizeof rng, hipMemcpyHostToDevice, s) != hipSuccess) return VOLDOR_EDEVICE;
     int rc = upload_M(c, M, T, s);
+    if (rc == 0) rc = launch_transpose_flows(c, (const float2 *)flows, T, H, W, s);
     if (rc == 0)
         rc = launch_sweep(c, theta_in, theta_out, (const float2 *)flows, dims(T, H, W, K), emis(K, p),
                           (float)p->gamma, p->seed, global_sweep, dir, c->range, q_out, s, p->criterion);

@@ -87,6 +87,7 @@ struct voldor_ctx {
     double *pose_tmp;      // [16]
     double *rel_tmp;       // [T_max][12] poses for step entry points
     float *theta_tmp;      // [H_max W_max]
+    float2 *flows_t;       // [T_max][W_max][H_max]: the window's flows transposed, for the column sweeps
     // all-pixel start candidates (pose_start = 1), n = 1 + sample slots at most
     float *cand_F;         // [n][12] FP32 frames of M_t = T_c o M_{t-1}
     int *cand_slot;        // [n] sample slot, -1 previous pose, -2 none
@@ -143,6 +144,9 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
                      const double *rel_poses = nullptr);
 int launch_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n,
                   hipStream_t s);
+// the window's flows transposed into c->flows_t; every sweep of columns reads
+// that copy, so it runs before a window's (or a step entry point's) sweeps
+int launch_transpose_flows(voldor_ctx *c, const float2 *flows, int T, int H, int W, hipStream_t s);
 // LDS bytes of one chain of length L with nt threads (256, 512, 768 or 1024)
 size_t sweep_lds_bytes(int T, int L, int criterion, int nt);
 // threads per chain and look-ahead cap of chains of length L (axis 0 rows, 1

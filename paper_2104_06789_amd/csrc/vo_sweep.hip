@@ -67,11 +67,35 @@ __device__ __forceinline__ void chain_xy(int dir, int H, int W, int c, int k, in
     y = (dir & 1) ? (dir == 1 ? k : H - 1 - k) : c;
 }
 
+// The four bilinear taps of frame plane f0 at (x0, y0): a (x0, y0), b (x0 + 1,
+// y0), c (x0, y0 + 1), d (x0 + 1, y0 + 1).  TR: the plane is stored transposed
+// ([W][H], the column sweeps' copy), where (x0, y0) and (x0, y0 + 1) are
+// neighbours, so that the lanes of a column chain, consecutive in y, read
+// neighbouring words; the values are the same either way.
+template <bool TR>
+__device__ __forceinline__ void flow_taps(const float2 *__restrict__ flows, int f0, int x0, int y0, int H, int W,
+                                          float2 &a, float2 &b, float2 &c, float2 &d)
+{
+    if constexpr (TR) {
+        const float2 *r0 = flows + (f0 + x0 * H + y0);
+        a = r0[0];
+        c = r0[1];
+        b = r0[H];
+        d = r0[H + 1];
+    } else {
+        const float2 *r0 = flows + (f0 + y0 * W + x0);
+        a = r0[0];
+        b = r0[1];
+        c = r0[W];
+        d = r0[W + 1];
+    }
+}
+
 // Depth score at chain position k, frames in chunks (three; two for the
 // log-form score) so that the flow gathers of a chunk are in flight together:
 // MIE (Eq. 10) sum_t q_t ell_t(th), a missing frame log 1/2; MLE (Eq. 9)
 // sum_t log mu_t - q_t d_t, a missing frame 0
-template <int CRIT, int MODEL>
+template <int CRIT, int MODEL, bool TR>
 __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__restrict__ flows,
                                              int T, int H, int W, const EmisParams &e, int x, int y,
                                              float xh, float yh, float th, const float *q, int L,
@@ -115,11 +139,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
             ax[u] = spx - fx0;
             ay[u] = spy - fy0;
             const int tf = val[u] ? t0 + u - 1 : 0;
-            const float2 *r0 = flows + (tf * HW + y0 * W + x0);
-            ta[u] = r0[0];
-            tb[u] = r0[1];
-            tc[u] = r0[W];
-            td[u] = r0[W + 1];
+            flow_taps<TR>(flows, tf * HW, x0, y0, H, W, ta[u], tb[u], tc[u], td[u]);
         }
 #pragma unroll
         for (int u = 0; u < FC; ++u) {
@@ -159,7 +179,7 @@ __device__ __forceinline__ float chain_score(const FrameF *fr, const float2 *__r
 // D = log2(mu/rho) for a batch of B independent (pixel, frame, depth) items;
 // the flow gathers of the whole batch are issued before any of them is used.
 // ok[b] false: missing observation (or inactive item).  MU: log mu as well.
-template <int B, int MODEL, bool MU = false>
+template <int B, int MODEL, bool MU, bool TR>
 __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *__restrict__ flows, int H,
                                                int W, const EmisParams &e, const int *x, const int *y,
                                                const float *th, const int *t, const bool *act, float *d,
@@ -184,11 +204,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
         const int x0 = min((int)floorf(spx), W - 2), y0 = min((int)floorf(spy), H - 2);
         ax[b] = spx - (float)x0;
         ay[b] = spy - (float)y0;
-        const float2 *r0 = flows + ((v ? tt - 1 : 0) * HW + y0 * W + x0);
-        ta[b] = r0[0];
-        tb[b] = r0[1];
-        tc[b] = r0[W];
-        td[b] = r0[W + 1];
+        flow_taps<TR>(flows, (v ? tt - 1 : 0) * HW, x0, y0, H, W, ta[b], tb[b], tc[b], td[b]);
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -210,7 +226,7 @@ __device__ __forceinline__ void batch_log_odds(const FrameF *fr, const float2 *_
 // previous depth thp and at the random sample ths: the frame geometry of an
 // item is computed once for both depths.  Every log-odds is the same FP32
 // function of (pixel, frame, depth) as in batch_log_odds and chain_score.
-template <int B, int MODEL>
+template <int B, int MODEL, bool TR>
 __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const float2 *__restrict__ flows, int H,
                                                     int W, const EmisParams &e, const int *x, const int *y,
                                                     const float *thp, const float *ths, const int *t,
@@ -245,11 +261,7 @@ __device__ __forceinline__ void batch_log_odds_pair(const FrameF *fr, const floa
             const int x0 = (int)fx0, y0 = (int)fy0;
             ax[i] = spx - fx0;
             ay[i] = spy - fy0;
-            const float2 *r0 = flows + ((ok ? tt - 1 : 0) * HW + y0 * W + x0);
-            ta[i] = r0[0];
-            tb[i] = r0[1];
-            tc[i] = r0[W];
-            td[i] = r0[W + 1];
+            flow_taps<TR>(flows, (ok ? tt - 1 : 0) * HW, x0, y0, H, W, ta[i], tb[i], tc[i], td[i]);
         }
     }
 #pragma unroll
@@ -274,6 +286,7 @@ struct SweepArgs {
     const float *theta_in;
     float *theta_out;
     const float2 *flows;
+    const float2 *flows_t;   // the same planes transposed, [T][W][H] (column sweeps)
     const double *Mcum;    // cumulative poses M_0..M_T (device)
     const double *range;   // d_lo, d_hi (device)
     float *q_out;
@@ -465,10 +478,12 @@ __device__ __forceinline__ int xcd_item(int block, int nitems)
 
 // The sweep of one chain by one workgroup; lds is the dynamic area, fr and
 // s_cnt the workgroup's frames and list counters.
-template <int CRIT, int NT, int MODEL>
+template <int CRIT, int NT, int MODEL, bool TR>
 __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain, float *lds, FrameF *fr,
                                             int *s_cnt)
 {
+    // column chains (TR) gather from the transposed copy of the flows
+    const float2 *__restrict__ fl = TR ? a.flows_t : a.flows;
     if (a.status && *a.status != kStatusOk) return;
     // MIE with the Gaussian residual model keeps lam = log(-ell) per item and
     // the scores in log form (LogScore in vo_device.hpp)
@@ -543,7 +558,7 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
                 k += NT;
                 while (k >= L) { k -= L; ++t; }
             }
-            batch_log_odds_pair<PB, MODEL>(fr, a.flows, H, W, a.e, xs, ys, thp, ths, ts, act, dp, ds, okp, oks);
+            batch_log_odds_pair<PB, MODEL, TR>(fr, fl, H, W, a.e, xs, ys, thp, ths, ts, act, dp, ds, okp, oks);
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
                 const int i = i0 + b * NT;
@@ -590,7 +605,7 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
         }
         {
             float lm[kMleItems];
-            batch_log_odds<kMleItems, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            batch_log_odds<kMleItems, MODEL, true, TR>(fr, fl, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < kMleItems; ++b) {
                 const int i = i0 + b * NT;
@@ -758,7 +773,7 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
                 k += NT;
                 while (k >= L) { k -= L; ++t; }
             }
-            batch_log_odds<kMleItems, MODEL, true>(fr, a.flows, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
+            batch_log_odds<kMleItems, MODEL, true, TR>(fr, fl, H, W, a.e, xs, ys, ths, ts, act, dd, ok, lm);
 #pragma unroll
             for (int b = 0; b < kMleItems; ++b) {
                 const int i = i0 + b * NT;
@@ -820,7 +835,7 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
                 int x, y;
                 chain_xy(dir, H, W, chain, jpos, x, y);
                 const float xh = ((float)x - a.e.cx) * a.e.ifx, yh = ((float)y - a.e.cy) * a.e.ify;
-                const float s = chain_score<CRIT, MODEL>(fr, a.flows, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
+                const float s = chain_score<CRIT, MODEL, TR>(fr, fl, T, H, W, a.e, x, y, xh, yh, aval[e.x], fq, L, jpos);
                 w = flg[jpos] ? (s >= sa[jpos]) : (s > sa[jpos]);
             }
             if (!w) atomicMin(&first[sl], p);
@@ -884,7 +899,11 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
     extern __shared__ float lds[];
     __shared__ FrameF fr[kTMax + 1];
     __shared__ int s_cnt[2];
-    sweep_chain<CRIT, NT, MODEL>(a, xcd_item(blockIdx.x, gridDim.x), lds, fr, s_cnt);
+    const int chain = xcd_item(blockIdx.x, gridDim.x);
+    if (a.dir & 1)
+        sweep_chain<CRIT, NT, MODEL, true>(a, chain, lds, fr, s_cnt);
+    else
+        sweep_chain<CRIT, NT, MODEL, false>(a, chain, lds, fr, s_cnt);
 }
 
 // One sweep of the chains of several windows (a lockstep batch lane): item u
@@ -901,7 +920,10 @@ __global__ void __launch_bounds__(NT, 6) k_sweep_multi(const SweepArgs *args, co
     int w = 0;
     while (w + 1 < nwin && u >= first[w + 1]) ++w;
     const SweepArgs a = args[w];
-    sweep_chain<CRIT, NT, MODEL>(a, u - first[w], lds, fr, s_cnt);
+    if (a.dir & 1)
+        sweep_chain<CRIT, NT, MODEL, true>(a, u - first[w], lds, fr, s_cnt);
+    else
+        sweep_chain<CRIT, NT, MODEL, false>(a, u - first[w], lds, fr, s_cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,6 +1183,7 @@ static void sweep_args(voldor_ctx *c, const float *theta_in, float *theta_out, c
     a.theta_in = theta_in;
     a.theta_out = theta_out;
     a.flows = flows;
+    a.flows_t = c->flows_t;
     a.Mcum = c->Mcum;
     a.range = range_dev;
     a.q_out = q_out;
@@ -1367,6 +1390,33 @@ int launch_rigidness(voldor_ctx *c, const float *theta, const float2 *flows, con
     a.nblk = blocks;
     hipLaunchKernelGGL(k_rigidness, dim3(blocks), dim3(256), 0, s, a);
     if (ll_out) hipLaunchKernelGGL(k_ll_reduce, dim3(1), dim3(256), 0, s, c->ll_part, blocks, c->status, ll_out);
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
+// The flow planes transposed ([T][H][W] -> [T][W][H]) through 32 x 32 LDS
+// tiles, for the column sweeps' gathers; once per window.
+__global__ void __launch_bounds__(256) k_transpose_flows(const float2 *__restrict__ X, float2 *__restrict__ Xt,
+                                                         int H, int W)
+{
+    __shared__ float2 tile[32][33];
+    const size_t plane = (size_t)H * W * blockIdx.z;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int x = x0 + threadIdx.x, y = y0 + j;
+        if (x < W && y < H) tile[j][threadIdx.x] = X[plane + (size_t)y * W + x];
+    }
+    __syncthreads();
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int y = y0 + threadIdx.x, x = x0 + j;
+        if (x < W && y < H) Xt[plane + (size_t)x * H + y] = tile[threadIdx.x][j];
+    }
+}
+
+int launch_transpose_flows(voldor_ctx *c, const float2 *flows, int T, int H, int W, hipStream_t s)
+{
+    if (T > c->T_max || H > c->H_max || W > c->W_max) return VOLDOR_EINVAL;
+    hipLaunchKernelGGL(k_transpose_flows, dim3((W + 31) / 32, (H + 31) / 32, T), dim3(32, 8), 0, s, flows,
+                       c->flows_t, H, W);
     return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
 }
 
