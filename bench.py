@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
 # profiles/k_sweep_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 47.70e6, "write_bytes": 1.24e6}
-SWEEP_SOURCES_SHA = "578d9a15bf3dd8f4"
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 44.47e6, "write_bytes": 1.23e6}
+SWEEP_SOURCES_SHA = "d97bd159ecf7fe58"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz = 39.3 T/s; the all-pixel candidate scoring (--pose-start
@@ -381,8 +381,8 @@ def run_batch(args):
 # HBM traffic of the sweeps of one batch step (rocprofv3 FETCH_SIZE + WRITE_SIZE
 # of k_sweep, summed over the step's launches, per launch, scaled by the copy
 # calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
-BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (35.93 + 1.38) * 1e6   # profiles/k_sweep_hbm_traffic.md
-BATCH_SWEEP_SOURCES_SHA = "578d9a15bf3dd8f4"
+BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (33.39 + 1.35) * 1e6   # profiles/k_sweep_hbm_traffic.md
+BATCH_SWEEP_SOURCES_SHA = "d97bd159ecf7fe58"
 BATCH_SWEEP_TRAFFIC_LOCKSTEP = True    # the batch mode the counters were taken in
 
 
