@@ -482,12 +482,15 @@ void lockstep_plan(voldor_ctx *const *wc, const voldor_window_desc *w, const std
     for (int k = 0; k < n; ++k) all[k] = k;
     for (int k = 0; k < n; ++k) {
         LockStep st = {};
-        st.kind = kStepBoot;
+        st.kind = kStepTranspose;
         st.win = k;
         steps.push_back(st);
     }
-    stamp(kPhaseBoot, 0);
     std::vector<MultiLaunch> ms;
+    plan_bootstrap(plan, ms, refs, all, p->lmeds_hypotheses, p->lmeds_eval_pixels, p->seed, p->depth_lo,
+                   p->depth_hi);
+    multi(ms);
+    stamp(kPhaseBoot, 0);
     for (int it = 0; it < p->n_iters; ++it) {
         for (int t = 1; t <= Tmax; ++t) {
             std::vector<int> act;
@@ -553,10 +556,19 @@ int lockstep_run(voldor_ctx *lane, const std::vector<WinRef> &refs, const std::v
                                       p->depth_lo, p->depth_hi, r.poses, r.depth, s, nullptr);
             break;
         }
+        case kStepTranspose: {
+            const WinRef &r = refs[st.win];
+            r.c->last_stream = s;
+            rc = launch_transpose_flows(r.c, r.X, r.d.T, r.d.H, r.d.W, s);
+            break;
+        }
         case kStepMulti:
-            rc = (st.m.kind == kMultiSweep || st.m.kind == kMultiRig || st.m.kind == kMultiLL)
-                     ? launch_sweep_multi(st.m, plan_dev, s)
-                     : launch_pose_multi(st.m, plan_dev, s);
+            if (st.m.kind == kMultiSweep || st.m.kind == kMultiRig || st.m.kind == kMultiLL)
+                rc = launch_sweep_multi(st.m, plan_dev, s);
+            else if (st.m.kind >= kMultiBootInit)
+                rc = launch_boot_multi(st.m, plan_dev, s);
+            else
+                rc = launch_pose_multi(st.m, plan_dev, s);
             break;
         case kStepStamp:
             mark(lane, s, st.phase, st.launches);

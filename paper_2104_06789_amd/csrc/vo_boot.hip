@@ -11,6 +11,8 @@
 //   k_boot_tri     two-view triangulation of every pixel along its frame-0 ray;
 //   k_hist/_pick   radix selection of the 1st, 50th and 99th percentile depth;
 //   k_boot_final   invalid depths -> median, clamp to [0.5 P1, 2 P99].
+#include <algorithm>
+
 #include "vo_internal.hpp"
 
 namespace vo {
@@ -105,7 +107,7 @@ struct HypArgs {
     uint64_t seed;
 };
 
-__global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
+__device__ __forceinline__ void boot_hyp_body(const HypArgs &a)
 {
     const int nhb = (a.M + 63) / 64;
     if ((int)blockIdx.x >= nhb) {
@@ -251,6 +253,8 @@ __global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a)
     for (int i = 0; i < 9; ++i) { out[i] = E[i]; out[9 + i] = F[i]; }
 }
 
+__global__ void __launch_bounds__(64) k_boot_hyp(HypArgs a) { boot_hyp_body(a); }
+
 // Bin of a 256-bin histogram (counts h, read by threads 0..255) that holds
 // the element of rank `rank`: the unique thread with excl <= rank < incl
 // writes the bin and the rank within it.  Called by the whole workgroup.
@@ -299,7 +303,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o)
 constexpr int kEvalCand = kEvalThreads;
 constexpr int kDigitBits = 12;   // 4096 bins = 8 per thread
 
-__global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
+__device__ __forceinline__ void boot_score_body(const ScoreArgs &a)
 {
     __shared__ uint32_t hist[1 << kDigitBits];
     __shared__ int cnt_red[kEvalThreads / 64];
@@ -444,6 +448,8 @@ __global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a)
     if (tid == 0) a.score[h] = __longlong_as_double((long long)prefix);
 }
 
+__global__ void __launch_bounds__(kEvalThreads) k_boot_score(ScoreArgs a) { boot_score_body(a); }
+
 // sel layout: [0..2] prefix, [3..5] rank, [8..11] cheirality votes, [12] valid count
 constexpr int kSelVotes = 8;
 
@@ -472,7 +478,7 @@ __device__ __forceinline__ double tri_depth(const double *R, const double *t, do
 
 // least median of squares: lowest finite score, lowest index on ties; the
 // two rotations and the translation direction of its essential matrix
-__global__ void __launch_bounds__(256) k_boot_pick(PickArgs a)
+__device__ __forceinline__ void boot_pick_body(const PickArgs &a)
 {
     __shared__ double s_rs[4];
     __shared__ int s_rh[4];
@@ -515,6 +521,8 @@ __global__ void __launch_bounds__(256) k_boot_pick(PickArgs a)
     a.info[1] = bs;
 }
 
+__global__ void __launch_bounds__(256) k_boot_pick(PickArgs a) { boot_pick_body(a); }
+
 struct VoteArgs {
     const float2 *X1;
     const double *cand;
@@ -526,7 +534,7 @@ struct VoteArgs {
 
 // cheirality vote of the four decompositions (R_a, +t), (R_a, -t), (R_b, +t),
 // (R_b, -t) over the pixel subset
-__global__ void __launch_bounds__(256) k_boot_vote(VoteArgs a)
+__device__ __forceinline__ void boot_vote_body(const VoteArgs &a)
 {
     if (*a.status != kStatusOk) return;
     __shared__ int red[4][4];
@@ -570,6 +578,8 @@ __global__ void __launch_bounds__(256) k_boot_vote(VoteArgs a)
     }
 }
 
+__global__ void __launch_bounds__(256) k_boot_vote(VoteArgs a) { boot_vote_body(a); }
+
 struct TriArgs {
     const float2 *X1;
     const double *cand;
@@ -586,7 +596,7 @@ struct TriArgs {
 
 // the decomposition with most points in front of both cameras (first on
 // ties) -> T_1 with |t_1| = 1; two-view depth of every pixel along its ray
-__global__ void __launch_bounds__(256) k_boot_tri(TriArgs a)
+__device__ __forceinline__ void boot_tri_body(const TriArgs &a)
 {
     if (*a.status != kStatusOk) return;
     __shared__ int red[4];
@@ -644,7 +654,9 @@ __global__ void __launch_bounds__(256) k_boot_tri(TriArgs a)
     }
 }
 
-__global__ void k_sel_init(uint32_t *sel, uint32_t *hist, int *status)
+__global__ void __launch_bounds__(256) k_boot_tri(TriArgs a) { boot_tri_body(a); }
+
+__device__ __forceinline__ void sel_init_body(uint32_t *sel, uint32_t *hist, int *status)
 {
     const int tid = threadIdx.x;
     for (int i = tid; i < 3 * 256; i += blockDim.x) hist[i] = 0;
@@ -660,8 +672,10 @@ __global__ void k_sel_init(uint32_t *sel, uint32_t *hist, int *status)
     }
 }
 
-__global__ void __launch_bounds__(256) k_hist(const uint32_t *keys, int64_t n, const uint32_t *sel,
-                                              uint32_t *hist, int pass, const int *status)
+__global__ void k_sel_init(uint32_t *sel, uint32_t *hist, int *status) { sel_init_body(sel, hist, status); }
+
+__device__ __forceinline__ void hist_body(const uint32_t *keys, int64_t n, const uint32_t *sel, uint32_t *hist,
+                                          int pass, const int *status)
 {
     if (*status != kStatusOk) return;
     __shared__ uint32_t lh[3][256];
@@ -686,7 +700,13 @@ __global__ void __launch_bounds__(256) k_hist(const uint32_t *keys, int64_t n, c
     }
 }
 
-__global__ void __launch_bounds__(256) k_hist_pick(uint32_t *sel, uint32_t *hist, int pass, const int *status)
+__global__ void __launch_bounds__(256) k_hist(const uint32_t *keys, int64_t n, const uint32_t *sel,
+                                              uint32_t *hist, int pass, const int *status)
+{
+    hist_body(keys, n, sel, hist, pass, status);
+}
+
+__device__ __forceinline__ void hist_pick_body(uint32_t *sel, uint32_t *hist, int pass, const int *status)
 {
     if (*status != kStatusOk) return;
     __shared__ uint32_t s_wtot[4], s_bin, s_rib;
@@ -708,9 +728,14 @@ __global__ void __launch_bounds__(256) k_hist_pick(uint32_t *sel, uint32_t *hist
     for (int i = threadIdx.x; i < 768; i += blockDim.x) hist[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_boot_final(float *theta, const uint32_t *keys, int64_t n,
-                                                    const uint32_t *sel, double *range, double *info,
-                                                    double depth_lo, double depth_hi, const int *status)
+__global__ void __launch_bounds__(256) k_hist_pick(uint32_t *sel, uint32_t *hist, int pass, const int *status)
+{
+    hist_pick_body(sel, hist, pass, status);
+}
+
+__device__ __forceinline__ void boot_final_body(float *theta, const uint32_t *keys, int64_t n, const uint32_t *sel,
+                                                double *range, double *info, double depth_lo, double depth_hi,
+                                                const int *status)
 {
     if (*status != kStatusOk) return;
     const float P1 = __uint_as_float(sel[0]), P50 = __uint_as_float(sel[1]), P99 = __uint_as_float(sel[2]);
@@ -731,11 +756,20 @@ __global__ void __launch_bounds__(256) k_boot_final(float *theta, const uint32_t
     }
 }
 
-__global__ void k_boot_init(int *status, uint32_t *sel)
+__global__ void __launch_bounds__(256) k_boot_final(float *theta, const uint32_t *keys, int64_t n,
+                                                    const uint32_t *sel, double *range, double *info,
+                                                    double depth_lo, double depth_hi, const int *status)
+{
+    boot_final_body(theta, keys, n, sel, range, info, depth_lo, depth_hi, status);
+}
+
+__device__ __forceinline__ void boot_init_body(int *status, uint32_t *sel)
 {
     if (threadIdx.x == 0) *status = kStatusOk;
     if (threadIdx.x < 16) sel[threadIdx.x] = 0;
 }
+
+__global__ void k_boot_init(int *status, uint32_t *sel) { boot_init_body(status, sel); }
 
 // T_1 given instead of estimated (overlapping consecutive batches, Sec. 5.3):
 // the pose becomes decomposition candidate 0 with the only vote, so that the
@@ -760,6 +794,163 @@ __global__ void k_boot_seed(const double *T1, double *cand, uint32_t *sel, doubl
 }
 
 // ---------------------------------------------------------------------------
+// The bootstrap of several windows at once (a lockstep batch lane): each
+// kernel is one launch whose blockIdx.y selects a window's arguments, those
+// of its launch_bootstrap; counts gathered by atomics are integers, so the
+// windows' grid strides may differ from a single window's without changing
+// any result.
+struct BootWin {
+    HypArgs h;
+    ScoreArgs sc;
+    PickArgs pk;
+    VoteArgs va;
+    TriArgs tr;
+    uint32_t *sel, *hist, *keys;
+    int *status;
+    float *theta;
+    double *range, *info;
+    int64_t HW;
+    double depth_lo, depth_hi;
+};
+
+__global__ void k_boot_init_multi(const BootWin *w)
+{
+    const BootWin &b = w[blockIdx.y];
+    boot_init_body(b.status, b.sel);
+}
+
+__global__ void __launch_bounds__(64) k_boot_hyp_multi(const BootWin *w)
+{
+    const BootWin &b = w[blockIdx.y];
+    if ((int)blockIdx.x >= (b.h.M + 63) / 64 + (b.h.Ne + 63) / 64) return;
+    boot_hyp_body(b.h);
+}
+
+__global__ void __launch_bounds__(kEvalThreads) k_boot_score_multi(const BootWin *w)
+{
+    boot_score_body(w[blockIdx.y].sc);
+}
+
+__global__ void __launch_bounds__(256) k_boot_pick_multi(const BootWin *w)
+{
+    boot_pick_body(w[blockIdx.y].pk);
+}
+
+__global__ void __launch_bounds__(256) k_boot_vote_multi(const BootWin *w)
+{
+    boot_vote_body(w[blockIdx.y].va);
+}
+
+__global__ void __launch_bounds__(256) k_boot_tri_multi(const BootWin *w)
+{
+    const BootWin &b = w[blockIdx.y];
+    if ((int64_t)blockIdx.x * 256 >= b.HW) return;   // past this window's pixels
+    boot_tri_body(b.tr);
+}
+
+__global__ void __launch_bounds__(256) k_sel_init_multi(const BootWin *w)
+{
+    const BootWin &b = w[blockIdx.y];
+    sel_init_body(b.sel, b.hist, b.status);
+}
+
+__global__ void __launch_bounds__(256) k_hist_multi(const BootWin *w, int pass)
+{
+    const BootWin &b = w[blockIdx.y];
+    hist_body(b.keys, b.HW, b.sel, b.hist, pass, b.status);
+}
+
+__global__ void __launch_bounds__(256) k_hist_pick_multi(const BootWin *w, int pass)
+{
+    const BootWin &b = w[blockIdx.y];
+    hist_pick_body(b.sel, b.hist, pass, b.status);
+}
+
+__global__ void __launch_bounds__(256) k_boot_final_multi(const BootWin *w)
+{
+    const BootWin &b = w[blockIdx.y];
+    boot_final_body(b.theta, b.keys, b.HW, b.sel, b.range, b.info, b.depth_lo, b.depth_hi, b.status);
+}
+
+void plan_bootstrap(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, int n_hyp, int n_eval, uint64_t seed, double depth_lo,
+                    double depth_hi)
+{
+    const int n = (int)idx.size();
+    std::vector<BootWin> bw(n);
+    int g_hyp = 0, g_vote = 0, g_px = 0, g_hist = 0;
+    for (int k = 0; k < n; ++k) {
+        const WinRef &r = w[idx[k]];
+        voldor_ctx *c = r.c;
+        const WinDims &d = r.d;
+        const int64_t HW = (int64_t)d.H * d.W;
+        const int Ne = (int)(n_eval < HW ? n_eval : HW);
+        BootWin &b = bw[k];
+        b.h = HypArgs{r.X, c->hyp, c->hyp_score, c->boot_sub, d.H, d.W, n_hyp, Ne, d.fx, d.fy, d.cx, d.cy, seed};
+        b.sc = ScoreArgs{c->boot_sub, c->hyp, c->hyp_score, Ne};
+        b.pk = PickArgs{c->hyp, c->hyp_score, c->boot_cand, c->boot_info, c->status, n_hyp};
+        b.va = VoteArgs{r.X, c->boot_cand, c->sel, c->status, d.H, d.W, Ne, d.fx, d.fy, d.cx, d.cy};
+        b.tr = TriArgs{r.X, c->boot_cand, r.poses, c->Mcum, c->boot_info, r.depth, c->dkeys, c->sel, c->status,
+                       d.H, d.W, d.T, d.fx, d.fy, d.cx, d.cy};
+        b.sel = c->sel;
+        b.hist = c->hist;
+        b.keys = c->dkeys;
+        b.status = c->status;
+        b.theta = r.depth;
+        b.range = c->range;
+        b.info = c->boot_info;
+        b.HW = HW;
+        b.depth_lo = depth_lo;
+        b.depth_hi = depth_hi;
+        g_hyp = std::max(g_hyp, (n_hyp + 63) / 64 + (Ne + 63) / 64);
+        g_vote = std::max(g_vote, (Ne + 255) / 256);
+        g_px = std::max(g_px, (int)((HW + 255) / 256));
+        g_hist = std::max(g_hist, (int)std::min<int64_t>((HW + 255) / 256, 1024));
+    }
+    MultiLaunch l = {};
+    l.nwin = n;
+    l.off = p.put(bw.data(), n);
+    auto emit = [&](int kind, int gx, int variant) {
+        l.kind = kind;
+        l.gx = gx;
+        l.variant = variant;
+        out.push_back(l);
+    };
+    emit(kMultiBootInit, 1, 0);
+    emit(kMultiBootHyp, g_hyp, 0);
+    emit(kMultiBootScore, n_hyp, 0);
+    emit(kMultiBootPick, 1, 0);
+    emit(kMultiBootVote, g_vote, 0);
+    emit(kMultiBootTri, g_px, 0);
+    emit(kMultiSelInit, 1, 0);
+    for (int pass = 3; pass >= 0; --pass) {
+        emit(kMultiHist, g_hist, pass);
+        emit(kMultiHistPick, 1, pass);
+    }
+    emit(kMultiBootFinal, g_px, 0);
+}
+
+int launch_boot_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s)
+{
+    if (m.nwin < 1) return 0;
+    const BootWin *w = (const BootWin *)(dev + m.off);
+    const dim3 grid(m.gx, m.nwin);
+    switch (m.kind) {
+    case kMultiBootInit: hipLaunchKernelGGL(k_boot_init_multi, grid, dim3(64), 0, s, w); break;
+    case kMultiBootHyp: hipLaunchKernelGGL(k_boot_hyp_multi, grid, dim3(64), 0, s, w); break;
+    case kMultiBootScore: hipLaunchKernelGGL(k_boot_score_multi, grid, dim3(kEvalThreads), 0, s, w); break;
+    case kMultiBootPick: hipLaunchKernelGGL(k_boot_pick_multi, grid, dim3(256), 0, s, w); break;
+    case kMultiBootVote: hipLaunchKernelGGL(k_boot_vote_multi, grid, dim3(256), 0, s, w); break;
+    case kMultiBootTri: hipLaunchKernelGGL(k_boot_tri_multi, grid, dim3(256), 0, s, w); break;
+    case kMultiSelInit: hipLaunchKernelGGL(k_sel_init_multi, grid, dim3(256), 0, s, w); break;
+    case kMultiHist: hipLaunchKernelGGL(k_hist_multi, grid, dim3(256), 0, s, w, m.variant); break;
+    case kMultiHistPick: hipLaunchKernelGGL(k_hist_pick_multi, grid, dim3(256), 0, s, w, m.variant); break;
+    case kMultiBootFinal: hipLaunchKernelGGL(k_boot_final_multi, grid, dim3(256), 0, s, w); break;
+    default: return VOLDOR_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : VOLDOR_EDEVICE;
+}
+
 int launch_bootstrap(voldor_ctx *c, const float2 *flows, const WinDims &d, int n_hyp, int n_eval,
                      uint64_t seed, double depth_lo, double depth_hi, double *rel_poses,
                      float *theta, hipStream_t s, const double *T1_seed)

@@ -194,7 +194,11 @@ struct MultiLaunch {
     int gx;            // grid x
     size_t lds;        // dynamic LDS bytes
 };
-enum : int { kMultiPoseGroups = 1, kMultiPoseSeed, kMultiPoseMs, kMultiGauge, kMultiSweep, kMultiRig, kMultiLL };
+enum : int {
+    kMultiPoseGroups = 1, kMultiPoseSeed, kMultiPoseMs, kMultiGauge, kMultiSweep, kMultiRig, kMultiLL,
+    kMultiBootInit, kMultiBootHyp, kMultiBootScore, kMultiBootPick, kMultiBootVote, kMultiBootTri, kMultiSelInit,
+    kMultiHist, kMultiHistPick, kMultiBootFinal
+};
 
 struct Plan {
     std::vector<unsigned char> host;
@@ -227,14 +231,20 @@ void plan_rigidness(Plan &p, std::vector<MultiLaunch> &out, const std::vector<Wi
                     const std::vector<int> &idx, bool gauge, const std::vector<double *> &ll);
 int launch_sweep_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s);
 
+// the bootstraps of the windows (no T_1 given): their kernels, one launch each
+void plan_bootstrap(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,
+                    const std::vector<int> &idx, int n_hyp, int n_eval, uint64_t seed, double depth_lo,
+                    double depth_hi);
+int launch_boot_multi(const MultiLaunch &m, const unsigned char *dev, hipStream_t s);
+
 // the steps of one lockstep lane, in stream order
 struct LockStep {
     int kind;          // kStep*
     MultiLaunch m;     // kStepMulti
-    int win;           // window (index into the lane's WinRef list) of a bootstrap or status copy
+    int win;           // window (index into the lane's WinRef list) of a transpose, bootstrap or status copy
     int phase, launches;   // timing stamp
 };
-enum : int { kStepMulti = 0, kStepBoot, kStepStamp, kStepStatus };
+enum : int { kStepMulti = 0, kStepBoot, kStepStamp, kStepStatus, kStepTranspose };
 // plans the lockstep schedule of windows w[idx[k]] (contexts wc[k]) under
 // parameters p: the lane's WinRef list, its steps, the argument arrays in plan
 void lockstep_plan(voldor_ctx *const *wc, const voldor_window_desc *w, const std::vector<int> &idx,
