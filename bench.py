@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
 # profiles/k_sweep_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 44.47e6, "write_bytes": 1.23e6}
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 44.49e6, "write_bytes": 1.23e6}
 SWEEP_SOURCES_SHA = "d97bd159ecf7fe58"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16

@@ -348,7 +348,7 @@ __device__ __forceinline__ Mat2 shfl_down_m(const Mat2 &m, int d)
 // and the forward message stay live (products of r and gamma shared by the
 // two passes would each stay live across both).  r stays in registers from
 // its first read, so both replays take the E-step's own r.
-template <int SEG, bool FF_LDS = false>
+template <int SEG>
 __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float g, float gc, int lane)
 {
     const int n = s1 - s0;
@@ -423,9 +423,7 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
         b1 = n1 * inv;
         b0 = n0 * inv;
     }
-    // forward messages: in registers, or (FF_LDS, long segments) in place of
-    // r in the segment's own LDS words, r staying in registers
-    float ff[FF_LDS ? 1 : SEG];
+    float ff[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
         const float r1 = rr[i];
@@ -434,17 +432,11 @@ __device__ __forceinline__ void fb_segment_regs(float *rq, int s0, int s1, float
         const float inv = frcp(n1 + n0);
         f1 = n1 * inv;
         f0 = n0 * inv;
-        if constexpr (FF_LDS) {
-            if (i < n) rq[s0 + i] = f1;
-        } else {
-            ff[i] = f1;
-        }
+        ff[i] = f1;
     }
 #pragma unroll
     for (int i = SEG - 1; i >= 0; --i) {
-        // past the segment (FF_LDS) the word read is the next segment's or
-        // the following region's, and unused
-        const float ff1 = FF_LDS ? rq[s0 + i] : ff[FF_LDS ? 0 : i], ff0 = 1.0f - ff1;
+        const float ff1 = ff[i], ff0 = 1.0f - ff1;
         const float n1 = ff1 * b1, n0 = ff0 * b0;
         if (i < n) rq[s0 + i] = n1 * frcp(n1 + n0);
         if (i > 0) {
@@ -642,8 +634,6 @@ __device__ __forceinline__ void sweep_chain(const SweepArgs &a, const int chain,
             if (seglen <= 5) { fb_segment_regs<5>(rq, s0, s1, g, gc, lane); continue; }
             if (seglen <= 7) { fb_segment_regs<7>(rq, s0, s1, g, gc, lane); continue; }
             if (seglen <= 11) { fb_segment_regs<11>(rq, s0, s1, g, gc, lane); continue; }
-            // chains up to 1344 positions: r in registers, forward messages in LDS
-            if (seglen <= 21) { fb_segment_regs<21, true>(rq, s0, s1, g, gc, lane); continue; }
             // segment transfer matrices: forward A_k = diag(r,1-r) Gamma,
             // product A_{s1-1}..A_{s0}; backward G_k = Gamma diag(r,1-r),
             // product G_{s0}..G_{s1-1}
