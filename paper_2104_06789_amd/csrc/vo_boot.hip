@@ -813,63 +813,116 @@ struct BootWin {
     double depth_lo, depth_hi;
 };
 
+// A window's arguments with their pointers in the global address space
+// (global_ptr): the kernels below read them from the array in device memory
+__device__ __forceinline__ HypArgs to_global(HypArgs a)
+{
+    a.X1 = global_ptr(a.X1);
+    a.hyp = global_ptr(a.hyp);
+    a.score = global_ptr(a.score);
+    a.sub = global_ptr(a.sub);
+    return a;
+}
+
+__device__ __forceinline__ ScoreArgs to_global(ScoreArgs a)
+{
+    a.sub = global_ptr(a.sub);
+    a.hyp = global_ptr(a.hyp);
+    a.score = global_ptr(a.score);
+    return a;
+}
+
+__device__ __forceinline__ PickArgs to_global(PickArgs a)
+{
+    a.hyp = global_ptr(a.hyp);
+    a.score = global_ptr(a.score);
+    a.cand = global_ptr(a.cand);
+    a.info = global_ptr(a.info);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
+__device__ __forceinline__ VoteArgs to_global(VoteArgs a)
+{
+    a.X1 = global_ptr(a.X1);
+    a.cand = global_ptr(a.cand);
+    a.sel = global_ptr(a.sel);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
+__device__ __forceinline__ TriArgs to_global(TriArgs a)
+{
+    a.X1 = global_ptr(a.X1);
+    a.cand = global_ptr(a.cand);
+    a.rel = global_ptr(a.rel);
+    a.Mcum = global_ptr(a.Mcum);
+    a.info = global_ptr(a.info);
+    a.theta = global_ptr(a.theta);
+    a.keys = global_ptr(a.keys);
+    a.sel = global_ptr(a.sel);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
 __global__ void k_boot_init_multi(const BootWin *w)
 {
     const BootWin &b = w[blockIdx.y];
-    boot_init_body(b.status, b.sel);
+    boot_init_body(global_ptr(b.status), global_ptr(b.sel));
 }
 
 __global__ void __launch_bounds__(64) k_boot_hyp_multi(const BootWin *w)
 {
     const BootWin &b = w[blockIdx.y];
     if ((int)blockIdx.x >= (b.h.M + 63) / 64 + (b.h.Ne + 63) / 64) return;
-    boot_hyp_body(b.h);
+    boot_hyp_body(to_global(b.h));
 }
 
 __global__ void __launch_bounds__(kEvalThreads) k_boot_score_multi(const BootWin *w)
 {
-    boot_score_body(w[blockIdx.y].sc);
+    boot_score_body(to_global(w[blockIdx.y].sc));
 }
 
 __global__ void __launch_bounds__(256) k_boot_pick_multi(const BootWin *w)
 {
-    boot_pick_body(w[blockIdx.y].pk);
+    boot_pick_body(to_global(w[blockIdx.y].pk));
 }
 
 __global__ void __launch_bounds__(256) k_boot_vote_multi(const BootWin *w)
 {
-    boot_vote_body(w[blockIdx.y].va);
+    boot_vote_body(to_global(w[blockIdx.y].va));
 }
 
 __global__ void __launch_bounds__(256) k_boot_tri_multi(const BootWin *w)
 {
     const BootWin &b = w[blockIdx.y];
     if ((int64_t)blockIdx.x * 256 >= b.HW) return;   // past this window's pixels
-    boot_tri_body(b.tr);
+    boot_tri_body(to_global(b.tr));
 }
 
 __global__ void __launch_bounds__(256) k_sel_init_multi(const BootWin *w)
 {
     const BootWin &b = w[blockIdx.y];
-    sel_init_body(b.sel, b.hist, b.status);
+    sel_init_body(global_ptr(b.sel), global_ptr(b.hist), global_ptr(b.status));
 }
 
 __global__ void __launch_bounds__(256) k_hist_multi(const BootWin *w, int pass)
 {
     const BootWin &b = w[blockIdx.y];
-    hist_body(b.keys, b.HW, b.sel, b.hist, pass, b.status);
+    hist_body(global_ptr(b.keys), b.HW, global_ptr(b.sel), global_ptr(b.hist), pass, global_ptr(b.status));
 }
 
 __global__ void __launch_bounds__(256) k_hist_pick_multi(const BootWin *w, int pass)
 {
     const BootWin &b = w[blockIdx.y];
-    hist_pick_body(b.sel, b.hist, pass, b.status);
+    hist_pick_body(global_ptr(b.sel), global_ptr(b.hist), pass, global_ptr(b.status));
 }
 
 __global__ void __launch_bounds__(256) k_boot_final_multi(const BootWin *w)
 {
     const BootWin &b = w[blockIdx.y];
-    boot_final_body(b.theta, b.keys, b.HW, b.sel, b.range, b.info, b.depth_lo, b.depth_hi, b.status);
+    boot_final_body(global_ptr(b.theta), global_ptr(b.keys), b.HW, global_ptr(b.sel), global_ptr(b.range),
+                    global_ptr(b.info), b.depth_lo, b.depth_hi, global_ptr(b.status));
 }
 
 void plan_bootstrap(Plan &p, std::vector<MultiLaunch> &out, const std::vector<WinRef> &w,

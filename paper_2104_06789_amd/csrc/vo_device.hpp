@@ -61,6 +61,21 @@ struct EmisParams {
     float l2a1, a2l;              // log2 a1, a2 / ln 2: log2 alpha = a2l |v| + l2a1
 };
 
+// A pointer that a kernel reads from device memory (the argument arrays of the
+// batched launches) is generic to the compiler, which then accesses memory
+// through it with flat instructions.  Those count on the LDS wait counter as
+// well, so every wait for an LDS result also waits for the loads from memory
+// in flight.  Passing it through the global address space lets the compiler
+// use global instructions.  Only for pointers into device memory, with one
+// value across the workgroup (they sit in scalar registers).
+template <class T>
+__device__ __forceinline__ T *global_ptr(T *p)
+{
+    __attribute__((address_space(1))) T *g = (__attribute__((address_space(1))) T *)p;
+    asm("" : "+s"(g));   // keeps the two casts from folding into none
+    return (T *)g;
+}
+
 // hardware reciprocal (v_rcp_f32, about 1 ulp) instead of an IEEE division
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 

@@ -193,9 +193,26 @@ __global__ void __launch_bounds__(64) k_pose_groups(GroupArgs a) { pose_groups_b
 // the kernels of a pose step over several windows at once (a lockstep batch
 // lane): blockIdx.y selects a window's arguments, which are those of a single
 // window's launch, so every window gets exactly its own result
+// their pointers in the global address space (global_ptr)
+__device__ __forceinline__ GroupArgs to_global(GroupArgs a)
+{
+    a.theta = global_ptr(a.theta);
+    a.rig = global_ptr(a.rig);
+    a.flows = global_ptr(a.flows);
+    a.Mprev = global_ptr(a.Mprev);
+    a.samples = global_ptr(a.samples);
+    a.gcnt = global_ptr(a.gcnt);
+    a.gpre = global_ptr(a.gpre);
+    a.bcnt = global_ptr(a.bcnt);
+    a.bws = global_ptr(a.bws);
+    a.sampf = global_ptr(a.sampf);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
 __global__ void __launch_bounds__(64) k_pose_groups_multi(const GroupArgs *args)
 {
-    const GroupArgs a = args[blockIdx.y];
+    const GroupArgs a = to_global(args[blockIdx.y]);
     if ((int)blockIdx.x * kGrpPerBlk >= a.S) return;   // past this window's blocks
     pose_groups_body(a);
 }
@@ -353,9 +370,21 @@ __device__ __forceinline__ void pose_seed_body(const SeedArgs &a)
 
 __global__ void __launch_bounds__(kSeedThreads) k_pose_seed(SeedArgs a) { pose_seed_body(a); }
 
+__device__ __forceinline__ SeedArgs to_global(SeedArgs a)
+{
+    a.samples = global_ptr(a.samples);
+    a.bcnt = global_ptr(a.bcnt);
+    a.seed_score = global_ptr(a.seed_score);
+    a.seed_part = global_ptr(a.seed_part);
+    a.prev = global_ptr(a.prev);
+    a.start_p = global_ptr(a.start_p);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
 __global__ void __launch_bounds__(kSeedThreads) k_pose_seed_multi(const SeedArgs *args)
 {
-    const SeedArgs a = args[blockIdx.y];
+    const SeedArgs a = to_global(args[blockIdx.y]);
     pose_seed_body(a);
 }
 
@@ -623,9 +652,23 @@ __device__ __forceinline__ void pose_ms_body(const MsArgs &a)
 
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms(MsArgs a) { pose_ms_body(a); }
 
+__device__ __forceinline__ MsArgs to_global(MsArgs a)
+{
+    a.sampf = global_ptr(a.sampf);
+    a.bcnt = global_ptr(a.bcnt);
+    a.bws = global_ptr(a.bws);
+    a.seed_score = global_ptr(a.seed_score);
+    a.seed_part = global_ptr(a.seed_part);
+    a.rel = global_ptr(a.rel);
+    a.Mcum = global_ptr(a.Mcum);
+    a.diag = global_ptr(a.diag);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
 __global__ void __launch_bounds__(kMsThreads) k_pose_ms_multi(const MsArgs *args)
 {
-    const MsArgs a = args[blockIdx.y];
+    const MsArgs a = to_global(args[blockIdx.y]);
     pose_ms_body(a);
 }
 
@@ -894,7 +937,7 @@ struct GaugeArgs {
 __global__ void k_gauge_poses_multi(const GaugeArgs *args)
 {
     const GaugeArgs a = args[blockIdx.y];
-    gauge_poses_body(a.rel, a.Mcum, a.range, a.T, a.status);
+    gauge_poses_body(global_ptr(a.rel), global_ptr(a.Mcum), global_ptr(a.range), a.T, global_ptr(a.status));
 }
 
 __global__ void k_cumulative(const double *rel, double *Mcum, int T)

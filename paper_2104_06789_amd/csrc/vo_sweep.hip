@@ -910,6 +910,21 @@ __global__ void __launch_bounds__(NT, 6) k_sweep(SweepArgs a)
 // is chain u - first[w] of window w, first[] the windows' chain offsets
 // (first[nwin] = gridDim.x); each window's arguments are those of its single
 // launch, so every chain gets exactly its single-window result.
+// the arguments of a batched launch with their pointers in the global
+// address space (global_ptr)
+__device__ __forceinline__ SweepArgs to_global(SweepArgs a)
+{
+    a.theta_in = global_ptr(a.theta_in);
+    a.theta_out = global_ptr(a.theta_out);
+    a.flows = global_ptr(a.flows);
+    a.flows_t = global_ptr(a.flows_t);
+    a.Mcum = global_ptr(a.Mcum);
+    a.range = global_ptr(a.range);
+    a.q_out = global_ptr(a.q_out);
+    a.status = global_ptr(a.status);
+    return a;
+}
+
 template <int CRIT, int NT, int MODEL>
 __global__ void __launch_bounds__(NT, 6) k_sweep_multi(const SweepArgs *args, const int *first, int nwin)
 {
@@ -919,7 +934,7 @@ __global__ void __launch_bounds__(NT, 6) k_sweep_multi(const SweepArgs *args, co
     const int u = xcd_item(blockIdx.x, gridDim.x);
     int w = 0;
     while (w + 1 < nwin && u >= first[w + 1]) ++w;
-    const SweepArgs a = args[w];
+    const SweepArgs a = to_global(args[w]);
     if (a.dir & 1)
         sweep_chain<CRIT, NT, MODEL, true>(a, u - first[w], lds, fr, s_cnt);
     else
@@ -1059,9 +1074,25 @@ __global__ void __launch_bounds__(256) k_rigidness(RigArgs a) { rigidness_body(a
 
 // the rigidness pass of several windows (a lockstep batch lane), blockIdx.y
 // selecting a window's arguments
+__device__ __forceinline__ RigArgs to_global(RigArgs a)
+{
+    a.theta = global_ptr(a.theta);
+    a.theta_gauge = global_ptr(a.theta_gauge);
+    a.rel = global_ptr(a.rel);
+    a.flows = global_ptr(a.flows);
+    a.Mcum = global_ptr(a.Mcum);
+    a.status = global_ptr(a.status);
+    a.r = global_ptr(a.r);
+    a.ell = global_ptr(a.ell);
+    a.logrho = global_ptr(a.logrho);
+    a.logmu = global_ptr(a.logmu);
+    a.ll_part = global_ptr(a.ll_part);
+    return a;
+}
+
 __global__ void __launch_bounds__(256) k_rigidness_multi(const RigArgs *args)
 {
-    const RigArgs a = args[blockIdx.y];
+    const RigArgs a = to_global(args[blockIdx.y]);
     if ((int)blockIdx.x >= a.nblk) return;   // past this window's workgroups
     rigidness_body(a);
 }
@@ -1107,7 +1138,7 @@ struct LLArgs {
 __global__ void k_ll_reduce_multi(const LLArgs *args)
 {
     const LLArgs a = args[blockIdx.y];
-    ll_reduce_body(a.part, a.n, a.status, a.out);
+    ll_reduce_body(global_ptr(a.part), a.n, global_ptr(a.status), global_ptr(a.out));
 }
 
 __global__ void k_philox(const uint64_t *ctr, uint64_t k0, uint64_t k1, uint64_t *out, int n)
