@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (x2.000 and x1.000); valid only while
 # the sweep kernel's sources hash to SWEEP_SOURCES_SHA (profile:
 # profiles/k_sweep_hbm_traffic.md)
-SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 44.49e6, "write_bytes": 1.23e6}
-SWEEP_SOURCES_SHA = "d97bd159ecf7fe58"
+SWEEP_TRAFFIC_INDOOR = {"fetch_bytes": 44.90e6, "write_bytes": 1.23e6}
+SWEEP_SOURCES_SHA = "cae795f93c1e31cf"
 SWEEP_SOURCES = ("vo_sweep.hip", "vo_device.hpp")   # the sweep's device code
 # Issue peak of non-packed FP32 VALU lane-instructions: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz = 39.3 T/s; the all-pixel candidate scoring (--pose-start
@@ -54,16 +54,18 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 def _sweep_traffic(workload):
     """Measured HBM bytes per sweep launch, or None if not measured for this
     workload or if the kernel changed since the counters were taken."""
-    import hashlib
-    if workload != "indoor":
+    if workload != "indoor" or _sweep_sources_sha() != SWEEP_SOURCES_SHA:
         return None
+    return SWEEP_TRAFFIC_INDOOR["fetch_bytes"] + SWEEP_TRAFFIC_INDOOR["write_bytes"]
+
+
+def _sweep_sources_sha():
+    import hashlib
     h = hashlib.sha256()
     for f in SWEEP_SOURCES:
         with open(os.path.join(ROOT, "paper_2104_06789_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != SWEEP_SOURCES_SHA:
-        return None
-    return SWEEP_TRAFFIC_INDOOR["fetch_bytes"] + SWEEP_TRAFFIC_INDOOR["write_bytes"]
+    return h.hexdigest()[:16]
 
 
 # HBM traffic of one residual-binning pass (k_resid_bins + k_resid_reduce) on the
@@ -351,7 +353,9 @@ def run_batch(args):
         "roofline": {"bound": "hbm", "kernel": "k_sweep_multi" if lockstep else "k_sweep",
                      "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
-                     "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_traffic_valid(lockstep) else None,
+                     "traffic": BATCH_SWEEP_TRAFFIC_PER_LAUNCH if _batch_sweep_counters_valid(lockstep) else None,
+                     "fetch_bytes_per_launch": (BATCH_SWEEP_FETCH_PER_LAUNCH
+                                                if _batch_sweep_counters_valid(lockstep) else None),
                      "alg_bytes_per_launch": alg_bytes / max(launches, 1.0),
                      "launch_ms": ph["sweeps_busy"] / max(launches, 1.0), "launches": launches,
                      "launch_ms_concurrent": ph["sweeps"] / max(launches, 1.0),
@@ -378,25 +382,22 @@ def run_batch(args):
     print(json.dumps(line))
 
 
-# HBM traffic of the sweeps of one batch step (rocprofv3 FETCH_SIZE + WRITE_SIZE
-# of k_sweep, summed over the step's launches, per launch, scaled by the copy
-# calibration); valid while the sweep's sources hash to BATCH_SWEEP_SOURCES_SHA
-BATCH_SWEEP_TRAFFIC_PER_LAUNCH = (33.39 + 1.35) * 1e6   # profiles/k_sweep_hbm_traffic.md
-BATCH_SWEEP_SOURCES_SHA = "d97bd159ecf7fe58"
+# HBM bytes of the sweeps of one batch step (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE of k_sweep_multi, summed over the step's launches, per window-sweep,
+# scaled by the copy calibration); valid while the sweep's sources hash to
+# BATCH_SWEEP_SOURCES_SHA (profiles/k_sweep_hbm_traffic.md).  On these sources
+# only the FETCH_SIZE pass was taken, so the traffic (read + write) is None and
+# the read bytes are reported on their own.
+BATCH_SWEEP_FETCH_PER_LAUNCH = 33.13e6
+BATCH_SWEEP_TRAFFIC_PER_LAUNCH = None
+BATCH_SWEEP_SOURCES_SHA = "cae795f93c1e31cf"
 BATCH_SWEEP_TRAFFIC_LOCKSTEP = True    # the batch mode the counters were taken in
 
 
-def _batch_sweep_traffic_valid(lockstep):
-    import hashlib
-    if BATCH_SWEEP_TRAFFIC_PER_LAUNCH is None or BATCH_SWEEP_SOURCES_SHA is None:
+def _batch_sweep_counters_valid(lockstep):
+    if BATCH_SWEEP_SOURCES_SHA is None or lockstep != BATCH_SWEEP_TRAFFIC_LOCKSTEP:
         return False
-    if lockstep != BATCH_SWEEP_TRAFFIC_LOCKSTEP:
-        return False
-    h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_2104_06789_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16] == BATCH_SWEEP_SOURCES_SHA
+    return _sweep_sources_sha() == BATCH_SWEEP_SOURCES_SHA
 
 
 LEARN_T, LEARN_H, LEARN_W = 6, 480, 640
