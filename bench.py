@@ -149,9 +149,13 @@ def _pose_error(poses, gt):
 
 
 BATCH_ITERS = 4
-# lanes of the batch workload per mode (measured on one box: lockstep 31.1 ms
-# per step at 8 lanes, 31.3 at 12, 31.5 at 16; stream-order lanes 34.7 ms at 4)
-BATCH_LOCKSTEP_LANES = 8
+# lanes of the batch workload per mode.  A replayed graph runs the work of at
+# most four lanes at once here (device timestamps: lanes 4-7 of eight start as
+# lanes 0-3 end, also with eight hardware queues), so more lanes only split the
+# batch into rounds, each with its own bootstrap and first pose steps; measured
+# on one box, lockstep: 2 lanes 30.3 ms per step, 3 lanes 28.7, 4 lanes 27.6,
+# 5 lanes 32.4, 6 lanes 30.2, 8 lanes 28.5; stream-order lanes 34.7 ms at 4
+BATCH_LOCKSTEP_LANES = 4
 BATCH_STREAM_LANES = 4
 # algorithmic FP32 work of one pixel-frame in one sweep: three candidate-frame
 # evaluations (previous depth, random sample, propagated neighbour), each about
@@ -388,7 +392,7 @@ def run_batch(args):
 # BATCH_SWEEP_SOURCES_SHA (profiles/k_sweep_hbm_traffic.md).  On these sources
 # only the FETCH_SIZE pass was taken, so the traffic (read + write) is None and
 # the read bytes are reported on their own.
-BATCH_SWEEP_FETCH_PER_LAUNCH = 33.13e6
+BATCH_SWEEP_FETCH_PER_LAUNCH = 32.83e6   # at 4 lockstep lanes
 BATCH_SWEEP_TRAFFIC_PER_LAUNCH = None
 BATCH_SWEEP_SOURCES_SHA = "cae795f93c1e31cf"
 BATCH_SWEEP_TRAFFIC_LOCKSTEP = True    # the batch mode the counters were taken in
@@ -855,7 +859,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="windows per step (--workload batch)")
     ap.add_argument("--lanes", type=int, default=0,
-                    help="concurrent streams of --workload batch (default: 8 in lockstep mode, 4 otherwise)")
+                    help="concurrent streams of --workload batch (default: 4 in either mode)")
     ap.add_argument("--batch-mode", choices=["lockstep", "lanes"], default="lockstep",
                     help="lockstep: the windows of each lane advance together, one launch per kernel over all "
                          "of them; lanes: each lane solves its windows one after another")

@@ -274,7 +274,9 @@ typedef struct {
  * context sized T_max x H_max x W_max x S_max.  Windows are independent, so a
  * batch is spread over the lanes (largest first, onto the least loaded lane)
  * and the lanes run concurrently: one window's latency-bound pose steps
- * overlap the sweeps of the others.  flags: VOLDOR_BATCH_GRAPH captures each
+ * overlap the sweeps of the others.  Measured on MI355X with ROCm's graph
+ * replay: the work of at most four lanes runs at once, a further lane starting
+ * when an earlier one ends.  flags: VOLDOR_BATCH_GRAPH captures each
  * distinct batch call into a HIP graph on first use and replays it when the
  * same call (descriptors, count, parameters, status array, stream) comes again.
  * Returns VOLDOR_EINVAL / VOLDOR_ENOMEM / VOLDOR_EDEVICE like voldor_create. */
